@@ -1,0 +1,195 @@
+"""Oracle selected inversion (test infrastructure only).
+
+Output convention: X is stored in panels with the layout of the factor panels
+(rows = K's columns then C(K)); the top s x s block holds the full symmetric
+A^{-1}_{K,K} and the bottom c x s block holds A^{-1}_{C,K}.  Together they are
+every selected entry of the lower triangle: (i, j) with L_ij != 0 (Alg. 1 and
+Alg. 2 output lines).  The upper triangle is the transpose (LDL^T
+specialization, Section 2.3).  Transposes are plain transposes, also for
+complex-symmetric matrices.
+
+Three independent formulations:
+  dense_selected  the definition: (P A P^T)^{-1} restricted to the pattern of L.
+  alg1            Alg. 1, second loop (steps 3-4 with the LDL^T specialization
+                  Uhat = Lhat^T), plus the diagonal-block symmetrization
+                  described after Alg. 2.
+  alg2            Alg. 2, the left-looking form: the diagonal update, then the
+                  outer-product update Eq. (outerprod) and the inner-product
+                  update Eq. (innerprod) pushed into the descendants C'(K)
+                  (Eq. (newset)), split as the D, O, I and ID tasks of Section 3.1.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+
+def gather_cc(sym, X, K):
+    """Dense A^{-1}_{C,C} for C = C(K) from ancestor panels (lower + transpose)."""
+    C = sym.rows[K]
+    c = C.shape[0]
+    dtype = np.result_type(*[X[int(J)].dtype for J in sym.seg_super[sym.seg_ptr[K]:sym.seg_ptr[K + 1]]]) if c else np.float64
+    G = np.zeros((c, c), dtype=dtype)
+    g0, g1 = sym.seg_ptr[K], sym.seg_ptr[K + 1]
+    for g in range(g0, g1):
+        J = int(sym.seg_super[g])
+        st = int(sym.seg_start[g])
+        en = int(sym.seg_start[g + 1]) if g + 1 < g1 else c
+        pos = sym.posarr[sym.seg_posoff[g]: sym.seg_posoff[g] + (c - st)]
+        cols = C[st:en] - sym.xsuper[J]
+        # column b of G (b in this segment), rows a >= st: X_J[pos[a - st], C[b] - first(J)]
+        G[st:, st:en] = X[J][np.ix_(pos, cols)]
+    lower = np.tril(G)
+    return lower + np.tril(G, -1).T
+
+
+def alg1(sym, lhat, dtinv):
+    """Alg. 1 second loop, K = N..1 (root first), pull form.
+
+    A^{-1}_{C,K} = -A^{-1}_{C,C} Lhat_{C,K}                   (step 3)
+    A^{-1}_{K,K} = Dt_K^{-1} - Lhat_{C,K}^T A^{-1}_{C,K}        (step 4, Uhat = Lhat^T)
+    A^{-1}_{K,K} <- (A^{-1}_{K,K} + A^{-T}_{K,K}) / 2            (symmetrization)
+    """
+    X = [None] * sym.nsuper
+    for K in reversed(range(sym.nsuper)):
+        s = sym.width(K)
+        c = sym.rows[K].shape[0]
+        dtype = dtinv[K].dtype
+        P = np.zeros((s + c, s), dtype=dtype)
+        if c:
+            G = gather_cc(sym, X, K)
+            Y = -G @ lhat[K]
+            T = dtinv[K] - lhat[K].T @ Y
+            P[s:, :] = Y
+        else:
+            T = dtinv[K].copy()
+        P[:s, :] = 0.5 * (T + T.T)
+        X[K] = P
+    return X
+
+
+def descendants(sym):
+    """C'(K) = {I' < K : L_{K,I'} != 0} for every K (Eq. (newset))."""
+    out = [[] for _ in range(sym.nsuper)]
+    for I in range(sym.nsuper):
+        for g in range(sym.seg_ptr[I], sym.seg_ptr[I + 1]):
+            out[int(sym.seg_super[g])].append((I, g))
+    return out
+
+
+def alg2(sym, lhat, dtinv):
+    """Alg. 2 (left-looking selected inversion), LDL^T specialization.
+
+    X starts at zero on the pattern of L.  For K = N..1:
+      D   : X_KK = Dt_K^{-1} - Lhat_{C,K}^T X_{C,K}, then symmetrize.
+      for each descendant I' in C'(K), with R_K = C(I') inside K's columns and
+      R_> = C(I') above K (all of which lie in C(K)):
+      O   : X[R_>, I'] -= X[R_>, R_K] Lhat[R_K, I']                  Eq. (outerprod)
+      I   : X[R_K, I'] -= X[R_>, R_K]^T Lhat[R_>, I']                 Eq. (innerprod), I in C
+      ID  : X[R_K, I'] -= X_KK[R_K, R_K] Lhat[R_K, I']                Eq. (innerprod), I = K
+    X[*, I'] is stored in I''s panel, rows s_I' + (index in C(I')).
+    """
+    xs = sym.xsuper
+    X = []
+    for K in range(sym.nsuper):
+        s = sym.width(K)
+        c = sym.rows[K].shape[0]
+        X.append(np.zeros((s + c, s), dtype=dtinv[K].dtype))
+    desc = descendants(sym)
+    for K in reversed(range(sym.nsuper)):
+        s = sym.width(K)
+        fK = int(xs[K])
+        PK = X[K]
+        # D task
+        T = dtinv[K] - lhat[K].T @ PK[s:, :]
+        PK[:s, :] = 0.5 * (T + T.T)
+        XKK = PK[:s, :]
+        for (I, g) in desc[K]:
+            sI = sym.width(I)
+            CI = sym.rows[I]
+            cI = CI.shape[0]
+            st = int(sym.seg_start[g])
+            g1 = sym.seg_ptr[I + 1]
+            en = int(sym.seg_start[g + 1]) if g + 1 < g1 else cI
+            pos = sym.posarr[sym.seg_posoff[g]: sym.seg_posoff[g] + (cI - st)]
+            rk = np.arange(st, en)          # indices into C(I) of R_K
+            ra = np.arange(en, cI)          # indices into C(I) of R_>
+            colsK = CI[rk] - fK             # columns of K's panel
+            posA = pos[en - st:]            # rows of K's panel holding R_>
+            XI = X[I]
+            Lh = lhat[I]
+            X_a_k = PK[np.ix_(posA, colsK)]  # X[R_>, R_K], part of X_{C(K),K}
+            # O task
+            if ra.size:
+                XI[sI + ra, :] -= X_a_k @ Lh[rk, :]
+            # I task
+            if ra.size:
+                XI[sI + rk, :] -= X_a_k.T @ Lh[ra, :]
+            # ID task
+            XI[sI + rk, :] -= XKK[np.ix_(colsK, colsK)] @ Lh[rk, :]
+    return X
+
+
+def dense_selected(sym, bdense):
+    """The definition: (P A P^T)^{-1} on the pattern of L, in panel layout."""
+    Xd = np.linalg.inv(bdense)
+    X = []
+    for K in range(sym.nsuper):
+        f, l1 = int(sym.xsuper[K]), int(sym.xsuper[K + 1])
+        rowsK = np.concatenate([np.arange(f, l1), sym.rows[K]])
+        X.append(Xd[np.ix_(rowsK, np.arange(f, l1))].copy())
+    return X
+
+
+def permuted_dense(sym, avals):
+    """Dense B = P A P^T from A's stored lower values (small problems)."""
+    n = sym.n
+    bvals = np.empty_like(avals)
+    bvals[sym.amap] = avals
+    Bd = np.zeros((n, n), dtype=np.asarray(avals).dtype)
+    cols = np.repeat(np.arange(n), np.diff(sym.Bcolptr))
+    Bd[sym.Browind, cols] = bvals
+    Bd[cols, sym.Browind] = bvals
+    return Bd
+
+
+def flatten(sym, X):
+    """Concatenate panels column-major into one vector (the device layout)."""
+    return np.concatenate([P.reshape(-1, order="F") for P in X]) if X else np.zeros(0)
+
+
+def unflatten(sym, vec):
+    out = []
+    off = 0
+    for K in range(sym.nsuper):
+        s = sym.width(K)
+        r = s + sym.rows[K].shape[0]
+        out.append(np.asarray(vec[off: off + r * s]).reshape((r, s), order="F"))
+        off += r * s
+    return out
+
+
+def on_pattern_of_A(sym, X, colptr, rowind):
+    """Selected entries at A's stored lower positions, original indexing.
+
+    A entry (r, c) reads X at (max(ip[r], ip[c]), min(...)) of B.
+    """
+    n = sym.n
+    ip = np.empty(n, dtype=np.int64)
+    ip[sym.perm] = np.arange(n)
+    cols = np.repeat(np.arange(n), np.diff(colptr))
+    i = ip[np.asarray(rowind)]
+    j = ip[cols]
+    hi, lo = np.maximum(i, j), np.minimum(i, j)
+    out = np.empty(hi.shape[0], dtype=X[0].dtype)
+    K = sym.col2super[lo]
+    for e in range(hi.shape[0]):
+        k = int(K[e])
+        f, l = int(sym.xsuper[k]), int(sym.xsuper[k + 1] - 1)
+        r = int(hi[e])
+        if r <= l:
+            pr = r - f
+        else:
+            pr = (l - f + 1) + int(np.searchsorted(sym.rows[k], r))
+        out[e] = X[k][pr, int(lo[e]) - f]
+    return out
