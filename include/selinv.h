@@ -1,0 +1,213 @@
+/*
+ * selinv.h -- C ABI of the MI355X selected-inversion library.
+ *
+ * Method: Jacquelin, Lin, Jia, Zhao, Yang, "A Left-Looking Selected Inversion
+ * Algorithm and Task Parallelism on Shared Memory Systems" (arXiv:1604.02528).
+ * Given a sparse symmetric (real) or complex-symmetric matrix A and a
+ * symmetric fill-reducing permutation P, the library computes every entry of
+ * B^{-1}, B = P A P^T, on the sparsity pattern of the L factor of B
+ * (Alg. 1 / Alg. 2 outputs: the selected blocks A^{-1}_{I,J} with L_{I,J}
+ * nonempty; the LDL^T specialization of Section 2.3 makes the upper triangle
+ * the transpose of the lower one).
+ *
+ * Conventions shared by every entry point
+ *  - Matrices: lower triangle incl. diagonal, CSC, 0-based, int64 indices,
+ *    rows strictly increasing inside a column, diagonal present
+ *    (structurally symmetric pattern, Section 2.1).
+ *  - perm: new -> old (B[i,j] = A[perm[i], perm[j]]); NULL = identity.
+ *    The paper permutes symmetrically without looking at values (Section 4).
+ *  - Values: `batch` matrices with one pattern (the shifts H - z_l S of a
+ *    pole expansion), laid out [batch][nnz] in rowind order.  SELINV_C128
+ *    values are interleaved (re, im) doubles.  Transposes are plain
+ *    transposes also for complex values (complex-symmetric, A = A^T).
+ *  - Panels: supernode K (columns first(K)..last(K), width s, row set C(K) of
+ *    size c, Eq. (newset)) owns a dense column-major (s + c) x s block whose
+ *    rows are K's own columns followed by C(K).  Panels are concatenated in K
+ *    order; one matrix of the batch occupies `panel_elems` scalars and matrix
+ *    l starts at l * panel_elems.  The same layout is used for the factor
+ *    panels and for the selected inverse X.
+ *  - Device memory is always allocated by the caller (sizes from
+ *    selinv_sizes) and never freed by the library.  Device pointers are plain
+ *    `void*` from hipMalloc (or a framework allocator on the same device).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Every function returns selinv_status; no C++ exception crosses the ABI.
+ *    On error, selinv_last_error(ctx) explains it and selinv_error_info(ctx, k)
+ *    gives integers (k = 0: column, k = 1: batch index) where meaningful.
+ *    After an error, output buffers are undefined.  A context is not
+ *    thread-safe; distinct contexts are independent.
+ */
+#ifndef SELINV_H
+#define SELINV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct selinv_ctx selinv_ctx;
+
+typedef enum {
+  SELINV_R64 = 0,  /* real float64 */
+  SELINV_C128 = 1  /* complex128, complex-symmetric */
+} selinv_dtype;
+
+typedef enum {
+  SELINV_OK = 0,
+  SELINV_EINVAL = 1,       /* bad argument (null pointer, size, option) */
+  SELINV_EPATTERN = 2,     /* malformed CSC pattern or permutation */
+  SELINV_ESINGULAR = 3,    /* zero or non-finite pivot (no pivoting is done) */
+  SELINV_ENOMEM = 4,       /* host allocation failed or size overflow */
+  SELINV_EDEVICE = 5,      /* HIP runtime error or device watchdog */
+  SELINV_ESTATE = 6,       /* calls out of order (e.g. run before factor) */
+  SELINV_EUNSUPPORTED = 7  /* dtype / mode not supported */
+} selinv_status;
+
+/* Scheduling of the selected-inversion traversal (root to leaves). */
+typedef enum {
+  SELINV_SCHED_PERSISTENT = 0, /* one launch; per-node dependency counters + device ready queue */
+  SELINV_SCHED_LEVELS = 1      /* one launch per etree level and phase (reference schedule) */
+} selinv_sched;
+
+typedef struct {
+  int32_t max_super;   /* supernode size cap (Section 2.1: the definition may cap it); default 256 */
+  int32_t dtype;       /* selinv_dtype */
+  int32_t batch;       /* number of matrices sharing the pattern, >= 1 */
+  int32_t sched;       /* selinv_sched */
+  double relax;        /* explicit-zero budget of supernode chain amalgamation, 0 = maximal supernodes */
+  int32_t nthreads;    /* host threads for the factorization; 0 = hardware concurrency */
+  int32_t tile_rows;   /* GEMM-1 row tile (64 or 128); 0 = autotuned default */
+  int64_t watchdog_ms; /* persistent kernel spin budget before it aborts (0 = 10000 ms) */
+} selinv_opts;
+
+/* Fill `o` with defaults (cap 256, R64, batch 1, persistent, relax 0). */
+void selinv_default_opts(selinv_opts *o);
+
+/*
+ * selinv_analyze -- symbolic analysis (Section 2.1, Eq. (newset)).
+ *   n, colptr[n+1], rowind[colptr[n]]: A's lower pattern (host, borrowed).
+ *   perm[n]: new -> old permutation or NULL.
+ *   opts: NULL = defaults.
+ * Computes B's pattern, the column elimination tree, column counts, the
+ * supernode partition (maximal supernodes capped at max_super, optionally
+ * relaxed along etree chains), C(K), the supernodal etree and the ancestor
+ * index maps.  Errors: SELINV_EPATTERN (error_info(0) = offending column),
+ * SELINV_EINVAL, SELINV_ENOMEM.  *out is owned by the caller and released
+ * with selinv_destroy.
+ */
+selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *rowind,
+                             const int64_t *perm, const selinv_opts *opts, selinv_ctx **out);
+
+/* Host views of the symbolic data; pointers stay valid until selinv_destroy. */
+typedef struct {
+  int64_t n, nsuper, nnzL, panel_elems, batch, dtype;
+  const int64_t *perm;       /* [n] new -> old */
+  const int64_t *parent;     /* [n] column etree, -1 = root */
+  const int64_t *colcount;   /* [n] nnz of each column of L, diagonal included */
+  const int64_t *xsuper;     /* [nsuper+1] */
+  const int64_t *sparent;    /* [nsuper] supernodal etree, -1 = root */
+  const int64_t *rowptr;     /* [nsuper+1] C(K) = rowind_L[rowptr[K] .. rowptr[K+1]) */
+  const int64_t *rowind_L;   /* sorted row sets */
+  const int64_t *panel_off;  /* [nsuper] element offset of K's panel inside one matrix */
+  /* canonical ancestor maps: segments of K are seg_ptr[K] .. seg_ptr[K+1]-1;
+     segment g: owner seg_super[g], first index seg_start[g] into C(K); the
+     panel-row positions inside the owner of rows C(K)[seg_start[g]:] are
+     posarr[seg_posoff[g] ...] */
+  const int64_t *seg_ptr, *seg_super, *seg_start, *seg_posoff;
+  const int32_t *posarr;
+  int64_t nseg, nposarr;
+  double flops_exact;        /* sum_K 2c^2 s + 2 c s^2 over the maximal (relax = 0) partition, x4 for complex */
+  double flops;              /* the same over the partition in use */
+  int64_t depth;             /* supernodal etree height */
+} selinv_symbolic_view;
+
+selinv_status selinv_symbolic(const selinv_ctx *h, selinv_symbolic_view *v);
+
+/* Device buffer sizes in bytes (each a multiple of 256). */
+typedef struct {
+  int64_t panels_bytes;  /* factor panels, batch * panel_elems scalars */
+  int64_t x_bytes;       /* selected inverse, same layout */
+  int64_t work_bytes;    /* device tables, normalize scratch, counters, queue */
+  int64_t dtilde_bytes;  /* optional pivot blocks Dt_K (needed by selinv_backward) */
+  int64_t abar_bytes;    /* adjoint output on A's pattern, batch * nnz(A) scalars */
+} selinv_sizes_t;
+
+selinv_status selinv_sizes(const selinv_ctx *h, selinv_sizes_t *s);
+
+/*
+ * selinv_factor -- numeric factorization and normalization.
+ *   values (host): [batch][nnz(A)] in A's rowind order.
+ *   panels_dev, work_dev (device, caller-owned, sizes from selinv_sizes).
+ *   dtilde_dev: device buffer of dtilde_bytes or NULL (then selinv_backward
+ *   is unavailable for this factorization).
+ * Host: unpivoted supernodal LDL^T of every matrix of the batch (the paper
+ * takes the factors from an external solver with no dynamic pivoting,
+ * Section 4), then an asynchronous copy to panels_dev.  Device: the
+ * normalize kernels of Alg. 1 steps 1-2 (Lhat_{C,K} = L_{C,K} L_KK^{-1},
+ * Dt_K^{-1} = (L_KK D_K L_KK^T)^{-1}), which leave Dt_K^{-1} in the top s x s
+ * block and Lhat_{C,K} in the bottom c x s block of each panel.
+ * Errors: SELINV_ESINGULAR on an exactly zero or non-finite pivot
+ * (error_info(0) = column of B, error_info(1) = batch index).
+ * Uploads the device tables into work_dev on the first call.
+ */
+selinv_status selinv_factor(selinv_ctx *h, const void *values, void *panels_dev, void *work_dev,
+                            void *dtilde_dev, void *stream);
+
+/*
+ * selinv_factor_host -- the host part of selinv_factor only: the LDL^T
+ * panels (strict lower L_KK, D_K on the diagonal, L_{C,K} below) of every
+ * matrix into panels_host ([batch][panel_elems] scalars, caller-owned).  No
+ * device work; does not enable selinv_run.  Errors as selinv_factor.
+ */
+selinv_status selinv_factor_host(selinv_ctx *h, const void *values, void *panels_host);
+
+/*
+ * selinv_run -- selected inversion (Alg. 1 second loop / Alg. 2, LDL^T form).
+ * For every supernode K, root first:
+ *   X_{C,K} = -X_{C,C} Lhat_{C,K};  X_KK = Dt_K^{-1} - Lhat_{C,K}^T X_{C,K};
+ *   X_KK <- (X_KK + X_KK^T) / 2.
+ * Reads panels_dev (normalized), writes x_dev (same layout: top block = the
+ * full symmetric X_KK, bottom block = X_{C,K}).  Asynchronous on `stream`.
+ */
+selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, void *work_dev, void *stream);
+
+/*
+ * selinv_extract -- X on A's stored lower pattern, original indexing:
+ * out_dev[l][e] = (A^{-1})_{rowind[e], col(e)} of matrix l.  Asynchronous.
+ */
+selinv_status selinv_extract(const selinv_ctx *h, const void *x_dev, void *work_dev, void *out_dev,
+                             void *stream);
+
+/*
+ * selinv_backward -- adjoint of selinv_run composed with the factorization.
+ *   xbar_dev: dloss/dx for every stored selected value x_ij = (B^{-1})_ij
+ *   with (i, j) in the pattern of L, i >= j, in the panel layout (the strict
+ *   upper triangle of each top block is ignored).  It is overwritten (used as
+ *   accumulation space).
+ *   abar_dev: dloss/da for A's stored lower values ([batch][nnz(A)], a stored
+ *   off-diagonal value stands for both (i,j) and (j,i)).
+ * Needs dtilde_dev from selinv_factor.  R64 only.  Asynchronous.
+ */
+selinv_status selinv_backward(selinv_ctx *h, const void *panels_dev, const void *x_dev,
+                              const void *dtilde_dev, void *xbar_dev, void *work_dev, void *abar_dev,
+                              void *stream);
+
+/* log det of each matrix of the batch (sum of log pivots; complex log for C128).
+   out_host: batch doubles (R64) or batch (re, im) pairs (C128).  Valid after selinv_factor. */
+selinv_status selinv_logdet(const selinv_ctx *h, double *out_host);
+
+/* Wait for `stream` and report device-side errors (watchdog, HIP errors). */
+selinv_status selinv_sync(selinv_ctx *h, void *stream);
+
+const char *selinv_last_error(const selinv_ctx *h);
+int64_t selinv_error_info(const selinv_ctx *h, int which);
+void selinv_destroy(selinv_ctx *h);
+
+/* Library version string. */
+const char *selinv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SELINV_H */

@@ -1,0 +1,622 @@
+// C ABI of the selected-inversion library: context, device plan construction
+// and upload, and the entry points declared in include/selinv.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "plan.hpp"
+
+namespace selinv {
+hipError_t launch_normalize(const DevPlan &pl, const LaunchAux &aux, bool cplx_, void *panels, void *dt,
+                            hipStream_t st);
+hipError_t launch_run(const DevPlan &pl, const LaunchAux &aux, bool cplx_, int sched, const void *panels, void *x,
+                      int64_t budget_ticks, int grid, hipStream_t st);
+hipError_t launch_extract(const DevPlan &pl, bool cplx_, const void *x, void *out, hipStream_t st);
+int persistent_blocks_per_cu(bool cplx_);
+hipError_t launch_backward(const DevPlan &pl, const LaunchAux &aux, const void *panels, const void *x,
+                           const void *dt, void *xbar, void *abar, hipStream_t st);
+}  // namespace selinv
+
+using namespace selinv;
+
+namespace {
+
+constexpr int64_t kAlign = 256;
+inline int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Host image of every device table plus its byte offset in the work buffer.
+struct HostPlan {
+  std::vector<int32_t> node_s, node_c;
+  std::vector<int64_t> node_off, node_rowptr, node_sq, node_first;
+  std::vector<int64_t> kcol, kpos;
+  std::vector<Item> items;
+  std::vector<int32_t> item_ptr, n_phase1, n_phase2, first_beg, first_end, push_ptr, push_list, root_list;
+  std::vector<int32_t> lvl_items, lvl_ptr;
+  std::vector<int2> chunks;
+  std::vector<int4> sq_tiles;
+  std::vector<int64_t> apos;
+  std::vector<uint8_t> adiag;
+  int64_t sq_elems = 0;
+  // byte offsets inside the work buffer
+  struct Off {
+    int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, kcol, kpos, posarr, items, item_ptr,
+        n_phase1, n_phase2, first_beg, first_end, push_ptr, push_list, root_list, lvl_items, chunks, sq_tiles,
+        apos, adiag, linv, dinv, cnt1, cnt2, queue, ctrl, end;
+  } off{};
+  int64_t tables_bytes = 0;  // [0, tables_bytes) is uploaded once
+};
+
+template <typename V>
+void put(std::vector<unsigned char> &img, int64_t off, const std::vector<V> &v) {
+  if (!v.empty()) std::memcpy(img.data() + off, v.data(), sizeof(V) * v.size());
+}
+
+void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan &H) {
+  const int64_t ns = S.nsuper();
+  H.node_s.resize(ns);
+  H.node_c.resize(ns);
+  H.node_off = S.panel_off;
+  H.node_rowptr.assign(S.rowptr.begin(), S.rowptr.end() - 1);
+  H.node_sq.resize(ns);
+  H.node_first.assign(S.xsuper.begin(), S.xsuper.end() - 1);
+  int64_t sq = 0;
+  for (int64_t K = 0; K < ns; ++K) {
+    H.node_s[K] = (int32_t)S.width(K);
+    H.node_c[K] = (int32_t)S.nrows(K);
+    H.node_sq[K] = sq;
+    sq += S.width(K) * S.width(K);
+  }
+  H.sq_elems = sq;
+  // per-row gather tables
+  H.kcol.resize(S.rowind_L.size());
+  H.kpos.resize(S.rowind_L.size());
+  for (int64_t K = 0; K < ns; ++K) {
+    const int64_t c = S.nrows(K), rp = S.rowptr[K];
+    for (int64_t g = S.seg_ptr[K]; g < S.seg_ptr[K + 1]; ++g) {
+      const int64_t J = S.seg_super[g], st = S.seg_start[g];
+      const int64_t en = (g + 1 < S.seg_ptr[K + 1]) ? S.seg_start[g + 1] : c;
+      const int64_t ldJ = S.width(J) + S.nrows(J);
+      for (int64_t k = st; k < en; ++k) {
+        H.kcol[rp + k] = S.panel_off[J] + (S.rowind_L[rp + k] - S.xsuper[J]) * ldJ;
+        H.kpos[rp + k] = S.seg_posoff[g] - st;
+      }
+    }
+  }
+  // work items
+  H.item_ptr.assign(ns + 1, 0);
+  H.n_phase1.assign(ns, 0);
+  H.n_phase2.assign(ns, 0);
+  H.items.clear();
+  for (int64_t K = 0; K < ns; ++K) {
+    const int32_t s = H.node_s[K], c = H.node_c[K];
+    H.item_ptr[K] = (int32_t)H.items.size();
+    const int32_t nb = (s + kTileN - 1) / kTileN;
+    if (c <= kSmallC && s <= kSmallS) {
+      H.items.push_back(Item{(int32_t)K, ITEM_S, 0, 0});
+      H.n_phase2[K] = 1;
+    } else {
+      if (c > 0) {
+        const int32_t nr = (c + kTileM - 1) / kTileM;
+        for (int32_t b = 0; b < nb; ++b)
+          for (int32_t a = 0; a < nr; ++a) H.items.push_back(Item{(int32_t)K, ITEM_Y, a, b});
+        H.n_phase1[K] = nr * nb;
+      }
+      for (int32_t a = 0; a < nb; ++a)
+        for (int32_t b = 0; b <= a; ++b) H.items.push_back(Item{(int32_t)K, ITEM_D, a, b});
+      H.n_phase2[K] = nb * (nb + 1) / 2;
+    }
+  }
+  H.item_ptr[ns] = (int32_t)H.items.size();
+  H.first_beg.resize(ns);
+  H.first_end.resize(ns);
+  for (int64_t K = 0; K < ns; ++K) {
+    H.first_beg[K] = H.item_ptr[K];
+    H.first_end[K] = H.item_ptr[K] + (H.n_phase1[K] > 0 ? H.n_phase1[K] : H.n_phase2[K]);
+  }
+  std::vector<std::vector<int32_t>> kids(ns);
+  for (int64_t K = 0; K < ns; ++K)
+    if (S.sparent[K] >= 0) kids[S.sparent[K]].push_back((int32_t)K);
+  H.push_ptr.assign(ns + 1, 0);
+  H.push_list.clear();
+  for (int64_t K = 0; K < ns; ++K) {
+    H.push_ptr[K] = (int32_t)H.push_list.size();
+    for (int32_t ch : kids[K])
+      for (int32_t it = H.first_beg[ch]; it < H.first_end[ch]; ++it) H.push_list.push_back(it);
+  }
+  H.push_ptr[ns] = (int32_t)H.push_list.size();
+  H.root_list.clear();
+  for (int64_t K = 0; K < ns; ++K)
+    if (S.sparent[K] < 0)
+      for (int32_t it = H.first_beg[K]; it < H.first_end[K]; ++it) H.root_list.push_back(it);
+  // level lists (phase 1, then phase 2, per etree depth)
+  H.lvl_items.clear();
+  H.lvl_ptr.assign(1, 0);
+  {
+    std::vector<std::vector<int64_t>> bydepth(S.depth);
+    for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
+    for (int64_t d = 0; d < S.depth; ++d) {
+      for (int64_t K : bydepth[d])
+        for (int32_t q = 0; q < H.n_phase1[K]; ++q) H.lvl_items.push_back(H.item_ptr[K] + q);
+      H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
+      for (int64_t K : bydepth[d])
+        for (int32_t q = 0; q < H.n_phase2[K]; ++q) H.lvl_items.push_back(H.item_ptr[K] + H.n_phase1[K] + q);
+      H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
+    }
+  }
+  // normalization work lists
+  H.chunks.clear();
+  H.sq_tiles.clear();
+  for (int64_t K = 0; K < ns; ++K) {
+    const int32_t s = H.node_s[K], c = H.node_c[K];
+    const int32_t nch = (s + c + 255) / 256;
+    for (int32_t q = 0; q < nch; ++q) H.chunks.push_back(int2{(int32_t)K, q});
+    const int32_t nt = (s + 31) / 32;
+    for (int32_t a = 0; a < nt; ++a)
+      for (int32_t b = 0; b < nt; ++b) H.sq_tiles.push_back(int4{(int32_t)K, a, b, 0});
+  }
+  H.apos = S.apos;
+  H.adiag = S.apos_diag;
+
+  // layout
+  auto &o = H.off;
+  int64_t p = 0;
+  auto take = [&](int64_t bytes) {
+    int64_t r = p;
+    p = align_up(p + std::max<int64_t>(bytes, 1));
+    return r;
+  };
+  o.node_s = take(4 * ns);
+  o.node_c = take(4 * ns);
+  o.node_off = take(8 * ns);
+  o.node_rowptr = take(8 * ns);
+  o.node_sq = take(8 * ns);
+  o.node_first = take(8 * ns);
+  o.kcol = take(8 * (int64_t)H.kcol.size());
+  o.kpos = take(8 * (int64_t)H.kpos.size());
+  o.posarr = take(4 * (int64_t)S.posarr.size());
+  o.items = take(16 * (int64_t)H.items.size());
+  o.item_ptr = take(4 * (ns + 1));
+  o.n_phase1 = take(4 * ns);
+  o.n_phase2 = take(4 * ns);
+  o.first_beg = take(4 * ns);
+  o.first_end = take(4 * ns);
+  o.push_ptr = take(4 * (ns + 1));
+  o.push_list = take(4 * (int64_t)H.push_list.size());
+  o.root_list = take(4 * (int64_t)H.root_list.size());
+  o.lvl_items = take(4 * (int64_t)H.lvl_items.size());
+  o.chunks = take(8 * (int64_t)H.chunks.size());
+  o.sq_tiles = take(16 * (int64_t)H.sq_tiles.size());
+  o.apos = take(8 * (int64_t)H.apos.size());
+  o.adiag = take((int64_t)H.adiag.size());
+  H.tables_bytes = p;
+  o.linv = take(scalar_bytes * batch * H.sq_elems);
+  o.dinv = take(scalar_bytes * batch * S.n);
+  o.cnt1 = take(4 * batch * ns);
+  o.cnt2 = take(4 * batch * ns);
+  o.queue = take(4 * batch * (int64_t)H.items.size());
+  o.ctrl = take(4 * CTRL_WORDS);
+  o.end = p;
+}
+
+}  // namespace
+
+struct selinv_ctx {
+  Symbolic S;
+  selinv_opts opts{};
+  HostPlan H;
+  std::vector<unsigned char> image;  // tables image (host)
+  std::string err;
+  int64_t info[2] = {-1, -1};
+  std::vector<double> logdet;        // 2 per matrix
+  bool factored = false;
+  bool have_logdet = false;
+  void *uploaded_to = nullptr;       // work buffer holding the tables
+  int device = -1;
+  double *pinned = nullptr;          // host staging of the factor panels
+  size_t pinned_bytes = 0;
+  int64_t wall_khz = 0;
+  int grid = 0;
+  // cached strings for views
+  std::vector<int64_t> panel_off_view;
+
+  ~selinv_ctx() {
+    if (pinned) (void)hipHostFree(pinned);
+  }
+  bool is_complex() const { return opts.dtype == SELINV_C128; }
+  int64_t sbytes() const { return is_complex() ? 16 : 8; }
+};
+
+namespace {
+
+selinv_status set_err(selinv_ctx *h, selinv_status st, const std::string &m, int64_t i0 = -1, int64_t i1 = -1) {
+  if (h) {
+    h->err = m;
+    h->info[0] = i0;
+    h->info[1] = i1;
+  }
+  return st;
+}
+
+selinv_status hip_err(selinv_ctx *h, hipError_t e, const char *where) {
+  return set_err(h, SELINV_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+DevPlan make_devplan(const selinv_ctx *h, void *work) {
+  const auto &H = h->H;
+  const auto &o = H.off;
+  unsigned char *b = static_cast<unsigned char *>(work);
+  DevPlan d{};
+  d.n = h->S.n;
+  d.ns = h->S.nsuper();
+  d.nitems = (int64_t)H.items.size();
+  d.batch = h->opts.batch;
+  d.panel_elems = h->S.panel_elems;
+  d.sq_elems = H.sq_elems;
+  d.nnzA = h->S.nnzA;
+  d.total_rows = (int64_t)H.kcol.size();
+  d.node_s = (int32_t *)(b + o.node_s);
+  d.node_c = (int32_t *)(b + o.node_c);
+  d.node_off = (int64_t *)(b + o.node_off);
+  d.node_rowptr = (int64_t *)(b + o.node_rowptr);
+  d.node_sq = (int64_t *)(b + o.node_sq);
+  d.node_first = (int64_t *)(b + o.node_first);
+  d.kcol = (int64_t *)(b + o.kcol);
+  d.kpos = (int64_t *)(b + o.kpos);
+  d.posarr = (int32_t *)(b + o.posarr);
+  d.items = (Item *)(b + o.items);
+  d.item_ptr = (int32_t *)(b + o.item_ptr);
+  d.n_phase1 = (int32_t *)(b + o.n_phase1);
+  d.n_phase2 = (int32_t *)(b + o.n_phase2);
+  d.first_beg = (int32_t *)(b + o.first_beg);
+  d.first_end = (int32_t *)(b + o.first_end);
+  d.push_ptr = (int32_t *)(b + o.push_ptr);
+  d.push_list = (int32_t *)(b + o.push_list);
+  d.root_list = (int32_t *)(b + o.root_list);
+  d.nroot_items = (int32_t)H.root_list.size();
+  d.lvl_items = (int32_t *)(b + o.lvl_items);
+  d.apos = (int64_t *)(b + o.apos);
+  d.adiag = (uint8_t *)(b + o.adiag);
+  d.linv = (void *)(b + o.linv);
+  d.dinv = (void *)(b + o.dinv);
+  d.cnt1 = (int32_t *)(b + o.cnt1);
+  d.cnt2 = (int32_t *)(b + o.cnt2);
+  d.queue = (int32_t *)(b + o.queue);
+  d.ctrl = (int32_t *)(b + o.ctrl);
+  return d;
+}
+
+LaunchAux make_aux(const selinv_ctx *h, void *work) {
+  const auto &H = h->H;
+  unsigned char *b = static_cast<unsigned char *>(work);
+  LaunchAux a{};
+  a.chunks = (const int2 *)(b + H.off.chunks);
+  a.nchunks = (int32_t)H.chunks.size();
+  a.sq_tiles = (const int4 *)(b + H.off.sq_tiles);
+  a.nsq_tiles = (int32_t)H.sq_tiles.size();
+  a.lvl_items = (const int32_t *)(b + H.off.lvl_items);
+  a.lvl_ptr = H.lvl_ptr.data();
+  a.nlvl = (int32_t)H.lvl_ptr.size() - 1;
+  return a;
+}
+
+void build_image(selinv_ctx *h) {
+  auto &H = h->H;
+  const auto &o = H.off;
+  h->image.assign((size_t)H.tables_bytes, 0);
+  auto &img = h->image;
+  put(img, o.node_s, H.node_s);
+  put(img, o.node_c, H.node_c);
+  put(img, o.node_off, H.node_off);
+  put(img, o.node_rowptr, H.node_rowptr);
+  put(img, o.node_sq, H.node_sq);
+  put(img, o.node_first, H.node_first);
+  put(img, o.kcol, H.kcol);
+  put(img, o.kpos, H.kpos);
+  put(img, o.posarr, h->S.posarr);
+  put(img, o.items, H.items);
+  put(img, o.item_ptr, H.item_ptr);
+  put(img, o.n_phase1, H.n_phase1);
+  put(img, o.n_phase2, H.n_phase2);
+  put(img, o.first_beg, H.first_beg);
+  put(img, o.first_end, H.first_end);
+  put(img, o.push_ptr, H.push_ptr);
+  put(img, o.push_list, H.push_list);
+  put(img, o.root_list, H.root_list);
+  put(img, o.lvl_items, H.lvl_items);
+  put(img, o.chunks, H.chunks);
+  put(img, o.sq_tiles, H.sq_tiles);
+  put(img, o.apos, H.apos);
+  put(img, o.adiag, H.adiag);
+}
+
+selinv_status ensure_uploaded(selinv_ctx *h, void *work, hipStream_t st) {
+  if (h->uploaded_to == work) return SELINV_OK;
+  hipError_t e = hipMemcpyAsync(work, h->image.data(), h->image.size(), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_err(h, e, "table upload");
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_err(h, e, "table upload sync");
+  h->uploaded_to = work;
+  return SELINV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void selinv_default_opts(selinv_opts *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->max_super = 256;
+  o->dtype = SELINV_R64;
+  o->batch = 1;
+  o->sched = SELINV_SCHED_PERSISTENT;
+  o->relax = 0.0;
+  o->nthreads = 0;
+  o->tile_rows = 0;
+  o->watchdog_ms = 0;
+}
+
+const char *selinv_version(void) { return "selinv-mi355x 0.1"; }
+
+selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *rowind, const int64_t *perm,
+                             const selinv_opts *opts, selinv_ctx **out) {
+  if (!out) return SELINV_EINVAL;
+  *out = nullptr;
+  selinv_ctx *h = new (std::nothrow) selinv_ctx();
+  if (!h) return SELINV_ENOMEM;
+  if (opts)
+    h->opts = *opts;
+  else
+    selinv_default_opts(&h->opts);
+  *out = h;
+  const selinv_opts &o = h->opts;
+  if (o.dtype != SELINV_R64 && o.dtype != SELINV_C128) return set_err(h, SELINV_EUNSUPPORTED, "unknown dtype");
+  if (o.batch < 1) return set_err(h, SELINV_EINVAL, "batch must be >= 1");
+  if (o.max_super < 1 || o.max_super > 256) return set_err(h, SELINV_EINVAL, "max_super must be in [1, 256]");
+  if (o.sched != SELINV_SCHED_PERSISTENT && o.sched != SELINV_SCHED_LEVELS)
+    return set_err(h, SELINV_EINVAL, "unknown schedule");
+  try {
+    analyze(h->S, n, colptr, rowind, perm, o.max_super, o.relax);
+    build_plan(h->S, o.batch, h->sbytes(), h->H);
+    if ((int64_t)h->H.items.size() * (int64_t)o.batch >= (int64_t)INT32_MAX)
+      return set_err(h, SELINV_ENOMEM, "too many work items for int32 queue entries");
+    build_image(h);
+  } catch (const Failure &f) {
+    return set_err(h, f.status, f.msg, f.info0, f.info1);
+  } catch (const std::bad_alloc &) {
+    return set_err(h, SELINV_ENOMEM, "host allocation failed in analyze");
+  } catch (...) {
+    return set_err(h, SELINV_EINVAL, "unexpected failure in analyze");
+  }
+  h->logdet.assign(2 * (size_t)o.batch, 0.0);
+  return SELINV_OK;
+}
+
+selinv_status selinv_symbolic(const selinv_ctx *h, selinv_symbolic_view *v) {
+  if (!h || !v) return SELINV_EINVAL;
+  const Symbolic &S = h->S;
+  if (S.n == 0) return SELINV_ESTATE;
+  std::memset(v, 0, sizeof(*v));
+  v->n = S.n;
+  v->nsuper = S.nsuper();
+  v->nnzL = S.nnzL;
+  v->panel_elems = S.panel_elems;
+  v->batch = h->opts.batch;
+  v->dtype = h->opts.dtype;
+  v->perm = S.perm.data();
+  v->parent = S.parent.data();
+  v->colcount = S.colcount.data();
+  v->xsuper = S.xsuper.data();
+  v->sparent = S.sparent.data();
+  v->rowptr = S.rowptr.data();
+  v->rowind_L = S.rowind_L.data();
+  v->panel_off = S.panel_off.data();
+  v->seg_ptr = S.seg_ptr.data();
+  v->seg_super = S.seg_super.data();
+  v->seg_start = S.seg_start.data();
+  v->seg_posoff = S.seg_posoff.data();
+  v->posarr = S.posarr.data();
+  v->nseg = (int64_t)S.seg_super.size();
+  v->nposarr = (int64_t)S.posarr.size();
+  const double mul = h->is_complex() ? 4.0 : 1.0;
+  v->flops = S.flops * mul;
+  v->flops_exact = S.flops_exact * mul;
+  v->depth = S.depth;
+  return SELINV_OK;
+}
+
+selinv_status selinv_sizes(const selinv_ctx *h, selinv_sizes_t *s) {
+  if (!h || !s) return SELINV_EINVAL;
+  if (h->S.n == 0) return SELINV_ESTATE;
+  const int64_t B = h->opts.batch, sb = h->sbytes();
+  s->panels_bytes = align_up(B * h->S.panel_elems * sb);
+  s->x_bytes = s->panels_bytes;
+  s->work_bytes = h->H.off.end;
+  s->dtilde_bytes = align_up(B * h->H.sq_elems * sb);
+  s->abar_bytes = align_up(B * h->S.nnzA * sb);
+  return SELINV_OK;
+}
+
+selinv_status selinv_factor(selinv_ctx *h, const void *values, void *panels_dev, void *work_dev, void *dtilde_dev,
+                            void *stream) {
+  if (!h) return SELINV_EINVAL;
+  if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
+  if (!values || !panels_dev || !work_dev) return set_err(h, SELINV_EINVAL, "null buffer");
+  hipStream_t st = (hipStream_t)stream;
+  h->factored = false;
+  h->have_logdet = false;
+  const int64_t B = h->opts.batch, sb = h->sbytes(), pe = h->S.panel_elems;
+  const size_t need = (size_t)(B * pe * sb);
+  hipError_t e;
+  if (h->pinned_bytes < need) {
+    if (h->pinned) (void)hipHostFree(h->pinned);
+    h->pinned = nullptr;
+    h->pinned_bytes = 0;
+    e = hipHostMalloc((void **)&h->pinned, need, 0);
+    if (e != hipSuccess) return hip_err(h, e, "pinned staging allocation");
+    h->pinned_bytes = need;
+  }
+  const int64_t scal = h->is_complex() ? 2 : 1;
+  const double *vals = static_cast<const double *>(values);
+  try {
+    for (int64_t l = 0; l < B; ++l) {
+      double ld[2] = {0.0, 0.0};
+      int64_t bad = factor_host(h->S, h->is_complex(), vals + l * h->S.nnzA * scal, h->pinned + l * pe * scal,
+                                h->opts.nthreads, ld);
+      if (bad >= 0) return set_err(h, SELINV_ESINGULAR, "zero or non-finite pivot", bad, l);
+      h->logdet[2 * l] = ld[0];
+      h->logdet[2 * l + 1] = ld[1];
+    }
+  } catch (const std::bad_alloc &) {
+    return set_err(h, SELINV_ENOMEM, "host allocation failed in factor");
+  }
+  h->have_logdet = true;
+  selinv_status ss = ensure_uploaded(h, work_dev, st);
+  if (ss != SELINV_OK) return ss;
+  e = hipMemcpyAsync(panels_dev, h->pinned, need, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_err(h, e, "panel upload");
+  DevPlan pl = make_devplan(h, work_dev);
+  LaunchAux aux = make_aux(h, work_dev);
+  e = launch_normalize(pl, aux, h->is_complex(), panels_dev, dtilde_dev, st);
+  if (e != hipSuccess) return hip_err(h, e, "normalize launch");
+  // the staging buffer is reused by the next call: wait for the copy
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_err(h, e, "factor sync");
+  h->factored = true;
+  return SELINV_OK;
+}
+
+selinv_status selinv_factor_host(selinv_ctx *h, const void *values, void *panels_host) {
+  if (!h) return SELINV_EINVAL;
+  if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
+  if (!values || !panels_host) return set_err(h, SELINV_EINVAL, "null buffer");
+  h->have_logdet = false;
+  const int64_t B = h->opts.batch, pe = h->S.panel_elems;
+  const int64_t scal = h->is_complex() ? 2 : 1;
+  const double *vals = static_cast<const double *>(values);
+  double *out = static_cast<double *>(panels_host);
+  try {
+    for (int64_t l = 0; l < B; ++l) {
+      double ld[2] = {0.0, 0.0};
+      int64_t bad = factor_host(h->S, h->is_complex(), vals + l * h->S.nnzA * scal, out + l * pe * scal,
+                                h->opts.nthreads, ld);
+      if (bad >= 0) return set_err(h, SELINV_ESINGULAR, "zero or non-finite pivot", bad, l);
+      h->logdet[2 * l] = ld[0];
+      h->logdet[2 * l + 1] = ld[1];
+    }
+  } catch (const std::bad_alloc &) {
+    return set_err(h, SELINV_ENOMEM, "host allocation failed in factor");
+  }
+  h->have_logdet = true;
+  return SELINV_OK;
+}
+
+selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, void *work_dev, void *stream) {
+  if (!h) return SELINV_EINVAL;
+  if (!h->factored) return set_err(h, SELINV_ESTATE, "selinv_run before a successful selinv_factor");
+  if (!panels_dev || !x_dev || !work_dev) return set_err(h, SELINV_EINVAL, "null buffer");
+  hipStream_t st = (hipStream_t)stream;
+  selinv_status ss = ensure_uploaded(h, work_dev, st);
+  if (ss != SELINV_OK) return ss;
+  hipError_t e;
+  if (h->grid == 0) {
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_err(h, e, "hipGetDevice");
+    int ncu = 0, khz = 0;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_err(h, e, "device attribute");
+    e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return hip_err(h, e, "device attribute");
+    int per = persistent_blocks_per_cu(h->is_complex());
+    if (per < 1) per = 1;
+    h->grid = ncu * per;
+    h->wall_khz = khz > 0 ? khz : 100000;
+  }
+  const int64_t ms = h->opts.watchdog_ms > 0 ? h->opts.watchdog_ms : 10000;
+  const int64_t budget = ms * h->wall_khz;
+  DevPlan pl = make_devplan(h, work_dev);
+  LaunchAux aux = make_aux(h, work_dev);
+  e = launch_run(pl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, budget, h->grid, st);
+  if (e != hipSuccess) return hip_err(h, e, "selinv launch");
+  return SELINV_OK;
+}
+
+selinv_status selinv_extract(const selinv_ctx *hc, const void *x_dev, void *work_dev, void *out_dev, void *stream) {
+  selinv_ctx *h = const_cast<selinv_ctx *>(hc);
+  if (!h) return SELINV_EINVAL;
+  if (!x_dev || !out_dev || !work_dev) return set_err(h, SELINV_EINVAL, "null buffer");
+  hipStream_t st = (hipStream_t)stream;
+  selinv_status ss = ensure_uploaded(h, work_dev, st);
+  if (ss != SELINV_OK) return ss;
+  DevPlan pl = make_devplan(h, work_dev);
+  hipError_t e = launch_extract(pl, h->is_complex(), x_dev, out_dev, st);
+  if (e != hipSuccess) return hip_err(h, e, "extract launch");
+  return SELINV_OK;
+}
+
+selinv_status selinv_backward(selinv_ctx *h, const void *panels_dev, const void *x_dev, const void *dtilde_dev,
+                              void *xbar_dev, void *work_dev, void *abar_dev, void *stream) {
+  if (!h) return SELINV_EINVAL;
+  if (!h->factored) return set_err(h, SELINV_ESTATE, "selinv_backward before a successful selinv_factor");
+  if (h->is_complex()) return set_err(h, SELINV_EUNSUPPORTED, "the adjoint is implemented for R64 only");
+  if (!panels_dev || !x_dev || !dtilde_dev || !xbar_dev || !work_dev || !abar_dev)
+    return set_err(h, SELINV_EINVAL, "null buffer");
+  hipStream_t st = (hipStream_t)stream;
+  selinv_status ss = ensure_uploaded(h, work_dev, st);
+  if (ss != SELINV_OK) return ss;
+  DevPlan pl = make_devplan(h, work_dev);
+  LaunchAux aux = make_aux(h, work_dev);
+  hipError_t e = launch_backward(pl, aux, panels_dev, x_dev, dtilde_dev, xbar_dev, abar_dev, st);
+  if (e != hipSuccess) return hip_err(h, e, "backward launch");
+  return SELINV_OK;
+}
+
+selinv_status selinv_logdet(const selinv_ctx *hc, double *out_host) {
+  selinv_ctx *h = const_cast<selinv_ctx *>(hc);
+  if (!h || !out_host) return SELINV_EINVAL;
+  if (!h->have_logdet) return set_err(h, SELINV_ESTATE, "selinv_logdet before a successful factorization");
+  for (int64_t l = 0; l < h->opts.batch; ++l) {
+    if (h->is_complex()) {
+      out_host[2 * l] = h->logdet[2 * l];
+      out_host[2 * l + 1] = h->logdet[2 * l + 1];
+    } else {
+      out_host[l] = h->logdet[2 * l];
+    }
+  }
+  return SELINV_OK;
+}
+
+selinv_status selinv_sync(selinv_ctx *h, void *stream) {
+  if (!h) return SELINV_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_err(h, e, "stream synchronize");
+  if (h->uploaded_to && h->opts.sched == SELINV_SCHED_PERSISTENT) {
+    int32_t ctrl[4] = {0, 0, 0, 0};
+    const unsigned char *b = static_cast<const unsigned char *>(h->uploaded_to);
+    e = hipMemcpy(ctrl, b + h->H.off.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_err(h, e, "control readback");
+    if (ctrl[CTRL_ERR] != 0)
+      return set_err(h, SELINV_EDEVICE, "persistent scheduler watchdog expired (ready queue stalled)");
+  }
+  return SELINV_OK;
+}
+
+const char *selinv_last_error(const selinv_ctx *h) { return h ? h->err.c_str() : "null context"; }
+
+int64_t selinv_error_info(const selinv_ctx *h, int which) {
+  if (!h || which < 0 || which > 1) return -1;
+  return h->info[which];
+}
+
+void selinv_destroy(selinv_ctx *h) { delete h; }
+
+}  // extern "C"

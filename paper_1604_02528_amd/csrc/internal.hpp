@@ -1,0 +1,61 @@
+// Internal declarations shared by the host-side translation units of the
+// selected-inversion library (symbolic analysis, host factorization, device
+// plan and the C ABI).  Nothing here is exported.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/selinv.h"
+
+namespace selinv {
+
+struct Failure {
+  selinv_status status;
+  std::string msg;
+  int64_t info0 = -1;
+  int64_t info1 = -1;
+};
+
+// Symbolic data of B = P A P^T (Section 2.1; Eq. (newset) for C(K)).
+struct Symbolic {
+  int64_t n = 0;
+  int64_t nnzA = 0;
+  int64_t cap = 256;
+  double relax = 0.0;
+  std::vector<int64_t> perm, iperm;          // new -> old, old -> new
+  std::vector<int64_t> Bcolptr, Browind;      // lower CSC of B
+  std::vector<int64_t> amap;                  // A entry -> B entry
+  std::vector<int64_t> parent, colcount;      // column etree, nnz per column of L
+  std::vector<int64_t> xsuper, col2super, sparent;
+  std::vector<int64_t> rowptr, rowind_L;      // C(K)
+  std::vector<int64_t> panel_off;             // element offset of K's panel
+  int64_t panel_elems = 0;
+  std::vector<int64_t> seg_ptr, seg_super, seg_start, seg_posoff;
+  std::vector<int32_t> posarr;
+  std::vector<int64_t> apos;                  // A entry -> element offset inside one matrix's panels
+  std::vector<uint8_t> apos_diag;             // A entry is a diagonal entry
+  std::vector<int64_t> sdepth;                // depth of each supernode (root = 0)
+  int64_t depth = 0;
+  int64_t nnzL = 0;
+  double flops = 0.0, flops_exact = 0.0;      // real-arithmetic counts (x4 applied by the caller for C128)
+
+  int64_t nsuper() const { return (int64_t)xsuper.size() - 1; }
+  int64_t width(int64_t K) const { return xsuper[K + 1] - xsuper[K]; }
+  int64_t nrows(int64_t K) const { return rowptr[K + 1] - rowptr[K]; }
+};
+
+// Throws Failure on malformed input.
+void analyze(Symbolic &S, int64_t n, const int64_t *colptr, const int64_t *rowind, const int64_t *perm,
+             int64_t cap, double relax);
+
+// Host numeric factorization into LDL^T panels (strict lower L_KK, D_K on the
+// diagonal, L_{C,K} below).  `vals` points at one matrix's values in A order;
+// `panels` receives panel_elems scalars.  Real or complex (interleaved).
+// Returns the failing column (>= 0) on a zero / non-finite pivot, else -1.
+// logdet receives sum log D_jj (re, im).
+int64_t factor_host(const Symbolic &S, bool is_complex, const double *vals, double *panels, int nthreads,
+                    double logdet[2]);
+
+}  // namespace selinv

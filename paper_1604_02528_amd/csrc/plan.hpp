@@ -1,0 +1,75 @@
+// Device plan: the tables the kernels read, their layout inside the caller's
+// work buffer, and the work-item vocabulary of the traversal.
+//
+// Work items (one workgroup each):
+//   ITEM_Y  (K, a, b): rows 64a.. of X_{C,K} and columns 64b.. -- the gather of
+//           X_{C,C} through the ancestor maps and GEMM-1 X_{C,K} = -X_{C,C} Lhat_{C,K}
+//           (Alg. 1 step 3).
+//   ITEM_D  (K, a, b), a >= b: blocks (a, b) and (b, a) of X_KK = Dt_K^{-1} -
+//           Lhat_{C,K}^T X_{C,K} (step 4), symmetrized (Section 2.3).
+//   ITEM_S  (K): a node with c <= 64 and s <= 64 done by one workgroup.
+// Phase 1 of a node = its ITEM_Y items, phase 2 = its ITEM_D / ITEM_S items.
+// A node's first phase becomes ready when its parent's phase 2 is done
+// (C(K) lies in the ancestors, Eq. (newset)); phase 2 becomes ready when its
+// phase 1 is done.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace selinv {
+
+enum ItemType : int32_t { ITEM_Y = 0, ITEM_D = 1, ITEM_S = 2 };
+
+constexpr int kTileM = 64;   // GEMM-1 rows per item
+constexpr int kTileN = 64;   // columns per item (of s)
+constexpr int kSmallC = 64;  // fused single-item node bounds
+constexpr int kSmallS = 64;
+
+struct alignas(16) Item {
+  int32_t K, type, a, b;
+};
+
+// Control words of the persistent scheduler.
+enum Ctrl : int32_t { CTRL_HEAD = 0, CTRL_TAIL = 1, CTRL_ERR = 2, CTRL_DONE = 3, CTRL_WORDS = 64 };
+
+// Raw device pointers, valid for one (context, work buffer) pair.
+struct DevPlan {
+  int64_t n, ns, nitems, batch, panel_elems, sq_elems, nnzA, total_rows;
+  int32_t *node_s, *node_c;
+  int64_t *node_off, *node_rowptr, *node_sq, *node_first;
+  int64_t *kcol, *kpos;
+  int32_t *posarr;
+  Item *items;
+  int32_t *item_ptr;   // [ns+1]
+  int32_t *n_phase1;   // [ns]
+  int32_t *n_phase2;   // [ns]
+  int32_t *first_beg, *first_end;  // [ns] range of a node's first-phase items
+  int32_t *push_ptr;   // [ns+1] children's first items, flattened
+  int32_t *push_list;
+  int32_t *root_list;  // items of all roots' first phases
+  int32_t nroot_items;
+  int32_t *lvl_items;  // item ids grouped by (level, phase)
+  int64_t *apos;       // [nnzA] A entry -> panel element
+  uint8_t *adiag;      // [nnzA]
+  // scratch
+  void *linv;          // [batch][sq_elems] scalars
+  void *dinv;          // [batch][n] scalars
+  int32_t *cnt1, *cnt2;  // [batch][ns]
+  int32_t *queue;      // [batch * nitems]
+  int32_t *ctrl;       // CTRL_WORDS
+};
+
+// Host-side launch lists (device pointers into the work buffer, except lvl_ptr).
+struct LaunchAux {
+  const int2 *chunks;       // normalization row chunks (K, chunk)
+  int32_t nchunks;
+  const int4 *sq_tiles;     // normalization 32 x 32 tiles (K, ti, tj, 0)
+  int32_t nsq_tiles;
+  const int32_t *lvl_items; // item ids grouped by (level, phase)
+  const int32_t *lvl_ptr;   // host array [nlvl + 1]
+  int32_t nlvl;
+};
+
+}  // namespace selinv

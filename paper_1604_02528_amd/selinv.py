@@ -1,0 +1,151 @@
+"""High-level handle over the C ABI: device buffers and streams from torch.
+
+    S = SelInv(n, colptr, rowind, perm, dtype="f64", batch=1)
+    S.factor(values)          # host LDL^T + upload + normalize kernels
+    S.run()                   # selected inversion on the GPU (async)
+    X = S.extract()           # [batch, nnz(A)] selected entries on A's pattern
+
+Everything numeric runs in the library (host C++ factorization, HIP kernels
+for the rest); this module only allocates buffers and passes pointers.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import capi
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _bytes(nbytes, device):
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class SelInv:
+    def __init__(self, n, colptr, rowind, perm=None, *, dtype="f64", batch=1, cap=256, relax=0.0,
+                 sched="persistent", nthreads=0, watchdog_ms=0, device="cuda"):
+        self.n = int(n)
+        self.is_complex = dtype in ("c128", "complex128", torch.complex128)
+        self.batch = int(batch)
+        self.device = device
+        o = capi.selinv_default_opts()
+        o.max_super = int(cap)
+        o.dtype = capi.SELINV_C128 if self.is_complex else capi.SELINV_R64
+        o.batch = self.batch
+        o.sched = capi.SCHED_LEVELS if sched == "levels" else capi.SCHED_PERSISTENT
+        o.relax = float(relax)
+        o.nthreads = int(nthreads)
+        o.watchdog_ms = int(watchdog_ms)
+        self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
+        self._rowind = np.ascontiguousarray(rowind, dtype=np.int64)
+        self._perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
+        self.h = capi.selinv_analyze(self.n, self._colptr, self._rowind, self._perm, o)
+        self.view = capi.selinv_symbolic(self.h)
+        self.sizes = capi.selinv_sizes(self.h)
+        self.nnzA = int(self._colptr[-1])
+        self.panel_elems = int(self.view.panel_elems)
+        self._bufs = None
+        self.dtilde = None
+
+    # -- symbolic data (host copies) -------------------------------------------
+    def symbolic(self):
+        v = self.view
+        ns, n = int(v.nsuper), int(v.n)
+        arr = lambda p, m: np.ctypeslib.as_array(p, shape=(m,)).copy() if m > 0 else np.zeros(0, np.int64)
+        rowptr = arr(v.rowptr, ns + 1)
+        return {
+            "n": n, "nsuper": ns, "nnzL": int(v.nnzL), "panel_elems": int(v.panel_elems),
+            "perm": arr(v.perm, n), "parent": arr(v.parent, n), "colcount": arr(v.colcount, n),
+            "xsuper": arr(v.xsuper, ns + 1), "sparent": arr(v.sparent, ns), "rowptr": rowptr,
+            "rowind_L": arr(v.rowind_L, int(rowptr[-1])), "panel_off": arr(v.panel_off, ns),
+            "seg_ptr": arr(v.seg_ptr, ns + 1), "seg_super": arr(v.seg_super, int(v.nseg)),
+            "seg_start": arr(v.seg_start, int(v.nseg)), "seg_posoff": arr(v.seg_posoff, int(v.nseg)),
+            "posarr": arr(v.posarr, int(v.nposarr)),
+            "flops": float(v.flops), "flops_exact": float(v.flops_exact), "depth": int(v.depth),
+        }
+
+    # -- buffers -----------------------------------------------------------------
+    @property
+    def scalar_dtype(self):
+        return torch.complex128 if self.is_complex else torch.float64
+
+    def _alloc(self, want_dtilde):
+        if self._bufs is None:
+            s = self.sizes
+            self._bufs = {
+                "panels": _bytes(s.panels_bytes, self.device),
+                "x": _bytes(s.x_bytes, self.device),
+                "work": _bytes(s.work_bytes, self.device),
+            }
+        if want_dtilde and self.dtilde is None:
+            self.dtilde = _bytes(self.sizes.dtilde_bytes, self.device)
+
+    def panels_view(self, which="x"):
+        """[batch, panel_elems] view of the panels or of X."""
+        b = self._bufs[which]
+        nb = self.batch * self.panel_elems * (16 if self.is_complex else 8)
+        return b[:nb].view(self.scalar_dtype).view(self.batch, self.panel_elems)
+
+    # -- numeric -----------------------------------------------------------------
+    def _values_host(self, values):
+        if isinstance(values, torch.Tensor):
+            values = values.detach().cpu().numpy()
+        dt = np.complex128 if self.is_complex else np.float64
+        v = np.ascontiguousarray(np.asarray(values).reshape(self.batch, self.nnzA), dtype=dt)
+        return v
+
+    def factor(self, values, want_dtilde=False):
+        self._alloc(want_dtilde)
+        v = self._values_host(values)
+        self._vals_keep = v
+        capi.selinv_factor(self.h, v, self._bufs["panels"], self._bufs["work"],
+                           self.dtilde if want_dtilde else None, _stream())
+
+    def factor_host(self, values):
+        """Host LDL^T panels only (numpy [batch, panel_elems])."""
+        v = self._values_host(values)
+        out = np.zeros((self.batch, self.panel_elems), dtype=np.complex128 if self.is_complex else np.float64)
+        capi.selinv_factor_host(self.h, v, out)
+        return out
+
+    def run(self):
+        capi.selinv_run(self.h, self._bufs["panels"], self._bufs["x"], self._bufs["work"], _stream())
+
+    def sync(self):
+        capi.selinv_sync(self.h, _stream())
+
+    def extract(self, out=None):
+        if out is None:
+            out = torch.empty((self.batch, self.nnzA), dtype=self.scalar_dtype, device=self.device)
+        capi.selinv_extract(self.h, self._bufs["x"], self._bufs["work"], out, _stream())
+        return out
+
+    def backward(self, xbar, abar=None):
+        """xbar: [batch, panel_elems] device tensor (overwritten)."""
+        if abar is None:
+            abar = torch.empty((self.batch, self.nnzA), dtype=self.scalar_dtype, device=self.device)
+        capi.selinv_backward(self.h, self._bufs["panels"], self._bufs["x"], self.dtilde, xbar,
+                             self._bufs["work"], abar, _stream())
+        return abar
+
+    def logdet(self):
+        out = np.zeros(self.batch * (2 if self.is_complex else 1))
+        capi.selinv_logdet(self.h, out)
+        if self.is_complex:
+            return out[0::2] + 1j * out[1::2]
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            capi.selinv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

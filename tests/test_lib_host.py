@@ -1,0 +1,73 @@
+"""Library host code vs the oracle: symbolic bit-exact, host LDL^T to rounding."""
+
+import numpy as np
+import pytest
+
+from oracle import factor, selinv, symbolic
+from tests._ref import oracle_sym, workload
+from workloads import random_pattern
+
+
+def lib_ctx(w, relax, cap=None):
+    from paper_1604_02528_amd import SelInv
+
+    return SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128" if w.is_complex else "f64", batch=w.batch,
+                  cap=cap or w.cap, relax=relax, device="cpu")
+
+
+def assert_same_symbolic(lib, sym):
+    assert lib["nsuper"] == sym.nsuper
+    for key, ref in [("parent", sym.parent), ("colcount", sym.colcount), ("xsuper", sym.xsuper),
+                     ("sparent", sym.sparent), ("seg_ptr", sym.seg_ptr), ("seg_super", sym.seg_super),
+                     ("seg_start", sym.seg_start), ("seg_posoff", sym.seg_posoff), ("posarr", sym.posarr)]:
+        assert np.array_equal(lib[key], ref), key
+    rows = np.concatenate(sym.rows) if sym.rows else np.zeros(0, np.int64)
+    assert np.array_equal(lib["rowind_L"], rows)
+    assert lib["nnzL"] == sym.nnzL()
+
+
+SYM_CASES = [("C1", None, None), ("C4s", None, None), ("C2", 16, None), ("C3", 10, 2), ("C5", 8, 1),
+             ("C4", None, None), ("C2", None, None)]
+
+
+@pytest.mark.parametrize("relax", [0.0, 0.05])
+@pytest.mark.parametrize("name,scale,batch", SYM_CASES)
+def test_symbolic_bit_exact(name, scale, batch, relax):
+    if name == "C2" and scale is None and relax == 0.0:
+        pytest.skip("the exact-partition oracle on 40^3 takes ~30 s; covered by the relaxed case and smaller grids")
+    w = workload(name, scale, batch)
+    sym = oracle_sym(name, scale, batch, relax)
+    assert_same_symbolic(lib_ctx(w, relax).symbolic(), sym)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_symbolic_bit_exact_random(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(2, 200))
+    colptr, rowind, vals = random_pattern(n, float(rng.uniform(0.005, 0.2)), rng)
+    perm = rng.permutation(n).astype(np.int64)
+    cap = int(rng.integers(1, 40))
+    relax = float(rng.choice([0.0, 0.05, 0.3]))
+    sym = symbolic.analyze(n, colptr, rowind, perm, cap=cap, relax=relax)
+    from paper_1604_02528_amd import SelInv
+
+    S = SelInv(n, colptr, rowind, perm, cap=cap, relax=relax, device="cpu")
+    assert_same_symbolic(S.symbolic(), sym)
+
+
+@pytest.mark.parametrize("relax", [0.0, 0.05])
+@pytest.mark.parametrize("name,scale,batch", [("C1", None, None), ("C2", 12, None), ("C3", 8, 2), ("C5", 6, 2)])
+def test_host_factor_matches_oracle(name, scale, batch, relax):
+    w = workload(name, scale, batch)
+    sym = oracle_sym(name, scale, batch, relax)
+    S = lib_ctx(w, relax)
+    P = S.factor_host(w.values)
+    mask = np.concatenate([np.tril(np.ones((sym.width(K) + sym.rows[K].shape[0], sym.width(K)), bool)).reshape(-1, order="F")
+                           for K in range(sym.nsuper)])
+    for l in range(w.batch):
+        ref = selinv.flatten(sym, factor.factor(sym, w.values[l]))
+        err = np.max(np.abs(P[l][mask] - ref[mask])) / np.max(np.abs(ref[mask]))
+        assert err < 1e-13
+        ld = S.logdet()[l]
+        ref_ld = factor.logdet(sym, factor.factor(sym, w.values[l]))
+        assert abs(ld - ref_ld) <= 1e-10 * max(1.0, abs(ref_ld))
