@@ -130,6 +130,7 @@ typedef struct {
   int64_t work_bytes;    /* device tables, normalize scratch, counters, queue */
   int64_t dtilde_bytes;  /* optional pivot blocks Dt_K (needed by selinv_backward) */
   int64_t abar_bytes;    /* adjoint output on A's pattern, batch * nnz(A) scalars */
+  int64_t trace_bytes;   /* optional selinv_trace buffer */
 } selinv_sizes_t;
 
 selinv_status selinv_sizes(const selinv_ctx *h, selinv_sizes_t *s);
@@ -152,6 +153,18 @@ selinv_status selinv_sizes(const selinv_ctx *h, selinv_sizes_t *s);
  */
 selinv_status selinv_factor(selinv_ctx *h, const void *values, void *panels_dev, void *work_dev,
                             void *dtilde_dev, void *stream);
+
+/*
+ * selinv_normalize -- the device part of selinv_factor on its own: Alg. 1
+ * steps 1-2 applied to LDL^T panels already in device memory.
+ *   ldlt_dev: [batch][panel_elems] LDL^T panels (strict lower L_KK, D_K on the
+ *   diagonal, L_{C,K} below), read only unless it equals panels_dev.
+ *   panels_dev: receives Dt_K^{-1} (top block, full) and Lhat_{C,K}.
+ *   dtilde_dev: optional Dt_K output (for selinv_backward) or NULL.
+ * Asynchronous on `stream`; enables selinv_run.
+ */
+selinv_status selinv_normalize(selinv_ctx *h, const void *ldlt_dev, void *panels_dev, void *work_dev,
+                               void *dtilde_dev, void *stream);
 
 /*
  * selinv_factor_host -- the host part of selinv_factor only: the LDL^T
@@ -191,6 +204,25 @@ selinv_status selinv_extract(const selinv_ctx *h, const void *x_dev, void *work_
 selinv_status selinv_backward(selinv_ctx *h, const void *panels_dev, const void *x_dev,
                               const void *dtilde_dev, void *xbar_dev, void *work_dev, void *abar_dev,
                               void *stream);
+
+/*
+ * selinv_check_plan -- host replay of the persistent schedule's protocol on
+ * the context's tables (ready queues by depth class, dependency counters,
+ * pushes).  Verifies that every work item is queued and run exactly once, no
+ * queue overflows, a node starts only after its parent finished and phase 2
+ * only after phase 1.  SELINV_OK or SELINV_EINVAL with a message.  Host only.
+ */
+selinv_status selinv_check_plan(const selinv_ctx *h);
+
+/*
+ * selinv_trace -- per-item timeline of the persistent schedule (diagnostics).
+ * trace_dev: device buffer of selinv_sizes_t.trace_bytes bytes, or NULL to
+ * switch tracing off.  Each selinv_run with the persistent
+ * schedule then writes, per ready-queue slot, eight int64 values:
+ * {item id (batch * items + item), workgroup, t_pop, t_start, t_end, 0, 0, 0}
+ * in device wall-clock ticks (hipDeviceAttributeWallClockRate kHz).
+ */
+selinv_status selinv_trace(selinv_ctx *h, void *trace_dev);
 
 /* log det of each matrix of the batch (sum of log pivots; complex log for C128).
    out_host: batch doubles (R64) or batch (re, im) pairs (C128).  Valid after selinv_factor. */

@@ -23,8 +23,8 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "EPATTERN", 3: "ESINGULAR", 4: "ENOMEM", 5: "
 
 EXPORTED = (
     "selinv_default_opts", "selinv_version", "selinv_analyze", "selinv_symbolic", "selinv_sizes",
-    "selinv_factor", "selinv_factor_host", "selinv_run", "selinv_extract", "selinv_backward",
-    "selinv_logdet", "selinv_sync", "selinv_last_error", "selinv_error_info", "selinv_destroy",
+    "selinv_factor", "selinv_normalize", "selinv_factor_host", "selinv_run", "selinv_extract", "selinv_backward",
+    "selinv_logdet", "selinv_check_plan", "selinv_trace", "selinv_sync", "selinv_last_error", "selinv_error_info", "selinv_destroy",
 )
 
 
@@ -50,7 +50,7 @@ class SymbolicView(C.Structure):
 
 class Sizes(C.Structure):
     _fields_ = [("panels_bytes", C.c_int64), ("x_bytes", C.c_int64), ("work_bytes", C.c_int64),
-                ("dtilde_bytes", C.c_int64), ("abar_bytes", C.c_int64)]
+                ("dtilde_bytes", C.c_int64), ("abar_bytes", C.c_int64), ("trace_bytes", C.c_int64)]
 
 
 class SelinvError(RuntimeError):
@@ -79,11 +79,14 @@ def load():
         "selinv_symbolic": (C.c_int, [vp, C.POINTER(SymbolicView)]),
         "selinv_sizes": (C.c_int, [vp, C.POINTER(Sizes)]),
         "selinv_factor": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "selinv_normalize": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "selinv_factor_host": (C.c_int, [vp, vp, vp]),
         "selinv_run": (C.c_int, [vp, vp, vp, vp, vp]),
         "selinv_extract": (C.c_int, [vp, vp, vp, vp, vp]),
         "selinv_backward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "selinv_logdet": (C.c_int, [vp, vp]),
+        "selinv_check_plan": (C.c_int, [vp]),
+        "selinv_trace": (C.c_int, [vp, vp]),
         "selinv_sync": (C.c_int, [vp, vp]),
         "selinv_last_error": (C.c_char_p, [vp]),
         "selinv_error_info": (C.c_int64, [vp, C.c_int]),
@@ -158,6 +161,10 @@ def selinv_factor(h, values, panels, work, dtilde, stream):
     check(h, load().selinv_factor(h, ptr(values), ptr(panels), ptr(work), ptr(dtilde), stream))
 
 
+def selinv_normalize(h, ldlt, panels, work, dtilde, stream):
+    check(h, load().selinv_normalize(h, ptr(ldlt), ptr(panels), ptr(work), ptr(dtilde), stream))
+
+
 def selinv_factor_host(h, values, panels_host):
     check(h, load().selinv_factor_host(h, ptr(values), ptr(panels_host)))
 
@@ -176,6 +183,14 @@ def selinv_backward(h, panels, x, dtilde, xbar, work, abar, stream):
 
 def selinv_logdet(h, out_host):
     check(h, load().selinv_logdet(h, ptr(out_host)))
+
+
+def selinv_check_plan(h):
+    check(h, load().selinv_check_plan(h))
+
+
+def selinv_trace(h, trace):
+    check(h, load().selinv_trace(h, ptr(trace)))
 
 
 def selinv_sync(h, stream):

@@ -5,8 +5,8 @@
 
 namespace selinv {
 
-hipError_t launch_backward(const DevPlan &, const LaunchAux &, const void *, const void *, const void *, void *,
-                           void *, hipStream_t) {
+hipError_t launch_backward(const DevPlan &, const DevPlan *, const LaunchAux &, const void *, const void *,
+                           const void *, void *, void *, hipStream_t) {
   return hipErrorNotSupported;
 }
 

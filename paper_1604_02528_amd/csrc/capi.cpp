@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -14,14 +15,14 @@
 #include "plan.hpp"
 
 namespace selinv {
-hipError_t launch_normalize(const DevPlan &pl, const LaunchAux &aux, bool cplx_, void *panels, void *dt,
-                            hipStream_t st);
-hipError_t launch_run(const DevPlan &pl, const LaunchAux &aux, bool cplx_, int sched, const void *panels, void *x,
-                      int64_t budget_ticks, int grid, hipStream_t st);
-hipError_t launch_extract(const DevPlan &pl, bool cplx_, const void *x, void *out, hipStream_t st);
+hipError_t launch_normalize(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, const void *src,
+                            void *panels, void *dt, hipStream_t st);
+hipError_t launch_run(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, int sched,
+                      const void *panels, void *x, int64_t budget_ticks, int grid, hipStream_t st);
+hipError_t launch_extract(const DevPlan &pl, const DevPlan *dpl, bool cplx_, const void *x, void *out, hipStream_t st);
 int persistent_blocks_per_cu(bool cplx_);
-hipError_t launch_backward(const DevPlan &pl, const LaunchAux &aux, const void *panels, const void *x,
-                           const void *dt, void *xbar, void *abar, hipStream_t st);
+hipError_t launch_backward(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const void *panels,
+                           const void *x, const void *dt, void *xbar, void *abar, hipStream_t st);
 }  // namespace selinv
 
 using namespace selinv;
@@ -34,21 +35,25 @@ inline int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; 
 // Host image of every device table plus its byte offset in the work buffer.
 struct HostPlan {
   std::vector<int32_t> node_s, node_c;
-  std::vector<int64_t> node_off, node_rowptr, node_sq, node_first;
+  std::vector<int64_t> node_off, node_rowptr, node_sq, node_first, node_poff;
   std::vector<int64_t> kcol, kpos;
   std::vector<Item> items;
   std::vector<int32_t> item_ptr, n_phase1, n_phase2, first_beg, first_end, push_ptr, push_list, root_list;
+  std::vector<int32_t> node_q, qbase;
+  int32_t nq = 1;
   std::vector<int32_t> lvl_items, lvl_ptr;
   std::vector<int2> chunks;
   std::vector<int4> sq_tiles;
   std::vector<int64_t> apos;
   std::vector<uint8_t> adiag;
   int64_t sq_elems = 0;
+  int64_t part_elems = 0;
   // byte offsets inside the work buffer
   struct Off {
-    int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, kcol, kpos, posarr, items, item_ptr,
-        n_phase1, n_phase2, first_beg, first_end, push_ptr, push_list, root_list, lvl_items, chunks, sq_tiles,
-        apos, adiag, linv, dinv, cnt1, cnt2, queue, ctrl, end;
+    int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
+        n_phase1, n_phase2, first_beg, first_end, push_ptr, push_list, root_list, node_q, qbase, lvl_items, chunks,
+        sq_tiles,
+        apos, adiag, plan, linv, dinv, part, cnt1, cnt2, queue, ctrl, end;
   } off{};
   int64_t tables_bytes = 0;  // [0, tables_bytes) is uploaded once
 };
@@ -74,6 +79,15 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan
     sq += S.width(K) * S.width(K);
   }
   H.sq_elems = sq;
+  // GEMM-2 partial products: one s x s block per 64-row tile of C(K)
+  H.node_poff.resize(ns);
+  int64_t pe = 0;
+  for (int64_t K = 0; K < ns; ++K) {
+    H.node_poff[K] = pe;
+    const int64_t nr = (S.nrows(K) + kTileM - 1) / kTileM;
+    pe += (nr * S.width(K) * S.width(K) + kPanelAlign - 1) / kPanelAlign * kPanelAlign;
+  }
+  H.part_elems = pe;
   // per-row gather tables
   H.kcol.resize(S.rowind_L.size());
   H.kpos.resize(S.rowind_L.size());
@@ -135,6 +149,16 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan
   for (int64_t K = 0; K < ns; ++K)
     if (S.sparent[K] < 0)
       for (int32_t it = H.first_beg[K]; it < H.first_end[K]; ++it) H.root_list.push_back(it);
+  // ready-queue classes by depth
+  H.nq = (int32_t)std::max<int64_t>(1, std::min<int64_t>(kMaxQ, S.depth));
+  H.node_q.resize(ns);
+  std::vector<int64_t> qcount(H.nq, 0);
+  for (int64_t K = 0; K < ns; ++K) {
+    H.node_q[K] = (int32_t)std::min<int64_t>(S.sdepth[K], H.nq - 1);
+    qcount[H.node_q[K]] += H.n_phase1[K] + H.n_phase2[K];
+  }
+  H.qbase.assign(H.nq + 1, 0);
+  for (int q = 0; q < H.nq; ++q) H.qbase[q + 1] = H.qbase[q] + (int32_t)(qcount[q] * batch);
   // level lists (phase 1, then phase 2, per etree depth)
   H.lvl_items.clear();
   H.lvl_ptr.assign(1, 0);
@@ -178,6 +202,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan
   o.node_rowptr = take(8 * ns);
   o.node_sq = take(8 * ns);
   o.node_first = take(8 * ns);
+  o.node_poff = take(8 * ns);
   o.kcol = take(8 * (int64_t)H.kcol.size());
   o.kpos = take(8 * (int64_t)H.kpos.size());
   o.posarr = take(4 * (int64_t)S.posarr.size());
@@ -190,14 +215,18 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan
   o.push_ptr = take(4 * (ns + 1));
   o.push_list = take(4 * (int64_t)H.push_list.size());
   o.root_list = take(4 * (int64_t)H.root_list.size());
+  o.node_q = take(4 * ns);
+  o.qbase = take(4 * (int64_t)H.qbase.size());
   o.lvl_items = take(4 * (int64_t)H.lvl_items.size());
   o.chunks = take(8 * (int64_t)H.chunks.size());
   o.sq_tiles = take(16 * (int64_t)H.sq_tiles.size());
   o.apos = take(8 * (int64_t)H.apos.size());
   o.adiag = take((int64_t)H.adiag.size());
   H.tables_bytes = p;
+  o.plan = take((int64_t)sizeof(DevPlan));
   o.linv = take(scalar_bytes * batch * H.sq_elems);
   o.dinv = take(scalar_bytes * batch * S.n);
+  o.part = take(scalar_bytes * batch * H.part_elems);
   o.cnt1 = take(4 * batch * ns);
   o.cnt2 = take(4 * batch * ns);
   o.queue = take(4 * batch * (int64_t)H.items.size());
@@ -222,6 +251,8 @@ struct selinv_ctx {
   double *pinned = nullptr;          // host staging of the factor panels
   size_t pinned_bytes = 0;
   int64_t wall_khz = 0;
+  DevPlan plan_host{};  // staging of the plan copy in the work buffer
+  void *trace = nullptr;  // optional device trace buffer for the persistent schedule
   int grid = 0;
   // cached strings for views
   std::vector<int64_t> panel_off_view;
@@ -259,6 +290,7 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.batch = h->opts.batch;
   d.panel_elems = h->S.panel_elems;
   d.sq_elems = H.sq_elems;
+  d.part_elems = H.part_elems;
   d.nnzA = h->S.nnzA;
   d.total_rows = (int64_t)H.kcol.size();
   d.node_s = (int32_t *)(b + o.node_s);
@@ -267,6 +299,7 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.node_rowptr = (int64_t *)(b + o.node_rowptr);
   d.node_sq = (int64_t *)(b + o.node_sq);
   d.node_first = (int64_t *)(b + o.node_first);
+  d.node_poff = (int64_t *)(b + o.node_poff);
   d.kcol = (int64_t *)(b + o.kcol);
   d.kpos = (int64_t *)(b + o.kpos);
   d.posarr = (int32_t *)(b + o.posarr);
@@ -280,16 +313,25 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.push_list = (int32_t *)(b + o.push_list);
   d.root_list = (int32_t *)(b + o.root_list);
   d.nroot_items = (int32_t)H.root_list.size();
+  d.nq = H.nq;
+  d.node_q = (int32_t *)(b + o.node_q);
+  d.qbase = (int32_t *)(b + o.qbase);
   d.lvl_items = (int32_t *)(b + o.lvl_items);
   d.apos = (int64_t *)(b + o.apos);
   d.adiag = (uint8_t *)(b + o.adiag);
   d.linv = (void *)(b + o.linv);
   d.dinv = (void *)(b + o.dinv);
+  d.part = (void *)(b + o.part);
   d.cnt1 = (int32_t *)(b + o.cnt1);
   d.cnt2 = (int32_t *)(b + o.cnt2);
   d.queue = (int32_t *)(b + o.queue);
   d.ctrl = (int32_t *)(b + o.ctrl);
+  d.trace = (int64_t *)h->trace;
   return d;
+}
+
+const DevPlan *dev_plan(const selinv_ctx *h, void *work) {
+  return reinterpret_cast<const DevPlan *>(static_cast<unsigned char *>(work) + h->H.off.plan);
 }
 
 LaunchAux make_aux(const selinv_ctx *h, void *work) {
@@ -317,6 +359,7 @@ void build_image(selinv_ctx *h) {
   put(img, o.node_rowptr, H.node_rowptr);
   put(img, o.node_sq, H.node_sq);
   put(img, o.node_first, H.node_first);
+  put(img, o.node_poff, H.node_poff);
   put(img, o.kcol, H.kcol);
   put(img, o.kpos, H.kpos);
   put(img, o.posarr, h->S.posarr);
@@ -329,6 +372,8 @@ void build_image(selinv_ctx *h) {
   put(img, o.push_ptr, H.push_ptr);
   put(img, o.push_list, H.push_list);
   put(img, o.root_list, H.root_list);
+  put(img, o.node_q, H.node_q);
+  put(img, o.qbase, H.qbase);
   put(img, o.lvl_items, H.lvl_items);
   put(img, o.chunks, H.chunks);
   put(img, o.sq_tiles, H.sq_tiles);
@@ -340,6 +385,10 @@ selinv_status ensure_uploaded(selinv_ctx *h, void *work, hipStream_t st) {
   if (h->uploaded_to == work) return SELINV_OK;
   hipError_t e = hipMemcpyAsync(work, h->image.data(), h->image.size(), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_err(h, e, "table upload");
+  h->plan_host = make_devplan(h, work);
+  e = hipMemcpyAsync(static_cast<unsigned char *>(work) + h->H.off.plan, &h->plan_host, sizeof(DevPlan),
+                     hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_err(h, e, "plan upload");
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_err(h, e, "table upload sync");
   h->uploaded_to = work;
@@ -441,6 +490,7 @@ selinv_status selinv_sizes(const selinv_ctx *h, selinv_sizes_t *s) {
   s->work_bytes = h->H.off.end;
   s->dtilde_bytes = align_up(B * h->H.sq_elems * sb);
   s->abar_bytes = align_up(B * h->S.nnzA * sb);
+  s->trace_bytes = align_up(64 * B * (int64_t)h->H.items.size());
   return SELINV_OK;
 }
 
@@ -484,11 +534,28 @@ selinv_status selinv_factor(selinv_ctx *h, const void *values, void *panels_dev,
   if (e != hipSuccess) return hip_err(h, e, "panel upload");
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
-  e = launch_normalize(pl, aux, h->is_complex(), panels_dev, dtilde_dev, st);
+  e = launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), panels_dev, panels_dev, dtilde_dev, st);
   if (e != hipSuccess) return hip_err(h, e, "normalize launch");
   // the staging buffer is reused by the next call: wait for the copy
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_err(h, e, "factor sync");
+  h->factored = true;
+  return SELINV_OK;
+}
+
+selinv_status selinv_normalize(selinv_ctx *h, const void *ldlt_dev, void *panels_dev, void *work_dev,
+                               void *dtilde_dev, void *stream) {
+  if (!h) return SELINV_EINVAL;
+  if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
+  if (!ldlt_dev || !panels_dev || !work_dev) return set_err(h, SELINV_EINVAL, "null buffer");
+  hipStream_t st = (hipStream_t)stream;
+  selinv_status ss = ensure_uploaded(h, work_dev, st);
+  if (ss != SELINV_OK) return ss;
+  DevPlan pl = make_devplan(h, work_dev);
+  LaunchAux aux = make_aux(h, work_dev);
+  hipError_t e =
+      launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st);
+  if (e != hipSuccess) return hip_err(h, e, "normalize launch");
   h->factored = true;
   return SELINV_OK;
 }
@@ -535,16 +602,22 @@ selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, voi
     if (e != hipSuccess) return hip_err(h, e, "device attribute");
     e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
     if (e != hipSuccess) return hip_err(h, e, "device attribute");
+    // One persistent workgroup per CU by default: with two, items at the
+    // narrow top of the tree can land on the same CU while others idle.
     int per = persistent_blocks_per_cu(h->is_complex());
+    int want = 1;
+    if (const char *e = std::getenv("SELINV_PERSISTENT_WG_PER_CU")) want = std::atoi(e);
+    if (want < 1) want = 1;
     if (per < 1) per = 1;
-    h->grid = ncu * per;
+    h->grid = ncu * std::min(per, want);
     h->wall_khz = khz > 0 ? khz : 100000;
   }
   const int64_t ms = h->opts.watchdog_ms > 0 ? h->opts.watchdog_ms : 10000;
   const int64_t budget = ms * h->wall_khz;
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
-  e = launch_run(pl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, budget, h->grid, st);
+  e = launch_run(pl, dev_plan(h, work_dev), aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, budget, h->grid,
+                 st);
   if (e != hipSuccess) return hip_err(h, e, "selinv launch");
   return SELINV_OK;
 }
@@ -557,7 +630,7 @@ selinv_status selinv_extract(const selinv_ctx *hc, const void *x_dev, void *work
   selinv_status ss = ensure_uploaded(h, work_dev, st);
   if (ss != SELINV_OK) return ss;
   DevPlan pl = make_devplan(h, work_dev);
-  hipError_t e = launch_extract(pl, h->is_complex(), x_dev, out_dev, st);
+  hipError_t e = launch_extract(pl, dev_plan(h, work_dev), h->is_complex(), x_dev, out_dev, st);
   if (e != hipSuccess) return hip_err(h, e, "extract launch");
   return SELINV_OK;
 }
@@ -574,7 +647,7 @@ selinv_status selinv_backward(selinv_ctx *h, const void *panels_dev, const void 
   if (ss != SELINV_OK) return ss;
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
-  hipError_t e = launch_backward(pl, aux, panels_dev, x_dev, dtilde_dev, xbar_dev, abar_dev, st);
+  hipError_t e = launch_backward(pl, dev_plan(h, work_dev), aux, panels_dev, x_dev, dtilde_dev, xbar_dev, abar_dev, st);
   if (e != hipSuccess) return hip_err(h, e, "backward launch");
   return SELINV_OK;
 }
@@ -591,6 +664,82 @@ selinv_status selinv_logdet(const selinv_ctx *hc, double *out_host) {
       out_host[l] = h->logdet[2 * l];
     }
   }
+  return SELINV_OK;
+}
+
+selinv_status selinv_check_plan(const selinv_ctx *hc) {
+  selinv_ctx *h = const_cast<selinv_ctx *>(hc);
+  if (!h) return SELINV_EINVAL;
+  if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
+  const HostPlan &H = h->H;
+  const Symbolic &S = h->S;
+  const int64_t ns = S.nsuper(), nit = (int64_t)H.items.size(), B = h->opts.batch;
+  // replay of the device protocol: queues by class, counters, pushes
+  std::vector<std::vector<int64_t>> q(H.nq);
+  std::vector<int64_t> cap(H.nq);
+  for (int c = 0; c < H.nq; ++c) cap[c] = H.qbase[c + 1] - H.qbase[c];
+  std::vector<int32_t> cnt1((size_t)(B * ns)), cnt2((size_t)(B * ns));
+  std::vector<uint8_t> seen((size_t)(B * nit), 0), node_done((size_t)(B * ns), 0), ph1_done((size_t)(B * ns), 0);
+  for (int64_t l = 0; l < B; ++l)
+    for (int64_t K = 0; K < ns; ++K) {
+      cnt1[l * ns + K] = H.n_phase1[K];
+      cnt2[l * ns + K] = H.n_phase2[K];
+    }
+  for (int64_t l = 0; l < B; ++l)
+    for (int32_t it : H.root_list) q[0].push_back(l * nit + it);
+  if ((int64_t)q[0].size() > cap[0]) return set_err(h, SELINV_EINVAL, "plan check: root items exceed queue 0");
+  std::vector<size_t> head(H.nq, 0);
+  int64_t done = 0;
+  while (true) {
+    int c = 0;
+    while (c < H.nq && head[c] >= q[c].size()) ++c;
+    if (c == H.nq) break;
+    const int64_t id = q[c][head[c]++];
+    const int64_t l = id / nit, itn = id % nit;
+    if (seen[id]) return set_err(h, SELINV_EINVAL, "plan check: item popped twice", itn, l);
+    seen[id] = 1;
+    const Item it = H.items[itn];
+    const int64_t K = it.K;
+    if (H.node_q[K] != c) return set_err(h, SELINV_EINVAL, "plan check: item in the wrong queue", itn, l);
+    const bool first = (H.n_phase1[K] > 0) ? it.type == ITEM_Y : true;
+    const int64_t P = S.sparent[K];
+    if (first && P >= 0 && !node_done[l * ns + P])
+      return set_err(h, SELINV_EINVAL, "plan check: node started before its parent finished", K, l);
+    if (it.type != ITEM_Y && H.n_phase1[K] > 0 && !ph1_done[l * ns + K])
+      return set_err(h, SELINV_EINVAL, "plan check: phase 2 before phase 1", K, l);
+    std::vector<int64_t> push;
+    int qc = 0;
+    if (it.type == ITEM_Y) {
+      if (--cnt1[l * ns + K] == 0) {
+        ph1_done[l * ns + K] = 1;
+        for (int32_t j = 0; j < H.n_phase2[K]; ++j) push.push_back(l * nit + H.item_ptr[K] + H.n_phase1[K] + j);
+        qc = H.node_q[K];
+      }
+    } else {
+      if (--cnt2[l * ns + K] == 0) {
+        node_done[l * ns + K] = 1;
+        for (int32_t j = H.push_ptr[K]; j < H.push_ptr[K + 1]; ++j) push.push_back(l * nit + H.push_list[j]);
+        qc = std::min(H.node_q[K] + 1, H.nq - 1);
+      }
+    }
+    for (int64_t v : push) {
+      if (H.node_q[H.items[v % nit].K] != qc) return set_err(h, SELINV_EINVAL, "plan check: push into a wrong queue", K, l);
+      q[qc].push_back(v);
+    }
+    if ((int64_t)q[qc].size() > cap[qc]) return set_err(h, SELINV_EINVAL, "plan check: queue overflow", qc, l);
+    ++done;
+  }
+  if (done != B * nit) return set_err(h, SELINV_EINVAL, "plan check: not every item ran", done, B * nit);
+  for (int64_t l = 0; l < B; ++l)
+    for (int64_t K = 0; K < ns; ++K)
+      if (!node_done[l * ns + K]) return set_err(h, SELINV_EINVAL, "plan check: node never finished", K, l);
+  return SELINV_OK;
+}
+
+selinv_status selinv_trace(selinv_ctx *h, void *trace_dev) {
+  if (!h) return SELINV_EINVAL;
+  h->trace = trace_dev;
+  h->uploaded_to = nullptr;  // the device copy of the plan carries the pointer
   return SELINV_OK;
 }
 

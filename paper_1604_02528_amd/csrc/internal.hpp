@@ -11,6 +11,9 @@
 
 namespace selinv {
 
+// Alignment (in elements) of every panel and partial-product block.
+constexpr int64_t kPanelAlign = 16;
+
 struct Failure {
   selinv_status status;
   std::string msg;

@@ -25,210 +25,9 @@
 
 #include "plan.hpp"
 #include "scalar.hpp"
+#include "tile.hpp"
 
 namespace selinv {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-constexpr int NT = 256;     // threads per workgroup (4 waves)
-constexpr int TK = 16;      // contraction step
-constexpr int PITCH = 65;   // LDS row pitch in doubles
-
-template <typename T> struct Planes;
-template <> struct Planes<double> {
-  static constexpr int P = 1;
-  static __device__ __forceinline__ double get(double v, int) { return v; }
-};
-template <> struct Planes<cplx> {
-  static constexpr int P = 2;
-  static __device__ __forceinline__ double get(cplx v, int p) { return p ? v.im : v.re; }
-};
-
-template <typename T> __device__ __forceinline__ T zero_of() { return SOps<T>::zero(); }
-
-// ---------------------------------------------------------------------------
-// 64 x 64 MFMA tile: acc += A (64 x kc) * B (kc x 64), operands staged
-// through LDS by loader functors (double buffered, one-step register prefetch).
-// LDS layout of one stage: A planes [P][TK][PITCH] (k-major), then B planes.
-// ---------------------------------------------------------------------------
-template <typename T> struct Acc {
-  d4 v[Planes<T>::P][2][2];
-};
-
-template <typename T> __device__ __forceinline__ constexpr int stage_doubles() {
-  return 2 * Planes<T>::P * TK * PITCH;
-}
-template <typename T> __device__ __forceinline__ constexpr int smem_doubles() {
-  return 2 * stage_doubles<T>();  // two stages == one 64 x PITCH tile per plane
-}
-
-template <typename T>
-__device__ __forceinline__ void stage_store(double *stg, const T va[4], const int ia[4], const T vb[4],
-                                            const int ib[4]) {
-  constexpr int P = Planes<T>::P;
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      stg[p * TK * PITCH + ia[m]] = Planes<T>::get(va[m], p);
-      stg[(P + p) * TK * PITCH + ib[m]] = Planes<T>::get(vb[m], p);
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void stage_compute(const double *stg, Acc<T> &acc) {
-  constexpr int P = Planes<T>::P;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wi = w & 1, wj = w >> 1;
-#pragma unroll
-  for (int k4 = 0; k4 < 4; ++k4) {
-    const int r = (4 * k4 + (lane >> 4)) * PITCH + (lane & 15);
-    double a[2][P], b[2][P];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-      for (int p = 0; p < P; ++p) {
-        a[x][p] = stg[p * TK * PITCH + r + 32 * wi + 16 * x];
-        b[x][p] = stg[(P + p) * TK * PITCH + r + 32 * wj + 16 * x];
-      }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) {
-        if constexpr (P == 1) {
-          acc.v[0][bi][bj] = mfma16(a[bi][0], b[bj][0], acc.v[0][bi][bj]);
-        } else {
-          acc.v[0][bi][bj] = mfma16(a[bi][0], b[bj][0], acc.v[0][bi][bj]);
-          acc.v[0][bi][bj] = mfma16(-a[bi][1], b[bj][1], acc.v[0][bi][bj]);
-          acc.v[1][bi][bj] = mfma16(a[bi][0], b[bj][1], acc.v[1][bi][bj]);
-          acc.v[1][bi][bj] = mfma16(a[bi][1], b[bj][0], acc.v[1][bi][bj]);
-        }
-      }
-  }
-}
-
-template <typename T, class LA, class LB>
-__device__ __forceinline__ void gemm_tile(int kc, const LA &la, const LB &lb, double *smem, Acc<T> &acc) {
-  constexpr int P = Planes<T>::P;
-#pragma unroll
-  for (int p = 0; p < P; ++p)
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) acc.v[p][bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
-  const int nk = (kc + TK - 1) / TK;
-  if (nk == 0) return;
-  T va[4], vb[4];
-  int ia[4], ib[4];
-  la(0, va, ia);
-  lb(0, vb, ib);
-  stage_store<T>(smem, va, ia, vb, ib);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    double *cur = smem + (kt & 1) * stage_doubles<T>();
-    double *nxt = smem + ((kt + 1) & 1) * stage_doubles<T>();
-    const bool more = kt + 1 < nk;
-    if (more) {
-      la((kt + 1) * TK, va, ia);
-      lb((kt + 1) * TK, vb, ib);
-    }
-    stage_compute<T>(cur, acc);
-    if (more) stage_store<T>(nxt, va, ia, vb, ib);
-    __syncthreads();
-  }
-}
-
-// Scatter the accumulators into an LDS tile C[j * PITCH + i] (per plane),
-// i = row 0..63, j = column 0..63.  Caller syncs before and after.
-template <typename T>
-__device__ __forceinline__ void acc_to_lds(const Acc<T> &acc, double *ct) {
-  constexpr int P = Planes<T>::P;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wi = w & 1, wj = w >> 1;
-#pragma unroll
-  for (int p = 0; p < P; ++p)
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = 32 * wi + 16 * bi + 4 * v + (lane >> 4);
-          const int j = 32 * wj + 16 * bj + (lane & 15);
-          ct[p * 64 * PITCH + j * PITCH + i] = acc.v[p][bi][bj][v];
-        }
-}
-
-template <typename T> __device__ __forceinline__ T lds_get(const double *ct, int i, int j);
-template <> __device__ __forceinline__ double lds_get<double>(const double *ct, int i, int j) {
-  return ct[j * PITCH + i];
-}
-template <> __device__ __forceinline__ cplx lds_get<cplx>(const double *ct, int i, int j) {
-  return cplx{ct[j * PITCH + i], ct[64 * PITCH + j * PITCH + i]};
-}
-
-// ---------------------------------------------------------------------------
-// Loaders.  Each fills 4 values per thread for the k-block starting at k0,
-// together with their LDS slot kk * PITCH + (row or column).
-// ---------------------------------------------------------------------------
-
-// A = X_{C,C} (rows i0.., cols k0..), gathered from the ancestors' X panels:
-// lower (i >= k): X[kcol[k] + posarr[kpos[k] + i]]; upper: the transpose.
-template <typename T> struct LoadGather {
-  const T *X;
-  const int64_t *kcol, *kpos;
-  const int32_t *posarr;
-  int c, i0;
-  __device__ __forceinline__ void operator()(int k0, T v[4], int idx[4]) const {
-    const bool upper = (i0 + 63 < k0);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int e = threadIdx.x + NT * m;
-      int i, kk;
-      if (!upper) {
-        i = e & 63;
-        kk = e >> 6;
-      } else {
-        kk = e & 15;
-        i = e >> 4;
-      }
-      const int ig = i0 + i, kg = k0 + kk;
-      T val = zero_of<T>();
-      if (ig < c && kg < c) {
-        if (ig >= kg)
-          val = X[kcol[kg] + posarr[kpos[kg] + ig]];
-        else
-          val = X[kcol[ig] + posarr[kpos[ig] + kg]];
-      }
-      v[m] = val;
-      idx[m] = kk * PITCH + i;
-    }
-  }
-};
-
-// Column block of a panel's bottom part read k-major: value(kk, x) =
-// P[off + (x0 + x) * ld + s + k0 + kk], x = 0..63 (rows of A^T or columns of B).
-template <typename T> struct LoadPanelK {
-  const T *Pn;
-  int64_t off;
-  int ld, s, c, x0, xmax;
-  __device__ __forceinline__ void operator()(int k0, T v[4], int idx[4]) const {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int e = threadIdx.x + NT * m;
-      const int kk = e & 15, x = e >> 4;
-      const int kg = k0 + kk, xg = x0 + x;
-      T val = zero_of<T>();
-      if (kg < c && xg < xmax) val = Pn[off + (int64_t)xg * ld + s + kg];
-      v[m] = val;
-      idx[m] = kk * PITCH + x;
-    }
-  }
-};
 
 // ---------------------------------------------------------------------------
 // Work items
@@ -237,104 +36,209 @@ template <typename T> struct Ctx {
   const DevPlan *pl;
   const T *Lp;  // normalized panels of this matrix
   T *Xp;        // selected inverse of this matrix
+  T *Pp;        // GEMM-2 partial products of this matrix
 };
 
-// GEMM-1 tile: X_{C,K}[64a.., 64b..] = -(X_{C,C} Lhat_{C,K})[...]
-template <typename T>
-__device__ void do_ytile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
+// GEMM-1 tile, rows 64a.. and columns 64b.. of X_{C,K}:
+//   Y = -X_{C,C} Lhat_{C,K}                                  (Alg. 1 step 3)
+// fused with this row tile's share of GEMM-2 (step 4):
+//   P_a[:, 64b..] = Lhat[rows of tile a, :]^T Y[tile a, 64b..]
+// written to the partial buffer (column-major s x s per row tile).
+template <typename T, bool COH>
+__device__ void do_ytile(const Ctx<T> &cx, int K, int a, int b, double *smem, int64_t *rt) {
+  constexpr int P = Planes<T>::P;
   const DevPlan &pl = *cx.pl;
-  const int s = pl.node_s[K], c = pl.node_c[K], ld = s + c;
-  const int64_t off = pl.node_off[K], rp = pl.node_rowptr[K];
-  LoadGather<T> la{cx.Xp, pl.kcol + rp, pl.kpos + rp, pl.posarr, c, a * 64};
-  LoadPanelK<T> lb{cx.Lp, off, ld, s, c, b * 64, s};
-  Acc<T> acc;
-  gemm_tile<T>(c, la, lb, smem, acc);
-  acc_to_lds<T>(acc, smem);
-  __syncthreads();
+  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
+  const int64_t off = gp(pl.node_off)[K], rp = gp(pl.node_rowptr)[K];
   const int i0 = a * 64, j0 = b * 64;
+  if (threadIdx.x < 64) {
+    const int ig = i0 + threadIdx.x;
+    rt[threadIdx.x] = gp(pl.kcol)[rp + (ig < c ? ig : 0)];
+    rt[64 + threadIdx.x] = gp(pl.kpos)[rp + (ig < c ? ig : 0)];
+  }
+  lds_barrier();
+  LoadGather<T, COH> la{cx.Xp, pl.kcol + rp, pl.kpos + rp, pl.posarr, rt, rt + 64, c, i0};
+  LoadPanelK<T, false> lb{cx.Lp, off, ld, s, 0, c, j0, s};
+  Acc<T> acc;
+  gemm_tile<T>(c, la, lb, smem, acc);  // acc = X_{C,C} Lhat = -Y (tile)
+  acc_to_lds<T>(acc, smem);
+  lds_barrier();
   for (int e = threadIdx.x; e < 64 * 64; e += NT) {
     const int i = e & 63, j = e >> 6;
-    if (i0 + i < c && j0 + j < s) {
-      T val = lds_get<T>(smem, i, j);
-      cx.Xp[off + (int64_t)(j0 + j) * ld + s + i0 + i] = SOps<T>::scale(-1.0, val);
-    }
+    if (i0 + i < c && j0 + j < s)
+      Mem<COH>::st(cx.Xp + off + (int64_t)(j0 + j) * ld + s + i0 + i, SOps<T>::scale(-1.0, lds_get<T>(smem, i, j)));
   }
-  __syncthreads();
+  lds_barrier();
+  // Partial GEMM-2 from the accumulators: they already sit in the MFMA
+  // B-operand layout for a contraction over the tile rows (register v of a
+  // 16 x 16 block holds rows 4v..4v+3 of lanes l / 16).
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w & 1, wj = w >> 1;
+  const int64_t pbase = gp(pl.node_poff)[K] + (int64_t)a * s * s;
+  double *Ls = smem;  // Lhat[i0 .. i0+63, q0 .. q0+63] as Ls[p][i * PITCH + x]
+  for (int q0 = 0; q0 < s; q0 += 64) {
+#pragma unroll
+    for (int q = 0; q < 64 * 64 / NT; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int i = e & 63, x = e >> 6;
+      const bool ok = i0 + i < c && q0 + x < s;
+      const T v = cx.Lp[ok ? off + (int64_t)(q0 + x) * ld + s + i0 + i : off];
+#pragma unroll
+      for (int p = 0; p < P; ++p) Ls[p * 64 * PITCH + i * PITCH + x] = ok ? Planes<T>::get(v, p) : 0.0;
+    }
+    lds_barrier();
+    d4 pacc[P][4][2];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int xb = 0; xb < 4; ++xb)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) pacc[p][xb][bj] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4) {
+        const int row = 32 * wi + 16 * bi + 4 * k4 + (lane >> 4);
+#pragma unroll
+        for (int xb = 0; xb < 4; ++xb) {
+          double af[P];
+#pragma unroll
+          for (int p = 0; p < P; ++p) af[p] = Ls[p * 64 * PITCH + row * PITCH + 16 * xb + (lane & 15)];
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) {
+            if constexpr (P == 1) {
+              pacc[0][xb][bj] = mfma16(af[0], acc.v[0][bi][bj][k4], pacc[0][xb][bj]);
+            } else {
+              pacc[0][xb][bj] = mfma16(af[0], acc.v[0][bi][bj][k4], pacc[0][xb][bj]);
+              pacc[0][xb][bj] = mfma16(-af[1], acc.v[1][bi][bj][k4], pacc[0][xb][bj]);
+              pacc[1][xb][bj] = mfma16(af[0], acc.v[1][bi][bj][k4], pacc[1][xb][bj]);
+              pacc[1][xb][bj] = mfma16(af[1], acc.v[0][bi][bj][k4], pacc[1][xb][bj]);
+            }
+          }
+        }
+      }
+    lds_barrier();
+    // sum the two row halves (wi = 0, 1) in LDS: R[p][j * PITCH + x]
+    double *R = smem;
+    for (int half = 0; half < 2; ++half) {
+      if (wi == half) {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+          for (int xb = 0; xb < 4; ++xb)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int x = 16 * xb + 4 * v + (lane >> 4);
+                const int j = 32 * wj + 16 * bj + (lane & 15);
+                double &r = R[p * 64 * PITCH + j * PITCH + x];
+                r = half == 0 ? pacc[p][xb][bj][v] : r + pacc[p][xb][bj][v];
+              }
+      }
+      lds_barrier();
+    }
+    // P = Lhat^T Y = -(Lhat^T acc)
+    for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+      const int x = e & 63, j = e >> 6;
+      if (q0 + x < s && j0 + j < s)
+        Mem<COH>::st(cx.Pp + pbase + (int64_t)(j0 + j) * s + q0 + x, SOps<T>::scale(-1.0, lds_get<T>(R, x, j)));
+    }
+    lds_barrier();
+  }
 }
 
-// GEMM-2 + symmetrization for the block pair (a, b), a >= b, of X_KK.
-template <typename T>
+// Blocks (a, b) and (b, a), a >= b, of X_KK = sym(Dt^{-1} - sum_r P_r)
+// (Alg. 1 step 4 and the symmetrization of Section 2.3).
+template <typename T, bool COH>
 __device__ void do_dtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
   const DevPlan &pl = *cx.pl;
-  const int s = pl.node_s[K], c = pl.node_c[K], ld = s + c;
-  const int64_t off = pl.node_off[K];
+  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
+  const int64_t off = gp(pl.node_off)[K];
+  const int nr = (c + 63) / 64;
+  const int64_t pb = gp(pl.node_poff)[K];
+  const int64_t ss = (int64_t)s * s;
   const T *Dti = cx.Lp + off;  // top block of the normalized panel = Dt^{-1}
   T *Xkk = cx.Xp + off;        // top block of the X panel
   const int a0 = a * 64, b0 = b * 64;
-  Acc<T> acc;
-  // T_ab = Dt^{-1}[a, b] - Lhat_a^T Y_b
-  {
-    LoadPanelK<T> la{cx.Lp, off, ld, s, c, a0, s};
-    LoadPanelK<T> lb{cx.Xp, off, ld, s, c, b0, s};
-    gemm_tile<T>(c, la, lb, smem, acc);
-  }
-  acc_to_lds<T>(acc, smem);
-  __syncthreads();
-  if (a == b) {
-    for (int e = threadIdx.x; e < 64 * 64; e += NT) {
-      const int i = e & 63, j = e >> 6;
-      if (a0 + i < s && a0 + j < s) {
-        T tij = Dti[(int64_t)(a0 + j) * ld + a0 + i] - lds_get<T>(smem, i, j);
-        T tji = Dti[(int64_t)(a0 + i) * ld + a0 + j] - lds_get<T>(smem, j, i);
-        Xkk[(int64_t)(a0 + j) * ld + a0 + i] = SOps<T>::scale(0.5, tij + tji);
+  double *Sab = smem, *Sba = smem + tile_doubles<T>();
+  // T[a0 + i, b0 + j] into Sab[i][j] and T[b0 + i, a0 + j] into Sba[i][j].
+  // Each thread owns 16 elements of each block, taken in two halves of 8;
+  // for every row tile the 16 loads of a half are issued together.
+  constexpr int Q = 64 * 64 / NT, QH = Q / 2;
+  const int ie = threadIdx.x & 63, jb = threadIdx.x >> 6;  // element (ie, jb + 4 q)
+  for (int h = 0; h < 2; ++h) {
+    T sab[QH], sba[QH];
+    int64_t mab[QH], mba[QH];
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      const int j = jb + 4 * (QH * h + q);
+      sab[q] = zero_of<T>();
+      sba[q] = zero_of<T>();
+      mab[q] = opaque_mask(a0 + ie < s && b0 + j < s);
+      mba[q] = opaque_mask(b0 + ie < s && a0 + j < s);
+    }
+    for (int r = 0; r < nr; ++r) {
+      const T *pr = cx.Pp + pb + r * ss;
+      T la[QH], lb[QH];
+#pragma unroll
+      for (int q = 0; q < QH; ++q) {
+        const int j = jb + 4 * (QH * h + q);
+        la[q] = Mem<COH>::ld(pr + (((int64_t)(b0 + j) * s + a0 + ie) & mab[q]));
+        lb[q] = Mem<COH>::ld(pr + (((int64_t)(a0 + j) * s + b0 + ie) & mba[q]));
+      }
+#pragma unroll
+      for (int q = 0; q < QH; ++q) {
+        sab[q] += la[q];
+        sba[q] += lb[q];
       }
     }
-    __syncthreads();
-    return;
-  }
-  // stash T_ab (unsymmetrized) in X_KK[a, b]
-  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
-    const int i = e & 63, j = e >> 6;
-    if (a0 + i < s && b0 + j < s)
-      Xkk[(int64_t)(b0 + j) * ld + a0 + i] = Dti[(int64_t)(b0 + j) * ld + a0 + i] - lds_get<T>(smem, i, j);
-  }
-  __threadfence_block();
-  __syncthreads();
-  // T_ba = Dt^{-1}[b, a] - Lhat_b^T Y_a
-  {
-    LoadPanelK<T> la{cx.Lp, off, ld, s, c, b0, s};
-    LoadPanelK<T> lb{cx.Xp, off, ld, s, c, a0, s};
-    gemm_tile<T>(c, la, lb, smem, acc);
-  }
-  acc_to_lds<T>(acc, smem);
-  __syncthreads();
-  // X[a, b] = X[b, a]^T = (T_ab + T_ba^T) / 2
-  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
-    const int i = e & 63, j = e >> 6;  // element (a0 + i, b0 + j)
-    if (a0 + i < s && b0 + j < s) {
-      T tab = Xkk[(int64_t)(b0 + j) * ld + a0 + i];
-      T tba = Dti[(int64_t)(a0 + i) * ld + b0 + j] - lds_get<T>(smem, j, i);
-      T x = SOps<T>::scale(0.5, tab + tba);
-      Xkk[(int64_t)(b0 + j) * ld + a0 + i] = x;
-      Xkk[(int64_t)(a0 + i) * ld + b0 + j] = x;
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      const int j = jb + 4 * (QH * h + q);
+      const T dab = gload(Dti + (((int64_t)(b0 + j) * ld + a0 + ie) & mab[q]));
+      const T dba = gload(Dti + (((int64_t)(a0 + j) * ld + b0 + ie) & mba[q]));
+      lds_put<T>(Sab, ie, j, masked(dab - sab[q], mab[q]));
+      lds_put<T>(Sba, ie, j, masked(dba - sba[q], mba[q]));
     }
   }
-  __syncthreads();
+  lds_barrier();
+  // x(i, j) = (T[a0+i, b0+j] + T[b0+j, a0+i]) / 2 ; keep it in Sab
+  T xv[64 * 64 / NT];
+#pragma unroll
+  for (int q = 0; q < 64 * 64 / NT; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int i = e & 63, j = e >> 6;
+    xv[q] = SOps<T>::scale(0.5, lds_get<T>(Sab, i, j) + lds_get<T>(Sba, j, i));
+  }
+  lds_barrier();
+#pragma unroll
+  for (int q = 0; q < 64 * 64 / NT; ++q) {
+    const int e = threadIdx.x + NT * q;
+    lds_put<T>(Sab, e & 63, e >> 6, xv[q]);
+  }
+  lds_barrier();
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int i = e & 63, j = e >> 6;
+    if (a0 + i < s && b0 + j < s) Mem<COH>::st(Xkk + (int64_t)(b0 + j) * ld + a0 + i, lds_get<T>(Sab, i, j));
+    if (a != b && b0 + i < s && a0 + j < s) Mem<COH>::st(Xkk + (int64_t)(a0 + j) * ld + b0 + i, lds_get<T>(Sab, j, i));
+  }
+  lds_barrier();
 }
 
-template <typename T>
-__device__ void do_item(const Ctx<T> &cx, const Item &it, double *smem) {
+template <typename T, bool COH>
+__device__ void do_item(const Ctx<T> &cx, const Item &it, double *smem, int64_t *rt) {
   if (it.type == ITEM_Y) {
-    do_ytile<T>(cx, it.K, it.a, it.b, smem);
+    do_ytile<T, COH>(cx, it.K, it.a, it.b, smem, rt);
   } else if (it.type == ITEM_D) {
-    do_dtile<T>(cx, it.K, it.a, it.b, smem);
+    do_dtile<T, COH>(cx, it.K, it.a, it.b, smem);
   } else {  // ITEM_S: the whole node (c <= 64, s <= 64) in this workgroup
     if (cx.pl->node_c[it.K] > 0) {
-      do_ytile<T>(cx, it.K, 0, 0, smem);
+      do_ytile<T, COH>(cx, it.K, 0, 0, smem, rt);
       __threadfence_block();
       __syncthreads();
     }
-    do_dtile<T>(cx, it.K, 0, 0, smem);
+    do_dtile<T, COH>(cx, it.K, 0, 0, smem);
   }
 }
 
@@ -342,44 +246,51 @@ __device__ void do_item(const Ctx<T> &cx, const Item &it, double *smem) {
 // Schedules
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(NT) k_items_list(DevPlan pl, const T *Lp, T *Xp, const int32_t *list,
+__global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1) k_items_list(const DevPlan *__restrict__ plp, const T *Lp, T *Xp, T *Pp, const int32_t *list,
                                                    int32_t count) {
+  const DevPlan &pl = *plp;
   __shared__ double smem[smem_doubles<T>()];
+  __shared__ int64_t rt[128];
   const int64_t g = blockIdx.x;
   const int64_t l = g / count;
   const int32_t it = list[g - l * count];
-  Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems};
-  do_item<T>(cx, pl.items[it], smem);
+  Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, Pp + l * pl.part_elems};
+  do_item<T, false>(cx, gload(pl.items + it), smem, rt);
 }
 
-__device__ __forceinline__ int32_t ld_acquire(const int32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Scheduler atomics.  Every cross-workgroup data access in the persistent
+// kernel goes through agent-scope atomics (see Mem<true>), so the queue and
+// counter protocol needs ordering but never a cache-wide invalidation:
+// producers finish their stores (release fence) before a counter or queue
+// update; consumers spin with relaxed loads and derive every data address from
+// the item they popped.
 __device__ __forceinline__ int32_t ld_relaxed(const int32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_release(int32_t *p, int32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void st_relaxed(int32_t *p, int32_t v) {
+  __hip_atomic_store(gw(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ int32_t fetch_add(int32_t *p, int32_t v) {
-  return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ int32_t add_relaxed(int32_t *p, int32_t v) {
+  return __hip_atomic_fetch_add(gw(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Reset the dependency counters and the control words.
-__global__ void k_sched_init(DevPlan pl) {
+__global__ void k_sched_init(const DevPlan *__restrict__ plp) {
+  const DevPlan &pl = *plp;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t nsb = pl.batch * pl.ns;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsb; i += stride) {
     const int64_t K = i % pl.ns;
-    pl.cnt1[i] = pl.n_phase1[K];
-    pl.cnt2[i] = pl.n_phase2[K];
+    gw(pl.cnt1)[i] = gp(pl.n_phase1)[K];
+    gw(pl.cnt2)[i] = gp(pl.n_phase2)[K];
   }
-  if (blockIdx.x == 0 && threadIdx.x < CTRL_WORDS) pl.ctrl[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < CTRL_WORDS) gw(pl.ctrl)[threadIdx.x] = 0;
 }
 
-// Seed the ready queue with the first-phase items of every root of every matrix.
-__global__ void k_sched_seed(DevPlan pl) {
-  // queue[0 .. batch*nroot) = roots of every matrix; the rest stays -1.
+// Seed queue 0 (depth 0) with the first-phase items of every root of every
+// matrix; every other slot starts empty (-1).
+__global__ void k_sched_seed(const DevPlan *__restrict__ plp) {
+  const DevPlan &pl = *plp;
   const int64_t nseed = pl.batch * pl.nroot_items;
   const int64_t total = pl.batch * pl.nitems;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -387,87 +298,160 @@ __global__ void k_sched_seed(DevPlan pl) {
     int32_t v = -1;
     if (i < nseed) {
       const int64_t l = i / pl.nroot_items;
-      v = (int32_t)(l * pl.nitems + pl.root_list[i - l * pl.nroot_items]);
+      v = (int32_t)(l * pl.nitems + gp(pl.root_list)[i - l * pl.nroot_items]);
     }
-    pl.queue[i] = v;
+    gw(pl.queue)[i] = v;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) pl.ctrl[CTRL_TAIL] = (int32_t)nseed;
+  if (blockIdx.x == 0 && threadIdx.x == 0) gw(pl.ctrl)[CTRL_QTAIL] = (int32_t)nseed;
+}
+
+__device__ __forceinline__ bool cas_relaxed(int32_t *p, int32_t expect, int32_t desire) {
+  return __hip_atomic_compare_exchange_strong(gw(p), &expect, desire, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Take one published item (executed by the 64 lanes of wave 0).  One vector
+// load reads every queue's head and tail, a ballot picks the shallowest
+// non-empty queue and lane 0 claims its head slot with a CAS, then waits for
+// the producer's slot store (it reserves slots just before writing them).
+// Idle polling backs off exponentially.  Returns the item id, -3 when every
+// item is done, -2 on error; the watchdog counts from kernel start.
+__device__ int32_t pop_item(const DevPlan &pl, int64_t total, int64_t t_begin, int64_t budget_ticks,
+                            int32_t &slot_out) {
+  const int lane = threadIdx.x & 63;
+  int backoff = 1;
+  while (true) {
+    int32_t h = 0, t = 0;
+    if (lane < pl.nq) {
+      h = ld_relaxed(pl.ctrl + CTRL_QHEAD + lane);
+      t = ld_relaxed(pl.ctrl + CTRL_QTAIL + lane);
+    }
+    const uint64_t nonempty = __ballot(h < t);
+    if (nonempty) {
+      const int q = __ffsll((unsigned long long)nonempty) - 1;
+      const int32_t hq = __shfl(h, q);
+      int got = 0;
+      if (lane == 0) got = cas_relaxed(pl.ctrl + CTRL_QHEAD + q, hq, hq + 1) ? 1 : 0;
+      got = __shfl(got, 0);
+      if (!got) continue;  // lost the race: rescan at once
+      const int32_t slot = gp(pl.qbase)[q] + hq;
+      int32_t id = -2;
+      if (lane == 0) {
+        while (true) {
+          id = ld_relaxed(pl.queue + slot);
+          if (id >= 0) break;
+          if (wall_clock64() - t_begin > budget_ticks) {
+            st_relaxed(pl.ctrl + CTRL_ERR, 1);
+            id = -2;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      slot_out = slot;
+      return __shfl(id, 0);
+    }
+    int32_t state = 0;  // 0: keep waiting, -3: all done, -2: error
+    if (lane == 0) {
+      if (ld_relaxed(pl.ctrl + CTRL_DONE) >= total) state = -3;
+      else if (ld_relaxed(pl.ctrl + CTRL_ERR) != 0) state = -2;
+      else if (wall_clock64() - t_begin > budget_ticks) {
+        st_relaxed(pl.ctrl + CTRL_ERR, 1);
+        state = -2;
+      }
+    }
+    state = __shfl(state, 0);
+    if (state != 0) return state;
+    for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(2);
+    backoff = backoff < 64 ? 2 * backoff : 64;
+  }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(NT) k_persistent(DevPlan pl, const T *Lp, T *Xp, int64_t budget_ticks) {
+__global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
+    k_persistent(const DevPlan *__restrict__ plp, const T *Lp, T *Xp, T *Pp, int64_t budget_ticks) {
+  const DevPlan &pl = *plp;
   __shared__ double smem[smem_doubles<T>()];
-  __shared__ int32_t s_id, s_push_beg, s_push_cnt, s_push_base, s_push_l, s_push_kind;
+  __shared__ int64_t rt[128];
+  __shared__ int32_t s_id, s_idx, s_push_beg, s_push_cnt, s_push_base, s_push_l, s_push_kind;
+  __shared__ int64_t s_tpop;
   const int64_t total = pl.batch * pl.nitems;
+  const int64_t t_begin = wall_clock64();
   while (true) {
-    if (threadIdx.x == 0) {
-      int32_t id = -3;
-      const int32_t idx = fetch_add(pl.ctrl + CTRL_HEAD, 1);
-      if (idx < total) {
-        const int64_t t0 = wall_clock64();
-        while (true) {
-          id = ld_acquire(pl.queue + idx);
-          if (id >= 0) break;
-          if (ld_relaxed(pl.ctrl + CTRL_ERR) != 0) {
-            id = -2;
-            break;
-          }
-          if (wall_clock64() - t0 > budget_ticks) {
-            __hip_atomic_store(pl.ctrl + CTRL_ERR, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            id = -2;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(4);
-        }
+    if (threadIdx.x < 64) {
+      int32_t slot = 0;
+      const int32_t id = pop_item(pl, total, t_begin, budget_ticks, slot);
+      if (threadIdx.x == 0) {
+        s_id = id;
+        s_idx = slot;
+        s_tpop = pl.trace ? wall_clock64() : 0;
       }
-      s_id = id;
     }
     __syncthreads();
     const int32_t id = s_id;
     if (id < 0) break;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // agent-scope acquire for every wave
+    const int64_t t_start = pl.trace ? wall_clock64() : 0;
     const int64_t l = id / pl.nitems;
     const int32_t itn = (int32_t)(id - l * pl.nitems);
-    const Item it = pl.items[itn];
-    Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems};
-    do_item<T>(cx, it, smem);
-    __threadfence();  // release this workgroup's stores at agent scope
+    const Item it = gload(pl.items + itn);
+    Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, Pp + l * pl.part_elems};
+    do_item<T, false>(cx, it, smem, rt);
+    // Publishing protocol: write back this item's stores (agent-scope release)
+    // before any counter or queue update.  Readers use plain cached loads:
+    // every panel and partial block starts on its own cache line, and a
+    // node's data is read only after the node has completed, so no L2 can
+    // hold a line of it from before it was written (caches start clean at
+    // kernel launch).
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
+      if (pl.trace) {
+        int64_t *tr = pl.trace + 8 * (int64_t)s_idx;
+        tr[0] = id;
+        tr[1] = blockIdx.x;
+        tr[2] = s_tpop;
+        tr[3] = t_start;
+        tr[4] = wall_clock64();
+      }
       const int64_t nk = l * pl.ns + it.K;
-      int32_t cnt = 0, beg = 0;
+      int32_t cnt = 0, beg = 0, kind = 0, q = 0;
       if (it.type == ITEM_Y) {
-        if (fetch_add(pl.cnt1 + nk, -1) == 1) {  // phase 1 done: release phase 2
-          beg = pl.item_ptr[it.K] + pl.n_phase1[it.K];
-          cnt = pl.n_phase2[it.K];
-          s_push_kind = 0;
+        if (add_relaxed(pl.cnt1 + nk, -1) == 1) {  // phase 1 done: release phase 2
+          beg = gp(pl.item_ptr)[it.K] + gp(pl.n_phase1)[it.K];
+          cnt = gp(pl.n_phase2)[it.K];
+          kind = 0;
+          q = gp(pl.node_q)[it.K];
         }
       } else {
-        if (fetch_add(pl.cnt2 + nk, -1) == 1) {  // node done: release the children
-          beg = pl.push_ptr[it.K];
-          cnt = pl.push_ptr[it.K + 1] - beg;
-          s_push_kind = 1;
+        if (add_relaxed(pl.cnt2 + nk, -1) == 1) {  // node done: release the children
+          beg = gp(pl.push_ptr)[it.K];
+          cnt = gp(pl.push_ptr)[it.K + 1] - beg;
+          kind = 1;
+          q = min(gp(pl.node_q)[it.K] + 1, pl.nq - 1);
         }
       }
       s_push_cnt = cnt;
       s_push_beg = beg;
+      s_push_kind = kind;
       s_push_l = (int32_t)l;
-      s_push_base = cnt > 0 ? fetch_add(pl.ctrl + CTRL_TAIL, cnt) : 0;
+      s_push_base = cnt > 0 ? gp(pl.qbase)[q] + add_relaxed(pl.ctrl + CTRL_QTAIL + q, cnt) : 0;
+      s_idx = cnt > 0 ? gp(pl.qbase)[q + 1] : 0;  // end of queue q (bound check below)
     }
     __syncthreads();
     const int32_t cnt = s_push_cnt;
     if (cnt > 0) {
-      const int32_t beg = s_push_beg, base = s_push_base, kind = s_push_kind;
+      const int32_t beg = s_push_beg, base = s_push_base, kind = s_push_kind, qend = s_idx;
       const int64_t loff = (int64_t)s_push_l * pl.nitems;
       for (int32_t q = threadIdx.x; q < cnt; q += NT) {
-        const int32_t item = kind == 0 ? beg + q : pl.push_list[beg + q];
-        if ((int64_t)base + q < total)
-          st_release(pl.queue + base + q, (int32_t)(loff + item));
-        else  // more pushes than items: a broken dependency table; stop everyone
-          __hip_atomic_store(pl.ctrl + CTRL_ERR, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t item = kind == 0 ? beg + q : gp(pl.push_list)[beg + q];
+        if (base + q < qend)
+          st_relaxed(pl.queue + base + q, (int32_t)(loff + item));
+        else  // more pushes than the queue holds: a broken dependency table; stop everyone
+          st_relaxed(pl.ctrl + CTRL_ERR, 2);
       }
     }
     __syncthreads();
+    if (threadIdx.x == 0) add_relaxed(pl.ctrl + CTRL_DONE, 1);
   }
 }
 
@@ -480,32 +464,35 @@ __global__ void __launch_bounds__(NT) k_persistent(DevPlan pl, const T *Lp, T *X
 // give Lhat in place (panel row r).  Back substitution in 16-column chunks,
 // L_KK chunks staged in LDS.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_normalize_rows(DevPlan pl, T *Lp_all, const int2 *chunks, int32_t nchunks) {
+__global__ void __launch_bounds__(NT) k_normalize_rows(const DevPlan *__restrict__ plp, const T *Src_all, T *Lp_all, const int2 *chunks,
+                                                       int32_t nchunks) {
+  const DevPlan &pl = *plp;
   __shared__ double ls[Planes<T>::P][16 * 257];
   const int64_t g = blockIdx.x;
   const int64_t l = g / nchunks;
   const int2 ck = chunks[g - l * nchunks];
   const int K = ck.x;
-  const int s = pl.node_s[K], c = pl.node_c[K], ld = s + c;
-  const int64_t off = pl.node_off[K];
-  T *P = Lp_all + l * pl.panel_elems + off;
-  T *Linv = reinterpret_cast<T *>(pl.linv) + l * pl.sq_elems + pl.node_sq[K];
-  T *dinv = reinterpret_cast<T *>(pl.dinv) + l * pl.n + pl.node_first[K];
+  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
+  const int64_t off = gp(pl.node_off)[K];
+  const T *Q = Src_all + l * pl.panel_elems + off;  // LDL^T panel (read only)
+  T *P = Lp_all + l * pl.panel_elems + off;         // normalized panel (may alias Q)
+  T *Linv = reinterpret_cast<T *>(pl.linv) + l * pl.sq_elems + gp(pl.node_sq)[K];
+  T *dinv = reinterpret_cast<T *>(pl.dinv) + l * pl.n + gp(pl.node_first)[K];
   const int r = ck.y * NT + threadIdx.x;
   const bool active = r < s + c;
-  if (ck.y == 0 && threadIdx.x < s) dinv[threadIdx.x] = SOps<T>::div(SOps<T>::one(), P[(int64_t)threadIdx.x * ld + threadIdx.x]);
+  if (ck.y == 0 && threadIdx.x < s) gstore(dinv + threadIdx.x, SOps<T>::div(SOps<T>::one(), Q[(int64_t)threadIdx.x * ld + threadIdx.x]));
   for (int jb = ((s - 1) / 16) * 16; jb >= 0; jb -= 16) {
     const int w = (s - jb < 16) ? s - jb : 16;
     const int nrow = s - jb;  // rows jb .. s-1 of L_KK, columns jb .. jb+w-1
-    __syncthreads();
+    lds_barrier();
     for (int e = threadIdx.x; e < 16 * nrow; e += NT) {
       const int q = e / nrow, i = e - q * nrow;
       T v = zero_of<T>();
-      if (q < w) v = P[(int64_t)(jb + q) * ld + jb + i];
+      if (q < w) v = Q[(int64_t)(jb + q) * ld + jb + i];
 #pragma unroll
       for (int p = 0; p < Planes<T>::P; ++p) ls[p][q * 257 + i] = Planes<T>::get(v, p);
     }
-    __syncthreads();
+    lds_barrier();
     if (active) {
       T x[16];
 #pragma unroll
@@ -515,12 +502,12 @@ __global__ void __launch_bounds__(NT) k_normalize_rows(DevPlan pl, T *Lp_all, co
           if (r < s)
             v = (r == jb + q) ? SOps<T>::one() : zero_of<T>();
           else
-            v = P[(int64_t)(jb + q) * ld + r];
+            v = Q[(int64_t)(jb + q) * ld + r];
         }
         x[q] = v;
       }
       for (int i = jb + w; i < s; ++i) {
-        const T xi = (r < s) ? Linv[(int64_t)i * s + r] : P[(int64_t)i * ld + r];
+        const T xi = (r < s) ? gload(Linv + (int64_t)i * s + r) : P[(int64_t)i * ld + r];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
           T lv;
@@ -547,7 +534,7 @@ __global__ void __launch_bounds__(NT) k_normalize_rows(DevPlan pl, T *Lp_all, co
       for (int q = 0; q < 16; ++q) {
         if (q < w) {
           if (r < s)
-            Linv[(int64_t)(jb + q) * s + r] = x[q];
+            gstore(Linv + (int64_t)(jb + q) * s + r, x[q]);
           else
             P[(int64_t)(jb + q) * ld + r] = x[q];
         }
@@ -560,17 +547,19 @@ __global__ void __launch_bounds__(NT) k_normalize_rows(DevPlan pl, T *Lp_all, co
 //   mode 0: Dt = L_KK D L_KK^T              -> dt buffer (reads the LDL^T top block)
 //   mode 1: Dt^{-1} = Linv^T D^{-1} Linv    -> panel top block
 template <typename T>
-__global__ void __launch_bounds__(NT) k_normalize_sq(DevPlan pl, T *Lp_all, T *dt_all, const int4 *tiles,
-                                                     int32_t ntiles, int mode) {
+__global__ void __launch_bounds__(NT) k_normalize_sq(const DevPlan *__restrict__ plp, const T *Src_all, T *Lp_all, T *dt_all,
+                                                     const int4 *tiles, int32_t ntiles, int mode) {
+  const DevPlan &pl = *plp;
   __shared__ double la[Planes<T>::P][32 * 33], lb[Planes<T>::P][32 * 33], dv[Planes<T>::P][32];
   const int64_t g = blockIdx.x;
   const int64_t l = g / ntiles;
   const int4 tk = tiles[g - l * ntiles];
   const int K = tk.x, i0 = tk.y * 32, j0 = tk.z * 32;
-  const int s = pl.node_s[K], c = pl.node_c[K], ld = s + c;
-  T *P = Lp_all + l * pl.panel_elems + pl.node_off[K];
-  const T *Linv = reinterpret_cast<const T *>(pl.linv) + l * pl.sq_elems + pl.node_sq[K];
-  const T *dinv = reinterpret_cast<const T *>(pl.dinv) + l * pl.n + pl.node_first[K];
+  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
+  const T *Q = Src_all + l * pl.panel_elems + gp(pl.node_off)[K];  // LDL^T panel (mode 0 reads it)
+  T *P = Lp_all + l * pl.panel_elems + gp(pl.node_off)[K];         // normalized panel (mode 1 writes it)
+  const T *Linv = reinterpret_cast<const T *>(pl.linv) + l * pl.sq_elems + gp(pl.node_sq)[K];
+  const T *dinv = reinterpret_cast<const T *>(pl.dinv) + l * pl.n + gp(pl.node_first)[K];
   T acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = zero_of<T>();
@@ -584,7 +573,7 @@ __global__ void __launch_bounds__(NT) k_normalize_sq(DevPlan pl, T *Lp_all, T *d
     ke = s;
   }
   for (int k0 = kb; k0 < ke; k0 += 32) {
-    __syncthreads();
+    lds_barrier();
     for (int e = threadIdx.x; e < 32 * 32; e += NT) {
       const int kk = e & 31, x = e >> 5;
       const int k = k0 + kk;
@@ -592,11 +581,11 @@ __global__ void __launch_bounds__(NT) k_normalize_sq(DevPlan pl, T *Lp_all, T *d
       if (k < ke) {
         const int ia = i0 + x, jb = j0 + x;
         if (mode == 0) {  // L[i][k] with unit diagonal
-          if (ia < s) va = (ia == k) ? SOps<T>::one() : (ia > k ? P[(int64_t)k * ld + ia] : zero_of<T>());
-          if (jb < s) vb = (jb == k) ? SOps<T>::one() : (jb > k ? P[(int64_t)k * ld + jb] : zero_of<T>());
+          if (ia < s) va = (ia == k) ? SOps<T>::one() : (ia > k ? Q[(int64_t)k * ld + ia] : zero_of<T>());
+          if (jb < s) vb = (jb == k) ? SOps<T>::one() : (jb > k ? Q[(int64_t)k * ld + jb] : zero_of<T>());
         } else {  // Linv[k][i] (column-major, ld s), lower triangular
-          if (ia < s) va = Linv[(int64_t)ia * s + k];
-          if (jb < s) vb = Linv[(int64_t)jb * s + k];
+          if (ia < s) va = gload(Linv + (int64_t)ia * s + k);
+          if (jb < s) vb = gload(Linv + (int64_t)jb * s + k);
         }
       }
 #pragma unroll
@@ -608,11 +597,11 @@ __global__ void __launch_bounds__(NT) k_normalize_sq(DevPlan pl, T *Lp_all, T *d
     if (threadIdx.x < 32) {
       const int k = k0 + threadIdx.x;
       T d = zero_of<T>();
-      if (k < ke) d = (mode == 0) ? P[(int64_t)k * ld + k] : dinv[k];
+      if (k < ke) d = (mode == 0) ? Q[(int64_t)k * ld + k] : gload(dinv + k);
 #pragma unroll
       for (int p = 0; p < Planes<T>::P; ++p) dv[p][threadIdx.x] = Planes<T>::get(d, p);
     }
-    __syncthreads();
+    lds_barrier();
     for (int kk = 0; kk < 32; ++kk) {
       T a, d;
       if constexpr (Planes<T>::P == 1) {
@@ -639,7 +628,7 @@ __global__ void __launch_bounds__(NT) k_normalize_sq(DevPlan pl, T *Lp_all, T *d
     const int j = j0 + tj * 4 + q;
     if (i < s && j < s) {
       if (mode == 0)
-        dt_all[l * pl.sq_elems + pl.node_sq[K] + (int64_t)j * s + i] = acc[q];
+        dt_all[l * pl.sq_elems + gp(pl.node_sq)[K] + (int64_t)j * s + i] = acc[q];
       else
         P[(int64_t)j * ld + i] = acc[q];
     }
@@ -647,11 +636,12 @@ __global__ void __launch_bounds__(NT) k_normalize_sq(DevPlan pl, T *Lp_all, T *d
 }
 
 template <typename T>
-__global__ void k_extract(DevPlan pl, const T *Xp, T *out) {
+__global__ void k_extract(const DevPlan *__restrict__ plp, const T *Xp, T *out) {
+  const DevPlan &pl = *plp;
   const int64_t total = pl.batch * pl.nnzA;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t l = q / pl.nnzA, e = q - l * pl.nnzA;
-    out[q] = Xp[l * pl.panel_elems + pl.apos[e]];
+    out[q] = Xp[l * pl.panel_elems + gp(pl.apos)[e]];
   }
 }
 
@@ -659,51 +649,55 @@ __global__ void k_extract(DevPlan pl, const T *Xp, T *out) {
 // Host-side launchers (called from the C ABI translation unit)
 // ---------------------------------------------------------------------------
 template <typename T>
-static hipError_t normalize_impl(const DevPlan &pl, const LaunchAux &aux, void *panels, void *dt, hipStream_t st) {
+static hipError_t normalize_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const void *src,
+                                 void *panels, void *dt, hipStream_t st) {
+  const T *Q = reinterpret_cast<const T *>(src);
   T *Lp = reinterpret_cast<T *>(panels);
   if (aux.nchunks > 0) {
-    hipLaunchKernelGGL(k_normalize_rows<T>, dim3((unsigned)(aux.nchunks * pl.batch)), dim3(NT), 0, st, pl, Lp,
+    hipLaunchKernelGGL(k_normalize_rows<T>, dim3((unsigned)(aux.nchunks * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
                        aux.chunks, aux.nchunks);
   }
   if (aux.nsq_tiles > 0) {
     if (dt)
-      hipLaunchKernelGGL(k_normalize_sq<T>, dim3((unsigned)(aux.nsq_tiles * pl.batch)), dim3(NT), 0, st, pl, Lp,
+      hipLaunchKernelGGL(k_normalize_sq<T>, dim3((unsigned)(aux.nsq_tiles * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
                          reinterpret_cast<T *>(dt), aux.sq_tiles, aux.nsq_tiles, 0);
-    hipLaunchKernelGGL(k_normalize_sq<T>, dim3((unsigned)(aux.nsq_tiles * pl.batch)), dim3(NT), 0, st, pl, Lp,
+    hipLaunchKernelGGL(k_normalize_sq<T>, dim3((unsigned)(aux.nsq_tiles * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
                        (T *)nullptr, aux.sq_tiles, aux.nsq_tiles, 1);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_normalize(const DevPlan &pl, const LaunchAux &aux, bool cplx_, void *panels, void *dt,
-                            hipStream_t st) {
-  return cplx_ ? normalize_impl<cplx>(pl, aux, panels, dt, st) : normalize_impl<double>(pl, aux, panels, dt, st);
+hipError_t launch_normalize(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, const void *src,
+                            void *panels, void *dt, hipStream_t st) {
+  return cplx_ ? normalize_impl<cplx>(pl, dpl, aux, src, panels, dt, st)
+               : normalize_impl<double>(pl, dpl, aux, src, panels, dt, st);
 }
 
 template <typename T>
-static hipError_t run_impl(const DevPlan &pl, const LaunchAux &aux, int sched, const void *panels, void *x,
+static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, int sched, const void *panels, void *x,
                            int64_t budget_ticks, int grid, hipStream_t st) {
   const T *Lp = reinterpret_cast<const T *>(panels);
   T *Xp = reinterpret_cast<T *>(x);
+  T *Pp = reinterpret_cast<T *>(pl.part);
   if (sched == 1) {
     for (int q = 0; q < aux.nlvl; ++q) {
       const int32_t b = aux.lvl_ptr[q], e = aux.lvl_ptr[q + 1];
       if (e > b)
-        hipLaunchKernelGGL(k_items_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, pl, Lp, Xp,
+        hipLaunchKernelGGL(k_items_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,
                            aux.lvl_items + b, e - b);
     }
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_sched_init, dim3(256), dim3(256), 0, st, pl);
-  hipLaunchKernelGGL(k_sched_seed, dim3(256), dim3(256), 0, st, pl);
-  hipLaunchKernelGGL(k_persistent<T>, dim3((unsigned)grid), dim3(NT), 0, st, pl, Lp, Xp, budget_ticks);
+  hipLaunchKernelGGL(k_sched_init, dim3(256), dim3(256), 0, st, dpl);
+  hipLaunchKernelGGL(k_sched_seed, dim3(256), dim3(256), 0, st, dpl);
+  hipLaunchKernelGGL(k_persistent<T>, dim3((unsigned)grid), dim3(NT), 0, st, dpl, Lp, Xp, Pp, budget_ticks);
   return hipGetLastError();
 }
 
-hipError_t launch_run(const DevPlan &pl, const LaunchAux &aux, bool cplx_, int sched, const void *panels, void *x,
-                      int64_t budget_ticks, int grid, hipStream_t st) {
-  return cplx_ ? run_impl<cplx>(pl, aux, sched, panels, x, budget_ticks, grid, st)
-               : run_impl<double>(pl, aux, sched, panels, x, budget_ticks, grid, st);
+hipError_t launch_run(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, int sched, const void *panels,
+                      void *x, int64_t budget_ticks, int grid, hipStream_t st) {
+  return cplx_ ? run_impl<cplx>(pl, dpl, aux, sched, panels, x, budget_ticks, grid, st)
+               : run_impl<double>(pl, dpl, aux, sched, panels, x, budget_ticks, grid, st);
 }
 
 int persistent_blocks_per_cu(bool cplx_) {
@@ -715,16 +709,16 @@ int persistent_blocks_per_cu(bool cplx_) {
   return nb;
 }
 
-hipError_t launch_extract(const DevPlan &pl, bool cplx_, const void *x, void *out, hipStream_t st) {
+hipError_t launch_extract(const DevPlan &pl, const DevPlan *dpl, bool cplx_, const void *x, void *out, hipStream_t st) {
   const int64_t total = pl.batch * pl.nnzA;
   unsigned grid = (unsigned)((total + 255) / 256);
   if (grid > 65536u) grid = 65536u;
   if (grid == 0) grid = 1;
   if (cplx_)
-    hipLaunchKernelGGL(k_extract<cplx>, dim3(grid), dim3(256), 0, st, pl, reinterpret_cast<const cplx *>(x),
+    hipLaunchKernelGGL(k_extract<cplx>, dim3(grid), dim3(256), 0, st, dpl, reinterpret_cast<const cplx *>(x),
                        reinterpret_cast<cplx *>(out));
   else
-    hipLaunchKernelGGL(k_extract<double>, dim3(grid), dim3(256), 0, st, pl, reinterpret_cast<const double *>(x),
+    hipLaunchKernelGGL(k_extract<double>, dim3(grid), dim3(256), 0, st, dpl, reinterpret_cast<const double *>(x),
                        reinterpret_cast<double *>(out));
   return hipGetLastError();
 }

@@ -32,13 +32,18 @@ struct alignas(16) Item {
 };
 
 // Control words of the persistent scheduler.
-enum Ctrl : int32_t { CTRL_HEAD = 0, CTRL_TAIL = 1, CTRL_ERR = 2, CTRL_DONE = 3, CTRL_WORDS = 64 };
+// Control words of the persistent scheduler: an error flag, the completed
+// item count, and head / tail of each ready queue.  Ready items are kept in
+// kMaxQ queues by etree depth class; workgroups always take from the
+// shallowest non-empty queue (nodes near the root lie on every critical path).
+constexpr int kMaxQ = 32;
+enum Ctrl : int32_t { CTRL_ERR = 0, CTRL_DONE = 1, CTRL_QHEAD = 16, CTRL_QTAIL = 16 + kMaxQ, CTRL_WORDS = 16 + 2 * kMaxQ };
 
 // Raw device pointers, valid for one (context, work buffer) pair.
 struct DevPlan {
-  int64_t n, ns, nitems, batch, panel_elems, sq_elems, nnzA, total_rows;
+  int64_t n, ns, nitems, batch, panel_elems, sq_elems, nnzA, total_rows, part_elems;
   int32_t *node_s, *node_c;
-  int64_t *node_off, *node_rowptr, *node_sq, *node_first;
+  int64_t *node_off, *node_rowptr, *node_sq, *node_first, *node_poff;
   int64_t *kcol, *kpos;
   int32_t *posarr;
   Item *items;
@@ -50,15 +55,20 @@ struct DevPlan {
   int32_t *push_list;
   int32_t *root_list;  // items of all roots' first phases
   int32_t nroot_items;
+  int32_t nq;          // number of ready queues in use (<= kMaxQ)
+  int32_t *node_q;     // [ns] queue of a node's items: min(depth, nq - 1)
+  int32_t *qbase;      // [nq + 1] first slot of each queue (all matrices of the batch)
   int32_t *lvl_items;  // item ids grouped by (level, phase)
   int64_t *apos;       // [nnzA] A entry -> panel element
   uint8_t *adiag;      // [nnzA]
   // scratch
   void *linv;          // [batch][sq_elems] scalars
   void *dinv;          // [batch][n] scalars
+  void *part;          // [batch][part_elems] GEMM-2 partial products
   int32_t *cnt1, *cnt2;  // [batch][ns]
   int32_t *queue;      // [batch * nitems]
   int32_t *ctrl;       // CTRL_WORDS
+  int64_t *trace;      // optional: per queue slot {item id, workgroup, t_pop, t_start, t_end, 0, 0, 0}
 };
 
 // Host-side launch lists (device pointers into the work buffer, except lvl_ptr).

@@ -234,7 +234,9 @@ void analyze(Symbolic &S, int64_t n, const int64_t *colptr, const int64_t *rowin
   for (int64_t K = 0; K < ns; ++K) {
     int64_t s = S.width(K), c = S.nrows(K);
     S.panel_off[K] = off;
-    off += (s + c) * s;
+    // each panel starts on a 16-element (>= 128-byte) boundary, so no cache
+    // line is shared by two nodes' panels
+    off += ((s + c) * s + kPanelAlign - 1) / kPanelAlign * kPanelAlign;
     fl += 2.0 * (double)c * (double)c * (double)s + 2.0 * (double)c * (double)s * (double)s;
   }
   S.panel_elems = off;

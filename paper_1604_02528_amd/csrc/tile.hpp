@@ -1,0 +1,400 @@
+// Device building blocks shared by the forward and adjoint kernels:
+// a 64 x 64 FP64 MFMA tile with a three-level software-pipelined operand
+// loader (index tables -> positions -> data), LDS staging, and memory
+// access policies for data produced by other workgroups of the same launch.
+//
+// MFMA f64 16x16x4 operand layout (measured on gfx950): lane l holds
+// A[l % 16][l / 16], B[l / 16][l % 16] and D[4 v + l / 16][l % 16] in its v-th
+// accumulator register.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.hpp"
+#include "scalar.hpp"
+
+namespace selinv {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Global-address-space views of pointers.  Table and data pointers live in the
+// device-resident plan, so the compiler sees them as generic pointers and
+// would emit flat loads, which count against the LDS wait counter too and
+// make every LDS wait drain the operand prefetch.
+#define SELINV_GAS __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ const SELINV_GAS T *gp(const T *p) { return (const SELINV_GAS T *)p; }
+template <typename T> __device__ __forceinline__ SELINV_GAS T *gw(T *p) { return (SELINV_GAS T *)p; }
+
+// An all-ones / all-zero mask the optimizer cannot see through: selecting
+// loaded values with it keeps every load unconditional (a plain select lets
+// the compiler sink a load into a branch, which then waits on it).
+__device__ __forceinline__ int64_t opaque_mask(bool keep) {
+  int64_t m = keep ? -1 : 0;
+  asm("" : "+v"(m));
+  return m;
+}
+__device__ __forceinline__ double masked(double v, int64_t m) {
+  return __builtin_bit_cast(double, __builtin_bit_cast(int64_t, v) & m);
+}
+
+__device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int NT = 256;    // threads per workgroup (4 waves)
+
+// Workgroup barrier that orders LDS only.  __syncthreads() also waits for
+// every outstanding global load (vmcnt(0)), which would drain the operand
+// prefetch pipeline at each stage; global-memory ordering inside a workgroup
+// uses __syncthreads() explicitly where it is needed.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+constexpr int PITCH = 65;  // LDS row pitch in doubles
+
+template <typename T> struct Planes;
+template <> struct Planes<double> {
+  static constexpr int P = 1;
+  static constexpr int TK = 16;  // contraction step per LDS stage
+  static __device__ __forceinline__ double get(double v, int) { return v; }
+};
+template <> struct Planes<cplx> {
+  static constexpr int P = 2;
+  static constexpr int TK = 16;
+  static __device__ __forceinline__ double get(cplx v, int p) { return p ? v.im : v.re; }
+};
+
+template <typename T> __device__ __forceinline__ T zero_of() { return SOps<T>::zero(); }
+
+// Elements of one operand stage loaded by each thread.
+template <typename T> __device__ __forceinline__ constexpr int ept() { return 64 * Planes<T>::TK / NT; }
+template <typename T> __device__ __forceinline__ constexpr int stage_doubles() {
+  return 2 * Planes<T>::P * Planes<T>::TK * PITCH;
+}
+// One 64 x PITCH tile (all planes).  Two stages fit in one tile.
+template <typename T> __device__ __forceinline__ constexpr int tile_doubles() { return Planes<T>::P * 64 * PITCH; }
+// Workgroup LDS: two tiles (the GEMM stages live in the first).
+template <typename T> __device__ __forceinline__ constexpr int smem_doubles() { return 2 * tile_doubles<T>(); }
+
+// ---------------------------------------------------------------------------
+// Memory policy for the selected inverse X (and partial products), which
+// other workgroups of the same launch write.  Coherent accesses are
+// agent-scope relaxed atomics: they bypass the non-coherent per-XCD caches,
+// so no cache-wide invalidation is ever needed to read a producer's data.
+// ---------------------------------------------------------------------------
+template <bool COH> struct Mem;
+template <> struct Mem<false> {
+  static __device__ __forceinline__ double ld(const double *p) { return *gp(p); }
+  static __device__ __forceinline__ cplx ld(const cplx *p) {
+    const double *q = reinterpret_cast<const double *>(p);
+    return cplx{*gp(q), *gp(q + 1)};
+  }
+  static __device__ __forceinline__ void st(double *p, double v) { *gw(p) = v; }
+  static __device__ __forceinline__ void st(cplx *p, cplx v) {
+    double *q = reinterpret_cast<double *>(p);
+    *gw(q) = v.re;
+    *gw(q + 1) = v.im;
+  }
+};
+template <> struct Mem<true> {
+  static __device__ __forceinline__ double ld(const double *p) {
+    return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  static __device__ __forceinline__ cplx ld(const cplx *p) {
+    const double *q = reinterpret_cast<const double *>(p);
+    return cplx{__hip_atomic_load(gp(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                __hip_atomic_load(gp(q + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+  }
+  static __device__ __forceinline__ void st(double *p, double v) {
+    __hip_atomic_store(gw(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  static __device__ __forceinline__ void st(cplx *p, cplx v) {
+    double *q = reinterpret_cast<double *>(p);
+    __hip_atomic_store(gw(q), v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(gw(q + 1), v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+
+__device__ __forceinline__ cplx masked(cplx v, int64_t m) { return cplx{masked(v.re, m), masked(v.im, m)}; }
+
+// Plain global loads / stores of scalars through generic pointers.
+template <typename T> __device__ __forceinline__ T gload(const T *p) { return Mem<false>::ld(p); }
+template <typename T> __device__ __forceinline__ void gstore(T *p, T v) { Mem<false>::st(p, v); }
+__device__ __forceinline__ Item gload(const Item *p) {
+  const int32_t *q = reinterpret_cast<const int32_t *>(p);
+  return Item{gp(q)[0], gp(q)[1], gp(q)[2], gp(q)[3]};
+}
+
+// ---------------------------------------------------------------------------
+// MFMA tile
+// ---------------------------------------------------------------------------
+template <typename T> struct Acc {
+  d4 v[Planes<T>::P][2][2];
+};
+
+template <typename T> __device__ __forceinline__ void acc_zero(Acc<T> &acc) {
+#pragma unroll
+  for (int p = 0; p < Planes<T>::P; ++p)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc.v[p][bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_compute(const double *stg, Acc<T> &acc) {
+  constexpr int P = Planes<T>::P, TK = Planes<T>::TK;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w & 1, wj = w >> 1;
+#pragma unroll
+  for (int k4 = 0; k4 < TK / 4; ++k4) {
+    const int r = (4 * k4 + (lane >> 4)) * PITCH + (lane & 15);
+    double a[2][P], b[2][P];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        a[x][p] = stg[p * TK * PITCH + r + 32 * wi + 16 * x];
+        b[x][p] = stg[(P + p) * TK * PITCH + r + 32 * wj + 16 * x];
+      }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        if constexpr (P == 1) {
+          acc.v[0][bi][bj] = mfma16(a[bi][0], b[bj][0], acc.v[0][bi][bj]);
+        } else {
+          acc.v[0][bi][bj] = mfma16(a[bi][0], b[bj][0], acc.v[0][bi][bj]);
+          acc.v[0][bi][bj] = mfma16(-a[bi][1], b[bj][1], acc.v[0][bi][bj]);
+          acc.v[1][bi][bj] = mfma16(a[bi][0], b[bj][1], acc.v[1][bi][bj]);
+          acc.v[1][bi][bj] = mfma16(a[bi][1], b[bj][0], acc.v[1][bi][bj]);
+        }
+      }
+  }
+}
+
+// Operand loaders run a three-level pipeline per stage of TK contraction
+// indices: lev1 (index tables), lev2 (positions), lev3 (values).  Each loader
+// defines its own per-stage state types S1, S2 (empty when a level has
+// nothing to load) and the LDS slot of its m-th element for a stage.
+template <typename T> struct Vals {
+  T v[64 * Planes<T>::TK / NT];
+};
+
+template <typename T, class L>
+__device__ __forceinline__ void stage_store(double *stg, int plane_off, int k0, const L &ld, const Vals<T> &v) {
+  constexpr int P = Planes<T>::P, TK = Planes<T>::TK;
+#pragma unroll
+  for (int m = 0; m < ept<T>(); ++m) {
+    const int slot = ld.slot(k0, m);
+#pragma unroll
+    for (int p = 0; p < P; ++p) stg[(plane_off + p) * TK * PITCH + slot] = Planes<T>::get(v.v[m], p);
+  }
+}
+
+// acc = A (64 x kc) * B (kc x 64).  LA fills the A planes, LB the B planes.
+// Pipeline: while stage kt is multiplied, the values of stage kt+2, the
+// positions of stage kt+3 and the index entries of stage kt+4 are in flight.
+// The loop body has no branches: prefetch stage indices are clamped to the
+// last stage (the redundant reloads at the end are harmless), so the waits
+// the compiler inserts are counted waits on the oldest loads only.
+template <typename T, class LA, class LB>
+__device__ __forceinline__ void gemm_tile(int kc, const LA &la, const LB &lb, double *smem, Acc<T> &acc) {
+  constexpr int P = Planes<T>::P, TK = Planes<T>::TK;
+  acc_zero<T>(acc);
+  const int nk = (kc + TK - 1) / TK;
+  if (nk == 0) return;
+  const int klast = (nk - 1) * TK;
+  typename LA::S1 a1;
+  typename LB::S1 b1;
+  typename LA::S2 a2;
+  typename LB::S2 b2;
+  Vals<T> av, bv;
+  la.lev1(0, a1);
+  lb.lev1(0, b1);
+  la.lev2(0, a1, a2);
+  lb.lev2(0, b1, b2);
+  la.lev3(0, a2, av);
+  lb.lev3(0, b2, bv);
+  stage_store<T>(smem, 0, 0, la, av);
+  stage_store<T>(smem, P, 0, lb, bv);
+  const int k1 = min(TK, klast), k2 = min(2 * TK, klast), k3 = min(3 * TK, klast);
+  la.lev1(k1, a1);
+  lb.lev1(k1, b1);
+  la.lev2(k1, a1, a2);
+  lb.lev2(k1, b1, b2);
+  la.lev3(k1, a2, av);
+  lb.lev3(k1, b2, bv);
+  la.lev1(k2, a1);
+  lb.lev1(k2, b1);
+  la.lev2(k2, a1, a2);
+  lb.lev2(k2, b1, b2);
+  la.lev1(k3, a1);
+  lb.lev1(k3, b1);
+  lds_barrier();
+  for (int kt = 0; kt < nk; ++kt) {
+    stage_compute<T>(smem + (kt & 1) * stage_doubles<T>(), acc);
+    double *nxt = smem + ((kt + 1) & 1) * stage_doubles<T>();
+    const int ks = min((kt + 1) * TK, klast);
+    stage_store<T>(nxt, 0, ks, la, av);
+    stage_store<T>(nxt, P, ks, lb, bv);
+    lds_barrier();
+    const int kv = min((kt + 2) * TK, klast), kp = min((kt + 3) * TK, klast), ki = min((kt + 4) * TK, klast);
+    la.lev3(kv, a2, av);
+    lb.lev3(kv, b2, bv);
+    la.lev2(kp, a1, a2);
+    lb.lev2(kp, b1, b2);
+    la.lev1(ki, a1);
+    lb.lev1(ki, b1);
+  }
+}
+
+// Scatter the accumulators into an LDS tile C[p][j * PITCH + i]; caller syncs.
+template <typename T>
+__device__ __forceinline__ void acc_to_lds(const Acc<T> &acc, double *ct) {
+  constexpr int P = Planes<T>::P;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w & 1, wj = w >> 1;
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 32 * wi + 16 * bi + 4 * v + (lane >> 4);
+          const int j = 32 * wj + 16 * bj + (lane & 15);
+          ct[p * 64 * PITCH + j * PITCH + i] = acc.v[p][bi][bj][v];
+        }
+}
+
+template <typename T> __device__ __forceinline__ T lds_get(const double *ct, int i, int j);
+template <> __device__ __forceinline__ double lds_get<double>(const double *ct, int i, int j) {
+  return ct[j * PITCH + i];
+}
+template <> __device__ __forceinline__ cplx lds_get<cplx>(const double *ct, int i, int j) {
+  return cplx{ct[j * PITCH + i], ct[64 * PITCH + j * PITCH + i]};
+}
+template <typename T> __device__ __forceinline__ void lds_put(double *ct, int i, int j, T v);
+template <> __device__ __forceinline__ void lds_put<double>(double *ct, int i, int j, double v) {
+  ct[j * PITCH + i] = v;
+}
+template <> __device__ __forceinline__ void lds_put<cplx>(double *ct, int i, int j, cplx v) {
+  ct[j * PITCH + i] = v.re;
+  ct[64 * PITCH + j * PITCH + i] = v.im;
+}
+
+// ---------------------------------------------------------------------------
+// Loaders
+// ---------------------------------------------------------------------------
+
+struct Empty {};
+
+// Column block of a panel's bottom part, k-major: value(kk, x) =
+// P[off + (x0 + x) * ld + s + kbase + k0 + kk] for kbase + k0 + kk < kend and
+// x0 + x < xmax (x = 0..63: a row of A^T or a column of B).
+template <typename T, bool COH> struct LoadPanelK {
+  using S1 = Empty;
+  using S2 = Empty;
+  const T *Pn;
+  int64_t off;
+  int ld, s, kbase, kend, x0, xmax;
+  __device__ __forceinline__ int slot(int, int m) const {
+    constexpr int TK = Planes<T>::TK;
+    const int e = threadIdx.x + NT * m;
+    return (e & (TK - 1)) * PITCH + e / TK;
+  }
+  __device__ __forceinline__ void lev1(int, S1 &) const {}
+  __device__ __forceinline__ void lev2(int, const S1 &, S2 &) const {}
+  // Branch-free: out-of-range elements read the panel's first element and are
+  // masked to zero, so all loads of a stage issue together.
+  __device__ __forceinline__ void lev3(int k0, const S2 &, Vals<T> &v) const {
+    constexpr int TK = Planes<T>::TK;
+#pragma unroll
+    for (int m = 0; m < ept<T>(); ++m) {
+      const int e = threadIdx.x + NT * m;
+      const int kk = e & (TK - 1), x = e / TK;
+      const int kg = kbase + k0 + kk, xg = x0 + x;
+      const bool ok = kg < kend && xg < xmax;
+      const int64_t msk = opaque_mask(ok);
+      const int64_t a = (((int64_t)xg * ld + s + kg) & msk) + off;
+      v.v[m] = masked(Mem<COH>::ld(Pn + a), msk);
+    }
+  }
+};
+
+// A = X_{C,C} of node K (rows i0.., all columns), gathered from the
+// ancestors' X panels through the canonical maps:
+//   lower (i >= k): X[kcol[k] + posarr[kpos[k] + i]],  upper: X[kcol[i] + posarr[kpos[i] + k]].
+// kcol/kpos of the 64 tile rows are staged in LDS (rt_col, rt_pos).  Lower
+// blocks map lanes along i, upper blocks along k, so both read panel columns
+// contiguously.
+template <typename T, bool COH> struct LoadGather {
+  static constexpr int E = 64 * Planes<T>::TK / NT;
+  struct S1 {
+    int64_t base[E];
+    int64_t pidx[E];
+    int64_t msk[E];
+  };
+  struct S2 {
+    int64_t addr[E];
+    int64_t msk[E];
+  };
+  const T *X;
+  const int64_t *kcol, *kpos;  // node-local per-row tables (global)
+  const int32_t *posarr;
+  const int64_t *rt_col, *rt_pos;  // LDS copies for rows i0 .. i0+63
+  int c, i0;
+  __device__ __forceinline__ void coords(int k0, int m, int &i, int &kk) const {
+    constexpr int TK = Planes<T>::TK;
+    const int e = threadIdx.x + NT * m;
+    if (i0 + 63 < k0) {  // strictly upper block
+      kk = e & (TK - 1);
+      i = e / TK;
+    } else {
+      i = e & 63;
+      kk = e >> 6;
+    }
+  }
+  __device__ __forceinline__ int slot(int k0, int m) const {
+    int i, kk;
+    coords(k0, m, i, kk);
+    return kk * PITCH + i;
+  }
+  // All three levels load unconditionally (clamped indices, opaque masks).
+  __device__ __forceinline__ void lev1(int k0, S1 &r) const {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      int i, kk;
+      coords(k0, m, i, kk);
+      const int ig = i0 + i, kg = k0 + kk;
+      const int64_t okm = opaque_mask(ig < c && kg < c);
+      const int64_t lm = opaque_mask(ig >= kg);
+      const int64_t kq = (int64_t)kg & okm & lm;
+      const int64_t bl = gp(kcol)[kq], plo = gp(kpos)[kq];
+      const int64_t bu = rt_col[i], pu = rt_pos[i];
+      r.base[m] = (bl & lm) | (bu & ~lm);
+      r.pidx[m] = (((plo + ig) & lm) | ((pu + kg) & ~lm)) & okm;
+      r.msk[m] = okm;
+    }
+  }
+  __device__ __forceinline__ void lev2(int, const S1 &r, S2 &q) const {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int64_t pos = (int64_t)gp(posarr)[r.pidx[m]];
+      q.addr[m] = (r.base[m] + pos) & r.msk[m];
+      q.msk[m] = r.msk[m];
+    }
+  }
+  __device__ __forceinline__ void lev3(int, const S2 &q, Vals<T> &v) const {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v.v[m] = masked(Mem<COH>::ld(X + q.addr[m]), q.msk[m]);
+  }
+};
+
+}  // namespace selinv

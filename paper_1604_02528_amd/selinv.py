@@ -90,6 +90,23 @@ class SelInv:
         nb = self.batch * self.panel_elems * (16 if self.is_complex else 8)
         return b[:nb].view(self.scalar_dtype).view(self.batch, self.panel_elems)
 
+    def packed_index(self):
+        """Element indices of the unpadded concatenation of the panels."""
+        if getattr(self, "_packed", None) is None:
+            sym = self.symbolic()
+            ws = np.diff(sym["xsuper"])
+            cs = np.diff(sym["rowptr"])
+            sizes = (ws + cs) * ws
+            starts = sym["panel_off"]
+            idx = np.concatenate([np.arange(st, st + sz) for st, sz in zip(starts, sizes)]) if len(sizes) else np.zeros(0, np.int64)
+            self._packed = idx
+        return self._packed
+
+    def to_host(self, which="x"):
+        """[batch, sum_K (s+c) s] numpy copy of X (or the panels), panels packed back to back."""
+        full = self.panels_view(which).cpu().numpy()
+        return full[:, self.packed_index()]
+
     # -- numeric -----------------------------------------------------------------
     def _values_host(self, values):
         if isinstance(values, torch.Tensor):
@@ -114,6 +131,16 @@ class SelInv:
 
     def run(self):
         capi.selinv_run(self.h, self._bufs["panels"], self._bufs["x"], self._bufs["work"], _stream())
+
+    def trace_run(self):
+        """Run once with per-item tracing; returns int64 [n_items, 8] rows
+        {item, workgroup, t_pop, t_start, t_end, 0, 0, 0} (wall-clock ticks)."""
+        tr = torch.zeros(self.sizes.trace_bytes // 8, dtype=torch.int64, device=self.device)
+        capi.selinv_trace(self.h, tr)
+        self.run()
+        self.sync()
+        capi.selinv_trace(self.h, None)
+        return tr.view(-1, 8).cpu().numpy()
 
     def sync(self):
         capi.selinv_sync(self.h, _stream())

@@ -31,7 +31,7 @@ def test_selinv_matches_oracle(name, scale, batch, relax, sched):
     S.factor(w.values)
     S.run()
     S.sync()
-    X = S.panels_view("x").cpu().numpy()
+    X = S.to_host("x")
     ref = oracle_x(name, scale, batch, relax)
     tol = 1e-9 if w.is_complex else 1e-10
     for l in range(w.batch):

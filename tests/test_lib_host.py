@@ -61,7 +61,7 @@ def test_host_factor_matches_oracle(name, scale, batch, relax):
     w = workload(name, scale, batch)
     sym = oracle_sym(name, scale, batch, relax)
     S = lib_ctx(w, relax)
-    P = S.factor_host(w.values)
+    P = S.factor_host(w.values)[:, S.packed_index()]
     mask = np.concatenate([np.tril(np.ones((sym.width(K) + sym.rows[K].shape[0], sym.width(K)), bool)).reshape(-1, order="F")
                            for K in range(sym.nsuper)])
     for l in range(w.batch):
@@ -71,3 +71,16 @@ def test_host_factor_matches_oracle(name, scale, batch, relax):
         ld = S.logdet()[l]
         ref_ld = factor.logdet(sym, factor.factor(sym, w.values[l]))
         assert abs(ld - ref_ld) <= 1e-10 * max(1.0, abs(ref_ld))
+
+
+@pytest.mark.parametrize("name,scale,batch,relax", [("C1", None, None, 0.0), ("C2", 12, None, 0.0),
+                                                     ("C2", None, None, 0.05), ("C3", 8, 3, 0.05),
+                                                     ("C5", 6, 2, 0.0)])
+def test_scheduler_plan_replay(name, scale, batch, relax):
+    """Host replay of the persistent scheduler's protocol: every item becomes
+    ready exactly once, after all of its dependencies, within queue capacity."""
+    from paper_1604_02528_amd import capi
+
+    w = workload(name, scale, batch)
+    S = lib_ctx(w, relax)
+    capi.selinv_check_plan(S.h)
