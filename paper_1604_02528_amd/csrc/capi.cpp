@@ -7,8 +7,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <new>
+#include <queue>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "internal.hpp"
@@ -38,9 +41,8 @@ struct HostPlan {
   std::vector<int64_t> node_off, node_rowptr, node_sq, node_first, node_poff;
   std::vector<int64_t> kcol, kpos;
   std::vector<Item> items;
-  std::vector<int32_t> item_ptr, n_phase1, n_phase2, first_beg, first_end, push_ptr, push_list, root_list;
-  std::vector<int32_t> node_q, qbase;
-  int32_t nq = 1;
+  std::vector<int32_t> item_ptr, n_phase1, n_phase2, node_parent;
+  std::vector<int32_t> order;  // ticket order of the persistent schedule (all matrices)
   std::vector<int32_t> lvl_items, lvl_ptr;
   std::vector<int2> chunks;
   std::vector<int4> sq_tiles;
@@ -51,7 +53,7 @@ struct HostPlan {
   // byte offsets inside the work buffer
   struct Off {
     int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
-        n_phase1, n_phase2, first_beg, first_end, push_ptr, push_list, root_list, node_q, qbase, lvl_items, chunks,
+        n_phase1, n_phase2, node_parent, order, lvl_items, chunks,
         sq_tiles,
         apos, adiag, plan, linv, dinv, part, cnt1, cnt2, queue, ctrl, end;
   } off{};
@@ -61,6 +63,110 @@ struct HostPlan {
 template <typename V>
 void put(std::vector<unsigned char> &img, int64_t off, const std::vector<V> &v) {
   if (!v.empty()) std::memcpy(img.data() + off, v.data(), sizeof(V) * v.size());
+}
+
+// Ticket order of the persistent schedule.  The dependency graph of every
+// matrix of the batch is list-scheduled on kSimWorkers identical workers
+// under a simple cost model (flops at a fixed per-workgroup rate plus a fixed
+// per-item overhead), always starting the ready item with the longest
+// remaining path to the end of the traversal; tickets follow the simulated
+// start order.  An item starts only after its dependencies have finished, so
+// every dependency of an item holds a smaller ticket: the kernel, which hands
+// tickets out in order and lets each workgroup wait for its own item's
+// dependencies, can never deadlock.
+constexpr int kSimWorkers = 256;
+
+double item_cost_ns(const HostPlan &H, const Item &it) {
+  const double s = H.node_s[it.K], c = H.node_c[it.K];
+  switch (it.type) {
+    case ITEM_Y: {
+      const double m = std::min<double>(kTileM, c - (double)kTileM * it.a);
+      const double nn = std::min<double>(kTileN, s - (double)kTileN * it.b);
+      return 1500.0 + (2.0 * m * nn * c + 2.0 * s * m * nn) / 100.0;
+    }
+    case ITEM_D: {
+      const double nr = std::ceil(c / kTileM);
+      return 1000.0 + nr * (double)kTileN * kTileN * 8.0 / 60.0;
+    }
+    default:
+      return 1500.0 + (2.0 * c * c * s + 2.0 * c * s * s) / 50.0;
+  }
+}
+
+void ticket_order(const Symbolic &S, HostPlan &H, int64_t batch) {
+  const int64_t ns = S.nsuper(), nit = (int64_t)H.items.size();
+  std::vector<double> cost(nit), height(nit);
+  for (int64_t i = 0; i < nit; ++i) cost[i] = item_cost_ns(H, H.items[i]);
+  // remaining path: supernodes are numbered children first
+  std::vector<double> first_h(ns, 0.0), tail(ns, 0.0);
+  for (int64_t K = 0; K < ns; ++K) {
+    const int32_t b = H.item_ptr[K], n1 = H.n_phase1[K], n2 = H.n_phase2[K];
+    double hmax2 = 0.0;
+    for (int32_t i = b + n1; i < b + n1 + n2; ++i) {
+      height[i] = cost[i] + tail[K];
+      hmax2 = std::max(hmax2, height[i]);
+    }
+    double hmax1 = hmax2;
+    if (n1 > 0) {
+      hmax1 = 0.0;
+      for (int32_t i = b; i < b + n1; ++i) {
+        height[i] = cost[i] + hmax2;
+        hmax1 = std::max(hmax1, height[i]);
+      }
+    }
+    first_h[K] = hmax1;
+    if (S.sparent[K] >= 0) tail[S.sparent[K]] = std::max(tail[S.sparent[K]], hmax1);
+  }
+  std::vector<std::vector<int32_t>> kids(ns);
+  for (int64_t K = 0; K < ns; ++K)
+    if (S.sparent[K] >= 0) kids[S.sparent[K]].push_back((int32_t)K);
+  // ready set: largest remaining path first, then the lowest id
+  using RItem = std::pair<double, int64_t>;
+  auto rcmp = [](const RItem &x, const RItem &y) { return x.first < y.first || (x.first == y.first && x.second > y.second); };
+  std::priority_queue<RItem, std::vector<RItem>, decltype(rcmp)> ready(rcmp);
+  using Ev = std::pair<double, int64_t>;
+  std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> running;
+  std::vector<int32_t> cnt1((size_t)(batch * ns)), cnt2((size_t)(batch * ns));
+  auto release_first = [&](int64_t l, int64_t K) {
+    const int32_t b = H.item_ptr[K];
+    const int32_t n = H.n_phase1[K] > 0 ? H.n_phase1[K] : H.n_phase2[K];
+    for (int32_t i = b; i < b + n; ++i) ready.push({height[i], l * nit + i});
+  };
+  for (int64_t l = 0; l < batch; ++l)
+    for (int64_t K = 0; K < ns; ++K) {
+      cnt1[l * ns + K] = H.n_phase1[K];
+      cnt2[l * ns + K] = H.n_phase2[K];
+      if (S.sparent[K] < 0) release_first(l, K);
+    }
+  H.order.clear();
+  H.order.reserve((size_t)(batch * nit));
+  double now = 0.0;
+  int64_t busy = 0;
+  while (!ready.empty() || !running.empty()) {
+    while (busy < kSimWorkers && !ready.empty()) {
+      const int64_t id = ready.top().second;
+      ready.pop();
+      H.order.push_back((int32_t)id);
+      running.push({now + cost[id % nit], id});
+      ++busy;
+    }
+    if (running.empty()) break;
+    now = running.top().first;
+    while (!running.empty() && running.top().first <= now) {
+      const int64_t id = running.top().second;
+      running.pop();
+      --busy;
+      const int64_t l = id / nit, i = id % nit, K = H.items[i].K;
+      if (H.items[i].type == ITEM_Y) {
+        if (--cnt1[l * ns + K] == 0) {
+          const int32_t b = H.item_ptr[K] + H.n_phase1[K];
+          for (int32_t j = b; j < b + H.n_phase2[K]; ++j) ready.push({height[j], l * nit + j});
+        }
+      } else if (--cnt2[l * ns + K] == 0) {
+        for (int32_t ch : kids[K]) release_first(l, ch);
+      }
+    }
+  }
 }
 
 void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan &H) {
@@ -128,37 +234,9 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan
     }
   }
   H.item_ptr[ns] = (int32_t)H.items.size();
-  H.first_beg.resize(ns);
-  H.first_end.resize(ns);
-  for (int64_t K = 0; K < ns; ++K) {
-    H.first_beg[K] = H.item_ptr[K];
-    H.first_end[K] = H.item_ptr[K] + (H.n_phase1[K] > 0 ? H.n_phase1[K] : H.n_phase2[K]);
-  }
-  std::vector<std::vector<int32_t>> kids(ns);
-  for (int64_t K = 0; K < ns; ++K)
-    if (S.sparent[K] >= 0) kids[S.sparent[K]].push_back((int32_t)K);
-  H.push_ptr.assign(ns + 1, 0);
-  H.push_list.clear();
-  for (int64_t K = 0; K < ns; ++K) {
-    H.push_ptr[K] = (int32_t)H.push_list.size();
-    for (int32_t ch : kids[K])
-      for (int32_t it = H.first_beg[ch]; it < H.first_end[ch]; ++it) H.push_list.push_back(it);
-  }
-  H.push_ptr[ns] = (int32_t)H.push_list.size();
-  H.root_list.clear();
-  for (int64_t K = 0; K < ns; ++K)
-    if (S.sparent[K] < 0)
-      for (int32_t it = H.first_beg[K]; it < H.first_end[K]; ++it) H.root_list.push_back(it);
-  // ready-queue classes by depth
-  H.nq = (int32_t)std::max<int64_t>(1, std::min<int64_t>(kMaxQ, S.depth));
-  H.node_q.resize(ns);
-  std::vector<int64_t> qcount(H.nq, 0);
-  for (int64_t K = 0; K < ns; ++K) {
-    H.node_q[K] = (int32_t)std::min<int64_t>(S.sdepth[K], H.nq - 1);
-    qcount[H.node_q[K]] += H.n_phase1[K] + H.n_phase2[K];
-  }
-  H.qbase.assign(H.nq + 1, 0);
-  for (int q = 0; q < H.nq; ++q) H.qbase[q + 1] = H.qbase[q] + (int32_t)(qcount[q] * batch);
+  H.node_parent.resize(ns);
+  for (int64_t K = 0; K < ns; ++K) H.node_parent[K] = (int32_t)S.sparent[K];
+  ticket_order(S, H, batch);
   // level lists (phase 1, then phase 2, per etree depth)
   H.lvl_items.clear();
   H.lvl_ptr.assign(1, 0);
@@ -210,13 +288,8 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan
   o.item_ptr = take(4 * (ns + 1));
   o.n_phase1 = take(4 * ns);
   o.n_phase2 = take(4 * ns);
-  o.first_beg = take(4 * ns);
-  o.first_end = take(4 * ns);
-  o.push_ptr = take(4 * (ns + 1));
-  o.push_list = take(4 * (int64_t)H.push_list.size());
-  o.root_list = take(4 * (int64_t)H.root_list.size());
-  o.node_q = take(4 * ns);
-  o.qbase = take(4 * (int64_t)H.qbase.size());
+  o.node_parent = take(4 * ns);
+  o.order = take(4 * (int64_t)H.order.size());
   o.lvl_items = take(4 * (int64_t)H.lvl_items.size());
   o.chunks = take(8 * (int64_t)H.chunks.size());
   o.sq_tiles = take(16 * (int64_t)H.sq_tiles.size());
@@ -229,7 +302,6 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan
   o.part = take(scalar_bytes * batch * H.part_elems);
   o.cnt1 = take(4 * batch * ns);
   o.cnt2 = take(4 * batch * ns);
-  o.queue = take(4 * batch * (int64_t)H.items.size());
   o.ctrl = take(4 * CTRL_WORDS);
   o.end = p;
 }
@@ -307,15 +379,8 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.item_ptr = (int32_t *)(b + o.item_ptr);
   d.n_phase1 = (int32_t *)(b + o.n_phase1);
   d.n_phase2 = (int32_t *)(b + o.n_phase2);
-  d.first_beg = (int32_t *)(b + o.first_beg);
-  d.first_end = (int32_t *)(b + o.first_end);
-  d.push_ptr = (int32_t *)(b + o.push_ptr);
-  d.push_list = (int32_t *)(b + o.push_list);
-  d.root_list = (int32_t *)(b + o.root_list);
-  d.nroot_items = (int32_t)H.root_list.size();
-  d.nq = H.nq;
-  d.node_q = (int32_t *)(b + o.node_q);
-  d.qbase = (int32_t *)(b + o.qbase);
+  d.node_parent = (int32_t *)(b + o.node_parent);
+  d.order = (int32_t *)(b + o.order);
   d.lvl_items = (int32_t *)(b + o.lvl_items);
   d.apos = (int64_t *)(b + o.apos);
   d.adiag = (uint8_t *)(b + o.adiag);
@@ -324,7 +389,6 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.part = (void *)(b + o.part);
   d.cnt1 = (int32_t *)(b + o.cnt1);
   d.cnt2 = (int32_t *)(b + o.cnt2);
-  d.queue = (int32_t *)(b + o.queue);
   d.ctrl = (int32_t *)(b + o.ctrl);
   d.trace = (int64_t *)h->trace;
   return d;
@@ -367,13 +431,8 @@ void build_image(selinv_ctx *h) {
   put(img, o.item_ptr, H.item_ptr);
   put(img, o.n_phase1, H.n_phase1);
   put(img, o.n_phase2, H.n_phase2);
-  put(img, o.first_beg, H.first_beg);
-  put(img, o.first_end, H.first_end);
-  put(img, o.push_ptr, H.push_ptr);
-  put(img, o.push_list, H.push_list);
-  put(img, o.root_list, H.root_list);
-  put(img, o.node_q, H.node_q);
-  put(img, o.qbase, H.qbase);
+  put(img, o.node_parent, H.node_parent);
+  put(img, o.order, H.order);
   put(img, o.lvl_items, H.lvl_items);
   put(img, o.chunks, H.chunks);
   put(img, o.sq_tiles, H.sq_tiles);
@@ -674,65 +733,40 @@ selinv_status selinv_check_plan(const selinv_ctx *hc) {
   const HostPlan &H = h->H;
   const Symbolic &S = h->S;
   const int64_t ns = S.nsuper(), nit = (int64_t)H.items.size(), B = h->opts.batch;
-  // replay of the device protocol: queues by class, counters, pushes
-  std::vector<std::vector<int64_t>> q(H.nq);
-  std::vector<int64_t> cap(H.nq);
-  for (int c = 0; c < H.nq; ++c) cap[c] = H.qbase[c + 1] - H.qbase[c];
+  // Replay of the ticket protocol: running the tickets one at a time in
+  // order, each item's dependencies must already be done when its turn comes.
+  if ((int64_t)H.order.size() != B * nit)
+    return set_err(h, SELINV_EINVAL, "plan check: ticket order has the wrong length", (int64_t)H.order.size(), B * nit);
   std::vector<int32_t> cnt1((size_t)(B * ns)), cnt2((size_t)(B * ns));
-  std::vector<uint8_t> seen((size_t)(B * nit), 0), node_done((size_t)(B * ns), 0), ph1_done((size_t)(B * ns), 0);
+  std::vector<uint8_t> seen((size_t)(B * nit), 0);
   for (int64_t l = 0; l < B; ++l)
     for (int64_t K = 0; K < ns; ++K) {
       cnt1[l * ns + K] = H.n_phase1[K];
       cnt2[l * ns + K] = H.n_phase2[K];
     }
-  for (int64_t l = 0; l < B; ++l)
-    for (int32_t it : H.root_list) q[0].push_back(l * nit + it);
-  if ((int64_t)q[0].size() > cap[0]) return set_err(h, SELINV_EINVAL, "plan check: root items exceed queue 0");
-  std::vector<size_t> head(H.nq, 0);
-  int64_t done = 0;
-  while (true) {
-    int c = 0;
-    while (c < H.nq && head[c] >= q[c].size()) ++c;
-    if (c == H.nq) break;
-    const int64_t id = q[c][head[c]++];
+  for (int64_t t = 0; t < B * nit; ++t) {
+    const int64_t id = H.order[t];
+    if (id < 0 || id >= B * nit) return set_err(h, SELINV_EINVAL, "plan check: ticket names no item", t, id);
     const int64_t l = id / nit, itn = id % nit;
-    if (seen[id]) return set_err(h, SELINV_EINVAL, "plan check: item popped twice", itn, l);
+    if (seen[id]) return set_err(h, SELINV_EINVAL, "plan check: item holds two tickets", itn, l);
     seen[id] = 1;
     const Item it = H.items[itn];
     const int64_t K = it.K;
-    if (H.node_q[K] != c) return set_err(h, SELINV_EINVAL, "plan check: item in the wrong queue", itn, l);
-    const bool first = (H.n_phase1[K] > 0) ? it.type == ITEM_Y : true;
-    const int64_t P = S.sparent[K];
-    if (first && P >= 0 && !node_done[l * ns + P])
-      return set_err(h, SELINV_EINVAL, "plan check: node started before its parent finished", K, l);
-    if (it.type != ITEM_Y && H.n_phase1[K] > 0 && !ph1_done[l * ns + K])
-      return set_err(h, SELINV_EINVAL, "plan check: phase 2 before phase 1", K, l);
-    std::vector<int64_t> push;
-    int qc = 0;
-    if (it.type == ITEM_Y) {
-      if (--cnt1[l * ns + K] == 0) {
-        ph1_done[l * ns + K] = 1;
-        for (int32_t j = 0; j < H.n_phase2[K]; ++j) push.push_back(l * nit + H.item_ptr[K] + H.n_phase1[K] + j);
-        qc = H.node_q[K];
-      }
+    if (it.type != ITEM_Y && H.n_phase1[K] > 0) {
+      if (cnt1[l * ns + K] != 0) return set_err(h, SELINV_EINVAL, "plan check: phase 2 before phase 1", K, l);
     } else {
-      if (--cnt2[l * ns + K] == 0) {
-        node_done[l * ns + K] = 1;
-        for (int32_t j = H.push_ptr[K]; j < H.push_ptr[K + 1]; ++j) push.push_back(l * nit + H.push_list[j]);
-        qc = std::min(H.node_q[K] + 1, H.nq - 1);
-      }
+      const int64_t P = H.node_parent[K];
+      if (P != S.sparent[K]) return set_err(h, SELINV_EINVAL, "plan check: wrong parent table", K, P);
+      if (P >= 0 && cnt2[l * ns + P] != 0)
+        return set_err(h, SELINV_EINVAL, "plan check: node started before its parent finished", K, l);
     }
-    for (int64_t v : push) {
-      if (H.node_q[H.items[v % nit].K] != qc) return set_err(h, SELINV_EINVAL, "plan check: push into a wrong queue", K, l);
-      q[qc].push_back(v);
-    }
-    if ((int64_t)q[qc].size() > cap[qc]) return set_err(h, SELINV_EINVAL, "plan check: queue overflow", qc, l);
-    ++done;
+    if (it.type == ITEM_Y) --cnt1[l * ns + K];
+    else --cnt2[l * ns + K];
   }
-  if (done != B * nit) return set_err(h, SELINV_EINVAL, "plan check: not every item ran", done, B * nit);
   for (int64_t l = 0; l < B; ++l)
     for (int64_t K = 0; K < ns; ++K)
-      if (!node_done[l * ns + K]) return set_err(h, SELINV_EINVAL, "plan check: node never finished", K, l);
+      if (cnt1[l * ns + K] != 0 || cnt2[l * ns + K] != 0)
+        return set_err(h, SELINV_EINVAL, "plan check: node never finished", K, l);
   return SELINV_OK;
 }
 
@@ -754,7 +788,7 @@ selinv_status selinv_sync(selinv_ctx *h, void *stream) {
     e = hipMemcpy(ctrl, b + h->H.off.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_err(h, e, "control readback");
     if (ctrl[CTRL_ERR] != 0)
-      return set_err(h, SELINV_EDEVICE, "persistent scheduler watchdog expired (ready queue stalled)");
+      return set_err(h, SELINV_EDEVICE, "persistent scheduler watchdog expired (an item waited too long for its dependencies)");
   }
   return SELINV_OK;
 }

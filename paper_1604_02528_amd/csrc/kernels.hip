@@ -227,13 +227,14 @@ __device__ void do_dtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
 }
 
 template <typename T, bool COH>
-__device__ void do_item(const Ctx<T> &cx, const Item &it, double *smem, int64_t *rt) {
+__device__ void do_item(const Ctx<T> &cx, const Item &item, double *smem, int64_t *rt) {
+  const Item it = uniform(item);
   if (it.type == ITEM_Y) {
     do_ytile<T, COH>(cx, it.K, it.a, it.b, smem, rt);
   } else if (it.type == ITEM_D) {
     do_dtile<T, COH>(cx, it.K, it.a, it.b, smem);
   } else {  // ITEM_S: the whole node (c <= 64, s <= 64) in this workgroup
-    if (cx.pl->node_c[it.K] > 0) {
+    if (uniform(gp(cx.pl->node_c)[it.K]) > 0) {
       do_ytile<T, COH>(cx, it.K, 0, 0, smem, rt);
       __threadfence_block();
       __syncthreads();
@@ -258,12 +259,10 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1) k_items_list(co
   do_item<T, false>(cx, gload(pl.items + it), smem, rt);
 }
 
-// Scheduler atomics.  Every cross-workgroup data access in the persistent
-// kernel goes through agent-scope atomics (see Mem<true>), so the queue and
-// counter protocol needs ordering but never a cache-wide invalidation:
-// producers finish their stores (release fence) before a counter or queue
-// update; consumers spin with relaxed loads and derive every data address from
-// the item they popped.
+// Scheduler atomics (agent scope, relaxed).  Producers order their data
+// stores before a counter update with a release fence; consumers spin on the
+// counter with relaxed loads and then read the data with plain loads (the
+// coherence argument is given at the release fence below).
 __device__ __forceinline__ int32_t ld_relaxed(const int32_t *p) {
   return __hip_atomic_load(gp(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -287,171 +286,95 @@ __global__ void k_sched_init(const DevPlan *__restrict__ plp) {
   if (blockIdx.x == 0 && threadIdx.x < CTRL_WORDS) gw(pl.ctrl)[threadIdx.x] = 0;
 }
 
-// Seed queue 0 (depth 0) with the first-phase items of every root of every
-// matrix; every other slot starts empty (-1).
-__global__ void k_sched_seed(const DevPlan *__restrict__ plp) {
-  const DevPlan &pl = *plp;
-  const int64_t nseed = pl.batch * pl.nroot_items;
-  const int64_t total = pl.batch * pl.nitems;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-    int32_t v = -1;
-    if (i < nseed) {
-      const int64_t l = i / pl.nroot_items;
-      v = (int32_t)(l * pl.nitems + gp(pl.root_list)[i - l * pl.nroot_items]);
-    }
-    gw(pl.queue)[i] = v;
+// Wait (executed by one whole wave, with wave-uniform control flow) until
+// item `it` of matrix l may run: a phase-2 item of a node that has phase-1
+// items waits for that phase; any other item waits for its node's parent to
+// finish (a root's first items are ready at once).  Returns false when
+// another workgroup raised the error flag or when the watchdog, counted from
+// kernel start, expires (then it raises the flag).
+__device__ bool wait_ready(const DevPlan &pl, int64_t l, const Item &it, int64_t t_begin, int64_t budget_ticks) {
+  const int32_t *ctr;
+  if (it.type != ITEM_Y && uniform(gp(pl.n_phase1)[it.K]) > 0) {
+    ctr = pl.cnt1 + l * pl.ns + it.K;
+  } else {
+    const int32_t P = uniform(gp(pl.node_parent)[it.K]);
+    if (P < 0) return true;
+    ctr = pl.cnt2 + l * pl.ns + P;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) gw(pl.ctrl)[CTRL_QTAIL] = (int32_t)nseed;
-}
-
-__device__ __forceinline__ bool cas_relaxed(int32_t *p, int32_t expect, int32_t desire) {
-  return __hip_atomic_compare_exchange_strong(gw(p), &expect, desire, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                              __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Take one published item (executed by the 64 lanes of wave 0).  One vector
-// load reads every queue's head and tail, a ballot picks the shallowest
-// non-empty queue and lane 0 claims its head slot with a CAS, then waits for
-// the producer's slot store (it reserves slots just before writing them).
-// Idle polling backs off exponentially.  Returns the item id, -3 when every
-// item is done, -2 on error; the watchdog counts from kernel start.
-__device__ int32_t pop_item(const DevPlan &pl, int64_t total, int64_t t_begin, int64_t budget_ticks,
-                            int32_t &slot_out) {
-  const int lane = threadIdx.x & 63;
   int backoff = 1;
-  while (true) {
-    int32_t h = 0, t = 0;
-    if (lane < pl.nq) {
-      h = ld_relaxed(pl.ctrl + CTRL_QHEAD + lane);
-      t = ld_relaxed(pl.ctrl + CTRL_QTAIL + lane);
+  while (uniform(ld_relaxed(ctr)) != 0) {
+    if (uniform(ld_relaxed(pl.ctrl + CTRL_ERR)) != 0) return false;
+    if (wall_clock64() - t_begin > budget_ticks) {
+      if ((threadIdx.x & 63) == 0) st_relaxed(pl.ctrl + CTRL_ERR, 1);
+      return false;
     }
-    const uint64_t nonempty = __ballot(h < t);
-    if (nonempty) {
-      const int q = __ffsll((unsigned long long)nonempty) - 1;
-      const int32_t hq = __shfl(h, q);
-      int got = 0;
-      if (lane == 0) got = cas_relaxed(pl.ctrl + CTRL_QHEAD + q, hq, hq + 1) ? 1 : 0;
-      got = __shfl(got, 0);
-      if (!got) continue;  // lost the race: rescan at once
-      const int32_t slot = gp(pl.qbase)[q] + hq;
-      int32_t id = -2;
-      if (lane == 0) {
-        while (true) {
-          id = ld_relaxed(pl.queue + slot);
-          if (id >= 0) break;
-          if (wall_clock64() - t_begin > budget_ticks) {
-            st_relaxed(pl.ctrl + CTRL_ERR, 1);
-            id = -2;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-      }
-      slot_out = slot;
-      return __shfl(id, 0);
-    }
-    int32_t state = 0;  // 0: keep waiting, -3: all done, -2: error
-    if (lane == 0) {
-      if (ld_relaxed(pl.ctrl + CTRL_DONE) >= total) state = -3;
-      else if (ld_relaxed(pl.ctrl + CTRL_ERR) != 0) state = -2;
-      else if (wall_clock64() - t_begin > budget_ticks) {
-        st_relaxed(pl.ctrl + CTRL_ERR, 1);
-        state = -2;
-      }
-    }
-    state = __shfl(state, 0);
-    if (state != 0) return state;
-    for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(2);
-    backoff = backoff < 64 ? 2 * backoff : 64;
+    for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(1);
+    backoff = backoff < 8 ? 2 * backoff : 8;
   }
+  return true;
 }
 
+// Persistent traversal: every workgroup draws tickets from one counter and
+// runs the items of the ticket order (a topological order of the dependency
+// graph), each after its own dependencies are done.  The ticket draw, the
+// wait and the counter update are done by wave 0 as a whole; every branch
+// around a barrier is wave-uniform.
 template <typename T>
 __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
     k_persistent(const DevPlan *__restrict__ plp, const T *Lp, T *Xp, T *Pp, int64_t budget_ticks) {
   const DevPlan &pl = *plp;
   __shared__ double smem[smem_doubles<T>()];
   __shared__ int64_t rt[128];
-  __shared__ int32_t s_id, s_idx, s_push_beg, s_push_cnt, s_push_base, s_push_l, s_push_kind;
+  __shared__ int32_t s_id, s_ticket;
   __shared__ int64_t s_tpop;
   const int64_t total = pl.batch * pl.nitems;
   const int64_t t_begin = wall_clock64();
+  const bool wave0 = uniform((int32_t)threadIdx.x) < 64;
+  const bool lane0 = threadIdx.x == 0;
   while (true) {
-    if (threadIdx.x < 64) {
-      int32_t slot = 0;
-      const int32_t id = pop_item(pl, total, t_begin, budget_ticks, slot);
-      if (threadIdx.x == 0) {
+    if (wave0) {
+      int32_t t = 0;
+      if (lane0) t = add_relaxed(pl.ctrl + CTRL_TICKET, 1);
+      t = uniform(t);
+      int32_t id = -1;
+      if (t < total) {
+        id = uniform(gp(pl.order)[t]);
+        const int64_t l = id / pl.nitems;
+        if (!wait_ready(pl, l, uniform(gload(pl.items + (id - l * pl.nitems))), t_begin, budget_ticks)) id = -2;
+      }
+      if (lane0) {
         s_id = id;
-        s_idx = slot;
+        s_ticket = t;
         s_tpop = pl.trace ? wall_clock64() : 0;
       }
     }
     __syncthreads();
-    const int32_t id = s_id;
+    const int32_t id = uniform(s_id);
     if (id < 0) break;
     const int64_t t_start = pl.trace ? wall_clock64() : 0;
     const int64_t l = id / pl.nitems;
     const int32_t itn = (int32_t)(id - l * pl.nitems);
-    const Item it = gload(pl.items + itn);
+    const Item it = uniform(gload(pl.items + itn));
     Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, Pp + l * pl.part_elems};
     do_item<T, false>(cx, it, smem, rt);
     // Publishing protocol: write back this item's stores (agent-scope release)
-    // before any counter or queue update.  Readers use plain cached loads:
-    // every panel and partial block starts on its own cache line, and a
-    // node's data is read only after the node has completed, so no L2 can
-    // hold a line of it from before it was written (caches start clean at
-    // kernel launch).
+    // before the counter update.  Readers use plain cached loads: every panel
+    // and partial block starts on its own cache line, and a node's data is
+    // read only after the node has completed, so no cache can hold a line of
+    // it from before it was written (caches start clean at kernel launch).
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (wave0 && lane0) {
       if (pl.trace) {
-        int64_t *tr = pl.trace + 8 * (int64_t)s_idx;
+        int64_t *tr = pl.trace + 8 * (int64_t)s_ticket;
         tr[0] = id;
         tr[1] = blockIdx.x;
         tr[2] = s_tpop;
         tr[3] = t_start;
         tr[4] = wall_clock64();
       }
-      const int64_t nk = l * pl.ns + it.K;
-      int32_t cnt = 0, beg = 0, kind = 0, q = 0;
-      if (it.type == ITEM_Y) {
-        if (add_relaxed(pl.cnt1 + nk, -1) == 1) {  // phase 1 done: release phase 2
-          beg = gp(pl.item_ptr)[it.K] + gp(pl.n_phase1)[it.K];
-          cnt = gp(pl.n_phase2)[it.K];
-          kind = 0;
-          q = gp(pl.node_q)[it.K];
-        }
-      } else {
-        if (add_relaxed(pl.cnt2 + nk, -1) == 1) {  // node done: release the children
-          beg = gp(pl.push_ptr)[it.K];
-          cnt = gp(pl.push_ptr)[it.K + 1] - beg;
-          kind = 1;
-          q = min(gp(pl.node_q)[it.K] + 1, pl.nq - 1);
-        }
-      }
-      s_push_cnt = cnt;
-      s_push_beg = beg;
-      s_push_kind = kind;
-      s_push_l = (int32_t)l;
-      s_push_base = cnt > 0 ? gp(pl.qbase)[q] + add_relaxed(pl.ctrl + CTRL_QTAIL + q, cnt) : 0;
-      s_idx = cnt > 0 ? gp(pl.qbase)[q + 1] : 0;  // end of queue q (bound check below)
+      add_relaxed((it.type == ITEM_Y ? pl.cnt1 : pl.cnt2) + l * pl.ns + it.K, -1);
     }
-    __syncthreads();
-    const int32_t cnt = s_push_cnt;
-    if (cnt > 0) {
-      const int32_t beg = s_push_beg, base = s_push_base, kind = s_push_kind, qend = s_idx;
-      const int64_t loff = (int64_t)s_push_l * pl.nitems;
-      for (int32_t q = threadIdx.x; q < cnt; q += NT) {
-        const int32_t item = kind == 0 ? beg + q : gp(pl.push_list)[beg + q];
-        if (base + q < qend)
-          st_relaxed(pl.queue + base + q, (int32_t)(loff + item));
-        else  // more pushes than the queue holds: a broken dependency table; stop everyone
-          st_relaxed(pl.ctrl + CTRL_ERR, 2);
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) add_relaxed(pl.ctrl + CTRL_DONE, 1);
   }
 }
 
@@ -689,7 +612,6 @@ static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_sched_init, dim3(256), dim3(256), 0, st, dpl);
-  hipLaunchKernelGGL(k_sched_seed, dim3(256), dim3(256), 0, st, dpl);
   hipLaunchKernelGGL(k_persistent<T>, dim3((unsigned)grid), dim3(NT), 0, st, dpl, Lp, Xp, Pp, budget_ticks);
   return hipGetLastError();
 }

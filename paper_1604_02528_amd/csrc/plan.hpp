@@ -31,13 +31,11 @@ struct alignas(16) Item {
   int32_t K, type, a, b;
 };
 
-// Control words of the persistent scheduler.
-// Control words of the persistent scheduler: an error flag, the completed
-// item count, and head / tail of each ready queue.  Ready items are kept in
-// kMaxQ queues by etree depth class; workgroups always take from the
-// shallowest non-empty queue (nodes near the root lie on every critical path).
-constexpr int kMaxQ = 32;
-enum Ctrl : int32_t { CTRL_ERR = 0, CTRL_DONE = 1, CTRL_QHEAD = 16, CTRL_QTAIL = 16 + kMaxQ, CTRL_WORDS = 16 + 2 * kMaxQ };
+// Control words of the persistent scheduler: an error flag and the ticket
+// counter, on cache lines of their own.  Workgroups draw tickets in order;
+// ticket t names the item order[t] (a topological order of the dependency
+// graph, so the smallest unfinished ticket can always run).
+enum Ctrl : int32_t { CTRL_ERR = 0, CTRL_TICKET = 32, CTRL_WORDS = 64 };
 
 // Raw device pointers, valid for one (context, work buffer) pair.
 struct DevPlan {
@@ -50,14 +48,8 @@ struct DevPlan {
   int32_t *item_ptr;   // [ns+1]
   int32_t *n_phase1;   // [ns]
   int32_t *n_phase2;   // [ns]
-  int32_t *first_beg, *first_end;  // [ns] range of a node's first-phase items
-  int32_t *push_ptr;   // [ns+1] children's first items, flattened
-  int32_t *push_list;
-  int32_t *root_list;  // items of all roots' first phases
-  int32_t nroot_items;
-  int32_t nq;          // number of ready queues in use (<= kMaxQ)
-  int32_t *node_q;     // [ns] queue of a node's items: min(depth, nq - 1)
-  int32_t *qbase;      // [nq + 1] first slot of each queue (all matrices of the batch)
+  int32_t *node_parent; // [ns] supernodal etree parent (-1 at a root)
+  int32_t *order;      // [batch * nitems] ticket -> l * nitems + item
   int32_t *lvl_items;  // item ids grouped by (level, phase)
   int64_t *apos;       // [nnzA] A entry -> panel element
   uint8_t *adiag;      // [nnzA]
@@ -66,9 +58,8 @@ struct DevPlan {
   void *dinv;          // [batch][n] scalars
   void *part;          // [batch][part_elems] GEMM-2 partial products
   int32_t *cnt1, *cnt2;  // [batch][ns]
-  int32_t *queue;      // [batch * nitems]
   int32_t *ctrl;       // CTRL_WORDS
-  int64_t *trace;      // optional: per queue slot {item id, workgroup, t_pop, t_start, t_end, 0, 0, 0}
+  int64_t *trace;      // optional: per ticket {item id, workgroup, t_ticket, t_start, t_end, 0, 0, 0}
 };
 
 // Host-side launch lists (device pointers into the work buffer, except lvl_ptr).

@@ -129,6 +129,16 @@ __device__ __forceinline__ Item gload(const Item *p) {
   return Item{gp(q)[0], gp(q)[1], gp(q)[2], gp(q)[3]};
 }
 
+// Value of the first active lane, held in a scalar register.  Every branch
+// and loop bound that a workgroup barrier depends on is made wave-uniform this
+// way: a condition the compiler takes for divergent lets it restructure the
+// loop so that some lanes of a wave reach the next barrier ahead of others
+// (the barrier counts waves, not lanes).
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ Item uniform(const Item &it) {
+  return Item{uniform(it.K), uniform(it.type), uniform(it.a), uniform(it.b)};
+}
+
 // ---------------------------------------------------------------------------
 // MFMA tile
 // ---------------------------------------------------------------------------

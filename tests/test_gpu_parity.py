@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 import torch
 
-from tests._ref import maxrel, oracle_x, workload
+from tests._ref import maxrel, oracle_sym, oracle_x, workload
 
 CASES = [
     # (name, scale, batch, relax)
@@ -38,3 +38,47 @@ def test_selinv_matches_oracle(name, scale, batch, relax, sched):
         err = maxrel(X[l], ref[l])
         print(f"  matrix {l}: max-norm rel err {err:.3e}", flush=True)
         assert err <= tol
+
+
+def _perturbed_values(w, seed):
+    """Same pattern, new SPD values: off-diagonal entries scaled by U[0.8, 1]
+    keep the weighted Laplacian diagonally dominant."""
+    rng = np.random.default_rng(seed)
+    cols = np.repeat(np.arange(w.n), np.diff(w.colptr))
+    off = w.rowind != cols
+    v = w.values.copy()
+    v[:, off] *= rng.uniform(0.8, 1.0, size=(w.batch, int(off.sum())))
+    return v
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("sched", ["levels", "persistent"])
+def test_rerun_new_values_and_determinism(sched):
+    """A second factor + run on the same context and buffers with new values
+    must give the new inverse (no stale data survives a launch), and a repeat
+    run must reproduce X bit for bit (the traversal has no data races)."""
+    from oracle import factor, selinv, symbolic
+    from paper_1604_02528_amd import SelInv
+
+    w = workload("C2", 12, None)
+    print(f"rerun case C2 scale=12 relax=0.05 sched={sched}", flush=True)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, batch=w.batch, cap=w.cap, relax=0.05, sched=sched,
+               watchdog_ms=20000)
+    S.factor(w.values)
+    S.run()
+    S.sync()
+    assert maxrel(S.to_host("x")[0], oracle_x("C2", 12, None, 0.05)[0]) <= 1e-10
+    v2 = _perturbed_values(w, 77)
+    S.factor(v2)
+    S.run()
+    S.sync()
+    X1 = S.to_host("x")
+    sym = oracle_sym("C2", 12, None, 0.05)
+    lh, dt = factor.normalize(sym, factor.factor(sym, v2[0]))
+    ref = selinv.flatten(sym, selinv.alg1(sym, lh, dt))
+    err = maxrel(X1[0], ref)
+    print(f"  new values: max-norm rel err {err:.3e}", flush=True)
+    assert err <= 1e-10
+    S.run()
+    S.sync()
+    assert np.array_equal(S.to_host("x"), X1)
