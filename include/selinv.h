@@ -76,8 +76,11 @@ typedef struct {
   int32_t sched;       /* selinv_sched */
   double relax;        /* explicit-zero budget of supernode chain amalgamation, 0 = maximal supernodes */
   int32_t nthreads;    /* host threads for the factorization; 0 = hardware concurrency */
-  int32_t tile_rows;   /* GEMM-1 row tile (64 or 128); 0 = autotuned default */
+  int32_t dense_min_c; /* nodes with |C(K)| >= this get a dense X_{C,C} buffer in the work area
+                          (gathered once, then read by plain GEMM tiles); 0 = 256, < 0 = never */
   int64_t watchdog_ms; /* persistent kernel spin budget before it aborts (0 = 10000 ms) */
+  int64_t dense_max_bytes; /* cap on those buffers for the whole batch; the threshold is doubled
+                              until they fit (0 = 32 GiB) */
 } selinv_opts;
 
 /* Fill `o` with defaults (cap 256, R64, batch 1, persistent, relax 0). */

@@ -30,8 +30,8 @@ EXPORTED = (
 
 class Opts(C.Structure):
     _fields_ = [("max_super", C.c_int32), ("dtype", C.c_int32), ("batch", C.c_int32), ("sched", C.c_int32),
-                ("relax", C.c_double), ("nthreads", C.c_int32), ("tile_rows", C.c_int32),
-                ("watchdog_ms", C.c_int64)]
+                ("relax", C.c_double), ("nthreads", C.c_int32), ("dense_min_c", C.c_int32),
+                ("watchdog_ms", C.c_int64), ("dense_max_bytes", C.c_int64)]
 
 
 _P64 = C.POINTER(C.c_int64)

@@ -41,7 +41,10 @@ struct HostPlan {
   std::vector<int64_t> node_off, node_rowptr, node_sq, node_first, node_poff;
   std::vector<int64_t> kcol, kpos;
   std::vector<Item> items;
-  std::vector<int32_t> item_ptr, n_phase1, n_phase2, node_parent;
+  std::vector<int32_t> item_ptr, n_phase0, n_phase1, n_phase2, node_parent, node_ldg;
+  std::vector<int64_t> node_goff;
+  int64_t g_elems = 0;
+  int64_t dense_min_c = 0;  // threshold in use (INT64_MAX: no dense buffers)
   std::vector<int32_t> order;  // ticket order of the persistent schedule (all matrices)
   std::vector<int32_t> lvl_items, lvl_ptr;
   std::vector<int2> chunks;
@@ -53,9 +56,9 @@ struct HostPlan {
   // byte offsets inside the work buffer
   struct Off {
     int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
-        n_phase1, n_phase2, node_parent, order, lvl_items, chunks,
+        n_phase0, n_phase1, n_phase2, node_goff, node_ldg, node_parent, order, lvl_items, chunks,
         sq_tiles,
-        apos, adiag, plan, linv, dinv, part, cnt1, cnt2, queue, ctrl, end;
+        apos, adiag, plan, linv, dinv, part, gbuf, cnt0, cnt1, cnt2, ctrl, end;
   } off{};
   int64_t tables_bytes = 0;  // [0, tables_bytes) is uploaded once
 };
@@ -75,47 +78,58 @@ void put(std::vector<unsigned char> &img, int64_t off, const std::vector<V> &v) 
 // tickets out in order and lets each workgroup wait for its own item's
 // dependencies, can never deadlock.
 constexpr int kSimWorkers = 256;
+constexpr int64_t kDefaultDenseMinC = 256;
+constexpr int64_t kDefaultDenseMaxBytes = int64_t(32) << 30;
 
 double item_cost_ns(const HostPlan &H, const Item &it) {
   const double s = H.node_s[it.K], c = H.node_c[it.K];
+  const bool dense = H.node_goff[it.K] >= 0;
   switch (it.type) {
+    case ITEM_G:
+      return 2500.0 + (double)kTileM * kTileM * 24.0 / 60.0;
     case ITEM_Y: {
       const double m = std::min<double>(kTileM, c - (double)kTileM * it.a);
       const double nn = std::min<double>(kTileN, s - (double)kTileN * it.b);
-      return 1500.0 + (2.0 * m * nn * c + 2.0 * s * m * nn) / 100.0;
+      return 1500.0 + (2.0 * m * nn * c) / (dense ? 150.0 : 40.0) + (2.0 * s * m * nn) / 150.0;
     }
     case ITEM_D: {
       const double nr = std::ceil(c / kTileM);
       return 1000.0 + nr * (double)kTileN * kTileN * 8.0 / 60.0;
     }
     default:
-      return 1500.0 + (2.0 * c * c * s + 2.0 * c * s * s) / 50.0;
+      return 1500.0 + (2.0 * c * c * s + 2.0 * c * s * s) / 40.0;
   }
 }
+
+// Items of phase ph of node K: [phase_begin, phase_begin + phase_count).
+int32_t phase_begin(const HostPlan &H, int64_t K, int ph) {
+  return H.item_ptr[K] + (ph > 0 ? H.n_phase0[K] : 0) + (ph > 1 ? H.n_phase1[K] : 0);
+}
+int32_t phase_count(const HostPlan &H, int64_t K, int ph) {
+  return ph == 0 ? H.n_phase0[K] : ph == 1 ? H.n_phase1[K] : H.n_phase2[K];
+}
+int first_phase(const HostPlan &H, int64_t K) { return H.n_phase0[K] > 0 ? 0 : H.n_phase1[K] > 0 ? 1 : 2; }
+int item_phase(const Item &it) { return it.type == ITEM_G ? 0 : it.type == ITEM_Y ? 1 : 2; }
 
 void ticket_order(const Symbolic &S, HostPlan &H, int64_t batch) {
   const int64_t ns = S.nsuper(), nit = (int64_t)H.items.size();
   std::vector<double> cost(nit), height(nit);
   for (int64_t i = 0; i < nit; ++i) cost[i] = item_cost_ns(H, H.items[i]);
   // remaining path: supernodes are numbered children first
-  std::vector<double> first_h(ns, 0.0), tail(ns, 0.0);
+  std::vector<double> tail(ns, 0.0);
   for (int64_t K = 0; K < ns; ++K) {
-    const int32_t b = H.item_ptr[K], n1 = H.n_phase1[K], n2 = H.n_phase2[K];
-    double hmax2 = 0.0;
-    for (int32_t i = b + n1; i < b + n1 + n2; ++i) {
-      height[i] = cost[i] + tail[K];
-      hmax2 = std::max(hmax2, height[i]);
-    }
-    double hmax1 = hmax2;
-    if (n1 > 0) {
-      hmax1 = 0.0;
-      for (int32_t i = b; i < b + n1; ++i) {
-        height[i] = cost[i] + hmax2;
-        hmax1 = std::max(hmax1, height[i]);
+    double next = tail[K];  // longest path after the current phase
+    for (int ph = 2; ph >= 0; --ph) {
+      const int32_t b = phase_begin(H, K, ph), n = phase_count(H, K, ph);
+      if (n == 0) continue;
+      double hmax = 0.0;
+      for (int32_t i = b; i < b + n; ++i) {
+        height[i] = cost[i] + next;
+        hmax = std::max(hmax, height[i]);
       }
+      next = hmax;
     }
-    first_h[K] = hmax1;
-    if (S.sparent[K] >= 0) tail[S.sparent[K]] = std::max(tail[S.sparent[K]], hmax1);
+    if (S.sparent[K] >= 0) tail[S.sparent[K]] = std::max(tail[S.sparent[K]], next);
   }
   std::vector<std::vector<int32_t>> kids(ns);
   for (int64_t K = 0; K < ns; ++K)
@@ -126,17 +140,15 @@ void ticket_order(const Symbolic &S, HostPlan &H, int64_t batch) {
   std::priority_queue<RItem, std::vector<RItem>, decltype(rcmp)> ready(rcmp);
   using Ev = std::pair<double, int64_t>;
   std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> running;
-  std::vector<int32_t> cnt1((size_t)(batch * ns)), cnt2((size_t)(batch * ns));
-  auto release_first = [&](int64_t l, int64_t K) {
-    const int32_t b = H.item_ptr[K];
-    const int32_t n = H.n_phase1[K] > 0 ? H.n_phase1[K] : H.n_phase2[K];
+  std::vector<int32_t> left((size_t)(batch * ns * 3));
+  auto release = [&](int64_t l, int64_t K, int ph) {
+    const int32_t b = phase_begin(H, K, ph), n = phase_count(H, K, ph);
     for (int32_t i = b; i < b + n; ++i) ready.push({height[i], l * nit + i});
   };
   for (int64_t l = 0; l < batch; ++l)
     for (int64_t K = 0; K < ns; ++K) {
-      cnt1[l * ns + K] = H.n_phase1[K];
-      cnt2[l * ns + K] = H.n_phase2[K];
-      if (S.sparent[K] < 0) release_first(l, K);
+      for (int ph = 0; ph < 3; ++ph) left[(l * ns + K) * 3 + ph] = phase_count(H, K, ph);
+      if (S.sparent[K] < 0) release(l, K, first_phase(H, K));
     }
   H.order.clear();
   H.order.reserve((size_t)(batch * nit));
@@ -157,19 +169,53 @@ void ticket_order(const Symbolic &S, HostPlan &H, int64_t batch) {
       running.pop();
       --busy;
       const int64_t l = id / nit, i = id % nit, K = H.items[i].K;
-      if (H.items[i].type == ITEM_Y) {
-        if (--cnt1[l * ns + K] == 0) {
-          const int32_t b = H.item_ptr[K] + H.n_phase1[K];
-          for (int32_t j = b; j < b + H.n_phase2[K]; ++j) ready.push({height[j], l * nit + j});
-        }
-      } else if (--cnt2[l * ns + K] == 0) {
-        for (int32_t ch : kids[K]) release_first(l, ch);
+      int ph = item_phase(H.items[i]);
+      if (--left[(l * ns + K) * 3 + ph] != 0) continue;
+      // phase done: release the next non-empty phase, or the children
+      int nx = ph + 1;
+      while (nx < 3 && phase_count(H, K, nx) == 0) ++nx;
+      if (nx < 3) {
+        release(l, K, nx);
+      } else {
+        for (int32_t ch : kids[K]) release(l, ch, first_phase(H, ch));
       }
     }
   }
 }
 
-void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan &H) {
+// Nodes with |C(K)| >= the threshold get a dense X_{C,C} buffer; the
+// threshold is the requested one, raised in powers of two until the buffers of
+// the whole batch fit in max_bytes.
+void choose_dense(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t min_c, int64_t max_bytes,
+                  HostPlan &H) {
+  const int64_t ns = S.nsuper();
+  H.node_goff.assign(ns, -1);
+  H.node_ldg.assign(ns, 0);
+  H.g_elems = 0;
+  H.dense_min_c = INT64_MAX;
+  if (min_c < 0) return;
+  int64_t t = std::max<int64_t>(min_c, kTileM + 1);
+  while (true) {
+    int64_t tot = 0;
+    for (int64_t K = 0; K < ns; ++K)
+      if (S.nrows(K) >= t) tot += (S.nrows(K) + kPanelAlign - 1) / kPanelAlign * kPanelAlign * S.nrows(K);
+    if (tot == 0) return;
+    if (tot * batch * scalar_bytes <= max_bytes) break;
+    t *= 2;
+  }
+  H.dense_min_c = t;
+  for (int64_t K = 0; K < ns; ++K) {
+    const int64_t c = S.nrows(K);
+    if (c < t) continue;
+    const int64_t ldg = (c + kPanelAlign - 1) / kPanelAlign * kPanelAlign;
+    H.node_goff[K] = H.g_elems;
+    H.node_ldg[K] = (int32_t)ldg;
+    H.g_elems += ldg * c;
+  }
+}
+
+void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t dense_min_c, int64_t dense_max_bytes,
+                HostPlan &H) {
   const int64_t ns = S.nsuper();
   H.node_s.resize(ns);
   H.node_c.resize(ns);
@@ -209,8 +255,10 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan
       }
     }
   }
-  // work items
+  // work items: phase 0 (dense gather), phase 1 (GEMM-1 tiles), phase 2
+  choose_dense(S, batch, scalar_bytes, dense_min_c, dense_max_bytes, H);
   H.item_ptr.assign(ns + 1, 0);
+  H.n_phase0.assign(ns, 0);
   H.n_phase1.assign(ns, 0);
   H.n_phase2.assign(ns, 0);
   H.items.clear();
@@ -218,12 +266,17 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan
     const int32_t s = H.node_s[K], c = H.node_c[K];
     H.item_ptr[K] = (int32_t)H.items.size();
     const int32_t nb = (s + kTileN - 1) / kTileN;
+    const int32_t nr = (c + kTileM - 1) / kTileM;
+    if (H.node_goff[K] >= 0) {
+      for (int32_t a = 0; a < nr; ++a)
+        for (int32_t b = 0; b <= a; ++b) H.items.push_back(Item{(int32_t)K, ITEM_G, a, b});
+      H.n_phase0[K] = nr * (nr + 1) / 2;
+    }
     if (c <= kSmallC && s <= kSmallS) {
       H.items.push_back(Item{(int32_t)K, ITEM_S, 0, 0});
       H.n_phase2[K] = 1;
     } else {
       if (c > 0) {
-        const int32_t nr = (c + kTileM - 1) / kTileM;
         for (int32_t b = 0; b < nb; ++b)
           for (int32_t a = 0; a < nr; ++a) H.items.push_back(Item{(int32_t)K, ITEM_Y, a, b});
         H.n_phase1[K] = nr * nb;
@@ -237,19 +290,21 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan
   H.node_parent.resize(ns);
   for (int64_t K = 0; K < ns; ++K) H.node_parent[K] = (int32_t)S.sparent[K];
   ticket_order(S, H, batch);
-  // level lists (phase 1, then phase 2, per etree depth)
+  // level lists (phases 0, 1, 2 per etree depth)
   H.lvl_items.clear();
   H.lvl_ptr.assign(1, 0);
   {
     std::vector<std::vector<int64_t>> bydepth(S.depth);
     for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
     for (int64_t d = 0; d < S.depth; ++d) {
-      for (int64_t K : bydepth[d])
-        for (int32_t q = 0; q < H.n_phase1[K]; ++q) H.lvl_items.push_back(H.item_ptr[K] + q);
-      H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
-      for (int64_t K : bydepth[d])
-        for (int32_t q = 0; q < H.n_phase2[K]; ++q) H.lvl_items.push_back(H.item_ptr[K] + H.n_phase1[K] + q);
-      H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
+      for (int ph = 0; ph < 3; ++ph) {
+        for (int64_t K : bydepth[d]) {
+          const int32_t b = H.item_ptr[K] + (ph > 0 ? H.n_phase0[K] : 0) + (ph > 1 ? H.n_phase1[K] : 0);
+          const int32_t n = ph == 0 ? H.n_phase0[K] : ph == 1 ? H.n_phase1[K] : H.n_phase2[K];
+          for (int32_t q = 0; q < n; ++q) H.lvl_items.push_back(b + q);
+        }
+        if ((int32_t)H.lvl_items.size() > H.lvl_ptr.back()) H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
+      }
     }
   }
   // normalization work lists
@@ -286,8 +341,11 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan
   o.posarr = take(4 * (int64_t)S.posarr.size());
   o.items = take(16 * (int64_t)H.items.size());
   o.item_ptr = take(4 * (ns + 1));
+  o.n_phase0 = take(4 * ns);
   o.n_phase1 = take(4 * ns);
   o.n_phase2 = take(4 * ns);
+  o.node_goff = take(8 * ns);
+  o.node_ldg = take(4 * ns);
   o.node_parent = take(4 * ns);
   o.order = take(4 * (int64_t)H.order.size());
   o.lvl_items = take(4 * (int64_t)H.lvl_items.size());
@@ -300,6 +358,8 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, HostPlan
   o.linv = take(scalar_bytes * batch * H.sq_elems);
   o.dinv = take(scalar_bytes * batch * S.n);
   o.part = take(scalar_bytes * batch * H.part_elems);
+  o.gbuf = take(scalar_bytes * batch * H.g_elems);
+  o.cnt0 = take(4 * batch * ns);
   o.cnt1 = take(4 * batch * ns);
   o.cnt2 = take(4 * batch * ns);
   o.ctrl = take(4 * CTRL_WORDS);
@@ -377,8 +437,12 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.posarr = (int32_t *)(b + o.posarr);
   d.items = (Item *)(b + o.items);
   d.item_ptr = (int32_t *)(b + o.item_ptr);
+  d.n_phase0 = (int32_t *)(b + o.n_phase0);
   d.n_phase1 = (int32_t *)(b + o.n_phase1);
   d.n_phase2 = (int32_t *)(b + o.n_phase2);
+  d.node_goff = (int64_t *)(b + o.node_goff);
+  d.node_ldg = (int32_t *)(b + o.node_ldg);
+  d.g_elems = H.g_elems;
   d.node_parent = (int32_t *)(b + o.node_parent);
   d.order = (int32_t *)(b + o.order);
   d.lvl_items = (int32_t *)(b + o.lvl_items);
@@ -387,6 +451,8 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.linv = (void *)(b + o.linv);
   d.dinv = (void *)(b + o.dinv);
   d.part = (void *)(b + o.part);
+  d.gbuf = (void *)(b + o.gbuf);
+  d.cnt0 = (int32_t *)(b + o.cnt0);
   d.cnt1 = (int32_t *)(b + o.cnt1);
   d.cnt2 = (int32_t *)(b + o.cnt2);
   d.ctrl = (int32_t *)(b + o.ctrl);
@@ -429,8 +495,11 @@ void build_image(selinv_ctx *h) {
   put(img, o.posarr, h->S.posarr);
   put(img, o.items, H.items);
   put(img, o.item_ptr, H.item_ptr);
+  put(img, o.n_phase0, H.n_phase0);
   put(img, o.n_phase1, H.n_phase1);
   put(img, o.n_phase2, H.n_phase2);
+  put(img, o.node_goff, H.node_goff);
+  put(img, o.node_ldg, H.node_ldg);
   put(img, o.node_parent, H.node_parent);
   put(img, o.order, H.order);
   put(img, o.lvl_items, H.lvl_items);
@@ -467,8 +536,9 @@ void selinv_default_opts(selinv_opts *o) {
   o->sched = SELINV_SCHED_PERSISTENT;
   o->relax = 0.0;
   o->nthreads = 0;
-  o->tile_rows = 0;
+  o->dense_min_c = 0;
   o->watchdog_ms = 0;
+  o->dense_max_bytes = 0;
 }
 
 const char *selinv_version(void) { return "selinv-mi355x 0.1"; }
@@ -492,9 +562,11 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *ro
     return set_err(h, SELINV_EINVAL, "unknown schedule");
   try {
     analyze(h->S, n, colptr, rowind, perm, o.max_super, o.relax);
-    build_plan(h->S, o.batch, h->sbytes(), h->H);
+    const int64_t min_c = o.dense_min_c == 0 ? kDefaultDenseMinC : o.dense_min_c;
+    const int64_t max_b = o.dense_max_bytes > 0 ? o.dense_max_bytes : kDefaultDenseMaxBytes;
+    build_plan(h->S, o.batch, h->sbytes(), min_c, max_b, h->H);
     if ((int64_t)h->H.items.size() * (int64_t)o.batch >= (int64_t)INT32_MAX)
-      return set_err(h, SELINV_ENOMEM, "too many work items for int32 queue entries");
+      return set_err(h, SELINV_ENOMEM, "too many work items for int32 item ids");
     build_image(h);
   } catch (const Failure &f) {
     return set_err(h, f.status, f.msg, f.info0, f.info1);
@@ -737,13 +809,11 @@ selinv_status selinv_check_plan(const selinv_ctx *hc) {
   // order, each item's dependencies must already be done when its turn comes.
   if ((int64_t)H.order.size() != B * nit)
     return set_err(h, SELINV_EINVAL, "plan check: ticket order has the wrong length", (int64_t)H.order.size(), B * nit);
-  std::vector<int32_t> cnt1((size_t)(B * ns)), cnt2((size_t)(B * ns));
+  std::vector<int32_t> left((size_t)(B * ns * 3));
   std::vector<uint8_t> seen((size_t)(B * nit), 0);
   for (int64_t l = 0; l < B; ++l)
-    for (int64_t K = 0; K < ns; ++K) {
-      cnt1[l * ns + K] = H.n_phase1[K];
-      cnt2[l * ns + K] = H.n_phase2[K];
-    }
+    for (int64_t K = 0; K < ns; ++K)
+      for (int ph = 0; ph < 3; ++ph) left[(l * ns + K) * 3 + ph] = phase_count(H, K, ph);
   for (int64_t t = 0; t < B * nit; ++t) {
     const int64_t id = H.order[t];
     if (id < 0 || id >= B * nit) return set_err(h, SELINV_EINVAL, "plan check: ticket names no item", t, id);
@@ -752,21 +822,28 @@ selinv_status selinv_check_plan(const selinv_ctx *hc) {
     seen[id] = 1;
     const Item it = H.items[itn];
     const int64_t K = it.K;
-    if (it.type != ITEM_Y && H.n_phase1[K] > 0) {
-      if (cnt1[l * ns + K] != 0) return set_err(h, SELINV_EINVAL, "plan check: phase 2 before phase 1", K, l);
+    const int ph = item_phase(it);
+    const int32_t b = phase_begin(H, K, ph);
+    if (itn < b || itn >= b + phase_count(H, K, ph))
+      return set_err(h, SELINV_EINVAL, "plan check: item outside its phase range", K, itn);
+    if (ph == 1 && (H.node_goff[K] >= 0) != (H.n_phase0[K] > 0))
+      return set_err(h, SELINV_EINVAL, "plan check: dense buffer without gather items", K, l);
+    // the kernel's wait rule: the previous non-empty phase, else the parent
+    int pv = ph - 1;
+    while (pv >= 0 && phase_count(H, K, pv) == 0) --pv;
+    if (pv >= 0) {
+      if (left[(l * ns + K) * 3 + pv] != 0)
+        return set_err(h, SELINV_EINVAL, "plan check: phase started before the previous one finished", K, l);
     } else {
       const int64_t P = H.node_parent[K];
       if (P != S.sparent[K]) return set_err(h, SELINV_EINVAL, "plan check: wrong parent table", K, P);
-      if (P >= 0 && cnt2[l * ns + P] != 0)
+      if (P >= 0 && left[(l * ns + P) * 3 + 2] != 0)
         return set_err(h, SELINV_EINVAL, "plan check: node started before its parent finished", K, l);
     }
-    if (it.type == ITEM_Y) --cnt1[l * ns + K];
-    else --cnt2[l * ns + K];
+    --left[(l * ns + K) * 3 + ph];
   }
-  for (int64_t l = 0; l < B; ++l)
-    for (int64_t K = 0; K < ns; ++K)
-      if (cnt1[l * ns + K] != 0 || cnt2[l * ns + K] != 0)
-        return set_err(h, SELINV_EINVAL, "plan check: node never finished", K, l);
+  for (size_t q = 0; q < left.size(); ++q)
+    if (left[q] != 0) return set_err(h, SELINV_EINVAL, "plan check: node never finished", (int64_t)(q / 3) % ns, (int64_t)(q / 3) / ns);
   return SELINV_OK;
 }
 

@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/selinv.h"
+#include "selinv.h"
 
 namespace selinv {
 

@@ -37,7 +37,58 @@ template <typename T> struct Ctx {
   const T *Lp;  // normalized panels of this matrix
   T *Xp;        // selected inverse of this matrix
   T *Pp;        // GEMM-2 partial products of this matrix
+  T *Gp;        // dense X_{C,C} buffers of this matrix
 };
+
+// Block (a, b), a >= b, of X_{C,C} for a node with a dense buffer G (column
+// major, leading dimension ldg): element (i, k), i >= k, is the lower-part
+// entry X[kcol[k] + posarr[kpos[k] + i]] of the ancestor owning column k; it
+// is written to G(i, k) and G(k, i).  Lanes run along i (one column k per
+// wave and step) for the gather and the G(i, k) stores; the mirror stores go
+// through an LDS transpose so that they are contiguous too.
+template <typename T>
+__device__ void do_gtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
+  const DevPlan &pl = *cx.pl;
+  const int c = uniform(gp(pl.node_c)[K]);
+  const int64_t rp = gp(pl.node_rowptr)[K];
+  const int ldg = gp(pl.node_ldg)[K];
+  T *G = cx.Gp + gp(pl.node_goff)[K];
+  const int i0 = a * 64, k0 = b * 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int Q = 64 * 64 / NT, QH = Q / 2;
+  for (int h = 0; h < 2; ++h) {
+    int64_t pidx[QH], base[QH], msk[QH];
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      const int kl = w + 4 * (QH * h + q), i = i0 + lane, k = k0 + kl;
+      msk[q] = opaque_mask(i < c && k < c && i >= k);
+      const int64_t kq = (int64_t)(k < c ? k : 0);
+      base[q] = gp(pl.kcol)[rp + kq];
+      pidx[q] = (gp(pl.kpos)[rp + kq] + i) & msk[q];
+    }
+    int64_t addr[QH];
+#pragma unroll
+    for (int q = 0; q < QH; ++q) addr[q] = (base[q] + (int64_t)gp(pl.posarr)[pidx[q]]) & msk[q];
+    T v[QH];
+#pragma unroll
+    for (int q = 0; q < QH; ++q) v[q] = masked(Mem<false>::ld(cx.Xp + addr[q]), msk[q]);
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      const int kl = w + 4 * (QH * h + q), i = i0 + lane, k = k0 + kl;
+      lds_put<T>(smem, lane, kl, v[q]);  // tile[i][k] at smem[k * PITCH + i]
+      if (i < c && k < c && i >= k) Mem<false>::st(G + (int64_t)k * ldg + i, v[q]);
+    }
+  }
+  lds_barrier();
+  // mirror: G(k, i) = tile[i][k], lanes along k
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int kl = e & 63, il = e >> 6, i = i0 + il, k = k0 + kl;
+    if (i < c && k < c && i > k) Mem<false>::st(G + (int64_t)i * ldg + k, lds_get<T>(smem, il, kl));
+  }
+  lds_barrier();
+}
 
 // GEMM-1 tile, rows 64a.. and columns 64b.. of X_{C,K}:
 //   Y = -X_{C,C} Lhat_{C,K}                                  (Alg. 1 step 3)
@@ -48,19 +99,28 @@ template <typename T, bool COH>
 __device__ void do_ytile(const Ctx<T> &cx, int K, int a, int b, double *smem, int64_t *rt) {
   constexpr int P = Planes<T>::P;
   const DevPlan &pl = *cx.pl;
-  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
+  const int s = uniform(gp(pl.node_s)[K]), c = uniform(gp(pl.node_c)[K]), ld = s + c;
   const int64_t off = gp(pl.node_off)[K], rp = gp(pl.node_rowptr)[K];
+  const int64_t goff = gp(pl.node_goff)[K];
   const int i0 = a * 64, j0 = b * 64;
-  if (threadIdx.x < 64) {
-    const int ig = i0 + threadIdx.x;
-    rt[threadIdx.x] = gp(pl.kcol)[rp + (ig < c ? ig : 0)];
-    rt[64 + threadIdx.x] = gp(pl.kpos)[rp + (ig < c ? ig : 0)];
-  }
-  lds_barrier();
-  LoadGather<T, COH> la{cx.Xp, pl.kcol + rp, pl.kpos + rp, pl.posarr, rt, rt + 64, c, i0};
-  LoadPanelK<T, false> lb{cx.Lp, off, ld, s, 0, c, j0, s};
   Acc<T> acc;
-  gemm_tile<T>(c, la, lb, smem, acc);  // acc = X_{C,C} Lhat = -Y (tile)
+  if (uniform(goff >= 0 ? 1 : 0)) {  // X_{C,C} already gathered into the dense buffer
+    constexpr int TK = DenseTK<T>::TK;
+    const T *G = static_cast<const T *>(cx.Gp) + goff;
+    LoadDenseA<T, TK> la{G, gp(pl.node_ldg)[K], c, i0};
+    LoadDenseB<T, TK> lb{cx.Lp, off, ld, s, c, j0, s};
+    gemm_dense<T>(c, la, lb, smem, acc);  // acc = X_{C,C} Lhat = -Y (tile)
+  } else {
+    if (threadIdx.x < 64) {
+      const int ig = i0 + threadIdx.x;
+      rt[threadIdx.x] = gp(pl.kcol)[rp + (ig < c ? ig : 0)];
+      rt[64 + threadIdx.x] = gp(pl.kpos)[rp + (ig < c ? ig : 0)];
+    }
+    lds_barrier();
+    LoadGather<T, COH> la{cx.Xp, pl.kcol + rp, pl.kpos + rp, pl.posarr, rt, rt + 64, c, i0};
+    LoadPanelK<T, false> lb{cx.Lp, off, ld, s, 0, c, j0, s};
+    gemm_tile<T>(c, la, lb, smem, acc);  // acc = X_{C,C} Lhat = -Y (tile)
+  }
   acc_to_lds<T>(acc, smem);
   lds_barrier();
   for (int e = threadIdx.x; e < 64 * 64; e += NT) {
@@ -229,7 +289,9 @@ __device__ void do_dtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
 template <typename T, bool COH>
 __device__ void do_item(const Ctx<T> &cx, const Item &item, double *smem, int64_t *rt) {
   const Item it = uniform(item);
-  if (it.type == ITEM_Y) {
+  if (it.type == ITEM_G) {
+    do_gtile<T>(cx, it.K, it.a, it.b, smem);
+  } else if (it.type == ITEM_Y) {
     do_ytile<T, COH>(cx, it.K, it.a, it.b, smem, rt);
   } else if (it.type == ITEM_D) {
     do_dtile<T, COH>(cx, it.K, it.a, it.b, smem);
@@ -255,7 +317,8 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1) k_items_list(co
   const int64_t g = blockIdx.x;
   const int64_t l = g / count;
   const int32_t it = list[g - l * count];
-  Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, Pp + l * pl.part_elems};
+  Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, Pp + l * pl.part_elems,
+            static_cast<T *>(pl.gbuf) + l * pl.g_elems};
   do_item<T, false>(cx, gload(pl.items + it), smem, rt);
 }
 
@@ -280,6 +343,7 @@ __global__ void k_sched_init(const DevPlan *__restrict__ plp) {
   const int64_t nsb = pl.batch * pl.ns;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsb; i += stride) {
     const int64_t K = i % pl.ns;
+    gw(pl.cnt0)[i] = gp(pl.n_phase0)[K];
     gw(pl.cnt1)[i] = gp(pl.n_phase1)[K];
     gw(pl.cnt2)[i] = gp(pl.n_phase2)[K];
   }
@@ -287,16 +351,21 @@ __global__ void k_sched_init(const DevPlan *__restrict__ plp) {
 }
 
 // Wait (executed by one whole wave, with wave-uniform control flow) until
-// item `it` of matrix l may run: a phase-2 item of a node that has phase-1
-// items waits for that phase; any other item waits for its node's parent to
-// finish (a root's first items are ready at once).  Returns false when
-// another workgroup raised the error flag or when the watchdog, counted from
-// kernel start, expires (then it raises the flag).
+// item `it` of matrix l may run: an item waits for the previous non-empty
+// phase of its node; an item of the node's first phase waits for the node's
+// parent to finish (a root's first items are ready at once).  Returns false
+// when another workgroup raised the error flag or when the watchdog, counted
+// from kernel start, expires (then it raises the flag).
 __device__ bool wait_ready(const DevPlan &pl, int64_t l, const Item &it, int64_t t_begin, int64_t budget_ticks) {
-  const int32_t *ctr;
-  if (it.type != ITEM_Y && uniform(gp(pl.n_phase1)[it.K]) > 0) {
-    ctr = pl.cnt1 + l * pl.ns + it.K;
-  } else {
+  const int64_t nk = l * pl.ns + it.K;
+  const int32_t *ctr = nullptr;
+  if (it.type == ITEM_Y) {
+    if (uniform(gp(pl.n_phase0)[it.K]) > 0) ctr = pl.cnt0 + nk;
+  } else if (it.type == ITEM_D || it.type == ITEM_S) {
+    if (uniform(gp(pl.n_phase1)[it.K]) > 0) ctr = pl.cnt1 + nk;
+    else if (uniform(gp(pl.n_phase0)[it.K]) > 0) ctr = pl.cnt0 + nk;
+  }
+  if (ctr == nullptr) {
     const int32_t P = uniform(gp(pl.node_parent)[it.K]);
     if (P < 0) return true;
     ctr = pl.cnt2 + l * pl.ns + P;
@@ -320,7 +389,7 @@ __device__ bool wait_ready(const DevPlan &pl, int64_t l, const Item &it, int64_t
 // wait and the counter update are done by wave 0 as a whole; every branch
 // around a barrier is wave-uniform.
 template <typename T>
-__global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
+__global__ void __launch_bounds__(NT, 1)
     k_persistent(const DevPlan *__restrict__ plp, const T *Lp, T *Xp, T *Pp, int64_t budget_ticks) {
   const DevPlan &pl = *plp;
   __shared__ double smem[smem_doubles<T>()];
@@ -336,6 +405,7 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
       int32_t t = 0;
       if (lane0) t = add_relaxed(pl.ctrl + CTRL_TICKET, 1);
       t = uniform(t);
+      const int64_t t_draw = pl.trace ? wall_clock64() : 0;
       int32_t id = -1;
       if (t < total) {
         id = uniform(gp(pl.order)[t]);
@@ -345,7 +415,7 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
       if (lane0) {
         s_id = id;
         s_ticket = t;
-        s_tpop = pl.trace ? wall_clock64() : 0;
+        s_tpop = t_draw;
       }
     }
     __syncthreads();
@@ -355,7 +425,8 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
     const int64_t l = id / pl.nitems;
     const int32_t itn = (int32_t)(id - l * pl.nitems);
     const Item it = uniform(gload(pl.items + itn));
-    Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, Pp + l * pl.part_elems};
+    Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, Pp + l * pl.part_elems,
+            static_cast<T *>(pl.gbuf) + l * pl.g_elems};
     do_item<T, false>(cx, it, smem, rt);
     // Publishing protocol: write back this item's stores (agent-scope release)
     // before the counter update.  Readers use plain cached loads: every panel
@@ -373,7 +444,8 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
         tr[3] = t_start;
         tr[4] = wall_clock64();
       }
-      add_relaxed((it.type == ITEM_Y ? pl.cnt1 : pl.cnt2) + l * pl.ns + it.K, -1);
+      int32_t *cnt = it.type == ITEM_G ? pl.cnt0 : it.type == ITEM_Y ? pl.cnt1 : pl.cnt2;
+      add_relaxed(cnt + l * pl.ns + it.K, -1);
     }
   }
 }

@@ -2,16 +2,21 @@
 // work buffer, and the work-item vocabulary of the traversal.
 //
 // Work items (one workgroup each):
-//   ITEM_Y  (K, a, b): rows 64a.. of X_{C,K} and columns 64b.. -- the gather of
-//           X_{C,C} through the ancestor maps and GEMM-1 X_{C,K} = -X_{C,C} Lhat_{C,K}
-//           (Alg. 1 step 3).
+//   ITEM_G  (K, a, b), a >= b: block (a, b) of X_{C,C}, gathered from the
+//           ancestors' X panels through the ancestor maps and written with its
+//           mirror into the node's dense c x c buffer (nodes with a dense
+//           buffer only).
+//   ITEM_Y  (K, a, b): rows 64a.. of X_{C,K} and columns 64b.. -- GEMM-1
+//           X_{C,K} = -X_{C,C} Lhat_{C,K} (Alg. 1 step 3), reading X_{C,C}
+//           from the dense buffer or gathering it on the fly, fused with the
+//           row tile's share of GEMM-2.
 //   ITEM_D  (K, a, b), a >= b: blocks (a, b) and (b, a) of X_KK = Dt_K^{-1} -
 //           Lhat_{C,K}^T X_{C,K} (step 4), symmetrized (Section 2.3).
 //   ITEM_S  (K): a node with c <= 64 and s <= 64 done by one workgroup.
-// Phase 1 of a node = its ITEM_Y items, phase 2 = its ITEM_D / ITEM_S items.
-// A node's first phase becomes ready when its parent's phase 2 is done
-// (C(K) lies in the ancestors, Eq. (newset)); phase 2 becomes ready when its
-// phase 1 is done.
+// Phase 0 of a node = its ITEM_G items, phase 1 = its ITEM_Y items, phase 2 =
+// its ITEM_D / ITEM_S items.  A node's first non-empty phase becomes ready
+// when its parent's phase 2 is done (C(K) lies in the ancestors, Eq. (newset));
+// every later phase becomes ready when the phase before it is done.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,7 +25,7 @@
 
 namespace selinv {
 
-enum ItemType : int32_t { ITEM_Y = 0, ITEM_D = 1, ITEM_S = 2 };
+enum ItemType : int32_t { ITEM_Y = 0, ITEM_D = 1, ITEM_S = 2, ITEM_G = 3 };
 
 constexpr int kTileM = 64;   // GEMM-1 rows per item
 constexpr int kTileN = 64;   // columns per item (of s)
@@ -46,8 +51,12 @@ struct DevPlan {
   int32_t *posarr;
   Item *items;
   int32_t *item_ptr;   // [ns+1]
+  int32_t *n_phase0;   // [ns]
   int32_t *n_phase1;   // [ns]
   int32_t *n_phase2;   // [ns]
+  int64_t *node_goff;  // [ns] element offset of the dense X_{C,C} buffer (-1: gathered on the fly)
+  int32_t *node_ldg;   // [ns] its leading dimension (c rounded up to 16)
+  int64_t g_elems;     // dense buffers of one matrix, in scalars
   int32_t *node_parent; // [ns] supernodal etree parent (-1 at a root)
   int32_t *order;      // [batch * nitems] ticket -> l * nitems + item
   int32_t *lvl_items;  // item ids grouped by (level, phase)
@@ -57,7 +66,8 @@ struct DevPlan {
   void *linv;          // [batch][sq_elems] scalars
   void *dinv;          // [batch][n] scalars
   void *part;          // [batch][part_elems] GEMM-2 partial products
-  int32_t *cnt1, *cnt2;  // [batch][ns]
+  void *gbuf;          // [batch][g_elems] dense X_{C,C} buffers
+  int32_t *cnt0, *cnt1, *cnt2;  // [batch][ns] outstanding items of each phase
   int32_t *ctrl;       // CTRL_WORDS
   int64_t *trace;      // optional: per ticket {item id, workgroup, t_ticket, t_start, t_end, 0, 0, 0}
 };

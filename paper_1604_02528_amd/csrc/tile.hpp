@@ -45,6 +45,7 @@ __device__ __forceinline__ d4 mfma16(double a, double b, d4 c) {
 
 constexpr int NT = 256;    // threads per workgroup (4 waves)
 
+
 // Workgroup barrier that orders LDS only.  __syncthreads() also waits for
 // every outstanding global load (vmcnt(0)), which would drain the operand
 // prefetch pipeline at each stage; global-memory ordering inside a workgroup
@@ -155,9 +156,9 @@ template <typename T> __device__ __forceinline__ void acc_zero(Acc<T> &acc) {
       for (int bj = 0; bj < 2; ++bj) acc.v[p][bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
 }
 
-template <typename T>
+template <typename T, int TK = Planes<T>::TK>
 __device__ __forceinline__ void stage_compute(const double *stg, Acc<T> &acc) {
-  constexpr int P = Planes<T>::P, TK = Planes<T>::TK;
+  constexpr int P = Planes<T>::P;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wi = w & 1, wj = w >> 1;
 #pragma unroll
@@ -195,14 +196,20 @@ template <typename T> struct Vals {
   T v[64 * Planes<T>::TK / NT];
 };
 
-template <typename T, class L>
-__device__ __forceinline__ void stage_store(double *stg, int plane_off, int k0, const L &ld, const Vals<T> &v) {
-  constexpr int P = Planes<T>::P, TK = Planes<T>::TK;
+// Loaders return raw loaded values; out-of-range elements (which were read
+// from a clamped, valid address) are zeroed here, where the values are
+// consumed.  Masking at the load would make the compiler wait for every load
+// in the iteration that issued it, which serializes the pipeline.
+template <typename T, class L, class V, int TK = Planes<T>::TK>
+__device__ __forceinline__ void stage_store(double *stg, int plane_off, int k0, const L &ld, const V &v) {
+  constexpr int P = Planes<T>::P;
+  constexpr int E = sizeof(v.v) / sizeof(v.v[0]);
 #pragma unroll
-  for (int m = 0; m < ept<T>(); ++m) {
+  for (int m = 0; m < E; ++m) {
     const int slot = ld.slot(k0, m);
+    const T x = masked(v.v[m], ld.mask(k0, m));
 #pragma unroll
-    for (int p = 0; p < P; ++p) stg[(plane_off + p) * TK * PITCH + slot] = Planes<T>::get(v.v[m], p);
+    for (int p = 0; p < P; ++p) stg[(plane_off + p) * TK * PITCH + slot] = Planes<T>::get(x, p);
   }
 }
 
@@ -260,6 +267,7 @@ __device__ __forceinline__ void gemm_tile(int kc, const LA &la, const LB &lb, do
     lb.lev2(kp, b1, b2);
     la.lev1(ki, a1);
     lb.lev1(ki, b1);
+    __builtin_amdgcn_sched_barrier(0);  // issue the loads before the next MFMA block
   }
 }
 
@@ -321,19 +329,21 @@ template <typename T, bool COH> struct LoadPanelK {
   }
   __device__ __forceinline__ void lev1(int, S1 &) const {}
   __device__ __forceinline__ void lev2(int, const S1 &, S2 &) const {}
-  // Branch-free: out-of-range elements read the panel's first element and are
-  // masked to zero, so all loads of a stage issue together.
+  __device__ __forceinline__ int64_t mask(int k0, int m) const {
+    constexpr int TK = Planes<T>::TK;
+    const int e = threadIdx.x + NT * m;
+    return opaque_mask(kbase + k0 + (e & (TK - 1)) < kend && x0 + e / TK < xmax);
+  }
+  // Branch-free: out-of-range elements read the panel's first element (zeroed
+  // when stored), so all loads of a stage issue together.
   __device__ __forceinline__ void lev3(int k0, const S2 &, Vals<T> &v) const {
     constexpr int TK = Planes<T>::TK;
 #pragma unroll
     for (int m = 0; m < ept<T>(); ++m) {
       const int e = threadIdx.x + NT * m;
-      const int kk = e & (TK - 1), x = e / TK;
-      const int kg = kbase + k0 + kk, xg = x0 + x;
-      const bool ok = kg < kend && xg < xmax;
-      const int64_t msk = opaque_mask(ok);
-      const int64_t a = (((int64_t)xg * ld + s + kg) & msk) + off;
-      v.v[m] = masked(Mem<COH>::ld(Pn + a), msk);
+      const int kg = kbase + k0 + (e & (TK - 1)), xg = x0 + e / TK;
+      const int64_t msk = mask(k0, m);
+      v.v[m] = Mem<COH>::ld(Pn + ((((int64_t)xg * ld + s + kg) & msk) + off));
     }
   }
 };
@@ -346,14 +356,13 @@ template <typename T, bool COH> struct LoadPanelK {
 // contiguously.
 template <typename T, bool COH> struct LoadGather {
   static constexpr int E = 64 * Planes<T>::TK / NT;
-  struct S1 {
-    int64_t base[E];
-    int64_t pidx[E];
-    int64_t msk[E];
+  struct S1 {  // raw kcol / kpos entries of the stage's lower-part columns
+    int64_t bl[E];
+    int64_t plo[E];
   };
-  struct S2 {
-    int64_t addr[E];
-    int64_t msk[E];
+  struct S2 {  // panel column base and raw posarr entry
+    int64_t base[E];
+    int32_t pos[E];
   };
   const T *X;
   const int64_t *kcol, *kpos;  // node-local per-row tables (global)
@@ -376,8 +385,25 @@ template <typename T, bool COH> struct LoadGather {
     coords(k0, m, i, kk);
     return kk * PITCH + i;
   }
-  // All three levels load unconditionally (clamped indices, opaque masks).
+  __device__ __forceinline__ int64_t mask(int k0, int m) const {
+    int i, kk;
+    coords(k0, m, i, kk);
+    return opaque_mask(i0 + i < c && k0 + kk < c);
+  }
+  // Each level loads unconditionally (clamped indices, opaque masks) and
+  // keeps the raw results; they are combined one level later.
   __device__ __forceinline__ void lev1(int k0, S1 &r) const {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      int i, kk;
+      coords(k0, m, i, kk);
+      const int ig = i0 + i, kg = k0 + kk;
+      const int64_t kq = (int64_t)kg & opaque_mask(ig < c && kg < c && ig >= kg);
+      r.bl[m] = gp(kcol)[kq];
+      r.plo[m] = gp(kpos)[kq];
+    }
+  }
+  __device__ __forceinline__ void lev2(int k0, const S1 &r, S2 &q) const {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       int i, kk;
@@ -385,26 +411,127 @@ template <typename T, bool COH> struct LoadGather {
       const int ig = i0 + i, kg = k0 + kk;
       const int64_t okm = opaque_mask(ig < c && kg < c);
       const int64_t lm = opaque_mask(ig >= kg);
-      const int64_t kq = (int64_t)kg & okm & lm;
-      const int64_t bl = gp(kcol)[kq], plo = gp(kpos)[kq];
       const int64_t bu = rt_col[i], pu = rt_pos[i];
-      r.base[m] = (bl & lm) | (bu & ~lm);
-      r.pidx[m] = (((plo + ig) & lm) | ((pu + kg) & ~lm)) & okm;
-      r.msk[m] = okm;
+      q.base[m] = (r.bl[m] & lm) | (bu & ~lm);
+      const int64_t pidx = (((r.plo[m] + ig) & lm) | ((pu + kg) & ~lm)) & okm;
+      q.pos[m] = gp(posarr)[pidx];
     }
   }
-  __device__ __forceinline__ void lev2(int, const S1 &r, S2 &q) const {
+  __device__ __forceinline__ void lev3(int k0, const S2 &q, Vals<T> &v) const {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int64_t pos = (int64_t)gp(posarr)[r.pidx[m]];
-      q.addr[m] = (r.base[m] + pos) & r.msk[m];
-      q.msk[m] = r.msk[m];
+      v.v[m] = Mem<COH>::ld(X + ((q.base[m] + (int64_t)q.pos[m]) & mask(k0, m)));
     }
   }
-  __device__ __forceinline__ void lev3(int, const S2 &q, Vals<T> &v) const {
+};
+
+// ---------------------------------------------------------------------------
+// Dense operands (no index chain): the node's X_{C,C} buffer and the panel.
+// ---------------------------------------------------------------------------
+template <typename T> struct DenseTK;
+template <> struct DenseTK<double> { static constexpr int TK = 32; };
+template <> struct DenseTK<cplx> { static constexpr int TK = 16; };
+
+template <typename T, int TK> struct DVals {
+  T v[64 * TK / NT];
+};
+
+// A(i, kk) = G[(k0 + kk) * ldg + i0 + i] (column-major c x c, i, k < c);
+// lanes run along i, so each column of the stage is one contiguous read.
+template <typename T, int TK> struct LoadDenseA {
+  const T *G;
+  int ldg, c, i0;
+  __device__ __forceinline__ int slot(int, int m) const {
+    const int e = threadIdx.x + NT * m;
+    return (e >> 6) * PITCH + (e & 63);
+  }
+  __device__ __forceinline__ int64_t mask(int k0, int m) const {
+    const int e = threadIdx.x + NT * m;
+    return opaque_mask(i0 + (e & 63) < c && k0 + (e >> 6) < c);
+  }
+  __device__ __forceinline__ void load(int k0, DVals<T, TK> &v) const {
 #pragma unroll
-    for (int m = 0; m < E; ++m) v.v[m] = masked(Mem<COH>::ld(X + q.addr[m]), q.msk[m]);
+    for (int m = 0; m < 64 * TK / NT; ++m) {
+      const int e = threadIdx.x + NT * m;
+      const int i = i0 + (e & 63), k = k0 + (e >> 6);
+      v.v[m] = Mem<false>::ld(G + (((int64_t)k * ldg + i) & mask(k0, m)));
+    }
   }
 };
+
+// B(kk, x) = P[off + (x0 + x) * ld + s + k0 + kk] for k0 + kk < kend,
+// x0 + x < xmax: a column block of a panel's bottom part, k-major.
+template <typename T, int TK> struct LoadDenseB {
+  const T *Pn;
+  int64_t off;
+  int ld, s, kend, x0, xmax;
+  __device__ __forceinline__ int slot(int, int m) const {
+    const int e = threadIdx.x + NT * m;
+    return (e & (TK - 1)) * PITCH + e / TK;
+  }
+  __device__ __forceinline__ int64_t mask(int k0, int m) const {
+    const int e = threadIdx.x + NT * m;
+    return opaque_mask(k0 + (e & (TK - 1)) < kend && x0 + e / TK < xmax);
+  }
+  __device__ __forceinline__ void load(int k0, DVals<T, TK> &v) const {
+#pragma unroll
+    for (int m = 0; m < 64 * TK / NT; ++m) {
+      const int e = threadIdx.x + NT * m;
+      const int kg = k0 + (e & (TK - 1)), xg = x0 + e / TK;
+      v.v[m] = Mem<false>::ld(Pn + ((((int64_t)xg * ld + s + kg) & mask(k0, m)) + off));
+    }
+  }
+};
+
+template <typename T, int TK> __device__ __forceinline__ constexpr int dense_stage_doubles() {
+  return 2 * Planes<T>::P * TK * PITCH;
+}
+
+// acc = A (64 x kc) * B (kc x 64) from dense operands.  Two register sets
+// alternate, so the loads of a stage are issued two stage-computations before
+// they are stored to LDS; waits are counted waits on the older set only.
+// kc must be wave-uniform.
+template <typename T, class LA, class LB>
+__device__ __forceinline__ void gemm_dense(int kc, const LA &la, const LB &lb, double *smem, Acc<T> &acc) {
+  constexpr int TK = DenseTK<T>::TK, P = Planes<T>::P;
+  constexpr int SD = dense_stage_doubles<T, TK>();
+  using V = DVals<T, TK>;
+  acc_zero<T>(acc);
+  const int nk = (kc + TK - 1) / TK;
+  if (nk == 0) return;
+  const int klast = (nk - 1) * TK;
+  V a0, b0, a1, b1;
+  la.load(0, a0);
+  lb.load(0, b0);
+  la.load(min(TK, klast), a1);
+  lb.load(min(TK, klast), b1);
+  stage_store<T, LA, V, TK>(smem, 0, 0, la, a0);
+  stage_store<T, LB, V, TK>(smem, P, 0, lb, b0);
+  la.load(min(2 * TK, klast), a0);
+  lb.load(min(2 * TK, klast), b0);
+  lds_barrier();
+  for (int kt = 0;; kt += 2) {
+    // LDS stage 0 holds kt; set 1 holds kt + 1, set 0 holds kt + 2
+    stage_compute<T, TK>(smem, acc);
+    if (kt + 1 >= nk) break;
+    const int k1 = min((kt + 1) * TK, klast);
+    stage_store<T, LA, V, TK>(smem + SD, 0, k1, la, a1);
+    stage_store<T, LB, V, TK>(smem + SD, P, k1, lb, b1);
+    lds_barrier();
+    la.load(min((kt + 3) * TK, klast), a1);
+    lb.load(min((kt + 3) * TK, klast), b1);
+    __builtin_amdgcn_sched_barrier(0);  // issue the loads before the MFMA block
+    stage_compute<T, TK>(smem + SD, acc);
+    if (kt + 2 >= nk) break;
+    const int k2 = min((kt + 2) * TK, klast);
+    stage_store<T, LA, V, TK>(smem, 0, k2, la, a0);
+    stage_store<T, LB, V, TK>(smem, P, k2, lb, b0);
+    lds_barrier();
+    la.load(min((kt + 4) * TK, klast), a0);
+    lb.load(min((kt + 4) * TK, klast), b0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  lds_barrier();  // the caller reuses the stage buffers
+}
 
 }  // namespace selinv

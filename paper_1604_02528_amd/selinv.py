@@ -27,7 +27,7 @@ def _bytes(nbytes, device):
 
 class SelInv:
     def __init__(self, n, colptr, rowind, perm=None, *, dtype="f64", batch=1, cap=256, relax=0.0,
-                 sched="persistent", nthreads=0, watchdog_ms=0, device="cuda"):
+                 sched="persistent", nthreads=0, watchdog_ms=0, dense_min_c=0, dense_max_bytes=0, device="cuda"):
         self.n = int(n)
         self.is_complex = dtype in ("c128", "complex128", torch.complex128)
         self.batch = int(batch)
@@ -40,6 +40,8 @@ class SelInv:
         o.relax = float(relax)
         o.nthreads = int(nthreads)
         o.watchdog_ms = int(watchdog_ms)
+        o.dense_min_c = int(dense_min_c)
+        o.dense_max_bytes = int(dense_max_bytes)
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         self._rowind = np.ascontiguousarray(rowind, dtype=np.int64)
         self._perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
@@ -133,8 +135,9 @@ class SelInv:
         capi.selinv_run(self.h, self._bufs["panels"], self._bufs["x"], self._bufs["work"], _stream())
 
     def trace_run(self):
-        """Run once with per-item tracing; returns int64 [n_items, 8] rows
-        {item, workgroup, t_pop, t_start, t_end, 0, 0, 0} (wall-clock ticks)."""
+        """Run once with per-item tracing; returns int64 [n_tickets, 8] rows
+        {item, workgroup, t_ticket, t_start, t_end, 0, 0, 0} in wall-clock
+        ticks: ticket drawn, dependencies met and item started, item done."""
         tr = torch.zeros(self.sizes.trace_bytes // 8, dtype=torch.int64, device=self.device)
         capi.selinv_trace(self.h, tr)
         self.run()

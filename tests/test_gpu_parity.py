@@ -14,20 +14,25 @@ CASES = [
     ("C2", 12, None, 0.05),
     ("C2", 20, None, 0.05),
     ("C3", 8, 2, 0.05),
+    ("C3", 14, 2, 0.05),
     ("C5", 6, 2, 0.05),
 ]
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("dense", [0, 65, -1], ids=["dense_default", "dense_all", "gather_only"])
 @pytest.mark.parametrize("sched", ["levels", "persistent"])
 @pytest.mark.parametrize("name,scale,batch,relax", CASES)
-def test_selinv_matches_oracle(name, scale, batch, relax, sched):
+def test_selinv_matches_oracle(name, scale, batch, relax, sched, dense):
+    """dense: threshold on |C(K)| for the dense X_{C,C} buffer (0 = library
+    default, 65 = every node with more than one row tile, -1 = never), so both
+    the gathered and the dense GEMM-1 operand paths are compared."""
     from paper_1604_02528_amd import SelInv
 
     w = workload(name, scale, batch)
-    print(f"case {name} scale={scale} batch={batch} relax={relax} sched={sched}", flush=True)
+    print(f"case {name} scale={scale} batch={batch} relax={relax} sched={sched} dense={dense}", flush=True)
     S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128" if w.is_complex else "f64", batch=w.batch,
-               cap=w.cap, relax=relax, sched=sched, watchdog_ms=20000)
+               cap=w.cap, relax=relax, sched=sched, watchdog_ms=20000, dense_min_c=dense)
     S.factor(w.values)
     S.run()
     S.sync()
