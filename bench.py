@@ -111,7 +111,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--relax", type=float, default=0.05)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
-    ap.add_argument("--sched", default="persistent", choices=["persistent", "levels"])
+    ap.add_argument("--sched", default="levels", choices=["persistent", "levels"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run its own "
@@ -168,7 +168,11 @@ def main():
         "s_per_solve": ms_step * 1e-3 / w.batch,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 5), "traffic": None,
-                     "kernel": "k_persistent<double> (selinv_run)", "avg_launch_ms": t_run * 1e3},
+                     "kernel": ("k_items_list<double>, one launch per etree level and phase"
+                                if args.sched == "levels" else "k_persistent<double>, one launch"),
+                     "selinv_run_ms": t_run * 1e3,
+                     "note": "achieved = algorithmic flops of the traversal / HIP-event time of selinv_run "
+                             "(all of its launches) on the launch stream"},
         "normalize_ms": t_norm * 1e3,
         "max_rel_err_vs_oracle": err,
         "t_analyze_s": g["t_analyze"],

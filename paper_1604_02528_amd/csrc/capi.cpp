@@ -47,7 +47,7 @@ struct HostPlan {
   int64_t dense_min_c = 0;  // threshold in use (INT64_MAX: no dense buffers)
   std::vector<int32_t> order;  // ticket order of the persistent schedule (all matrices)
   std::vector<int32_t> lvl_items, lvl_ptr;
-  std::vector<int2> chunks;
+  std::vector<int2> chunks, rblocks;
   std::vector<int4> sq_tiles;
   std::vector<int64_t> apos;
   std::vector<uint8_t> adiag;
@@ -56,7 +56,7 @@ struct HostPlan {
   // byte offsets inside the work buffer
   struct Off {
     int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
-        n_phase0, n_phase1, n_phase2, node_goff, node_ldg, node_parent, order, lvl_items, chunks,
+        n_phase0, n_phase1, n_phase2, node_goff, node_ldg, node_parent, order, lvl_items, chunks, rblocks,
         sq_tiles,
         apos, adiag, plan, linv, dinv, part, gbuf, cnt0, cnt1, cnt2, ctrl, end;
   } off{};
@@ -309,11 +309,13 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   }
   // normalization work lists
   H.chunks.clear();
+  H.rblocks.clear();
   H.sq_tiles.clear();
   for (int64_t K = 0; K < ns; ++K) {
     const int32_t s = H.node_s[K], c = H.node_c[K];
-    const int32_t nch = (s + c + 255) / 256;
+    const int32_t nch = (s + 255) / 256;
     for (int32_t q = 0; q < nch; ++q) H.chunks.push_back(int2{(int32_t)K, q});
+    for (int32_t a = 0; a < (c + kTileM - 1) / kTileM; ++a) H.rblocks.push_back(int2{(int32_t)K, a});
     const int32_t nt = (s + 31) / 32;
     for (int32_t a = 0; a < nt; ++a)
       for (int32_t b = 0; b < nt; ++b) H.sq_tiles.push_back(int4{(int32_t)K, a, b, 0});
@@ -350,6 +352,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.order = take(4 * (int64_t)H.order.size());
   o.lvl_items = take(4 * (int64_t)H.lvl_items.size());
   o.chunks = take(8 * (int64_t)H.chunks.size());
+  o.rblocks = take(8 * (int64_t)H.rblocks.size());
   o.sq_tiles = take(16 * (int64_t)H.sq_tiles.size());
   o.apos = take(8 * (int64_t)H.apos.size());
   o.adiag = take((int64_t)H.adiag.size());
@@ -470,6 +473,8 @@ LaunchAux make_aux(const selinv_ctx *h, void *work) {
   LaunchAux a{};
   a.chunks = (const int2 *)(b + H.off.chunks);
   a.nchunks = (int32_t)H.chunks.size();
+  a.rblocks = (const int2 *)(b + H.off.rblocks);
+  a.nrblocks = (int32_t)H.rblocks.size();
   a.sq_tiles = (const int4 *)(b + H.off.sq_tiles);
   a.nsq_tiles = (int32_t)H.sq_tiles.size();
   a.lvl_items = (const int32_t *)(b + H.off.lvl_items);
@@ -504,6 +509,7 @@ void build_image(selinv_ctx *h) {
   put(img, o.order, H.order);
   put(img, o.lvl_items, H.lvl_items);
   put(img, o.chunks, H.chunks);
+  put(img, o.rblocks, H.rblocks);
   put(img, o.sq_tiles, H.sq_tiles);
   put(img, o.apos, H.apos);
   put(img, o.adiag, H.adiag);

@@ -107,9 +107,9 @@ __device__ void do_ytile(const Ctx<T> &cx, int K, int a, int b, double *smem, in
   if (uniform(goff >= 0 ? 1 : 0)) {  // X_{C,C} already gathered into the dense buffer
     constexpr int TK = DenseTK<T>::TK;
     const T *G = static_cast<const T *>(cx.Gp) + goff;
-    LoadDenseA<T, TK> la{G, gp(pl.node_ldg)[K], c, i0};
+    LoadDenseA<T, TK> la{G, gp(pl.node_ldg)[K], c, c, i0};
     LoadDenseB<T, TK> lb{cx.Lp, off, ld, s, c, j0, s};
-    gemm_dense<T>(c, la, lb, smem, acc);  // acc = X_{C,C} Lhat = -Y (tile)
+    gemm_dense<T>(0, c, la, lb, smem, acc);  // acc = X_{C,C} Lhat = -Y (tile)
   } else {
     if (threadIdx.x < 64) {
       const int ig = i0 + threadIdx.x;
@@ -454,10 +454,9 @@ __global__ void __launch_bounds__(NT, 1)
 // Normalization (Alg. 1 steps 1-2)
 // ---------------------------------------------------------------------------
 
-// One thread per row r of [I_s; L_{C,K}] solving x L_KK = rhs (L_KK unit lower):
-// rows r < s give row r of L_KK^{-1} (scratch, column-major ld s); rows r >= s
-// give Lhat in place (panel row r).  Back substitution in 16-column chunks,
-// L_KK chunks staged in LDS.
+// One thread per row r < s of I_s solving x L_KK = e_r (L_KK unit lower): row r
+// of L_KK^{-1} (scratch, column-major ld s), and D_K^{-1}.  Back substitution
+// in 16-column chunks, L_KK chunks staged in LDS.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_normalize_rows(const DevPlan *__restrict__ plp, const T *Src_all, T *Lp_all, const int2 *chunks,
                                                        int32_t nchunks) {
@@ -474,7 +473,7 @@ __global__ void __launch_bounds__(NT) k_normalize_rows(const DevPlan *__restrict
   T *Linv = reinterpret_cast<T *>(pl.linv) + l * pl.sq_elems + gp(pl.node_sq)[K];
   T *dinv = reinterpret_cast<T *>(pl.dinv) + l * pl.n + gp(pl.node_first)[K];
   const int r = ck.y * NT + threadIdx.x;
-  const bool active = r < s + c;
+  const bool active = r < s;
   if (ck.y == 0 && threadIdx.x < s) gstore(dinv + threadIdx.x, SOps<T>::div(SOps<T>::one(), Q[(int64_t)threadIdx.x * ld + threadIdx.x]));
   for (int jb = ((s - 1) / 16) * 16; jb >= 0; jb -= 16) {
     const int w = (s - jb < 16) ? s - jb : 16;
@@ -491,24 +490,27 @@ __global__ void __launch_bounds__(NT) k_normalize_rows(const DevPlan *__restrict
     if (active) {
       T x[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        T v = zero_of<T>();
-        if (q < w) {
-          if (r < s)
-            v = (r == jb + q) ? SOps<T>::one() : zero_of<T>();
-          else
-            v = Q[(int64_t)(jb + q) * ld + r];
-        }
-        x[q] = v;
-      }
-      for (int i = jb + w; i < s; ++i) {
-        const T xi = (r < s) ? gload(Linv + (int64_t)i * s + r) : P[(int64_t)i * ld + r];
+      for (int q = 0; q < 16; ++q) x[q] = (q < w && r == jb + q) ? SOps<T>::one() : zero_of<T>();
+      // x_i for i beyond the chunk: this thread's own earlier results, read
+      // 16 at a time so the loads overlap (indices past s are clamped and
+      // their values zeroed)
+      for (int ib = jb + w; ib < s; ib += 16) {
+        T xi[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          T lv;
-          if constexpr (Planes<T>::P == 1) lv = ls[0][q * 257 + (i - jb)];
-          else lv = T{ls[0][q * 257 + (i - jb)], ls[1][q * 257 + (i - jb)]};
-          x[q] -= xi * lv;
+        for (int u = 0; u < 16; ++u) {
+          const int i = min(ib + u, s - 1);
+          xi[u] = masked(gload(Linv + (int64_t)i * s + r), opaque_mask(ib + u < s));
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int ii = min(ib + u, s - 1) - jb;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            T lv;
+            if constexpr (Planes<T>::P == 1) lv = ls[0][q * 257 + ii];
+            else lv = T{ls[0][q * 257 + ii], ls[1][q * 257 + ii]};
+            x[q] -= xi[u] * lv;
+          }
         }
       }
 #pragma unroll
@@ -526,15 +528,44 @@ __global__ void __launch_bounds__(NT) k_normalize_rows(const DevPlan *__restrict
         }
       }
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        if (q < w) {
-          if (r < s)
-            gstore(Linv + (int64_t)(jb + q) * s + r, x[q]);
-          else
-            P[(int64_t)(jb + q) * ld + r] = x[q];
-        }
-      }
+      for (int q = 0; q < 16; ++q)
+        if (q < w) gstore(Linv + (int64_t)(jb + q) * s + r, x[q]);
     }
+  }
+}
+
+// Lhat_{C,K} = L_{C,K} L_KK^{-1} (Alg. 1 steps 1-2) for one 64-row block a of
+// C(K), column tiles left to right on MFMA.  Column x of Lhat needs only
+// columns k >= x of L (L_KK^{-1} is lower triangular), so a workgroup that
+// owns its row block and writes tile b after finishing it never reads a
+// column it has already overwritten: Q may alias P.
+template <typename T>
+__global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
+    k_normalize_gemm(const DevPlan *__restrict__ plp, const T *Src_all, T *Lp_all, const int2 *rblocks, int32_t nrb) {
+  const DevPlan &pl = *plp;
+  __shared__ double smem[smem_doubles<T>()];
+  constexpr int TK = DenseTK<T>::TK;
+  const int64_t g = blockIdx.x;
+  const int64_t l = g / nrb;
+  const int2 rb = rblocks[g - l * nrb];
+  const int K = uniform(rb.x), i0 = uniform(rb.y) * 64;
+  const int s = uniform(gp(pl.node_s)[K]), c = uniform(gp(pl.node_c)[K]), ld = s + c;
+  const int64_t off = gp(pl.node_off)[K];
+  const T *Q = Src_all + l * pl.panel_elems + off;
+  T *P = Lp_all + l * pl.panel_elems + off;
+  const T *Linv = reinterpret_cast<const T *>(pl.linv) + l * pl.sq_elems + gp(pl.node_sq)[K];
+  for (int x0 = 0; x0 < s; x0 += 64) {
+    LoadDenseA<T, TK> la{Q + s, ld, c, s, i0};      // L_{C,K}(i, k)
+    LoadDenseB<T, TK> lb{Linv, 0, s, 0, s, x0, s};  // L_KK^{-1}(k, x)
+    Acc<T> acc;
+    gemm_dense<T>(x0, s, la, lb, smem, acc);
+    acc_to_lds<T>(acc, smem);
+    lds_barrier();
+    for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+      const int i = e & 63, x = e >> 6;
+      if (i0 + i < c && x0 + x < s) P[(int64_t)(x0 + x) * ld + s + i0 + i] = lds_get<T>(smem, i, x);
+    }
+    lds_barrier();
   }
 }
 
@@ -651,6 +682,10 @@ static hipError_t normalize_impl(const DevPlan &pl, const DevPlan *dpl, const La
   if (aux.nchunks > 0) {
     hipLaunchKernelGGL(k_normalize_rows<T>, dim3((unsigned)(aux.nchunks * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
                        aux.chunks, aux.nchunks);
+  }
+  if (aux.nrblocks > 0) {
+    hipLaunchKernelGGL(k_normalize_gemm<T>, dim3((unsigned)(aux.nrblocks * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
+                       aux.rblocks, aux.nrblocks);
   }
   if (aux.nsq_tiles > 0) {
     if (dt)

@@ -74,8 +74,10 @@ struct DevPlan {
 
 // Host-side launch lists (device pointers into the work buffer, except lvl_ptr).
 struct LaunchAux {
-  const int2 *chunks;       // normalization row chunks (K, chunk)
+  const int2 *chunks;       // normalization row chunks (K, chunk) of the s x s blocks
   int32_t nchunks;
+  const int2 *rblocks;      // normalization GEMM row blocks (K, 64-row block of C(K))
+  int32_t nrblocks;
   const int4 *sq_tiles;     // normalization 32 x 32 tiles (K, ti, tj, 0)
   int32_t nsq_tiles;
   const int32_t *lvl_items; // item ids grouped by (level, phase)

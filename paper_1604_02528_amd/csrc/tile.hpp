@@ -436,18 +436,18 @@ template <typename T, int TK> struct DVals {
   T v[64 * TK / NT];
 };
 
-// A(i, kk) = G[(k0 + kk) * ldg + i0 + i] (column-major c x c, i, k < c);
+// A(i, k) = G[k * ldg + i0 + i] for i0 + i < rows, k < kend (column-major);
 // lanes run along i, so each column of the stage is one contiguous read.
 template <typename T, int TK> struct LoadDenseA {
   const T *G;
-  int ldg, c, i0;
+  int ldg, rows, kend, i0;
   __device__ __forceinline__ int slot(int, int m) const {
     const int e = threadIdx.x + NT * m;
     return (e >> 6) * PITCH + (e & 63);
   }
   __device__ __forceinline__ int64_t mask(int k0, int m) const {
     const int e = threadIdx.x + NT * m;
-    return opaque_mask(i0 + (e & 63) < c && k0 + (e >> 6) < c);
+    return opaque_mask(i0 + (e & 63) < rows && k0 + (e >> 6) < kend);
   }
   __device__ __forceinline__ void load(int k0, DVals<T, TK> &v) const {
 #pragma unroll
@@ -487,48 +487,47 @@ template <typename T, int TK> __device__ __forceinline__ constexpr int dense_sta
   return 2 * Planes<T>::P * TK * PITCH;
 }
 
-// acc = A (64 x kc) * B (kc x 64) from dense operands.  Two register sets
-// alternate, so the loads of a stage are issued two stage-computations before
-// they are stored to LDS; waits are counted waits on the older set only.
-// kc must be wave-uniform.
+// acc = A (64 x [kb, ke)) * B ([kb, ke) x 64) from dense operands.  Two
+// register sets alternate, so the loads of a stage are issued two
+// stage-computations before they are stored to LDS; waits are counted waits
+// on the older set only.  kb and ke must be wave-uniform.
 template <typename T, class LA, class LB>
-__device__ __forceinline__ void gemm_dense(int kc, const LA &la, const LB &lb, double *smem, Acc<T> &acc) {
+__device__ __forceinline__ void gemm_dense(int kb, int ke, const LA &la, const LB &lb, double *smem, Acc<T> &acc) {
   constexpr int TK = DenseTK<T>::TK, P = Planes<T>::P;
   constexpr int SD = dense_stage_doubles<T, TK>();
   using V = DVals<T, TK>;
   acc_zero<T>(acc);
-  const int nk = (kc + TK - 1) / TK;
-  if (nk == 0) return;
-  const int klast = (nk - 1) * TK;
+  const int nk = (ke - kb + TK - 1) / TK;
+  if (nk <= 0) return;
+  const int klast = kb + (nk - 1) * TK;
+  auto kat = [&](int j) { return min(kb + j * TK, klast); };
   V a0, b0, a1, b1;
-  la.load(0, a0);
-  lb.load(0, b0);
-  la.load(min(TK, klast), a1);
-  lb.load(min(TK, klast), b1);
-  stage_store<T, LA, V, TK>(smem, 0, 0, la, a0);
-  stage_store<T, LB, V, TK>(smem, P, 0, lb, b0);
-  la.load(min(2 * TK, klast), a0);
-  lb.load(min(2 * TK, klast), b0);
+  la.load(kb, a0);
+  lb.load(kb, b0);
+  la.load(kat(1), a1);
+  lb.load(kat(1), b1);
+  stage_store<T, LA, V, TK>(smem, 0, kb, la, a0);
+  stage_store<T, LB, V, TK>(smem, P, kb, lb, b0);
+  la.load(kat(2), a0);
+  lb.load(kat(2), b0);
   lds_barrier();
   for (int kt = 0;; kt += 2) {
     // LDS stage 0 holds kt; set 1 holds kt + 1, set 0 holds kt + 2
     stage_compute<T, TK>(smem, acc);
     if (kt + 1 >= nk) break;
-    const int k1 = min((kt + 1) * TK, klast);
-    stage_store<T, LA, V, TK>(smem + SD, 0, k1, la, a1);
-    stage_store<T, LB, V, TK>(smem + SD, P, k1, lb, b1);
+    stage_store<T, LA, V, TK>(smem + SD, 0, kat(kt + 1), la, a1);
+    stage_store<T, LB, V, TK>(smem + SD, P, kat(kt + 1), lb, b1);
     lds_barrier();
-    la.load(min((kt + 3) * TK, klast), a1);
-    lb.load(min((kt + 3) * TK, klast), b1);
+    la.load(kat(kt + 3), a1);
+    lb.load(kat(kt + 3), b1);
     __builtin_amdgcn_sched_barrier(0);  // issue the loads before the MFMA block
     stage_compute<T, TK>(smem + SD, acc);
     if (kt + 2 >= nk) break;
-    const int k2 = min((kt + 2) * TK, klast);
-    stage_store<T, LA, V, TK>(smem, 0, k2, la, a0);
-    stage_store<T, LB, V, TK>(smem, P, k2, lb, b0);
+    stage_store<T, LA, V, TK>(smem, 0, kat(kt + 2), la, a0);
+    stage_store<T, LB, V, TK>(smem, P, kat(kt + 2), lb, b0);
     lds_barrier();
-    la.load(min((kt + 4) * TK, klast), a0);
-    lb.load(min((kt + 4) * TK, klast), b0);
+    la.load(kat(kt + 4), a0);
+    lb.load(kat(kt + 4), b0);
     __builtin_amdgcn_sched_barrier(0);
   }
   lds_barrier();  // the caller reuses the stage buffers
