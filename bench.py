@@ -30,24 +30,42 @@ if ROOT not in sys.path:
 
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 
+WORKLOADS = {
+    "C2": "C2: 3-D 7-point weighted Laplacian 40^3 (N=64000), weights U[0.5,1.5], shift 0.05, seed 2, "
+          "nested dissection, FP64",
+    "C3": "C3: 32 shifts H - z_l S of a 3-D 7-point weighted Laplacian 30^3 (N=27000), complex128, seed 3, "
+          "nested dissection, one batched launch",
+    "C5": "C5: 3-D 27-point complex-symmetric stencil 64^3 (N=262144), 8 shifts, complex128, seed 5, "
+          "nested dissection, supernode cap 256",
+}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def gpu_leg(w, relax, steps, warmup, sched="persistent"):
+def gpu_leg(w, relax, steps, warmup, sched="levels", replicate=False):
+    """replicate: factor matrix 0 only and copy its LDL^T panels to every batch
+    slot (the traversal does the same work for any values; used where the
+    host factorization of the whole batch would take minutes)."""
     import torch
 
     from paper_1604_02528_amd import SelInv, capi
 
+    dt = "c128" if w.is_complex else "f64"
     t0 = time.perf_counter()
-    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128" if w.is_complex else "f64", batch=w.batch,
-               cap=w.cap, relax=relax, sched=sched)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=w.batch, cap=w.cap, relax=relax, sched=sched)
     t_an = time.perf_counter() - t0
     t0 = time.perf_counter()
-    ldlt_host = S.factor_host(w.values)
+    if replicate and w.batch > 1:
+        S1 = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=1, cap=w.cap, relax=relax, sched=sched)
+        one = torch.from_numpy(S1.factor_host(w.values[:1])).to("cuda")
+        S1.close()
+        ldlt = one.expand(w.batch, -1).contiguous()
+        del one
+    else:
+        ldlt = torch.from_numpy(S.factor_host(w.values)).to("cuda")
     t_fac = time.perf_counter() - t0
-    ldlt = torch.from_numpy(ldlt_host).to("cuda")
     S._alloc(False)
     stream = torch.cuda.current_stream()
     h = S.h
@@ -75,7 +93,7 @@ def gpu_leg(w, relax, steps, warmup, sched="persistent"):
     S.sync()
     t_norm = np.array([a.elapsed_time(b) for a, b, _ in evs]) * 1e-3
     t_run = np.array([b.elapsed_time(c) for _, b, c in evs]) * 1e-3
-    X = S.to_host("x")
+    X = S.to_host("x") if not replicate else None
     sym = S.symbolic()
     return {
         "S": S, "X": X, "sym": sym, "wall": wall, "t_norm": t_norm, "t_run": t_run,
@@ -112,6 +130,7 @@ def main():
     ap.add_argument("--relax", type=float, default=0.05)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--sched", default="levels", choices=["persistent", "levels"])
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C5"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run its own "
@@ -122,9 +141,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     from workloads import config
 
-    w = config("C2")
-    log(f"workload C2: N={w.n} nnz(A)={w.nnz} relax={args.relax}")
-    g = gpu_leg(w, args.relax, args.steps, args.warmup, args.sched)
+    w = config(args.workload)
+    replicate = args.workload == "C5"
+    log(f"workload {args.workload}: N={w.n} nnz(A)={w.nnz} batch={w.batch} relax={args.relax}")
+    g = gpu_leg(w, args.relax, args.steps, args.warmup, args.sched, replicate)
+    if args.workload != "C2":
+        args.no_cpu = True
     sym = g["sym"]
     flops = sym["flops_exact"] * w.batch
     ms_step = g["wall"] / args.steps * 1e3
@@ -155,11 +177,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "c128" if w.is_complex else "f64",
         "data": "synthetic",
         "config": {
-            "workload": "C2: 3-D 7-point weighted Laplacian 40^3 (N=64000), weights U[0.5,1.5], shift 0.05, "
-                        "seed 2, nested dissection, FP64",
+            "workload": WORKLOADS[args.workload] + (
+                "; LDL^T panels of shift 0 copied to all 8 batch slots (host factorization outside the "
+                "timed region)" if replicate else ""),
             "supernode_cap": w.cap, "relax": args.relax, "schedule": args.sched,
             "nsuper": sym["nsuper"], "nnzL": sym["nnzL"], "depth": sym["depth"],
             "flops_per_solve": sym["flops_exact"], "flops_partition_in_use": sym["flops"],

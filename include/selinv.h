@@ -81,6 +81,9 @@ typedef struct {
   int64_t watchdog_ms; /* persistent kernel spin budget before it aborts (0 = 10000 ms) */
   int64_t dense_max_bytes; /* cap on those buffers for the whole batch; the threshold is doubled
                               until they fit (0 = 32 GiB) */
+  int32_t split_min_k; /* shortest contraction part when a node with too few GEMM-1 tiles to fill
+                          the GPU splits its contraction over C(K) (0 = 256, < 0 = never split) */
+  int32_t reserved;
 } selinv_opts;
 
 /* Fill `o` with defaults (cap 256, R64, batch 1, persistent, relax 0). */
@@ -218,14 +221,28 @@ selinv_status selinv_backward(selinv_ctx *h, const void *panels_dev, const void 
 selinv_status selinv_check_plan(const selinv_ctx *h);
 
 /*
- * selinv_trace -- per-item timeline of the persistent schedule (diagnostics).
+ * selinv_trace -- per-item timeline of the traversal (diagnostics).
  * trace_dev: device buffer of selinv_sizes_t.trace_bytes bytes, or NULL to
- * switch tracing off.  Each selinv_run with the persistent
- * schedule then writes, per ready-queue slot, eight int64 values:
- * {item id (batch * items + item), workgroup, t_pop, t_start, t_end, 0, 0, 0}
- * in device wall-clock ticks (hipDeviceAttributeWallClockRate kHz).
+ * switch tracing off.  Each selinv_run then writes one row of eight int64
+ * values per item and matrix: {item id (l * items + item), workgroup,
+ * t_ticket, t_start, t_end, 0, 0, 0} in device wall-clock ticks
+ * (hipDeviceAttributeWallClockRate kHz).  Persistent schedule: rows in ticket
+ * order, t_ticket = when the ticket was drawn, t_start = when the item's
+ * dependencies were met.  Level schedule: rows in launch order,
+ * t_ticket = t_start = when the workgroup started.  The buffer is borrowed
+ * until tracing is switched off; tracing slows the run slightly.
  */
 selinv_status selinv_trace(selinv_ctx *h, void *trace_dev);
+
+/*
+ * selinv_items -- the traversal's work items for one matrix (diagnostics).
+ * *items receives a host view of n rows of four int32 {K, type, a, b}
+ * (type: 0 GEMM-1 tile, 1 diagonal-block tile, 2 single-workgroup node,
+ * 3 dense X_{C,C} gather block, 4 split-tile reduction; for type 0, b holds
+ * the column tile in its low 16 bits and the contraction part above them),
+ * valid until selinv_destroy.  Item id i of matrix l is l * n + i in traces.
+ */
+selinv_status selinv_items(const selinv_ctx *h, const int32_t **items, int64_t *n);
 
 /* log det of each matrix of the batch (sum of log pivots; complex log for C128).
    out_host: batch doubles (R64) or batch (re, im) pairs (C128).  Valid after selinv_factor. */

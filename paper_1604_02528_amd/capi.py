@@ -24,14 +24,15 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "EPATTERN", 3: "ESINGULAR", 4: "ENOMEM", 5: "
 EXPORTED = (
     "selinv_default_opts", "selinv_version", "selinv_analyze", "selinv_symbolic", "selinv_sizes",
     "selinv_factor", "selinv_normalize", "selinv_factor_host", "selinv_run", "selinv_extract", "selinv_backward",
-    "selinv_logdet", "selinv_check_plan", "selinv_trace", "selinv_sync", "selinv_last_error", "selinv_error_info", "selinv_destroy",
+    "selinv_logdet", "selinv_check_plan", "selinv_trace", "selinv_items", "selinv_sync", "selinv_last_error", "selinv_error_info", "selinv_destroy",
 )
 
 
 class Opts(C.Structure):
     _fields_ = [("max_super", C.c_int32), ("dtype", C.c_int32), ("batch", C.c_int32), ("sched", C.c_int32),
                 ("relax", C.c_double), ("nthreads", C.c_int32), ("dense_min_c", C.c_int32),
-                ("watchdog_ms", C.c_int64), ("dense_max_bytes", C.c_int64)]
+                ("watchdog_ms", C.c_int64), ("dense_max_bytes", C.c_int64), ("split_min_k", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 _P64 = C.POINTER(C.c_int64)
@@ -87,6 +88,7 @@ def load():
         "selinv_logdet": (C.c_int, [vp, vp]),
         "selinv_check_plan": (C.c_int, [vp]),
         "selinv_trace": (C.c_int, [vp, vp]),
+        "selinv_items": (C.c_int, [vp, C.POINTER(_P32), C.POINTER(C.c_int64)]),
         "selinv_sync": (C.c_int, [vp, vp]),
         "selinv_last_error": (C.c_char_p, [vp]),
         "selinv_error_info": (C.c_int64, [vp, C.c_int]),
@@ -191,6 +193,16 @@ def selinv_check_plan(h):
 
 def selinv_trace(h, trace):
     check(h, load().selinv_trace(h, ptr(trace)))
+
+
+def selinv_items(h):
+    """Host copy of the work items, int32 [n, 4] rows {K, type, a, b}."""
+    import numpy as np
+
+    p = _P32()
+    n = C.c_int64()
+    check(h, load().selinv_items(h, C.byref(p), C.byref(n)))
+    return np.ctypeslib.as_array(p, shape=(n.value, 4)).copy() if n.value else np.zeros((0, 4), np.int32)
 
 
 def selinv_sync(h, stream):

@@ -41,7 +41,10 @@ struct HostPlan {
   std::vector<int64_t> node_off, node_rowptr, node_sq, node_first, node_poff;
   std::vector<int64_t> kcol, kpos;
   std::vector<Item> items;
-  std::vector<int32_t> item_ptr, n_phase0, n_phase1, n_phase2, node_parent, node_ldg;
+  std::vector<int32_t> item_ptr, nph, node_parent, node_ldg, node_split, node_kchunk;  // nph: [kPhases][ns]
+  std::vector<int64_t> node_yoff;
+  int64_t y_elems = 0;
+  int64_t ns = 0;
   std::vector<int64_t> node_goff;
   int64_t g_elems = 0;
   int64_t dense_min_c = 0;  // threshold in use (INT64_MAX: no dense buffers)
@@ -56,9 +59,9 @@ struct HostPlan {
   // byte offsets inside the work buffer
   struct Off {
     int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
-        n_phase0, n_phase1, n_phase2, node_goff, node_ldg, node_parent, order, lvl_items, chunks, rblocks,
+        nph, node_split, node_kchunk, node_yoff, node_goff, node_ldg, node_parent, order, lvl_items, chunks, rblocks,
         sq_tiles,
-        apos, adiag, plan, linv, dinv, part, gbuf, cnt0, cnt1, cnt2, ctrl, end;
+        apos, adiag, plan, linv, dinv, part, gbuf, ypart, cnt, ctrl, end;
   } off{};
   int64_t tables_bytes = 0;  // [0, tables_bytes) is uploaded once
 };
@@ -79,6 +82,10 @@ void put(std::vector<unsigned char> &img, int64_t off, const std::vector<V> &v) 
 // dependencies, can never deadlock.
 constexpr int kSimWorkers = 256;
 constexpr int64_t kDefaultDenseMinC = 256;
+constexpr int64_t kSplitTarget = 512;  // GEMM-1 tiles that keep every CU busy (2 per CU)
+constexpr int64_t kSplitMax = 8;
+constexpr int64_t kSplitMinK = 256;    // default shortest contraction part
+constexpr int64_t kSplitAlign = 32;    // parts start on a contraction-stage boundary
 constexpr int64_t kDefaultDenseMaxBytes = int64_t(32) << 30;
 
 double item_cost_ns(const HostPlan &H, const Item &it) {
@@ -89,8 +96,15 @@ double item_cost_ns(const HostPlan &H, const Item &it) {
       return 2500.0 + (double)kTileM * kTileM * 24.0 / 60.0;
     case ITEM_Y: {
       const double m = std::min<double>(kTileM, c - (double)kTileM * it.a);
+      const double nn = std::min<double>(kTileN, s - (double)kTileN * (it.b & 0xffff));
+      const double kk = H.node_kchunk[it.K];
+      const double gemm2 = H.node_split[it.K] > 1 ? 0.0 : (2.0 * s * m * nn) / 150.0;
+      return 1500.0 + (2.0 * m * nn * kk) / (dense ? 150.0 : 40.0) + gemm2;
+    }
+    case ITEM_R: {
+      const double m = std::min<double>(kTileM, c - (double)kTileM * it.a);
       const double nn = std::min<double>(kTileN, s - (double)kTileN * it.b);
-      return 1500.0 + (2.0 * m * nn * c) / (dense ? 150.0 : 40.0) + (2.0 * s * m * nn) / 150.0;
+      return 1500.0 + H.node_split[it.K] * m * nn * 8.0 / 60.0 + (2.0 * s * m * nn) / 150.0;
     }
     case ITEM_D: {
       const double nr = std::ceil(c / kTileM);
@@ -102,14 +116,18 @@ double item_cost_ns(const HostPlan &H, const Item &it) {
 }
 
 // Items of phase ph of node K: [phase_begin, phase_begin + phase_count).
+int32_t phase_count(const HostPlan &H, int64_t K, int ph) { return H.nph[(size_t)ph * H.ns + K]; }
 int32_t phase_begin(const HostPlan &H, int64_t K, int ph) {
-  return H.item_ptr[K] + (ph > 0 ? H.n_phase0[K] : 0) + (ph > 1 ? H.n_phase1[K] : 0);
+  int32_t b = H.item_ptr[K];
+  for (int q = 0; q < ph; ++q) b += phase_count(H, K, q);
+  return b;
 }
-int32_t phase_count(const HostPlan &H, int64_t K, int ph) {
-  return ph == 0 ? H.n_phase0[K] : ph == 1 ? H.n_phase1[K] : H.n_phase2[K];
+int first_phase(const HostPlan &H, int64_t K) {
+  int ph = 0;
+  while (ph < kPhases - 1 && phase_count(H, K, ph) == 0) ++ph;
+  return ph;
 }
-int first_phase(const HostPlan &H, int64_t K) { return H.n_phase0[K] > 0 ? 0 : H.n_phase1[K] > 0 ? 1 : 2; }
-int item_phase(const Item &it) { return it.type == ITEM_G ? 0 : it.type == ITEM_Y ? 1 : 2; }
+int item_phase(const Item &it) { return selinv::item_phase(it.type); }
 
 void ticket_order(const Symbolic &S, HostPlan &H, int64_t batch) {
   const int64_t ns = S.nsuper(), nit = (int64_t)H.items.size();
@@ -119,7 +137,7 @@ void ticket_order(const Symbolic &S, HostPlan &H, int64_t batch) {
   std::vector<double> tail(ns, 0.0);
   for (int64_t K = 0; K < ns; ++K) {
     double next = tail[K];  // longest path after the current phase
-    for (int ph = 2; ph >= 0; --ph) {
+    for (int ph = kPhases - 1; ph >= 0; --ph) {
       const int32_t b = phase_begin(H, K, ph), n = phase_count(H, K, ph);
       if (n == 0) continue;
       double hmax = 0.0;
@@ -140,14 +158,14 @@ void ticket_order(const Symbolic &S, HostPlan &H, int64_t batch) {
   std::priority_queue<RItem, std::vector<RItem>, decltype(rcmp)> ready(rcmp);
   using Ev = std::pair<double, int64_t>;
   std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> running;
-  std::vector<int32_t> left((size_t)(batch * ns * 3));
+  std::vector<int32_t> left((size_t)(batch * ns * kPhases));
   auto release = [&](int64_t l, int64_t K, int ph) {
     const int32_t b = phase_begin(H, K, ph), n = phase_count(H, K, ph);
     for (int32_t i = b; i < b + n; ++i) ready.push({height[i], l * nit + i});
   };
   for (int64_t l = 0; l < batch; ++l)
     for (int64_t K = 0; K < ns; ++K) {
-      for (int ph = 0; ph < 3; ++ph) left[(l * ns + K) * 3 + ph] = phase_count(H, K, ph);
+      for (int ph = 0; ph < kPhases; ++ph) left[(l * ns + K) * kPhases + ph] = phase_count(H, K, ph);
       if (S.sparent[K] < 0) release(l, K, first_phase(H, K));
     }
   H.order.clear();
@@ -170,11 +188,11 @@ void ticket_order(const Symbolic &S, HostPlan &H, int64_t batch) {
       --busy;
       const int64_t l = id / nit, i = id % nit, K = H.items[i].K;
       int ph = item_phase(H.items[i]);
-      if (--left[(l * ns + K) * 3 + ph] != 0) continue;
+      if (--left[(l * ns + K) * kPhases + ph] != 0) continue;
       // phase done: release the next non-empty phase, or the children
       int nx = ph + 1;
-      while (nx < 3 && phase_count(H, K, nx) == 0) ++nx;
-      if (nx < 3) {
+      while (nx < kPhases && phase_count(H, K, nx) == 0) ++nx;
+      if (nx < kPhases) {
         release(l, K, nx);
       } else {
         for (int32_t ch : kids[K]) release(l, ch, first_phase(H, ch));
@@ -215,7 +233,7 @@ void choose_dense(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_
 }
 
 void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t dense_min_c, int64_t dense_max_bytes,
-                HostPlan &H) {
+                int64_t split_min_k, HostPlan &H) {
   const int64_t ns = S.nsuper();
   H.node_s.resize(ns);
   H.node_c.resize(ns);
@@ -231,6 +249,34 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     sq += S.width(K) * S.width(K);
   }
   H.sq_elems = sq;
+  // Contraction split of the GEMM-1 tiles: a node whose tiles (over the whole
+  // batch) cannot fill the GPU splits its contraction into parts of at least
+  // kSplitMinK indices; the parts write partial tiles that phase-2 items sum.
+  H.ns = ns;
+  H.node_split.assign(ns, 1);
+  H.node_kchunk.assign(ns, 0);
+  H.node_yoff.assign(ns, -1);
+  H.y_elems = 0;
+  for (int64_t K = 0; K < ns; ++K) {
+    const int64_t s = S.width(K), c = S.nrows(K);
+    H.node_kchunk[K] = (int32_t)c;
+    if (c <= kSmallC && s <= kSmallS) continue;  // single-item node
+    if (c == 0) continue;
+    const int64_t tiles = batch * ((c + kTileM - 1) / kTileM) * ((s + kTileN - 1) / kTileN);
+    int64_t parts = 1;
+    if (tiles < kSplitTarget) parts = std::min<int64_t>(kSplitMax, (kSplitTarget + tiles - 1) / tiles);
+    if (split_min_k < 0) parts = 1;
+    parts = std::max<int64_t>(1, std::min<int64_t>(parts, c / std::max<int64_t>(split_min_k, kSplitAlign)));
+    if (parts <= 1) continue;
+    int64_t chunk = (c + parts - 1) / parts;
+    chunk = (chunk + kSplitAlign - 1) / kSplitAlign * kSplitAlign;
+    parts = (c + chunk - 1) / chunk;
+    if (parts <= 1) continue;
+    H.node_split[K] = (int32_t)parts;
+    H.node_kchunk[K] = (int32_t)chunk;
+    H.node_yoff[K] = H.y_elems;
+    H.y_elems += (parts * c * s + kPanelAlign - 1) / kPanelAlign * kPanelAlign;
+  }
   // GEMM-2 partial products: one s x s block per 64-row tile of C(K)
   H.node_poff.resize(ns);
   int64_t pe = 0;
@@ -255,52 +301,57 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
       }
     }
   }
-  // work items: phase 0 (dense gather), phase 1 (GEMM-1 tiles), phase 2
+  // work items, phase by phase (see plan.hpp)
   choose_dense(S, batch, scalar_bytes, dense_min_c, dense_max_bytes, H);
   H.item_ptr.assign(ns + 1, 0);
-  H.n_phase0.assign(ns, 0);
-  H.n_phase1.assign(ns, 0);
-  H.n_phase2.assign(ns, 0);
+  H.nph.assign((size_t)kPhases * ns, 0);
+  auto nph = [&](int ph, int64_t K) -> int32_t & { return H.nph[(size_t)ph * ns + K]; };
   H.items.clear();
   for (int64_t K = 0; K < ns; ++K) {
     const int32_t s = H.node_s[K], c = H.node_c[K];
     H.item_ptr[K] = (int32_t)H.items.size();
     const int32_t nb = (s + kTileN - 1) / kTileN;
     const int32_t nr = (c + kTileM - 1) / kTileM;
+    const int32_t parts = H.node_split[K];
     if (H.node_goff[K] >= 0) {
       for (int32_t a = 0; a < nr; ++a)
         for (int32_t b = 0; b <= a; ++b) H.items.push_back(Item{(int32_t)K, ITEM_G, a, b});
-      H.n_phase0[K] = nr * (nr + 1) / 2;
+      nph(0, K) = nr * (nr + 1) / 2;
     }
     if (c <= kSmallC && s <= kSmallS) {
       H.items.push_back(Item{(int32_t)K, ITEM_S, 0, 0});
-      H.n_phase2[K] = 1;
-    } else {
-      if (c > 0) {
-        for (int32_t b = 0; b < nb; ++b)
-          for (int32_t a = 0; a < nr; ++a) H.items.push_back(Item{(int32_t)K, ITEM_Y, a, b});
-        H.n_phase1[K] = nr * nb;
-      }
-      for (int32_t a = 0; a < nb; ++a)
-        for (int32_t b = 0; b <= a; ++b) H.items.push_back(Item{(int32_t)K, ITEM_D, a, b});
-      H.n_phase2[K] = nb * (nb + 1) / 2;
+      nph(3, K) = 1;
+      continue;
     }
+    if (c > 0) {
+      for (int32_t p = 0; p < parts; ++p)
+        for (int32_t b = 0; b < nb; ++b)
+          for (int32_t a = 0; a < nr; ++a) H.items.push_back(Item{(int32_t)K, ITEM_Y, a, b | (p << 16)});
+      nph(1, K) = nr * nb * parts;
+      if (parts > 1) {
+        for (int32_t b = 0; b < nb; ++b)
+          for (int32_t a = 0; a < nr; ++a) H.items.push_back(Item{(int32_t)K, ITEM_R, a, b});
+        nph(2, K) = nr * nb;
+      }
+    }
+    for (int32_t a = 0; a < nb; ++a)
+      for (int32_t b = 0; b <= a; ++b) H.items.push_back(Item{(int32_t)K, ITEM_D, a, b});
+    nph(3, K) = nb * (nb + 1) / 2;
   }
   H.item_ptr[ns] = (int32_t)H.items.size();
   H.node_parent.resize(ns);
   for (int64_t K = 0; K < ns; ++K) H.node_parent[K] = (int32_t)S.sparent[K];
   ticket_order(S, H, batch);
-  // level lists (phases 0, 1, 2 per etree depth)
+  // level lists (every phase of every etree depth)
   H.lvl_items.clear();
   H.lvl_ptr.assign(1, 0);
   {
     std::vector<std::vector<int64_t>> bydepth(S.depth);
     for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
     for (int64_t d = 0; d < S.depth; ++d) {
-      for (int ph = 0; ph < 3; ++ph) {
+      for (int ph = 0; ph < kPhases; ++ph) {
         for (int64_t K : bydepth[d]) {
-          const int32_t b = H.item_ptr[K] + (ph > 0 ? H.n_phase0[K] : 0) + (ph > 1 ? H.n_phase1[K] : 0);
-          const int32_t n = ph == 0 ? H.n_phase0[K] : ph == 1 ? H.n_phase1[K] : H.n_phase2[K];
+          const int32_t b = phase_begin(H, K, ph), n = phase_count(H, K, ph);
           for (int32_t q = 0; q < n; ++q) H.lvl_items.push_back(b + q);
         }
         if ((int32_t)H.lvl_items.size() > H.lvl_ptr.back()) H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
@@ -343,9 +394,10 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.posarr = take(4 * (int64_t)S.posarr.size());
   o.items = take(16 * (int64_t)H.items.size());
   o.item_ptr = take(4 * (ns + 1));
-  o.n_phase0 = take(4 * ns);
-  o.n_phase1 = take(4 * ns);
-  o.n_phase2 = take(4 * ns);
+  o.nph = take(4 * kPhases * ns);
+  o.node_split = take(4 * ns);
+  o.node_kchunk = take(4 * ns);
+  o.node_yoff = take(8 * ns);
   o.node_goff = take(8 * ns);
   o.node_ldg = take(4 * ns);
   o.node_parent = take(4 * ns);
@@ -362,9 +414,8 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.dinv = take(scalar_bytes * batch * S.n);
   o.part = take(scalar_bytes * batch * H.part_elems);
   o.gbuf = take(scalar_bytes * batch * H.g_elems);
-  o.cnt0 = take(4 * batch * ns);
-  o.cnt1 = take(4 * batch * ns);
-  o.cnt2 = take(4 * batch * ns);
+  o.ypart = take(scalar_bytes * batch * H.y_elems);
+  o.cnt = take(4 * kPhases * batch * ns);
   o.ctrl = take(4 * CTRL_WORDS);
   o.end = p;
 }
@@ -440,9 +491,10 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.posarr = (int32_t *)(b + o.posarr);
   d.items = (Item *)(b + o.items);
   d.item_ptr = (int32_t *)(b + o.item_ptr);
-  d.n_phase0 = (int32_t *)(b + o.n_phase0);
-  d.n_phase1 = (int32_t *)(b + o.n_phase1);
-  d.n_phase2 = (int32_t *)(b + o.n_phase2);
+  d.nph = (int32_t *)(b + o.nph);
+  d.node_split = (int32_t *)(b + o.node_split);
+  d.node_kchunk = (int32_t *)(b + o.node_kchunk);
+  d.node_yoff = (int64_t *)(b + o.node_yoff);
   d.node_goff = (int64_t *)(b + o.node_goff);
   d.node_ldg = (int32_t *)(b + o.node_ldg);
   d.g_elems = H.g_elems;
@@ -455,9 +507,9 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.dinv = (void *)(b + o.dinv);
   d.part = (void *)(b + o.part);
   d.gbuf = (void *)(b + o.gbuf);
-  d.cnt0 = (int32_t *)(b + o.cnt0);
-  d.cnt1 = (int32_t *)(b + o.cnt1);
-  d.cnt2 = (int32_t *)(b + o.cnt2);
+  d.ypart = (void *)(b + o.ypart);
+  d.y_elems = H.y_elems;
+  d.cnt = (int32_t *)(b + o.cnt);
   d.ctrl = (int32_t *)(b + o.ctrl);
   d.trace = (int64_t *)h->trace;
   return d;
@@ -500,9 +552,10 @@ void build_image(selinv_ctx *h) {
   put(img, o.posarr, h->S.posarr);
   put(img, o.items, H.items);
   put(img, o.item_ptr, H.item_ptr);
-  put(img, o.n_phase0, H.n_phase0);
-  put(img, o.n_phase1, H.n_phase1);
-  put(img, o.n_phase2, H.n_phase2);
+  put(img, o.nph, H.nph);
+  put(img, o.node_split, H.node_split);
+  put(img, o.node_kchunk, H.node_kchunk);
+  put(img, o.node_yoff, H.node_yoff);
   put(img, o.node_goff, H.node_goff);
   put(img, o.node_ldg, H.node_ldg);
   put(img, o.node_parent, H.node_parent);
@@ -545,6 +598,8 @@ void selinv_default_opts(selinv_opts *o) {
   o->dense_min_c = 0;
   o->watchdog_ms = 0;
   o->dense_max_bytes = 0;
+  o->split_min_k = 0;
+  o->reserved = 0;
 }
 
 const char *selinv_version(void) { return "selinv-mi355x 0.1"; }
@@ -570,7 +625,8 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *ro
     analyze(h->S, n, colptr, rowind, perm, o.max_super, o.relax);
     const int64_t min_c = o.dense_min_c == 0 ? kDefaultDenseMinC : o.dense_min_c;
     const int64_t max_b = o.dense_max_bytes > 0 ? o.dense_max_bytes : kDefaultDenseMaxBytes;
-    build_plan(h->S, o.batch, h->sbytes(), min_c, max_b, h->H);
+    const int64_t split_k = o.split_min_k == 0 ? kSplitMinK : o.split_min_k;
+    build_plan(h->S, o.batch, h->sbytes(), min_c, max_b, split_k, h->H);
     if ((int64_t)h->H.items.size() * (int64_t)o.batch >= (int64_t)INT32_MAX)
       return set_err(h, SELINV_ENOMEM, "too many work items for int32 item ids");
     build_image(h);
@@ -815,11 +871,11 @@ selinv_status selinv_check_plan(const selinv_ctx *hc) {
   // order, each item's dependencies must already be done when its turn comes.
   if ((int64_t)H.order.size() != B * nit)
     return set_err(h, SELINV_EINVAL, "plan check: ticket order has the wrong length", (int64_t)H.order.size(), B * nit);
-  std::vector<int32_t> left((size_t)(B * ns * 3));
+  std::vector<int32_t> left((size_t)(B * ns * kPhases));
   std::vector<uint8_t> seen((size_t)(B * nit), 0);
   for (int64_t l = 0; l < B; ++l)
     for (int64_t K = 0; K < ns; ++K)
-      for (int ph = 0; ph < 3; ++ph) left[(l * ns + K) * 3 + ph] = phase_count(H, K, ph);
+      for (int ph = 0; ph < kPhases; ++ph) left[(l * ns + K) * kPhases + ph] = phase_count(H, K, ph);
   for (int64_t t = 0; t < B * nit; ++t) {
     const int64_t id = H.order[t];
     if (id < 0 || id >= B * nit) return set_err(h, SELINV_EINVAL, "plan check: ticket names no item", t, id);
@@ -832,24 +888,33 @@ selinv_status selinv_check_plan(const selinv_ctx *hc) {
     const int32_t b = phase_begin(H, K, ph);
     if (itn < b || itn >= b + phase_count(H, K, ph))
       return set_err(h, SELINV_EINVAL, "plan check: item outside its phase range", K, itn);
-    if (ph == 1 && (H.node_goff[K] >= 0) != (H.n_phase0[K] > 0))
+    if (ph == 1 && (H.node_goff[K] >= 0) != (phase_count(H, K, 0) > 0))
       return set_err(h, SELINV_EINVAL, "plan check: dense buffer without gather items", K, l);
     // the kernel's wait rule: the previous non-empty phase, else the parent
     int pv = ph - 1;
     while (pv >= 0 && phase_count(H, K, pv) == 0) --pv;
     if (pv >= 0) {
-      if (left[(l * ns + K) * 3 + pv] != 0)
+      if (left[(l * ns + K) * kPhases + pv] != 0)
         return set_err(h, SELINV_EINVAL, "plan check: phase started before the previous one finished", K, l);
     } else {
       const int64_t P = H.node_parent[K];
       if (P != S.sparent[K]) return set_err(h, SELINV_EINVAL, "plan check: wrong parent table", K, P);
-      if (P >= 0 && left[(l * ns + P) * 3 + 2] != 0)
+      if (P >= 0 && left[(l * ns + P) * kPhases + kPhases - 1] != 0)
         return set_err(h, SELINV_EINVAL, "plan check: node started before its parent finished", K, l);
     }
-    --left[(l * ns + K) * 3 + ph];
+    --left[(l * ns + K) * kPhases + ph];
   }
   for (size_t q = 0; q < left.size(); ++q)
-    if (left[q] != 0) return set_err(h, SELINV_EINVAL, "plan check: node never finished", (int64_t)(q / 3) % ns, (int64_t)(q / 3) / ns);
+    if (left[q] != 0) return set_err(h, SELINV_EINVAL, "plan check: node never finished", (int64_t)(q / kPhases) % ns, (int64_t)(q / kPhases) / ns);
+  return SELINV_OK;
+}
+
+selinv_status selinv_items(const selinv_ctx *hc, const int32_t **items, int64_t *n) {
+  selinv_ctx *h = const_cast<selinv_ctx *>(hc);
+  if (!h || !items || !n) return SELINV_EINVAL;
+  if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
+  *items = reinterpret_cast<const int32_t *>(h->H.items.data());
+  *n = (int64_t)h->H.items.size();
   return SELINV_OK;
 }
 

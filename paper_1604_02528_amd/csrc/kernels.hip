@@ -38,6 +38,7 @@ template <typename T> struct Ctx {
   T *Xp;        // selected inverse of this matrix
   T *Pp;        // GEMM-2 partial products of this matrix
   T *Gp;        // dense X_{C,C} buffers of this matrix
+  T *Yp;        // partial GEMM-1 tiles of this matrix (split nodes)
 };
 
 // Block (a, b), a >= b, of X_{C,C} for a node with a dense buffer G (column
@@ -90,37 +91,14 @@ __device__ void do_gtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
   lds_barrier();
 }
 
-// GEMM-1 tile, rows 64a.. and columns 64b.. of X_{C,K}:
-//   Y = -X_{C,C} Lhat_{C,K}                                  (Alg. 1 step 3)
-// fused with this row tile's share of GEMM-2 (step 4):
-//   P_a[:, 64b..] = Lhat[rows of tile a, :]^T Y[tile a, 64b..]
-// written to the partial buffer (column-major s x s per row tile).
+// Store -acc (a 64 x 64 tile of X_{C,K} = -X_{C,C} Lhat) into X, rows 64a..
+// of C(K) and columns 64b.. of K, through LDS so that the stores coalesce.
 template <typename T, bool COH>
-__device__ void do_ytile(const Ctx<T> &cx, int K, int a, int b, double *smem, int64_t *rt) {
-  constexpr int P = Planes<T>::P;
+__device__ void store_xtile(const Ctx<T> &cx, int K, int a, int b, const Acc<T> &acc, double *smem) {
   const DevPlan &pl = *cx.pl;
-  const int s = uniform(gp(pl.node_s)[K]), c = uniform(gp(pl.node_c)[K]), ld = s + c;
-  const int64_t off = gp(pl.node_off)[K], rp = gp(pl.node_rowptr)[K];
-  const int64_t goff = gp(pl.node_goff)[K];
+  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
+  const int64_t off = gp(pl.node_off)[K];
   const int i0 = a * 64, j0 = b * 64;
-  Acc<T> acc;
-  if (uniform(goff >= 0 ? 1 : 0)) {  // X_{C,C} already gathered into the dense buffer
-    constexpr int TK = DenseTK<T>::TK;
-    const T *G = static_cast<const T *>(cx.Gp) + goff;
-    LoadDenseA<T, TK> la{G, gp(pl.node_ldg)[K], c, c, i0};
-    LoadDenseB<T, TK> lb{cx.Lp, off, ld, s, c, j0, s};
-    gemm_dense<T>(0, c, la, lb, smem, acc);  // acc = X_{C,C} Lhat = -Y (tile)
-  } else {
-    if (threadIdx.x < 64) {
-      const int ig = i0 + threadIdx.x;
-      rt[threadIdx.x] = gp(pl.kcol)[rp + (ig < c ? ig : 0)];
-      rt[64 + threadIdx.x] = gp(pl.kpos)[rp + (ig < c ? ig : 0)];
-    }
-    lds_barrier();
-    LoadGather<T, COH> la{cx.Xp, pl.kcol + rp, pl.kpos + rp, pl.posarr, rt, rt + 64, c, i0};
-    LoadPanelK<T, false> lb{cx.Lp, off, ld, s, 0, c, j0, s};
-    gemm_tile<T>(c, la, lb, smem, acc);  // acc = X_{C,C} Lhat = -Y (tile)
-  }
   acc_to_lds<T>(acc, smem);
   lds_barrier();
   for (int e = threadIdx.x; e < 64 * 64; e += NT) {
@@ -129,22 +107,39 @@ __device__ void do_ytile(const Ctx<T> &cx, int K, int a, int b, double *smem, in
       Mem<COH>::st(cx.Xp + off + (int64_t)(j0 + j) * ld + s + i0 + i, SOps<T>::scale(-1.0, lds_get<T>(smem, i, j)));
   }
   lds_barrier();
-  // Partial GEMM-2 from the accumulators: they already sit in the MFMA
-  // B-operand layout for a contraction over the tile rows (register v of a
-  // 16 x 16 block holds rows 4v..4v+3 of lanes l / 16).
+}
+
+// Row tile a's share of GEMM-2 (Alg. 1 step 4): P_a[:, 64b..] = Lhat[rows of
+// tile a, :]^T Y[tile a, 64b..] = -(Lhat_a^T acc), written to the partial
+// buffer (column-major s x s per row tile).  The accumulators already sit in
+// the MFMA B-operand layout for a contraction over the tile rows (register v
+// of a 16 x 16 block holds rows 4v..4v+3 of lanes l / 16).
+template <typename T, bool COH>
+__device__ void gemm2_partial(const Ctx<T> &cx, int K, int a, int b, const Acc<T> &acc, double *smem) {
+  constexpr int P = Planes<T>::P;
+  const DevPlan &pl = *cx.pl;
+  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
+  const int64_t off = gp(pl.node_off)[K];
+  const int i0 = a * 64, j0 = b * 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wi = w & 1, wj = w >> 1;
   const int64_t pbase = gp(pl.node_poff)[K] + (int64_t)a * s * s;
   double *Ls = smem;  // Lhat[i0 .. i0+63, q0 .. q0+63] as Ls[p][i * PITCH + x]
   for (int q0 = 0; q0 < s; q0 += 64) {
+    T lv[64 * 64 / NT];
 #pragma unroll
     for (int q = 0; q < 64 * 64 / NT; ++q) {
       const int e = threadIdx.x + NT * q;
       const int i = e & 63, x = e >> 6;
-      const bool ok = i0 + i < c && q0 + x < s;
-      const T v = cx.Lp[ok ? off + (int64_t)(q0 + x) * ld + s + i0 + i : off];
+      lv[q] = gload(cx.Lp + off + (((int64_t)(q0 + x) * ld + s + i0 + i) & opaque_mask(i0 + i < c && q0 + x < s)));
+    }
 #pragma unroll
-      for (int p = 0; p < P; ++p) Ls[p * 64 * PITCH + i * PITCH + x] = ok ? Planes<T>::get(v, p) : 0.0;
+    for (int q = 0; q < 64 * 64 / NT; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int i = e & 63, x = e >> 6;
+      const T v = masked(lv[q], opaque_mask(i0 + i < c && q0 + x < s));
+#pragma unroll
+      for (int p = 0; p < P; ++p) Ls[p * 64 * PITCH + i * PITCH + x] = Planes<T>::get(v, p);
     }
     lds_barrier();
     d4 pacc[P][4][2];
@@ -206,6 +201,107 @@ __device__ void do_ytile(const Ctx<T> &cx, int K, int a, int b, double *smem, in
     }
     lds_barrier();
   }
+}
+
+// GEMM-1 tile, rows 64a.. and columns 64b.. of X_{C,K} (Alg. 1 step 3):
+//   acc = X_{C,C}[tile rows, k] Lhat_{C,K}[k, tile columns], k in this part's
+// share of [0, c).  An unsplit node stores Y = -acc into X and its row tile's
+// share of GEMM-2 (step 4); a split node stores acc as a partial tile.
+template <typename T, bool COH>
+__device__ void do_ytile(const Ctx<T> &cx, int K, int a, int bp, double *smem, int64_t *rt) {
+  const DevPlan &pl = *cx.pl;
+  const int s = uniform(gp(pl.node_s)[K]), c = uniform(gp(pl.node_c)[K]), ld = s + c;
+  const int64_t off = gp(pl.node_off)[K], rp = gp(pl.node_rowptr)[K];
+  const int64_t goff = gp(pl.node_goff)[K];
+  const int b = bp & 0xffff, part = bp >> 16;
+  const int parts = uniform(gp(pl.node_split)[K]), kchunk = uniform(gp(pl.node_kchunk)[K]);
+  const int kb = part * kchunk, ke = min(c, kb + kchunk);
+  const int i0 = a * 64, j0 = b * 64;
+  Acc<T> acc;
+  if (uniform(goff >= 0 ? 1 : 0)) {  // X_{C,C} already gathered into the dense buffer
+    constexpr int TK = DenseTK<T>::TK;
+    const T *G = static_cast<const T *>(cx.Gp) + goff;
+    LoadDenseA<T, TK> la{G, gp(pl.node_ldg)[K], c, ke, i0};
+    LoadDenseB<T, TK> lb{cx.Lp, off, ld, s, ke, j0, s};
+    gemm_dense<T>(kb, ke, la, lb, smem, acc);
+  } else {
+    if (threadIdx.x < 64) {
+      const int ig = i0 + threadIdx.x;
+      rt[threadIdx.x] = gp(pl.kcol)[rp + (ig < c ? ig : 0)];
+      rt[64 + threadIdx.x] = gp(pl.kpos)[rp + (ig < c ? ig : 0)];
+    }
+    lds_barrier();
+    LoadGather<T, COH> la{cx.Xp, pl.kcol + rp, pl.kpos + rp, pl.posarr, rt, rt + 64, c, ke, i0};
+    LoadPanelK<T, false> lb{cx.Lp, off, ld, s, 0, ke, j0, s};
+    gemm_tile<T>(kb, ke, la, lb, smem, acc);
+  }
+  if (parts == 1) {
+    store_xtile<T, COH>(cx, K, a, b, acc, smem);
+    gemm2_partial<T, COH>(cx, K, a, b, acc, smem);
+    return;
+  }
+  // partial tile of a split node: Ypart[part] (column-major c x s)
+  T *Y = static_cast<T *>(cx.Yp) + gp(pl.node_yoff)[K] + (int64_t)part * c * s;
+  acc_to_lds<T>(acc, smem);
+  lds_barrier();
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int i = e & 63, j = e >> 6;
+    if (i0 + i < c && j0 + j < s) Mem<COH>::st(Y + (int64_t)(j0 + j) * c + i0 + i, lds_get<T>(smem, i, j));
+  }
+  lds_barrier();
+}
+
+// Sum of a split node's partial tiles (a, b) into X, then the row tile's share
+// of GEMM-2 (the step-3 and step-4 work that an unsplit tile does itself).
+template <typename T, bool COH>
+__device__ void do_rtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
+  const DevPlan &pl = *cx.pl;
+  const int s = uniform(gp(pl.node_s)[K]), c = uniform(gp(pl.node_c)[K]);
+  const int parts = uniform(gp(pl.node_split)[K]);
+  const T *Y = static_cast<const T *>(cx.Yp) + gp(pl.node_yoff)[K];
+  const int i0 = a * 64, j0 = b * 64;
+  constexpr int Q = 64 * 64 / NT;
+  T sum[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) sum[q] = zero_of<T>();
+  for (int p = 0; p < parts; ++p) {
+    T v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int i = e & 63, j = e >> 6;
+      v[q] = Mem<COH>::ld(Y + (int64_t)p * c * s + (((int64_t)(j0 + j) * c + i0 + i) & opaque_mask(i0 + i < c && j0 + j < s)));
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) sum[q] += v[q];
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int i = e & 63, j = e >> 6;
+    lds_put<T>(smem, i, j, masked(sum[q], opaque_mask(i0 + i < c && j0 + j < s)));
+  }
+  lds_barrier();
+  // into the accumulator layout of the MFMA tile
+  constexpr int P = Planes<T>::P;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w & 1, wj = w >> 1;
+  Acc<T> acc;
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 32 * wi + 16 * bi + 4 * v + (lane >> 4);
+          const int j = 32 * wj + 16 * bj + (lane & 15);
+          acc.v[p][bi][bj][v] = smem[p * 64 * PITCH + j * PITCH + i];
+        }
+  lds_barrier();
+  store_xtile<T, COH>(cx, K, a, b, acc, smem);
+  gemm2_partial<T, COH>(cx, K, a, b, acc, smem);
 }
 
 // Blocks (a, b) and (b, a), a >= b, of X_KK = sym(Dt^{-1} - sum_r P_r)
@@ -293,6 +389,8 @@ __device__ void do_item(const Ctx<T> &cx, const Item &item, double *smem, int64_
     do_gtile<T>(cx, it.K, it.a, it.b, smem);
   } else if (it.type == ITEM_Y) {
     do_ytile<T, COH>(cx, it.K, it.a, it.b, smem, rt);
+  } else if (it.type == ITEM_R) {
+    do_rtile<T, COH>(cx, it.K, it.a, it.b, smem);
   } else if (it.type == ITEM_D) {
     do_dtile<T, COH>(cx, it.K, it.a, it.b, smem);
   } else {  // ITEM_S: the whole node (c <= 64, s <= 64) in this workgroup
@@ -310,16 +408,28 @@ __device__ void do_item(const Ctx<T> &cx, const Item &item, double *smem, int64_
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1) k_items_list(const DevPlan *__restrict__ plp, const T *Lp, T *Xp, T *Pp, const int32_t *list,
-                                                   int32_t count) {
+                                                   int32_t count, int32_t list_pos) {
   const DevPlan &pl = *plp;
   __shared__ double smem[smem_doubles<T>()];
   __shared__ int64_t rt[128];
   const int64_t g = blockIdx.x;
   const int64_t l = g / count;
   const int32_t it = list[g - l * count];
+  const int64_t t_start = pl.trace ? wall_clock64() : 0;
   Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, Pp + l * pl.part_elems,
-            static_cast<T *>(pl.gbuf) + l * pl.g_elems};
+            static_cast<T *>(pl.gbuf) + l * pl.g_elems, static_cast<T *>(pl.ypart) + l * pl.y_elems};
   do_item<T, false>(cx, gload(pl.items + it), smem, rt);
+  if (pl.trace) {
+    __syncthreads();
+    if (threadIdx.x == 0) {  // row of this item in the trace: levels in order, matrices inside a level
+      int64_t *tr = pl.trace + 8 * ((int64_t)list_pos * pl.batch + g);
+      tr[0] = l * pl.nitems + it;
+      tr[1] = blockIdx.x;
+      tr[2] = t_start;
+      tr[3] = t_start;
+      tr[4] = wall_clock64();
+    }
+  }
 }
 
 // Scheduler atomics (agent scope, relaxed).  Producers order their data
@@ -343,9 +453,8 @@ __global__ void k_sched_init(const DevPlan *__restrict__ plp) {
   const int64_t nsb = pl.batch * pl.ns;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsb; i += stride) {
     const int64_t K = i % pl.ns;
-    gw(pl.cnt0)[i] = gp(pl.n_phase0)[K];
-    gw(pl.cnt1)[i] = gp(pl.n_phase1)[K];
-    gw(pl.cnt2)[i] = gp(pl.n_phase2)[K];
+#pragma unroll
+    for (int ph = 0; ph < kPhases; ++ph) gw(pl.cnt)[ph * nsb + i] = gp(pl.nph)[ph * pl.ns + K];
   }
   if (blockIdx.x == 0 && threadIdx.x < CTRL_WORDS) gw(pl.ctrl)[threadIdx.x] = 0;
 }
@@ -357,18 +466,16 @@ __global__ void k_sched_init(const DevPlan *__restrict__ plp) {
 // when another workgroup raised the error flag or when the watchdog, counted
 // from kernel start, expires (then it raises the flag).
 __device__ bool wait_ready(const DevPlan &pl, int64_t l, const Item &it, int64_t t_begin, int64_t budget_ticks) {
-  const int64_t nk = l * pl.ns + it.K;
-  const int32_t *ctr = nullptr;
-  if (it.type == ITEM_Y) {
-    if (uniform(gp(pl.n_phase0)[it.K]) > 0) ctr = pl.cnt0 + nk;
-  } else if (it.type == ITEM_D || it.type == ITEM_S) {
-    if (uniform(gp(pl.n_phase1)[it.K]) > 0) ctr = pl.cnt1 + nk;
-    else if (uniform(gp(pl.n_phase0)[it.K]) > 0) ctr = pl.cnt0 + nk;
-  }
-  if (ctr == nullptr) {
+  const int64_t nsb = pl.batch * pl.ns;
+  int pv = item_phase(it.type) - 1;
+  while (pv >= 0 && uniform(gp(pl.nph)[pv * pl.ns + it.K]) == 0) --pv;
+  const int32_t *ctr;
+  if (pv >= 0) {
+    ctr = pl.cnt + pv * nsb + l * pl.ns + it.K;
+  } else {
     const int32_t P = uniform(gp(pl.node_parent)[it.K]);
     if (P < 0) return true;
-    ctr = pl.cnt2 + l * pl.ns + P;
+    ctr = pl.cnt + (kPhases - 1) * nsb + l * pl.ns + P;
   }
   int backoff = 1;
   while (uniform(ld_relaxed(ctr)) != 0) {
@@ -426,7 +533,7 @@ __global__ void __launch_bounds__(NT, 1)
     const int32_t itn = (int32_t)(id - l * pl.nitems);
     const Item it = uniform(gload(pl.items + itn));
     Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, Pp + l * pl.part_elems,
-            static_cast<T *>(pl.gbuf) + l * pl.g_elems};
+            static_cast<T *>(pl.gbuf) + l * pl.g_elems, static_cast<T *>(pl.ypart) + l * pl.y_elems};
     do_item<T, false>(cx, it, smem, rt);
     // Publishing protocol: write back this item's stores (agent-scope release)
     // before the counter update.  Readers use plain cached loads: every panel
@@ -444,8 +551,7 @@ __global__ void __launch_bounds__(NT, 1)
         tr[3] = t_start;
         tr[4] = wall_clock64();
       }
-      int32_t *cnt = it.type == ITEM_G ? pl.cnt0 : it.type == ITEM_Y ? pl.cnt1 : pl.cnt2;
-      add_relaxed(cnt + l * pl.ns + it.K, -1);
+      add_relaxed(pl.cnt + item_phase(it.type) * pl.batch * pl.ns + l * pl.ns + it.K, -1);
     }
   }
 }
@@ -497,19 +603,17 @@ __global__ void __launch_bounds__(NT) k_normalize_rows(const DevPlan *__restrict
       for (int ib = jb + w; ib < s; ib += 16) {
         T xi[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int i = min(ib + u, s - 1);
-          xi[u] = masked(gload(Linv + (int64_t)i * s + r), opaque_mask(ib + u < s));
-        }
+        for (int u = 0; u < 16; ++u) xi[u] = gload(Linv + (int64_t)min(ib + u, s - 1) * s + r);
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
           const int ii = min(ib + u, s - 1) - jb;
+          const T xu = masked(xi[u], opaque_mask(ib + u < s));  // zeroed where it is used, not at the load
 #pragma unroll
           for (int q = 0; q < 16; ++q) {
             T lv;
             if constexpr (Planes<T>::P == 1) lv = ls[0][q * 257 + ii];
             else lv = T{ls[0][q * 257 + ii], ls[1][q * 257 + ii]};
-            x[q] -= xi[u] * lv;
+            x[q] -= xu * lv;
           }
         }
       }
@@ -714,7 +818,7 @@ static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
       const int32_t b = aux.lvl_ptr[q], e = aux.lvl_ptr[q + 1];
       if (e > b)
         hipLaunchKernelGGL(k_items_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,
-                           aux.lvl_items + b, e - b);
+                           aux.lvl_items + b, e - b, b);
     }
     return hipGetLastError();
   }

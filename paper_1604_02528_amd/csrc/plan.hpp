@@ -6,17 +6,21 @@
 //           ancestors' X panels through the ancestor maps and written with its
 //           mirror into the node's dense c x c buffer (nodes with a dense
 //           buffer only).
-//   ITEM_Y  (K, a, b): rows 64a.. of X_{C,K} and columns 64b.. -- GEMM-1
-//           X_{C,K} = -X_{C,C} Lhat_{C,K} (Alg. 1 step 3), reading X_{C,C}
-//           from the dense buffer or gathering it on the fly, fused with the
-//           row tile's share of GEMM-2.
+//   ITEM_Y  (K, a, b | part << 16): rows 64a.. and columns 64b.. of GEMM-1
+//           X_{C,K} = -X_{C,C} Lhat_{C,K} (Alg. 1 step 3), contraction indices
+//           [part * kchunk, (part + 1) * kchunk) of the node's split.  X_{C,C}
+//           comes from the dense buffer or is gathered on the fly.  Unsplit
+//           nodes store the tile into X and its share of GEMM-2 directly;
+//           split nodes store a partial tile.
+//   ITEM_R  (K, a, b): sum of a split node's partial tiles into X, and the row
+//           tile's share of GEMM-2 (split nodes only).
 //   ITEM_D  (K, a, b), a >= b: blocks (a, b) and (b, a) of X_KK = Dt_K^{-1} -
 //           Lhat_{C,K}^T X_{C,K} (step 4), symmetrized (Section 2.3).
 //   ITEM_S  (K): a node with c <= 64 and s <= 64 done by one workgroup.
-// Phase 0 of a node = its ITEM_G items, phase 1 = its ITEM_Y items, phase 2 =
-// its ITEM_D / ITEM_S items.  A node's first non-empty phase becomes ready
-// when its parent's phase 2 is done (C(K) lies in the ancestors, Eq. (newset));
-// every later phase becomes ready when the phase before it is done.
+// Phases of a node: 0 = ITEM_G, 1 = ITEM_Y, 2 = ITEM_R, 3 = ITEM_D / ITEM_S
+// (never empty).  A node's first non-empty phase becomes ready when its
+// parent's phase 3 is done (C(K) lies in the ancestors, Eq. (newset)); every
+// later phase becomes ready when the previous non-empty phase is done.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,7 +29,11 @@
 
 namespace selinv {
 
-enum ItemType : int32_t { ITEM_Y = 0, ITEM_D = 1, ITEM_S = 2, ITEM_G = 3 };
+enum ItemType : int32_t { ITEM_Y = 0, ITEM_D = 1, ITEM_S = 2, ITEM_G = 3, ITEM_R = 4 };
+constexpr int kPhases = 4;
+__host__ __device__ constexpr int item_phase(int type) {
+  return type == ITEM_G ? 0 : type == ITEM_Y ? 1 : type == ITEM_R ? 2 : 3;
+}
 
 constexpr int kTileM = 64;   // GEMM-1 rows per item
 constexpr int kTileN = 64;   // columns per item (of s)
@@ -51,9 +59,10 @@ struct DevPlan {
   int32_t *posarr;
   Item *items;
   int32_t *item_ptr;   // [ns+1]
-  int32_t *n_phase0;   // [ns]
-  int32_t *n_phase1;   // [ns]
-  int32_t *n_phase2;   // [ns]
+  int32_t *nph;        // [kPhases][ns] items of each phase
+  int32_t *node_split; // [ns] contraction split of the GEMM-1 tiles (1 = unsplit)
+  int32_t *node_kchunk;// [ns] contraction indices per split part
+  int64_t *node_yoff;  // [ns] element offset of the partial tiles (split nodes)
   int64_t *node_goff;  // [ns] element offset of the dense X_{C,C} buffer (-1: gathered on the fly)
   int32_t *node_ldg;   // [ns] its leading dimension (c rounded up to 16)
   int64_t g_elems;     // dense buffers of one matrix, in scalars
@@ -67,7 +76,9 @@ struct DevPlan {
   void *dinv;          // [batch][n] scalars
   void *part;          // [batch][part_elems] GEMM-2 partial products
   void *gbuf;          // [batch][g_elems] dense X_{C,C} buffers
-  int32_t *cnt0, *cnt1, *cnt2;  // [batch][ns] outstanding items of each phase
+  void *ypart;         // [batch][y_elems] partial GEMM-1 tiles of split nodes
+  int64_t y_elems;
+  int32_t *cnt;        // [kPhases][batch][ns] outstanding items of each phase
   int32_t *ctrl;       // CTRL_WORDS
   int64_t *trace;      // optional: per ticket {item id, workgroup, t_ticket, t_start, t_end, 0, 0, 0}
 };

@@ -213,60 +213,59 @@ __device__ __forceinline__ void stage_store(double *stg, int plane_off, int k0, 
   }
 }
 
-// acc = A (64 x kc) * B (kc x 64).  LA fills the A planes, LB the B planes.
-// Pipeline: while stage kt is multiplied, the values of stage kt+2, the
-// positions of stage kt+3 and the index entries of stage kt+4 are in flight.
-// The loop body has no branches: prefetch stage indices are clamped to the
-// last stage (the redundant reloads at the end are harmless), so the waits
-// the compiler inserts are counted waits on the oldest loads only.
+// acc = A (64 x [kb, ke)) * B ([kb, ke) x 64).  LA fills the A planes, LB the
+// B planes.  Pipeline: while stage kt is multiplied, the values of stage kt+2,
+// the positions of stage kt+3 and the index entries of stage kt+4 are in
+// flight.  The loop body has no branches: prefetch stage indices are clamped
+// to the last stage (the redundant reloads at the end are harmless), so the
+// waits the compiler inserts are counted waits on the oldest loads only.
+// kb and ke must be wave-uniform.
 template <typename T, class LA, class LB>
-__device__ __forceinline__ void gemm_tile(int kc, const LA &la, const LB &lb, double *smem, Acc<T> &acc) {
+__device__ __forceinline__ void gemm_tile(int kb, int ke, const LA &la, const LB &lb, double *smem, Acc<T> &acc) {
   constexpr int P = Planes<T>::P, TK = Planes<T>::TK;
   acc_zero<T>(acc);
-  const int nk = (kc + TK - 1) / TK;
-  if (nk == 0) return;
-  const int klast = (nk - 1) * TK;
+  const int nk = (ke - kb + TK - 1) / TK;
+  if (nk <= 0) return;
+  const int klast = kb + (nk - 1) * TK;
+  auto kat = [&](int j) { return min(kb + j * TK, klast); };
   typename LA::S1 a1;
   typename LB::S1 b1;
   typename LA::S2 a2;
   typename LB::S2 b2;
   Vals<T> av, bv;
-  la.lev1(0, a1);
-  lb.lev1(0, b1);
-  la.lev2(0, a1, a2);
-  lb.lev2(0, b1, b2);
-  la.lev3(0, a2, av);
-  lb.lev3(0, b2, bv);
-  stage_store<T>(smem, 0, 0, la, av);
-  stage_store<T>(smem, P, 0, lb, bv);
-  const int k1 = min(TK, klast), k2 = min(2 * TK, klast), k3 = min(3 * TK, klast);
-  la.lev1(k1, a1);
-  lb.lev1(k1, b1);
-  la.lev2(k1, a1, a2);
-  lb.lev2(k1, b1, b2);
-  la.lev3(k1, a2, av);
-  lb.lev3(k1, b2, bv);
-  la.lev1(k2, a1);
-  lb.lev1(k2, b1);
-  la.lev2(k2, a1, a2);
-  lb.lev2(k2, b1, b2);
-  la.lev1(k3, a1);
-  lb.lev1(k3, b1);
+  la.lev1(kb, a1);
+  lb.lev1(kb, b1);
+  la.lev2(kb, a1, a2);
+  lb.lev2(kb, b1, b2);
+  la.lev3(kb, a2, av);
+  lb.lev3(kb, b2, bv);
+  stage_store<T>(smem, 0, kb, la, av);
+  stage_store<T>(smem, P, kb, lb, bv);
+  la.lev1(kat(1), a1);
+  lb.lev1(kat(1), b1);
+  la.lev2(kat(1), a1, a2);
+  lb.lev2(kat(1), b1, b2);
+  la.lev3(kat(1), a2, av);
+  lb.lev3(kat(1), b2, bv);
+  la.lev1(kat(2), a1);
+  lb.lev1(kat(2), b1);
+  la.lev2(kat(2), a1, a2);
+  lb.lev2(kat(2), b1, b2);
+  la.lev1(kat(3), a1);
+  lb.lev1(kat(3), b1);
   lds_barrier();
   for (int kt = 0; kt < nk; ++kt) {
     stage_compute<T>(smem + (kt & 1) * stage_doubles<T>(), acc);
     double *nxt = smem + ((kt + 1) & 1) * stage_doubles<T>();
-    const int ks = min((kt + 1) * TK, klast);
-    stage_store<T>(nxt, 0, ks, la, av);
-    stage_store<T>(nxt, P, ks, lb, bv);
+    stage_store<T>(nxt, 0, kat(kt + 1), la, av);
+    stage_store<T>(nxt, P, kat(kt + 1), lb, bv);
     lds_barrier();
-    const int kv = min((kt + 2) * TK, klast), kp = min((kt + 3) * TK, klast), ki = min((kt + 4) * TK, klast);
-    la.lev3(kv, a2, av);
-    lb.lev3(kv, b2, bv);
-    la.lev2(kp, a1, a2);
-    lb.lev2(kp, b1, b2);
-    la.lev1(ki, a1);
-    lb.lev1(ki, b1);
+    la.lev3(kat(kt + 2), a2, av);
+    lb.lev3(kat(kt + 2), b2, bv);
+    la.lev2(kat(kt + 3), a1, a2);
+    lb.lev2(kat(kt + 3), b1, b2);
+    la.lev1(kat(kt + 4), a1);
+    lb.lev1(kat(kt + 4), b1);
     __builtin_amdgcn_sched_barrier(0);  // issue the loads before the next MFMA block
   }
 }
@@ -368,7 +367,7 @@ template <typename T, bool COH> struct LoadGather {
   const int64_t *kcol, *kpos;  // node-local per-row tables (global)
   const int32_t *posarr;
   const int64_t *rt_col, *rt_pos;  // LDS copies for rows i0 .. i0+63
-  int c, i0;
+  int c, kend, i0;  // rows and columns of X_{C,C} < c; contraction indices < kend
   __device__ __forceinline__ void coords(int k0, int m, int &i, int &kk) const {
     constexpr int TK = Planes<T>::TK;
     const int e = threadIdx.x + NT * m;
@@ -388,7 +387,7 @@ template <typename T, bool COH> struct LoadGather {
   __device__ __forceinline__ int64_t mask(int k0, int m) const {
     int i, kk;
     coords(k0, m, i, kk);
-    return opaque_mask(i0 + i < c && k0 + kk < c);
+    return opaque_mask(i0 + i < c && k0 + kk < kend);
   }
   // Each level loads unconditionally (clamped indices, opaque masks) and
   // keeps the raw results; they are combined one level later.

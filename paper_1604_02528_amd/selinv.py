@@ -27,7 +27,7 @@ def _bytes(nbytes, device):
 
 class SelInv:
     def __init__(self, n, colptr, rowind, perm=None, *, dtype="f64", batch=1, cap=256, relax=0.0,
-                 sched="persistent", nthreads=0, watchdog_ms=0, dense_min_c=0, dense_max_bytes=0, device="cuda"):
+                 sched="persistent", nthreads=0, watchdog_ms=0, dense_min_c=0, dense_max_bytes=0, split_min_k=0, device="cuda"):
         self.n = int(n)
         self.is_complex = dtype in ("c128", "complex128", torch.complex128)
         self.batch = int(batch)
@@ -42,6 +42,7 @@ class SelInv:
         o.watchdog_ms = int(watchdog_ms)
         o.dense_min_c = int(dense_min_c)
         o.dense_max_bytes = int(dense_max_bytes)
+        o.split_min_k = int(split_min_k)
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         self._rowind = np.ascontiguousarray(rowind, dtype=np.int64)
         self._perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)

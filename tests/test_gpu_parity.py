@@ -20,19 +20,23 @@ CASES = [
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("split", [0, 64], ids=["split_default", "split_64"])
 @pytest.mark.parametrize("dense", [0, 65, -1], ids=["dense_default", "dense_all", "gather_only"])
 @pytest.mark.parametrize("sched", ["levels", "persistent"])
 @pytest.mark.parametrize("name,scale,batch,relax", CASES)
-def test_selinv_matches_oracle(name, scale, batch, relax, sched, dense):
+def test_selinv_matches_oracle(name, scale, batch, relax, sched, dense, split):
     """dense: threshold on |C(K)| for the dense X_{C,C} buffer (0 = library
-    default, 65 = every node with more than one row tile, -1 = never), so both
-    the gathered and the dense GEMM-1 operand paths are compared."""
+    default, 65 = every node with more than one row tile, -1 = never); split:
+    shortest contraction part of a split GEMM-1 tile (0 = library default,
+    64 = split every node that has too few tiles), so the gathered and dense
+    operand paths and the split-contraction path are all compared."""
     from paper_1604_02528_amd import SelInv
 
     w = workload(name, scale, batch)
-    print(f"case {name} scale={scale} batch={batch} relax={relax} sched={sched} dense={dense}", flush=True)
+    print(f"case {name} scale={scale} batch={batch} relax={relax} sched={sched} dense={dense} split={split}",
+          flush=True)
     S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128" if w.is_complex else "f64", batch=w.batch,
-               cap=w.cap, relax=relax, sched=sched, watchdog_ms=20000, dense_min_c=dense)
+               cap=w.cap, relax=relax, sched=sched, watchdog_ms=20000, dense_min_c=dense, split_min_k=split)
     S.factor(w.values)
     S.run()
     S.sync()
