@@ -44,29 +44,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def gpu_leg(w, relax, steps, warmup, sched="levels", replicate=False):
-    """replicate: factor matrix 0 only and copy its LDL^T panels to every batch
-    slot (the traversal does the same work for any values; used where the
-    host factorization of the whole batch would take minutes)."""
+def timed_steps(S, ldlt, steps, warmup):
+    """warmup + steps passes of selinv_normalize + selinv_run on one stream,
+    HIP events around each call; returns wall seconds and per-step times."""
     import torch
 
-    from paper_1604_02528_amd import SelInv, capi
+    from paper_1604_02528_amd import capi
 
-    dt = "c128" if w.is_complex else "f64"
-    t0 = time.perf_counter()
-    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=w.batch, cap=w.cap, relax=relax, sched=sched)
-    t_an = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    if replicate and w.batch > 1:
-        S1 = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=1, cap=w.cap, relax=relax, sched=sched)
-        one = torch.from_numpy(S1.factor_host(w.values[:1])).to("cuda")
-        S1.close()
-        ldlt = one.expand(w.batch, -1).contiguous()
-        del one
-    else:
-        ldlt = torch.from_numpy(S.factor_host(w.values)).to("cuda")
-    t_fac = time.perf_counter() - t0
-    S._alloc(False)
     stream = torch.cuda.current_stream()
     h = S.h
 
@@ -93,12 +77,117 @@ def gpu_leg(w, relax, steps, warmup, sched="levels", replicate=False):
     S.sync()
     t_norm = np.array([a.elapsed_time(b) for a, b, _ in evs]) * 1e-3
     t_run = np.array([b.elapsed_time(c) for _, b, c in evs]) * 1e-3
-    X = S.to_host("x") if not replicate else None
+    return wall, t_norm, t_run
+
+
+def factor_on_device(w, relax, sched, batch, replicate):
+    """LDL^T panels on the device for `batch` matrices (host factorization,
+    outside every timed region).  replicate: factor matrix 0 only and copy its
+    panels to every batch slot (the traversal does the same work for any
+    values; used where the host factorization of the whole batch takes
+    minutes)."""
+    import torch
+
+    from paper_1604_02528_amd import SelInv
+
+    dt = "c128" if w.is_complex else "f64"
+    if replicate and batch > 1:
+        S1 = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=1, cap=w.cap, relax=relax, sched=sched)
+        one = torch.from_numpy(S1.factor_host(w.values[:1])).to("cuda")
+        S1.close()
+        ldlt = one.expand(batch, -1).contiguous()
+        del one
+        return ldlt
+    S1 = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=batch, cap=w.cap, relax=relax, sched=sched)
+    out = torch.from_numpy(S1.factor_host(w.values[:batch])).to("cuda")
+    S1.close()
+    return out
+
+
+def gpu_leg(w, relax, steps, warmup, sched="levels", replicate=False, batch=None, want_x=False):
+    from paper_1604_02528_amd import SelInv
+
+    batch = w.batch if batch is None else batch
+    dt = "c128" if w.is_complex else "f64"
+    t0 = time.perf_counter()
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=batch, cap=w.cap, relax=relax, sched=sched)
+    t_an = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ldlt = factor_on_device(w, relax, sched, batch, replicate)
+    t_fac = time.perf_counter() - t0
+    S._alloc(False)
+    wall, t_norm, t_run = timed_steps(S, ldlt, steps, warmup)
+    X = S.to_host("x") if want_x else None
     sym = S.symbolic()
+    del ldlt
     return {
         "S": S, "X": X, "sym": sym, "wall": wall, "t_norm": t_norm, "t_run": t_run,
         "t_analyze": t_an, "t_factor": t_fac,
     }
+
+
+def summary(w, g, steps, name):
+    sym = g["sym"]
+    flops = sym["flops_exact"] * w.batch
+    ms_step = g["wall"] / steps * 1e3
+    t_run = float(np.mean(g["t_run"]))
+    return {
+        "workload": WORKLOADS[name], "dtype": "c128" if w.is_complex else "f64", "batch": w.batch,
+        "gflops": round(flops / (ms_step * 1e-3) / 1e9, 2),
+        "pct_fp64_mfma_peak": round(100.0 * flops / (ms_step * 1e-3) / (PEAK_FP64_TFLOPS * 1e12), 3),
+        "ms_per_step": round(ms_step, 4), "s_per_solve": ms_step * 1e-3 / w.batch,
+        "selinv_run_ms": round(t_run * 1e3, 4), "normalize_ms": round(float(np.mean(g["t_norm"])) * 1e3, 4),
+        "traversal_tflops": round(flops / t_run / 1e12, 4),
+        "traversal_frac_of_peak": round(flops / t_run / 1e12 / PEAK_FP64_TFLOPS, 5),
+        "flops_per_solve": sym["flops_exact"], "nsuper": sym["nsuper"], "depth": sym["depth"],
+        "t_factor_host_s": round(g["t_factor"], 2),
+    }
+
+
+def largest_3d_leg(relax, sched):
+    """C5: 8 complex128 shifts of a 64^3 27-point stencil in one batched run."""
+    import torch
+
+    from workloads import config
+
+    w = config("C5")
+    g = gpu_leg(w, relax, 2, 1, sched, replicate=True)
+    out = summary(w, g, 2, "C5")
+    out["note"] = ("LDL^T panels of shift 0 copied to all 8 batch slots (host factorization outside the timed "
+                   "region); the traversal does the full 8-shift work")
+    g["S"].close()
+    del g
+    torch.cuda.empty_cache()
+    log(f"C5: {out['gflops']} GFLOP/s ({out['pct_fp64_mfma_peak']}% of FP64 MFMA peak), step {out['ms_per_step']} ms")
+    return out
+
+
+def batched_leg(relax, sched):
+    """C3: 32 complex128 shifts in one launch vs 32 single-shift runs."""
+    import torch
+
+    from workloads import config
+
+    w = config("C3")
+    g = gpu_leg(w, relax, 3, 1, sched)
+    out = summary(w, g, 3, "C3")
+    g["S"].close()
+    del g
+    torch.cuda.empty_cache()
+    # 32 sequential single-shift solves (normalize + run each), same pattern
+    from paper_1604_02528_amd import SelInv
+
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128", batch=1, cap=w.cap, relax=relax, sched=sched)
+    ldlt = factor_on_device(w, relax, sched, 1, False)
+    S._alloc(False)
+    wall, _, _ = timed_steps(S, ldlt, 3 * w.batch, w.batch)
+    S.close()
+    seq_ms = wall / 3 * 1e3  # per 32 sequential solves
+    out["sequential_ms_per_32_solves"] = round(seq_ms, 4)
+    out["batched_vs_sequential_speedup"] = round(seq_ms / out["ms_per_step"], 3)
+    log(f"C3: batched {out['ms_per_step']} ms vs 32 sequential {seq_ms:.3f} ms "
+        f"(x{out['batched_vs_sequential_speedup']})")
+    return out
 
 
 def cpu_leg(w, relax, reps=3):
@@ -131,6 +220,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--sched", default="levels", choices=["persistent", "levels"])
     ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C5"])
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the C3 batched-vs-sequential and C5 (largest 3-D case) legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run its own "
@@ -144,11 +235,11 @@ def main():
     w = config(args.workload)
     replicate = args.workload == "C5"
     log(f"workload {args.workload}: N={w.n} nnz(A)={w.nnz} batch={w.batch} relax={args.relax}")
-    g = gpu_leg(w, args.relax, args.steps, args.warmup, args.sched, replicate)
     if args.workload != "C2":
         args.no_cpu = True
-    sym = g["sym"]
-    flops = sym["flops_exact"] * w.batch
+    g = gpu_leg(w, args.relax, args.steps, args.warmup, args.sched, replicate, want_x=not args.no_cpu)
+    sm = summary(w, g, args.steps, args.workload)
+    flops = g["sym"]["flops_exact"] * w.batch
     ms_step = g["wall"] / args.steps * 1e3
     value = flops / (ms_step * 1e-3) / 1e9
     t_run = float(np.mean(g["t_run"]))
@@ -166,6 +257,15 @@ def main():
                          "with the same supernode partition, median of 3, factorization excluded",
                "seconds": c["t"]}
         log(f"oracle Alg. 1: {c['t']:.2f} s on {c['threads']} threads; GPU vs oracle max-norm rel err {err:.2e}")
+    g["S"].close()
+    del g
+    extras = {}
+    if args.workload == "C2" and not args.no_extras:
+        import torch
+
+        torch.cuda.empty_cache()
+        extras["batched"] = batched_leg(args.relax, args.sched)
+        extras["largest_3d"] = largest_3d_leg(args.relax, args.sched)
     out = {
         "metric": "selinv FP64 GFLOP/s (% MFMA peak) + s/solve; batched 32-shift & adjoint vs plain",
         "value": round(value, 2),
@@ -184,23 +284,23 @@ def main():
                 "; LDL^T panels of shift 0 copied to all 8 batch slots (host factorization outside the "
                 "timed region)" if replicate else ""),
             "supernode_cap": w.cap, "relax": args.relax, "schedule": args.sched,
-            "nsuper": sym["nsuper"], "nnzL": sym["nnzL"], "depth": sym["depth"],
-            "flops_per_solve": sym["flops_exact"], "flops_partition_in_use": sym["flops"],
+            "nsuper": sm["nsuper"], "depth": sm["depth"],
+            "flops_per_solve": sm["flops_per_solve"],
         },
         "pct_fp64_mfma_peak": round(100.0 * value / (PEAK_FP64_TFLOPS * 1e3), 3),
         "s_per_solve": ms_step * 1e-3 / w.batch,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 5), "traffic": None,
-                     "kernel": ("k_items_list<double>, one launch per etree level and phase"
-                                if args.sched == "levels" else "k_persistent<double>, one launch"),
-                     "selinv_run_ms": t_run * 1e3,
+                     "kernel": ("k_items_list, one launch per etree level and phase"
+                                if args.sched == "levels" else "k_persistent, one launch"),
+                     "selinv_run_ms": round(t_run * 1e3, 4),
                      "note": "achieved = algorithmic flops of the traversal / HIP-event time of selinv_run "
                              "(all of its launches) on the launch stream"},
-        "normalize_ms": t_norm * 1e3,
+        "normalize_ms": round(t_norm * 1e3, 4),
         "max_rel_err_vs_oracle": err,
-        "t_analyze_s": g["t_analyze"],
-        "t_factor_host_s": g["t_factor"],
+        "t_factor_host_s": round(sm["t_factor_host_s"], 2),
         "cpu_baseline": cpu,
+        **extras,
     }
     print(json.dumps(out), flush=True)
 
