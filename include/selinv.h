@@ -198,18 +198,32 @@ selinv_status selinv_extract(const selinv_ctx *h, const void *x_dev, void *work_
                              void *stream);
 
 /*
- * selinv_backward -- adjoint of selinv_run composed with the factorization.
- *   xbar_dev: dloss/dx for every stored selected value x_ij = (B^{-1})_ij
- *   with (i, j) in the pattern of L, i >= j, in the panel layout (the strict
- *   upper triangle of each top block is ignored).  It is overwritten (used as
- *   accumulation space).
- *   abar_dev: dloss/da for A's stored lower values ([batch][nnz(A)], a stored
- *   off-diagonal value stands for both (i,j) and (j,i)).
- * Needs dtilde_dev from selinv_factor.  R64 only.  Asynchronous.
+ * selinv_scatter -- the transpose of selinv_extract: panel_dev (panel layout,
+ * [batch][panel_elems] scalars) is zeroed and vals_dev[l][e] (on A's stored
+ * lower pattern, [batch][nnz(A)]) is written at the position of entry e.
+ * Used to turn a gradient with respect to the extracted entries into the
+ * xbar of selinv_backward.  Asynchronous on `stream`.
  */
-selinv_status selinv_backward(selinv_ctx *h, const void *panels_dev, const void *x_dev,
-                              const void *dtilde_dev, void *xbar_dev, void *work_dev, void *abar_dev,
-                              void *stream);
+selinv_status selinv_scatter(const selinv_ctx *h, const void *vals_dev, void *work_dev, void *panel_dev,
+                             void *stream);
+
+/*
+ * selinv_backward -- adjoint of selected inversion (not in the paper; reverse
+ * mode through Alg. 1 and the block LDL^T of Section 2.3).  FP64 only.
+ *   xbar_dev [batch][panel_elems] (panel layout): dloss/dx for the stored
+ *     selected entries (top blocks: lower triangle incl. diagonal; the strict
+ *     upper triangle of every top block is ignored).  Overwritten: used as the
+ *     accumulator of the reverse sweep.
+ *   abar_dev [batch][nnz(A)]: dloss/da for A's stored lower values, original
+ *     indexing (off-diagonal values stand for both (i, j) and (j, i)).
+ * Needs the panels and x of a completed selinv_factor (with dtilde_dev) and
+ * selinv_run, and the same work buffer.  Runs the level schedule (R1 leaves to
+ * root with FP64 atomic scatter-adds, then R3 root to leaves); asynchronous on
+ * `stream`.  Errors: SELINV_ESTATE (before factor), SELINV_EUNSUPPORTED
+ * (complex), SELINV_EINVAL (null buffer).
+ */
+selinv_status selinv_backward(selinv_ctx *h, const void *panels_dev, const void *x_dev, const void *dtilde_dev,
+                              void *xbar_dev, void *work_dev, void *abar_dev, void *stream);
 
 /*
  * selinv_check_plan -- host replay of the persistent schedule's protocol on

@@ -9,7 +9,8 @@ fails loudly if it has not been built.
 
 from .capi import load as _load
 from .selinv import SelInv  # noqa: F401
+from .autograd import SelInvFunction  # noqa: F401
 
 _load()
 
-__all__ = ["SelInv"]
+__all__ = ["SelInv", "SelInvFunction"]

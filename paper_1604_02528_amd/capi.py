@@ -23,7 +23,8 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "EPATTERN", 3: "ESINGULAR", 4: "ENOMEM", 5: "
 
 EXPORTED = (
     "selinv_default_opts", "selinv_version", "selinv_analyze", "selinv_symbolic", "selinv_sizes",
-    "selinv_factor", "selinv_normalize", "selinv_factor_host", "selinv_run", "selinv_extract", "selinv_backward",
+    "selinv_factor", "selinv_normalize", "selinv_factor_host", "selinv_run", "selinv_extract", "selinv_scatter",
+    "selinv_backward",
     "selinv_logdet", "selinv_check_plan", "selinv_trace", "selinv_items", "selinv_sync", "selinv_last_error", "selinv_error_info", "selinv_destroy",
 )
 
@@ -84,6 +85,7 @@ def load():
         "selinv_factor_host": (C.c_int, [vp, vp, vp]),
         "selinv_run": (C.c_int, [vp, vp, vp, vp, vp]),
         "selinv_extract": (C.c_int, [vp, vp, vp, vp, vp]),
+        "selinv_scatter": (C.c_int, [vp, vp, vp, vp, vp]),
         "selinv_backward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "selinv_logdet": (C.c_int, [vp, vp]),
         "selinv_check_plan": (C.c_int, [vp]),
@@ -177,6 +179,10 @@ def selinv_run(h, panels, x, work, stream):
 
 def selinv_extract(h, x, work, out, stream):
     check(h, load().selinv_extract(h, ptr(x), ptr(work), ptr(out), stream))
+
+
+def selinv_scatter(h, vals, work, panel, stream):
+    check(h, load().selinv_scatter(h, ptr(vals), ptr(work), ptr(panel), stream))
 
 
 def selinv_backward(h, panels, x, dtilde, xbar, work, abar, stream):

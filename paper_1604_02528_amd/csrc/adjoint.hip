@@ -1,13 +1,296 @@
-// Adjoint kernels (placeholder until the reverse sweep lands).
+// Adjoint of the selected inversion (reverse mode), FP64 on gfx950.
+//
+// Not in the paper.  A loss depends on the stored lower selected entries
+// x_pq = (A^{-1})_pq on the pattern F of L; the caller passes W_pq =
+// dloss/dx_pq in the panel layout (stored-value convention: an off-diagonal
+// value stands for (p, q) and (q, p)).  The gradient with respect to the
+// stored values of A is G_ij (i = j) or 2 G_ij (i != j), G = -X W_s X,
+// W_s = (W + W^T)/2.  It is computed node by node by reversing the forward
+// traversal (Alg. 1 with the LDL^T normalization of Section 2.3) and the
+// block LDL^T factorization, re-reading X instead of storing per-node
+// intermediates.  In stored-value units (E = Dt^{-1}, Lhat, X_{C,K} = Y):
+//
+//  R1, leaves -> root (a node starts once every descendant has pushed into W):
+//    Tbar = sym(W_KK) (diagonal kept, off-diagonal halved and mirrored)
+//    Zbar = W_{C,K} - Lhat Tbar
+//    Lhatbar = -(X_{C,C} Zbar + Y Tbar)
+//    W[ancestors] += -(Zbar Lhat^T + Lhat Zbar^T) on the lower part of C(K) x C(K)
+//                    (halved on the diagonal), through the ancestor index maps
+//  R2: Dtbar0 = -E Tbar E
+//  R3, root -> leaves, Sbar the adjoint of the trailing Schur complements:
+//    M = Sbar_{C,C} Lhat,  Lb = Lhatbar - 2 M Dt,  N = Lb E
+//    Sbar_{C,K} = N / 2,  Sbar_KK = sym(Dtbar0 - Lhat^T (M + N))
+//  Output: Abar = Sbar on A's pattern, doubled off the diagonal.
+//
+// Every step is a 64 x 64 tile on the MFMA machinery of the forward sweep;
+// the scatter-add uses hardware FP64 atomics (summation order, and hence the
+// last bits, may differ between runs).
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+
+#include "items.hpp"
 #include "plan.hpp"
+#include "tile.hpp"
 
 namespace selinv {
+namespace {
 
-hipError_t launch_backward(const DevPlan &, const DevPlan *, const LaunchAux &, const void *, const void *,
-                           const void *, void *, void *, hipStream_t) {
-  return hipErrorNotSupported;
+struct BCtx {
+  Ctx<double> cx;        // Lp normalized panels, Xp the forward X, Pp partials, Gp dense buffers
+  double *W;             // stored-value gradient on F, accumulated in place
+  double *Z, *L, *S;     // panel-layout scratch: Zbar then M; Lhatbar then Lb; Sbar
+  double *TB, *FB, *DB;  // s x s scratch: Tbar; F = Tbar E; Dtbar0
+  const double *DT;      // Dt = L_KK D_K L_KK^T
+};
+
+struct Geo {
+  int s, c, ld;
+  int64_t off, sq, rp, goff;
+  int ldg;
+};
+
+__device__ __forceinline__ Geo geo(const DevPlan &pl, int K) {
+  Geo g;
+  g.s = uniform(gp(pl.node_s)[K]);
+  g.c = uniform(gp(pl.node_c)[K]);
+  g.ld = g.s + g.c;
+  g.off = gp(pl.node_off)[K];
+  g.sq = gp(pl.node_sq)[K];
+  g.rp = gp(pl.node_rowptr)[K];
+  g.goff = gp(pl.node_goff)[K];
+  g.ldg = gp(pl.node_ldg)[K];
+  return g;
+}
+
+// dst[(j0 + j) * ld + i0 + i] = f(i0 + i, j0 + j, acc(i, j)) for i0 + i < rows,
+// j0 + j < cols, through LDS so that the stores coalesce.
+template <class F>
+__device__ void store_tile(const Acc<double> &acc, double *smem, double *dst, int64_t ld, int i0, int j0, int rows,
+                           int cols, F f) {
+  acc_to_lds<double>(acc, smem);
+  lds_barrier();
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int i = e & 63, j = e >> 6;
+    if (i0 + i < rows && j0 + j < cols) {
+      const int64_t q = (int64_t)(j0 + j) * ld + i0 + i;
+      dst[q] = f(q, smem[j * PITCH + i]);
+    }
+  }
+  lds_barrier();
+}
+
+using DA = LoadDenseA<double, DenseTK<double>::TK>;
+using DB = LoadDenseB<double, DenseTK<double>::TK>;
+using DBT = LoadDenseBT<double, DenseTK<double>::TK>;
+
+// acc = X_{C,C}[tile rows, :] B[:, tile cols] with X_{C,C} gathered from Src (panel
+// layout) or read from the node's dense buffer; B = the c x s bottom block of a
+// panel-layout array Bp.
+__device__ void gemm_cc(const BCtx &bx, const Geo &g, const double *Src, const double *Bp, int i0, int j0,
+                        double *smem, int64_t *rt, Acc<double> &acc) {
+  const DevPlan &pl = *bx.cx.pl;
+  if (uniform(g.goff >= 0 ? 1 : 0)) {
+    DA la{bx.cx.Gp + g.goff, g.ldg, g.c, g.c, i0};
+    DB lb{Bp, g.off, g.ld, g.s, g.c, j0, g.s};
+    gemm_dense<double>(0, g.c, la, lb, smem, acc);
+  } else {
+    if (threadIdx.x < 64) {
+      const int ig = i0 + threadIdx.x;
+      rt[threadIdx.x] = gp(pl.kcol)[g.rp + (ig < g.c ? ig : 0)];
+      rt[64 + threadIdx.x] = gp(pl.kpos)[g.rp + (ig < g.c ? ig : 0)];
+    }
+    lds_barrier();
+    LoadGather<double, false> la{Src, pl.kcol + g.rp, pl.kpos + g.rp, pl.posarr, rt, rt + 64, g.c, g.c, i0};
+    LoadPanelK<double, false> lb{Bp, g.off, g.ld, g.s, 0, g.c, j0, g.s};
+    gemm_tile<double>(0, g.c, la, lb, smem, acc);
+  }
+}
+
+__device__ void bi_t(const BCtx &bx, const Geo &g, int a, int b) {
+  const int i0 = a * 64, j0 = b * 64;
+  const double *Wk = bx.W + g.off;
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int i = i0 + (e & 63), j = j0 + (e >> 6);
+    if (i < g.s && j < g.s) {
+      const double w = i >= j ? Wk[(int64_t)j * g.ld + i] : Wk[(int64_t)i * g.ld + j];
+      bx.TB[g.sq + (int64_t)j * g.s + i] = i == j ? w : 0.5 * w;
+    }
+  }
+}
+
+__device__ void bi_z(const BCtx &bx, const Geo &g, int a, int b, double *smem) {
+  const int i0 = a * 64, j0 = b * 64;
+  Acc<double> acc;
+  gemm_dense<double>(0, g.s, DA{bx.cx.Lp + g.off + g.s, g.ld, g.c, g.s, i0}, DB{bx.TB + g.sq, 0, g.s, 0, g.s, j0, g.s},
+                     smem, acc);
+  const double *Wb = bx.W + g.off + g.s;
+  store_tile(acc, smem, bx.Z + g.off + g.s, g.ld, i0, j0, g.c, g.s,
+             [&](int64_t q, double v) { return Wb[q] - v; });
+}
+
+__device__ void bi_l(const BCtx &bx, const Geo &g, int a, int b, double *smem, int64_t *rt) {
+  const int i0 = a * 64, j0 = b * 64;
+  Acc<double> acc;
+  gemm_cc(bx, g, bx.cx.Xp, bx.Z, i0, j0, smem, rt, acc);  // X_{C,C} Zbar
+  gemm_dense<double>(0, g.s, DA{bx.cx.Xp + g.off + g.s, g.ld, g.c, g.s, i0}, DB{bx.TB + g.sq, 0, g.s, 0, g.s, j0, g.s},
+                     smem, acc, true);  // + Y Tbar
+  store_tile(acc, smem, bx.L + g.off + g.s, g.ld, i0, j0, g.c, g.s, [](int64_t, double v) { return -v; });
+}
+
+// Rows 64a.., columns 64a2.. (a >= a2) of Zbar Lhat^T + Lhat Zbar^T, subtracted
+// from the stored-value gradient of the ancestors' entries of X_{C,C}.
+__device__ void bi_sc(const BCtx &bx, const Geo &g, int a, int a2, double *smem) {
+  const DevPlan &pl = *bx.cx.pl;
+  const int i0 = a * 64, k0 = a2 * 64;
+  const double *Zb = bx.Z + g.off + g.s, *Lh = bx.cx.Lp + g.off + g.s;
+  Acc<double> acc;
+  gemm_dense<double>(0, g.s, DA{Zb, g.ld, g.c, g.s, i0}, DBT{Lh, g.ld, g.s, k0, g.c}, smem, acc);
+  gemm_dense<double>(0, g.s, DA{Lh, g.ld, g.c, g.s, i0}, DBT{Zb, g.ld, g.s, k0, g.c}, smem, acc, true);
+  acc_to_lds<double>(acc, smem);
+  lds_barrier();
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int i = e & 63, k = e >> 6;
+    const int ig = i0 + i, kg = k0 + k;
+    if (ig < g.c && kg < g.c && ig >= kg) {
+      const double v = smem[k * PITCH + i];
+      const int64_t addr = gp(pl.kcol)[g.rp + kg] + gp(pl.posarr)[gp(pl.kpos)[g.rp + kg] + ig];
+      unsafeAtomicAdd(bx.W + addr, ig == kg ? -0.5 * v : -v);
+    }
+  }
+  lds_barrier();
+}
+
+__device__ void bi_f(const BCtx &bx, const Geo &g, int a, int b, double *smem) {
+  const int i0 = a * 64, j0 = b * 64;
+  Acc<double> acc;
+  gemm_dense<double>(0, g.s, DA{bx.TB + g.sq, g.s, g.s, g.s, i0}, DB{bx.cx.Lp, g.off, g.ld, 0, g.s, j0, g.s}, smem,
+                     acc);
+  store_tile(acc, smem, bx.FB + g.sq, g.s, i0, j0, g.s, g.s, [](int64_t, double v) { return v; });
+}
+
+__device__ void bi_d0(const BCtx &bx, const Geo &g, int a, int b, double *smem) {
+  const int i0 = a * 64, j0 = b * 64;
+  Acc<double> acc;
+  gemm_dense<double>(0, g.s, DA{bx.cx.Lp + g.off, g.ld, g.s, g.s, i0}, DB{bx.FB + g.sq, 0, g.s, 0, g.s, j0, g.s},
+                     smem, acc);
+  store_tile(acc, smem, bx.DB + g.sq, g.s, i0, j0, g.s, g.s, [](int64_t, double v) { return -v; });
+}
+
+__device__ void bi_m(const BCtx &bx, const Geo &g, int a, int b, double *smem, int64_t *rt) {
+  const int i0 = a * 64, j0 = b * 64;
+  Acc<double> acc;
+  gemm_cc(bx, g, bx.S, bx.cx.Lp, i0, j0, smem, rt, acc);  // Sbar_{C,C} Lhat
+  store_tile(acc, smem, bx.Z + g.off + g.s, g.ld, i0, j0, g.c, g.s, [](int64_t, double v) { return v; });
+}
+
+__device__ void bi_lb(const BCtx &bx, const Geo &g, int a, int b, double *smem) {
+  const int i0 = a * 64, j0 = b * 64;
+  Acc<double> acc;
+  gemm_dense<double>(0, g.s, DA{bx.Z + g.off + g.s, g.ld, g.c, g.s, i0}, DB{bx.DT + g.sq, 0, g.s, 0, g.s, j0, g.s},
+                     smem, acc);
+  double *Lb = bx.L + g.off + g.s;
+  store_tile(acc, smem, Lb, g.ld, i0, j0, g.c, g.s, [&](int64_t q, double v) { return Lb[q] - 2.0 * v; });
+}
+
+__device__ void bi_n(const BCtx &bx, const Geo &g, int K, int a, int b, double *smem) {
+  const int i0 = a * 64, j0 = b * 64;
+  Acc<double> acc;
+  gemm_dense<double>(0, g.s, DA{bx.L + g.off + g.s, g.ld, g.c, g.s, i0}, DB{bx.cx.Lp, g.off, g.ld, 0, g.s, j0, g.s},
+                     smem, acc);  // N = Lb E
+  store_tile(acc, smem, bx.S + g.off + g.s, g.ld, i0, j0, g.c, g.s, [](int64_t, double v) { return 0.5 * v; });
+  // acc <- -(M + N) in the accumulator layout, then the row tile's share of
+  // Lhat^T (M + N) into the partial products
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w & 1, wj = w >> 1;
+  const double *M = bx.Z + g.off + g.s;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 32 * wi + 16 * bi + 4 * v + (lane >> 4);
+        const int j = j0 + 32 * wj + 16 * bj + (lane & 15);
+        const int64_t m = opaque_mask(i < g.c && j < g.s);
+        const double mv = masked(M[((int64_t)j * g.ld + i) & m], m);
+        acc.v[0][bi][bj][v] = -(mv + masked(acc.v[0][bi][bj][v], m));
+      }
+  gemm2_partial<double, false>(bx.cx, K, a, b, acc, smem);
+}
+
+__global__ void __launch_bounds__(NT, 2)
+    k_back_items(const DevPlan *__restrict__ plp, const double *panels, const double *x, const double *dt,
+                 double *xbar, int32_t first, int32_t count) {
+  const DevPlan &pl = *plp;
+  __shared__ double smem[smem_doubles<double>()];
+  __shared__ int64_t rt[128];
+  const int64_t g0 = blockIdx.x;
+  const int64_t l = g0 / count;
+  const Item it = uniform(gload(pl.bitems + first + (g0 - l * count)));
+  const int64_t pe = pl.panel_elems, sq = pl.sq_elems;
+  BCtx bx;
+  bx.cx = Ctx<double>{&pl, panels + l * pe, const_cast<double *>(x) + l * pe,
+                      static_cast<double *>(pl.part) + l * pl.part_elems,
+                      static_cast<double *>(pl.gbuf) + l * pl.g_elems, nullptr};
+  bx.W = xbar + l * pe;
+  bx.Z = static_cast<double *>(pl.adj_z) + l * pe;
+  bx.L = static_cast<double *>(pl.adj_l) + l * pe;
+  bx.S = static_cast<double *>(pl.adj_s) + l * pe;
+  bx.TB = static_cast<double *>(pl.adj_t) + l * sq;
+  bx.FB = static_cast<double *>(pl.adj_f) + l * sq;
+  bx.DB = static_cast<double *>(pl.adj_d) + l * sq;
+  bx.DT = dt + l * sq;
+  const Geo g = geo(pl, it.K);
+  switch (it.type) {
+    case BI_T: bi_t(bx, g, it.a, it.b); break;
+    case BI_G: do_gtile<double>(bx.cx, it.K, it.a, it.b, smem, bx.cx.Xp); break;
+    case BI_Z: bi_z(bx, g, it.a, it.b, smem); break;
+    case BI_L: bi_l(bx, g, it.a, it.b, smem, rt); break;
+    case BI_SC: bi_sc(bx, g, it.a, it.b, smem); break;
+    case BI_F: bi_f(bx, g, it.a, it.b, smem); break;
+    case BI_D0: bi_d0(bx, g, it.a, it.b, smem); break;
+    case BI_SG: do_gtile<double>(bx.cx, it.K, it.a, it.b, smem, bx.S); break;
+    case BI_M: bi_m(bx, g, it.a, it.b, smem, rt); break;
+    case BI_LB: bi_lb(bx, g, it.a, it.b, smem); break;
+    case BI_N: bi_n(bx, g, it.K, it.a, it.b, smem); break;
+    case BI_DF:
+      dtile_core<double, false>(bx.cx, it.K, it.a, it.b, smem, bx.DB + g.sq, g.s, bx.S + g.off, g.ld);
+      break;
+    default: break;
+  }
+}
+
+// Abar on A's pattern (stored-value convention: doubled off the diagonal).
+__global__ void k_abar(const DevPlan *__restrict__ plp, double *abar) {
+  const DevPlan &pl = *plp;
+  const int64_t total = pl.batch * pl.nnzA;
+  const double *S = static_cast<const double *>(pl.adj_s);
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = q / pl.nnzA, e = q - l * pl.nnzA;
+    const double v = S[l * pl.panel_elems + gp(pl.apos)[e]];
+    abar[q] = gp(pl.adiag)[e] ? v : 2.0 * v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_backward(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const void *panels,
+                           const void *x, const void *dt, void *xbar, void *abar, hipStream_t st) {
+  if (!pl.adj_s) return hipErrorNotSupported;
+  for (int q = 0; q < aux.nblvl; ++q) {
+    const int32_t b = aux.blvl_ptr[q], e = aux.blvl_ptr[q + 1];
+    if (e > b)
+      hipLaunchKernelGGL(k_back_items, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl,
+                         static_cast<const double *>(panels), static_cast<const double *>(x),
+                         static_cast<const double *>(dt), static_cast<double *>(xbar), b, e - b);
+  }
+  const int64_t total = pl.batch * pl.nnzA;
+  unsigned grid = (unsigned)((total + 255) / 256);
+  if (grid > 65536u) grid = 65536u;
+  if (grid == 0) grid = 1;
+  hipLaunchKernelGGL(k_abar, dim3(grid), dim3(256), 0, st, dpl, static_cast<double *>(abar));
+  return hipGetLastError();
 }
 
 }  // namespace selinv

@@ -26,6 +26,8 @@ hipError_t launch_extract(const DevPlan &pl, const DevPlan *dpl, bool cplx_, con
 int persistent_blocks_per_cu(bool cplx_);
 hipError_t launch_backward(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const void *panels,
                            const void *x, const void *dt, void *xbar, void *abar, hipStream_t st);
+hipError_t launch_scatter(const DevPlan &pl, const DevPlan *dpl, bool cplx_, const void *vals, void *panel,
+                          hipStream_t st);
 }  // namespace selinv
 
 using namespace selinv;
@@ -49,6 +51,9 @@ struct HostPlan {
   int64_t g_elems = 0;
   int64_t dense_min_c = 0;  // threshold in use (INT64_MAX: no dense buffers)
   std::vector<int32_t> order;  // ticket order of the persistent schedule (all matrices)
+  std::vector<Item> bitems;    // adjoint items in (sweep, depth, phase) order
+  std::vector<int32_t> blvl_ptr;  // [nblvl + 1] ranges of bitems launched together
+  bool adjoint = false;        // adjoint scratch allocated (FP64 only)
   std::vector<int32_t> lvl_items, lvl_ptr;
   std::vector<int2> chunks, rblocks;
   std::vector<int4> sq_tiles;
@@ -61,7 +66,7 @@ struct HostPlan {
     int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
         nph, node_split, node_kchunk, node_yoff, node_goff, node_ldg, node_parent, order, lvl_items, chunks, rblocks,
         sq_tiles,
-        apos, adiag, plan, linv, dinv, part, gbuf, ypart, cnt, ctrl, end;
+        apos, adiag, bitems, plan, linv, dinv, part, gbuf, ypart, cnt, adj_z, adj_l, adj_s, adj_t, adj_f, adj_d, ctrl, end;
   } off{};
   int64_t tables_bytes = 0;  // [0, tables_bytes) is uploaded once
 };
@@ -358,6 +363,58 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
       }
     }
   }
+  // adjoint items: R1 leaves -> root (deepest level first), then R3 root -> leaves
+  H.bitems.clear();
+  H.blvl_ptr.assign(1, 0);
+  {
+    std::vector<std::vector<int64_t>> bydepth(S.depth);
+    for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
+    auto emit = [&](int64_t K, int32_t type) {
+      const int32_t s = H.node_s[K], c = H.node_c[K];
+      const int32_t nb = (s + kTileN - 1) / kTileN, nr = (c + kTileM - 1) / kTileM;
+      const bool dense = H.node_goff[K] >= 0;
+      switch (type) {
+        case BI_T: case BI_F: case BI_D0:
+          for (int32_t a = 0; a < nb; ++a)
+            for (int32_t b = 0; b < nb; ++b) H.bitems.push_back(Item{(int32_t)K, type, a, b});
+          break;
+        case BI_DF:
+          for (int32_t a = 0; a < nb; ++a)
+            for (int32_t b = 0; b <= a; ++b) H.bitems.push_back(Item{(int32_t)K, type, a, b});
+          break;
+        case BI_G: case BI_SG:
+          if (dense)
+            for (int32_t a = 0; a < nr; ++a)
+              for (int32_t b = 0; b <= a; ++b) H.bitems.push_back(Item{(int32_t)K, type, a, b});
+          break;
+        case BI_SC:
+          for (int32_t a = 0; a < nr; ++a)
+            for (int32_t b = 0; b <= a; ++b) H.bitems.push_back(Item{(int32_t)K, type, a, b});
+          break;
+        default:  // c x s tiles
+          for (int32_t b = 0; b < nb; ++b)
+            for (int32_t a = 0; a < nr; ++a) H.bitems.push_back(Item{(int32_t)K, type, a, b});
+      }
+    };
+    auto close = [&]() {
+      if ((int32_t)H.bitems.size() > H.blvl_ptr.back()) H.blvl_ptr.push_back((int32_t)H.bitems.size());
+    };
+    static const int32_t r1[kBackR1Phases][3] = {{BI_T, BI_G, -1}, {BI_Z, -1, -1}, {BI_L, BI_SC, BI_F}, {BI_D0, -1, -1}};
+    static const int32_t r3[kBackR3Phases][3] = {{BI_SG, -1, -1}, {BI_M, -1, -1}, {BI_LB, -1, -1}, {BI_N, -1, -1},
+                                                 {BI_DF, -1, -1}};
+    for (int64_t d = S.depth - 1; d >= 0; --d)
+      for (int ph = 0; ph < kBackR1Phases; ++ph) {
+        for (int64_t K : bydepth[d])
+          for (int q = 0; q < 3 && r1[ph][q] >= 0; ++q) emit(K, r1[ph][q]);
+        close();
+      }
+    for (int64_t d = 0; d < S.depth; ++d)
+      for (int ph = 0; ph < kBackR3Phases; ++ph) {
+        for (int64_t K : bydepth[d])
+          for (int q = 0; q < 3 && r3[ph][q] >= 0; ++q) emit(K, r3[ph][q]);
+        close();
+      }
+  }
   // normalization work lists
   H.chunks.clear();
   H.rblocks.clear();
@@ -408,6 +465,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.sq_tiles = take(16 * (int64_t)H.sq_tiles.size());
   o.apos = take(8 * (int64_t)H.apos.size());
   o.adiag = take((int64_t)H.adiag.size());
+  o.bitems = take(16 * (int64_t)H.bitems.size());
   H.tables_bytes = p;
   o.plan = take((int64_t)sizeof(DevPlan));
   o.linv = take(scalar_bytes * batch * H.sq_elems);
@@ -416,6 +474,15 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.gbuf = take(scalar_bytes * batch * H.g_elems);
   o.ypart = take(scalar_bytes * batch * H.y_elems);
   o.cnt = take(4 * kPhases * batch * ns);
+  H.adjoint = scalar_bytes == 8;
+  const int64_t pan = H.adjoint ? scalar_bytes * batch * S.panel_elems : 0;
+  const int64_t sqb = H.adjoint ? scalar_bytes * batch * H.sq_elems : 0;
+  o.adj_z = take(pan);
+  o.adj_l = take(pan);
+  o.adj_s = take(pan);
+  o.adj_t = take(sqb);
+  o.adj_f = take(sqb);
+  o.adj_d = take(sqb);
   o.ctrl = take(4 * CTRL_WORDS);
   o.end = p;
 }
@@ -510,6 +577,13 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.ypart = (void *)(b + o.ypart);
   d.y_elems = H.y_elems;
   d.cnt = (int32_t *)(b + o.cnt);
+  d.adj_z = H.adjoint ? (void *)(b + o.adj_z) : nullptr;
+  d.adj_l = H.adjoint ? (void *)(b + o.adj_l) : nullptr;
+  d.adj_s = H.adjoint ? (void *)(b + o.adj_s) : nullptr;
+  d.adj_t = H.adjoint ? (void *)(b + o.adj_t) : nullptr;
+  d.adj_f = H.adjoint ? (void *)(b + o.adj_f) : nullptr;
+  d.adj_d = H.adjoint ? (void *)(b + o.adj_d) : nullptr;
+  d.bitems = (Item *)(b + o.bitems);
   d.ctrl = (int32_t *)(b + o.ctrl);
   d.trace = (int64_t *)h->trace;
   return d;
@@ -532,6 +606,9 @@ LaunchAux make_aux(const selinv_ctx *h, void *work) {
   a.lvl_items = (const int32_t *)(b + H.off.lvl_items);
   a.lvl_ptr = H.lvl_ptr.data();
   a.nlvl = (int32_t)H.lvl_ptr.size() - 1;
+  a.blvl_items = nullptr;
+  a.blvl_ptr = H.blvl_ptr.data();
+  a.nblvl = (int32_t)H.blvl_ptr.size() - 1;
   return a;
 }
 
@@ -566,6 +643,7 @@ void build_image(selinv_ctx *h) {
   put(img, o.sq_tiles, H.sq_tiles);
   put(img, o.apos, H.apos);
   put(img, o.adiag, H.adiag);
+  put(img, o.bitems, H.bitems);
 }
 
 selinv_status ensure_uploaded(selinv_ctx *h, void *work, hipStream_t st) {
@@ -825,6 +903,21 @@ selinv_status selinv_extract(const selinv_ctx *hc, const void *x_dev, void *work
   DevPlan pl = make_devplan(h, work_dev);
   hipError_t e = launch_extract(pl, dev_plan(h, work_dev), h->is_complex(), x_dev, out_dev, st);
   if (e != hipSuccess) return hip_err(h, e, "extract launch");
+  return SELINV_OK;
+}
+
+selinv_status selinv_scatter(const selinv_ctx *hc, const void *vals_dev, void *work_dev, void *panel_dev,
+                             void *stream) {
+  selinv_ctx *h = const_cast<selinv_ctx *>(hc);
+  if (!h) return SELINV_EINVAL;
+  if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
+  if (!vals_dev || !panel_dev || !work_dev) return set_err(h, SELINV_EINVAL, "null buffer");
+  hipStream_t st = (hipStream_t)stream;
+  selinv_status ss = ensure_uploaded(h, work_dev, st);
+  if (ss != SELINV_OK) return ss;
+  DevPlan pl = make_devplan(h, work_dev);
+  hipError_t e = launch_scatter(pl, dev_plan(h, work_dev), h->is_complex(), vals_dev, panel_dev, st);
+  if (e != hipSuccess) return hip_err(h, e, "scatter launch");
   return SELINV_OK;
 }
 

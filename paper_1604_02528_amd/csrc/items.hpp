@@ -1,0 +1,407 @@
+// Work items of the selected-inversion traversal (device code shared by the
+// forward and adjoint kernels): the dense X_{C,C} gather, the GEMM-1 tile with
+// its fused share of GEMM-2, the split-tile reduction and the diagonal-block
+// tile.  See plan.hpp for the item vocabulary.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.hpp"
+#include "scalar.hpp"
+#include "tile.hpp"
+
+namespace selinv {
+
+// ---------------------------------------------------------------------------
+// Work items
+// ---------------------------------------------------------------------------
+template <typename T> struct Ctx {
+  const DevPlan *pl;
+  const T *Lp;  // normalized panels of this matrix
+  T *Xp;        // selected inverse of this matrix
+  T *Pp;        // GEMM-2 partial products of this matrix
+  T *Gp;        // dense X_{C,C} buffers of this matrix
+  T *Yp;        // partial GEMM-1 tiles of this matrix (split nodes)
+};
+
+// Block (a, b), a >= b, of X_{C,C} for a node with a dense buffer G (column
+// major, leading dimension ldg): element (i, k), i >= k, is the lower-part
+// entry Src[kcol[k] + posarr[kpos[k] + i]] of the ancestor owning column k
+// (Src: the X panels, or any array in the same panel layout); it is written
+// to G(i, k) and G(k, i).  Lanes run along i (one column k per
+// wave and step) for the gather and the G(i, k) stores; the mirror stores go
+// through an LDS transpose so that they are contiguous too.
+template <typename T>
+__device__ void do_gtile(const Ctx<T> &cx, int K, int a, int b, double *smem, const T *Src) {
+  const DevPlan &pl = *cx.pl;
+  const int c = uniform(gp(pl.node_c)[K]);
+  const int64_t rp = gp(pl.node_rowptr)[K];
+  const int ldg = gp(pl.node_ldg)[K];
+  T *G = cx.Gp + gp(pl.node_goff)[K];
+  const int i0 = a * 64, k0 = b * 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int Q = 64 * 64 / NT, QH = Q / 2;
+  for (int h = 0; h < 2; ++h) {
+    int64_t pidx[QH], base[QH], msk[QH];
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      const int kl = w + 4 * (QH * h + q), i = i0 + lane, k = k0 + kl;
+      msk[q] = opaque_mask(i < c && k < c && i >= k);
+      const int64_t kq = (int64_t)(k < c ? k : 0);
+      base[q] = gp(pl.kcol)[rp + kq];
+      pidx[q] = (gp(pl.kpos)[rp + kq] + i) & msk[q];
+    }
+    int64_t addr[QH];
+#pragma unroll
+    for (int q = 0; q < QH; ++q) addr[q] = (base[q] + (int64_t)gp(pl.posarr)[pidx[q]]) & msk[q];
+    T v[QH];
+#pragma unroll
+    for (int q = 0; q < QH; ++q) v[q] = masked(Mem<false>::ld(Src + addr[q]), msk[q]);
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      const int kl = w + 4 * (QH * h + q), i = i0 + lane, k = k0 + kl;
+      lds_put<T>(smem, lane, kl, v[q]);  // tile[i][k] at smem[k * PITCH + i]
+      if (i < c && k < c && i >= k) Mem<false>::st(G + (int64_t)k * ldg + i, v[q]);
+    }
+  }
+  lds_barrier();
+  // mirror: G(k, i) = tile[i][k], lanes along k
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int kl = e & 63, il = e >> 6, i = i0 + il, k = k0 + kl;
+    if (i < c && k < c && i > k) Mem<false>::st(G + (int64_t)i * ldg + k, lds_get<T>(smem, il, kl));
+  }
+  lds_barrier();
+}
+
+// Store -acc (a 64 x 64 tile of X_{C,K} = -X_{C,C} Lhat) into X, rows 64a..
+// of C(K) and columns 64b.. of K, through LDS so that the stores coalesce.
+template <typename T, bool COH>
+__device__ void store_xtile(const Ctx<T> &cx, int K, int a, int b, const Acc<T> &acc, double *smem) {
+  const DevPlan &pl = *cx.pl;
+  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
+  const int64_t off = gp(pl.node_off)[K];
+  const int i0 = a * 64, j0 = b * 64;
+  acc_to_lds<T>(acc, smem);
+  lds_barrier();
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int i = e & 63, j = e >> 6;
+    if (i0 + i < c && j0 + j < s)
+      Mem<COH>::st(cx.Xp + off + (int64_t)(j0 + j) * ld + s + i0 + i, SOps<T>::scale(-1.0, lds_get<T>(smem, i, j)));
+  }
+  lds_barrier();
+}
+
+// Row tile a's share of GEMM-2 (Alg. 1 step 4): P_a[:, 64b..] = Lhat[rows of
+// tile a, :]^T Y[tile a, 64b..] = -(Lhat_a^T acc), written to the partial
+// buffer (column-major s x s per row tile).  The accumulators already sit in
+// the MFMA B-operand layout for a contraction over the tile rows (register v
+// of a 16 x 16 block holds rows 4v..4v+3 of lanes l / 16).
+template <typename T, bool COH>
+__device__ void gemm2_partial(const Ctx<T> &cx, int K, int a, int b, const Acc<T> &acc, double *smem) {
+  constexpr int P = Planes<T>::P;
+  const DevPlan &pl = *cx.pl;
+  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
+  const int64_t off = gp(pl.node_off)[K];
+  const int i0 = a * 64, j0 = b * 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w & 1, wj = w >> 1;
+  const int64_t pbase = gp(pl.node_poff)[K] + (int64_t)a * s * s;
+  double *Ls = smem;  // Lhat[i0 .. i0+63, q0 .. q0+63] as Ls[p][i * PITCH + x]
+  for (int q0 = 0; q0 < s; q0 += 64) {
+    T lv[64 * 64 / NT];
+#pragma unroll
+    for (int q = 0; q < 64 * 64 / NT; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int i = e & 63, x = e >> 6;
+      lv[q] = gload(cx.Lp + off + (((int64_t)(q0 + x) * ld + s + i0 + i) & opaque_mask(i0 + i < c && q0 + x < s)));
+    }
+#pragma unroll
+    for (int q = 0; q < 64 * 64 / NT; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int i = e & 63, x = e >> 6;
+      const T v = masked(lv[q], opaque_mask(i0 + i < c && q0 + x < s));
+#pragma unroll
+      for (int p = 0; p < P; ++p) Ls[p * 64 * PITCH + i * PITCH + x] = Planes<T>::get(v, p);
+    }
+    lds_barrier();
+    d4 pacc[P][4][2];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int xb = 0; xb < 4; ++xb)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) pacc[p][xb][bj] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4) {
+        const int row = 32 * wi + 16 * bi + 4 * k4 + (lane >> 4);
+#pragma unroll
+        for (int xb = 0; xb < 4; ++xb) {
+          double af[P];
+#pragma unroll
+          for (int p = 0; p < P; ++p) af[p] = Ls[p * 64 * PITCH + row * PITCH + 16 * xb + (lane & 15)];
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) {
+            if constexpr (P == 1) {
+              pacc[0][xb][bj] = mfma16(af[0], acc.v[0][bi][bj][k4], pacc[0][xb][bj]);
+            } else {
+              pacc[0][xb][bj] = mfma16(af[0], acc.v[0][bi][bj][k4], pacc[0][xb][bj]);
+              pacc[0][xb][bj] = mfma16(-af[1], acc.v[1][bi][bj][k4], pacc[0][xb][bj]);
+              pacc[1][xb][bj] = mfma16(af[0], acc.v[1][bi][bj][k4], pacc[1][xb][bj]);
+              pacc[1][xb][bj] = mfma16(af[1], acc.v[0][bi][bj][k4], pacc[1][xb][bj]);
+            }
+          }
+        }
+      }
+    lds_barrier();
+    // sum the two row halves (wi = 0, 1) in LDS: R[p][j * PITCH + x]
+    double *R = smem;
+    for (int half = 0; half < 2; ++half) {
+      if (wi == half) {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+          for (int xb = 0; xb < 4; ++xb)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int x = 16 * xb + 4 * v + (lane >> 4);
+                const int j = 32 * wj + 16 * bj + (lane & 15);
+                double &r = R[p * 64 * PITCH + j * PITCH + x];
+                r = half == 0 ? pacc[p][xb][bj][v] : r + pacc[p][xb][bj][v];
+              }
+      }
+      lds_barrier();
+    }
+    // P = Lhat^T Y = -(Lhat^T acc)
+    for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+      const int x = e & 63, j = e >> 6;
+      if (q0 + x < s && j0 + j < s)
+        Mem<COH>::st(cx.Pp + pbase + (int64_t)(j0 + j) * s + q0 + x, SOps<T>::scale(-1.0, lds_get<T>(R, x, j)));
+    }
+    lds_barrier();
+  }
+}
+
+// GEMM-1 tile, rows 64a.. and columns 64b.. of X_{C,K} (Alg. 1 step 3):
+//   acc = X_{C,C}[tile rows, k] Lhat_{C,K}[k, tile columns], k in this part's
+// share of [0, c).  An unsplit node stores Y = -acc into X and its row tile's
+// share of GEMM-2 (step 4); a split node stores acc as a partial tile.
+template <typename T, bool COH>
+__device__ void do_ytile(const Ctx<T> &cx, int K, int a, int bp, double *smem, int64_t *rt) {
+  const DevPlan &pl = *cx.pl;
+  const int s = uniform(gp(pl.node_s)[K]), c = uniform(gp(pl.node_c)[K]), ld = s + c;
+  const int64_t off = gp(pl.node_off)[K], rp = gp(pl.node_rowptr)[K];
+  const int64_t goff = gp(pl.node_goff)[K];
+  const int b = bp & 0xffff, part = bp >> 16;
+  const int parts = uniform(gp(pl.node_split)[K]), kchunk = uniform(gp(pl.node_kchunk)[K]);
+  const int kb = part * kchunk, ke = min(c, kb + kchunk);
+  const int i0 = a * 64, j0 = b * 64;
+  Acc<T> acc;
+  if (uniform(goff >= 0 ? 1 : 0)) {  // X_{C,C} already gathered into the dense buffer
+    constexpr int TK = DenseTK<T>::TK;
+    const T *G = static_cast<const T *>(cx.Gp) + goff;
+    LoadDenseA<T, TK> la{G, gp(pl.node_ldg)[K], c, ke, i0};
+    LoadDenseB<T, TK> lb{cx.Lp, off, ld, s, ke, j0, s};
+    gemm_dense<T>(kb, ke, la, lb, smem, acc);
+  } else {
+    if (threadIdx.x < 64) {
+      const int ig = i0 + threadIdx.x;
+      rt[threadIdx.x] = gp(pl.kcol)[rp + (ig < c ? ig : 0)];
+      rt[64 + threadIdx.x] = gp(pl.kpos)[rp + (ig < c ? ig : 0)];
+    }
+    lds_barrier();
+    LoadGather<T, COH> la{cx.Xp, pl.kcol + rp, pl.kpos + rp, pl.posarr, rt, rt + 64, c, ke, i0};
+    LoadPanelK<T, false> lb{cx.Lp, off, ld, s, 0, ke, j0, s};
+    gemm_tile<T>(kb, ke, la, lb, smem, acc);
+  }
+  if (parts == 1) {
+    store_xtile<T, COH>(cx, K, a, b, acc, smem);
+    gemm2_partial<T, COH>(cx, K, a, b, acc, smem);
+    return;
+  }
+  // partial tile of a split node: Ypart[part] (column-major c x s)
+  T *Y = static_cast<T *>(cx.Yp) + gp(pl.node_yoff)[K] + (int64_t)part * c * s;
+  acc_to_lds<T>(acc, smem);
+  lds_barrier();
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int i = e & 63, j = e >> 6;
+    if (i0 + i < c && j0 + j < s) Mem<COH>::st(Y + (int64_t)(j0 + j) * c + i0 + i, lds_get<T>(smem, i, j));
+  }
+  lds_barrier();
+}
+
+// Sum of a split node's partial tiles (a, b) into X, then the row tile's share
+// of GEMM-2 (the step-3 and step-4 work that an unsplit tile does itself).
+template <typename T, bool COH>
+__device__ void do_rtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
+  const DevPlan &pl = *cx.pl;
+  const int s = uniform(gp(pl.node_s)[K]), c = uniform(gp(pl.node_c)[K]);
+  const int parts = uniform(gp(pl.node_split)[K]);
+  const T *Y = static_cast<const T *>(cx.Yp) + gp(pl.node_yoff)[K];
+  const int i0 = a * 64, j0 = b * 64;
+  constexpr int Q = 64 * 64 / NT;
+  T sum[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) sum[q] = zero_of<T>();
+  for (int p = 0; p < parts; ++p) {
+    T v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int i = e & 63, j = e >> 6;
+      v[q] = Mem<COH>::ld(Y + (int64_t)p * c * s + (((int64_t)(j0 + j) * c + i0 + i) & opaque_mask(i0 + i < c && j0 + j < s)));
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) sum[q] += v[q];
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int i = e & 63, j = e >> 6;
+    lds_put<T>(smem, i, j, masked(sum[q], opaque_mask(i0 + i < c && j0 + j < s)));
+  }
+  lds_barrier();
+  // into the accumulator layout of the MFMA tile
+  constexpr int P = Planes<T>::P;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w & 1, wj = w >> 1;
+  Acc<T> acc;
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 32 * wi + 16 * bi + 4 * v + (lane >> 4);
+          const int j = 32 * wj + 16 * bj + (lane & 15);
+          acc.v[p][bi][bj][v] = smem[p * 64 * PITCH + j * PITCH + i];
+        }
+  lds_barrier();
+  store_xtile<T, COH>(cx, K, a, b, acc, smem);
+  gemm2_partial<T, COH>(cx, K, a, b, acc, smem);
+}
+
+// Blocks (a, b) and (b, a), a >= b, of sym(Src - sum_r P_r) into Dst, where
+// Src and Dst are s x s column-major with leading dimensions sld and dld and
+// P_r are the node's row-tile partial products.
+template <typename T, bool COH>
+__device__ void dtile_core(const Ctx<T> &cx, int K, int a, int b, double *smem, const T *Dti, int sld, T *Xkk,
+                           int dld) {
+  const DevPlan &pl = *cx.pl;
+  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K];
+  const int nr = (c + 63) / 64;
+  const int64_t pb = gp(pl.node_poff)[K];
+  const int64_t ss = (int64_t)s * s;
+  const int a0 = a * 64, b0 = b * 64;
+  double *Sab = smem, *Sba = smem + tile_doubles<T>();
+  // T[a0 + i, b0 + j] into Sab[i][j] and T[b0 + i, a0 + j] into Sba[i][j].
+  // Each thread owns 16 elements of each block, taken in two halves of 8;
+  // for every row tile the 16 loads of a half are issued together.
+  constexpr int Q = 64 * 64 / NT, QH = Q / 2;
+  const int ie = threadIdx.x & 63, jb = threadIdx.x >> 6;  // element (ie, jb + 4 q)
+  for (int h = 0; h < 2; ++h) {
+    T sab[QH], sba[QH];
+    int64_t mab[QH], mba[QH];
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      const int j = jb + 4 * (QH * h + q);
+      sab[q] = zero_of<T>();
+      sba[q] = zero_of<T>();
+      mab[q] = opaque_mask(a0 + ie < s && b0 + j < s);
+      mba[q] = opaque_mask(b0 + ie < s && a0 + j < s);
+    }
+    // two row tiles per round trip: their 32 loads are issued together
+    for (int r = 0; r < nr; r += 2) {
+      const T *pr0 = cx.Pp + pb + r * ss;
+      const T *pr1 = cx.Pp + pb + min(r + 1, nr - 1) * ss;
+      const int64_t m1 = opaque_mask(r + 1 < nr);
+      T la0[QH], lb0[QH], la1[QH], lb1[QH];
+#pragma unroll
+      for (int q = 0; q < QH; ++q) {
+        const int j = jb + 4 * (QH * h + q);
+        la0[q] = Mem<COH>::ld(pr0 + (((int64_t)(b0 + j) * s + a0 + ie) & mab[q]));
+        lb0[q] = Mem<COH>::ld(pr0 + (((int64_t)(a0 + j) * s + b0 + ie) & mba[q]));
+        la1[q] = Mem<COH>::ld(pr1 + (((int64_t)(b0 + j) * s + a0 + ie) & mab[q]));
+        lb1[q] = Mem<COH>::ld(pr1 + (((int64_t)(a0 + j) * s + b0 + ie) & mba[q]));
+      }
+#pragma unroll
+      for (int q = 0; q < QH; ++q) {
+        sab[q] += la0[q] + masked(la1[q], m1);
+        sba[q] += lb0[q] + masked(lb1[q], m1);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      const int j = jb + 4 * (QH * h + q);
+      const T dab = gload(Dti + (((int64_t)(b0 + j) * sld + a0 + ie) & mab[q]));
+      const T dba = gload(Dti + (((int64_t)(a0 + j) * sld + b0 + ie) & mba[q]));
+      lds_put<T>(Sab, ie, j, masked(dab - sab[q], mab[q]));
+      lds_put<T>(Sba, ie, j, masked(dba - sba[q], mba[q]));
+    }
+  }
+  lds_barrier();
+  // x(i, j) = (T[a0+i, b0+j] + T[b0+j, a0+i]) / 2 ; keep it in Sab
+  T xv[64 * 64 / NT];
+#pragma unroll
+  for (int q = 0; q < 64 * 64 / NT; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int i = e & 63, j = e >> 6;
+    xv[q] = SOps<T>::scale(0.5, lds_get<T>(Sab, i, j) + lds_get<T>(Sba, j, i));
+  }
+  lds_barrier();
+#pragma unroll
+  for (int q = 0; q < 64 * 64 / NT; ++q) {
+    const int e = threadIdx.x + NT * q;
+    lds_put<T>(Sab, e & 63, e >> 6, xv[q]);
+  }
+  lds_barrier();
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int i = e & 63, j = e >> 6;
+    if (a0 + i < s && b0 + j < s) Mem<COH>::st(Xkk + (int64_t)(b0 + j) * dld + a0 + i, lds_get<T>(Sab, i, j));
+    if (a != b && b0 + i < s && a0 + j < s) Mem<COH>::st(Xkk + (int64_t)(a0 + j) * dld + b0 + i, lds_get<T>(Sab, j, i));
+  }
+  lds_barrier();
+}
+
+// Blocks (a, b) and (b, a), a >= b, of X_KK = sym(Dt^{-1} - sum_r P_r)
+// (Alg. 1 step 4 and the symmetrization of Section 2.3).
+template <typename T, bool COH>
+__device__ void do_dtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
+  const DevPlan &pl = *cx.pl;
+  const int ld = gp(pl.node_s)[K] + gp(pl.node_c)[K];
+  const int64_t off = gp(pl.node_off)[K];
+  // top block of the normalized panel = Dt^{-1}; top block of the X panel
+  dtile_core<T, COH>(cx, K, a, b, smem, cx.Lp + off, ld, cx.Xp + off, ld);
+}
+
+template <typename T, bool COH>
+__device__ void do_item(const Ctx<T> &cx, const Item &item, double *smem, int64_t *rt) {
+  const Item it = uniform(item);
+  if (it.type == ITEM_G) {
+    do_gtile<T>(cx, it.K, it.a, it.b, smem, cx.Xp);
+  } else if (it.type == ITEM_Y) {
+    do_ytile<T, COH>(cx, it.K, it.a, it.b, smem, rt);
+  } else if (it.type == ITEM_R) {
+    do_rtile<T, COH>(cx, it.K, it.a, it.b, smem);
+  } else if (it.type == ITEM_D) {
+    do_dtile<T, COH>(cx, it.K, it.a, it.b, smem);
+  } else {  // ITEM_S: the whole node (c <= 64, s <= 64) in this workgroup
+    if (uniform(gp(cx.pl->node_c)[it.K]) > 0) {
+      do_ytile<T, COH>(cx, it.K, 0, 0, smem, rt);
+      __threadfence_block();
+      __syncthreads();
+    }
+    do_dtile<T, COH>(cx, it.K, 0, 0, smem);
+  }
+}
+
+}  // namespace selinv

@@ -35,6 +35,25 @@ __host__ __device__ constexpr int item_phase(int type) {
   return type == ITEM_G ? 0 : type == ITEM_Y ? 1 : type == ITEM_R ? 2 : 3;
 }
 
+// Work items of the adjoint (reverse) sweep, FP64; see adjoint.hip.  R1 runs
+// leaves -> root, R3 root -> leaves; each is listed by etree depth and phase.
+enum BackItemType : int32_t {
+  BI_T = 0,   // R1 phase 0: Tbar = sym(Xbar_KK) from the stored lower triangle
+  BI_G = 1,   // R1 phase 0: dense X_{C,C} gather block (nodes with a dense buffer)
+  BI_Z = 2,   // R1 phase 1: Zbar = Xbar_{C,K} - Lhat Tbar
+  BI_L = 3,   // R1 phase 2: Lhatbar = -(X_{C,C} Zbar + X_{C,K} Tbar)
+  BI_SC = 4,  // R1 phase 2: scatter-add of -(Zbar Lhat^T + Lhat Zbar^T) into the ancestors
+  BI_F = 5,   // R1 phase 2: F = Tbar E   (E = Dt^{-1})
+  BI_D0 = 6,  // R1 phase 3: Dtbar0 = -E F
+  BI_SG = 7,  // R3 phase 0: dense Sbar_{C,C} gather block
+  BI_M = 8,   // R3 phase 1: M = Sbar_{C,C} Lhat
+  BI_LB = 9,  // R3 phase 2: Lb = Lhatbar - 2 M Dt
+  BI_N = 10,  // R3 phase 3: N = Lb E; Sbar_{C,K} = N / 2; GEMM-2 share of Lhat^T (M + N)
+  BI_DF = 11  // R3 phase 4: Sbar_KK = sym(Dtbar0 - Lhat^T (M + N))
+};
+constexpr int kBackR1Phases = 4;
+constexpr int kBackR3Phases = 5;
+
 constexpr int kTileM = 64;   // GEMM-1 rows per item
 constexpr int kTileN = 64;   // columns per item (of s)
 constexpr int kSmallC = 64;  // fused single-item node bounds
@@ -79,6 +98,11 @@ struct DevPlan {
   void *ypart;         // [batch][y_elems] partial GEMM-1 tiles of split nodes
   int64_t y_elems;
   int32_t *cnt;        // [kPhases][batch][ns] outstanding items of each phase
+  // adjoint scratch, [batch][panel_elems] each (panel layout) and
+  // [batch][sq_elems] each (s x s per node, column-major); null for complex
+  void *adj_z, *adj_l, *adj_s;  // Zbar then M; Lhatbar then Lb; Sbar
+  void *adj_t, *adj_f, *adj_d;  // Tbar; F; Dtbar0
+  Item *bitems;        // adjoint work items
   int32_t *ctrl;       // CTRL_WORDS
   int64_t *trace;      // optional: per ticket {item id, workgroup, t_ticket, t_start, t_end, 0, 0, 0}
 };
@@ -94,6 +118,9 @@ struct LaunchAux {
   const int32_t *lvl_items; // item ids grouped by (level, phase)
   const int32_t *lvl_ptr;   // host array [nlvl + 1]
   int32_t nlvl;
+  const int32_t *blvl_items;  // adjoint item ids grouped by (sweep, level, phase)
+  const int32_t *blvl_ptr;    // host array [nblvl + 1]
+  int32_t nblvl;
 };
 
 }  // namespace selinv

@@ -482,20 +482,44 @@ template <typename T, int TK> struct LoadDenseB {
   }
 };
 
+// B(k, x) = M[k * ld + x0 + x] for k < kend, x0 + x < xmax: a row-major view
+// (the transpose of a column-major block); lanes run along x.
+template <typename T, int TK> struct LoadDenseBT {
+  const T *M;
+  int ld, kend, x0, xmax;
+  __device__ __forceinline__ int slot(int, int m) const {
+    const int e = threadIdx.x + NT * m;
+    return (e >> 6) * PITCH + (e & 63);
+  }
+  __device__ __forceinline__ int64_t mask(int k0, int m) const {
+    const int e = threadIdx.x + NT * m;
+    return opaque_mask(k0 + (e >> 6) < kend && x0 + (e & 63) < xmax);
+  }
+  __device__ __forceinline__ void load(int k0, DVals<T, TK> &v) const {
+#pragma unroll
+    for (int m = 0; m < 64 * TK / NT; ++m) {
+      const int e = threadIdx.x + NT * m;
+      const int k = k0 + (e >> 6), x = x0 + (e & 63);
+      v.v[m] = Mem<false>::ld(M + (((int64_t)k * ld + x) & mask(k0, m)));
+    }
+  }
+};
+
 template <typename T, int TK> __device__ __forceinline__ constexpr int dense_stage_doubles() {
   return 2 * Planes<T>::P * TK * PITCH;
 }
 
-// acc = A (64 x [kb, ke)) * B ([kb, ke) x 64) from dense operands.  Two
+// acc (+)= A (64 x [kb, ke)) * B ([kb, ke) x 64) from dense operands.  Two
 // register sets alternate, so the loads of a stage are issued two
 // stage-computations before they are stored to LDS; waits are counted waits
-// on the older set only.  kb and ke must be wave-uniform.
+// on the older set only.  kb, ke and accumulate must be wave-uniform.
 template <typename T, class LA, class LB>
-__device__ __forceinline__ void gemm_dense(int kb, int ke, const LA &la, const LB &lb, double *smem, Acc<T> &acc) {
+__device__ __forceinline__ void gemm_dense(int kb, int ke, const LA &la, const LB &lb, double *smem, Acc<T> &acc,
+                                           bool accumulate = false) {
   constexpr int TK = DenseTK<T>::TK, P = Planes<T>::P;
   constexpr int SD = dense_stage_doubles<T, TK>();
   using V = DVals<T, TK>;
-  acc_zero<T>(acc);
+  if (!accumulate) acc_zero<T>(acc);
   const int nk = (ke - kb + TK - 1) / TK;
   if (nk <= 0) return;
   const int klast = kb + (nk - 1) * TK;

@@ -155,8 +155,17 @@ class SelInv:
         capi.selinv_extract(self.h, self._bufs["x"], self._bufs["work"], out, _stream())
         return out
 
+    def scatter(self, vals):
+        """[batch, panel_elems] device tensor: zeros, with vals ([batch, nnz(A)],
+        on A's pattern) at the positions of A's entries (the transpose of extract)."""
+        out = torch.empty((self.batch, self.panel_elems), dtype=self.scalar_dtype, device=self.device)
+        capi.selinv_scatter(self.h, vals, self._bufs["work"], out, _stream())
+        return out
+
     def backward(self, xbar, abar=None):
-        """xbar: [batch, panel_elems] device tensor (overwritten)."""
+        """Adjoint (FP64): xbar [batch, panel_elems] device tensor, dloss/dx for the
+        stored selected entries (overwritten); returns dloss/da on A's pattern
+        [batch, nnz(A)].  Needs factor(..., want_dtilde=True) and run() first."""
         if abar is None:
             abar = torch.empty((self.batch, self.nnzA), dtype=self.scalar_dtype, device=self.device)
         capi.selinv_backward(self.h, self._bufs["panels"], self._bufs["x"], self.dtilde, xbar,

@@ -92,3 +92,26 @@ def test_sizes_are_consistent():
     assert s.panels_bytes >= 3 * sym["panel_elems"] * 16 and s.panels_bytes % 256 == 0
     assert s.abar_bytes >= 3 * w.nnz * 16
     assert s.work_bytes > 0
+
+
+def test_backward_before_factor_is_a_state_error():
+    from paper_1604_02528_amd import capi
+
+    w = workload("C1")
+    S = _ctx(w)
+    with pytest.raises(capi.SelinvError) as ei:
+        capi.selinv_backward(S.h, 1, 1, 1, 1, 1, 1, None)
+    assert ei.value.status == 6
+
+
+def test_adjoint_items_cover_every_node_once_per_sweep():
+    """Host plan of the reverse sweep: R1 visits depths deepest first, R3 root
+    first; every node gets its diagonal-block items once in each sweep."""
+    from paper_1604_02528_amd import capi
+
+    w = workload("C2", 10)
+    S = _ctx(w, relax=0.05)
+    it = capi.selinv_items(S.h)  # forward items, for the node count
+    sym = S.symbolic()
+    ns = sym["nsuper"]
+    assert it.shape[1] == 4 and it[:, 0].max() == ns - 1
