@@ -211,6 +211,53 @@ def cpu_leg(w, relax, reps=3):
     return {"t": float(np.median(times)), "X": selinv.flatten(sym, X), "threads": int(threads)}
 
 
+def adjoint_leg(relax):
+    """C4: the adjoint (selinv_backward) against the forward pass (normalize +
+    run) on the 200 x 200 GMRF, loss = sum_i c_i (Q^{-1})_ii."""
+    import torch
+
+    from paper_1604_02528_amd import SelInv, capi
+    from workloads import config
+
+    w = config("C4")
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, batch=1, cap=w.cap, relax=relax, sched="levels")
+    S.factor(w.values, want_dtilde=True)
+    S.run()
+    ldlt = torch.from_numpy(S.factor_host(w.values)).to("cuda")
+    # dloss/dx on A's pattern: c_i on the diagonal entries, scattered to the panel layout
+    gx = np.zeros((1, w.nnz))
+    gx[0, np.asarray(w.colptr[:-1])] = np.asarray(w.meta["c"], dtype=np.float64)
+    xbar0 = S.scatter(torch.from_numpy(gx).to("cuda"))
+    xbar = torch.empty_like(xbar0)
+    abar = torch.empty((1, w.nnz), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    fw, bw = [], []
+    for it in range(6):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record(stream)
+        capi.selinv_normalize(S.h, ldlt, S._bufs["panels"], S._bufs["work"], S.dtilde, stream.cuda_stream)
+        capi.selinv_run(S.h, S._bufs["panels"], S._bufs["x"], S._bufs["work"], stream.cuda_stream)
+        e[1].record(stream)
+        xbar.copy_(xbar0)
+        e[2].record(stream)
+        capi.selinv_backward(S.h, S._bufs["panels"], S._bufs["x"], S.dtilde, xbar, S._bufs["work"], abar,
+                             stream.cuda_stream)
+        e[3].record(stream)
+        torch.cuda.synchronize()
+        if it >= 2:
+            fw.append(e[0].elapsed_time(e[1]))
+            bw.append(e[2].elapsed_time(e[3]))
+    S.sync()
+    S.close()
+    out = {"workload": "C4: 200 x 200 GMRF precision kappa^2 I + weighted 5-point Laplacian (N=40000), FP64, "
+                       "loss sum_i c_i (Q^{-1})_ii",
+           "forward_ms": round(float(np.median(fw)), 4), "backward_ms": round(float(np.median(bw)), 4)}
+    out["backward_vs_forward"] = round(out["backward_ms"] / out["forward_ms"], 3)
+    log(f"C4 adjoint: forward {out['forward_ms']} ms, backward {out['backward_ms']} ms "
+        f"(x{out['backward_vs_forward']})")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,7 +268,7 @@ def main():
     ap.add_argument("--sched", default="levels", choices=["persistent", "levels"])
     ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C5"])
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the C3 batched-vs-sequential and C5 (largest 3-D case) legs")
+                    help="skip the C3 batched-vs-sequential, C4 adjoint-vs-forward and C5 (largest 3-D case) legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run its own "
@@ -265,6 +312,7 @@ def main():
 
         torch.cuda.empty_cache()
         extras["batched"] = batched_leg(args.relax, args.sched)
+        extras["adjoint"] = adjoint_leg(args.relax)
         extras["largest_3d"] = largest_3d_leg(args.relax, args.sched)
     out = {
         "metric": "selinv FP64 GFLOP/s (% MFMA peak) + s/solve; batched 32-shift & adjoint vs plain",
