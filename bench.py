@@ -44,6 +44,39 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "selinv_C2_levels_hbm_traffic.json")
+
+
+def measured_traffic(workload, sched):
+    """HBM bytes per traversal from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record (scaled by a 1 GiB copy), or None when it does not match
+    this run or the kernel sources have changed since it was taken."""
+    import hashlib
+
+    if workload != "C2" or sched != "levels" or not os.path.exists(TRAFFIC_RECORD):
+        return None
+    rec = json.load(open(TRAFFIC_RECORD))
+    h = hashlib.sha256()
+    for f in rec["source_files"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return rec["traffic_bytes_per_step"] if h.hexdigest() == rec["source_sha256"] else None
+
+
+def algorithmic_bytes(w, relax):
+    """sum_K [c(c+1)/2 + cs + s(s+1)/2] reads + [cs + s^2] writes over the
+    supernode partition in use, times the scalar size."""
+    from paper_1604_02528_amd import SelInv
+
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128" if w.is_complex else "f64", batch=1, cap=w.cap,
+               relax=relax, device="cpu")
+    sym = S.symbolic()
+    S.close()
+    s = np.diff(sym["xsuper"]).astype(np.float64)
+    c = np.diff(sym["rowptr"]).astype(np.float64)
+    elems = np.sum(c * (c + 1) / 2 + c * s + s * (s + 1) / 2 + c * s + s * s)
+    return float(elems * (16 if w.is_complex else 8) * w.batch)
+
+
 def timed_steps(S, ldlt, steps, warmup):
     """warmup + steps passes of selinv_normalize + selinv_run on one stream,
     HIP events around each call; returns wall seconds and per-step times."""
@@ -267,6 +300,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--sched", default="levels", choices=["persistent", "levels"])
     ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C5"])
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with three 1 GiB device-to-device copies (reference for HBM byte counters)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the C3 batched-vs-sequential, C4 adjoint-vs-forward and C5 (largest 3-D case) legs")
     args = ap.parse_args()
@@ -338,7 +373,11 @@ def main():
         "pct_fp64_mfma_peak": round(100.0 * value / (PEAK_FP64_TFLOPS * 1e3), 3),
         "s_per_solve": ms_step * 1e-3 / w.batch,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 5), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 5),
+                     "traffic": measured_traffic(args.workload, args.sched),
+                     "traffic_unit": "HBM bytes per traversal (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, calibrated "
+                                     "on a 1 GiB device copy)",
+                     "algorithmic_bytes": algorithmic_bytes(w, args.relax),
                      "kernel": ("k_items_list, one launch per etree level and phase"
                                 if args.sched == "levels" else "k_persistent, one launch"),
                      "selinv_run_ms": round(t_run * 1e3, 4),
@@ -351,6 +390,15 @@ def main():
         **extras,
     }
     print(json.dumps(out), flush=True)
+    if args.calibrate_copy:
+        import torch
+
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration: three copies of 1 GiB (read 1 GiB + write 1 GiB each)")
 
 
 if __name__ == "__main__":
