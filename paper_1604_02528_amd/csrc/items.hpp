@@ -95,11 +95,73 @@ __device__ void store_xtile(const Ctx<T> &cx, int K, int a, int b, const Acc<T> 
   lds_barrier();
 }
 
+// R[p][j * PITCH + x] = (Ls^T acc)(x, j) for a 64 x 64 block: Ls holds
+// Lhat[tile rows i, 64 columns x] as Ls[p][i * PITCH + x] (already in LDS,
+// barrier done); acc is a 64 x 64 GEMM-1 tile in the accumulator layout,
+// which is the MFMA B-operand layout for a contraction over the tile rows
+// (register v of a 16 x 16 block holds rows 4v..4v+3 of lanes l / 16).  R
+// overwrites Ls; ends with a barrier.
+template <typename T>
+__device__ void gemm2_block(const Acc<T> &acc, double *Ls) {
+  constexpr int P = Planes<T>::P;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w & 1, wj = w >> 1;
+  d4 pacc[P][4][2];
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int xb = 0; xb < 4; ++xb)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) pacc[p][xb][bj] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int k4 = 0; k4 < 4; ++k4) {
+      const int row = 32 * wi + 16 * bi + 4 * k4 + (lane >> 4);
+#pragma unroll
+      for (int xb = 0; xb < 4; ++xb) {
+        double af[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) af[p] = Ls[p * 64 * PITCH + row * PITCH + 16 * xb + (lane & 15)];
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          if constexpr (P == 1) {
+            pacc[0][xb][bj] = mfma16(af[0], acc.v[0][bi][bj][k4], pacc[0][xb][bj]);
+          } else {
+            pacc[0][xb][bj] = mfma16(af[0], acc.v[0][bi][bj][k4], pacc[0][xb][bj]);
+            pacc[0][xb][bj] = mfma16(-af[1], acc.v[1][bi][bj][k4], pacc[0][xb][bj]);
+            pacc[1][xb][bj] = mfma16(af[0], acc.v[1][bi][bj][k4], pacc[1][xb][bj]);
+            pacc[1][xb][bj] = mfma16(af[1], acc.v[0][bi][bj][k4], pacc[1][xb][bj]);
+          }
+        }
+      }
+    }
+  lds_barrier();
+  // sum the two row halves (wi = 0, 1) in LDS
+  double *R = Ls;
+  for (int half = 0; half < 2; ++half) {
+    if (wi == half) {
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int xb = 0; xb < 4; ++xb)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int x = 16 * xb + 4 * v + (lane >> 4);
+              const int j = 32 * wj + 16 * bj + (lane & 15);
+              double &r = R[p * 64 * PITCH + j * PITCH + x];
+              r = half == 0 ? pacc[p][xb][bj][v] : r + pacc[p][xb][bj][v];
+            }
+    }
+    lds_barrier();
+  }
+}
+
 // Row tile a's share of GEMM-2 (Alg. 1 step 4): P_a[:, 64b..] = Lhat[rows of
 // tile a, :]^T Y[tile a, 64b..] = -(Lhat_a^T acc), written to the partial
-// buffer (column-major s x s per row tile).  The accumulators already sit in
-// the MFMA B-operand layout for a contraction over the tile rows (register v
-// of a 16 x 16 block holds rows 4v..4v+3 of lanes l / 16).
+// buffer (column-major s x s per row tile).
 template <typename T, bool COH>
 __device__ void gemm2_partial(const Ctx<T> &cx, int K, int a, int b, const Acc<T> &acc, double *smem) {
   constexpr int P = Planes<T>::P;
@@ -107,8 +169,6 @@ __device__ void gemm2_partial(const Ctx<T> &cx, int K, int a, int b, const Acc<T
   const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
   const int64_t off = gp(pl.node_off)[K];
   const int i0 = a * 64, j0 = b * 64;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wi = w & 1, wj = w >> 1;
   const int64_t pbase = gp(pl.node_poff)[K] + (int64_t)a * s * s;
   double *Ls = smem;  // Lhat[i0 .. i0+63, q0 .. q0+63] as Ls[p][i * PITCH + x]
   for (int q0 = 0; q0 < s; q0 += 64) {
@@ -128,58 +188,9 @@ __device__ void gemm2_partial(const Ctx<T> &cx, int K, int a, int b, const Acc<T
       for (int p = 0; p < P; ++p) Ls[p * 64 * PITCH + i * PITCH + x] = Planes<T>::get(v, p);
     }
     lds_barrier();
-    d4 pacc[P][4][2];
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-#pragma unroll
-      for (int xb = 0; xb < 4; ++xb)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) pacc[p][xb][bj] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int k4 = 0; k4 < 4; ++k4) {
-        const int row = 32 * wi + 16 * bi + 4 * k4 + (lane >> 4);
-#pragma unroll
-        for (int xb = 0; xb < 4; ++xb) {
-          double af[P];
-#pragma unroll
-          for (int p = 0; p < P; ++p) af[p] = Ls[p * 64 * PITCH + row * PITCH + 16 * xb + (lane & 15)];
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj) {
-            if constexpr (P == 1) {
-              pacc[0][xb][bj] = mfma16(af[0], acc.v[0][bi][bj][k4], pacc[0][xb][bj]);
-            } else {
-              pacc[0][xb][bj] = mfma16(af[0], acc.v[0][bi][bj][k4], pacc[0][xb][bj]);
-              pacc[0][xb][bj] = mfma16(-af[1], acc.v[1][bi][bj][k4], pacc[0][xb][bj]);
-              pacc[1][xb][bj] = mfma16(af[0], acc.v[1][bi][bj][k4], pacc[1][xb][bj]);
-              pacc[1][xb][bj] = mfma16(af[1], acc.v[0][bi][bj][k4], pacc[1][xb][bj]);
-            }
-          }
-        }
-      }
-    lds_barrier();
-    // sum the two row halves (wi = 0, 1) in LDS: R[p][j * PITCH + x]
-    double *R = smem;
-    for (int half = 0; half < 2; ++half) {
-      if (wi == half) {
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-          for (int xb = 0; xb < 4; ++xb)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                const int x = 16 * xb + 4 * v + (lane >> 4);
-                const int j = 32 * wj + 16 * bj + (lane & 15);
-                double &r = R[p * 64 * PITCH + j * PITCH + x];
-                r = half == 0 ? pacc[p][xb][bj][v] : r + pacc[p][xb][bj][v];
-              }
-      }
-      lds_barrier();
-    }
+    gemm2_block<T>(acc, Ls);
     // P = Lhat^T Y = -(Lhat^T acc)
+    const double *R = Ls;
     for (int e = threadIdx.x; e < 64 * 64; e += NT) {
       const int x = e & 63, j = e >> 6;
       if (q0 + x < s && j0 + j < s)
@@ -383,6 +394,114 @@ __device__ void do_dtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
   dtile_core<T, COH>(cx, K, a, b, smem, cx.Lp + off, ld, cx.Xp + off, ld);
 }
 
+// A whole node with c <= 64 and s <= 64 in one workgroup (Alg. 1 steps 3-4
+// and the symmetrization of Section 2.3), in three dependent rounds of
+// memory reads: (1) the row tables of C(K), Lhat and Dt^{-1}; (2) the panel
+// positions of X_{C,C} (the column tables of X_{C,C} are the row tables:
+// both index C(K)); (3) the values of X_{C,C}.  GEMM-1, GEMM-2 and the
+// diagonal block then run from LDS; nothing goes through the partial buffer.
+template <typename T, bool COH>
+__device__ void do_stile(const Ctx<T> &cx, int K, double *smem, int64_t *rt) {
+  constexpr int P = Planes<T>::P, TK = Planes<T>::TK;
+  constexpr int Q = 64 * 64 / NT;
+  const DevPlan &pl = *cx.pl;
+  const int s = uniform(gp(pl.node_s)[K]), c = uniform(gp(pl.node_c)[K]), ld = s + c;
+  const int64_t off = gp(pl.node_off)[K], rp = gp(pl.node_rowptr)[K];
+  // round 1: row tables, Lhat (c x s) and Dt^{-1} (s x s); element e -> (i = e & 63, j = e >> 6)
+  if (threadIdx.x < 64) {
+    const int ig = threadIdx.x < c ? threadIdx.x : 0;
+    rt[threadIdx.x] = gp(pl.kcol)[rp + ig];
+    rt[64 + threadIdx.x] = gp(pl.kpos)[rp + ig];
+  }
+  T lv[Q], dv[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int i = e & 63, j = e >> 6;
+    lv[q] = gload(cx.Lp + off + ((((int64_t)j * ld + s + i) & opaque_mask(i < c && j < s))));
+    dv[q] = gload(cx.Lp + off + ((((int64_t)j * ld + i) & opaque_mask(i < s && j < s))));
+  }
+  lds_barrier();
+  Acc<T> acc;
+  acc_zero<T>(acc);
+  if (c > 0) {
+    // round 2: positions of X_{C,C}(i, k): lower part (i >= k) through column
+    // k's table, upper part through row i's table; element e -> (i = e & 63, k = e >> 6)
+    int64_t base[Q];
+    int32_t pos[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int i = e & 63, k = e >> 6;
+      const int64_t okm = opaque_mask(i < c && k < c);
+      const int64_t lm = opaque_mask(i >= k);
+      base[q] = (rt[k] & lm) | (rt[i] & ~lm);
+      const int64_t pidx = (((rt[64 + k] + i) & lm) | ((rt[64 + i] + k) & ~lm)) & okm;
+      pos[q] = gp(pl.posarr)[pidx];
+    }
+    // round 3: the values
+    T gv[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int i = e & 63, k = e >> 6;
+      gv[q] = Mem<COH>::ld(cx.Xp + ((base[q] + (int64_t)pos[q]) & opaque_mask(i < c && k < c)));
+    }
+    // GEMM-1 from LDS: four stages of TK contraction indices, A = X_{C,C}, B = Lhat
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int i = e & 63, k = e >> 6;  // A(i, k) and B(k = i', x = j): the same index pattern
+      const T g = masked(gv[q], opaque_mask(i < c && k < c));
+      const T l = masked(lv[q], opaque_mask(i < c && k < s));
+      double *stg = smem + (k / TK) * stage_doubles<T>();
+      double *stgb = smem + (i / TK) * stage_doubles<T>();
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        stg[p * TK * PITCH + (k % TK) * PITCH + i] = Planes<T>::get(g, p);           // A plane [kk][i]
+        stgb[(P + p) * TK * PITCH + (i % TK) * PITCH + k] = Planes<T>::get(l, p);    // B plane [kk][x]
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int st = 0; st < 64 / TK; ++st) stage_compute<T>(smem + st * stage_doubles<T>(), acc);
+    lds_barrier();
+    // Y = -acc into X_{C,K}
+    store_xtile<T, COH>(cx, K, 0, 0, acc, smem);
+    // Lhat into LDS as Ls[p][i * PITCH + x], then R = Lhat^T acc
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int i = e & 63, x = e >> 6;
+      const T l = masked(lv[q], opaque_mask(i < c && x < s));
+#pragma unroll
+      for (int p = 0; p < P; ++p) smem[p * 64 * PITCH + i * PITCH + x] = Planes<T>::get(l, p);
+    }
+    lds_barrier();
+    gemm2_block<T>(acc, smem);  // R[p][j * PITCH + x] = (Lhat^T acc)(x, j) = -(Lhat^T Y)(x, j)
+  } else {
+#pragma unroll
+    for (int e = threadIdx.x; e < 64 * 64; e += NT) lds_put<T>(smem, e >> 6, e & 63, zero_of<T>());
+    lds_barrier();
+  }
+  // T = Dt^{-1} - Lhat^T Y = Dt^{-1} + R; X_KK = (T + T^T) / 2
+  double *Tt = smem + tile_doubles<T>();
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int i = e & 63, j = e >> 6;
+    const T d = masked(dv[q], opaque_mask(i < s && j < s));
+    lds_put<T>(Tt, i, j, d + lds_get<T>(smem, i, j));
+  }
+  lds_barrier();
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int i = e & 63, j = e >> 6;
+    if (i < s && j < s)
+      Mem<COH>::st(cx.Xp + off + (int64_t)j * ld + i, SOps<T>::scale(0.5, lds_get<T>(Tt, i, j) + lds_get<T>(Tt, j, i)));
+  }
+  lds_barrier();
+}
+
 template <typename T, bool COH>
 __device__ void do_item(const Ctx<T> &cx, const Item &item, double *smem, int64_t *rt) {
   const Item it = uniform(item);
@@ -395,12 +514,7 @@ __device__ void do_item(const Ctx<T> &cx, const Item &item, double *smem, int64_
   } else if (it.type == ITEM_D) {
     do_dtile<T, COH>(cx, it.K, it.a, it.b, smem);
   } else {  // ITEM_S: the whole node (c <= 64, s <= 64) in this workgroup
-    if (uniform(gp(cx.pl->node_c)[it.K]) > 0) {
-      do_ytile<T, COH>(cx, it.K, 0, 0, smem, rt);
-      __threadfence_block();
-      __syncthreads();
-    }
-    do_dtile<T, COH>(cx, it.K, 0, 0, smem);
+    do_stile<T, COH>(cx, it.K, smem, rt);
   }
 }
 
