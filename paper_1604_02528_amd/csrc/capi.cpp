@@ -54,7 +54,9 @@ struct HostPlan {
   std::vector<Item> bitems;    // adjoint items in (sweep, depth, phase) order
   std::vector<int32_t> blvl_ptr;  // [nblvl + 1] ranges of bitems launched together
   bool adjoint = false;        // adjoint scratch allocated (FP64 only)
-  std::vector<int32_t> lvl_items, lvl_ptr;
+  std::vector<int32_t> lvl_items, lvl_ptr, lvl_tiny;
+  std::vector<TinyRec> tiny;  // single-wavefront nodes, in launch order
+  std::vector<int64_t> toff;  // their X_{C,C} offset tables
   std::vector<int2> chunks, rblocks;
   std::vector<int4> sq_tiles;
   std::vector<int64_t> apos;
@@ -65,7 +67,7 @@ struct HostPlan {
   struct Off {
     int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
         nph, node_split, node_kchunk, node_yoff, node_goff, node_ldg, node_parent, order, lvl_items, chunks, rblocks,
-        sq_tiles,
+        sq_tiles, tiny, toff,
         apos, adiag, bitems, plan, linv, dinv, part, gbuf, ypart, cnt, adj_z, adj_l, adj_s, adj_t, adj_f, adj_d, ctrl, end;
   } off{};
   int64_t tables_bytes = 0;  // [0, tables_bytes) is uploaded once
@@ -347,20 +349,44 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   H.node_parent.resize(ns);
   for (int64_t K = 0; K < ns; ++K) H.node_parent[K] = (int32_t)S.sparent[K];
   ticket_order(S, H, batch);
-  // level lists (every phase of every etree depth)
+  // level lists (every phase of every etree depth); at phase 3 the
+  // single-wavefront nodes of a depth form a range of their own
   H.lvl_items.clear();
   H.lvl_ptr.assign(1, 0);
+  H.lvl_tiny.clear();
+  H.tiny.clear();
+  H.toff.clear();
   {
+    auto is_tiny = [&](int64_t K) { return H.node_c[K] <= kTinyC && H.node_s[K] <= kTinyS; };
+    auto close = [&](int32_t tiny_base) {
+      if ((int32_t)H.lvl_items.size() > H.lvl_ptr.back()) {
+        H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
+        H.lvl_tiny.push_back(tiny_base);
+      }
+    };
     std::vector<std::vector<int64_t>> bydepth(S.depth);
     for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
     for (int64_t d = 0; d < S.depth; ++d) {
       for (int ph = 0; ph < kPhases; ++ph) {
         for (int64_t K : bydepth[d]) {
+          if (ph == 3 && is_tiny(K)) continue;
           const int32_t b = phase_begin(H, K, ph), n = phase_count(H, K, ph);
           for (int32_t q = 0; q < n; ++q) H.lvl_items.push_back(b + q);
         }
-        if ((int32_t)H.lvl_items.size() > H.lvl_ptr.back()) H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
+        close(-1);
       }
+      const int32_t tiny_base = (int32_t)H.tiny.size();
+      for (int64_t K : bydepth[d]) {
+        if (!is_tiny(K)) continue;
+        const int32_t it = phase_begin(H, K, 3);
+        const int64_t c = H.node_c[K], rp = S.rowptr[K];
+        H.lvl_items.push_back(it);
+        H.tiny.push_back(TinyRec{(int32_t)K, it, H.node_s[K], (int32_t)c, S.panel_off[K], (int64_t)H.toff.size()});
+        // X(row i, row k), i >= k, lives in the panel of row k's supernode
+        for (int64_t i = 0; i < c; ++i)
+          for (int64_t k = 0; k <= i; ++k) H.toff.push_back(H.kcol[rp + k] + S.posarr[H.kpos[rp + k] + i]);
+      }
+      close(tiny_base);
     }
   }
   // adjoint items: R1 leaves -> root (deepest level first), then R3 root -> leaves
@@ -460,6 +486,8 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.node_parent = take(4 * ns);
   o.order = take(4 * (int64_t)H.order.size());
   o.lvl_items = take(4 * (int64_t)H.lvl_items.size());
+  o.tiny = take((int64_t)sizeof(TinyRec) * (int64_t)H.tiny.size());
+  o.toff = take(8 * (int64_t)H.toff.size());
   o.chunks = take(8 * (int64_t)H.chunks.size());
   o.rblocks = take(8 * (int64_t)H.rblocks.size());
   o.sq_tiles = take(16 * (int64_t)H.sq_tiles.size());
@@ -568,6 +596,7 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.node_parent = (int32_t *)(b + o.node_parent);
   d.order = (int32_t *)(b + o.order);
   d.lvl_items = (int32_t *)(b + o.lvl_items);
+  d.toff = (int64_t *)(b + o.toff);
   d.apos = (int64_t *)(b + o.apos);
   d.adiag = (uint8_t *)(b + o.adiag);
   d.linv = (void *)(b + o.linv);
@@ -605,6 +634,8 @@ LaunchAux make_aux(const selinv_ctx *h, void *work) {
   a.nsq_tiles = (int32_t)H.sq_tiles.size();
   a.lvl_items = (const int32_t *)(b + H.off.lvl_items);
   a.lvl_ptr = H.lvl_ptr.data();
+  a.lvl_tiny = H.lvl_tiny.data();
+  a.tiny = (const TinyRec *)(b + H.off.tiny);
   a.nlvl = (int32_t)H.lvl_ptr.size() - 1;
   a.blvl_items = nullptr;
   a.blvl_ptr = H.blvl_ptr.data();
@@ -638,6 +669,8 @@ void build_image(selinv_ctx *h) {
   put(img, o.node_parent, H.node_parent);
   put(img, o.order, H.order);
   put(img, o.lvl_items, H.lvl_items);
+  put(img, o.tiny, H.tiny);
+  put(img, o.toff, H.toff);
   put(img, o.chunks, H.chunks);
   put(img, o.rblocks, H.rblocks);
   put(img, o.sq_tiles, H.sq_tiles);

@@ -502,6 +502,83 @@ __device__ void do_stile(const Ctx<T> &cx, int K, double *smem, int64_t *rt) {
   lds_barrier();
 }
 
+// A whole small node (c <= kTinyC, s <= kTinyS) of one matrix in one
+// wavefront, for the level schedule.  Three dependent memory rounds: the
+// record, then the offsets of X_{C,C} (host table), Lhat and Dt^{-1}, then
+// the X_{C,C} values.  Lane (i, grp) holds X_{C,C}(i, k) for k = grp + G u;
+// the partial sums of X_{C,C} Lhat over the G lane groups are combined with
+// a fixed butterfly, so the result does not depend on timing.
+//   Y = -X_{C,C} Lhat (stored into X_{C,K});  T = Dt^{-1} - Lhat^T Y;
+//   X_{K,K} = (T + T^T) / 2                      (Alg. 1, Eqs. (2.9)-(2.10))
+template <typename T, int CM>
+__device__ __forceinline__ void do_tiny(const TinyRec &r, const int64_t *toff, const T *L, T *X, T *ls, T *ys) {
+  constexpr int G = 64 / CM, U = CM / G;
+  const int lane = threadIdx.x, i = lane % CM, grp = lane / CM;
+  const int s = r.s, c = r.c;
+  const int64_t ld = s + c;
+  // round 2: the offsets of this lane's X_{C,C}(i, k); Lhat as ls[j * kTinyC + k]; Dt^{-1}(x, y), (y, x)
+  int64_t o[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = grp + G * u, hi = i > k ? i : k, lo = i > k ? k : i;
+    o[u] = gp(toff)[(r.tbl + hi * (hi + 1) / 2 + lo) & opaque_mask(i < c && k < c)];
+  }
+  constexpr int QL = kTinyC * kTinyS / 64;
+  T lv[QL];
+#pragma unroll
+  for (int q = 0; q < QL; ++q) {
+    const int e = lane + 64 * q, k = e % kTinyC, j = e / kTinyC;
+    lv[q] = gload(L + r.off + ((j * ld + s + k) & opaque_mask(k < c && j < s)));
+  }
+  const int x = lane % kTinyS, y = lane / kTinyS;
+  const int64_t dm = opaque_mask(x < s && y < s);
+  const T dxy = gload(L + r.off + ((y * ld + x) & dm)), dyx = gload(L + r.off + ((x * ld + y) & dm));
+  // round 3: the values
+  T xv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) xv[u] = gload(X + o[u]);
+#pragma unroll
+  for (int q = 0; q < QL; ++q) {
+    const int e = lane + 64 * q, k = e % kTinyC, j = e / kTinyC;
+    ls[e] = masked(lv[q], opaque_mask(k < c && j < s));
+  }
+  __syncthreads();
+  T acc[kTinyS];
+#pragma unroll
+  for (int j = 0; j < kTinyS; ++j) acc[j] = zero_of<T>();
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = grp + G * u;
+    const T g = masked(xv[u], opaque_mask(i < c && k < c));
+#pragma unroll
+    for (int j = 0; j < kTinyS; ++j)
+      if (j < s) acc[j] += g * ls[j * kTinyC + k];
+  }
+#pragma unroll
+  for (int m = CM; m < 64; m <<= 1)
+#pragma unroll
+    for (int j = 0; j < kTinyS; ++j)
+      if (j < s) acc[j] += shfl_xor_t(acc[j], m);
+  if (grp == 0 && i < c) {
+#pragma unroll
+    for (int j = 0; j < kTinyS; ++j)
+      if (j < s) {
+        X[r.off + j * ld + s + i] = SOps<T>::scale(-1.0, acc[j]);
+        ys[j * kTinyC + i] = acc[j];
+      }
+  }
+  __syncthreads();
+  // T = Dt^{-1} + Lhat^T (X_{C,C} Lhat)
+  if (x < s && y < s) {
+    T rxy = zero_of<T>(), ryx = zero_of<T>();
+    for (int q = 0; q < c; ++q) {
+      rxy += ls[x * kTinyC + q] * ys[y * kTinyC + q];
+      ryx += ls[y * kTinyC + q] * ys[x * kTinyC + q];
+    }
+    X[r.off + y * ld + x] = SOps<T>::scale(0.5, (dxy + rxy) + (dyx + ryx));
+  }
+}
+
 template <typename T, bool COH>
 __device__ void do_item(const Ctx<T> &cx, const Item &item, double *smem, int64_t *rt) {
   const Item it = uniform(item);

@@ -59,6 +59,37 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1) k_items_list(co
   }
 }
 
+// Small nodes of one level, one wavefront each (see do_tiny).
+template <typename T>
+__global__ void __launch_bounds__(64) k_tiny(const DevPlan *__restrict__ plp, const T *Lp, T *Xp,
+                                             const TinyRec *__restrict__ recs, int32_t count, int32_t list_pos) {
+  const DevPlan &pl = *plp;
+  __shared__ T ls[kTinyS * kTinyC], ys[kTinyS * kTinyC];
+  const int64_t g = blockIdx.x;
+  const int64_t l = g / count;
+  const TinyRec r = recs[g - l * count];
+  const int64_t t_start = pl.trace ? wall_clock64() : 0;
+  const T *L = Lp + l * pl.panel_elems;
+  T *X = Xp + l * pl.panel_elems;
+  if (r.c <= 8)
+    do_tiny<T, 8>(r, pl.toff, L, X, ls, ys);
+  else if (r.c <= 16)
+    do_tiny<T, 16>(r, pl.toff, L, X, ls, ys);
+  else
+    do_tiny<T, 32>(r, pl.toff, L, X, ls, ys);
+  if (pl.trace) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t *tr = pl.trace + 8 * ((int64_t)list_pos * pl.batch + g);
+      tr[0] = l * pl.nitems + r.it;
+      tr[1] = blockIdx.x;
+      tr[2] = t_start;
+      tr[3] = t_start;
+      tr[4] = wall_clock64();
+    }
+  }
+}
+
 // Scheduler atomics (agent scope, relaxed).  Producers order their data
 // stores before a counter update with a release fence; consumers spin on the
 // counter with relaxed loads and then read the data with plain loads (the
@@ -464,7 +495,11 @@ static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
   if (sched == 1) {
     for (int q = 0; q < aux.nlvl; ++q) {
       const int32_t b = aux.lvl_ptr[q], e = aux.lvl_ptr[q + 1];
-      if (e > b)
+      if (e <= b) continue;
+      if (aux.lvl_tiny[q] >= 0)
+        hipLaunchKernelGGL(k_tiny<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(64), 0, st, dpl, Lp, Xp,
+                           aux.tiny + aux.lvl_tiny[q], e - b, b);
+      else
         hipLaunchKernelGGL(k_items_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,
                            aux.lvl_items + b, e - b, b);
     }

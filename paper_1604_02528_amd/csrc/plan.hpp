@@ -63,6 +63,17 @@ struct alignas(16) Item {
   int32_t K, type, a, b;
 };
 
+// Nodes small enough for one wavefront (c <= kTinyC, s <= kTinyS) skip the
+// 64 x 64 tile machinery in the level schedule: one record each, in launch
+// order, and a host-built table of the absolute X offsets of the lower
+// triangle of X_{C,C} (row-major, entry i (i + 1) / 2 + k for i >= k).
+constexpr int kTinyC = 32;
+constexpr int kTinyS = 8;
+struct alignas(16) TinyRec {
+  int32_t K, it, s, c;  // node, its item id, width, off-diagonal rows
+  int64_t off, tbl;     // panel offset of the node; first table entry
+};
+
 // Control words of the persistent scheduler: an error flag and the ticket
 // counter, on cache lines of their own.  Workgroups draw tickets in order;
 // ticket t names the item order[t] (a topological order of the dependency
@@ -88,6 +99,7 @@ struct DevPlan {
   int32_t *node_parent; // [ns] supernodal etree parent (-1 at a root)
   int32_t *order;      // [batch * nitems] ticket -> l * nitems + item
   int32_t *lvl_items;  // item ids grouped by (level, phase)
+  int64_t *toff;       // X_{C,C} offset tables of the single-wavefront nodes
   int64_t *apos;       // [nnzA] A entry -> panel element
   uint8_t *adiag;      // [nnzA]
   // scratch
@@ -117,6 +129,8 @@ struct LaunchAux {
   int32_t nsq_tiles;
   const int32_t *lvl_items; // item ids grouped by (level, phase)
   const int32_t *lvl_ptr;   // host array [nlvl + 1]
+  const int32_t *lvl_tiny;  // host array [nlvl]: -1 (work items), else the first TinyRec of the range
+  const TinyRec *tiny;      // single-wavefront node records, in launch order
   int32_t nlvl;
   const int32_t *blvl_items;  // adjoint item ids grouped by (sweep, level, phase)
   const int32_t *blvl_ptr;    // host array [nblvl + 1]

@@ -121,6 +121,8 @@ template <> struct Mem<true> {
 };
 
 __device__ __forceinline__ cplx masked(cplx v, int64_t m) { return cplx{masked(v.re, m), masked(v.im, m)}; }
+__device__ __forceinline__ double shfl_xor_t(double v, int m) { return __shfl_xor(v, m); }
+__device__ __forceinline__ cplx shfl_xor_t(cplx v, int m) { return cplx{__shfl_xor(v.re, m), __shfl_xor(v.im, m)}; }
 
 // Plain global loads / stores of scalars through generic pointers.
 template <typename T> __device__ __forceinline__ T gload(const T *p) { return Mem<false>::ld(p); }
