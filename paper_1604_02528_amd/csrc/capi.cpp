@@ -115,7 +115,8 @@ double item_cost_ns(const HostPlan &H, const Item &it) {
     }
     case ITEM_D: {
       const double nr = std::ceil(c / kTileM);
-      return 1000.0 + nr * (double)kTileN * kTileN * 8.0 / 60.0;
+      const double w = (it.b >> 16) ? kDSlabW : kTileN;
+      return 1000.0 + nr * (double)kTileN * w * 8.0 / 60.0;
     }
     default:
       return 1500.0 + (2.0 * c * c * s + 2.0 * c * s * s) / 40.0;
@@ -341,9 +342,11 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
         nph(2, K) = nr * nb;
       }
     }
+    const int32_t nsl = nr >= kDSlabRows ? 64 / kDSlabW : 1;
     for (int32_t a = 0; a < nb; ++a)
-      for (int32_t b = 0; b <= a; ++b) H.items.push_back(Item{(int32_t)K, ITEM_D, a, b});
-    nph(3, K) = nb * (nb + 1) / 2;
+      for (int32_t b = 0; b <= a; ++b)
+        for (int32_t q = 0; q < nsl; ++q) H.items.push_back(Item{(int32_t)K, ITEM_D, a, nsl > 1 ? b | ((q + 1) << 16) : b});
+    nph(3, K) = nb * (nb + 1) / 2 * nsl;
   }
   H.item_ptr[ns] = (int32_t)H.items.size();
   H.node_parent.resize(ns);

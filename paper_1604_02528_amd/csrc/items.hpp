@@ -385,18 +385,106 @@ __device__ void dtile_core(const Ctx<T> &cx, int K, int a, int b, double *smem, 
 
 // Blocks (a, b) and (b, a), a >= b, of X_KK = sym(Dt^{-1} - sum_r P_r)
 // (Alg. 1 step 4 and the symmetrization of Section 2.3).
+// The same as dtile_core for the column slab [b0 + kDSlabW sl, b0 +
+// kDSlabW (sl + 1)) of block (a, b) only (and the matching row slab of block
+// (b, a)), for nodes with many row tiles: with a quarter of the elements per
+// thread, the loads of several row tiles' partials are in flight together.
+template <typename T, bool COH>
+__device__ void dtile_slab(const Ctx<T> &cx, int K, int a, int b, int sl, double *smem, const T *Dti, int sld, T *Xkk,
+                           int dld) {
+  constexpr int W = kDSlabW, QE = 64 * W / NT;
+  constexpr int R = Planes<T>::P == 1 ? 4 : 2;  // row tiles per round trip
+  const DevPlan &pl = *cx.pl;
+  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K];
+  const int nr = uniform((c + 63) / 64);
+  const int64_t pb = gp(pl.node_poff)[K];
+  const int64_t ss = (int64_t)s * s;
+  const int a0 = a * 64, b0 = b * 64 + sl * W;
+  // element q of a thread: (i, j) = (e % 64, e / 64) of the (a, b) slab, and
+  // (j', i') = (e % W, e / W) of the (b, a) slab, e = threadIdx.x + NT q
+  int64_t oab[QE], oba[QE];
+  T sab[QE], sba[QE];
+#pragma unroll
+  for (int q = 0; q < QE; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int ia = e % 64, ja = e / 64, jb = e % W, ib = e / W;
+    oab[q] = ((int64_t)(b0 + ja) * s + a0 + ia) & opaque_mask(a0 + ia < s && b0 + ja < s);
+    oba[q] = ((int64_t)(a0 + ib) * s + b0 + jb) & opaque_mask(b0 + jb < s && a0 + ib < s);
+    sab[q] = zero_of<T>();
+    sba[q] = zero_of<T>();
+  }
+  for (int r = 0; r < nr; r += R) {
+    T la[R][QE], lb[R][QE];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      const T *pr = cx.Pp + pb + min(r + rr, nr - 1) * ss;
+#pragma unroll
+      for (int q = 0; q < QE; ++q) {
+        la[rr][q] = Mem<COH>::ld(pr + oab[q]);
+        lb[rr][q] = Mem<COH>::ld(pr + oba[q]);
+      }
+    }
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      const int64_t m = opaque_mask(r + rr < nr);
+#pragma unroll
+      for (int q = 0; q < QE; ++q) {
+        sab[q] += masked(la[rr][q], m);
+        sba[q] += masked(lb[rr][q], m);
+      }
+    }
+  }
+  T *Sab = reinterpret_cast<T *>(smem);  // [i + 64 j]
+  T *Sba = Sab + 64 * W;                  // [j' + W i']
+  T *Xs = Sba + 64 * W;                   // [i + 64 j]
+#pragma unroll
+  for (int q = 0; q < QE; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int ia = e % 64, ja = e / 64, jb = e % W, ib = e / W;
+    const int64_t mab = opaque_mask(a0 + ia < s && b0 + ja < s), mba = opaque_mask(b0 + jb < s && a0 + ib < s);
+    const T dab = gload(Dti + (((int64_t)(b0 + ja) * sld + a0 + ia) & mab));
+    const T dba = gload(Dti + (((int64_t)(a0 + ib) * sld + b0 + jb) & mba));
+    Sab[e] = masked(dab - sab[q], mab);
+    Sba[e] = masked(dba - sba[q], mba);
+  }
+  lds_barrier();
+  // x(i, j) = (T[a0 + i, b0 + j] + T[b0 + j, a0 + i]) / 2
+#pragma unroll
+  for (int q = 0; q < QE; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int ia = e % 64, ja = e / 64;
+    const T x = SOps<T>::scale(0.5, Sab[e] + Sba[ja + W * ia]);
+    Xs[e] = x;
+    if (a0 + ia < s && b0 + ja < s) Mem<COH>::st(Xkk + (int64_t)(b0 + ja) * dld + a0 + ia, x);
+  }
+  lds_barrier();
+  if (a != b) {
+#pragma unroll
+    for (int q = 0; q < QE; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int jb = e % W, ib = e / W;
+      if (b0 + jb < s && a0 + ib < s) Mem<COH>::st(Xkk + (int64_t)(a0 + ib) * dld + b0 + jb, Xs[ib + 64 * jb]);
+    }
+  }
+  lds_barrier();
+}
+
 template <typename T, bool COH>
 __device__ void do_dtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
   const DevPlan &pl = *cx.pl;
   const int ld = gp(pl.node_s)[K] + gp(pl.node_c)[K];
   const int64_t off = gp(pl.node_off)[K];
-  // top block of the normalized panel = Dt^{-1}; top block of the X panel
-  dtile_core<T, COH>(cx, K, a, b, smem, cx.Lp + off, ld, cx.Xp + off, ld);
+  // top block of the normalized panel = Dt^{-1}; top block of the X panel.
+  // b carries the slab number + 1 in its high half for slab items.
+  if (b >> 16)
+    dtile_slab<T, COH>(cx, K, a, b & 0xffff, (b >> 16) - 1, smem, cx.Lp + off, ld, cx.Xp + off, ld);
+  else
+    dtile_core<T, COH>(cx, K, a, b, smem, cx.Lp + off, ld, cx.Xp + off, ld);
 }
 
 // A whole node with c <= 64 and s <= 64 in one workgroup (Alg. 1 steps 3-4
 // and the symmetrization of Section 2.3), in three dependent rounds of
-// memory reads: (1) the row tables of C(K), Lhat and Dt^{-1}; (2) the panel
+// memory reads (and Dt^{-1} at the end): (1) the row tables of C(K) and Lhat; (2) the panel
 // positions of X_{C,C} (the column tables of X_{C,C} are the row tables:
 // both index C(K)); (3) the values of X_{C,C}.  GEMM-1, GEMM-2 and the
 // diagonal block then run from LDS; nothing goes through the partial buffer.
@@ -407,19 +495,30 @@ __device__ void do_stile(const Ctx<T> &cx, int K, double *smem, int64_t *rt) {
   const DevPlan &pl = *cx.pl;
   const int s = uniform(gp(pl.node_s)[K]), c = uniform(gp(pl.node_c)[K]), ld = s + c;
   const int64_t off = gp(pl.node_off)[K], rp = gp(pl.node_rowptr)[K];
-  // round 1: row tables, Lhat (c x s) and Dt^{-1} (s x s); element e -> (i = e & 63, j = e >> 6)
+  // round 1: row tables into LDS; Lhat (c x s) straight into the B planes of
+  // the four GEMM-1 stages (B(k, x) = Lhat(k, x): plane [kk][x] of stage k / TK)
   if (threadIdx.x < 64) {
     const int ig = threadIdx.x < c ? threadIdx.x : 0;
     rt[threadIdx.x] = gp(pl.kcol)[rp + ig];
     rt[64 + threadIdx.x] = gp(pl.kpos)[rp + ig];
   }
-  T lv[Q], dv[Q];
+  {
+    T lv[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = threadIdx.x + NT * q;
-    const int i = e & 63, j = e >> 6;
-    lv[q] = gload(cx.Lp + off + ((((int64_t)j * ld + s + i) & opaque_mask(i < c && j < s))));
-    dv[q] = gload(cx.Lp + off + ((((int64_t)j * ld + i) & opaque_mask(i < s && j < s))));
+    for (int q = 0; q < Q; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int i = e & 63, j = e >> 6;
+      lv[q] = gload(cx.Lp + off + ((((int64_t)j * ld + s + i) & opaque_mask(i < c && j < s))));
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int i = e & 63, j = e >> 6;
+      const T l = masked(lv[q], opaque_mask(i < c && j < s));
+      double *stgb = smem + (i / TK) * stage_doubles<T>() + P * TK * PITCH + (i % TK) * PITCH + j;
+#pragma unroll
+      for (int p = 0; p < P; ++p) stgb[p * TK * PITCH] = Planes<T>::get(l, p);
+    }
   }
   lds_barrier();
   Acc<T> acc;
@@ -427,7 +526,6 @@ __device__ void do_stile(const Ctx<T> &cx, int K, double *smem, int64_t *rt) {
   if (c > 0) {
     // round 2: positions of X_{C,C}(i, k): lower part (i >= k) through column
     // k's table, upper part through row i's table; element e -> (i = e & 63, k = e >> 6)
-    int64_t base[Q];
     int32_t pos[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -435,36 +533,41 @@ __device__ void do_stile(const Ctx<T> &cx, int K, double *smem, int64_t *rt) {
       const int i = e & 63, k = e >> 6;
       const int64_t okm = opaque_mask(i < c && k < c);
       const int64_t lm = opaque_mask(i >= k);
-      base[q] = (rt[k] & lm) | (rt[i] & ~lm);
       const int64_t pidx = (((rt[64 + k] + i) & lm) | ((rt[64 + i] + k) & ~lm)) & okm;
       pos[q] = gp(pl.posarr)[pidx];
     }
-    // round 3: the values
+    // round 3: the values (panel column bases read again from LDS)
     T gv[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int e = threadIdx.x + NT * q;
       const int i = e & 63, k = e >> 6;
-      gv[q] = Mem<COH>::ld(cx.Xp + ((base[q] + (int64_t)pos[q]) & opaque_mask(i < c && k < c)));
+      const int64_t lm = opaque_mask(i >= k);
+      const int64_t base = (rt[k] & lm) | (rt[i] & ~lm);
+      gv[q] = Mem<COH>::ld(cx.Xp + ((base + (int64_t)pos[q]) & opaque_mask(i < c && k < c)));
     }
     // GEMM-1 from LDS: four stages of TK contraction indices, A = X_{C,C}, B = Lhat
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int e = threadIdx.x + NT * q;
-      const int i = e & 63, k = e >> 6;  // A(i, k) and B(k = i', x = j): the same index pattern
+      const int i = e & 63, k = e >> 6;
       const T g = masked(gv[q], opaque_mask(i < c && k < c));
-      const T l = masked(lv[q], opaque_mask(i < c && k < s));
-      double *stg = smem + (k / TK) * stage_doubles<T>();
-      double *stgb = smem + (i / TK) * stage_doubles<T>();
+      double *stg = smem + (k / TK) * stage_doubles<T>() + (k % TK) * PITCH + i;
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        stg[p * TK * PITCH + (k % TK) * PITCH + i] = Planes<T>::get(g, p);           // A plane [kk][i]
-        stgb[(P + p) * TK * PITCH + (i % TK) * PITCH + k] = Planes<T>::get(l, p);    // B plane [kk][x]
-      }
+      for (int p = 0; p < P; ++p) stg[p * TK * PITCH] = Planes<T>::get(g, p);  // A plane [kk][i]
     }
     lds_barrier();
 #pragma unroll
     for (int st = 0; st < 64 / TK; ++st) stage_compute<T>(smem + st * stage_doubles<T>(), acc);
+    // Lhat back out of the B planes before store_xtile reuses the stages
+    T lv[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int i = e & 63, x = e >> 6;
+      lv[q] = Planes<T>::from(smem + (i / TK) * stage_doubles<T>() + P * TK * PITCH + (i % TK) * PITCH + x,
+                              TK * PITCH);
+    }
     lds_barrier();
     // Y = -acc into X_{C,K}
     store_xtile<T, COH>(cx, K, 0, 0, acc, smem);
@@ -473,9 +576,8 @@ __device__ void do_stile(const Ctx<T> &cx, int K, double *smem, int64_t *rt) {
     for (int q = 0; q < Q; ++q) {
       const int e = threadIdx.x + NT * q;
       const int i = e & 63, x = e >> 6;
-      const T l = masked(lv[q], opaque_mask(i < c && x < s));
 #pragma unroll
-      for (int p = 0; p < P; ++p) smem[p * 64 * PITCH + i * PITCH + x] = Planes<T>::get(l, p);
+      for (int p = 0; p < P; ++p) smem[p * 64 * PITCH + i * PITCH + x] = Planes<T>::get(lv[q], p);
     }
     lds_barrier();
     gemm2_block<T>(acc, smem);  // R[p][j * PITCH + x] = (Lhat^T acc)(x, j) = -(Lhat^T Y)(x, j)
@@ -484,8 +586,16 @@ __device__ void do_stile(const Ctx<T> &cx, int K, double *smem, int64_t *rt) {
     for (int e = threadIdx.x; e < 64 * 64; e += NT) lds_put<T>(smem, e >> 6, e & 63, zero_of<T>());
     lds_barrier();
   }
-  // T = Dt^{-1} - Lhat^T Y = Dt^{-1} + R; X_KK = (T + T^T) / 2
+  // T = Dt^{-1} - Lhat^T Y = Dt^{-1} + R; X_KK = (T + T^T) / 2.  Dt^{-1} is
+  // read only now: holding it through both products costs registers.
   double *Tt = smem + tile_doubles<T>();
+  T dv[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int i = e & 63, j = e >> 6;
+    dv[q] = gload(cx.Lp + off + ((((int64_t)j * ld + i) & opaque_mask(i < s && j < s))));
+  }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int e = threadIdx.x + NT * q;

@@ -15,7 +15,9 @@
 //   ITEM_R  (K, a, b): sum of a split node's partial tiles into X, and the row
 //           tile's share of GEMM-2 (split nodes only).
 //   ITEM_D  (K, a, b), a >= b: blocks (a, b) and (b, a) of X_KK = Dt_K^{-1} -
-//           Lhat_{C,K}^T X_{C,K} (step 4), symmetrized (Section 2.3).
+//           Lhat_{C,K}^T X_{C,K} (step 4), symmetrized (Section 2.3).  Nodes
+//           with at least kDSlabRows row tiles split each block pair into
+//           64 / kDSlabW column slabs: b = block | (slab + 1) << 16.
 //   ITEM_S  (K): a node with c <= 64 and s <= 64 done by one workgroup.
 // Phases of a node: 0 = ITEM_G, 1 = ITEM_Y, 2 = ITEM_R, 3 = ITEM_D / ITEM_S
 // (never empty).  A node's first non-empty phase becomes ready when its
@@ -57,6 +59,8 @@ constexpr int kBackR3Phases = 5;
 constexpr int kTileM = 64;   // GEMM-1 rows per item
 constexpr int kTileN = 64;   // columns per item (of s)
 constexpr int kSmallC = 64;  // fused single-item node bounds
+constexpr int kDSlabW = 16;     // column slab of a split ITEM_D
+constexpr int kDSlabRows = 4;   // row tiles from which ITEM_D splits
 constexpr int kSmallS = 64;
 
 struct alignas(16) Item {

@@ -62,11 +62,14 @@ template <> struct Planes<double> {
   static constexpr int P = 1;
   static constexpr int TK = 16;  // contraction step per LDS stage
   static __device__ __forceinline__ double get(double v, int) { return v; }
+  // the value whose planes are q[0], q[stride], ...
+  static __device__ __forceinline__ double from(const double *q, int) { return q[0]; }
 };
 template <> struct Planes<cplx> {
   static constexpr int P = 2;
   static constexpr int TK = 16;
   static __device__ __forceinline__ double get(cplx v, int p) { return p ? v.im : v.re; }
+  static __device__ __forceinline__ cplx from(const double *q, int stride) { return cplx{q[0], q[stride]}; }
 };
 
 template <typename T> __device__ __forceinline__ T zero_of() { return SOps<T>::zero(); }
