@@ -440,75 +440,163 @@ template <typename T, int TK> struct DVals {
   T v[64 * TK / NT];
 };
 
+// Dense operand loaders.  Each thread owns fixed positions of the stage
+// (slot m of thread t is element e = t + NT m); everything that does not move
+// with the stage is computed once, so a full stage costs 64 TK / NT plain
+// loads addressed as (wave-uniform base pointer) + (fixed 32-bit per-thread
+// byte offset) and no per-load arithmetic.  Positions outside the operand are
+// clamped onto valid memory and zeroed when the stage is stored to LDS; a
+// stage that reaches past kend (the last one) clamps its contraction index.
+
+// Load at a (wave-uniform) base plus a 32-bit byte offset, with the addition
+// done on global-space pointers so that it maps onto the scalar-base +
+// vector-offset addressing of the global loads.
+__device__ __forceinline__ double ld_off(const double *base, uint32_t b) {
+  return *reinterpret_cast<const SELINV_GAS double *>(reinterpret_cast<const SELINV_GAS char *>(gp(base)) + b);
+}
+__device__ __forceinline__ cplx ld_off(const cplx *base, uint32_t b) {
+  const SELINV_GAS char *q = reinterpret_cast<const SELINV_GAS char *>(gp(base)) + b;
+  return cplx{*reinterpret_cast<const SELINV_GAS double *>(q), *reinterpret_cast<const SELINV_GAS double *>(q + 8)};
+}
+
 // A(i, k) = G[k * ldg + i0 + i] for i0 + i < rows, k < kend (column-major);
-// lanes run along i, so each column of the stage is one contiguous read.
+// lanes run along i, so each column of the stage is one contiguous read.  The
+// contraction index of a slot, k0 + (t >> 6) + 4 m, is uniform in a wave.
 template <typename T, int TK> struct LoadDenseA {
+  static constexpr int E = 64 * TK / NT;
   const T *G;
-  int ldg, rows, kend, i0;
+  int64_t ldg;
+  int kend, kq;
+  uint32_t vrow;  // byte offset of this thread's row (row 0 when outside)
+  int64_t rmask;
+  bool rows_full;
+  __device__ __forceinline__ LoadDenseA(const T *G_, int ldg_, int rows, int kend_, int i0)
+      : G(G_), ldg(ldg_), kend(kend_) {
+    const int i = i0 + (threadIdx.x & 63);
+    kq = uniform((int)(threadIdx.x >> 6));
+    vrow = (uint32_t)(i < rows ? i : 0) * (uint32_t)sizeof(T);
+    rmask = opaque_mask(i < rows);
+    rows_full = i0 + 64 <= rows;
+  }
   __device__ __forceinline__ int slot(int, int m) const {
     const int e = threadIdx.x + NT * m;
     return (e >> 6) * PITCH + (e & 63);
   }
+  __device__ __forceinline__ bool all_valid(int k0) const { return rows_full && k0 + TK <= kend; }
   __device__ __forceinline__ int64_t mask(int k0, int m) const {
-    const int e = threadIdx.x + NT * m;
-    return opaque_mask(i0 + (e & 63) < rows && k0 + (e >> 6) < kend);
+    return rmask & opaque_mask(k0 + kq + (NT / 64) * m < kend);
   }
   __device__ __forceinline__ void load(int k0, DVals<T, TK> &v) const {
 #pragma unroll
-    for (int m = 0; m < 64 * TK / NT; ++m) {
-      const int e = threadIdx.x + NT * m;
-      const int i = i0 + (e & 63), k = k0 + (e >> 6);
-      v.v[m] = Mem<false>::ld(G + (((int64_t)k * ldg + i) & mask(k0, m)));
+    for (int m = 0; m < E; ++m) {
+      const int k = min(k0 + kq + (NT / 64) * m, kend - 1);
+      v.v[m] = ld_off(G + (int64_t)k * ldg, vrow);
     }
   }
 };
 
 // B(kk, x) = P[off + (x0 + x) * ld + s + k0 + kk] for k0 + kk < kend,
-// x0 + x < xmax: a column block of a panel's bottom part, k-major.
+// x0 + x < xmax: a column block of a panel's bottom part, k-major.  Slot m of
+// a thread is kk = t % TK, x = t / TK + (NT / TK) m.
 template <typename T, int TK> struct LoadDenseB {
-  const T *Pn;
-  int64_t off;
-  int ld, s, kend, x0, xmax;
+  static constexpr int E = 64 * TK / NT;
+  const T *Pn;  // + off
+  int kend, kk, xq, x0, xmax;
+  uint32_t voff[E];  // byte offsets of (x, kk) relative to Pn + k0 (columns clamped)
+  bool cols_full;
+  __device__ __forceinline__ LoadDenseB(const T *Pn_, int64_t off, int ld, int s, int kend_, int x0_, int xmax_)
+      : Pn(Pn_ + off), kend(kend_), x0(x0_), xmax(xmax_) {
+    kk = threadIdx.x % TK;
+    xq = threadIdx.x / TK;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int x = min(x0 + xq + (NT / TK) * m, xmax - 1);
+      voff[m] = (uint32_t)((int64_t)x * ld + s + kk) * (uint32_t)sizeof(T);
+    }
+    cols_full = x0 + 64 <= xmax;
+  }
   __device__ __forceinline__ int slot(int, int m) const {
     const int e = threadIdx.x + NT * m;
     return (e & (TK - 1)) * PITCH + e / TK;
   }
+  __device__ __forceinline__ bool all_valid(int k0) const { return cols_full && k0 + TK <= kend; }
   __device__ __forceinline__ int64_t mask(int k0, int m) const {
-    const int e = threadIdx.x + NT * m;
-    return opaque_mask(k0 + (e & (TK - 1)) < kend && x0 + e / TK < xmax);
+    return opaque_mask(k0 + kk < kend && x0 + xq + (NT / TK) * m < xmax);
   }
   __device__ __forceinline__ void load(int k0, DVals<T, TK> &v) const {
+    if (k0 + TK <= kend) {
+      const T *base = Pn + k0;
 #pragma unroll
-    for (int m = 0; m < 64 * TK / NT; ++m) {
-      const int e = threadIdx.x + NT * m;
-      const int kg = k0 + (e & (TK - 1)), xg = x0 + e / TK;
-      v.v[m] = Mem<false>::ld(Pn + ((((int64_t)xg * ld + s + kg) & mask(k0, m)) + off));
+      for (int m = 0; m < E; ++m) v.v[m] = ld_off(base, voff[m]);
+    } else {  // last stage: clamp kk onto kend - 1
+      const int over = k0 + kk - (kend - 1);
+      const uint32_t back = (uint32_t)(over > 0 ? over : 0) * (uint32_t)sizeof(T);
+      const T *base = Pn + k0;
+#pragma unroll
+      for (int m = 0; m < E; ++m) v.v[m] = ld_off(base, voff[m] - back);
     }
   }
 };
 
 // B(k, x) = M[k * ld + x0 + x] for k < kend, x0 + x < xmax: a row-major view
-// (the transpose of a column-major block); lanes run along x.
+// (the transpose of a column-major block); lanes run along x, and the row of a
+// slot, k0 + (t >> 6) + 4 m, is uniform in a wave.
 template <typename T, int TK> struct LoadDenseBT {
+  static constexpr int E = 64 * TK / NT;
   const T *M;
-  int ld, kend, x0, xmax;
+  int64_t ld;
+  int kend, kq;
+  uint32_t vcol;
+  int64_t cmask;
+  bool cols_full;
+  __device__ __forceinline__ LoadDenseBT(const T *M_, int ld_, int kend_, int x0, int xmax)
+      : M(M_), ld(ld_), kend(kend_) {
+    const int x = x0 + (threadIdx.x & 63);
+    kq = uniform((int)(threadIdx.x >> 6));
+    vcol = (uint32_t)(x < xmax ? x : x0) * (uint32_t)sizeof(T);
+    cmask = opaque_mask(x < xmax);
+    cols_full = x0 + 64 <= xmax;
+  }
   __device__ __forceinline__ int slot(int, int m) const {
     const int e = threadIdx.x + NT * m;
     return (e >> 6) * PITCH + (e & 63);
   }
+  __device__ __forceinline__ bool all_valid(int k0) const { return cols_full && k0 + TK <= kend; }
   __device__ __forceinline__ int64_t mask(int k0, int m) const {
-    const int e = threadIdx.x + NT * m;
-    return opaque_mask(k0 + (e >> 6) < kend && x0 + (e & 63) < xmax);
+    return cmask & opaque_mask(k0 + kq + (NT / 64) * m < kend);
   }
   __device__ __forceinline__ void load(int k0, DVals<T, TK> &v) const {
 #pragma unroll
-    for (int m = 0; m < 64 * TK / NT; ++m) {
-      const int e = threadIdx.x + NT * m;
-      const int k = k0 + (e >> 6), x = x0 + (e & 63);
-      v.v[m] = Mem<false>::ld(M + (((int64_t)k * ld + x) & mask(k0, m)));
+    for (int m = 0; m < E; ++m) {
+      const int k = min(k0 + kq + (NT / 64) * m, kend - 1);
+      v.v[m] = ld_off(M + (int64_t)k * ld, vcol);
     }
   }
 };
+
+// Stage store of the dense loaders: a stage wholly inside the operand (the
+// common case) is stored without masks.
+template <typename T, class L, class V, int TK>
+__device__ __forceinline__ void stage_store_dense(double *stg, int plane_off, int k0, const L &ld, const V &v) {
+  constexpr int P = Planes<T>::P;
+  constexpr int E = sizeof(v.v) / sizeof(v.v[0]);
+  if (uniform(ld.all_valid(k0) ? 1 : 0)) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int slot = ld.slot(k0, m);
+#pragma unroll
+      for (int p = 0; p < P; ++p) stg[(plane_off + p) * TK * PITCH + slot] = Planes<T>::get(v.v[m], p);
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int slot = ld.slot(k0, m);
+      const T x = masked(v.v[m], ld.mask(k0, m));
+#pragma unroll
+      for (int p = 0; p < P; ++p) stg[(plane_off + p) * TK * PITCH + slot] = Planes<T>::get(x, p);
+    }
+  }
+}
 
 template <typename T, int TK> __device__ __forceinline__ constexpr int dense_stage_doubles() {
   return 2 * Planes<T>::P * TK * PITCH;
@@ -534,8 +622,8 @@ __device__ __forceinline__ void gemm_dense(int kb, int ke, const LA &la, const L
   lb.load(kb, b0);
   la.load(kat(1), a1);
   lb.load(kat(1), b1);
-  stage_store<T, LA, V, TK>(smem, 0, kb, la, a0);
-  stage_store<T, LB, V, TK>(smem, P, kb, lb, b0);
+  stage_store_dense<T, LA, V, TK>(smem, 0, kb, la, a0);
+  stage_store_dense<T, LB, V, TK>(smem, P, kb, lb, b0);
   la.load(kat(2), a0);
   lb.load(kat(2), b0);
   lds_barrier();
@@ -543,16 +631,16 @@ __device__ __forceinline__ void gemm_dense(int kb, int ke, const LA &la, const L
     // LDS stage 0 holds kt; set 1 holds kt + 1, set 0 holds kt + 2
     stage_compute<T, TK>(smem, acc);
     if (kt + 1 >= nk) break;
-    stage_store<T, LA, V, TK>(smem + SD, 0, kat(kt + 1), la, a1);
-    stage_store<T, LB, V, TK>(smem + SD, P, kat(kt + 1), lb, b1);
+    stage_store_dense<T, LA, V, TK>(smem + SD, 0, kat(kt + 1), la, a1);
+    stage_store_dense<T, LB, V, TK>(smem + SD, P, kat(kt + 1), lb, b1);
     lds_barrier();
     la.load(kat(kt + 3), a1);
     lb.load(kat(kt + 3), b1);
     __builtin_amdgcn_sched_barrier(0);  // issue the loads before the MFMA block
     stage_compute<T, TK>(smem + SD, acc);
     if (kt + 2 >= nk) break;
-    stage_store<T, LA, V, TK>(smem, 0, kat(kt + 2), la, a0);
-    stage_store<T, LB, V, TK>(smem, P, kat(kt + 2), lb, b0);
+    stage_store_dense<T, LA, V, TK>(smem, 0, kat(kt + 2), la, a0);
+    stage_store_dense<T, LB, V, TK>(smem, P, kat(kt + 2), lb, b0);
     lds_barrier();
     la.load(kat(kt + 4), a0);
     lb.load(kat(kt + 4), b0);
