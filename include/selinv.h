@@ -80,7 +80,9 @@ typedef struct {
                           (gathered once, then read by plain GEMM tiles); 0 = 256, < 0 = never */
   int64_t watchdog_ms; /* persistent kernel spin budget before it aborts (0 = 10000 ms) */
   int64_t dense_max_bytes; /* cap on those buffers for the whole batch; the threshold is doubled
-                              until they fit (0 = 32 GiB) */
+                              until they fit (0 = 32 GiB).  Under SELINV_SCHED_LEVELS the buffers
+                              of different etree depths share memory, so the cap applies to the
+                              largest depth; under SELINV_SCHED_PERSISTENT to their sum */
   int32_t split_min_k; /* shortest contraction part when a node with too few GEMM-1 tiles to fill
                           the GPU splits its contraction over C(K) (0 = 256, < 0 = never split) */
   int32_t reserved;

@@ -212,36 +212,50 @@ void ticket_order(const Symbolic &S, HostPlan &H, int64_t batch) {
 // Nodes with |C(K)| >= the threshold get a dense X_{C,C} buffer; the
 // threshold is the requested one, raised in powers of two until the buffers of
 // the whole batch fit in max_bytes.
+// Dense X_{C,C} buffers for the nodes with c >= threshold.  Under the level
+// schedule a buffer is live only while its own depth runs (the G items fill
+// it, the Y items of the same depth read it; the adjoint sweeps also fill and
+// read it within one depth), so the nodes of each depth are packed from
+// offset 0 of one shared pool and only the largest depth counts against
+// max_bytes.  The persistent schedule overlaps depths: every node gets its own
+// buffer.  The threshold doubles until the footprint fits.
 void choose_dense(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t min_c, int64_t max_bytes,
-                  HostPlan &H) {
+                  bool per_level, HostPlan &H) {
   const int64_t ns = S.nsuper();
   H.node_goff.assign(ns, -1);
   H.node_ldg.assign(ns, 0);
   H.g_elems = 0;
   H.dense_min_c = INT64_MAX;
   if (min_c < 0) return;
+  auto ldg_of = [](int64_t c) { return (c + kPanelAlign - 1) / kPanelAlign * kPanelAlign; };
+  auto footprint = [&](int64_t t) {
+    std::vector<int64_t> per(per_level ? S.depth : 1, 0);
+    for (int64_t K = 0; K < ns; ++K)
+      if (S.nrows(K) >= t) per[per_level ? S.sdepth[K] : 0] += ldg_of(S.nrows(K)) * S.nrows(K);
+    return *std::max_element(per.begin(), per.end());
+  };
   int64_t t = std::max<int64_t>(min_c, kTileM + 1);
   while (true) {
-    int64_t tot = 0;
-    for (int64_t K = 0; K < ns; ++K)
-      if (S.nrows(K) >= t) tot += (S.nrows(K) + kPanelAlign - 1) / kPanelAlign * kPanelAlign * S.nrows(K);
+    const int64_t tot = footprint(t);
     if (tot == 0) return;
     if (tot * batch * scalar_bytes <= max_bytes) break;
     t *= 2;
   }
   H.dense_min_c = t;
+  std::vector<int64_t> next(per_level ? S.depth : 1, 0);
   for (int64_t K = 0; K < ns; ++K) {
     const int64_t c = S.nrows(K);
     if (c < t) continue;
-    const int64_t ldg = (c + kPanelAlign - 1) / kPanelAlign * kPanelAlign;
-    H.node_goff[K] = H.g_elems;
-    H.node_ldg[K] = (int32_t)ldg;
-    H.g_elems += ldg * c;
+    int64_t &o = next[per_level ? S.sdepth[K] : 0];
+    H.node_goff[K] = o;
+    H.node_ldg[K] = (int32_t)ldg_of(c);
+    o += ldg_of(c) * c;
+    H.g_elems = std::max(H.g_elems, o);
   }
 }
 
 void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t dense_min_c, int64_t dense_max_bytes,
-                int64_t split_min_k, HostPlan &H) {
+                int64_t split_min_k, bool per_level, HostPlan &H) {
   const int64_t ns = S.nsuper();
   H.node_s.resize(ns);
   H.node_c.resize(ns);
@@ -310,7 +324,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     }
   }
   // work items, phase by phase (see plan.hpp)
-  choose_dense(S, batch, scalar_bytes, dense_min_c, dense_max_bytes, H);
+  choose_dense(S, batch, scalar_bytes, dense_min_c, dense_max_bytes, per_level, H);
   H.item_ptr.assign(ns + 1, 0);
   H.nph.assign((size_t)kPhases * ns, 0);
   auto nph = [&](int ph, int64_t K) -> int32_t & { return H.nph[(size_t)ph * ns + K]; };
@@ -740,7 +754,7 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *ro
     const int64_t min_c = o.dense_min_c == 0 ? kDefaultDenseMinC : o.dense_min_c;
     const int64_t max_b = o.dense_max_bytes > 0 ? o.dense_max_bytes : kDefaultDenseMaxBytes;
     const int64_t split_k = o.split_min_k == 0 ? kSplitMinK : o.split_min_k;
-    build_plan(h->S, o.batch, h->sbytes(), min_c, max_b, split_k, h->H);
+    build_plan(h->S, o.batch, h->sbytes(), min_c, max_b, split_k, o.sched == SELINV_SCHED_LEVELS, h->H);
     if ((int64_t)h->H.items.size() * (int64_t)o.batch >= (int64_t)INT32_MAX)
       return set_err(h, SELINV_ENOMEM, "too many work items for int32 item ids");
     build_image(h);
