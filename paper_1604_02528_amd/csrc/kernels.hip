@@ -218,80 +218,171 @@ __global__ void __launch_bounds__(NT, 1)
 // Normalization (Alg. 1 steps 1-2)
 // ---------------------------------------------------------------------------
 
-// One thread per row r < s of I_s solving x L_KK = e_r (L_KK unit lower): row r
-// of L_KK^{-1} (scratch, column-major ld s), and D_K^{-1}.  Back substitution
-// in 16-column chunks, L_KK chunks staged in LDS.
+// L_KK^{-1} and D_K^{-1} (Alg. 1 step 1, with the LDL^T factor of Section
+// 2.3: L_KK is unit lower triangular, its diagonal slot holds D).  The
+// columns of X = L_KK^{-1} are independent: one workgroup per 16-column block
+// [j0, j0 + 16) of one node solves L_KK X(:, J) = I(:, J) by forward
+// substitution down 16-row strips, with X(:, J) held in LDS.  Strip I:
+//   X(I, J) = I(I, J) - L(I, j0:I0) X(j0:I0, J)   (all threads, one entry each)
+// then the 16 x 16 unit triangular solve with L(I, I) (one thread per column).
+// The L strip of the next row block is loaded while the current one is used.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_normalize_rows(const DevPlan *__restrict__ plp, const T *Src_all, T *Lp_all, const int2 *chunks,
-                                                       int32_t nchunks) {
+__global__ void __launch_bounds__(NT) k_normalize_inv(const DevPlan *__restrict__ plp, const T *Src_all, const int2 *chunks,
+                                                      int32_t nchunks) {
+  constexpr int P = Planes<T>::P, XP = 17, LPI = 257;
   const DevPlan &pl = *plp;
-  __shared__ double ls[Planes<T>::P][16 * 257];
+  __shared__ double xs[P][256 * XP];  // X(j0 + r, j0 + q) at [r * XP + q]
+  __shared__ double lsd[P][16 * LPI];  // L(I0 + i, j0 + k) at [i * LPI + k]
   const int64_t g = blockIdx.x;
   const int64_t l = g / nchunks;
   const int2 ck = chunks[g - l * nchunks];
-  const int K = ck.x;
-  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
-  const int64_t off = gp(pl.node_off)[K];
-  const T *Q = Src_all + l * pl.panel_elems + off;  // LDL^T panel (read only)
-  T *P = Lp_all + l * pl.panel_elems + off;         // normalized panel (may alias Q)
+  const int K = uniform(ck.x), j0 = uniform(ck.y) * 16;
+  const int s = uniform(gp(pl.node_s)[K]), c = gp(pl.node_c)[K], ld = s + c;
+  const T *Q = Src_all + l * pl.panel_elems + gp(pl.node_off)[K];  // LDL^T panel (read only)
   T *Linv = reinterpret_cast<T *>(pl.linv) + l * pl.sq_elems + gp(pl.node_sq)[K];
   T *dinv = reinterpret_cast<T *>(pl.dinv) + l * pl.n + gp(pl.node_first)[K];
-  const int r = ck.y * NT + threadIdx.x;
-  const bool active = r < s;
-  if (ck.y == 0 && threadIdx.x < s) gstore(dinv + threadIdx.x, SOps<T>::div(SOps<T>::one(), Q[(int64_t)threadIdx.x * ld + threadIdx.x]));
-  for (int jb = ((s - 1) / 16) * 16; jb >= 0; jb -= 16) {
-    const int w = (s - jb < 16) ? s - jb : 16;
-    const int nrow = s - jb;  // rows jb .. s-1 of L_KK, columns jb .. jb+w-1
-    lds_barrier();
-    for (int e = threadIdx.x; e < 16 * nrow; e += NT) {
-      const int q = e / nrow, i = e - q * nrow;
-      T v = zero_of<T>();
-      if (q < w) v = Q[(int64_t)(jb + q) * ld + jb + i];
+  const int w = min(16, s - j0);
+  const int t = threadIdx.x;
+  if (t < w) gstore(dinv + j0 + t, SOps<T>::div(SOps<T>::one(), Q[(int64_t)(j0 + t) * ld + j0 + t]));
+  // strip element u of thread t: i = e & 15, k = e >> 4 with e = t + NT u (k < 256)
+  auto strip_ok = [&](int I0, int u) {
+    const int e = t + NT * u, i = e & 15, k = e >> 4;
+    return k < min(I0 + 16, s) - j0 && I0 + i < s;
+  };
+  T pre[16];
+  auto load_strip = [&](int I0) {
 #pragma unroll
-      for (int p = 0; p < Planes<T>::P; ++p) ls[p][q * 257 + i] = Planes<T>::get(v, p);
+    for (int u = 0; u < 16; ++u) {
+      const int e = t + NT * u, i = e & 15, k = e >> 4;
+      pre[u] = gload(Q + (((int64_t)(j0 + k) * ld + I0 + i) & opaque_mask(strip_ok(I0, u))));
+    }
+  };
+  load_strip(j0);
+  const int ti = t & 15, tq = t >> 4;
+  for (int I0 = j0; I0 < s; I0 += 16) {
+    const int h = min(16, s - I0), r0 = I0 - j0;
+    lds_barrier();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = t + NT * u, i = e & 15, k = e >> 4;
+      const T v = masked(pre[u], opaque_mask(strip_ok(I0, u)));
+#pragma unroll
+      for (int p = 0; p < P; ++p) lsd[p][i * LPI + k] = Planes<T>::get(v, p);
+    }
+    if (I0 + 16 < s) load_strip(I0 + 16);
+    lds_barrier();
+    // X(I0 + ti, j0 + tq) before the diagonal block: identity minus the earlier strips
+    if (ti < h) {
+      T acc = (I0 + ti == j0 + tq) ? SOps<T>::one() : zero_of<T>();
+      for (int k = 0; k < r0; ++k)
+        acc -= Planes<T>::from(&lsd[0][ti * LPI + k], 16 * LPI) * Planes<T>::from(&xs[0][k * XP + tq], 256 * XP);
+#pragma unroll
+      for (int p = 0; p < P; ++p) xs[p][(r0 + ti) * XP + tq] = Planes<T>::get(acc, p);
     }
     lds_barrier();
-    if (active) {
-      T x[16];
+    // unit lower triangular solve with L(I, I), one thread per column
+    if (t < 16) {
+      T xv[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) x[q] = (q < w && r == jb + q) ? SOps<T>::one() : zero_of<T>();
-      // x_i for i beyond the chunk: this thread's own earlier results, read
-      // 16 at a time so the loads overlap (indices past s are clamped and
-      // their values zeroed)
-      for (int ib = jb + w; ib < s; ib += 16) {
-        T xi[16];
+      for (int i = 0; i < 16; ++i) {
+        if (i < h) {
+          T v = Planes<T>::from(&xs[0][(r0 + i) * XP + t], 256 * XP);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) xi[u] = gload(Linv + (int64_t)min(ib + u, s - 1) * s + r);
+          for (int k = 0; k < i; ++k) v -= Planes<T>::from(&lsd[0][i * LPI + r0 + k], 16 * LPI) * xv[k];
+          xv[i] = v;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int ii = min(ib + u, s - 1) - jb;
-          const T xu = masked(xi[u], opaque_mask(ib + u < s));  // zeroed where it is used, not at the load
-#pragma unroll
-          for (int q = 0; q < 16; ++q) {
-            T lv;
-            if constexpr (Planes<T>::P == 1) lv = ls[0][q * 257 + ii];
-            else lv = T{ls[0][q * 257 + ii], ls[1][q * 257 + ii]};
-            x[q] -= xu * lv;
-          }
+          for (int p = 0; p < P; ++p) xs[p][(r0 + i) * XP + t] = Planes<T>::get(v, p);
         }
       }
+    }
+  }
+  lds_barrier();
+  // whole columns j0 .. j0 + w - 1 of L_KK^{-1} (column-major, ld s), zeros above the diagonal
+  for (int q = 0; q < w; ++q)
+    for (int r = t; r < s; r += NT)
+      gstore(Linv + (int64_t)(j0 + q) * s + r,
+             r < j0 ? zero_of<T>() : Planes<T>::from(&xs[0][(r - j0) * XP + q], 256 * XP));
+}
+
+// All of the normalization (Alg. 1 steps 1-2, LDL^T form of Section 2.3) of
+// a node with s <= kSmallNormS in one wavefront: L_KK^{-1} by forward
+// substitution (lane q owns column q), D^{-1}, Dt^{-1} = L_KK^{-T} D^{-1}
+// L_KK^{-1} into the top block, Dt = L_KK D L_KK^T when dt is given, and
+// Lhat_{C,K} = L_{C,K} L_KK^{-1} one row per lane.  L_KK is read into LDS
+// before anything is written, and each row of L_{C,K} is read by the lane that
+// overwrites it, so Src may alias Lp.
+template <typename T>
+__global__ void __launch_bounds__(64) k_normalize_small(const DevPlan *__restrict__ plp, const T *Src_all, T *Lp_all,
+                                                        T *dt_all, const int32_t *__restrict__ nodes, int32_t count) {
+  constexpr int S = kSmallNormS, SP = S + 1;
+  const DevPlan &pl = *plp;
+  __shared__ T lk[S * SP], xs[S * SP], dv[S];
+  const int64_t g = blockIdx.x;
+  const int64_t l = g / count;
+  const int K = nodes[g - l * count];
+  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
+  const int64_t off = gp(pl.node_off)[K];
+  const T *Q = Src_all + l * pl.panel_elems + off;
+  T *P = Lp_all + l * pl.panel_elems + off;
+  T *dinv = reinterpret_cast<T *>(pl.dinv) + l * pl.n + gp(pl.node_first)[K];
+  const int t = threadIdx.x;
 #pragma unroll
-      for (int q = 15; q >= 0; --q) {
-        if (q < w) {
+  for (int u = 0; u < S * S / 64; ++u) {
+    const int e = t + 64 * u, i = e % S, k = e / S;
+    lk[i * SP + k] = (i < s && k < s) ? Q[(int64_t)k * ld + i] : zero_of<T>();
+  }
+  __syncthreads();
+  if (t < s) {
+    const T d = SOps<T>::div(SOps<T>::one(), lk[t * SP + t]);
+    dv[t] = d;
+    gstore(dinv + t, d);
+    T xv[S];
 #pragma unroll
-          for (int q2 = q + 1; q2 < 16; ++q2) {
-            if (q2 < w) {
-              T lv;
-              if constexpr (Planes<T>::P == 1) lv = ls[0][q * 257 + q2];
-              else lv = T{ls[0][q * 257 + q2], ls[1][q * 257 + q2]};
-              x[q] -= x[q2] * lv;
-            }
-          }
+    for (int i = 0; i < S; ++i) {
+      if (i < s) {
+        T v = (i == t) ? SOps<T>::one() : zero_of<T>();
+#pragma unroll
+        for (int k = 0; k < i; ++k)
+          if (k >= t) v -= lk[i * SP + k] * xv[k];
+        xv[i] = v;
+        xs[i * SP + t] = v;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < S * S / 64; ++u) {
+    const int e = t + 64 * u, a = e % S, b = e / S;
+    if (a < s && b < s) {
+      T acc = zero_of<T>();
+      for (int k = a > b ? a : b; k < s; ++k) acc += (xs[k * SP + a] * dv[k]) * xs[k * SP + b];
+      P[(int64_t)b * ld + a] = acc;
+      if (dt_all) {
+        T dd = zero_of<T>();
+        for (int k = 0; k <= (a < b ? a : b); ++k) {
+          const T la = (a == k) ? SOps<T>::one() : lk[a * SP + k], lb = (b == k) ? SOps<T>::one() : lk[b * SP + k];
+          dd += (la * lk[k * SP + k]) * lb;
+        }
+        dt_all[l * pl.sq_elems + gp(pl.node_sq)[K] + (int64_t)b * s + a] = dd;
+      }
+    }
+  }
+  for (int i0 = 0; i0 < c; i0 += 64) {
+    const int i = i0 + t;
+    if (i < c) {
+      T lr[S];
+#pragma unroll
+      for (int k = 0; k < S; ++k) lr[k] = k < s ? Q[(int64_t)k * ld + s + i] : zero_of<T>();
+#pragma unroll
+      for (int q = 0; q < S; ++q) {
+        if (q < s) {
+          T v = zero_of<T>();
+#pragma unroll
+          for (int k = q; k < S; ++k)
+            if (k < s) v += lr[k] * xs[k * SP + q];
+          P[(int64_t)q * ld + s + i] = v;
         }
       }
-#pragma unroll
-      for (int q = 0; q < 16; ++q)
-        if (q < w) gstore(Linv + (int64_t)(jb + q) * s + r, x[q]);
     }
   }
 }
@@ -462,8 +553,12 @@ static hipError_t normalize_impl(const DevPlan &pl, const DevPlan *dpl, const La
                                  void *panels, void *dt, hipStream_t st) {
   const T *Q = reinterpret_cast<const T *>(src);
   T *Lp = reinterpret_cast<T *>(panels);
+  if (aux.nsmall > 0) {
+    hipLaunchKernelGGL(k_normalize_small<T>, dim3((unsigned)(aux.nsmall * pl.batch)), dim3(64), 0, st, dpl, Q, Lp,
+                       reinterpret_cast<T *>(dt), aux.small_nodes, aux.nsmall);
+  }
   if (aux.nchunks > 0) {
-    hipLaunchKernelGGL(k_normalize_rows<T>, dim3((unsigned)(aux.nchunks * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
+    hipLaunchKernelGGL(k_normalize_inv<T>, dim3((unsigned)(aux.nchunks * pl.batch)), dim3(NT), 0, st, dpl, Q,
                        aux.chunks, aux.nchunks);
   }
   if (aux.nrblocks > 0) {

@@ -59,6 +59,7 @@ constexpr int kBackR3Phases = 5;
 constexpr int kTileM = 64;   // GEMM-1 rows per item
 constexpr int kTileN = 64;   // columns per item (of s)
 constexpr int kSmallC = 64;  // fused single-item node bounds
+constexpr int kSmallNormS = 16;  // widest node normalized by the single-wavefront kernel
 constexpr int kDSlabW = 16;     // column slab of a split ITEM_D
 constexpr int kDSlabRows = 4;   // row tiles from which ITEM_D splits
 constexpr int kSmallS = 64;
@@ -125,7 +126,9 @@ struct DevPlan {
 
 // Host-side launch lists (device pointers into the work buffer, except lvl_ptr).
 struct LaunchAux {
-  const int2 *chunks;       // normalization row chunks (K, chunk) of the s x s blocks
+  const int32_t *small_nodes;  // nodes with s <= kSmallNormS, normalized by one wavefront each
+  int32_t nsmall;
+  const int2 *chunks;       // normalization column blocks (K, 16-column block) of L_KK^{-1}
   int32_t nchunks;
   const int2 *rblocks;      // normalization GEMM row blocks (K, 64-row block of C(K))
   int32_t nrblocks;
