@@ -171,14 +171,18 @@ __device__ void gemm2_partial(const Ctx<T> &cx, int K, int a, int b, const Acc<T
   const int i0 = a * 64, j0 = b * 64;
   const int64_t pbase = gp(pl.node_poff)[K] + (int64_t)a * s * s;
   double *Ls = smem;  // Lhat[i0 .. i0+63, q0 .. q0+63] as Ls[p][i * PITCH + x]
-  for (int q0 = 0; q0 < s; q0 += 64) {
-    T lv[64 * 64 / NT];
+  // the next 64 columns of Lhat are loaded while the current block is multiplied
+  T lv[64 * 64 / NT];
+  auto load_l = [&](int q0) {
 #pragma unroll
     for (int q = 0; q < 64 * 64 / NT; ++q) {
       const int e = threadIdx.x + NT * q;
       const int i = e & 63, x = e >> 6;
       lv[q] = gload(cx.Lp + off + (((int64_t)(q0 + x) * ld + s + i0 + i) & opaque_mask(i0 + i < c && q0 + x < s)));
     }
+  };
+  load_l(0);
+  for (int q0 = 0; q0 < s; q0 += 64) {
 #pragma unroll
     for (int q = 0; q < 64 * 64 / NT; ++q) {
       const int e = threadIdx.x + NT * q;
@@ -188,6 +192,7 @@ __device__ void gemm2_partial(const Ctx<T> &cx, int K, int a, int b, const Acc<T
       for (int p = 0; p < P; ++p) Ls[p * 64 * PITCH + i * PITCH + x] = Planes<T>::get(v, p);
     }
     lds_barrier();
+    if (q0 + 64 < s) load_l(q0 + 64);
     gemm2_block<T>(acc, Ls);
     // P = Lhat^T Y = -(Lhat^T acc)
     const double *R = Ls;
@@ -261,16 +266,26 @@ __device__ void do_rtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
   T sum[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) sum[q] = zero_of<T>();
-  for (int p = 0; p < parts; ++p) {
-    T v[Q];
+  // the loads of PB parts are issued together; the sum runs over p in order
+  constexpr int PB = 2 / Planes<T>::P;
+  for (int p0 = 0; p0 < parts; p0 += PB) {
+    T v[PB][Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int e = threadIdx.x + NT * q;
-      const int i = e & 63, j = e >> 6;
-      v[q] = Mem<COH>::ld(Y + (int64_t)p * c * s + (((int64_t)(j0 + j) * c + i0 + i) & opaque_mask(i0 + i < c && j0 + j < s)));
+    for (int pp = 0; pp < PB; ++pp) {
+      const int64_t pbase = (int64_t)min(p0 + pp, parts - 1) * c * s;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int e = threadIdx.x + NT * q;
+        const int i = e & 63, j = e >> 6;
+        v[pp][q] = Mem<COH>::ld(Y + pbase + (((int64_t)(j0 + j) * c + i0 + i) & opaque_mask(i0 + i < c && j0 + j < s)));
+      }
     }
 #pragma unroll
-    for (int q = 0; q < Q; ++q) sum[q] += v[q];
+    for (int pp = 0; pp < PB; ++pp) {
+      const int64_t m = opaque_mask(p0 + pp < parts);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) sum[q] += masked(v[pp][q], m);
+    }
   }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
