@@ -261,6 +261,197 @@ __global__ void __launch_bounds__(NT, 2)
   }
 }
 
+// Small nodes (c <= kTinyC, s <= kTinyS): all of R1 (mode 1) or all of R3
+// (mode 2) of one node in one wavefront, with the same algebra as the tile
+// items above.  X_{C,C} (R1) and Sbar_{C,C} (R3) are read through the node's
+// offset table (lower triangle, row-major), and the R1 scatter goes through
+// the same table.  LDS blocks are [j * kTinyC + i] (c x s) and [j * 8 + i]
+// (s x s).
+
+// acc[j] = (Src_{C,C} B)(i, j), i = lane % CM, for B in LDS; lane groups
+// over the contraction index are combined by a fixed butterfly.
+template <int CM>
+__device__ __forceinline__ void tiny_cc(const TinyRec &r, const int64_t *toff, const double *Src, const double *bs,
+                                        double (&acc)[kTinyS]) {
+  constexpr int G = 64 / CM, U = CM / G;
+  const int lane = threadIdx.x, i = lane % CM, grp = lane / CM;
+  const int s = r.s, c = r.c;
+  int64_t o[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = grp + G * u, hi = i > k ? i : k, lo = i > k ? k : i;
+    o[u] = gp(toff)[(r.tbl + hi * (hi + 1) / 2 + lo) & opaque_mask(i < c && k < c)];
+  }
+  double xv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) xv[u] = gload(Src + o[u]);
+#pragma unroll
+  for (int j = 0; j < kTinyS; ++j) acc[j] = 0.0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = grp + G * u;
+    const double g = masked(xv[u], opaque_mask(i < c && k < c));
+#pragma unroll
+    for (int j = 0; j < kTinyS; ++j)
+      if (j < s) acc[j] += g * bs[j * kTinyC + k];
+  }
+#pragma unroll
+  for (int m = CM; m < 64; m <<= 1)
+#pragma unroll
+    for (int j = 0; j < kTinyS; ++j)
+      if (j < s) acc[j] += shfl_xor_t(acc[j], m);
+}
+
+__device__ __forceinline__ void tiny_cc_any(const TinyRec &r, const int64_t *toff, const double *Src, const double *bs,
+                                            double (&acc)[kTinyS]) {
+  if (r.c <= 8)
+    tiny_cc<8>(r, toff, Src, bs, acc);
+  else if (r.c <= 16)
+    tiny_cc<16>(r, toff, Src, bs, acc);
+  else
+    tiny_cc<32>(r, toff, Src, bs, acc);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(64) k_back_tiny(const DevPlan *__restrict__ plp, const double *panels,
+                                                  const double *x, const double *dt, double *xbar,
+                                                  const TinyRec *__restrict__ recs, int32_t count) {
+  constexpr int TC = kTinyC, TS = kTinyS;
+  const DevPlan &pl = *plp;
+  __shared__ double lh[TS * TC], cb[TS * TC], yb[TS * TC];  // Lhat; Zbar (R1) / M + N (R3); Y Tbar (R1)
+  __shared__ double tb[64], eb[64], fb[64];                   // Tbar (R1) / Dt (R3); E = Dt^{-1}; F (R1) / Dtbar0 (R3)
+  const int64_t g0 = blockIdx.x;
+  const int64_t l = g0 / count;
+  const TinyRec r = recs[g0 - l * count];
+  const int64_t pe = pl.panel_elems, sqe = pl.sq_elems;
+  const double *Lp = panels + l * pe, *Xp = x + l * pe;
+  double *W = xbar + l * pe;
+  double *Lbar = static_cast<double *>(pl.adj_l) + l * pe;
+  double *Sb = static_cast<double *>(pl.adj_s) + l * pe;
+  double *DB = static_cast<double *>(pl.adj_d) + l * sqe;
+  const double *DT = dt + l * sqe;
+  const int s = r.s, c = r.c, lane = threadIdx.x;
+  const int64_t ld = s + c, off = r.off, sq = gp(pl.node_sq)[r.K];
+  const int x8 = lane % 8, y8 = lane / 8;  // (x, y) of an s x s block
+  const bool in_sq = x8 < s && y8 < s;
+#pragma unroll
+  for (int u = 0; u < TS * TC / 64; ++u) {
+    const int e = lane + 64 * u, k = e % TC, j = e / TC;
+    lh[e] = (k < c && j < s) ? Lp[off + j * ld + s + k] : 0.0;
+  }
+  eb[lane] = in_sq ? Lp[off + (int64_t)y8 * ld + x8] : 0.0;
+  if (MODE == 1) {
+    // Tbar = sym(W_KK)
+    double t = 0.0;
+    if (in_sq) {
+      const double w = x8 >= y8 ? W[off + (int64_t)y8 * ld + x8] : W[off + (int64_t)x8 * ld + y8];
+      t = x8 == y8 ? w : 0.5 * w;
+    }
+    tb[lane] = t;
+    __syncthreads();
+    // Zbar = W_{C,K} - Lhat Tbar;  Y Tbar (Y = X_{C,K}).  Every entry of the
+    // Zbar block is written (zeros outside c x s): it is the B operand below.
+    if (lane < TC) {
+      const bool row = lane < c;
+      double yr[TS];
+#pragma unroll
+      for (int k = 0; k < TS; ++k) yr[k] = (row && k < s) ? Xp[off + k * ld + s + lane] : 0.0;
+#pragma unroll
+      for (int j = 0; j < TS; ++j) {
+        double z = 0.0, yt = 0.0;
+        if (row && j < s) {
+          z = W[off + j * ld + s + lane];
+#pragma unroll
+          for (int k = 0; k < TS; ++k) {
+            z -= lh[k * TC + lane] * tb[j * 8 + k];
+            yt += yr[k] * tb[j * 8 + k];
+          }
+        }
+        cb[j * TC + lane] = z;
+        yb[j * TC + lane] = yt;
+      }
+    }
+    __syncthreads();
+    // Lhatbar = -(X_{C,C} Zbar + Y Tbar)
+    double acc[TS];
+    tiny_cc_any(r, pl.toff, Xp, cb, acc);
+    if (lane < c && lane < (c <= 8 ? 8 : c <= 16 ? 16 : 32)) {
+#pragma unroll
+      for (int j = 0; j < TS; ++j)
+        if (j < s) Lbar[off + j * ld + s + lane] = -(acc[j] + yb[j * TC + lane]);
+    }
+    // W[ancestors] -= Zbar Lhat^T + Lhat Zbar^T on the lower part (halved on the diagonal)
+    const int ne = c * (c + 1) / 2;
+    for (int e = lane; e < ne; e += 64) {
+      int i = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+      while (i * (i + 1) / 2 > e) --i;
+      while ((i + 1) * (i + 2) / 2 <= e) ++i;
+      const int k = e - i * (i + 1) / 2;
+      double v = 0.0;
+#pragma unroll
+      for (int j = 0; j < TS; ++j)
+        if (j < s) v += cb[j * TC + i] * lh[j * TC + k] + lh[j * TC + i] * cb[j * TC + k];
+      unsafeAtomicAdd(W + gp(pl.toff)[r.tbl + e], i == k ? -0.5 * v : -v);
+    }
+    // F = Tbar E;  Dtbar0 = -E F
+    if (in_sq) {
+      double f = 0.0;
+      for (int k = 0; k < s; ++k) f += tb[k * 8 + x8] * eb[y8 * 8 + k];
+      fb[lane] = f;
+    }
+    __syncthreads();
+    if (in_sq) {
+      double d = 0.0;
+      for (int k = 0; k < s; ++k) d += eb[k * 8 + x8] * fb[y8 * 8 + k];
+      DB[sq + (int64_t)y8 * s + x8] = -d;
+    }
+  } else {
+    // Dt, Dtbar0
+    tb[lane] = in_sq ? DT[sq + (int64_t)y8 * s + x8] : 0.0;
+    fb[lane] = in_sq ? DB[sq + (int64_t)y8 * s + x8] : 0.0;
+    __syncthreads();
+    // M = Sbar_{C,C} Lhat;  Lb = Lhatbar - 2 M Dt;  N = Lb E;  Sbar_{C,K} = N / 2
+    double m[TS];
+    tiny_cc_any(r, pl.toff, Sb, lh, m);
+    if (lane < c && lane < (c <= 8 ? 8 : c <= 16 ? 16 : 32)) {
+      double lb[TS];
+#pragma unroll
+      for (int j = 0; j < TS; ++j) {
+        double v = 0.0;
+        if (j < s) {
+          double md = 0.0;
+#pragma unroll
+          for (int k = 0; k < TS; ++k)
+            if (k < s) md += m[k] * tb[j * 8 + k];
+          v = Lbar[off + j * ld + s + lane] - 2.0 * md;
+        }
+        lb[j] = v;
+      }
+#pragma unroll
+      for (int j = 0; j < TS; ++j) {
+        if (j < s) {
+          double nv = 0.0;
+#pragma unroll
+          for (int k = 0; k < TS; ++k)
+            if (k < s) nv += lb[k] * eb[j * 8 + k];
+          Sb[off + j * ld + s + lane] = 0.5 * nv;
+          cb[j * TC + lane] = m[j] + nv;
+        }
+      }
+    }
+    __syncthreads();
+    // Sbar_KK = sym(Dtbar0 - Lhat^T (M + N))
+    if (in_sq) {
+      double rxy = 0.0, ryx = 0.0;
+      for (int i = 0; i < c; ++i) {
+        rxy += lh[x8 * TC + i] * cb[y8 * TC + i];
+        ryx += lh[y8 * TC + i] * cb[x8 * TC + i];
+      }
+      Sb[off + (int64_t)y8 * ld + x8] = 0.5 * ((fb[y8 * 8 + x8] - rxy) + (fb[x8 * 8 + y8] - ryx));
+    }
+  }
+}
+
 // Abar on A's pattern (stored-value convention: doubled off the diagonal).
 __global__ void k_abar(const DevPlan *__restrict__ plp, double *abar) {
   const DevPlan &pl = *plp;
@@ -278,12 +469,19 @@ __global__ void k_abar(const DevPlan *__restrict__ plp, double *abar) {
 hipError_t launch_backward(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const void *panels,
                            const void *x, const void *dt, void *xbar, void *abar, hipStream_t st) {
   if (!pl.adj_s) return hipErrorNotSupported;
-  for (int q = 0; q < aux.nblvl; ++q) {
-    const int32_t b = aux.blvl_ptr[q], e = aux.blvl_ptr[q + 1];
-    if (e > b)
-      hipLaunchKernelGGL(k_back_items, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl,
-                         static_cast<const double *>(panels), static_cast<const double *>(x),
-                         static_cast<const double *>(dt), static_cast<double *>(xbar), b, e - b);
+  const double *P = static_cast<const double *>(panels), *X = static_cast<const double *>(x),
+               *D = static_cast<const double *>(dt);
+  double *Wb = static_cast<double *>(xbar);
+  for (int q = 0; q < aux.nblaunch; ++q) {
+    const int4 bl = aux.blaunch[q];  // {kind, first, count}: 0 items, 1 small-node R1, 2 small-node R3
+    if (bl.z <= 0) continue;
+    const dim3 grid((unsigned)(bl.z * pl.batch));
+    if (bl.x == 0)
+      hipLaunchKernelGGL(k_back_items, grid, dim3(NT), 0, st, dpl, P, X, D, Wb, bl.y, bl.z);
+    else if (bl.x == 1)
+      hipLaunchKernelGGL(k_back_tiny<1>, grid, dim3(64), 0, st, dpl, P, X, D, Wb, aux.tiny + bl.y, bl.z);
+    else
+      hipLaunchKernelGGL(k_back_tiny<2>, grid, dim3(64), 0, st, dpl, P, X, D, Wb, aux.tiny + bl.y, bl.z);
   }
   const int64_t total = pl.batch * pl.nnzA;
   unsigned grid = (unsigned)((total + 255) / 256);

@@ -52,7 +52,8 @@ struct HostPlan {
   int64_t dense_min_c = 0;  // threshold in use (INT64_MAX: no dense buffers)
   std::vector<int32_t> order;  // ticket order of the persistent schedule (all matrices)
   std::vector<Item> bitems;    // adjoint items in (sweep, depth, phase) order
-  std::vector<int32_t> blvl_ptr;  // [nblvl + 1] ranges of bitems launched together
+  std::vector<int4> blaunch;   // adjoint launches in order (see LaunchAux)
+  std::vector<int32_t> tiny_dptr;  // [depth + 1] small-node records of each etree depth
   bool adjoint = false;        // adjoint scratch allocated (FP64 only)
   std::vector<int32_t> lvl_items, lvl_ptr, lvl_tiny;
   std::vector<TinyRec> tiny;  // single-wavefront nodes, in launch order
@@ -374,6 +375,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   H.lvl_tiny.clear();
   H.tiny.clear();
   H.toff.clear();
+  H.tiny_dptr.assign(S.depth + 1, 0);
   {
     auto is_tiny = [&](int64_t K) { return H.node_c[K] <= kTinyC && H.node_s[K] <= kTinyS; };
     auto close = [&](int32_t tiny_base) {
@@ -394,6 +396,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
         close(-1);
       }
       const int32_t tiny_base = (int32_t)H.tiny.size();
+      H.tiny_dptr[d] = tiny_base;
       for (int64_t K : bydepth[d]) {
         if (!is_tiny(K)) continue;
         const int32_t it = phase_begin(H, K, 3);
@@ -406,11 +409,14 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
       }
       close(tiny_base);
     }
+    H.tiny_dptr[S.depth] = (int32_t)H.tiny.size();
   }
   // adjoint items: R1 leaves -> root (deepest level first), then R3 root -> leaves
   H.bitems.clear();
-  H.blvl_ptr.assign(1, 0);
+  H.blaunch.clear();
   {
+    auto is_tiny = [&](int64_t K) { return H.node_c[K] <= kTinyC && H.node_s[K] <= kTinyS; };
+    int32_t bstart = 0;
     std::vector<std::vector<int64_t>> bydepth(S.depth);
     for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
     auto emit = [&](int64_t K, int32_t type) {
@@ -441,23 +447,35 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
       }
     };
     auto close = [&]() {
-      if ((int32_t)H.bitems.size() > H.blvl_ptr.back()) H.blvl_ptr.push_back((int32_t)H.bitems.size());
+      const int32_t n = (int32_t)H.bitems.size() - bstart;
+      if (n > 0) H.blaunch.push_back(int4{0, bstart, n, 0});
+      bstart = (int32_t)H.bitems.size();
+    };
+    auto tiny_launch = [&](int64_t d, int32_t kind) {
+      const int32_t n = H.tiny_dptr[d + 1] - H.tiny_dptr[d];
+      if (n > 0) H.blaunch.push_back(int4{kind, H.tiny_dptr[d], n, 0});
     };
     static const int32_t r1[kBackR1Phases][3] = {{BI_T, BI_G, -1}, {BI_Z, -1, -1}, {BI_L, BI_SC, BI_F}, {BI_D0, -1, -1}};
     static const int32_t r3[kBackR3Phases][3] = {{BI_SG, -1, -1}, {BI_M, -1, -1}, {BI_LB, -1, -1}, {BI_N, -1, -1},
                                                  {BI_DF, -1, -1}};
-    for (int64_t d = S.depth - 1; d >= 0; --d)
+    for (int64_t d = S.depth - 1; d >= 0; --d) {
       for (int ph = 0; ph < kBackR1Phases; ++ph) {
         for (int64_t K : bydepth[d])
-          for (int q = 0; q < 3 && r1[ph][q] >= 0; ++q) emit(K, r1[ph][q]);
+          if (!is_tiny(K))
+            for (int q = 0; q < 3 && r1[ph][q] >= 0; ++q) emit(K, r1[ph][q]);
         close();
       }
-    for (int64_t d = 0; d < S.depth; ++d)
+      tiny_launch(d, 1);
+    }
+    for (int64_t d = 0; d < S.depth; ++d) {
       for (int ph = 0; ph < kBackR3Phases; ++ph) {
         for (int64_t K : bydepth[d])
-          for (int q = 0; q < 3 && r3[ph][q] >= 0; ++q) emit(K, r3[ph][q]);
+          if (!is_tiny(K))
+            for (int q = 0; q < 3 && r3[ph][q] >= 0; ++q) emit(K, r3[ph][q]);
         close();
       }
+      tiny_launch(d, 2);
+    }
   }
   // normalization work lists
   H.chunks.clear();
@@ -663,9 +681,8 @@ LaunchAux make_aux(const selinv_ctx *h, void *work) {
   a.lvl_tiny = H.lvl_tiny.data();
   a.tiny = (const TinyRec *)(b + H.off.tiny);
   a.nlvl = (int32_t)H.lvl_ptr.size() - 1;
-  a.blvl_items = nullptr;
-  a.blvl_ptr = H.blvl_ptr.data();
-  a.nblvl = (int32_t)H.blvl_ptr.size() - 1;
+  a.blaunch = H.blaunch.data();
+  a.nblaunch = (int32_t)H.blaunch.size();
   return a;
 }
 

@@ -139,9 +139,9 @@ struct LaunchAux {
   const int32_t *lvl_tiny;  // host array [nlvl]: -1 (work items), else the first TinyRec of the range
   const TinyRec *tiny;      // single-wavefront node records, in launch order
   int32_t nlvl;
-  const int32_t *blvl_items;  // adjoint item ids grouped by (sweep, level, phase)
-  const int32_t *blvl_ptr;    // host array [nblvl + 1]
-  int32_t nblvl;
+  const int4 *blaunch;        // host array: adjoint launches {kind, first, count, 0} in order; kind 0 =
+                              // bitems [first, first + count), 1 / 2 = R1 / R3 of small-node records
+  int32_t nblaunch;
 };
 
 }  // namespace selinv
