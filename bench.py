@@ -378,7 +378,8 @@ def main():
                      "traffic_unit": "HBM bytes per traversal (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, calibrated "
                                      "on a 1 GiB device copy)",
                      "algorithmic_bytes": algorithmic_bytes(w, args.relax),
-                     "kernel": ("k_items_list, one launch per etree level and phase"
+                     "kernel": ("k_items_list (one launch per etree level and phase) with k_tiny (the "
+                                "single-wavefront small nodes of each level)"
                                 if args.sched == "levels" else "k_persistent, one launch"),
                      "selinv_run_ms": round(t_run * 1e3, 4),
                      "note": "achieved = algorithmic flops of the traversal / HIP-event time of selinv_run "
