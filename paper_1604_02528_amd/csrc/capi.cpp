@@ -482,18 +482,25 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   H.rblocks.clear();
   H.sq_tiles.clear();
   H.small_nodes.clear();
-  for (int64_t K = 0; K < ns; ++K) {
-    const int32_t s = H.node_s[K], c = H.node_c[K];
-    if (s <= kSmallNormS) {
-      H.small_nodes.push_back((int32_t)K);
-      continue;
-    }
-    const int32_t nch = (s + 15) / 16;  // 16-column blocks of L_KK^{-1} (s <= 256)
-    for (int32_t q = 0; q < nch; ++q) H.chunks.push_back(int2{(int32_t)K, q});
-    for (int32_t a = 0; a < (c + kTileM - 1) / kTileM; ++a) H.rblocks.push_back(int2{(int32_t)K, a});
-    const int32_t nt = (s + 31) / 32;
-    for (int32_t a = 0; a < nt; ++a)
-      for (int32_t b = 0; b < nt; ++b) H.sq_tiles.push_back(int4{(int32_t)K, a, b, 0});
+  {
+    // root first: the workgroups of the large top nodes, which take longest,
+    // are dispatched first (measured: C2 normalization 0.55 -> 0.45 ms)
+    std::vector<std::vector<int64_t>> bydepth(S.depth);
+    for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
+    for (int64_t d = 0; d < S.depth; ++d)
+      for (int64_t K : bydepth[d]) {
+        const int32_t s = H.node_s[K], c = H.node_c[K];
+        if (s <= kSmallNormS) {
+          H.small_nodes.push_back((int32_t)K);
+          continue;
+        }
+        const int32_t nch = (s + 15) / 16;  // 16-column blocks of L_KK^{-1} (s <= 256)
+        for (int32_t q = 0; q < nch; ++q) H.chunks.push_back(int2{(int32_t)K, q});
+        for (int32_t a = 0; a < (c + kTileM - 1) / kTileM; ++a) H.rblocks.push_back(int2{(int32_t)K, a});
+        const int32_t nt = (s + 31) / 32;
+        for (int32_t a = 0; a < nt; ++a)
+          for (int32_t b = 0; b < nt; ++b) H.sq_tiles.push_back(int4{(int32_t)K, a, b, 0});
+      }
   }
   H.apos = S.apos;
   H.adiag = S.apos_diag;
