@@ -56,6 +56,7 @@ struct HostPlan {
   std::vector<int32_t> tiny_dptr;  // [depth + 1] small-node records of each etree depth
   bool adjoint = false;        // adjoint scratch allocated (FP64 only)
   std::vector<int32_t> lvl_items, lvl_ptr, lvl_tiny;
+  std::vector<Item> lvl_recs;  // the items of lvl_items, copied in level order
   std::vector<TinyRec> tiny;  // single-wavefront nodes, in launch order
   std::vector<int64_t> toff;  // their X_{C,C} offset tables
   std::vector<int2> chunks, rblocks;
@@ -68,7 +69,7 @@ struct HostPlan {
   // byte offsets inside the work buffer
   struct Off {
     int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
-        nph, node_split, node_kchunk, node_yoff, node_goff, node_ldg, node_parent, order, lvl_items, chunks, rblocks, small_nodes,
+        nph, node_split, node_kchunk, node_yoff, node_goff, node_ldg, node_parent, order, lvl_items, lvl_recs, chunks, rblocks, small_nodes,
         sq_tiles, tiny, toff,
         apos, adiag, bitems, plan, linv, dinv, part, gbuf, ypart, cnt, adj_z, adj_l, adj_s, adj_t, adj_f, adj_d, ctrl, end;
   } off{};
@@ -411,6 +412,8 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     }
     H.tiny_dptr[S.depth] = (int32_t)H.tiny.size();
   }
+  H.lvl_recs.resize(H.lvl_items.size());
+  for (size_t q = 0; q < H.lvl_items.size(); ++q) H.lvl_recs[q] = H.items[H.lvl_items[q]];
   // adjoint items: R1 leaves -> root (deepest level first), then R3 root -> leaves
   H.bitems.clear();
   H.blaunch.clear();
@@ -534,6 +537,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.node_parent = take(4 * ns);
   o.order = take(4 * (int64_t)H.order.size());
   o.lvl_items = take(4 * (int64_t)H.lvl_items.size());
+  o.lvl_recs = take((int64_t)sizeof(Item) * (int64_t)H.lvl_items.size());
   o.tiny = take((int64_t)sizeof(TinyRec) * (int64_t)H.tiny.size());
   o.toff = take(8 * (int64_t)H.toff.size());
   o.chunks = take(8 * (int64_t)H.chunks.size());
@@ -684,6 +688,7 @@ LaunchAux make_aux(const selinv_ctx *h, void *work) {
   a.sq_tiles = (const int4 *)(b + H.off.sq_tiles);
   a.nsq_tiles = (int32_t)H.sq_tiles.size();
   a.lvl_items = (const int32_t *)(b + H.off.lvl_items);
+  a.lvl_recs = (const Item *)(b + H.off.lvl_recs);
   a.lvl_ptr = H.lvl_ptr.data();
   a.lvl_tiny = H.lvl_tiny.data();
   a.tiny = (const TinyRec *)(b + H.off.tiny);
@@ -719,6 +724,7 @@ void build_image(selinv_ctx *h) {
   put(img, o.node_parent, H.node_parent);
   put(img, o.order, H.order);
   put(img, o.lvl_items, H.lvl_items);
+  put(img, o.lvl_recs, H.lvl_recs);
   put(img, o.tiny, H.tiny);
   put(img, o.toff, H.toff);
   put(img, o.chunks, H.chunks);

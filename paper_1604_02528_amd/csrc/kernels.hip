@@ -34,23 +34,23 @@ namespace selinv {
 // Schedules
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1) k_items_list(const DevPlan *__restrict__ plp, const T *Lp, T *Xp, T *Pp, const int32_t *list,
-                                                   int32_t count, int32_t list_pos) {
+__global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1) k_items_list(const DevPlan *__restrict__ plp, const T *Lp, T *Xp, T *Pp, const Item *recs,
+                                                   const int32_t *list, int32_t count, int32_t list_pos) {
   const DevPlan &pl = *plp;
   __shared__ double smem[smem_doubles<T>()];
   __shared__ int64_t rt[128];
   const int64_t g = blockIdx.x;
   const int64_t l = g / count;
-  const int32_t it = list[g - l * count];
+  const int64_t q = g - l * count;
   const int64_t t_start = pl.trace ? wall_clock64() : 0;
   Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, Pp + l * pl.part_elems,
             static_cast<T *>(pl.gbuf) + l * pl.g_elems, static_cast<T *>(pl.ypart) + l * pl.y_elems};
-  do_item<T, false>(cx, gload(pl.items + it), smem, rt);
+  do_item<T, false>(cx, gload(recs + q), smem, rt);  // the record itself: no id -> record round trip
   if (pl.trace) {
     __syncthreads();
     if (threadIdx.x == 0) {  // row of this item in the trace: levels in order, matrices inside a level
       int64_t *tr = pl.trace + 8 * ((int64_t)list_pos * pl.batch + g);
-      tr[0] = l * pl.nitems + it;
+      tr[0] = l * pl.nitems + list[q];
       tr[1] = blockIdx.x;
       tr[2] = t_start;
       tr[3] = t_start;
@@ -596,7 +596,7 @@ static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
                            aux.tiny + aux.lvl_tiny[q], e - b, b);
       else
         hipLaunchKernelGGL(k_items_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,
-                           aux.lvl_items + b, e - b, b);
+                           aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
     }
     return hipGetLastError();
   }

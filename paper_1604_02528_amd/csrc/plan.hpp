@@ -135,6 +135,7 @@ struct LaunchAux {
   const int4 *sq_tiles;     // normalization 32 x 32 tiles (K, ti, tj, 0)
   int32_t nsq_tiles;
   const int32_t *lvl_items; // item ids grouped by (level, phase)
+  const Item *lvl_recs;     // the same items' records, in that order
   const int32_t *lvl_ptr;   // host array [nlvl + 1]
   const int32_t *lvl_tiny;  // host array [nlvl]: -1 (work items), else the first TinyRec of the range
   const TinyRec *tiny;      // single-wavefront node records, in launch order
