@@ -244,13 +244,13 @@ __global__ void __launch_bounds__(NT, 2)
   const Geo g = geo(pl, it.K);
   switch (it.type) {
     case BI_T: bi_t(bx, g, it.a, it.b); break;
-    case BI_G: do_gtile<double>(bx.cx, it.K, it.a, it.b, smem, bx.cx.Xp); break;
+    case BI_G: do_gtile<double>(bx.cx, it.K, it.a, it.b, smem, rt, bx.cx.Xp); break;
     case BI_Z: bi_z(bx, g, it.a, it.b, smem); break;
     case BI_L: bi_l(bx, g, it.a, it.b, smem, rt); break;
     case BI_SC: bi_sc(bx, g, it.a, it.b, smem); break;
     case BI_F: bi_f(bx, g, it.a, it.b, smem); break;
     case BI_D0: bi_d0(bx, g, it.a, it.b, smem); break;
-    case BI_SG: do_gtile<double>(bx.cx, it.K, it.a, it.b, smem, bx.S); break;
+    case BI_SG: do_gtile<double>(bx.cx, it.K, it.a, it.b, smem, rt, bx.S); break;
     case BI_M: bi_m(bx, g, it.a, it.b, smem, rt); break;
     case BI_LB: bi_lb(bx, g, it.a, it.b, smem); break;
     case BI_N: bi_n(bx, g, it.K, it.a, it.b, smem); break;

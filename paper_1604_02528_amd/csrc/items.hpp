@@ -34,7 +34,7 @@ template <typename T> struct Ctx {
 // wave and step) for the gather and the G(i, k) stores; the mirror stores go
 // through an LDS transpose so that they are contiguous too.
 template <typename T>
-__device__ void do_gtile(const Ctx<T> &cx, int K, int a, int b, double *smem, const T *Src) {
+__device__ void do_gtile(const Ctx<T> &cx, int K, int a, int b, double *smem, int64_t *rt, const T *Src) {
   const DevPlan &pl = *cx.pl;
   const int c = uniform(gp(pl.node_c)[K]);
   const int64_t rp = gp(pl.node_rowptr)[K];
@@ -42,29 +42,37 @@ __device__ void do_gtile(const Ctx<T> &cx, int K, int a, int b, double *smem, co
   T *G = cx.Gp + gp(pl.node_goff)[K];
   const int i0 = a * 64, k0 = b * 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  constexpr int Q = 64 * 64 / NT, QH = Q / 2;
-  for (int h = 0; h < 2; ++h) {
-    int64_t pidx[QH], base[QH], msk[QH];
+  constexpr int Q = 64 * 64 / NT;
+  // three dependent rounds: the gather tables of the block's 64 columns (into
+  // LDS), the positions of all of a thread's elements, then their values.
+  // Element q of a thread: row i = i0 + lane, column k = k0 + w + 4 q.
+  if (threadIdx.x < 64) {
+    const int k = k0 + threadIdx.x;
+    const int64_t kq = k < c ? k : 0;
+    rt[threadIdx.x] = gp(pl.kcol)[rp + kq];
+    rt[64 + threadIdx.x] = gp(pl.kpos)[rp + kq];
+  }
+  lds_barrier();
+  const int i = i0 + lane;
+  int32_t pos[Q];
 #pragma unroll
-    for (int q = 0; q < QH; ++q) {
-      const int kl = w + 4 * (QH * h + q), i = i0 + lane, k = k0 + kl;
-      msk[q] = opaque_mask(i < c && k < c && i >= k);
-      const int64_t kq = (int64_t)(k < c ? k : 0);
-      base[q] = gp(pl.kcol)[rp + kq];
-      pidx[q] = (gp(pl.kpos)[rp + kq] + i) & msk[q];
-    }
-    int64_t addr[QH];
+  for (int q = 0; q < Q; ++q) {
+    const int kl = w + 4 * q, k = k0 + kl;
+    pos[q] = gp(pl.posarr)[(rt[64 + kl] + i) & opaque_mask(i < c && k < c && i >= k)];
+  }
+  T v[Q];
 #pragma unroll
-    for (int q = 0; q < QH; ++q) addr[q] = (base[q] + (int64_t)gp(pl.posarr)[pidx[q]]) & msk[q];
-    T v[QH];
+  for (int q = 0; q < Q; ++q) {
+    const int kl = w + 4 * q, k = k0 + kl;
+    v[q] = Mem<false>::ld(Src + ((rt[kl] + (int64_t)pos[q]) & opaque_mask(i < c && k < c && i >= k)));
+  }
 #pragma unroll
-    for (int q = 0; q < QH; ++q) v[q] = masked(Mem<false>::ld(Src + addr[q]), msk[q]);
-#pragma unroll
-    for (int q = 0; q < QH; ++q) {
-      const int kl = w + 4 * (QH * h + q), i = i0 + lane, k = k0 + kl;
-      lds_put<T>(smem, lane, kl, v[q]);  // tile[i][k] at smem[k * PITCH + i]
-      if (i < c && k < c && i >= k) Mem<false>::st(G + (int64_t)k * ldg + i, v[q]);
-    }
+  for (int q = 0; q < Q; ++q) {
+    const int kl = w + 4 * q, k = k0 + kl;
+    const bool ok = i < c && k < c && i >= k;
+    const T x = masked(v[q], opaque_mask(ok));
+    lds_put<T>(smem, lane, kl, x);  // tile[i][k] at smem[k * PITCH + i]
+    if (ok) Mem<false>::st(G + (int64_t)k * ldg + i, x);
   }
   lds_barrier();
   // mirror: G(k, i) = tile[i][k], lanes along k
@@ -708,7 +716,7 @@ template <typename T, bool COH>
 __device__ void do_item(const Ctx<T> &cx, const Item &item, double *smem, int64_t *rt) {
   const Item it = uniform(item);
   if (it.type == ITEM_G) {
-    do_gtile<T>(cx, it.K, it.a, it.b, smem, cx.Xp);
+    do_gtile<T>(cx, it.K, it.a, it.b, smem, rt, cx.Xp);
   } else if (it.type == ITEM_Y) {
     do_ytile<T, COH>(cx, it.K, it.a, it.b, smem, rt);
   } else if (it.type == ITEM_R) {
