@@ -59,7 +59,7 @@ struct HostPlan {
   std::vector<Item> lvl_recs;  // the items of lvl_items, copied in level order
   std::vector<TinyRec> tiny;  // single-wavefront nodes, in launch order
   std::vector<int64_t> toff;  // their X_{C,C} offset tables
-  std::vector<int2> chunks, rblocks;
+  std::vector<int2> chunks, chunks_narrow, rblocks;
   std::vector<int32_t> small_nodes;  // normalized by the single-wavefront kernel
   std::vector<int4> sq_tiles;
   std::vector<int64_t> apos;
@@ -69,7 +69,7 @@ struct HostPlan {
   // byte offsets inside the work buffer
   struct Off {
     int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
-        nph, node_split, node_kchunk, node_yoff, node_goff, node_ldg, node_parent, order, lvl_items, lvl_recs, chunks, rblocks, small_nodes,
+        nph, node_split, node_kchunk, node_yoff, node_goff, node_ldg, node_parent, order, lvl_items, lvl_recs, chunks, chunks_narrow, rblocks, small_nodes,
         sq_tiles, tiny, toff,
         apos, adiag, bitems, plan, linv, dinv, part, gbuf, ypart, cnt, adj_z, adj_l, adj_s, adj_t, adj_f, adj_d, ctrl, end;
   } off{};
@@ -482,6 +482,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   }
   // normalization work lists
   H.chunks.clear();
+  H.chunks_narrow.clear();
   H.rblocks.clear();
   H.sq_tiles.clear();
   H.small_nodes.clear();
@@ -498,7 +499,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
           continue;
         }
         const int32_t nch = (s + 15) / 16;  // 16-column blocks of L_KK^{-1} (s <= 256)
-        for (int32_t q = 0; q < nch; ++q) H.chunks.push_back(int2{(int32_t)K, q});
+        for (int32_t q = 0; q < nch; ++q) (s <= 64 ? H.chunks_narrow : H.chunks).push_back(int2{(int32_t)K, q});
         for (int32_t a = 0; a < (c + kTileM - 1) / kTileM; ++a) H.rblocks.push_back(int2{(int32_t)K, a});
         const int32_t nt = (s + 31) / 32;
         for (int32_t a = 0; a < nt; ++a)
@@ -541,6 +542,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.tiny = take((int64_t)sizeof(TinyRec) * (int64_t)H.tiny.size());
   o.toff = take(8 * (int64_t)H.toff.size());
   o.chunks = take(8 * (int64_t)H.chunks.size());
+  o.chunks_narrow = take(8 * (int64_t)H.chunks_narrow.size());
   o.small_nodes = take(4 * (int64_t)H.small_nodes.size());
   o.rblocks = take(8 * (int64_t)H.rblocks.size());
   o.sq_tiles = take(16 * (int64_t)H.sq_tiles.size());
@@ -683,6 +685,8 @@ LaunchAux make_aux(const selinv_ctx *h, void *work) {
   a.nsmall = (int32_t)H.small_nodes.size();
   a.chunks = (const int2 *)(b + H.off.chunks);
   a.nchunks = (int32_t)H.chunks.size();
+  a.chunks_narrow = (const int2 *)(b + H.off.chunks_narrow);
+  a.nchunks_narrow = (int32_t)H.chunks_narrow.size();
   a.rblocks = (const int2 *)(b + H.off.rblocks);
   a.nrblocks = (int32_t)H.rblocks.size();
   a.sq_tiles = (const int4 *)(b + H.off.sq_tiles);
@@ -728,6 +732,7 @@ void build_image(selinv_ctx *h) {
   put(img, o.tiny, H.tiny);
   put(img, o.toff, H.toff);
   put(img, o.chunks, H.chunks);
+  put(img, o.chunks_narrow, H.chunks_narrow);
   put(img, o.small_nodes, H.small_nodes);
   put(img, o.rblocks, H.rblocks);
   put(img, o.sq_tiles, H.sq_tiles);

@@ -226,12 +226,14 @@ __global__ void __launch_bounds__(NT, 1)
 //   X(I, J) = I(I, J) - L(I, j0:I0) X(j0:I0, J)   (all threads, one entry each)
 // then the 16 x 16 unit triangular solve with L(I, I) (one thread per column).
 // The L strip of the next row block is loaded while the current one is used.
-template <typename T>
+// MAXS bounds s for the nodes of the launch (256, or 64 for a launch of narrow
+// nodes with a quarter of the LDS, so that more workgroups share a CU).
+template <typename T, int MAXS>
 __global__ void __launch_bounds__(NT) k_normalize_inv(const DevPlan *__restrict__ plp, const T *Src_all, const int2 *chunks,
                                                       int32_t nchunks) {
-  constexpr int P = Planes<T>::P, XP = 17, LPI = 257;
+  constexpr int P = Planes<T>::P, XP = 17, LPI = MAXS + 1, U = MAXS / 16;
   const DevPlan &pl = *plp;
-  __shared__ double xs[P][256 * XP];  // X(j0 + r, j0 + q) at [r * XP + q]
+  __shared__ double xs[P][MAXS * XP];  // X(j0 + r, j0 + q) at [r * XP + q]
   __shared__ double lsd[P][16 * LPI];  // L(I0 + i, j0 + k) at [i * LPI + k]
   const int64_t g = blockIdx.x;
   const int64_t l = g / nchunks;
@@ -244,15 +246,15 @@ __global__ void __launch_bounds__(NT) k_normalize_inv(const DevPlan *__restrict_
   const int w = min(16, s - j0);
   const int t = threadIdx.x;
   if (t < w) gstore(dinv + j0 + t, SOps<T>::div(SOps<T>::one(), Q[(int64_t)(j0 + t) * ld + j0 + t]));
-  // strip element u of thread t: i = e & 15, k = e >> 4 with e = t + NT u (k < 256)
+  // strip element u of thread t: i = e & 15, k = e >> 4 with e = t + NT u (k < MAXS)
   auto strip_ok = [&](int I0, int u) {
     const int e = t + NT * u, i = e & 15, k = e >> 4;
     return k < min(I0 + 16, s) - j0 && I0 + i < s;
   };
-  T pre[16];
+  T pre[U];
   auto load_strip = [&](int I0) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int e = t + NT * u, i = e & 15, k = e >> 4;
       pre[u] = gload(Q + (((int64_t)(j0 + k) * ld + I0 + i) & opaque_mask(strip_ok(I0, u))));
     }
@@ -263,7 +265,7 @@ __global__ void __launch_bounds__(NT) k_normalize_inv(const DevPlan *__restrict_
     const int h = min(16, s - I0), r0 = I0 - j0;
     lds_barrier();
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int e = t + NT * u, i = e & 15, k = e >> 4;
       const T v = masked(pre[u], opaque_mask(strip_ok(I0, u)));
 #pragma unroll
@@ -275,7 +277,7 @@ __global__ void __launch_bounds__(NT) k_normalize_inv(const DevPlan *__restrict_
     if (ti < h) {
       T acc = (I0 + ti == j0 + tq) ? SOps<T>::one() : zero_of<T>();
       for (int k = 0; k < r0; ++k)
-        acc -= Planes<T>::from(&lsd[0][ti * LPI + k], 16 * LPI) * Planes<T>::from(&xs[0][k * XP + tq], 256 * XP);
+        acc -= Planes<T>::from(&lsd[0][ti * LPI + k], 16 * LPI) * Planes<T>::from(&xs[0][k * XP + tq], MAXS * XP);
 #pragma unroll
       for (int p = 0; p < P; ++p) xs[p][(r0 + ti) * XP + tq] = Planes<T>::get(acc, p);
     }
@@ -286,7 +288,7 @@ __global__ void __launch_bounds__(NT) k_normalize_inv(const DevPlan *__restrict_
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         if (i < h) {
-          T v = Planes<T>::from(&xs[0][(r0 + i) * XP + t], 256 * XP);
+          T v = Planes<T>::from(&xs[0][(r0 + i) * XP + t], MAXS * XP);
 #pragma unroll
           for (int k = 0; k < i; ++k) v -= Planes<T>::from(&lsd[0][i * LPI + r0 + k], 16 * LPI) * xv[k];
           xv[i] = v;
@@ -301,7 +303,7 @@ __global__ void __launch_bounds__(NT) k_normalize_inv(const DevPlan *__restrict_
   for (int q = 0; q < w; ++q)
     for (int r = t; r < s; r += NT)
       gstore(Linv + (int64_t)(j0 + q) * s + r,
-             r < j0 ? zero_of<T>() : Planes<T>::from(&xs[0][(r - j0) * XP + q], 256 * XP));
+             r < j0 ? zero_of<T>() : Planes<T>::from(&xs[0][(r - j0) * XP + q], MAXS * XP));
 }
 
 // All of the normalization (Alg. 1 steps 1-2, LDL^T form of Section 2.3) of
@@ -396,7 +398,10 @@ template <typename T>
 __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
     k_normalize_gemm(const DevPlan *__restrict__ plp, const T *Src_all, T *Lp_all, const int2 *rblocks, int32_t nrb) {
   const DevPlan &pl = *plp;
-  __shared__ double smem[smem_doubles<T>()];
+  // two GEMM stages or one 64 x 64 result tile, whichever is larger (complex:
+  // half of smem_doubles, so that two workgroups share a CU)
+  constexpr int kStages = 2 * dense_stage_doubles<T, DenseTK<T>::TK>();
+  __shared__ double smem[kStages > tile_doubles<T>() ? kStages : tile_doubles<T>()];
   constexpr int TK = DenseTK<T>::TK;
   const int64_t g = blockIdx.x;
   const int64_t l = g / nrb;
@@ -557,8 +562,11 @@ static hipError_t normalize_impl(const DevPlan &pl, const DevPlan *dpl, const La
     hipLaunchKernelGGL(k_normalize_small<T>, dim3((unsigned)(aux.nsmall * pl.batch)), dim3(64), 0, st, dpl, Q, Lp,
                        reinterpret_cast<T *>(dt), aux.small_nodes, aux.nsmall);
   }
+  if (aux.nchunks_narrow > 0)
+    hipLaunchKernelGGL((k_normalize_inv<T, 64>), dim3((unsigned)(aux.nchunks_narrow * pl.batch)), dim3(NT), 0, st, dpl,
+                       Q, aux.chunks_narrow, aux.nchunks_narrow);
   if (aux.nchunks > 0) {
-    hipLaunchKernelGGL(k_normalize_inv<T>, dim3((unsigned)(aux.nchunks * pl.batch)), dim3(NT), 0, st, dpl, Q,
+    hipLaunchKernelGGL((k_normalize_inv<T, 256>), dim3((unsigned)(aux.nchunks * pl.batch)), dim3(NT), 0, st, dpl, Q,
                        aux.chunks, aux.nchunks);
   }
   if (aux.nrblocks > 0) {

@@ -128,8 +128,10 @@ struct DevPlan {
 struct LaunchAux {
   const int32_t *small_nodes;  // nodes with s <= kSmallNormS, normalized by one wavefront each
   int32_t nsmall;
-  const int2 *chunks;       // normalization column blocks (K, 16-column block) of L_KK^{-1}
+  const int2 *chunks;       // normalization column blocks (K, 16-column block) of L_KK^{-1}, s > 64
   int32_t nchunks;
+  const int2 *chunks_narrow;  // the same for 16 < s <= 64
+  int32_t nchunks_narrow;
   const int2 *rblocks;      // normalization GEMM row blocks (K, 64-row block of C(K))
   int32_t nrblocks;
   const int4 *sq_tiles;     // normalization 32 x 32 tiles (K, ti, tj, 0)
