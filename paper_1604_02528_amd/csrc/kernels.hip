@@ -334,21 +334,14 @@ __global__ void __launch_bounds__(64) k_normalize_small(const DevPlan *__restric
     lk[i * SP + k] = (i < s && k < s) ? Q[(int64_t)k * ld + i] : zero_of<T>();
   }
   __syncthreads();
-  if (t < s) {
+  if (t < s) {  // column t of L_KK^{-1}, kept in LDS (only this lane touches it)
     const T d = SOps<T>::div(SOps<T>::one(), lk[t * SP + t]);
     dv[t] = d;
     gstore(dinv + t, d);
-    T xv[S];
-#pragma unroll
-    for (int i = 0; i < S; ++i) {
-      if (i < s) {
-        T v = (i == t) ? SOps<T>::one() : zero_of<T>();
-#pragma unroll
-        for (int k = 0; k < i; ++k)
-          if (k >= t) v -= lk[i * SP + k] * xv[k];
-        xv[i] = v;
-        xs[i * SP + t] = v;
-      }
+    for (int i = 0; i < s; ++i) {
+      T v = (i == t) ? SOps<T>::one() : zero_of<T>();
+      for (int k = t; k < i; ++k) v -= lk[i * SP + k] * xs[k * SP + t];
+      xs[i * SP + t] = v;
     }
   }
   __syncthreads();
@@ -375,15 +368,13 @@ __global__ void __launch_bounds__(64) k_normalize_small(const DevPlan *__restric
       T lr[S];
 #pragma unroll
       for (int k = 0; k < S; ++k) lr[k] = k < s ? Q[(int64_t)k * ld + s + i] : zero_of<T>();
+#pragma unroll 1
+      for (int q = 0; q < s; ++q) {
+        T v = zero_of<T>();
 #pragma unroll
-      for (int q = 0; q < S; ++q) {
-        if (q < s) {
-          T v = zero_of<T>();
-#pragma unroll
-          for (int k = q; k < S; ++k)
-            if (k < s) v += lr[k] * xs[k * SP + q];
-          P[(int64_t)q * ld + s + i] = v;
-        }
+        for (int k = 0; k < S; ++k)
+          if (k >= q) v += lr[k] * xs[k * SP + q];
+        P[(int64_t)q * ld + s + i] = v;
       }
     }
   }
