@@ -216,7 +216,7 @@ __device__ void bi_n(const BCtx &bx, const Geo &g, int K, int a, int b, double *
         const double mv = masked(M[((int64_t)j * g.ld + i) & m], m);
         acc.v[0][bi][bj][v] = -(mv + masked(acc.v[0][bi][bj][v], m));
       }
-  gemm2_partial<double, false>(bx.cx, K, a, b, acc, smem);
+  gemm2_partial<double, false>(bx.cx, node_info(*bx.cx.pl, K), a, b, acc, smem);
 }
 
 __global__ void __launch_bounds__(NT, 2)
@@ -244,18 +244,18 @@ __global__ void __launch_bounds__(NT, 2)
   const Geo g = geo(pl, it.K);
   switch (it.type) {
     case BI_T: bi_t(bx, g, it.a, it.b); break;
-    case BI_G: do_gtile<double>(bx.cx, it.K, it.a, it.b, smem, rt, bx.cx.Xp); break;
+    case BI_G: do_gtile<double>(bx.cx, node_info(pl, it.K), it.a, it.b, smem, rt, bx.cx.Xp); break;
     case BI_Z: bi_z(bx, g, it.a, it.b, smem); break;
     case BI_L: bi_l(bx, g, it.a, it.b, smem, rt); break;
     case BI_SC: bi_sc(bx, g, it.a, it.b, smem); break;
     case BI_F: bi_f(bx, g, it.a, it.b, smem); break;
     case BI_D0: bi_d0(bx, g, it.a, it.b, smem); break;
-    case BI_SG: do_gtile<double>(bx.cx, it.K, it.a, it.b, smem, rt, bx.S); break;
+    case BI_SG: do_gtile<double>(bx.cx, node_info(pl, it.K), it.a, it.b, smem, rt, bx.S); break;
     case BI_M: bi_m(bx, g, it.a, it.b, smem, rt); break;
     case BI_LB: bi_lb(bx, g, it.a, it.b, smem); break;
     case BI_N: bi_n(bx, g, it.K, it.a, it.b, smem); break;
     case BI_DF:
-      dtile_core<double, false>(bx.cx, it.K, it.a, it.b, smem, bx.DB + g.sq, g.s, bx.S + g.off, g.ld);
+      dtile_core<double, false>(bx.cx, node_info(pl, it.K), it.a, it.b, smem, bx.DB + g.sq, g.s, bx.S + g.off, g.ld);
       break;
     default: break;
   }

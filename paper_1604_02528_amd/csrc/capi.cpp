@@ -56,7 +56,7 @@ struct HostPlan {
   std::vector<int32_t> tiny_dptr;  // [depth + 1] small-node records of each etree depth
   bool adjoint = false;        // adjoint scratch allocated (FP64 only)
   std::vector<int32_t> lvl_items, lvl_ptr, lvl_tiny;
-  std::vector<Item> lvl_recs;  // the items of lvl_items, copied in level order
+  std::vector<LRec> lvl_recs;  // the items of lvl_items with their nodes, in level order
   std::vector<TinyRec> tiny;  // single-wavefront nodes, in launch order
   std::vector<int64_t> toff;  // their X_{C,C} offset tables
   std::vector<int2> chunks, chunks_narrow, rblocks;
@@ -413,7 +413,23 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     H.tiny_dptr[S.depth] = (int32_t)H.tiny.size();
   }
   H.lvl_recs.resize(H.lvl_items.size());
-  for (size_t q = 0; q < H.lvl_items.size(); ++q) H.lvl_recs[q] = H.items[H.lvl_items[q]];
+  for (size_t q = 0; q < H.lvl_items.size(); ++q) {
+    const Item &it = H.items[H.lvl_items[q]];
+    const int64_t K = it.K;
+    NodeInfo n{};
+    n.K = it.K;
+    n.s = H.node_s[K];
+    n.c = H.node_c[K];
+    n.ldg = H.node_ldg[K];
+    n.split = H.node_split[K];
+    n.kchunk = H.node_kchunk[K];
+    n.off = H.node_off[K];
+    n.rp = H.node_rowptr[K];
+    n.goff = H.node_goff[K];
+    n.poff = H.node_poff[K];
+    n.yoff = H.node_yoff[K];
+    H.lvl_recs[q] = LRec{it, n};
+  }
   // adjoint items: R1 leaves -> root (deepest level first), then R3 root -> leaves
   H.bitems.clear();
   H.blaunch.clear();
@@ -538,7 +554,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.node_parent = take(4 * ns);
   o.order = take(4 * (int64_t)H.order.size());
   o.lvl_items = take(4 * (int64_t)H.lvl_items.size());
-  o.lvl_recs = take((int64_t)sizeof(Item) * (int64_t)H.lvl_items.size());
+  o.lvl_recs = take((int64_t)sizeof(LRec) * (int64_t)H.lvl_items.size());
   o.tiny = take((int64_t)sizeof(TinyRec) * (int64_t)H.tiny.size());
   o.toff = take(8 * (int64_t)H.toff.size());
   o.chunks = take(8 * (int64_t)H.chunks.size());
@@ -692,7 +708,7 @@ LaunchAux make_aux(const selinv_ctx *h, void *work) {
   a.sq_tiles = (const int4 *)(b + H.off.sq_tiles);
   a.nsq_tiles = (int32_t)H.sq_tiles.size();
   a.lvl_items = (const int32_t *)(b + H.off.lvl_items);
-  a.lvl_recs = (const Item *)(b + H.off.lvl_recs);
+  a.lvl_recs = (const LRec *)(b + H.off.lvl_recs);
   a.lvl_ptr = H.lvl_ptr.data();
   a.lvl_tiny = H.lvl_tiny.data();
   a.tiny = (const TinyRec *)(b + H.off.tiny);

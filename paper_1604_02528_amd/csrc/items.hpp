@@ -26,6 +26,47 @@ template <typename T> struct Ctx {
   T *Yp;        // partial GEMM-1 tiles of this matrix (split nodes)
 };
 
+// The same from a record (wave-uniform values, kept in scalar registers).
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = uniform((int32_t)(uint32_t)v), hi = uniform((int32_t)(v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ NodeInfo uniform(const NodeInfo &a) {
+  NodeInfo n = a;
+  n.K = uniform(a.K);
+  n.s = uniform(a.s);
+  n.c = uniform(a.c);
+  n.ldg = uniform(a.ldg);
+  n.split = uniform(a.split);
+  n.kchunk = uniform(a.kchunk);
+  n.off = uniform64(a.off);
+  n.rp = uniform64(a.rp);
+  n.goff = uniform64(a.goff);
+  n.poff = uniform64(a.poff);
+  n.yoff = uniform64(a.yoff);
+  return n;
+}
+
+// NodeInfo from the plan's node tables (the persistent schedule and the
+// adjoint, whose items carry only the node index).
+__device__ __forceinline__ NodeInfo node_info(const DevPlan &pl, int K) {
+  NodeInfo n;
+  n.K = K;
+  n.s = uniform(gp(pl.node_s)[K]);
+  n.c = uniform(gp(pl.node_c)[K]);
+  n.ldg = uniform(gp(pl.node_ldg)[K]);
+  n.split = uniform(gp(pl.node_split)[K]);
+  n.kchunk = uniform(gp(pl.node_kchunk)[K]);
+  n.pad0 = n.pad1 = 0;
+  n.off = uniform64(gp(pl.node_off)[K]);
+  n.rp = uniform64(gp(pl.node_rowptr)[K]);
+  n.goff = uniform64(gp(pl.node_goff)[K]);
+  n.poff = uniform64(gp(pl.node_poff)[K]);
+  n.yoff = uniform64(gp(pl.node_yoff)[K]);
+  n.pad2 = 0;
+  return n;
+}
+
 // Block (a, b), a >= b, of X_{C,C} for a node with a dense buffer G (column
 // major, leading dimension ldg): element (i, k), i >= k, is the lower-part
 // entry Src[kcol[k] + posarr[kpos[k] + i]] of the ancestor owning column k
@@ -34,12 +75,12 @@ template <typename T> struct Ctx {
 // wave and step) for the gather and the G(i, k) stores; the mirror stores go
 // through an LDS transpose so that they are contiguous too.
 template <typename T>
-__device__ void do_gtile(const Ctx<T> &cx, int K, int a, int b, double *smem, int64_t *rt, const T *Src) {
+__device__ void do_gtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, double *smem, int64_t *rt, const T *Src) {
   const DevPlan &pl = *cx.pl;
-  const int c = uniform(gp(pl.node_c)[K]);
-  const int64_t rp = gp(pl.node_rowptr)[K];
-  const int ldg = gp(pl.node_ldg)[K];
-  T *G = cx.Gp + gp(pl.node_goff)[K];
+  const int c = uniform(nd.c);
+  const int64_t rp = nd.rp;
+  const int ldg = nd.ldg;
+  T *G = cx.Gp + nd.goff;
   const int i0 = a * 64, k0 = b * 64;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   constexpr int Q = 64 * 64 / NT;
@@ -88,10 +129,10 @@ __device__ void do_gtile(const Ctx<T> &cx, int K, int a, int b, double *smem, in
 // Store -acc (a 64 x 64 tile of X_{C,K} = -X_{C,C} Lhat) into X, rows 64a..
 // of C(K) and columns 64b.. of K, through LDS so that the stores coalesce.
 template <typename T, bool COH>
-__device__ void store_xtile(const Ctx<T> &cx, int K, int a, int b, const Acc<T> &acc, double *smem) {
+__device__ void store_xtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, const Acc<T> &acc, double *smem) {
   const DevPlan &pl = *cx.pl;
-  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
-  const int64_t off = gp(pl.node_off)[K];
+  const int s = nd.s, c = nd.c, ld = s + c;
+  const int64_t off = nd.off;
   const int i0 = a * 64, j0 = b * 64;
   acc_to_lds<T>(acc, smem);
   lds_barrier();
@@ -171,13 +212,13 @@ __device__ void gemm2_block(const Acc<T> &acc, double *Ls) {
 // tile a, :]^T Y[tile a, 64b..] = -(Lhat_a^T acc), written to the partial
 // buffer (column-major s x s per row tile).
 template <typename T, bool COH>
-__device__ void gemm2_partial(const Ctx<T> &cx, int K, int a, int b, const Acc<T> &acc, double *smem) {
+__device__ void gemm2_partial(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, const Acc<T> &acc, double *smem) {
   constexpr int P = Planes<T>::P;
   const DevPlan &pl = *cx.pl;
-  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
-  const int64_t off = gp(pl.node_off)[K];
+  const int s = nd.s, c = nd.c, ld = s + c;
+  const int64_t off = nd.off;
   const int i0 = a * 64, j0 = b * 64;
-  const int64_t pbase = gp(pl.node_poff)[K] + (int64_t)a * s * s;
+  const int64_t pbase = nd.poff + (int64_t)a * s * s;
   double *Ls = smem;  // Lhat[i0 .. i0+63, q0 .. q0+63] as Ls[p][i * PITCH + x]
   // the next 64 columns of Lhat are loaded while the current block is multiplied
   T lv[64 * 64 / NT];
@@ -218,20 +259,20 @@ __device__ void gemm2_partial(const Ctx<T> &cx, int K, int a, int b, const Acc<T
 // share of [0, c).  An unsplit node stores Y = -acc into X and its row tile's
 // share of GEMM-2 (step 4); a split node stores acc as a partial tile.
 template <typename T, bool COH>
-__device__ void do_ytile(const Ctx<T> &cx, int K, int a, int bp, double *smem, int64_t *rt) {
+__device__ void do_ytile(const Ctx<T> &cx, const NodeInfo &nd, int a, int bp, double *smem, int64_t *rt) {
   const DevPlan &pl = *cx.pl;
-  const int s = uniform(gp(pl.node_s)[K]), c = uniform(gp(pl.node_c)[K]), ld = s + c;
-  const int64_t off = gp(pl.node_off)[K], rp = gp(pl.node_rowptr)[K];
-  const int64_t goff = gp(pl.node_goff)[K];
+  const int s = uniform(nd.s), c = uniform(nd.c), ld = s + c;
+  const int64_t off = nd.off, rp = nd.rp;
+  const int64_t goff = nd.goff;
   const int b = bp & 0xffff, part = bp >> 16;
-  const int parts = uniform(gp(pl.node_split)[K]), kchunk = uniform(gp(pl.node_kchunk)[K]);
+  const int parts = uniform(nd.split), kchunk = uniform(nd.kchunk);
   const int kb = part * kchunk, ke = min(c, kb + kchunk);
   const int i0 = a * 64, j0 = b * 64;
   Acc<T> acc;
   if (uniform(goff >= 0 ? 1 : 0)) {  // X_{C,C} already gathered into the dense buffer
     constexpr int TK = DenseTK<T>::TK;
     const T *G = static_cast<const T *>(cx.Gp) + goff;
-    LoadDenseA<T, TK> la{G, gp(pl.node_ldg)[K], c, ke, i0};
+    LoadDenseA<T, TK> la{G, nd.ldg, c, ke, i0};
     LoadDenseB<T, TK> lb{cx.Lp, off, ld, s, ke, j0, s};
     gemm_dense<T>(kb, ke, la, lb, smem, acc);
   } else {
@@ -246,12 +287,12 @@ __device__ void do_ytile(const Ctx<T> &cx, int K, int a, int bp, double *smem, i
     gemm_tile<T>(kb, ke, la, lb, smem, acc);
   }
   if (parts == 1) {
-    store_xtile<T, COH>(cx, K, a, b, acc, smem);
-    gemm2_partial<T, COH>(cx, K, a, b, acc, smem);
+    store_xtile<T, COH>(cx, nd, a, b, acc, smem);
+    gemm2_partial<T, COH>(cx, nd, a, b, acc, smem);
     return;
   }
   // partial tile of a split node: Ypart[part] (column-major c x s)
-  T *Y = static_cast<T *>(cx.Yp) + gp(pl.node_yoff)[K] + (int64_t)part * c * s;
+  T *Y = static_cast<T *>(cx.Yp) + nd.yoff + (int64_t)part * c * s;
   acc_to_lds<T>(acc, smem);
   lds_barrier();
   for (int e = threadIdx.x; e < 64 * 64; e += NT) {
@@ -264,11 +305,11 @@ __device__ void do_ytile(const Ctx<T> &cx, int K, int a, int bp, double *smem, i
 // Sum of a split node's partial tiles (a, b) into X, then the row tile's share
 // of GEMM-2 (the step-3 and step-4 work that an unsplit tile does itself).
 template <typename T, bool COH>
-__device__ void do_rtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
+__device__ void do_rtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, double *smem) {
   const DevPlan &pl = *cx.pl;
-  const int s = uniform(gp(pl.node_s)[K]), c = uniform(gp(pl.node_c)[K]);
-  const int parts = uniform(gp(pl.node_split)[K]);
-  const T *Y = static_cast<const T *>(cx.Yp) + gp(pl.node_yoff)[K];
+  const int s = uniform(nd.s), c = uniform(nd.c);
+  const int parts = uniform(nd.split);
+  const T *Y = static_cast<const T *>(cx.Yp) + nd.yoff;
   const int i0 = a * 64, j0 = b * 64;
   constexpr int Q = 64 * 64 / NT;
   T sum[Q];
@@ -320,20 +361,20 @@ __device__ void do_rtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
           acc.v[p][bi][bj][v] = smem[p * 64 * PITCH + j * PITCH + i];
         }
   lds_barrier();
-  store_xtile<T, COH>(cx, K, a, b, acc, smem);
-  gemm2_partial<T, COH>(cx, K, a, b, acc, smem);
+  store_xtile<T, COH>(cx, nd, a, b, acc, smem);
+  gemm2_partial<T, COH>(cx, nd, a, b, acc, smem);
 }
 
 // Blocks (a, b) and (b, a), a >= b, of sym(Src - sum_r P_r) into Dst, where
 // Src and Dst are s x s column-major with leading dimensions sld and dld and
 // P_r are the node's row-tile partial products.
 template <typename T, bool COH>
-__device__ void dtile_core(const Ctx<T> &cx, int K, int a, int b, double *smem, const T *Dti, int sld, T *Xkk,
+__device__ void dtile_core(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, double *smem, const T *Dti, int sld, T *Xkk,
                            int dld) {
   const DevPlan &pl = *cx.pl;
-  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K];
+  const int s = nd.s, c = nd.c;
   const int nr = (c + 63) / 64;
-  const int64_t pb = gp(pl.node_poff)[K];
+  const int64_t pb = nd.poff;
   const int64_t ss = (int64_t)s * s;
   const int a0 = a * 64, b0 = b * 64;
   double *Sab = smem, *Sba = smem + tile_doubles<T>();
@@ -413,14 +454,14 @@ __device__ void dtile_core(const Ctx<T> &cx, int K, int a, int b, double *smem, 
 // (b, a)), for nodes with many row tiles: with a quarter of the elements per
 // thread, the loads of several row tiles' partials are in flight together.
 template <typename T, bool COH>
-__device__ void dtile_slab(const Ctx<T> &cx, int K, int a, int b, int sl, double *smem, const T *Dti, int sld, T *Xkk,
+__device__ void dtile_slab(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, int sl, double *smem, const T *Dti, int sld, T *Xkk,
                            int dld) {
   constexpr int W = kDSlabW, QE = 64 * W / NT;
   constexpr int R = Planes<T>::P == 1 ? 4 : 2;  // row tiles per round trip
   const DevPlan &pl = *cx.pl;
-  const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K];
+  const int s = nd.s, c = nd.c;
   const int nr = uniform((c + 63) / 64);
-  const int64_t pb = gp(pl.node_poff)[K];
+  const int64_t pb = nd.poff;
   const int64_t ss = (int64_t)s * s;
   const int a0 = a * 64, b0 = b * 64 + sl * W;
   // element q of a thread: (i, j) = (e % 64, e / 64) of the (a, b) slab, and
@@ -493,16 +534,16 @@ __device__ void dtile_slab(const Ctx<T> &cx, int K, int a, int b, int sl, double
 }
 
 template <typename T, bool COH>
-__device__ void do_dtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
+__device__ void do_dtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, double *smem) {
   const DevPlan &pl = *cx.pl;
-  const int ld = gp(pl.node_s)[K] + gp(pl.node_c)[K];
-  const int64_t off = gp(pl.node_off)[K];
+  const int ld = nd.s + nd.c;
+  const int64_t off = nd.off;
   // top block of the normalized panel = Dt^{-1}; top block of the X panel.
   // b carries the slab number + 1 in its high half for slab items.
   if (b >> 16)
-    dtile_slab<T, COH>(cx, K, a, b & 0xffff, (b >> 16) - 1, smem, cx.Lp + off, ld, cx.Xp + off, ld);
+    dtile_slab<T, COH>(cx, nd, a, b & 0xffff, (b >> 16) - 1, smem, cx.Lp + off, ld, cx.Xp + off, ld);
   else
-    dtile_core<T, COH>(cx, K, a, b, smem, cx.Lp + off, ld, cx.Xp + off, ld);
+    dtile_core<T, COH>(cx, nd, a, b, smem, cx.Lp + off, ld, cx.Xp + off, ld);
 }
 
 // A whole node with c <= 64 and s <= 64 in one workgroup (Alg. 1 steps 3-4
@@ -512,12 +553,12 @@ __device__ void do_dtile(const Ctx<T> &cx, int K, int a, int b, double *smem) {
 // both index C(K)); (3) the values of X_{C,C}.  GEMM-1, GEMM-2 and the
 // diagonal block then run from LDS; nothing goes through the partial buffer.
 template <typename T, bool COH>
-__device__ void do_stile(const Ctx<T> &cx, int K, double *smem, int64_t *rt) {
+__device__ void do_stile(const Ctx<T> &cx, const NodeInfo &nd, double *smem, int64_t *rt) {
   constexpr int P = Planes<T>::P, TK = Planes<T>::TK;
   constexpr int Q = 64 * 64 / NT;
   const DevPlan &pl = *cx.pl;
-  const int s = uniform(gp(pl.node_s)[K]), c = uniform(gp(pl.node_c)[K]), ld = s + c;
-  const int64_t off = gp(pl.node_off)[K], rp = gp(pl.node_rowptr)[K];
+  const int s = uniform(nd.s), c = uniform(nd.c), ld = s + c;
+  const int64_t off = nd.off, rp = nd.rp;
   // round 1: row tables into LDS; Lhat (c x s) straight into the B planes of
   // the four GEMM-1 stages (B(k, x) = Lhat(k, x): plane [kk][x] of stage k / TK)
   if (threadIdx.x < 64) {
@@ -593,7 +634,7 @@ __device__ void do_stile(const Ctx<T> &cx, int K, double *smem, int64_t *rt) {
     }
     lds_barrier();
     // Y = -acc into X_{C,K}
-    store_xtile<T, COH>(cx, K, 0, 0, acc, smem);
+    store_xtile<T, COH>(cx, nd, 0, 0, acc, smem);
     // Lhat into LDS as Ls[p][i * PITCH + x], then R = Lhat^T acc
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -712,19 +753,22 @@ __device__ __forceinline__ void do_tiny(const TinyRec &r, const int64_t *toff, c
   }
 }
 
+// Inlined into the kernels, so that the node record stays in scalar registers
+// (a call would pass it through the stack).
 template <typename T, bool COH>
-__device__ void do_item(const Ctx<T> &cx, const Item &item, double *smem, int64_t *rt) {
+__device__ __forceinline__ void do_item(const Ctx<T> &cx, const Item &item, const NodeInfo &nd, double *smem,
+                                        int64_t *rt) {
   const Item it = uniform(item);
   if (it.type == ITEM_G) {
-    do_gtile<T>(cx, it.K, it.a, it.b, smem, rt, cx.Xp);
+    do_gtile<T>(cx, nd, it.a, it.b, smem, rt, cx.Xp);
   } else if (it.type == ITEM_Y) {
-    do_ytile<T, COH>(cx, it.K, it.a, it.b, smem, rt);
+    do_ytile<T, COH>(cx, nd, it.a, it.b, smem, rt);
   } else if (it.type == ITEM_R) {
-    do_rtile<T, COH>(cx, it.K, it.a, it.b, smem);
+    do_rtile<T, COH>(cx, nd, it.a, it.b, smem);
   } else if (it.type == ITEM_D) {
-    do_dtile<T, COH>(cx, it.K, it.a, it.b, smem);
+    do_dtile<T, COH>(cx, nd, it.a, it.b, smem);
   } else {  // ITEM_S: the whole node (c <= 64, s <= 64) in this workgroup
-    do_stile<T, COH>(cx, it.K, smem, rt);
+    do_stile<T, COH>(cx, nd, smem, rt);
   }
 }
 

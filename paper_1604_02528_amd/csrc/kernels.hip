@@ -34,7 +34,7 @@ namespace selinv {
 // Schedules
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1) k_items_list(const DevPlan *__restrict__ plp, const T *Lp, T *Xp, T *Pp, const Item *recs,
+__global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1) k_items_list(const DevPlan *__restrict__ plp, const T *Lp, T *Xp, T *Pp, const LRec *recs,
                                                    const int32_t *list, int32_t count, int32_t list_pos) {
   const DevPlan &pl = *plp;
   __shared__ double smem[smem_doubles<T>()];
@@ -45,7 +45,9 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1) k_items_list(co
   const int64_t t_start = pl.trace ? wall_clock64() : 0;
   Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, Pp + l * pl.part_elems,
             static_cast<T *>(pl.gbuf) + l * pl.g_elems, static_cast<T *>(pl.ypart) + l * pl.y_elems};
-  do_item<T, false>(cx, gload(recs + q), smem, rt);  // the record itself: no id -> record round trip
+  // the record carries the item and its node: one dependent load before the operands
+  const LRec rec = recs[q];
+  do_item<T, false>(cx, rec.it, uniform(rec.nd), smem, rt);
   if (pl.trace) {
     __syncthreads();
     if (threadIdx.x == 0) {  // row of this item in the trace: levels in order, matrices inside a level
@@ -192,7 +194,7 @@ __global__ void __launch_bounds__(NT, 1)
     const Item it = uniform(gload(pl.items + itn));
     Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, Pp + l * pl.part_elems,
             static_cast<T *>(pl.gbuf) + l * pl.g_elems, static_cast<T *>(pl.ypart) + l * pl.y_elems};
-    do_item<T, false>(cx, it, smem, rt);
+    do_item<T, false>(cx, it, node_info(pl, it.K), smem, rt);
     // Publishing protocol: write back this item's stores (agent-scope release)
     // before the counter update.  Readers use plain cached loads: every panel
     // and partial block starts on its own cache line, and a node's data is

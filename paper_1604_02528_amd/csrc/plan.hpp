@@ -68,6 +68,19 @@ struct alignas(16) Item {
   int32_t K, type, a, b;
 };
 
+// What a traversal item reads about its node.  The level launches carry it in
+// each item's record, so an item's first dependent load is its record alone.
+struct alignas(16) NodeInfo {
+  int32_t K, s, c, ldg;      // node, width, |C(K)|, leading dimension of its dense X_{C,C} buffer
+  int32_t split, kchunk, pad0, pad1;  // GEMM-1 contraction parts and their length
+  int64_t off, rp, goff;     // panel offset, first row of C(K) in the row tables, dense buffer (-1: none)
+  int64_t poff, yoff, pad2;  // GEMM-2 partial products, partial tiles of a split contraction
+};
+struct alignas(16) LRec {
+  Item it;
+  NodeInfo nd;
+};
+
 // Nodes small enough for one wavefront (c <= kTinyC, s <= kTinyS) skip the
 // 64 x 64 tile machinery in the level schedule: one record each, in launch
 // order, and a host-built table of the absolute X offsets of the lower
@@ -137,7 +150,7 @@ struct LaunchAux {
   const int4 *sq_tiles;     // normalization 32 x 32 tiles (K, ti, tj, 0)
   int32_t nsq_tiles;
   const int32_t *lvl_items; // item ids grouped by (level, phase)
-  const Item *lvl_recs;     // the same items' records, in that order
+  const LRec *lvl_recs;     // the same items' records with their nodes, in that order
   const int32_t *lvl_ptr;   // host array [nlvl + 1]
   const int32_t *lvl_tiny;  // host array [nlvl]: -1 (work items), else the first TinyRec of the range
   const TinyRec *tiny;      // single-wavefront node records, in launch order
