@@ -264,27 +264,26 @@ __global__ void __launch_bounds__(NT, 2)
 // Small nodes (c <= kTinyC, s <= kTinyS): all of R1 (mode 1) or all of R3
 // (mode 2) of one node in one wavefront, with the same algebra as the tile
 // items above.  X_{C,C} (R1) and Sbar_{C,C} (R3) are read through the node's
-// offset table (lower triangle, row-major), and the R1 scatter goes through
+// offset table (c x c row-major byte offsets), and the R1 scatter goes through
 // the same table.  LDS blocks are [j * kTinyC + i] (c x s) and [j * 8 + i]
 // (s x s).
 
 // acc[j] = (Src_{C,C} B)(i, j), i = lane % CM, for B in LDS; lane groups
 // over the contraction index are combined by a fixed butterfly.
 template <int CM>
-__device__ __forceinline__ void tiny_cc(const TinyRec &r, const int64_t *toff, const double *Src, const double *bs,
+__device__ __forceinline__ void tiny_cc(const TinyRec &r, const uint32_t *toff, const double *Src, const double *bs,
                                         double (&acc)[kTinyS]) {
   constexpr int G = 64 / CM, U = CM / G;
   const int lane = threadIdx.x, i = lane % CM, grp = lane / CM;
   const int s = r.s, c = r.c;
-  int64_t o[U];
+  const uint32_t *tb = toff + r.tbl;
+  const uint32_t rowb = 4u * ((uint32_t)(i * c + grp) & opaque_mask32(i < c));
+  uint32_t o[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int k = grp + G * u, hi = i > k ? i : k, lo = i > k ? k : i;
-    o[u] = gp(toff)[(r.tbl + hi * (hi + 1) / 2 + lo) & opaque_mask(i < c && k < c)];
-  }
+  for (int u = 0; u < U; ++u) o[u] = ld_off(tb, rowb + 4u * (G * u));
   double xv[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) xv[u] = gload(Src + o[u]);
+  for (int u = 0; u < U; ++u) xv[u] = ld_off(Src, o[u]);
 #pragma unroll
   for (int j = 0; j < kTinyS; ++j) acc[j] = 0.0;
 #pragma unroll
@@ -302,7 +301,7 @@ __device__ __forceinline__ void tiny_cc(const TinyRec &r, const int64_t *toff, c
       if (j < s) acc[j] += shfl_xor_t(acc[j], m);
 }
 
-__device__ __forceinline__ void tiny_cc_any(const TinyRec &r, const int64_t *toff, const double *Src, const double *bs,
+__device__ __forceinline__ void tiny_cc_any(const TinyRec &r, const uint32_t *toff, const double *Src, const double *bs,
                                             double (&acc)[kTinyS]) {
   if (r.c <= 8)
     tiny_cc<8>(r, toff, Src, bs, acc);
@@ -391,7 +390,8 @@ __global__ void __launch_bounds__(64) k_back_tiny(const DevPlan *__restrict__ pl
 #pragma unroll
       for (int j = 0; j < TS; ++j)
         if (j < s) v += cb[j * TC + i] * lh[j * TC + k] + lh[j * TC + i] * cb[j * TC + k];
-      unsafeAtomicAdd(W + gp(pl.toff)[r.tbl + e], i == k ? -0.5 * v : -v);
+      unsafeAtomicAdd(reinterpret_cast<double *>(reinterpret_cast<char *>(W) + gp(pl.toff)[r.tbl + i * c + k]),
+                      i == k ? -0.5 * v : -v);
     }
     // F = Tbar E;  Dtbar0 = -E F
     if (in_sq) {

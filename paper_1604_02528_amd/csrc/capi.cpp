@@ -54,11 +54,12 @@ struct HostPlan {
   std::vector<Item> bitems;    // adjoint items in (sweep, depth, phase) order
   std::vector<int4> blaunch;   // adjoint launches in order (see LaunchAux)
   std::vector<int32_t> tiny_dptr;  // [depth + 1] small-node records of each etree depth
+  std::vector<int32_t> tiny_dadj;  // [depth] end of each depth's c <= kTinyC prefix (the adjoint's)
   bool adjoint = false;        // adjoint scratch allocated (FP64 only)
   std::vector<int32_t> lvl_items, lvl_ptr, lvl_tiny;
   std::vector<LRec> lvl_recs;  // the items of lvl_items with their nodes, in level order
   std::vector<TinyRec> tiny;  // single-wavefront nodes, in launch order
-  std::vector<int64_t> toff;  // their X_{C,C} offset tables
+  std::vector<uint32_t> toff;  // their X_{C,C} tables (byte offsets into the panel array)
   std::vector<int2> chunks, chunks_narrow, rblocks;
   std::vector<int32_t> small_nodes;  // normalized by the single-wavefront kernel
   std::vector<int4> sq_tiles;
@@ -113,8 +114,9 @@ double item_cost_ns(const HostPlan &H, const Item &it) {
     }
     case ITEM_R: {
       const double m = std::min<double>(kTileM, c - (double)kTileM * it.a);
-      const double nn = std::min<double>(kTileN, s - (double)kTileN * it.b);
-      return 1500.0 + H.node_split[it.K] * m * nn * 8.0 / 60.0 + (2.0 * s * m * nn) / 150.0;
+      const double nn = std::min<double>(kTileN, s - (double)kTileN * (it.b & 0xffff));
+      const double rq = std::max(1, it.b >> 24);
+      return 1500.0 + H.node_split[it.K] * m * nn * 8.0 / 60.0 + (2.0 * s * m * nn) / 150.0 / rq;
     }
     case ITEM_D: {
       const double nr = std::ceil(c / kTileM);
@@ -328,6 +330,14 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   }
   // work items, phase by phase (see plan.hpp)
   choose_dense(S, batch, scalar_bytes, dense_min_c, dense_max_bytes, per_level, H);
+  // GEMM-2 shares of the R items: a depth whose R tiles (over the batch)
+  // cannot fill the GPU cuts each tile's share into rq items by 64-row blocks
+  // of P (the R phase of the top separator chain is otherwise one long item
+  // per tile).
+  std::vector<int64_t> rtiles(S.depth, 0);
+  for (int64_t K = 0; K < ns; ++K)
+    if (H.node_split[K] > 1)
+      rtiles[S.sdepth[K]] += batch * ((S.nrows(K) + kTileM - 1) / kTileM) * ((S.width(K) + kTileN - 1) / kTileN);
   H.item_ptr.assign(ns + 1, 0);
   H.nph.assign((size_t)kPhases * ns, 0);
   auto nph = [&](int ph, int64_t K) -> int32_t & { return H.nph[(size_t)ph * ns + K]; };
@@ -354,9 +364,13 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
           for (int32_t a = 0; a < nr; ++a) H.items.push_back(Item{(int32_t)K, ITEM_Y, a, b | (p << 16)});
       nph(1, K) = nr * nb * parts;
       if (parts > 1) {
-        for (int32_t b = 0; b < nb; ++b)
-          for (int32_t a = 0; a < nr; ++a) H.items.push_back(Item{(int32_t)K, ITEM_R, a, b});
-        nph(2, K) = nr * nb;
+        const int64_t nq = (s + kTileN - 1) / kTileN;
+        const int32_t rq = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nq, kSplitTarget / rtiles[S.sdepth[K]]));
+        for (int32_t r = 0; r < rq; ++r)
+          for (int32_t b = 0; b < nb; ++b)
+            for (int32_t a = 0; a < nr; ++a)
+              H.items.push_back(Item{(int32_t)K, ITEM_R, a, rq > 1 ? b | (r << 16) | (rq << 24) : b});
+        nph(2, K) = nr * nb * rq;
       }
     }
     const int32_t nsl = nr >= kDSlabRows ? 64 / kDSlabW : 1;
@@ -377,8 +391,13 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   H.tiny.clear();
   H.toff.clear();
   H.tiny_dptr.assign(S.depth + 1, 0);
+  H.tiny_dadj.assign(S.depth, 0);
+  // small nodes address X through 32-bit byte offsets
+  const bool tiny_ok = S.panel_elems * scalar_bytes < (int64_t(1) << 32);
+  const int64_t tiny_cf = scalar_bytes == 8 ? kTinyCF : kTinyC;
+  auto adj_tiny = [&](int64_t K) { return tiny_ok && H.node_c[K] <= kTinyC && H.node_s[K] <= kTinyS; };
   {
-    auto is_tiny = [&](int64_t K) { return H.node_c[K] <= kTinyC && H.node_s[K] <= kTinyS; };
+    auto is_tiny = [&](int64_t K) { return tiny_ok && H.node_c[K] <= tiny_cf && H.node_s[K] <= kTinyS; };
     auto close = [&](int32_t tiny_base) {
       if ((int32_t)H.lvl_items.size() > H.lvl_ptr.back()) {
         H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
@@ -398,15 +417,27 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
       }
       const int32_t tiny_base = (int32_t)H.tiny.size();
       H.tiny_dptr[d] = tiny_base;
-      for (int64_t K : bydepth[d]) {
-        if (!is_tiny(K)) continue;
-        const int32_t it = phase_begin(H, K, 3);
-        const int64_t c = H.node_c[K], rp = S.rowptr[K];
-        H.lvl_items.push_back(it);
-        H.tiny.push_back(TinyRec{(int32_t)K, it, H.node_s[K], (int32_t)c, S.panel_off[K], (int64_t)H.toff.size()});
-        // X(row i, row k), i >= k, lives in the panel of row k's supernode
-        for (int64_t i = 0; i < c; ++i)
-          for (int64_t k = 0; k <= i; ++k) H.toff.push_back(H.kcol[rp + k] + S.posarr[H.kpos[rp + k] + i]);
+      // the adjoint's nodes (c <= kTinyC) first, then the forward-only ones
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int64_t K : bydepth[d]) {
+          if (!is_tiny(K) || adj_tiny(K) != (pass == 0)) continue;
+          const int32_t it = phase_begin(H, K, 3);
+          const int64_t c = H.node_c[K], rp = S.rowptr[K];
+          H.lvl_items.push_back(it);
+          H.tiny.push_back(TinyRec{(int32_t)K, it, H.node_s[K], (int32_t)c, S.panel_off[K], (int64_t)H.toff.size()});
+          // X(row i, row k), i >= k, lives in the panel of row k's supernode;
+          // the table is c x c (both triangles), then one padding row of
+          // offset 0 so that the loads of columns k < 64 of any row stay in it
+          const size_t t0 = H.toff.size();
+          H.toff.resize(t0 + c * c + kTinyCF, 0u);
+          for (int64_t i = 0; i < c; ++i)
+            for (int64_t k = 0; k <= i; ++k) {
+              const uint32_t v = (uint32_t)((H.kcol[rp + k] + S.posarr[H.kpos[rp + k] + i]) * scalar_bytes);
+              H.toff[t0 + i * c + k] = v;
+              H.toff[t0 + k * c + i] = v;
+            }
+        }
+        if (pass == 0) H.tiny_dadj[d] = (int32_t)H.tiny.size();
       }
       close(tiny_base);
     }
@@ -434,7 +465,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   H.bitems.clear();
   H.blaunch.clear();
   {
-    auto is_tiny = [&](int64_t K) { return H.node_c[K] <= kTinyC && H.node_s[K] <= kTinyS; };
+    auto is_tiny = adj_tiny;
     int32_t bstart = 0;
     std::vector<std::vector<int64_t>> bydepth(S.depth);
     for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
@@ -471,7 +502,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
       bstart = (int32_t)H.bitems.size();
     };
     auto tiny_launch = [&](int64_t d, int32_t kind) {
-      const int32_t n = H.tiny_dptr[d + 1] - H.tiny_dptr[d];
+      const int32_t n = H.tiny_dadj[d] - H.tiny_dptr[d];
       if (n > 0) H.blaunch.push_back(int4{kind, H.tiny_dptr[d], n, 0});
     };
     static const int32_t r1[kBackR1Phases][3] = {{BI_T, BI_G, -1}, {BI_Z, -1, -1}, {BI_L, BI_SC, BI_F}, {BI_D0, -1, -1}};
@@ -556,7 +587,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.lvl_items = take(4 * (int64_t)H.lvl_items.size());
   o.lvl_recs = take((int64_t)sizeof(LRec) * (int64_t)H.lvl_items.size());
   o.tiny = take((int64_t)sizeof(TinyRec) * (int64_t)H.tiny.size());
-  o.toff = take(8 * (int64_t)H.toff.size());
+  o.toff = take(4 * (int64_t)H.toff.size());
   o.chunks = take(8 * (int64_t)H.chunks.size());
   o.chunks_narrow = take(8 * (int64_t)H.chunks_narrow.size());
   o.small_nodes = take(4 * (int64_t)H.small_nodes.size());
@@ -667,7 +698,7 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.node_parent = (int32_t *)(b + o.node_parent);
   d.order = (int32_t *)(b + o.order);
   d.lvl_items = (int32_t *)(b + o.lvl_items);
-  d.toff = (int64_t *)(b + o.toff);
+  d.toff = (uint32_t *)(b + o.toff);
   d.apos = (int64_t *)(b + o.apos);
   d.adiag = (uint8_t *)(b + o.adiag);
   d.linv = (void *)(b + o.linv);

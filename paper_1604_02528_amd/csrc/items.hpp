@@ -210,9 +210,10 @@ __device__ void gemm2_block(const Acc<T> &acc, double *Ls) {
 
 // Row tile a's share of GEMM-2 (Alg. 1 step 4): P_a[:, 64b..] = Lhat[rows of
 // tile a, :]^T Y[tile a, 64b..] = -(Lhat_a^T acc), written to the partial
-// buffer (column-major s x s per row tile).
+// buffer (column-major s x s per row tile); rows 64qb .. 64qe - 1 of P_a only.
 template <typename T, bool COH>
-__device__ void gemm2_partial(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, const Acc<T> &acc, double *smem) {
+__device__ void gemm2_partial(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, const Acc<T> &acc, double *smem,
+                              int qb = 0, int qe = 1 << 20) {
   constexpr int P = Planes<T>::P;
   const DevPlan &pl = *cx.pl;
   const int s = nd.s, c = nd.c, ld = s + c;
@@ -230,8 +231,9 @@ __device__ void gemm2_partial(const Ctx<T> &cx, const NodeInfo &nd, int a, int b
       lv[q] = gload(cx.Lp + off + (((int64_t)(q0 + x) * ld + s + i0 + i) & opaque_mask(i0 + i < c && q0 + x < s)));
     }
   };
-  load_l(0);
-  for (int q0 = 0; q0 < s; q0 += 64) {
+  const int qend = min(s, qe * 64);
+  load_l(qb * 64);
+  for (int q0 = qb * 64; q0 < qend; q0 += 64) {
 #pragma unroll
     for (int q = 0; q < 64 * 64 / NT; ++q) {
       const int e = threadIdx.x + NT * q;
@@ -241,7 +243,7 @@ __device__ void gemm2_partial(const Ctx<T> &cx, const NodeInfo &nd, int a, int b
       for (int p = 0; p < P; ++p) Ls[p * 64 * PITCH + i * PITCH + x] = Planes<T>::get(v, p);
     }
     lds_barrier();
-    if (q0 + 64 < s) load_l(q0 + 64);
+    if (q0 + 64 < qend) load_l(q0 + 64);
     gemm2_block<T>(acc, Ls);
     // P = Lhat^T Y = -(Lhat^T acc)
     const double *R = Ls;
@@ -304,10 +306,16 @@ __device__ void do_ytile(const Ctx<T> &cx, const NodeInfo &nd, int a, int bp, do
 
 // Sum of a split node's partial tiles (a, b) into X, then the row tile's share
 // of GEMM-2 (the step-3 and step-4 work that an unsplit tile does itself).
+// With br = b | r << 16 | rq << 24 and rq > 1, the tile's GEMM-2 share is cut
+// into rq items by rows of P_a: item r computes 64-row blocks [r nq / rq,
+// (r + 1) nq / rq) of the nq = ceil(s / 64), and item 0 alone stores the tile.
+// Every item sums the parts in the same order, so the result is the same.
 template <typename T, bool COH>
-__device__ void do_rtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, double *smem) {
+__device__ void do_rtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int br, double *smem) {
   const DevPlan &pl = *cx.pl;
   const int s = uniform(nd.s), c = uniform(nd.c);
+  const int b = br & 0xffff, r = (br >> 16) & 0xff, rq = max(1, br >> 24);
+  const int nq = (s + 63) / 64, qb = uniform(r * nq / rq), qe = uniform((r + 1) * nq / rq);
   const int parts = uniform(nd.split);
   const T *Y = static_cast<const T *>(cx.Yp) + nd.yoff;
   const int i0 = a * 64, j0 = b * 64;
@@ -361,8 +369,8 @@ __device__ void do_rtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, dou
           acc.v[p][bi][bj][v] = smem[p * 64 * PITCH + j * PITCH + i];
         }
   lds_barrier();
-  store_xtile<T, COH>(cx, nd, a, b, acc, smem);
-  gemm2_partial<T, COH>(cx, nd, a, b, acc, smem);
+  if (r == 0) store_xtile<T, COH>(cx, nd, a, b, acc, smem);
+  gemm2_partial<T, COH>(cx, nd, a, b, acc, smem, qb, qe);
 }
 
 // Blocks (a, b) and (b, a), a >= b, of sym(Src - sum_r P_r) into Dst, where
@@ -676,32 +684,32 @@ __device__ void do_stile(const Ctx<T> &cx, const NodeInfo &nd, double *smem, int
   lds_barrier();
 }
 
-// A whole small node (c <= kTinyC, s <= kTinyS) of one matrix in one
+// A whole small node (c <= CM <= kTinyCF, s <= kTinyS) of one matrix in one
 // wavefront, for the level schedule.  Three dependent memory rounds: the
-// record, then the offsets of X_{C,C} (host table), Lhat and Dt^{-1}, then
-// the X_{C,C} values.  Lane (i, grp) holds X_{C,C}(i, k) for k = grp + G u;
+// record, then the byte offsets of X_{C,C} in the panel array (host table:
+// c x c row-major, then padding), Lhat and Dt^{-1}, then the X_{C,C} values.  Lane (i, grp) holds X_{C,C}(i, k) for k = grp + G u;
 // the partial sums of X_{C,C} Lhat over the G lane groups are combined with
-// a fixed butterfly, so the result does not depend on timing.
+// a fixed butterfly, so the result does not depend on timing.  LDS blocks
+// are c x s with leading dimension tiny_ldc<T>().
 //   Y = -X_{C,C} Lhat (stored into X_{C,K});  T = Dt^{-1} - Lhat^T Y;
 //   X_{K,K} = (T + T^T) / 2                      (Alg. 1, Eqs. (2.9)-(2.10))
 template <typename T, int CM>
-__device__ __forceinline__ void do_tiny(const TinyRec &r, const int64_t *toff, const T *L, T *X, T *ls, T *ys) {
-  constexpr int G = 64 / CM, U = CM / G;
+__device__ __forceinline__ void do_tiny(const TinyRec &r, const uint32_t *toff, const T *L, T *X, T *ls, T *ys) {
+  constexpr int G = 64 / CM, U = CM / G, LDC = tiny_ldc<T>();
   const int lane = threadIdx.x, i = lane % CM, grp = lane / CM;
   const int s = r.s, c = r.c;
   const int64_t ld = s + c;
-  // round 2: the offsets of this lane's X_{C,C}(i, k); Lhat as ls[j * kTinyC + k]; Dt^{-1}(x, y), (y, x)
-  int64_t o[U];
+  const uint32_t *tb = toff + r.tbl;
+  // round 2: the offsets of this lane's X_{C,C}(i, k); Lhat as ls[j * LDC + k]; Dt^{-1}(x, y), (y, x)
+  const uint32_t rowb = 4u * ((uint32_t)(i * c + grp) & opaque_mask32(i < c));
+  uint32_t o[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int k = grp + G * u, hi = i > k ? i : k, lo = i > k ? k : i;
-    o[u] = gp(toff)[(r.tbl + hi * (hi + 1) / 2 + lo) & opaque_mask(i < c && k < c)];
-  }
-  constexpr int QL = kTinyC * kTinyS / 64;
+  for (int u = 0; u < U; ++u) o[u] = ld_off(tb, rowb + 4u * (G * u));
+  constexpr int QL = CM * kTinyS / 64;
   T lv[QL];
 #pragma unroll
   for (int q = 0; q < QL; ++q) {
-    const int e = lane + 64 * q, k = e % kTinyC, j = e / kTinyC;
+    const int e = lane + 64 * q, k = e % CM, j = e / CM;
     lv[q] = gload(L + r.off + ((j * ld + s + k) & opaque_mask(k < c && j < s)));
   }
   const int x = lane % kTinyS, y = lane / kTinyS;
@@ -710,11 +718,11 @@ __device__ __forceinline__ void do_tiny(const TinyRec &r, const int64_t *toff, c
   // round 3: the values
   T xv[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u) xv[u] = gload(X + o[u]);
+  for (int u = 0; u < U; ++u) xv[u] = ld_off(X, o[u]);
 #pragma unroll
   for (int q = 0; q < QL; ++q) {
-    const int e = lane + 64 * q, k = e % kTinyC, j = e / kTinyC;
-    ls[e] = masked(lv[q], opaque_mask(k < c && j < s));
+    const int e = lane + 64 * q, k = e % CM, j = e / CM;
+    ls[j * LDC + k] = masked(lv[q], opaque_mask(k < c && j < s));
   }
   __syncthreads();
   T acc[kTinyS];
@@ -726,7 +734,7 @@ __device__ __forceinline__ void do_tiny(const TinyRec &r, const int64_t *toff, c
     const T g = masked(xv[u], opaque_mask(i < c && k < c));
 #pragma unroll
     for (int j = 0; j < kTinyS; ++j)
-      if (j < s) acc[j] += g * ls[j * kTinyC + k];
+      if (j < s) acc[j] += g * ls[j * LDC + k];
   }
 #pragma unroll
   for (int m = CM; m < 64; m <<= 1)
@@ -738,7 +746,7 @@ __device__ __forceinline__ void do_tiny(const TinyRec &r, const int64_t *toff, c
     for (int j = 0; j < kTinyS; ++j)
       if (j < s) {
         X[r.off + j * ld + s + i] = SOps<T>::scale(-1.0, acc[j]);
-        ys[j * kTinyC + i] = acc[j];
+        ys[j * LDC + i] = acc[j];
       }
   }
   __syncthreads();
@@ -746,8 +754,78 @@ __device__ __forceinline__ void do_tiny(const TinyRec &r, const int64_t *toff, c
   if (x < s && y < s) {
     T rxy = zero_of<T>(), ryx = zero_of<T>();
     for (int q = 0; q < c; ++q) {
-      rxy += ls[x * kTinyC + q] * ys[y * kTinyC + q];
-      ryx += ls[y * kTinyC + q] * ys[x * kTinyC + q];
+      rxy += ls[x * LDC + q] * ys[y * LDC + q];
+      ryx += ls[y * LDC + q] * ys[x * LDC + q];
+    }
+    X[r.off + y * ld + x] = SOps<T>::scale(0.5, (dxy + rxy) + (dyx + ryx));
+  }
+}
+
+// The same for 32 < c <= kTinyCF (FP64): lane i holds row i of X_{C,C}, and
+// the contraction runs in two halves of 32 columns so that one half's
+// offsets and one half's values are in registers at a time; Y(i, j) is
+// accumulated in LDS (each lane owns its row), one column j at a time.  Four
+// dependent rounds: the record; Lhat, Dt^{-1} and the first half's offsets;
+// the first half's values with the second half's offsets; the second half's
+// values.
+template <typename T>
+__device__ __forceinline__ void do_tiny64(const TinyRec &r, const uint32_t *toff, const T *L, T *X, T *ls, T *ys) {
+  constexpr int H = kTinyCF / 2, LDC = kTinyCF;
+  const int i = threadIdx.x;
+  const int s = r.s, c = r.c;
+  const int64_t ld = s + c;
+  const uint32_t *tb = toff + r.tbl;
+  constexpr int QL = kTinyCF * kTinyS / 64;
+  T lv[QL];
+#pragma unroll
+  for (int q = 0; q < QL; ++q) {
+    const int e = i + 64 * q, k = e % kTinyCF, j = e / kTinyCF;
+    lv[q] = gload(L + r.off + ((j * ld + s + k) & opaque_mask(k < c && j < s)));
+  }
+  const int x = i % kTinyS, y = i / kTinyS;
+  const int64_t dm = opaque_mask(x < s && y < s);
+  const T dxy = gload(L + r.off + ((y * ld + x) & dm)), dyx = gload(L + r.off + ((x * ld + y) & dm));
+  const uint32_t rowb = 4u * ((uint32_t)(i * c) & opaque_mask32(i < c));
+  uint32_t o[H];
+  T xv[H];
+#pragma unroll
+  for (int u = 0; u < H; ++u) o[u] = ld_off(tb, rowb + 4u * u);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int u = 0; u < H; ++u) xv[u] = ld_off(X, o[u]);
+    if (h == 0) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < H; ++u) o[u] = ld_off(tb, rowb + 4u * (H + u));
+#pragma unroll
+      for (int q = 0; q < QL; ++q) {
+        const int e = i + 64 * q, k = e % kTinyCF, j = e / kTinyCF;
+        ls[j * LDC + k] = masked(lv[q], opaque_mask(k < c && j < s));
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < H; ++u) xv[u] = masked(xv[u], opaque_mask(i < c && H * h + u < c));
+#pragma unroll 1
+    for (int j = 0; j < s; ++j) {
+      T a = h ? ys[j * LDC + i] : zero_of<T>();
+#pragma unroll
+      for (int u = 0; u < H; ++u) {
+        a += xv[u] * ls[j * LDC + H * h + u];
+        if (u % 8 == 7) __builtin_amdgcn_sched_barrier(0);  // bounds the Lhat reads in flight
+      }
+      ys[j * LDC + i] = a;
+    }
+  }
+  if (i < c)
+    for (int j = 0; j < s; ++j) X[r.off + j * ld + s + i] = SOps<T>::scale(-1.0, ys[j * LDC + i]);
+  __syncthreads();
+  if (x < s && y < s) {
+    T rxy = zero_of<T>(), ryx = zero_of<T>();
+    for (int q = 0; q < c; ++q) {
+      rxy += ls[x * LDC + q] * ys[y * LDC + q];
+      ryx += ls[y * LDC + q] * ys[x * LDC + q];
     }
     X[r.off + y * ld + x] = SOps<T>::scale(0.5, (dxy + rxy) + (dyx + ryx));
   }

@@ -66,7 +66,7 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_tiny(const DevPlan *__restrict__ plp, const T *Lp, T *Xp,
                                              const TinyRec *__restrict__ recs, int32_t count, int32_t list_pos) {
   const DevPlan &pl = *plp;
-  __shared__ T ls[kTinyS * kTinyC], ys[kTinyS * kTinyC];
+  __shared__ T ls[kTinyS * tiny_ldc<T>()], ys[kTinyS * tiny_ldc<T>()];
   const int64_t g = blockIdx.x;
   const int64_t l = g / count;
   const TinyRec r = recs[g - l * count];
@@ -77,8 +77,12 @@ __global__ void __launch_bounds__(64) k_tiny(const DevPlan *__restrict__ plp, co
     do_tiny<T, 8>(r, pl.toff, L, X, ls, ys);
   else if (r.c <= 16)
     do_tiny<T, 16>(r, pl.toff, L, X, ls, ys);
-  else
+  else if constexpr (sizeof(T) == 16)  // complex plans list c <= kTinyC only
     do_tiny<T, 32>(r, pl.toff, L, X, ls, ys);
+  else if (r.c <= 32)
+    do_tiny<T, 32>(r, pl.toff, L, X, ls, ys);
+  else
+    do_tiny64<T>(r, pl.toff, L, X, ls, ys);
   if (pl.trace) {
     __syncthreads();
     if (threadIdx.x == 0) {

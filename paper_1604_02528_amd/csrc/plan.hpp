@@ -12,8 +12,10 @@
 //           comes from the dense buffer or is gathered on the fly.  Unsplit
 //           nodes store the tile into X and its share of GEMM-2 directly;
 //           split nodes store a partial tile.
-//   ITEM_R  (K, a, b): sum of a split node's partial tiles into X, and the row
-//           tile's share of GEMM-2 (split nodes only).
+//   ITEM_R  (K, a, b | r << 16 | rq << 24): sum of a split node's partial
+//           tiles into X, and the row tile's share of GEMM-2 (split nodes
+//           only); with rq > 1 the share is cut into rq items by 64-row
+//           blocks of the s x s product and item r = 0 stores the tile.
 //   ITEM_D  (K, a, b), a >= b: blocks (a, b) and (b, a) of X_KK = Dt_K^{-1} -
 //           Lhat_{C,K}^T X_{C,K} (step 4), symmetrized (Section 2.3).  Nodes
 //           with at least kDSlabRows row tiles split each block pair into
@@ -83,10 +85,18 @@ struct alignas(16) LRec {
 
 // Nodes small enough for one wavefront (c <= kTinyC, s <= kTinyS) skip the
 // 64 x 64 tile machinery in the level schedule: one record each, in launch
-// order, and a host-built table of the absolute X offsets of the lower
-// triangle of X_{C,C} (row-major, entry i (i + 1) / 2 + k for i >= k).
+// order, and a host-built table of the byte offsets of X_{C,C} in the panel
+// array (c x c row-major, entry i c + k, followed by kTinyCF zeros).  The
+// forward sweep of an FP64 plan takes nodes up to c <= kTinyCF that way
+// (one row of X_{C,C} per lane); each depth lists its c <= kTinyC nodes
+// first, and the adjoint's small-node launches cover that prefix only.
+// Table entries are 32-bit byte offsets (plans whose panel array of one
+// matrix spans 4 GiB or more have no single-wavefront nodes).
 constexpr int kTinyC = 32;
+constexpr int kTinyCF = 64;
 constexpr int kTinyS = 8;
+// leading dimension of the forward sweep's LDS blocks
+template <typename T> __host__ __device__ constexpr int tiny_ldc() { return sizeof(T) == 8 ? kTinyCF : kTinyC; }
 struct alignas(16) TinyRec {
   int32_t K, it, s, c;  // node, its item id, width, off-diagonal rows
   int64_t off, tbl;     // panel offset of the node; first table entry
@@ -117,7 +127,7 @@ struct DevPlan {
   int32_t *node_parent; // [ns] supernodal etree parent (-1 at a root)
   int32_t *order;      // [batch * nitems] ticket -> l * nitems + item
   int32_t *lvl_items;  // item ids grouped by (level, phase)
-  int64_t *toff;       // X_{C,C} offset tables of the single-wavefront nodes
+  uint32_t *toff;      // X_{C,C} offset tables of the single-wavefront nodes
   int64_t *apos;       // [nnzA] A entry -> panel element
   uint8_t *adiag;      // [nnzA]
   // scratch

@@ -30,6 +30,11 @@ template <typename T> __device__ __forceinline__ SELINV_GAS T *gw(T *p) { return
 // An all-ones / all-zero mask the optimizer cannot see through: selecting
 // loaded values with it keeps every load unconditional (a plain select lets
 // the compiler sink a load into a branch, which then waits on it).
+__device__ __forceinline__ uint32_t opaque_mask32(bool keep) {
+  uint32_t m = keep ? ~0u : 0u;
+  asm("" : "+v"(m));
+  return m;
+}
 __device__ __forceinline__ int64_t opaque_mask(bool keep) {
   int64_t m = keep ? -1 : 0;
   asm("" : "+v"(m));
@@ -453,6 +458,9 @@ template <typename T, int TK> struct DVals {
 // vector-offset addressing of the global loads.
 __device__ __forceinline__ double ld_off(const double *base, uint32_t b) {
   return *reinterpret_cast<const SELINV_GAS double *>(reinterpret_cast<const SELINV_GAS char *>(gp(base)) + b);
+}
+__device__ __forceinline__ uint32_t ld_off(const uint32_t *base, uint32_t b) {
+  return *reinterpret_cast<const SELINV_GAS uint32_t *>(reinterpret_cast<const SELINV_GAS char *>(gp(base)) + b);
 }
 __device__ __forceinline__ cplx ld_off(const cplx *base, uint32_t b) {
   const SELINV_GAS char *q = reinterpret_cast<const SELINV_GAS char *>(gp(base)) + b;
