@@ -109,7 +109,7 @@ double item_cost_ns(const HostPlan &H, const Item &it) {
       const double m = std::min<double>(kTileM, c - (double)kTileM * it.a);
       const double nn = std::min<double>(kTileN, s - (double)kTileN * (it.b & 0xffff));
       const double kk = H.node_kchunk[it.K];
-      const double gemm2 = H.node_split[it.K] > 1 ? 0.0 : (2.0 * s * m * nn) / 150.0;
+      const double gemm2 = H.node_yoff[it.K] >= 0 ? 0.0 : (2.0 * s * m * nn) / 150.0;
       return 1500.0 + (2.0 * m * nn * kk) / (dense ? 150.0 : 40.0) + gemm2;
     }
     case ITEM_R: {
@@ -284,21 +284,33 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   H.node_kchunk.assign(ns, 0);
   H.node_yoff.assign(ns, -1);
   H.y_elems = 0;
+  // GEMM-1 tiles of each depth (over the batch)
+  std::vector<int64_t> dtiles(S.depth, 0);
+  for (int64_t K = 0; K < ns; ++K)
+    if (!(S.nrows(K) <= kSmallC && S.width(K) <= kSmallS))
+      dtiles[S.sdepth[K]] += batch * ((S.nrows(K) + kTileM - 1) / kTileM) * ((S.width(K) + kTileN - 1) / kTileN);
   for (int64_t K = 0; K < ns; ++K) {
     const int64_t s = S.width(K), c = S.nrows(K);
     H.node_kchunk[K] = (int32_t)c;
     if (c <= kSmallC && s <= kSmallS) continue;  // single-item node
     if (c == 0) continue;
     const int64_t tiles = batch * ((c + kTileM - 1) / kTileM) * ((s + kTileN - 1) / kTileN);
+    const int64_t nq = (s + kTileN - 1) / kTileN;
     int64_t parts = 1;
     if (tiles < kSplitTarget) parts = std::min<int64_t>(kSplitMax, (kSplitTarget + tiles - 1) / tiles);
     if (split_min_k < 0) parts = 1;
     parts = std::max<int64_t>(1, std::min<int64_t>(parts, c / std::max<int64_t>(split_min_k, kSplitAlign)));
-    if (parts <= 1) continue;
-    int64_t chunk = (c + parts - 1) / parts;
-    chunk = (chunk + kSplitAlign - 1) / kSplitAlign * kSplitAlign;
-    parts = (c + chunk - 1) / chunk;
-    if (parts <= 1) continue;
+    int64_t chunk = c;
+    if (parts > 1) {
+      chunk = (c + parts - 1) / parts;
+      chunk = (chunk + kSplitAlign - 1) / kSplitAlign * kSplitAlign;
+      parts = (c + chunk - 1) / chunk;
+    }
+    // An unsplit node whose GEMM-2 share spans several 64-row blocks of P,
+    // at a depth with few tiles, also takes the R phase (one part): its
+    // tiles' GEMM-2 shares are then cut into R items instead of running
+    // block after block at the end of each GEMM-1 tile.
+    if (parts <= 1 && !(nq > 1 && dtiles[S.sdepth[K]] * nq <= kSplitTarget)) continue;
     H.node_split[K] = (int32_t)parts;
     H.node_kchunk[K] = (int32_t)chunk;
     H.node_yoff[K] = H.y_elems;
@@ -336,7 +348,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   // per tile).
   std::vector<int64_t> rtiles(S.depth, 0);
   for (int64_t K = 0; K < ns; ++K)
-    if (H.node_split[K] > 1)
+    if (H.node_yoff[K] >= 0)
       rtiles[S.sdepth[K]] += batch * ((S.nrows(K) + kTileM - 1) / kTileM) * ((S.width(K) + kTileN - 1) / kTileN);
   H.item_ptr.assign(ns + 1, 0);
   H.nph.assign((size_t)kPhases * ns, 0);
@@ -363,7 +375,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
         for (int32_t b = 0; b < nb; ++b)
           for (int32_t a = 0; a < nr; ++a) H.items.push_back(Item{(int32_t)K, ITEM_Y, a, b | (p << 16)});
       nph(1, K) = nr * nb * parts;
-      if (parts > 1) {
+      if (H.node_yoff[K] >= 0) {  // partial tiles, summed by R items
         const int64_t nq = (s + kTileN - 1) / kTileN;
         const int32_t rq = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nq, kSplitTarget / rtiles[S.sdepth[K]]));
         for (int32_t r = 0; r < rq; ++r)

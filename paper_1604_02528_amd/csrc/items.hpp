@@ -258,8 +258,10 @@ __device__ void gemm2_partial(const Ctx<T> &cx, const NodeInfo &nd, int a, int b
 
 // GEMM-1 tile, rows 64a.. and columns 64b.. of X_{C,K} (Alg. 1 step 3):
 //   acc = X_{C,C}[tile rows, k] Lhat_{C,K}[k, tile columns], k in this part's
-// share of [0, c).  An unsplit node stores Y = -acc into X and its row tile's
-// share of GEMM-2 (step 4); a split node stores acc as a partial tile.
+// share of [0, c).  A node without an R phase stores Y = -acc into X and its
+// row tile's share of GEMM-2 (step 4); otherwise acc is stored as a partial
+// tile (a split node's parts, or the one part of a node whose GEMM-2 shares
+// are cut into R items).
 template <typename T, bool COH>
 __device__ void do_ytile(const Ctx<T> &cx, const NodeInfo &nd, int a, int bp, double *smem, int64_t *rt) {
   const DevPlan &pl = *cx.pl;
@@ -288,12 +290,12 @@ __device__ void do_ytile(const Ctx<T> &cx, const NodeInfo &nd, int a, int bp, do
     LoadPanelK<T, false> lb{cx.Lp, off, ld, s, 0, ke, j0, s};
     gemm_tile<T>(kb, ke, la, lb, smem, acc);
   }
-  if (parts == 1) {
+  if (nd.yoff < 0) {
     store_xtile<T, COH>(cx, nd, a, b, acc, smem);
     gemm2_partial<T, COH>(cx, nd, a, b, acc, smem);
     return;
   }
-  // partial tile of a split node: Ypart[part] (column-major c x s)
+  // partial tile of a node with an R phase: Ypart[part] (column-major c x s)
   T *Y = static_cast<T *>(cx.Yp) + nd.yoff + (int64_t)part * c * s;
   acc_to_lds<T>(acc, smem);
   lds_barrier();

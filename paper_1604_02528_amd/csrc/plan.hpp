@@ -9,13 +9,14 @@
 //   ITEM_Y  (K, a, b | part << 16): rows 64a.. and columns 64b.. of GEMM-1
 //           X_{C,K} = -X_{C,C} Lhat_{C,K} (Alg. 1 step 3), contraction indices
 //           [part * kchunk, (part + 1) * kchunk) of the node's split.  X_{C,C}
-//           comes from the dense buffer or is gathered on the fly.  Unsplit
-//           nodes store the tile into X and its share of GEMM-2 directly;
-//           split nodes store a partial tile.
-//   ITEM_R  (K, a, b | r << 16 | rq << 24): sum of a split node's partial
-//           tiles into X, and the row tile's share of GEMM-2 (split nodes
-//           only); with rq > 1 the share is cut into rq items by 64-row
-//           blocks of the s x s product and item r = 0 stores the tile.
+//           comes from the dense buffer or is gathered on the fly.  Nodes
+//           without an R phase store the tile into X and its share of
+//           GEMM-2 directly; the others store a partial tile.
+//   ITEM_R  (K, a, b | r << 16 | rq << 24): sum of a node's partial tiles
+//           into X, and the row tile's share of GEMM-2 (split nodes, and
+//           unsplit nodes of sparsely filled depths whose share spans several
+//           64-row blocks); with rq > 1 the share is cut into rq items by
+//           64-row blocks of the s x s product and item r = 0 stores the tile.
 //   ITEM_D  (K, a, b), a >= b: blocks (a, b) and (b, a) of X_KK = Dt_K^{-1} -
 //           Lhat_{C,K}^T X_{C,K} (step 4), symmetrized (Section 2.3).  Nodes
 //           with at least kDSlabRows row tiles split each block pair into
