@@ -84,7 +84,9 @@ typedef struct {
                               of different etree depths share memory, so the cap applies to the
                               largest depth; under SELINV_SCHED_PERSISTENT to their sum */
   int32_t split_min_k; /* shortest contraction part when a node with too few GEMM-1 tiles to fill
-                          the GPU splits its contraction over C(K) (0 = 256, < 0 = never split) */
+                          the GPU splits its contraction over C(K) (0 = 320, < 0 = never split);
+                          a quarter of it at etree depths whose tiles fill at most a quarter of
+                          the GPU */
   int32_t reserved;
 } selinv_opts;
 

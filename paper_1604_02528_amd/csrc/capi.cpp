@@ -95,7 +95,7 @@ constexpr int kSimWorkers = 256;
 constexpr int64_t kDefaultDenseMinC = 256;
 constexpr int64_t kSplitTarget = 512;  // GEMM-1 tiles that keep every CU busy (2 per CU)
 constexpr int64_t kSplitMax = 8;
-constexpr int64_t kSplitMinK = 256;    // default shortest contraction part
+constexpr int64_t kSplitMinK = 320;    // default shortest contraction part
 constexpr int64_t kSplitAlign = 32;    // parts start on a contraction-stage boundary
 constexpr int64_t kDefaultDenseMaxBytes = int64_t(32) << 30;
 
@@ -299,7 +299,14 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     int64_t parts = 1;
     if (tiles < kSplitTarget) parts = std::min<int64_t>(kSplitMax, (kSplitTarget + tiles - 1) / tiles);
     if (split_min_k < 0) parts = 1;
-    parts = std::max<int64_t>(1, std::min<int64_t>(parts, c / std::max<int64_t>(split_min_k, kSplitAlign)));
+    // at a depth that fills at most a quarter of the GPU, the parts may be a
+    // quarter as long (as many as one round of items over the GPU allows):
+    // there the GEMM-1 tiles wait on memory latency, and the R items that sum
+    // the extra parts run on otherwise idle CUs
+    const bool sparse = dtiles[S.sdepth[K]] * 4 <= kSplitTarget;
+    const int64_t mink = sparse ? std::max<int64_t>(2 * kSplitAlign, split_min_k / 4) : split_min_k;
+    if (sparse) parts = std::min<int64_t>(parts, kSplitTarget / dtiles[S.sdepth[K]]);  // one round of items
+    parts = std::max<int64_t>(1, std::min<int64_t>(parts, c / std::max<int64_t>(mink, kSplitAlign)));
     int64_t chunk = c;
     if (parts > 1) {
       chunk = (c + parts - 1) / parts;
