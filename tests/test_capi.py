@@ -115,3 +115,54 @@ def test_adjoint_items_cover_every_node_once_per_sweep():
     sym = S.symbolic()
     ns = sym["nsuper"]
     assert it.shape[1] == 4 and it[:, 0].max() == ns - 1
+
+
+@pytest.mark.parametrize("name,scale", [("C2", None), ("C3", 14), ("C4", None)])
+def test_forward_items_cover_every_tile_once(name, scale):
+    """Host plan of the forward traversal: per node, the GEMM-1 items cover
+    every (row tile, column tile, part) once; the R items, where present,
+    cover every tile once per share and their 64-row blocks of P partition
+    [0, ceil(s/64)); the D items cover the lower block pairs (in slabs for
+    nodes with many row tiles); nodes with c, s <= 64 are one S item."""
+    from paper_1604_02528_amd import capi
+
+    w = workload(name, scale)
+    S = _ctx(w, relax=0.05)
+    it = capi.selinv_items(S.h)
+    sym = S.symbolic()
+    s_all = np.diff(sym["xsuper"]).astype(int)
+    c_all = np.diff(sym["rowptr"]).astype(int)
+    ITEM_Y, ITEM_D, ITEM_S, ITEM_G, ITEM_R = 0, 1, 2, 3, 4
+    order = np.argsort(it[:, 0], kind="stable")
+    bounds = np.searchsorted(it[order, 0], np.arange(len(s_all) + 1))
+    n_rsplit = 0
+    for K in range(len(s_all)):
+        rows = it[order[bounds[K]:bounds[K + 1]]]
+        s, c = int(s_all[K]), int(c_all[K])
+        nr, nb = -(-c // 64), -(-s // 64)
+        types = rows[:, 1]
+        if c <= 64 and s <= 64:
+            assert list(types[types != ITEM_G]) == [ITEM_S]
+            continue
+        y = rows[types == ITEM_Y]
+        parts = len(y) // (nr * nb)
+        assert parts >= 1 and len(y) == nr * nb * parts
+        keys = {(int(a), int(b) & 0xFFFF, int(b) >> 16) for _, _, a, b in y}
+        assert keys == {(a, b, p) for a in range(nr) for b in range(nb) for p in range(parts)}
+        r = rows[types == ITEM_R]
+        if len(r):
+            rq = max(1, int(r[0, 3]) >> 24)
+            nq = nb
+            assert 1 <= rq <= nq and len(r) == nr * nb * rq
+            got = sorted((int(a), int(b) & 0xFFFF, (int(b) >> 16) & 0xFF, max(1, int(b) >> 24)) for _, _, a, b in r)
+            assert got == sorted((a, b, q, rq) for a in range(nr) for b in range(nb) for q in range(rq))
+            cover = sorted(x for q in range(rq) for x in range(q * nq // rq, (q + 1) * nq // rq))
+            assert cover == list(range(nq))
+            n_rsplit += rq > 1
+        else:
+            assert parts == 1
+        d = rows[types == ITEM_D]
+        nsl = 4 if nr >= 4 else 1
+        assert len(d) == nb * (nb + 1) // 2 * nsl
+    if name == "C2":
+        assert n_rsplit > 0  # the top separator chain cuts its GEMM-2 shares
