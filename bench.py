@@ -78,35 +78,45 @@ def algorithmic_bytes(w, relax):
 
 
 def timed_steps(S, ldlt, steps, warmup):
-    """warmup + steps passes of selinv_normalize + selinv_run on one stream,
-    HIP events around each call; returns wall seconds and per-step times."""
+    """warmup + steps passes of the step, selinv_normalize_run (normalization
+    and traversal on one stream, the deeper nodes' normalization overlapped
+    with the top depths' traversal), timed by the wall clock between two
+    device synchronizations; then `steps` passes of selinv_normalize and
+    selinv_run as separate calls with HIP events around each, for the
+    breakdown.  Returns wall seconds of the timed steps and the per-pass
+    normalization and traversal times."""
     import torch
 
     from paper_1604_02528_amd import capi
 
     stream = torch.cuda.current_stream()
     h = S.h
+    P, X, W = S._bufs["panels"], S._bufs["x"], S._bufs["work"]
 
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        capi.selinv_normalize(h, ldlt, S._bufs["panels"], S._bufs["work"], None, stream.cuda_stream)
-        if ev is not None:
-            ev[1].record(stream)
-        capi.selinv_run(h, S._bufs["panels"], S._bufs["x"], S._bufs["work"], stream.cuda_stream)
-        if ev is not None:
-            ev[2].record(stream)
+    def step():
+        capi.selinv_normalize_run(h, ldlt, P, X, W, None, stream.cuda_stream)
+
+    def split(ev):
+        ev[0].record(stream)
+        capi.selinv_normalize(h, ldlt, P, W, None, stream.cuda_stream)
+        ev[1].record(stream)
+        capi.selinv_run(h, P, X, W, stream.cuda_stream)
+        ev[2].record(stream)
 
     for _ in range(warmup):
         step()
     S.sync()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(steps):
-        step(evs[k])
+    for _ in range(steps):
+        step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    S.sync()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for k in range(steps):
+        split(evs[k])
+    torch.cuda.synchronize()
     S.sync()
     t_norm = np.array([a.elapsed_time(b) for a, b, _ in evs]) * 1e-3
     t_run = np.array([b.elapsed_time(c) for _, b, c in evs]) * 1e-3

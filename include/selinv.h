@@ -195,6 +195,26 @@ selinv_status selinv_factor_host(selinv_ctx *h, const void *values, void *panels
 selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, void *work_dev, void *stream);
 
 /*
+ * selinv_normalize_run -- selinv_normalize followed by selinv_run (Alg. 1
+ * steps 1-2, then its second loop), with the same arguments and results, but
+ * with the two overlapped under SELINV_SCHED_LEVELS: the nodes of the top
+ * etree depths (those whose GEMM-1 tiles fill at most a quarter of the GPU)
+ * are normalized on `stream` and their depths traversed there, while the
+ * other nodes are normalized on a second stream owned by the context; the
+ * traversal waits for that stream before its first deeper depth.  The second
+ * stream (default priority) and two events are created on the first call,
+ * on the current device, and destroyed by selinv_destroy; a context used
+ * this way stays on that device (ESTATE otherwise).  Everything is ordered
+ * after the work already enqueued on `stream`, and the work of the call is
+ * complete when `stream` has reached it.  Under SELINV_SCHED_PERSISTENT, or
+ * when the tree has no such top depths, this is the two calls in sequence.
+ * Errors as selinv_normalize and selinv_run, plus EDEVICE when the stream or
+ * events cannot be created.
+ */
+selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *panels_dev, void *x_dev, void *work_dev,
+                                   void *dtilde_dev, void *stream);
+
+/*
  * selinv_extract -- X on A's stored lower pattern, original indexing:
  * out_dev[l][e] = (A^{-1})_{rowind[e], col(e)} of matrix l.  Asynchronous.
  */

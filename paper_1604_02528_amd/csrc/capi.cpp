@@ -19,9 +19,9 @@
 
 namespace selinv {
 hipError_t launch_normalize(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, const void *src,
-                            void *panels, void *dt, hipStream_t st);
+                            void *panels, void *dt, hipStream_t st, int part);
 hipError_t launch_run(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, int sched,
-                      const void *panels, void *x, int64_t budget_ticks, int grid, hipStream_t st);
+                      const void *panels, void *x, int64_t budget_ticks, int grid, hipStream_t st, int q0, int q1);
 hipError_t launch_extract(const DevPlan &pl, const DevPlan *dpl, bool cplx_, const void *x, void *out, hipStream_t st);
 int persistent_blocks_per_cu(bool cplx_);
 hipError_t launch_backward(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const void *panels,
@@ -57,6 +57,8 @@ struct HostPlan {
   std::vector<int32_t> tiny_dadj;  // [depth] end of each depth's c <= kTinyC prefix (the adjoint's)
   bool adjoint = false;        // adjoint scratch allocated (FP64 only)
   std::vector<int32_t> lvl_items, lvl_ptr, lvl_tiny;
+  int32_t lvl_top = 0;        // level launches of the top depths (see LaunchAux)
+  int32_t norm_top[5] = {0, 0, 0, 0, 0};  // their normalization entries: small, narrow, chunks, rblocks, sq
   std::vector<LRec> lvl_recs;  // the items of lvl_items with their nodes, in level order
   std::vector<TinyRec> tiny;  // single-wavefront nodes, in launch order
   std::vector<uint32_t> toff;  // their X_{C,C} tables (byte offsets into the panel array)
@@ -289,6 +291,9 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   for (int64_t K = 0; K < ns; ++K)
     if (!(S.nrows(K) <= kSmallC && S.width(K) <= kSmallS))
       dtiles[S.sdepth[K]] += batch * ((S.nrows(K) + kTileM - 1) / kTileM) * ((S.width(K) + kTileN - 1) / kTileN);
+  // the top depths: every depth down to here fills at most a quarter of the GPU
+  int64_t top_depth = -1;
+  while (top_depth + 1 < S.depth && dtiles[top_depth + 1] * 4 <= kSplitTarget) ++top_depth;
   for (int64_t K = 0; K < ns; ++K) {
     const int64_t s = S.width(K), c = S.nrows(K);
     H.node_kchunk[K] = (int32_t)c;
@@ -406,6 +411,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   // single-wavefront nodes of a depth form a range of their own
   H.lvl_items.clear();
   H.lvl_ptr.assign(1, 0);
+  H.lvl_top = 0;
   H.lvl_tiny.clear();
   H.tiny.clear();
   H.toff.clear();
@@ -459,6 +465,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
         if (pass == 0) H.tiny_dadj[d] = (int32_t)H.tiny.size();
       }
       close(tiny_base);
+      if (d == top_depth && d + 1 < S.depth) H.lvl_top = (int32_t)H.lvl_ptr.size() - 1;
     }
     H.tiny_dptr[S.depth] = (int32_t)H.tiny.size();
   }
@@ -552,12 +559,20 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   H.rblocks.clear();
   H.sq_tiles.clear();
   H.small_nodes.clear();
+  for (int32_t &v : H.norm_top) v = 0;
   {
     // root first: the workgroups of the large top nodes, which take longest,
     // are dispatched first (measured: C2 normalization 0.55 -> 0.45 ms)
     std::vector<std::vector<int64_t>> bydepth(S.depth);
     for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
-    for (int64_t d = 0; d < S.depth; ++d)
+    for (int64_t d = 0; d < S.depth; ++d) {
+      if (d == top_depth + 1 && H.lvl_top > 0) {
+        H.norm_top[0] = (int32_t)H.small_nodes.size();
+        H.norm_top[1] = (int32_t)H.chunks_narrow.size();
+        H.norm_top[2] = (int32_t)H.chunks.size();
+        H.norm_top[3] = (int32_t)H.rblocks.size();
+        H.norm_top[4] = (int32_t)H.sq_tiles.size();
+      }
       for (int64_t K : bydepth[d]) {
         const int32_t s = H.node_s[K], c = H.node_c[K];
         if (s <= kSmallNormS) {
@@ -571,6 +586,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
         for (int32_t a = 0; a < nt; ++a)
           for (int32_t b = 0; b < nt; ++b) H.sq_tiles.push_back(int4{(int32_t)K, a, b, 0});
       }
+    }
   }
   H.apos = S.apos;
   H.adiag = S.apos_diag;
@@ -659,8 +675,15 @@ struct selinv_ctx {
   // cached strings for views
   std::vector<int64_t> panel_off_view;
 
+  hipStream_t side = nullptr;  // second stream of selinv_normalize_run, and its fork/join events
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int side_device = -1;
+
   ~selinv_ctx() {
     if (pinned) (void)hipHostFree(pinned);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
   }
   bool is_complex() const { return opts.dtype == SELINV_C128; }
   int64_t sbytes() const { return is_complex() ? 16 : 8; }
@@ -765,6 +788,12 @@ LaunchAux make_aux(const selinv_ctx *h, void *work) {
   a.nlvl = (int32_t)H.lvl_ptr.size() - 1;
   a.blaunch = H.blaunch.data();
   a.nblaunch = (int32_t)H.blaunch.size();
+  a.lvl_top = H.lvl_top;
+  a.nsmall_top = H.norm_top[0];
+  a.nchunks_narrow_top = H.norm_top[1];
+  a.nchunks_top = H.norm_top[2];
+  a.nrblocks_top = H.norm_top[3];
+  a.nsq_tiles_top = H.norm_top[4];
   return a;
 }
 
@@ -966,7 +995,7 @@ selinv_status selinv_factor(selinv_ctx *h, const void *values, void *panels_dev,
   if (e != hipSuccess) return hip_err(h, e, "panel upload");
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
-  e = launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), panels_dev, panels_dev, dtilde_dev, st);
+  e = launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), panels_dev, panels_dev, dtilde_dev, st, 0);
   if (e != hipSuccess) return hip_err(h, e, "normalize launch");
   // the staging buffer is reused by the next call: wait for the copy
   e = hipStreamSynchronize(st);
@@ -986,7 +1015,7 @@ selinv_status selinv_normalize(selinv_ctx *h, const void *ldlt_dev, void *panels
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
   hipError_t e =
-      launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st);
+      launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st, 0);
   if (e != hipSuccess) return hip_err(h, e, "normalize launch");
   h->factored = true;
   return SELINV_OK;
@@ -1049,7 +1078,56 @@ selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, voi
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
   e = launch_run(pl, dev_plan(h, work_dev), aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, budget, h->grid,
-                 st);
+                 st, 0, aux.nlvl);
+  if (e != hipSuccess) return hip_err(h, e, "selinv launch");
+  return SELINV_OK;
+}
+
+selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *panels_dev, void *x_dev, void *work_dev,
+                                   void *dtilde_dev, void *stream) {
+  if (!h) return SELINV_EINVAL;
+  if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
+  if (!ldlt_dev || !panels_dev || !x_dev || !work_dev) return set_err(h, SELINV_EINVAL, "null buffer");
+  hipStream_t st = (hipStream_t)stream;
+  selinv_status ss = ensure_uploaded(h, work_dev, st);
+  if (ss != SELINV_OK) return ss;
+  LaunchAux aux = make_aux(h, work_dev);
+  if (h->opts.sched != SELINV_SCHED_LEVELS || aux.lvl_top == 0) {
+    ss = selinv_normalize(h, ldlt_dev, panels_dev, work_dev, dtilde_dev, stream);
+    return ss != SELINV_OK ? ss : selinv_run(h, panels_dev, x_dev, work_dev, stream);
+  }
+  hipError_t e;
+  int dev = 0;
+  e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_err(h, e, "hipGetDevice");
+  if (h->side && h->side_device != dev) return set_err(h, SELINV_ESTATE, "context used on another device");
+  if (!h->side) {
+    e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_err(h, e, "side stream");
+    e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_err(h, e, "side stream events");
+    h->side_device = dev;
+  }
+  DevPlan pl = make_devplan(h, work_dev);
+  const DevPlan *dpl = dev_plan(h, work_dev);
+  // fork: the deeper nodes' normalization on the side stream, after the
+  // caller's earlier work
+  e = hipEventRecord(h->ev_fork, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->ev_fork, 0);
+  if (e == hipSuccess)
+    e = launch_normalize(pl, dpl, aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, h->side, 2);
+  if (e == hipSuccess) e = hipEventRecord(h->ev_join, h->side);
+  if (e != hipSuccess) return hip_err(h, e, "normalize (side stream)");
+  // the top nodes' normalization and traversal on the caller's stream
+  e = launch_normalize(pl, dpl, aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st, 1);
+  if (e != hipSuccess) return hip_err(h, e, "normalize launch");
+  h->factored = true;
+  e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, 0, aux.lvl_top);
+  // join before the first depth that needs the deeper nodes
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, h->ev_join, 0);
+  if (e == hipSuccess)
+    e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, aux.lvl_top, aux.nlvl);
   if (e != hipSuccess) return hip_err(h, e, "selinv launch");
   return SELINV_OK;
 }

@@ -550,50 +550,62 @@ __global__ void k_scatter(const DevPlan *__restrict__ plp, const T *vals, T *P) 
 // ---------------------------------------------------------------------------
 // Host-side launchers (called from the C ABI translation unit)
 // ---------------------------------------------------------------------------
+// part 0: every node; 1: the nodes of the top depths (the leading entries of
+// each list); 2: the others.
 template <typename T>
 static hipError_t normalize_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const void *src,
-                                 void *panels, void *dt, hipStream_t st) {
+                                 void *panels, void *dt, hipStream_t st, int part) {
   const T *Q = reinterpret_cast<const T *>(src);
   T *Lp = reinterpret_cast<T *>(panels);
-  if (aux.nsmall > 0) {
-    hipLaunchKernelGGL(k_normalize_small<T>, dim3((unsigned)(aux.nsmall * pl.batch)), dim3(64), 0, st, dpl, Q, Lp,
-                       reinterpret_cast<T *>(dt), aux.small_nodes, aux.nsmall);
-  }
-  if (aux.nchunks_narrow > 0)
-    hipLaunchKernelGGL((k_normalize_inv<T, 64>), dim3((unsigned)(aux.nchunks_narrow * pl.batch)), dim3(NT), 0, st, dpl,
-                       Q, aux.chunks_narrow, aux.nchunks_narrow);
-  if (aux.nchunks > 0) {
-    hipLaunchKernelGGL((k_normalize_inv<T, 256>), dim3((unsigned)(aux.nchunks * pl.batch)), dim3(NT), 0, st, dpl, Q,
-                       aux.chunks, aux.nchunks);
-  }
-  if (aux.nrblocks > 0) {
-    hipLaunchKernelGGL(k_normalize_gemm<T>, dim3((unsigned)(aux.nrblocks * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
-                       aux.rblocks, aux.nrblocks);
-  }
-  if (aux.nsq_tiles > 0) {
+  // [b, b + n) of a list with nall entries, ntop of them in the top part
+  auto range = [&](int32_t nall, int32_t ntop, int32_t &b) {
+    b = part == 2 ? ntop : 0;
+    return part == 0 ? nall : part == 1 ? ntop : nall - ntop;
+  };
+  int32_t b;
+  const int32_t nsm = range(aux.nsmall, aux.nsmall_top, b);
+  if (nsm > 0)
+    hipLaunchKernelGGL(k_normalize_small<T>, dim3((unsigned)(nsm * pl.batch)), dim3(64), 0, st, dpl, Q, Lp,
+                       reinterpret_cast<T *>(dt), aux.small_nodes + b, nsm);
+  const int32_t nna = range(aux.nchunks_narrow, aux.nchunks_narrow_top, b);
+  if (nna > 0)
+    hipLaunchKernelGGL((k_normalize_inv<T, 64>), dim3((unsigned)(nna * pl.batch)), dim3(NT), 0, st, dpl, Q,
+                       aux.chunks_narrow + b, nna);
+  const int32_t nch = range(aux.nchunks, aux.nchunks_top, b);
+  if (nch > 0)
+    hipLaunchKernelGGL((k_normalize_inv<T, 256>), dim3((unsigned)(nch * pl.batch)), dim3(NT), 0, st, dpl, Q,
+                       aux.chunks + b, nch);
+  const int32_t nrb = range(aux.nrblocks, aux.nrblocks_top, b);
+  if (nrb > 0)
+    hipLaunchKernelGGL(k_normalize_gemm<T>, dim3((unsigned)(nrb * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
+                       aux.rblocks + b, nrb);
+  const int32_t nsq = range(aux.nsq_tiles, aux.nsq_tiles_top, b);
+  if (nsq > 0) {
     if (dt)
-      hipLaunchKernelGGL(k_normalize_sq<T>, dim3((unsigned)(aux.nsq_tiles * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
-                         reinterpret_cast<T *>(dt), aux.sq_tiles, aux.nsq_tiles, 0);
-    hipLaunchKernelGGL(k_normalize_sq<T>, dim3((unsigned)(aux.nsq_tiles * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
-                       (T *)nullptr, aux.sq_tiles, aux.nsq_tiles, 1);
+      hipLaunchKernelGGL(k_normalize_sq<T>, dim3((unsigned)(nsq * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
+                         reinterpret_cast<T *>(dt), aux.sq_tiles + b, nsq, 0);
+    hipLaunchKernelGGL(k_normalize_sq<T>, dim3((unsigned)(nsq * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
+                       (T *)nullptr, aux.sq_tiles + b, nsq, 1);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_normalize(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, const void *src,
-                            void *panels, void *dt, hipStream_t st) {
-  return cplx_ ? normalize_impl<cplx>(pl, dpl, aux, src, panels, dt, st)
-               : normalize_impl<double>(pl, dpl, aux, src, panels, dt, st);
+                            void *panels, void *dt, hipStream_t st, int part) {
+  return cplx_ ? normalize_impl<cplx>(pl, dpl, aux, src, panels, dt, st, part)
+               : normalize_impl<double>(pl, dpl, aux, src, panels, dt, st, part);
 }
 
+// Level launches [q0, q1) under the level schedule (the whole traversal
+// is [0, aux.nlvl)); the persistent schedule ignores the range.
 template <typename T>
 static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, int sched, const void *panels, void *x,
-                           int64_t budget_ticks, int grid, hipStream_t st) {
+                           int64_t budget_ticks, int grid, hipStream_t st, int q0, int q1) {
   const T *Lp = reinterpret_cast<const T *>(panels);
   T *Xp = reinterpret_cast<T *>(x);
   T *Pp = reinterpret_cast<T *>(pl.part);
   if (sched == 1) {
-    for (int q = 0; q < aux.nlvl; ++q) {
+    for (int q = q0; q < q1; ++q) {
       const int32_t b = aux.lvl_ptr[q], e = aux.lvl_ptr[q + 1];
       if (e <= b) continue;
       if (aux.lvl_tiny[q] >= 0)
@@ -611,9 +623,9 @@ static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
 }
 
 hipError_t launch_run(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, int sched, const void *panels,
-                      void *x, int64_t budget_ticks, int grid, hipStream_t st) {
-  return cplx_ ? run_impl<cplx>(pl, dpl, aux, sched, panels, x, budget_ticks, grid, st)
-               : run_impl<double>(pl, dpl, aux, sched, panels, x, budget_ticks, grid, st);
+                      void *x, int64_t budget_ticks, int grid, hipStream_t st, int q0, int q1) {
+  return cplx_ ? run_impl<cplx>(pl, dpl, aux, sched, panels, x, budget_ticks, grid, st, q0, q1)
+               : run_impl<double>(pl, dpl, aux, sched, panels, x, budget_ticks, grid, st, q0, q1);
 }
 
 int persistent_blocks_per_cu(bool cplx_) {

@@ -169,6 +169,11 @@ struct LaunchAux {
   const int4 *blaunch;        // host array: adjoint launches {kind, first, count, 0} in order; kind 0 =
                               // bitems [first, first + count), 1 / 2 = R1 / R3 of small-node records
   int32_t nblaunch;
+  // Top of the tree: the level launches of the depths whose tiles fill at
+  // most a quarter of the GPU (0: none), and the leading entries of each
+  // normalization list that belong to those depths (the lists run root first).
+  int32_t lvl_top;
+  int32_t nsmall_top, nchunks_narrow_top, nchunks_top, nrblocks_top, nsq_tiles_top;
 };
 
 }  // namespace selinv
