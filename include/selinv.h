@@ -199,10 +199,11 @@ selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, voi
  * steps 1-2, then its second loop), with the same arguments and results, but
  * with the two overlapped under SELINV_SCHED_LEVELS: the nodes of the top
  * etree depths (those whose GEMM-1 tiles fill at most a quarter of the GPU)
- * are normalized on `stream` and their depths traversed there, while the
- * other nodes are normalized on a second stream owned by the context; the
- * traversal waits for that stream before its first deeper depth.  The second
- * stream (default priority) and two events are created on the first call,
+ * are normalized on `stream` (their Dt^{-1} blocks on a second stream of the
+ * context, at the same time as their Lhat) and their depths traversed there,
+ * while the other nodes are normalized on a third stream of the context; the
+ * traversal waits for that stream before its first deeper depth.  The two
+ * streams (default priority) and four events are created on the first call,
  * on the current device, and destroyed by selinv_destroy; a context used
  * this way stays on that device (ESTATE otherwise).  Everything is ordered
  * after the work already enqueued on `stream`, and the work of the call is

@@ -19,7 +19,7 @@
 
 namespace selinv {
 hipError_t launch_normalize(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, const void *src,
-                            void *panels, void *dt, hipStream_t st, int part);
+                            void *panels, void *dt, hipStream_t st, int part, int steps);
 hipError_t launch_run(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, int sched,
                       const void *panels, void *x, int64_t budget_ticks, int grid, hipStream_t st, int q0, int q1);
 hipError_t launch_extract(const DevPlan &pl, const DevPlan *dpl, bool cplx_, const void *x, void *out, hipStream_t st);
@@ -675,15 +675,16 @@ struct selinv_ctx {
   // cached strings for views
   std::vector<int64_t> panel_off_view;
 
-  hipStream_t side = nullptr;  // second stream of selinv_normalize_run, and its fork/join events
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t side = nullptr, side2 = nullptr;  // side streams of selinv_normalize_run, and its events
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_inv = nullptr, ev_sq = nullptr;
   int side_device = -1;
 
   ~selinv_ctx() {
     if (pinned) (void)hipHostFree(pinned);
-    if (ev_fork) (void)hipEventDestroy(ev_fork);
-    if (ev_join) (void)hipEventDestroy(ev_join);
+    for (hipEvent_t ev : {ev_fork, ev_join, ev_inv, ev_sq})
+      if (ev) (void)hipEventDestroy(ev);
     if (side) (void)hipStreamDestroy(side);
+    if (side2) (void)hipStreamDestroy(side2);
   }
   bool is_complex() const { return opts.dtype == SELINV_C128; }
   int64_t sbytes() const { return is_complex() ? 16 : 8; }
@@ -995,7 +996,8 @@ selinv_status selinv_factor(selinv_ctx *h, const void *values, void *panels_dev,
   if (e != hipSuccess) return hip_err(h, e, "panel upload");
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
-  e = launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), panels_dev, panels_dev, dtilde_dev, st, 0);
+  e = launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), panels_dev, panels_dev, dtilde_dev, st, 0,
+                       NORM_ALL);
   if (e != hipSuccess) return hip_err(h, e, "normalize launch");
   // the staging buffer is reused by the next call: wait for the copy
   e = hipStreamSynchronize(st);
@@ -1015,7 +1017,7 @@ selinv_status selinv_normalize(selinv_ctx *h, const void *ldlt_dev, void *panels
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
   hipError_t e =
-      launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st, 0);
+      launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st, 0, NORM_ALL);
   if (e != hipSuccess) return hip_err(h, e, "normalize launch");
   h->factored = true;
   return SELINV_OK;
@@ -1103,24 +1105,33 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
   if (h->side && h->side_device != dev) return set_err(h, SELINV_ESTATE, "context used on another device");
   if (!h->side) {
     e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
-    if (e != hipSuccess) return hip_err(h, e, "side stream");
-    e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->side2, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_err(h, e, "side streams");
+    for (hipEvent_t *ev : {&h->ev_fork, &h->ev_join, &h->ev_inv, &h->ev_sq})
+      if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
     if (e != hipSuccess) return hip_err(h, e, "side stream events");
     h->side_device = dev;
   }
   DevPlan pl = make_devplan(h, work_dev);
   const DevPlan *dpl = dev_plan(h, work_dev);
-  // fork: the deeper nodes' normalization on the side stream, after the
-  // caller's earlier work
+  const bool cx = h->is_complex();
+  // fork: the deeper nodes' normalization on the first side stream, after
+  // the caller's earlier work
   e = hipEventRecord(h->ev_fork, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->ev_fork, 0);
-  if (e == hipSuccess)
-    e = launch_normalize(pl, dpl, aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, h->side, 2);
+  if (e == hipSuccess) e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, h->side, 2, NORM_ALL);
   if (e == hipSuccess) e = hipEventRecord(h->ev_join, h->side);
   if (e != hipSuccess) return hip_err(h, e, "normalize (side stream)");
-  // the top nodes' normalization and traversal on the caller's stream
-  e = launch_normalize(pl, dpl, aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st, 1);
+  // the top nodes: L_KK^{-1} on the caller's stream, then Lhat there and
+  // Dt^{-1} on the second side stream at the same time (both need only
+  // L_KK^{-1}; they write different parts of the panels)
+  e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, st, 1, NORM_INV);
+  if (e == hipSuccess) e = hipEventRecord(h->ev_inv, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(h->side2, h->ev_inv, 0);
+  if (e == hipSuccess) e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, h->side2, 1, NORM_SQ);
+  if (e == hipSuccess) e = hipEventRecord(h->ev_sq, h->side2);
+  if (e == hipSuccess) e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, st, 1, NORM_GEMM);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, h->ev_sq, 0);
   if (e != hipSuccess) return hip_err(h, e, "normalize launch");
   h->factored = true;
   e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, 0, aux.lvl_top);

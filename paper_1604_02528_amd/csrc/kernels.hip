@@ -551,10 +551,12 @@ __global__ void k_scatter(const DevPlan *__restrict__ plp, const T *vals, T *P) 
 // Host-side launchers (called from the C ABI translation unit)
 // ---------------------------------------------------------------------------
 // part 0: every node; 1: the nodes of the top depths (the leading entries of
-// each list); 2: the others.
+// each list); 2: the others.  steps: a mask of NORM_INV (the small nodes'
+// whole normalization and L_KK^{-1}), NORM_GEMM (Lhat) and NORM_SQ (Dt^{-1},
+// and Dt when dt is given); NORM_GEMM and NORM_SQ need NORM_INV done.
 template <typename T>
 static hipError_t normalize_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const void *src,
-                                 void *panels, void *dt, hipStream_t st, int part) {
+                                 void *panels, void *dt, hipStream_t st, int part, int steps) {
   const T *Q = reinterpret_cast<const T *>(src);
   T *Lp = reinterpret_cast<T *>(panels);
   // [b, b + n) of a list with nall entries, ntop of them in the top part
@@ -563,23 +565,23 @@ static hipError_t normalize_impl(const DevPlan &pl, const DevPlan *dpl, const La
     return part == 0 ? nall : part == 1 ? ntop : nall - ntop;
   };
   int32_t b;
-  const int32_t nsm = range(aux.nsmall, aux.nsmall_top, b);
+  const int32_t nsm = (steps & NORM_INV) ? range(aux.nsmall, aux.nsmall_top, b) : 0;
   if (nsm > 0)
     hipLaunchKernelGGL(k_normalize_small<T>, dim3((unsigned)(nsm * pl.batch)), dim3(64), 0, st, dpl, Q, Lp,
                        reinterpret_cast<T *>(dt), aux.small_nodes + b, nsm);
-  const int32_t nna = range(aux.nchunks_narrow, aux.nchunks_narrow_top, b);
+  const int32_t nna = (steps & NORM_INV) ? range(aux.nchunks_narrow, aux.nchunks_narrow_top, b) : 0;
   if (nna > 0)
     hipLaunchKernelGGL((k_normalize_inv<T, 64>), dim3((unsigned)(nna * pl.batch)), dim3(NT), 0, st, dpl, Q,
                        aux.chunks_narrow + b, nna);
-  const int32_t nch = range(aux.nchunks, aux.nchunks_top, b);
+  const int32_t nch = (steps & NORM_INV) ? range(aux.nchunks, aux.nchunks_top, b) : 0;
   if (nch > 0)
     hipLaunchKernelGGL((k_normalize_inv<T, 256>), dim3((unsigned)(nch * pl.batch)), dim3(NT), 0, st, dpl, Q,
                        aux.chunks + b, nch);
-  const int32_t nrb = range(aux.nrblocks, aux.nrblocks_top, b);
+  const int32_t nrb = (steps & NORM_GEMM) ? range(aux.nrblocks, aux.nrblocks_top, b) : 0;
   if (nrb > 0)
     hipLaunchKernelGGL(k_normalize_gemm<T>, dim3((unsigned)(nrb * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
                        aux.rblocks + b, nrb);
-  const int32_t nsq = range(aux.nsq_tiles, aux.nsq_tiles_top, b);
+  const int32_t nsq = (steps & NORM_SQ) ? range(aux.nsq_tiles, aux.nsq_tiles_top, b) : 0;
   if (nsq > 0) {
     if (dt)
       hipLaunchKernelGGL(k_normalize_sq<T>, dim3((unsigned)(nsq * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
@@ -591,9 +593,9 @@ static hipError_t normalize_impl(const DevPlan &pl, const DevPlan *dpl, const La
 }
 
 hipError_t launch_normalize(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, const void *src,
-                            void *panels, void *dt, hipStream_t st, int part) {
-  return cplx_ ? normalize_impl<cplx>(pl, dpl, aux, src, panels, dt, st, part)
-               : normalize_impl<double>(pl, dpl, aux, src, panels, dt, st, part);
+                            void *panels, void *dt, hipStream_t st, int part, int steps) {
+  return cplx_ ? normalize_impl<cplx>(pl, dpl, aux, src, panels, dt, st, part, steps)
+               : normalize_impl<double>(pl, dpl, aux, src, panels, dt, st, part, steps);
 }
 
 // Level launches [q0, q1) under the level schedule (the whole traversal

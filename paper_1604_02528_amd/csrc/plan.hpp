@@ -176,4 +176,7 @@ struct LaunchAux {
   int32_t nsmall_top, nchunks_narrow_top, nchunks_top, nrblocks_top, nsq_tiles_top;
 };
 
+// Normalization steps, for launching them separately.
+enum NormSteps : int { NORM_INV = 1, NORM_GEMM = 2, NORM_SQ = 4, NORM_ALL = 7 };
+
 }  // namespace selinv
