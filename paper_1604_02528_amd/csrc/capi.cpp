@@ -1017,7 +1017,8 @@ selinv_status selinv_normalize(selinv_ctx *h, const void *ldlt_dev, void *panels
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
   hipError_t e =
-      launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st, 0, NORM_ALL);
+      launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st, 0,
+                       NORM_ALL);
   if (e != hipSuccess) return hip_err(h, e, "normalize launch");
   h->factored = true;
   return SELINV_OK;
@@ -1138,7 +1139,8 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
   // join before the first depth that needs the deeper nodes
   if (e == hipSuccess) e = hipStreamWaitEvent(st, h->ev_join, 0);
   if (e == hipSuccess)
-    e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, aux.lvl_top, aux.nlvl);
+    e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, aux.lvl_top,
+                   aux.nlvl);
   if (e != hipSuccess) return hip_err(h, e, "selinv launch");
   return SELINV_OK;
 }

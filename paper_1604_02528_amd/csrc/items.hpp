@@ -689,10 +689,11 @@ __device__ void do_stile(const Ctx<T> &cx, const NodeInfo &nd, double *smem, int
 // A whole small node (c <= CM <= kTinyCF, s <= kTinyS) of one matrix in one
 // wavefront, for the level schedule.  Three dependent memory rounds: the
 // record, then the byte offsets of X_{C,C} in the panel array (host table:
-// c x c row-major, then padding), Lhat and Dt^{-1}, then the X_{C,C} values.  Lane (i, grp) holds X_{C,C}(i, k) for k = grp + G u;
-// the partial sums of X_{C,C} Lhat over the G lane groups are combined with
-// a fixed butterfly, so the result does not depend on timing.  LDS blocks
-// are c x s with leading dimension tiny_ldc<T>().
+// c x c row-major, then padding), Lhat and Dt^{-1}, then the X_{C,C} values.
+// Lane (i, grp) holds X_{C,C}(i, k) for k = grp + G u; the partial sums of
+// X_{C,C} Lhat over the G lane groups are combined with a fixed butterfly, so
+// the result does not depend on timing.  LDS blocks are c x s with leading
+// dimension tiny_ldc<T>().
 //   Y = -X_{C,C} Lhat (stored into X_{C,K});  T = Dt^{-1} - Lhat^T Y;
 //   X_{K,K} = (T + T^T) / 2                      (Alg. 1, Eqs. (2.9)-(2.10))
 template <typename T, int CM>
