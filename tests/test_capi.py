@@ -84,6 +84,18 @@ def test_run_before_factor_is_a_state_error():
     assert ei.value.status == 6
 
 
+def test_normalize_run_rejects_null_buffers():
+    """EINVAL (status 1) for a missing buffer, before any device work."""
+    from paper_1604_02528_amd import capi
+
+    w = workload("C1")
+    S = _ctx(w, sched="levels")
+    for args in [(None, 1, 1, 1), (1, None, 1, 1), (1, 1, None, 1), (1, 1, 1, None)]:
+        with pytest.raises(capi.SelinvError) as ei:
+            capi.selinv_normalize_run(S.h, *args, None, None)
+        assert ei.value.status == 1
+
+
 def test_sizes_are_consistent():
     w = workload("C3", 6, 3)
     S = _ctx(w, relax=0.05)
