@@ -316,8 +316,8 @@ def main():
                     help="skip the C3 batched-vs-sequential, C4 adjoint-vs-forward and C5 (largest 3-D case) legs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run its own "
-              "matrices or subtrees; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (each GPU would run its own "
+              "shifts, or its own etree subtrees below a shared top). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
 
