@@ -1104,15 +1104,35 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
   e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_err(h, e, "hipGetDevice");
   if (h->side && h->side_device != dev) return set_err(h, SELINV_ESTATE, "context used on another device");
-  if (!h->side) {
-    e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->side2, hipStreamNonBlocking);
-    if (e != hipSuccess) return hip_err(h, e, "side streams");
-    for (hipEvent_t *ev : {&h->ev_fork, &h->ev_join, &h->ev_inv, &h->ev_sq})
-      if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_err(h, e, "side stream events");
+  if (!h->side) {  // all or nothing: the context keeps them only if every one was created
+    hipStream_t s1 = nullptr, s2 = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    e = hipStreamCreateWithFlags(&s1, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+    for (hipEvent_t &v : ev)
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&v, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      for (hipEvent_t v : ev)
+        if (v) (void)hipEventDestroy(v);
+      if (s1) (void)hipStreamDestroy(s1);
+      if (s2) (void)hipStreamDestroy(s2);
+      return hip_err(h, e, "side streams and events");
+    }
+    h->side = s1;
+    h->side2 = s2;
+    h->ev_fork = ev[0];
+    h->ev_join = ev[1];
+    h->ev_inv = ev[2];
+    h->ev_sq = ev[3];
     h->side_device = dev;
   }
+  // on a failure after the fork, the side streams are drained before
+  // returning, so that no work of this call still writes the caller's buffers
+  auto fail = [&](hipError_t err, const char *what) {
+    (void)hipStreamSynchronize(h->side);
+    (void)hipStreamSynchronize(h->side2);
+    return hip_err(h, err, what);
+  };
   DevPlan pl = make_devplan(h, work_dev);
   const DevPlan *dpl = dev_plan(h, work_dev);
   const bool cx = h->is_complex();
@@ -1122,7 +1142,7 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
   if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->ev_fork, 0);
   if (e == hipSuccess) e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, h->side, 2, NORM_ALL);
   if (e == hipSuccess) e = hipEventRecord(h->ev_join, h->side);
-  if (e != hipSuccess) return hip_err(h, e, "normalize (side stream)");
+  if (e != hipSuccess) return fail(e, "normalize (side stream)");
   // the top nodes: L_KK^{-1} on the caller's stream, then Lhat there and
   // Dt^{-1} on the second side stream at the same time (both need only
   // L_KK^{-1}; they write different parts of the panels)
@@ -1133,7 +1153,7 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
   if (e == hipSuccess) e = hipEventRecord(h->ev_sq, h->side2);
   if (e == hipSuccess) e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, st, 1, NORM_GEMM);
   if (e == hipSuccess) e = hipStreamWaitEvent(st, h->ev_sq, 0);
-  if (e != hipSuccess) return hip_err(h, e, "normalize launch");
+  if (e != hipSuccess) return fail(e, "normalize launch");
   h->factored = true;
   e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, 0, aux.lvl_top);
   // join before the first depth that needs the deeper nodes
@@ -1141,7 +1161,7 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
   if (e == hipSuccess)
     e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, aux.lvl_top,
                    aux.nlvl);
-  if (e != hipSuccess) return hip_err(h, e, "selinv launch");
+  if (e != hipSuccess) return fail(e, "selinv launch");
   return SELINV_OK;
 }
 
