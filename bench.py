@@ -283,7 +283,7 @@ def adjoint_leg(relax):
         e[1].record(stream)
         xbar.copy_(xbar0)
         e[2].record(stream)
-        capi.selinv_backward(S.h, S._bufs["panels"], S._bufs["x"], S.dtilde, xbar, S._bufs["work"], abar,
+        capi.selinv_backward(S.h, S._bufs["panels"], S._bufs["x"], S.dtilde, xbar, None, S._bufs["work"], abar,
                              stream.cuda_stream)
         e[3].record(stream)
         torch.cuda.synchronize()

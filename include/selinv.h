@@ -65,8 +65,9 @@ typedef enum {
 
 /* Scheduling of the selected-inversion traversal (root to leaves). */
 typedef enum {
-  SELINV_SCHED_PERSISTENT = 0, /* one launch; per-node dependency counters + device ready queue */
-  SELINV_SCHED_LEVELS = 1      /* one launch per etree level and phase (reference schedule) */
+  SELINV_SCHED_PERSISTENT = 0, /* one launch; workgroups draw tickets of a topological order and wait on
+                                  per-node dependency counters */
+  SELINV_SCHED_LEVELS = 1      /* one launch per etree depth and phase (the default: measured faster) */
 } selinv_sched;
 
 typedef struct {
@@ -78,7 +79,10 @@ typedef struct {
   int32_t nthreads;    /* host threads for the factorization; 0 = hardware concurrency */
   int32_t dense_min_c; /* nodes with |C(K)| >= this get a dense X_{C,C} buffer in the work area
                           (gathered once, then read by plain GEMM tiles); 0 = 256, < 0 = never */
-  int64_t watchdog_ms; /* persistent kernel spin budget before it aborts (0 = 10000 ms) */
+  int64_t watchdog_ms; /* persistent schedule: budget of each single dependency wait, in ms (0 = 10000);
+                          < 0: -watchdog_ms device clock ticks (a way to exercise the expiry path).  An
+                          expired wait raises the device error flag, every workgroup exits, and
+                          selinv_sync returns SELINV_EDEVICE; X is then undefined */
   int64_t dense_max_bytes; /* cap on those buffers for the whole batch; the threshold is doubled
                               until they fit (0 = 32 GiB).  Under SELINV_SCHED_LEVELS the buffers
                               of different etree depths share memory, so the cap applies to the
@@ -90,7 +94,8 @@ typedef struct {
   int32_t reserved;
 } selinv_opts;
 
-/* Fill `o` with defaults (cap 256, R64, batch 1, persistent, relax 0). */
+/* Fill `o` with defaults (cap 256, R64, batch 1, level schedule, relax 0.05).  relax = 0 gives the
+   paper's maximal supernodes exactly; the default 0.05 is the fastest measured setting. */
 void selinv_default_opts(selinv_opts *o);
 
 /*
@@ -239,16 +244,23 @@ selinv_status selinv_scatter(const selinv_ctx *h, const void *vals_dev, void *wo
  *     selected entries (top blocks: lower triangle incl. diagonal; the strict
  *     upper triangle of every top block is ignored).  Overwritten: used as the
  *     accumulator of the reverse sweep.
+ *   wlogdet_dev [batch] (device) or NULL: dloss/d(log det A_l) for a loss that
+ *     also depends on the log-determinants (selinv_logdet).  Since
+ *     d log det A / dA = A^{-1}, matrix l adds wlogdet[l] times its selected
+ *     inverse on A's pattern (x2 off the diagonal) to abar.
  *   abar_dev [batch][nnz(A)]: dloss/da for A's stored lower values, original
  *     indexing (off-diagonal values stand for both (i, j) and (j, i)).
- * Needs the panels and x of a completed selinv_factor (with dtilde_dev) and
- * selinv_run, and the same work buffer.  Runs the level schedule (R1 leaves to
- * root with FP64 atomic scatter-adds, then R3 root to leaves); asynchronous on
- * `stream`.  Errors: SELINV_ESTATE (before factor), SELINV_EUNSUPPORTED
- * (complex), SELINV_EINVAL (null buffer).
+ * State: panels_dev and dtilde_dev must be the buffers the last
+ * selinv_factor / selinv_normalize / selinv_normalize_run wrote (that call
+ * given a dtilde_dev), and x_dev the buffer of a selinv_run (or
+ * selinv_normalize_run) after it; SELINV_ESTATE otherwise.  Same work buffer.
+ * Runs the level schedule (R1 leaves to root with FP64 atomic scatter-adds,
+ * then R3 root to leaves); asynchronous on `stream`.  Errors: SELINV_ESTATE,
+ * SELINV_EUNSUPPORTED (complex), SELINV_EINVAL (null buffer).
  */
 selinv_status selinv_backward(selinv_ctx *h, const void *panels_dev, const void *x_dev, const void *dtilde_dev,
-                              void *xbar_dev, void *work_dev, void *abar_dev, void *stream);
+                              void *xbar_dev, const void *wlogdet_dev, void *work_dev, void *abar_dev,
+                              void *stream);
 
 /*
  * selinv_check_plan -- host replay of the persistent schedule's protocol on
@@ -274,14 +286,20 @@ selinv_status selinv_check_plan(const selinv_ctx *h);
 selinv_status selinv_trace(selinv_ctx *h, void *trace_dev);
 
 /*
- * selinv_items -- the traversal's work items for one matrix (diagnostics).
- * *items receives a host view of n rows of four int32 {K, type, a, b}
- * (type: 0 GEMM-1 tile, 1 diagonal-block tile, 2 single-workgroup node,
- * 3 dense X_{C,C} gather block, 4 split-tile reduction; for type 0, b holds
- * the column tile in its low 16 bits and the contraction part above them),
- * valid until selinv_destroy.  Item id i of matrix l is l * n + i in traces.
+ * selinv_items -- work items for one matrix (diagnostics).  *items receives a
+ * host view of n rows of four int32 {K, type, a, b}, valid until
+ * selinv_destroy.
+ *   which = 0: the forward traversal's items (type: 0 GEMM-1 tile,
+ *     1 diagonal-block tile, 2 single-workgroup node, 3 dense X_{C,C} gather
+ *     block, 4 split-tile reduction; for type 0, b holds the column tile in
+ *     its low 16 bits and the contraction part above them).  Item id i of
+ *     matrix l is l * n + i in traces.
+ *   which = 1: the adjoint's items in launch order (R1 leaves to root, then
+ *     R3 root to leaves); type 0..11 as the BackItemType of the device plan,
+ *     12 / 13 = the whole R1 / R3 of a small node in one wavefront.
+ * Errors: SELINV_EINVAL for another `which`.
  */
-selinv_status selinv_items(const selinv_ctx *h, const int32_t **items, int64_t *n);
+selinv_status selinv_items(const selinv_ctx *h, int32_t which, const int32_t **items, int64_t *n);
 
 /* log det of each matrix of the batch (sum of log pivots; complex log for C128).
    out_host: batch doubles (R64) or batch (re, im) pairs (C128).  Valid after selinv_factor. */

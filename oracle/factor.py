@@ -136,13 +136,27 @@ def dtilde(sym, panels):
 
 
 def logdet(sym, panels):
-    """log det B = sum_j log D_jj (complex log for complex-symmetric B)."""
-    tot = 0.0
+    """log det B from the pivots: B = L D L^T with L unit lower triangular
+    (Section 2.3), so det B = prod_j D_jj.
+
+    Branch convention: the sum over j of the principal logarithm of D_jj
+    (not reduced to one branch afterwards).  Its real part is log|det B| and
+    its exponential is det B.  A real B with positive pivots gives a float; a
+    real B with negative pivots gives a complex value whose imaginary part is
+    pi times the number of negative pivots (the inertia), and a complex B the
+    sum of the pivots' arguments.
+    """
+    tot = 0.0 + 0.0j
+    neg = False
     for K in range(sym.nsuper):
         s = sym.width(K)
         d = np.diag(panels[K][:s, :s])
-        tot = tot + np.sum(np.log(d.astype(np.complex128) if np.iscomplexobj(d) else d))
-    return tot
+        if not np.iscomplexobj(d):
+            neg = neg or bool(np.any(d < 0))
+        tot = tot + np.sum(np.log(d.astype(np.complex128)))
+    if not np.iscomplexobj(panels[0]) and not neg:
+        return float(tot.real)
+    return complex(tot)
 
 
 def to_dense_L(sym, panels):

@@ -8,51 +8,43 @@
 x holds the selected entries of A^{-1} on A's stored lower pattern (original
 indexing), logdet the log-determinants.  Gradients use the stored-value
 convention: an off-diagonal value stands for both (i, j) and (j, i).  The
-backward pass scatters dloss/dx into the panel layout (selinv_scatter) and runs
-the library's reverse sweep (selinv_backward); d logdet / da is the selected
-inverse itself (doubled off the diagonal).  S keeps the state of the last
-forward call, so each forward must be followed by its own backward before S is
-used again.
+backward pass hands dloss/dx to the library's scatter (panel layout) and its
+reverse sweep (selinv_backward), which also adds the log-det term
+d log det A / dA = A^{-1}; no arithmetic happens here.  S holds the buffers of
+the last forward call: a backward whose forward is no longer the latest
+factorization of S raises instead of differentiating the wrong matrix.
 """
 
 from __future__ import annotations
 
-import numpy as np
 import torch
 
 from .selinv import SelInv
 
 
-def _offdiag_scale(S: SelInv) -> torch.Tensor:
-    if getattr(S, "_offdiag", None) is None:
-        cols = np.repeat(np.arange(S.n), np.diff(S._colptr))
-        scale = np.where(S._rowind == cols, 1.0, 2.0)
-        S._offdiag = torch.from_numpy(scale).to(S.device)
-    return S._offdiag
-
-
 class SelInvFunction(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, values, S):
+    def forward(ctx, values, S: SelInv):
         if S.is_complex:
-            raise NotImplementedError("the adjoint is implemented for float64 only")
+            raise NotImplementedError("the autograd binding is implemented for float64 only")
         S.factor(values.detach(), want_dtilde=True)
         S.run()
         x = S.extract()
         logdet = torch.as_tensor(S.logdet(), dtype=torch.float64, device=x.device)
         ctx.S = S
+        ctx.generation = S.generation
         ctx.in_device = values.device
-        ctx.save_for_backward(x)
         return x, logdet
 
     @staticmethod
     def backward(ctx, gx, glogdet):
         S = ctx.S
-        (x,) = ctx.saved_tensors
+        if S.generation != ctx.generation:
+            raise RuntimeError("SelInvFunction.backward: S was factored again after this forward call; "
+                               "run each forward's backward before the next forward on the same SelInv")
         if gx is None:
-            gx = torch.zeros_like(x)
+            gx = torch.zeros((S.batch, S.nnzA), dtype=torch.float64, device=S.device)
         xbar = S.scatter(gx.contiguous())
-        abar = S.backward(xbar)
-        if glogdet is not None:
-            abar = abar + glogdet.reshape(-1, 1) * x * _offdiag_scale(S)
+        wl = None if glogdet is None else glogdet.contiguous()
+        abar = S.backward(xbar, wl)
         return abar.to(ctx.in_device), None

@@ -88,11 +88,11 @@ def load():
         "selinv_normalize_run": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "selinv_extract": (C.c_int, [vp, vp, vp, vp, vp]),
         "selinv_scatter": (C.c_int, [vp, vp, vp, vp, vp]),
-        "selinv_backward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp]),
+        "selinv_backward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
         "selinv_logdet": (C.c_int, [vp, vp]),
         "selinv_check_plan": (C.c_int, [vp]),
         "selinv_trace": (C.c_int, [vp, vp]),
-        "selinv_items": (C.c_int, [vp, C.POINTER(_P32), C.POINTER(C.c_int64)]),
+        "selinv_items": (C.c_int, [vp, C.c_int32, C.POINTER(_P32), C.POINTER(C.c_int64)]),
         "selinv_sync": (C.c_int, [vp, vp]),
         "selinv_last_error": (C.c_char_p, [vp]),
         "selinv_error_info": (C.c_int64, [vp, C.c_int]),
@@ -191,8 +191,9 @@ def selinv_scatter(h, vals, work, panel, stream):
     check(h, load().selinv_scatter(h, ptr(vals), ptr(work), ptr(panel), stream))
 
 
-def selinv_backward(h, panels, x, dtilde, xbar, work, abar, stream):
-    check(h, load().selinv_backward(h, ptr(panels), ptr(x), ptr(dtilde), ptr(xbar), ptr(work), ptr(abar), stream))
+def selinv_backward(h, panels, x, dtilde, xbar, wlogdet, work, abar, stream):
+    check(h, load().selinv_backward(h, ptr(panels), ptr(x), ptr(dtilde), ptr(xbar), ptr(wlogdet), ptr(work),
+                                    ptr(abar), stream))
 
 
 def selinv_logdet(h, out_host):
@@ -207,13 +208,14 @@ def selinv_trace(h, trace):
     check(h, load().selinv_trace(h, ptr(trace)))
 
 
-def selinv_items(h):
-    """Host copy of the work items, int32 [n, 4] rows {K, type, a, b}."""
+def selinv_items(h, which=0):
+    """Host copy of the work items, int32 [n, 4] rows {K, type, a, b}
+    (which = 0: the forward traversal, 1: the adjoint in launch order)."""
     import numpy as np
 
     p = _P32()
     n = C.c_int64()
-    check(h, load().selinv_items(h, C.byref(p), C.byref(n)))
+    check(h, load().selinv_items(h, which, C.byref(p), C.byref(n)))
     return np.ctypeslib.as_array(p, shape=(n.value, 4)).copy() if n.value else np.zeros((0, 4), np.int32)
 
 

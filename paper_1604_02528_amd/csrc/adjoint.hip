@@ -452,14 +452,17 @@ __global__ void __launch_bounds__(64) k_back_tiny(const DevPlan *__restrict__ pl
   }
 }
 
-// Abar on A's pattern (stored-value convention: doubled off the diagonal).
-__global__ void k_abar(const DevPlan *__restrict__ plp, double *abar) {
+// Abar on A's pattern (stored-value convention: doubled off the diagonal),
+// plus wlogdet[l] X (d log det A / dA = A^{-1}) when the loss has log-det terms.
+__global__ void k_abar(const DevPlan *__restrict__ plp, const double *x, const double *wlogdet, double *abar) {
   const DevPlan &pl = *plp;
   const int64_t total = pl.batch * pl.nnzA;
   const double *S = static_cast<const double *>(pl.adj_s);
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t l = q / pl.nnzA, e = q - l * pl.nnzA;
-    const double v = S[l * pl.panel_elems + gp(pl.apos)[e]];
+    const int64_t p = l * pl.panel_elems + gp(pl.apos)[e];
+    double v = S[p];
+    if (wlogdet) v += wlogdet[l] * x[p];
     abar[q] = gp(pl.adiag)[e] ? v : 2.0 * v;
   }
 }
@@ -467,7 +470,7 @@ __global__ void k_abar(const DevPlan *__restrict__ plp, double *abar) {
 }  // namespace
 
 hipError_t launch_backward(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const void *panels,
-                           const void *x, const void *dt, void *xbar, void *abar, hipStream_t st) {
+                           const void *x, const void *dt, void *xbar, const void *wlogdet, void *abar, hipStream_t st) {
   if (!pl.adj_s) return hipErrorNotSupported;
   const double *P = static_cast<const double *>(panels), *X = static_cast<const double *>(x),
                *D = static_cast<const double *>(dt);
@@ -487,7 +490,8 @@ hipError_t launch_backward(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
   unsigned grid = (unsigned)((total + 255) / 256);
   if (grid > 65536u) grid = 65536u;
   if (grid == 0) grid = 1;
-  hipLaunchKernelGGL(k_abar, dim3(grid), dim3(256), 0, st, dpl, static_cast<double *>(abar));
+  hipLaunchKernelGGL(k_abar, dim3(grid), dim3(256), 0, st, dpl, X, static_cast<const double *>(wlogdet),
+                     static_cast<double *>(abar));
   return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ hipError_t launch_run(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &au
 hipError_t launch_extract(const DevPlan &pl, const DevPlan *dpl, bool cplx_, const void *x, void *out, hipStream_t st);
 int persistent_blocks_per_cu(bool cplx_);
 hipError_t launch_backward(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const void *panels,
-                           const void *x, const void *dt, void *xbar, void *abar, hipStream_t st);
+                           const void *x, const void *dt, void *xbar, const void *wlogdet, void *abar, hipStream_t st);
 hipError_t launch_scatter(const DevPlan &pl, const DevPlan *dpl, bool cplx_, const void *vals, void *panel,
                           hipStream_t st);
 }  // namespace selinv
@@ -404,6 +404,16 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     nph(3, K) = nb * (nb + 1) / 2 * nsl;
   }
   H.item_ptr[ns] = (int32_t)H.items.size();
+  // item ids of the whole batch are int32 (and the ticket order holds one per
+  // item and matrix): refuse before anything of that size is allocated
+  if ((int64_t)H.items.size() * batch >= (int64_t)INT32_MAX) {
+    Failure f;
+    f.status = SELINV_ENOMEM;
+    f.msg = "too many work items for int32 item ids (batch x items)";
+    f.info0 = (int64_t)H.items.size();
+    f.info1 = batch;
+    throw f;
+  }
   H.node_parent.resize(ns);
   for (int64_t K = 0; K < ns; ++K) H.node_parent[K] = (int32_t)S.sparent[K];
   ticket_order(S, H, batch);
@@ -664,6 +674,13 @@ struct selinv_ctx {
   std::vector<double> logdet;        // 2 per matrix
   bool factored = false;
   bool have_logdet = false;
+  // What the buffers hold, for selinv_backward's state checks: `gen` counts
+  // successful normalizations (selinv_factor / selinv_normalize /
+  // selinv_normalize_run); the others record the generation and the buffer
+  // of the last Dt output and of the last traversal.
+  uint64_t gen = 0, dtilde_gen = 0, run_gen = 0;
+  const void *panels_at = nullptr, *dtilde_at = nullptr, *x_at = nullptr;
+  std::vector<Item> bseq;            // adjoint launch sequence for selinv_items (built on demand)
   void *uploaded_to = nullptr;       // work buffer holding the tables
   int device = -1;
   double *pinned = nullptr;          // host staging of the factor panels
@@ -699,6 +716,17 @@ selinv_status set_err(selinv_ctx *h, selinv_status st, const std::string &m, int
     h->info[1] = i1;
   }
   return st;
+}
+
+// A normalization into panels_dev (with Dt into dtilde_dev when non-null) was enqueued.
+void note_normalized(selinv_ctx *h, const void *panels_dev, const void *dtilde_dev) {
+  h->factored = true;
+  h->gen++;
+  h->panels_at = panels_dev;
+  if (dtilde_dev) {
+    h->dtilde_gen = h->gen;
+    h->dtilde_at = dtilde_dev;
+  }
 }
 
 selinv_status hip_err(selinv_ctx *h, hipError_t e, const char *where) {
@@ -861,8 +889,8 @@ void selinv_default_opts(selinv_opts *o) {
   o->max_super = 256;
   o->dtype = SELINV_R64;
   o->batch = 1;
-  o->sched = SELINV_SCHED_PERSISTENT;
-  o->relax = 0.0;
+  o->sched = SELINV_SCHED_LEVELS;
+  o->relax = 0.05;
   o->nthreads = 0;
   o->dense_min_c = 0;
   o->watchdog_ms = 0;
@@ -1002,7 +1030,7 @@ selinv_status selinv_factor(selinv_ctx *h, const void *values, void *panels_dev,
   // the staging buffer is reused by the next call: wait for the copy
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_err(h, e, "factor sync");
-  h->factored = true;
+  note_normalized(h, panels_dev, dtilde_dev);
   return SELINV_OK;
 }
 
@@ -1020,7 +1048,7 @@ selinv_status selinv_normalize(selinv_ctx *h, const void *ldlt_dev, void *panels
       launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st, 0,
                        NORM_ALL);
   if (e != hipSuccess) return hip_err(h, e, "normalize launch");
-  h->factored = true;
+  note_normalized(h, panels_dev, dtilde_dev);
   return SELINV_OK;
 }
 
@@ -1076,13 +1104,16 @@ selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, voi
     h->grid = ncu * std::min(per, want);
     h->wall_khz = khz > 0 ? khz : 100000;
   }
-  const int64_t ms = h->opts.watchdog_ms > 0 ? h->opts.watchdog_ms : 10000;
-  const int64_t budget = ms * h->wall_khz;
+  // per-wait budget: watchdog_ms milliseconds, 0 = 10 s, < 0 = -watchdog_ms device clock ticks
+  const int64_t wd = h->opts.watchdog_ms;
+  const int64_t budget = wd < 0 ? -wd : (wd > 0 ? wd : 10000) * h->wall_khz;
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
   e = launch_run(pl, dev_plan(h, work_dev), aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, budget, h->grid,
                  st, 0, aux.nlvl);
   if (e != hipSuccess) return hip_err(h, e, "selinv launch");
+  h->run_gen = h->gen;
+  h->x_at = x_dev;
   return SELINV_OK;
 }
 
@@ -1154,7 +1185,7 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
   if (e == hipSuccess) e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, st, 1, NORM_GEMM);
   if (e == hipSuccess) e = hipStreamWaitEvent(st, h->ev_sq, 0);
   if (e != hipSuccess) return fail(e, "normalize launch");
-  h->factored = true;
+  note_normalized(h, panels_dev, dtilde_dev);
   e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, 0, aux.lvl_top);
   // join before the first depth that needs the deeper nodes
   if (e == hipSuccess) e = hipStreamWaitEvent(st, h->ev_join, 0);
@@ -1162,6 +1193,8 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
     e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, aux.lvl_top,
                    aux.nlvl);
   if (e != hipSuccess) return fail(e, "selinv launch");
+  h->run_gen = h->gen;
+  h->x_at = x_dev;
   return SELINV_OK;
 }
 
@@ -1194,18 +1227,28 @@ selinv_status selinv_scatter(const selinv_ctx *hc, const void *vals_dev, void *w
 }
 
 selinv_status selinv_backward(selinv_ctx *h, const void *panels_dev, const void *x_dev, const void *dtilde_dev,
-                              void *xbar_dev, void *work_dev, void *abar_dev, void *stream) {
+                              void *xbar_dev, const void *wlogdet_dev, void *work_dev, void *abar_dev,
+                              void *stream) {
   if (!h) return SELINV_EINVAL;
   if (!h->factored) return set_err(h, SELINV_ESTATE, "selinv_backward before a successful selinv_factor");
   if (h->is_complex()) return set_err(h, SELINV_EUNSUPPORTED, "the adjoint is implemented for R64 only");
   if (!panels_dev || !x_dev || !dtilde_dev || !xbar_dev || !work_dev || !abar_dev)
     return set_err(h, SELINV_EINVAL, "null buffer");
+  if (h->dtilde_gen != h->gen || dtilde_dev != h->dtilde_at)
+    return set_err(h, SELINV_ESTATE, "selinv_backward: dtilde_dev does not hold the Dt blocks of the last "
+                                     "factorization (pass dtilde_dev to selinv_factor / selinv_normalize)");
+  if (panels_dev != h->panels_at)
+    return set_err(h, SELINV_ESTATE, "selinv_backward: panels_dev is not the buffer of the last factorization");
+  if (h->run_gen != h->gen || x_dev != h->x_at)
+    return set_err(h, SELINV_ESTATE, "selinv_backward: x_dev does not hold the selected inverse of the last "
+                                     "factorization (call selinv_run after selinv_factor)");
   hipStream_t st = (hipStream_t)stream;
   selinv_status ss = ensure_uploaded(h, work_dev, st);
   if (ss != SELINV_OK) return ss;
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
-  hipError_t e = launch_backward(pl, dev_plan(h, work_dev), aux, panels_dev, x_dev, dtilde_dev, xbar_dev, abar_dev, st);
+  hipError_t e = launch_backward(pl, dev_plan(h, work_dev), aux, panels_dev, x_dev, dtilde_dev, xbar_dev, wlogdet_dev,
+                                 abar_dev, st);
   if (e != hipSuccess) return hip_err(h, e, "backward launch");
   return SELINV_OK;
 }
@@ -1274,12 +1317,31 @@ selinv_status selinv_check_plan(const selinv_ctx *hc) {
   return SELINV_OK;
 }
 
-selinv_status selinv_items(const selinv_ctx *hc, const int32_t **items, int64_t *n) {
+selinv_status selinv_items(const selinv_ctx *hc, int32_t which, const int32_t **items, int64_t *n) {
   selinv_ctx *h = const_cast<selinv_ctx *>(hc);
   if (!h || !items || !n) return SELINV_EINVAL;
   if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
-  *items = reinterpret_cast<const int32_t *>(h->H.items.data());
-  *n = (int64_t)h->H.items.size();
+  if (which == 0) {
+    *items = reinterpret_cast<const int32_t *>(h->H.items.data());
+    *n = (int64_t)h->H.items.size();
+    return SELINV_OK;
+  }
+  if (which != 1) return set_err(h, SELINV_EINVAL, "selinv_items: which must be 0 (forward) or 1 (adjoint)");
+  // the adjoint's launches in order, a small-node launch expanded into one
+  // row per node
+  if (h->bseq.empty()) {
+    const HostPlan &H = h->H;
+    for (const int4 &bl : H.blaunch) {
+      if (bl.x == 0) {
+        for (int32_t q = bl.y; q < bl.y + bl.z; ++q) h->bseq.push_back(H.bitems[q]);
+      } else {
+        for (int32_t q = bl.y; q < bl.y + bl.z; ++q)
+          h->bseq.push_back(Item{H.tiny[q].K, bl.x == 1 ? BI_TINY_R1 : BI_TINY_R3, 0, 0});
+      }
+    }
+  }
+  *items = reinterpret_cast<const int32_t *>(h->bseq.data());
+  *n = (int64_t)h->bseq.size();
   return SELINV_OK;
 }
 
@@ -1300,6 +1362,8 @@ selinv_status selinv_sync(selinv_ctx *h, void *stream) {
     const unsigned char *b = static_cast<const unsigned char *>(h->uploaded_to);
     e = hipMemcpy(ctrl, b + h->H.off.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_err(h, e, "control readback");
+    if (ctrl[CTRL_ERR] == 2)
+      return set_err(h, SELINV_EDEVICE, "persistent scheduler: a workgroup drew more tickets than there are items");
     if (ctrl[CTRL_ERR] != 0)
       return set_err(h, SELINV_EDEVICE, "persistent scheduler watchdog expired (an item waited too long for its dependencies)");
   }

@@ -127,9 +127,11 @@ __global__ void k_sched_init(const DevPlan *__restrict__ plp) {
 // item `it` of matrix l may run: an item waits for the previous non-empty
 // phase of its node; an item of the node's first phase waits for the node's
 // parent to finish (a root's first items are ready at once).  Returns false
-// when another workgroup raised the error flag or when the watchdog, counted
-// from kernel start, expires (then it raises the flag).
-__device__ bool wait_ready(const DevPlan &pl, int64_t l, const Item &it, int64_t t_begin, int64_t budget_ticks) {
+// when another workgroup raised the error flag or when this wait alone has
+// spun for more than budget_ticks device clock ticks (then it raises the
+// flag): a long traversal is never cut short, only a dependency that does
+// not arrive.
+__device__ bool wait_ready(const DevPlan &pl, int64_t l, const Item &it, int64_t budget_ticks) {
   const int64_t nsb = pl.batch * pl.ns;
   int pv = item_phase(it.type) - 1;
   while (pv >= 0 && uniform(gp(pl.nph)[pv * pl.ns + it.K]) == 0) --pv;
@@ -142,6 +144,7 @@ __device__ bool wait_ready(const DevPlan &pl, int64_t l, const Item &it, int64_t
     ctr = pl.cnt + (kPhases - 1) * nsb + l * pl.ns + P;
   }
   int backoff = 1;
+  const int64_t t_begin = wall_clock64();
   while (uniform(ld_relaxed(ctr)) != 0) {
     if (uniform(ld_relaxed(pl.ctrl + CTRL_ERR)) != 0) return false;
     if (wall_clock64() - t_begin > budget_ticks) {
@@ -158,7 +161,10 @@ __device__ bool wait_ready(const DevPlan &pl, int64_t l, const Item &it, int64_t
 // runs the items of the ticket order (a topological order of the dependency
 // graph), each after its own dependencies are done.  The ticket draw, the
 // wait and the counter update are done by wave 0 as a whole; every branch
-// around a barrier is wave-uniform.
+// around a barrier is wave-uniform.  Exits: the tickets run out, the error
+// flag is up (checked at every draw), a wait expires, or a workgroup has
+// drawn more tickets than there are items (impossible unless the loop
+// misbehaves; it then raises the flag instead of spinning on).
 template <typename T>
 __global__ void __launch_bounds__(NT, 1)
     k_persistent(const DevPlan *__restrict__ plp, const T *Lp, T *Xp, T *Pp, int64_t budget_ticks) {
@@ -168,20 +174,28 @@ __global__ void __launch_bounds__(NT, 1)
   __shared__ int32_t s_id, s_ticket;
   __shared__ int64_t s_tpop;
   const int64_t total = pl.batch * pl.nitems;
-  const int64_t t_begin = wall_clock64();
   const bool wave0 = uniform((int32_t)threadIdx.x) < 64;
   const bool lane0 = threadIdx.x == 0;
+  int64_t draws = 0;
   while (true) {
     if (wave0) {
-      int32_t t = 0;
-      if (lane0) t = add_relaxed(pl.ctrl + CTRL_TICKET, 1);
-      t = uniform(t);
-      const int64_t t_draw = pl.trace ? wall_clock64() : 0;
       int32_t id = -1;
-      if (t < total) {
-        id = uniform(gp(pl.order)[t]);
-        const int64_t l = id / pl.nitems;
-        if (!wait_ready(pl, l, uniform(gload(pl.items + (id - l * pl.nitems))), t_begin, budget_ticks)) id = -2;
+      int32_t t = 0;
+      int64_t t_draw = 0;
+      if (uniform(ld_relaxed(pl.ctrl + CTRL_ERR)) != 0) {
+        id = -2;
+      } else if (++draws > total + 1) {
+        if (lane0) st_relaxed(pl.ctrl + CTRL_ERR, 2);
+        id = -2;
+      } else {
+        if (lane0) t = add_relaxed(pl.ctrl + CTRL_TICKET, 1);
+        t = uniform(t);
+        t_draw = pl.trace ? wall_clock64() : 0;
+        if (t < total) {
+          id = uniform(gp(pl.order)[t]);
+          const int64_t l = id / pl.nitems;
+          if (!wait_ready(pl, l, uniform(gload(pl.items + (id - l * pl.nitems))), budget_ticks)) id = -2;
+        }
       }
       if (lane0) {
         s_id = id;

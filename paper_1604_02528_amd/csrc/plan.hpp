@@ -54,7 +54,9 @@ enum BackItemType : int32_t {
   BI_M = 8,   // R3 phase 1: M = Sbar_{C,C} Lhat
   BI_LB = 9,  // R3 phase 2: Lb = Lhatbar - 2 M Dt
   BI_N = 10,  // R3 phase 3: N = Lb E; Sbar_{C,K} = N / 2; GEMM-2 share of Lhat^T (M + N)
-  BI_DF = 11  // R3 phase 4: Sbar_KK = sym(Dtbar0 - Lhat^T (M + N))
+  BI_DF = 11, // R3 phase 4: Sbar_KK = sym(Dtbar0 - Lhat^T (M + N))
+  BI_TINY_R1 = 12,  // (selinv_items only) all of R1 for a small node, one wavefront
+  BI_TINY_R3 = 13   // (selinv_items only) all of R3 for a small node, one wavefront
 };
 constexpr int kBackR1Phases = 4;
 constexpr int kBackR3Phases = 5;

@@ -26,8 +26,8 @@ def _bytes(nbytes, device):
 
 
 class SelInv:
-    def __init__(self, n, colptr, rowind, perm=None, *, dtype="f64", batch=1, cap=256, relax=0.0,
-                 sched="persistent", nthreads=0, watchdog_ms=0, dense_min_c=0, dense_max_bytes=0, split_min_k=0, device="cuda"):
+    def __init__(self, n, colptr, rowind, perm=None, *, dtype="f64", batch=1, cap=256, relax=0.05,
+                 sched="levels", nthreads=0, watchdog_ms=0, dense_min_c=0, dense_max_bytes=0, split_min_k=0, device="cuda"):
         self.n = int(n)
         self.is_complex = dtype in ("c128", "complex128", torch.complex128)
         self.batch = int(batch)
@@ -53,6 +53,7 @@ class SelInv:
         self.panel_elems = int(self.view.panel_elems)
         self._bufs = None
         self.dtilde = None
+        self.generation = 0  # successful factor() calls (the autograd binding checks it)
 
     # -- symbolic data (host copies) -------------------------------------------
     def symbolic(self):
@@ -124,6 +125,7 @@ class SelInv:
         self._vals_keep = v
         capi.selinv_factor(self.h, v, self._bufs["panels"], self._bufs["work"],
                            self.dtilde if want_dtilde else None, _stream())
+        self.generation += 1
 
     def factor_host(self, values):
         """Host LDL^T panels only (numpy [batch, panel_elems])."""
@@ -162,13 +164,15 @@ class SelInv:
         capi.selinv_scatter(self.h, vals, self._bufs["work"], out, _stream())
         return out
 
-    def backward(self, xbar, abar=None):
+    def backward(self, xbar, wlogdet=None, abar=None):
         """Adjoint (FP64): xbar [batch, panel_elems] device tensor, dloss/dx for the
-        stored selected entries (overwritten); returns dloss/da on A's pattern
-        [batch, nnz(A)].  Needs factor(..., want_dtilde=True) and run() first."""
+        stored selected entries (overwritten); wlogdet: None or a [batch] device
+        tensor, dloss/d(log det A_l); returns dloss/da on A's pattern
+        [batch, nnz(A)].  Needs factor(..., want_dtilde=True) and run() first
+        (the library returns ESTATE otherwise)."""
         if abar is None:
             abar = torch.empty((self.batch, self.nnzA), dtype=self.scalar_dtype, device=self.device)
-        capi.selinv_backward(self.h, self._bufs["panels"], self._bufs["x"], self.dtilde, xbar,
+        capi.selinv_backward(self.h, self._bufs["panels"], self._bufs["x"], self.dtilde, xbar, wlogdet,
                              self._bufs["work"], abar, _stream())
         return abar
 

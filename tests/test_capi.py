@@ -112,21 +112,152 @@ def test_backward_before_factor_is_a_state_error():
     w = workload("C1")
     S = _ctx(w)
     with pytest.raises(capi.SelinvError) as ei:
-        capi.selinv_backward(S.h, 1, 1, 1, 1, 1, 1, None)
+        capi.selinv_backward(S.h, 1, 1, 1, 1, None, 1, 1, None)
     assert ei.value.status == 6
 
 
-def test_adjoint_items_cover_every_node_once_per_sweep():
-    """Host plan of the reverse sweep: R1 visits depths deepest first, R3 root
-    first; every node gets its diagonal-block items once in each sweep."""
+@pytest.mark.parametrize("name,scale,relax,dense", [("C2", 10, 0.05, 0), ("C2", 12, 0.0, 65), ("C4s", None, 0.0, 0),
+                                                   ("C4", None, 0.05, 0)])
+def test_adjoint_items_cover_every_node_once_per_sweep(name, scale, relax, dense):
+    """Host plan of the reverse sweep (selinv_items(which=1), launch order):
+    every node is visited exactly once in R1 and once in R3, either as the
+    whole-node small kernel or as a full set of tile items (T, Z, L, F, D0
+    over its s x s / c x s blocks, SC over the lower block pairs of c x c, G
+    iff it has a dense X_{C,C} buffer; M, LB, N, DF, SG likewise in R3); R1
+    visits a node only after all of its children are complete and R3 only
+    after its parent is complete."""
     from paper_1604_02528_amd import capi
 
-    w = workload("C2", 10)
-    S = _ctx(w, relax=0.05)
-    it = capi.selinv_items(S.h)  # forward items, for the node count
+    w = workload(name, scale)
+    S = _ctx(w, relax=relax, dense_min_c=dense)
+    seq = capi.selinv_items(S.h, 1)
     sym = S.symbolic()
     ns = sym["nsuper"]
-    assert it.shape[1] == 4 and it[:, 0].max() == ns - 1
+    s_all = np.diff(sym["xsuper"]).astype(int)
+    c_all = np.diff(sym["rowptr"]).astype(int)
+    sparent = sym["sparent"]
+    R1 = {0: "T", 1: "G", 2: "Z", 3: "L", 4: "SC", 5: "F", 6: "D0"}
+    R3 = {7: "SG", 8: "M", 9: "LB", 10: "N", 11: "DF"}
+    # split the sequence into the two sweeps: R1 types / tiny R1 first, then R3
+    is_r1 = np.isin(seq[:, 1], list(R1) + [12])
+    n1 = int(is_r1.sum())
+    assert is_r1[:n1].all() and not is_r1[n1:].any()
+    for sweep, types, tiny in ((seq[:n1], R1, 12), (seq[n1:], R3, 13)):
+        first, last = np.full(ns, -1), np.full(ns, -1)
+        for pos, (K, t, a, b) in enumerate(sweep):
+            if first[K] < 0:
+                first[K] = pos
+            last[K] = pos
+        assert (first >= 0).all(), "a node is missing from a sweep"
+        for K in range(ns):
+            rows = sweep[first[K]:last[K] + 1]
+            rows = rows[rows[:, 0] == K]
+            s, c = int(s_all[K]), int(c_all[K])
+            nb, nr = -(-s // 64), -(-c // 64)
+            got = sorted(map(tuple, rows[:, 1:].tolist()))
+            if (rows[:, 1] == tiny).any():
+                assert got == [(tiny, 0, 0)]
+                continue
+            want = []
+            sq = [(a, b) for a in range(nb) for b in range(nb)]
+            tiles = [(a, b) for b in range(nb) for a in range(nr)]
+            lower_c = [(a, b) for a in range(nr) for b in range(a + 1)]
+            lower_s = [(a, b) for a in range(nb) for b in range(a + 1)]
+            dense_buf = sum(1 for r in rows if r[1] in (1, 7)) > 0
+            if types is R1:
+                want += [(0,) + p for p in sq] + [(5,) + p for p in sq] + [(6,) + p for p in sq]
+                want += [(2,) + p for p in tiles] + [(3,) + p for p in tiles] + [(4,) + p for p in lower_c]
+                if dense_buf:
+                    want += [(1,) + p for p in lower_c]
+            else:
+                want += [(8,) + p for p in tiles] + [(9,) + p for p in tiles] + [(10,) + p for p in tiles]
+                want += [(11,) + p for p in lower_s]
+                if dense_buf:
+                    want += [(7,) + p for p in lower_c]
+            assert got == sorted(want), (K, s, c)
+        # order: R1 after every child is complete, R3 after the parent is complete
+        for K in range(ns):
+            P = int(sparent[K])
+            if P < 0:
+                continue
+            if types is R1:
+                assert last[K] < first[P]
+            else:
+                assert last[P] < first[K]
+
+
+def test_adjoint_items_which_is_checked():
+    from paper_1604_02528_amd import capi
+
+    S = _ctx(workload("C1"))
+    with pytest.raises(capi.SelinvError) as ei:
+        capi.selinv_items(S.h, 2)
+    assert ei.value.status == 1
+
+
+def _drop_entry(colptr, rowind, vals, j, k):
+    """The pattern without entry k of column j."""
+    p = colptr[j] + k
+    cp = colptr.copy()
+    cp[j + 1:] -= 1
+    return cp, np.delete(rowind, p), np.delete(vals, p, axis=1)
+
+
+def test_pattern_errors_report_the_column():
+    """EPATTERN (status 2) with the offending column in error_info(0): a
+    duplicate row, a row index out of range, a missing diagonal, an entry
+    above the diagonal, a colptr that is not monotone."""
+    from paper_1604_02528_amd import SelInv
+    from paper_1604_02528_amd.capi import SelinvError
+
+    w = workload("C1")
+    n = w.n
+    j = 17
+    cases = {}
+    r = w.rowind.copy()
+    r[w.colptr[j] + 2] = r[w.colptr[j] + 1]  # duplicate
+    cases["duplicate"] = (w.colptr, r, j)
+    r = w.rowind.copy()
+    r[w.colptr[n - 40 + 1] - 1] = n  # last entry of a column past the matrix
+    cases["out_of_range"] = (w.colptr, r, n - 40)
+    cp, r, _ = _drop_entry(w.colptr, w.rowind, w.values, j, 0)  # the diagonal
+    cases["missing_diagonal"] = (cp, r, j)
+    r = w.rowind.copy()
+    r[w.colptr[j]] = j - 1  # an upper-triangle entry in front of the diagonal
+    cases["upper_entry"] = (w.colptr, r, j)
+    cp = w.colptr.copy()
+    cp[j + 1] = cp[j]  # empty column
+    cases["empty_column"] = (cp, w.rowind, j)
+    for what, (cp, r, col) in cases.items():
+        with pytest.raises(SelinvError) as ei:
+            SelInv(n, cp, r, w.perm, device="cpu")
+        assert ei.value.status == 2 and ei.value.info[0] == col, what
+
+
+def test_absurd_batch_is_enomem_and_unknown_dtype_unsupported():
+    """ENOMEM (4) before anything of the batch's size is allocated: the item
+    ids of the whole batch must fit in int32.  EUNSUPPORTED (7) for a dtype
+    the library does not have."""
+    from paper_1604_02528_amd import capi
+
+    w = workload("C1")
+    o = capi.selinv_default_opts()
+    o.batch = 1 << 30
+    with pytest.raises(capi.SelinvError) as ei:
+        capi.selinv_analyze(w.n, w.colptr, w.rowind, w.perm, o)
+    assert ei.value.status == 4
+    o = capi.selinv_default_opts()
+    o.dtype = 5
+    with pytest.raises(capi.SelinvError) as ei:
+        capi.selinv_analyze(w.n, w.colptr, w.rowind, w.perm, o)
+    assert ei.value.status == 7
+
+
+def test_default_options_are_the_measured_fastest():
+    from paper_1604_02528_amd import capi
+
+    o = capi.selinv_default_opts()
+    assert o.sched == capi.SCHED_LEVELS and o.relax == 0.05 and o.max_super == 256
 
 
 @pytest.mark.parametrize("name,scale", [("C2", None), ("C3", 14), ("C4", None)])

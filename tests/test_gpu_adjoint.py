@@ -37,14 +37,16 @@ def gpu_abar(w, relax, W_panels, sym, dense=0, split=0):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("split", [0, 64], ids=["split_default", "split_64"])
+@pytest.mark.parametrize("relax", [0.0, 0.05], ids=["relax0", "relax005"])
 @pytest.mark.parametrize("name,scale,dense", [("C4s", None, 0), ("C1", None, 0), ("C2", 8, 0), ("C2", 12, 0),
                                               ("C2", 12, 65)], ids=["C4s", "C1", "C2_8", "C2_12", "C2_12_dense"])
-def test_backward_matches_dense_gradient(name, scale, dense):
+def test_backward_matches_dense_gradient(name, scale, dense, relax, split):
     w = workload(name, scale, None)
-    print(f"adjoint case {name} scale={scale} dense={dense}", flush=True)
-    sym = oracle_sym(name, scale, None, 0.0)
+    print(f"adjoint case {name} scale={scale} dense={dense} relax={relax} split={split}", flush=True)
+    sym = oracle_sym(name, scale, None, relax)
     W = random_w(sym, 11)
-    got = gpu_abar(w, 0.0, W, sym, dense=dense)
+    got = gpu_abar(w, relax, W, sym, dense=dense, split=split)
     ref = adjoint.dense_abar(sym, w.values[0], W, w.colptr, w.rowind)
     err = maxrel(got, ref)
     print(f"  max-norm rel err {err:.3e}", flush=True)
@@ -93,3 +95,116 @@ def test_autograd_function_c4s_loss():
     err = maxrel(got, ref)
     print(f"autograd C4s: max-norm rel err {err:.3e}", flush=True)
     assert err <= TOL
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("relax", [0.0, 0.05])
+def test_c4s_theta_gradient_vs_finite_differences(relax):
+    """The 30 x 30 GMRF of C4 on the GPU: SelInvFunction gives dloss/dQ for
+    loss = sum_i c_i (Q^{-1})_ii + log det Q, chained by torch to kappa and to
+    every edge log-weight w_e (Q is built from theta with torch ops, so
+    autograd does the chain rule); compared with the dense gradient and with
+    central differences of the loss (exact rank-one updates of a dense
+    inverse for each w_e, the oracle's forward path for kappa)."""
+    from paper_1604_02528_amd import SelInv, SelInvFunction
+    from workloads import gmrf_2d
+
+    w = workload("C4s", None, None)
+    m = w.meta["grid"][0]
+    kappa0, wlog0, cvec = w.meta["kappa"], np.asarray(w.meta["w"]), np.asarray(w.meta["c"])
+    print(f"theta gradient C4s relax={relax}", flush=True)
+    colptr, rowind, vals0, edges = gmrf_2d(m, m, kappa0, wlog0)
+    n, nnz = m * m, len(rowind)
+    cols = np.repeat(np.arange(n), np.diff(colptr))
+    pos = {(int(rowind[p]), int(cols[p])): p for p in range(nnz)}
+    a, b = edges[:, 0], edges[:, 1]
+    ip = torch.tensor([pos[(max(x, y), min(x, y))] for x, y in zip(a, b)], device="cuda")
+    diag = torch.tensor(colptr[:-1], device="cuda")
+    kappa = torch.tensor(kappa0, dtype=torch.float64, device="cuda", requires_grad=True)
+    wl = torch.tensor(wlog0, dtype=torch.float64, device="cuda", requires_grad=True)
+    ew = torch.exp(wl)
+    vals = torch.zeros(nnz, dtype=torch.float64, device="cuda")
+    vals = vals.index_add(0, ip, -ew)
+    vals = vals.index_add(0, diag[torch.from_numpy(a).cuda()], ew).index_add(0, diag[torch.from_numpy(b).cuda()], ew)
+    vals = vals.index_add(0, diag, (kappa * kappa).expand(n))
+    assert np.allclose(vals.detach().cpu().numpy(), vals0[0])
+    S = SelInv(n, colptr, rowind, w.perm, batch=1, cap=w.cap, relax=relax)
+    x, logdet = SelInvFunction.apply(vals[None, :], S)
+    c = torch.from_numpy(cvec).cuda()
+    loss = (c * x[0, diag]).sum() + logdet.sum()
+    loss.backward()
+    g_kappa, g_w = float(kappa.grad), wl.grad.cpu().numpy()
+    Q = np.zeros((n, n))
+    Q[rowind, cols] = vals0[0]
+    Q[cols, rowind] = vals0[0]
+    X = np.linalg.inv(Q)
+    G = -(X * cvec[None, :]) @ X + X
+    ref_k = 2 * kappa0 * np.trace(G)
+    ref_w = np.exp(wlog0) * (G[a, a] + G[b, b] - 2 * G[a, b])
+    assert abs(g_kappa - ref_k) <= 1e-9 * abs(ref_k)
+    assert np.max(np.abs(g_w - ref_w)) <= 1e-9 * np.max(np.abs(ref_w))
+    h = 1e-4
+    XU = X[:, a] - X[:, b]
+    q = XU[a, np.arange(len(a))] - XU[b, np.arange(len(a))]
+    cq = (cvec[:, None] * XU * XU).sum(axis=0)
+    we = np.exp(wlog0)
+    dp, dm = np.exp(wlog0 + h) - we, np.exp(wlog0 - h) - we
+    fd_w = ((-dp / (1 + dp * q) + dm / (1 + dm * q)) * cq + np.log1p(dp * q) - np.log1p(dm * q)) / (2 * h)
+    assert np.max(np.abs(fd_w - g_w) / np.maximum(1.0, np.abs(g_w))) < 1e-8
+    from tests.test_oracle_adjoint import loss_theta
+
+    hk = 1e-5
+    fd_k = (loss_theta(m, kappa0 + hk, wlog0, cvec) - loss_theta(m, kappa0 - hk, wlog0, cvec)) / (2 * hk)
+    assert abs(fd_k - g_kappa) / abs(g_kappa) < 1e-7
+    print(f"  dkappa {g_kappa:.12e} (dense {ref_k:.12e}), max |dw - fd| {np.max(np.abs(fd_w - g_w)):.2e}", flush=True)
+
+
+@pytest.mark.gpu
+def test_backward_state_checks():
+    """selinv_backward refuses (ESTATE) a Dt buffer that the last
+    factorization did not write and an X that does not belong to it."""
+    from paper_1604_02528_amd import SelInv, capi
+
+    w = workload("C1", None, None)
+    sym = oracle_sym("C1", None, None, 0.05)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, batch=1, cap=w.cap, relax=0.05)
+
+    def xbar():
+        W = random_w(sym, 5)
+        t = torch.zeros((1, S.panel_elems), dtype=torch.float64)
+        t[0, torch.from_numpy(S.packed_index())] = torch.from_numpy(selinv.flatten(sym, W))
+        return t.cuda()
+
+    S.factor(w.values, want_dtilde=True)
+    S.run()
+    ok = S.backward(xbar())
+    S.sync()
+    S.factor(w.values)  # no Dt this time; the old Dt buffer is stale
+    S.run()
+    with pytest.raises(capi.SelinvError) as ei:
+        S.backward(xbar())
+    assert ei.value.status == 6
+    S.factor(w.values, want_dtilde=True)  # no run after it
+    with pytest.raises(capi.SelinvError) as ei:
+        S.backward(xbar())
+    assert ei.value.status == 6
+    S.run()
+    again = S.backward(xbar())
+    S.sync()
+    assert torch.equal(ok, again) or maxrel(again.cpu().numpy(), ok.cpu().numpy()) < 1e-13
+
+
+@pytest.mark.gpu
+def test_autograd_refuses_a_stale_forward():
+    from paper_1604_02528_amd import SelInv, SelInvFunction
+
+    w = workload("C4s", None, None)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, batch=1, cap=w.cap)
+    v1 = torch.from_numpy(np.ascontiguousarray(w.values)).cuda().requires_grad_(True)
+    v2 = (v1.detach() * 1.01).requires_grad_(True)
+    x1, _ = SelInvFunction.apply(v1, S)
+    x2, _ = SelInvFunction.apply(v2, S)
+    with pytest.raises(RuntimeError, match="factored again"):
+        x1.sum().backward()
+    x2.sum().backward()
+    assert torch.isfinite(v2.grad).all()

@@ -26,15 +26,14 @@ def assert_same_symbolic(lib, sym):
     assert lib["nnzL"] == sym.nnzL()
 
 
+# the last three are the full benchmark sizes (40^3, 30^3 with 32 shifts, 64^3 with 8 shifts)
 SYM_CASES = [("C1", None, None), ("C4s", None, None), ("C2", 16, None), ("C3", 10, 2), ("C5", 8, 1),
-             ("C4", None, None), ("C2", None, None)]
+             ("C4", None, None), ("C2", None, None), ("C3", None, None), ("C5", None, None)]
 
 
 @pytest.mark.parametrize("relax", [0.0, 0.05])
 @pytest.mark.parametrize("name,scale,batch", SYM_CASES)
 def test_symbolic_bit_exact(name, scale, batch, relax):
-    if name == "C2" and scale is None and relax == 0.0:
-        pytest.skip("the exact-partition oracle on 40^3 takes ~30 s; covered by the relaxed case and smaller grids")
     w = workload(name, scale, batch)
     sym = oracle_sym(name, scale, batch, relax)
     assert_same_symbolic(lib_ctx(w, relax).symbolic(), sym)

@@ -43,6 +43,7 @@ def test_three_routes_agree(which, relax):
 
 
 def loss_theta(m, kappa, wlog, cvec):
+    """The C4 loss through the oracle's forward path (factor, Alg. 1, log det)."""
     colptr, rowind, vals, edges = gmrf_2d(m, m, kappa, wlog)
     from workloads import nested_dissection
     perm = nested_dissection((m, m))
@@ -55,14 +56,10 @@ def loss_theta(m, kappa, wlog, cvec):
     return float(np.dot(cvec, xa[diag_pos]) + factor.logdet(sym, P))
 
 
-def test_c4_gradient_vs_finite_differences():
-    """loss = sum_i c_i (Q^{-1})_ii + log det Q; dQ/dkappa = 2 kappa I, dQ/dw_e = e^{w_e} L_e."""
-    m = 12
-    rng = np.random.default_rng(4)
-    nedge = 2 * m * (m - 1)
-    wlog = rng.normal(0.0, 0.3, size=nedge)
-    cvec = rng.uniform(0.0, 1.0, size=m * m)
-    kappa = 0.5
+def oracle_theta_gradient(m, kappa, wlog, cvec):
+    """dloss/dkappa and dloss/dw_e from the oracle's reverse sweep plus the
+    log det term (d log det Q / dQ = Q^{-1}), chained through dQ/dkappa = 2
+    kappa I and dQ/dw_e = e^{w_e} (e_a - e_b)(e_a - e_b)^T."""
     colptr, rowind, vals, edges = gmrf_2d(m, m, kappa, wlog)
     from workloads import nested_dissection
     perm = nested_dissection((m, m))
@@ -73,27 +70,77 @@ def test_c4_gradient_vs_finite_differences():
     W = adjoint.w_diag(sym, cvec)
     S = adjoint.reverse_mode(sym, lh, dt, factor.dtilde(sym, P), X, W)
     gA = adjoint.abar_from_sbar(sym, S, colptr, rowind)
-    # log det Q contributes X (stored convention: x2 off the diagonal)
     xa = selinv.on_pattern_of_A(sym, X, colptr, rowind)
     cols = np.repeat(np.arange(m * m), np.diff(colptr))
     gA = gA + np.where(rowind == cols, xa, 2.0 * xa)
-    # chain rule to theta (stored values: diagonal entries and one entry per edge)
     diag_pos = colptr[:-1]
     g_kappa = 2.0 * kappa * np.sum(gA[diag_pos])
-    pos = {}
-    for p in range(rowind.shape[0]):
-        pos[(int(rowind[p]), int(cols[p]))] = p
-    g_w = np.empty(nedge)
-    for e, (a, b) in enumerate(edges):
-        hi, lo = max(a, b), min(a, b)
-        we = np.exp(wlog[e])
-        g_w[e] = we * (gA[diag_pos[a]] + gA[diag_pos[b]] - gA[pos[(hi, lo)]])
-    h = 1e-5
-    fd_k = (loss_theta(m, kappa + h, wlog, cvec) - loss_theta(m, kappa - h, wlog, cvec)) / (2 * h)
+    pos = {(int(rowind[p]), int(cols[p])): p for p in range(rowind.shape[0])}
+    g_w = np.array([np.exp(wlog[e]) * (gA[diag_pos[a]] + gA[diag_pos[b]] - gA[pos[(max(a, b), min(a, b))]])
+                    for e, (a, b) in enumerate(edges)])
+    return g_kappa, g_w, (colptr, rowind, vals, edges)
+
+
+def test_c4s_gradient_vs_finite_differences_every_parameter():
+    """The 30 x 30 GMRF of C4 (kappa = 0.5, its seeded w_e and c_i):
+    loss = sum_i c_i (Q^{-1})_ii + log det Q, central differences in kappa and
+    in every one of the 1,740 edge log-weights.
+
+    The perturbed losses for w_e come from exact rank-one identities on the
+    dense inverse (numpy), independent of the oracle: Q' = Q + d u u^T with
+    u = e_a - e_b and d = e^{w_e +- h} - e^{w_e} gives
+    diag(Q'^{-1}) = diag(X) - d (X u)^2 / (1 + d q), q = u^T X u
+    (Sherman-Morrison) and log det Q' = log det Q + log(1 + d q) (matrix
+    determinant lemma), so each difference loss(+h) - loss(-h) is formed
+    without cancellation.  kappa and ten random edges also go through the
+    oracle's own forward path."""
+    w = config("C4s")
+    m = w.meta["grid"][0]
+    kappa, wlog, cvec = w.meta["kappa"], np.asarray(w.meta["w"]), np.asarray(w.meta["c"])
+    g_kappa, g_w, (colptr, rowind, vals, edges) = oracle_theta_gradient(m, kappa, wlog, cvec)
+    n = m * m
+    Lq = np.zeros((n, n))
+    cols = np.repeat(np.arange(n), np.diff(colptr))
+    Lq[rowind, cols] = vals[0]
+    Lq[cols, rowind] = vals[0]
+    X = np.linalg.inv(Lq)
+    h = 1e-4
+    a, b = edges[:, 0], edges[:, 1]
+    XU = X[:, a] - X[:, b]                      # columns X u_e
+    q = XU[a, np.arange(len(a))] - XU[b, np.arange(len(a))]
+    cq = (cvec[:, None] * XU * XU).sum(axis=0)  # sum_i c_i (X u)_i^2
+    we = np.exp(wlog)
+    dp, dm = np.exp(wlog + h) - we, np.exp(wlog - h) - we
+    diff = (-dp / (1 + dp * q) + dm / (1 + dm * q)) * cq + np.log1p(dp * q) - np.log1p(dm * q)
+    fd_w = diff / (2 * h)
+    err_w = np.abs(fd_w - g_w) / np.maximum(1.0, np.abs(g_w))
+    assert np.max(err_w) < 1e-8, (int(np.argmax(err_w)), float(np.max(err_w)))
+    hk = 1e-5
+    fd_k = (loss_theta(m, kappa + hk, wlog, cvec) - loss_theta(m, kappa - hk, wlog, cvec)) / (2 * hk)
     assert abs(fd_k - g_kappa) / abs(g_kappa) < 1e-7
-    for e in rng.choice(nedge, size=12, replace=False):
+    rng = np.random.default_rng(4)
+    for e in rng.choice(len(wlog), size=10, replace=False):
         wp, wm = wlog.copy(), wlog.copy()
-        wp[e] += h
-        wm[e] -= h
-        fd = (loss_theta(m, kappa, wp, cvec) - loss_theta(m, kappa, wm, cvec)) / (2 * h)
+        wp[e] += hk
+        wm[e] -= hk
+        fd = (loss_theta(m, kappa, wp, cvec) - loss_theta(m, kappa, wm, cvec)) / (2 * hk)
         assert abs(fd - g_w[e]) <= 1e-6 * max(1.0, abs(g_w[e]))
+
+
+def test_c4s_gradient_vs_dense_gradient():
+    """The same gradient from the dense definition G = -X diag(c) X + X."""
+    w = config("C4s")
+    m = w.meta["grid"][0]
+    kappa, wlog, cvec = w.meta["kappa"], np.asarray(w.meta["w"]), np.asarray(w.meta["c"])
+    g_kappa, g_w, (colptr, rowind, vals, edges) = oracle_theta_gradient(m, kappa, wlog, cvec)
+    n = m * m
+    Q = np.zeros((n, n))
+    cols = np.repeat(np.arange(n), np.diff(colptr))
+    Q[rowind, cols] = vals[0]
+    Q[cols, rowind] = vals[0]
+    X = np.linalg.inv(Q)
+    G = -(X * cvec[None, :]) @ X + X
+    assert abs(2 * kappa * np.trace(G) - g_kappa) <= 1e-10 * abs(g_kappa)
+    a, b = edges[:, 0], edges[:, 1]
+    ref = np.exp(wlog) * (G[a, a] + G[b, b] - 2 * G[a, b])
+    assert np.max(np.abs(ref - g_w)) <= 1e-10 * np.max(np.abs(ref))

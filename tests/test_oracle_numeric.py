@@ -170,3 +170,70 @@ def test_zero_pivot_is_reported():
     with pytest.raises(factor.ZeroPivot) as ei:
         factor.factor(sym, vals)
     assert ei.value.column == 0
+
+
+# --------------------------------------------------------------------------
+# log det B from the pivots (det B = prod_j D_jj for B = L D L^T, Section 2.3).
+# Branch convention: the sum of the principal logarithms of the pivots.  Pinned
+# against numpy's slogdet / det of the dense matrix (LU with partial pivoting,
+# an independent route), and against the inertia from the eigenvalues.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,scale", [("C1", None), ("C4s", None), ("C2", 8)])
+def test_logdet_real_spd_vs_slogdet(name, scale):
+    w = config(name, scale=scale)
+    sym, P, lh, dt = run_oracle(w)
+    ld = factor.logdet(sym, P)
+    sign, la = np.linalg.slogdet(selinv.permuted_dense(sym, w.values[0]))
+    assert isinstance(ld, float) and sign == 1.0
+    assert abs(ld - la) <= 1e-12 * max(1.0, abs(la))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_logdet_real_indefinite_vs_slogdet_and_inertia(seed):
+    """Mixed-sign strictly diagonally dominant matrices: no zero pivot without
+    pivoting; the number of negative pivots is the number of negative
+    eigenvalues (Sylvester's law of inertia)."""
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.integers(30, 150))
+    colptr, rowind, vals = random_pattern(n, 0.08, rng)
+    v = vals[0].copy()
+    flip = rng.random(n) < 0.4
+    v[colptr[:-1][flip]] *= -1.0  # diagonal opens every column
+    perm = rng.permutation(n).astype(np.int64)
+    sym = symbolic.analyze(n, colptr, rowind, perm, cap=16)
+    P = factor.factor(sym, v)
+    ld = factor.logdet(sym, P)
+    Bd = selinv.permuted_dense(sym, v)
+    sign, la = np.linalg.slogdet(Bd)
+    nneg = int(np.sum(np.linalg.eigvalsh(Bd) < 0))
+    assert nneg > 0 and isinstance(ld, complex)
+    assert abs(ld.real - la) <= 1e-12 * max(1.0, abs(la))
+    assert abs(ld.imag - np.pi * nneg) <= 1e-12 * np.pi * n
+    assert abs(np.exp(1j * ld.imag) - sign) < 1e-12
+
+
+@pytest.mark.parametrize("name,scale,batch", [("C3", 6, 3), ("C5", 5, 2)])
+def test_logdet_complex_vs_det(name, scale, batch):
+    w = config(name, scale=scale, batch=batch)
+    for l in range(w.batch):
+        sym, P, lh, dt = run_oracle(w, l)
+        ld = factor.logdet(sym, P)
+        Bd = selinv.permuted_dense(sym, w.values[l])
+        sign, la = np.linalg.slogdet(Bd)
+        assert abs(ld.real - la) <= 1e-12 * max(1.0, abs(la))
+        assert abs(np.exp(1j * ld.imag) - sign) < 1e-11
+        if name == "C3":  # Im(pivot) < 0: every argument lies in (-pi, 0)
+            assert -np.pi * w.n < ld.imag < 0.0
+
+
+def test_logdet_complex_small_vs_det_value():
+    """exp(log det) against numpy's det itself where it does not overflow."""
+    rng = np.random.default_rng(77)
+    for n in (12, 40, 90):
+        colptr, rowind, vals = random_pattern(n, 0.1, rng, complex_values=True)
+        v = vals[0] / np.abs(vals[0][colptr[:-1]]).mean()  # |det| of order one
+        sym = symbolic.analyze(n, colptr, rowind, rng.permutation(n).astype(np.int64), cap=8)
+        ld = factor.logdet(sym, factor.factor(sym, v))
+        d = np.linalg.det(selinv.permuted_dense(sym, v))
+        assert abs(np.exp(ld) - d) <= 1e-11 * abs(d)
