@@ -1,15 +1,17 @@
 """Benchmark: selected inversion on one MI355X (FP64 GFLOP/s and % of MFMA peak).
 
-Workload (default): the 3-D 7-point weighted Laplacian on a 40^3 grid
-(N = 64,000; weights U[0.5, 1.5], shift 0.05, seed 2), geometric nested
-dissection, FP64, supernode cap 256 with chain relaxation 0.05.
+Workload (default, the largest 3-D case): a 27-point complex-symmetric
+stencil on a 64^3 grid (N = 262,144), 8 shifted matrices A - z_l I in one
+batched run, complex128, geometric nested dissection, supernode cap 256 with
+chain relaxation 0.05.  --workload C2 / C3 selects the 40^3 FP64 Laplacian or
+the 32-shift 30^3 batch instead.
 
 A step is one pass of the hot path on inputs resident in HBM: the
 normalization of the LDL^T panels (Alg. 1 steps 1-2) followed by the
 root-to-leaves selected inversion (steps 3-4 with the diagonal
-symmetrization).  The LDL^T factors are produced once, before timing, by the
-library's host factorization.  GFLOP/s counts sum_K 2 c^2 s + 2 c s^2 over
-the maximal (unrelaxed) supernodes, i.e. the algorithmic work of the method.
+symmetrization).  The LDL^T factors are produced once, before timing.
+GFLOP/s counts sum_K 2 c^2 s + 2 c s^2 (x4 for complex) over the maximal
+(unrelaxed) supernodes, i.e. the algorithmic work of the method.
 
 Output: one JSON line (plus human-readable lines on stderr).
 """
@@ -39,23 +41,26 @@ WORKLOADS = {
           "nested dissection, supernode cap 256",
 }
 
+TRAFFIC_RECORDS = {
+    "C2": os.path.join(ROOT, "profiles", "selinv_C2_levels_hbm_traffic.json"),
+    "C5": os.path.join(ROOT, "profiles", "selinv_C5_levels_hbm_traffic.json"),
+}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "selinv_C2_levels_hbm_traffic.json")
-
-
 def measured_traffic(workload, sched):
     """HBM bytes per traversal from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE record (scaled by a 1 GiB copy), or None when it does not match
-    this run or the kernel sources have changed since it was taken."""
+    WRITE_SIZE record of this workload (scaled by a 1 GiB copy), or None when
+    there is none or the kernel sources have changed since it was taken."""
     import hashlib
 
-    if workload != "C2" or sched != "levels" or not os.path.exists(TRAFFIC_RECORD):
+    rec_path = TRAFFIC_RECORDS.get(workload)
+    if sched != "levels" or rec_path is None or not os.path.exists(rec_path):
         return None
-    rec = json.load(open(TRAFFIC_RECORD))
+    rec = json.load(open(rec_path))
     h = hashlib.sha256()
     for f in rec["source_files"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
@@ -187,24 +192,6 @@ def summary(w, g, steps, name):
     }
 
 
-def largest_3d_leg(relax, sched):
-    """C5: 8 complex128 shifts of a 64^3 27-point stencil in one batched run."""
-    import torch
-
-    from workloads import config
-
-    w = config("C5")
-    g = gpu_leg(w, relax, 2, 1, sched, replicate=True)
-    out = summary(w, g, 2, "C5")
-    out["note"] = ("LDL^T panels of shift 0 copied to all 8 batch slots (host factorization outside the timed "
-                   "region); the traversal does the full 8-shift work")
-    g["S"].close()
-    del g
-    torch.cuda.empty_cache()
-    log(f"C5: {out['gflops']} GFLOP/s ({out['pct_fp64_mfma_peak']}% of FP64 MFMA peak), step {out['ms_per_step']} ms")
-    return out
-
-
 def batched_leg(relax, sched):
     """C3: 32 complex128 shifts in one launch vs 32 single-shift runs."""
     import torch
@@ -233,15 +220,38 @@ def batched_leg(relax, sched):
     return out
 
 
-def cpu_leg(w, relax, reps=3):
-    """The oracle's Alg. 1 (selected-inversion phase) on the host cores."""
-    from oracle import factor, selinv, symbolic
+def host_cpu():
+    """CPU model and the number of host cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except Exception:
+        avail = os.cpu_count()
+    return {"model": model, "cores_available": avail, "logical_cpus": os.cpu_count()}
 
+
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()]))
     except Exception:
-        threads = os.cpu_count()
+        return int(os.cpu_count())
+
+
+def cpu_leg(w, relax, reps=3):
+    """The oracle's Alg. 1 (selected-inversion phase) on the whole matrix 0 of
+    the workload, on the host cores (numpy BLAS), median of `reps`."""
+    from oracle import factor, selinv, symbolic
+
     sym = symbolic.analyze(w.n, w.colptr, w.rowind, w.perm, cap=w.cap, relax=relax)
     P = factor.factor(sym, w.values[0])
     lh, dt = factor.normalize(sym, P)
@@ -251,7 +261,59 @@ def cpu_leg(w, relax, reps=3):
         t0 = time.perf_counter()
         X = selinv.alg1(sym, lh, dt)
         times.append(time.perf_counter() - t0)
-    return {"t": float(np.median(times)), "X": selinv.flatten(sym, X), "threads": int(threads)}
+    return {"t": float(np.median(times)), "X": selinv.flatten(sym, X), "threads": blas_threads(),
+            "flops": sym.flops(w.is_complex)}
+
+
+_SAMPLE_SYM = {}
+
+
+def cpu_leg_sample(w, relax, target_flops, one_thread=False):
+    """The oracle's Alg. 1 on a bounded sample of the workload: the first M
+    supernodes of its loop (root first; they need no other supernode), M the
+    smallest count whose work reaches target_flops.  Alg. 1's time depends on
+    the shapes only, so the normalized factors of the sample are seeded random
+    values of the right shapes (the oracle's factorization of the whole
+    matrix would take far longer than the sample).  Returns the rate in
+    GFLOP/s of the sample's algorithmic flops."""
+    from oracle import selinv, symbolic
+
+    key = (w.name, w.n, relax)
+    if key not in _SAMPLE_SYM:
+        _SAMPLE_SYM[key] = symbolic.analyze(w.n, w.colptr, w.rowind, w.perm, cap=w.cap, relax=relax)
+    sym = _SAMPLE_SYM[key]
+    mul = 4.0 if w.is_complex else 1.0
+    rng = np.random.default_rng(0)
+    lh, dt = [None] * sym.nsuper, [None] * sym.nsuper
+    tot, M = 0.0, 0
+    for K in reversed(range(sym.nsuper)):
+        s_, c_ = sym.width(K), len(sym.rows[K])
+        shape_l, shape_d = (c_, s_), (s_, s_)
+        if w.is_complex:
+            lh[K] = rng.standard_normal(shape_l) + 1j * rng.standard_normal(shape_l)
+            dt[K] = rng.standard_normal(shape_d) + 1j * rng.standard_normal(shape_d)
+        else:
+            lh[K] = rng.standard_normal(shape_l)
+            dt[K] = rng.standard_normal(shape_d)
+        tot += mul * (2.0 * c_ * c_ * s_ + 2.0 * c_ * s_ * s_)
+        M += 1
+        if tot >= target_flops:
+            break
+    if one_thread:
+        from threadpoolctl import threadpool_limits
+
+        with threadpool_limits(limits=1):
+            threads = blas_threads()
+            t0 = time.perf_counter()
+            selinv.alg1(sym, lh, dt, stop_after=M)
+            t = time.perf_counter() - t0
+    else:
+        threads = blas_threads()
+        t0 = time.perf_counter()
+        selinv.alg1(sym, lh, dt, stop_after=M)
+        t = time.perf_counter() - t0
+    return {"t": t, "flops": tot, "nodes": M, "nsuper": sym.nsuper, "threads": threads,
+            "frac_of_workload": tot / (mul * sym.flops())}
 
 
 def adjoint_leg(relax):
@@ -301,19 +363,37 @@ def adjoint_leg(relax):
     return out
 
 
+def c2_leg(relax, sched, steps):
+    """C2 (40^3 FP64 Laplacian) as an extra line: timing, and the GPU result
+    against the oracle's Alg. 1 on the whole matrix."""
+    from workloads import config
+
+    w = config("C2")
+    g = gpu_leg(w, relax, steps, 2, sched, want_x=True)
+    out = summary(w, g, steps, "C2")
+    c = cpu_leg(w, relax)
+    out["max_rel_err_vs_oracle"] = float(np.max(np.abs(g["X"][0] - c["X"])) / np.max(np.abs(c["X"])))
+    out["cpu_oracle_gflops"] = round(c["flops"] / c["t"] / 1e9, 3)
+    out["cpu_oracle_threads"] = c["threads"]
+    out["traffic"] = measured_traffic("C2", sched)
+    g["S"].close()
+    log(f"C2: {out['gflops']} GFLOP/s, step {out['ms_per_step']} ms, vs oracle {out['max_rel_err_vs_oracle']:.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--relax", type=float, default=0.05)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline legs")
     ap.add_argument("--sched", default="levels", choices=["persistent", "levels"])
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C5"])
+    ap.add_argument("--workload", default="C5", choices=["C2", "C3", "C5"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three 1 GiB device-to-device copies (reference for HBM byte counters)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the C3 batched-vs-sequential, C4 adjoint-vs-forward and C5 (largest 3-D case) legs")
+                    help="skip the C2 line, the C3 batched-vs-sequential and the C4 adjoint-vs-forward legs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (each GPU would run its own "
@@ -327,9 +407,8 @@ def main():
     w = config(args.workload)
     replicate = args.workload == "C5"
     log(f"workload {args.workload}: N={w.n} nnz(A)={w.nnz} batch={w.batch} relax={args.relax}")
-    if args.workload != "C2":
-        args.no_cpu = True
-    g = gpu_leg(w, args.relax, args.steps, args.warmup, args.sched, replicate, want_x=not args.no_cpu)
+    g = gpu_leg(w, args.relax, args.steps, args.warmup, args.sched, replicate,
+                want_x=args.workload == "C2" and not args.no_cpu)
     sm = summary(w, g, args.steps, args.workload)
     flops = g["sym"]["flops_exact"] * w.batch
     ms_step = g["wall"] / args.steps * 1e3
@@ -337,28 +416,53 @@ def main():
     t_run = float(np.mean(g["t_run"]))
     t_norm = float(np.mean(g["t_norm"]))
     achieved = flops / t_run / 1e12
-    log(f"analyze {g['t_analyze']:.2f}s host factor {g['t_factor']:.2f}s | step {ms_step:.3f} ms "
+    log(f"analyze {g['t_analyze']:.2f}s factor {g['t_factor']:.2f}s | step {ms_step:.3f} ms "
         f"(normalize {t_norm*1e3:.3f} ms, selinv {t_run*1e3:.3f} ms) | {value:.1f} GFLOP/s")
+    X0 = g["X"][0] if g["X"] is not None else None
+    g["S"].close()
+    del g
+    torch.cuda.empty_cache()
     cpu = None
     err = None
     if not args.no_cpu:
-        c = cpu_leg(w, args.relax)
-        err = float(np.max(np.abs(g["X"][0] - c["X"])) / np.max(np.abs(c["X"])))
-        cpu = {"value": flops / c["t"] / 1e9, "unit": "GFLOP/s", "cores": c["threads"], "kind": "oracle",
-               "sample": "whole workload: the oracle's Alg. 1 (selected-inversion phase, numpy BLAS) on C2 "
-                         "with the same supernode partition, median of 3, factorization excluded",
-               "seconds": c["t"]}
-        log(f"oracle Alg. 1: {c['t']:.2f} s on {c['threads']} threads; GPU vs oracle max-norm rel err {err:.2e}")
-    g["S"].close()
-    del g
+        hc = host_cpu()
+        if args.workload == "C2":
+            c = cpu_leg(w, args.relax)
+            err = float(np.max(np.abs(X0 - c["X"])) / np.max(np.abs(c["X"])))
+            rate, secs, thr = c["flops"] / c["t"] / 1e9, c["t"], c["threads"]
+            sample = ("whole workload: the oracle's Alg. 1 (selected-inversion phase, numpy BLAS) on the C2 "
+                      "matrix with the same supernode partition, median of 3, factorization excluded")
+            one = cpu_leg_sample(w, args.relax, 5e9, one_thread=True)
+        else:
+            c = cpu_leg_sample(w, args.relax, 8e11 if args.workload == "C5" else 1e11)
+            rate, secs, thr = c["flops"] / c["t"] / 1e9, c["t"], c["threads"]
+            sample = (f"the oracle's Alg. 1 (numpy BLAS) on the first {c['nodes']} of {c['nsuper']} supernodes of "
+                      f"its root-first loop for one matrix ({100 * c['frac_of_workload']:.1f}% of one matrix's "
+                      f"flops, {c['flops']:.3e}), with seeded random normalized factors of the same shapes (the "
+                      f"time depends on the shapes only); GFLOP/s of that sample")
+            one = cpu_leg_sample(w, args.relax, 2e11 if args.workload == "C5" else 2e10, one_thread=True)
+        cpu = {"value": round(rate, 3), "unit": "GFLOP/s", "cores": thr, "kind": "oracle", "sample": sample,
+               "seconds": round(secs, 3), "host_cpu": hc["model"], "host_cores_available": hc["cores_available"],
+               "one_thread": {"value": round(one["flops"] / one["t"] / 1e9, 3), "cores": one["threads"],
+                              "seconds": round(one["t"], 3),
+                              "sample": f"first {one['nodes']} supernodes of the root-first loop "
+                                        f"({one['flops']:.3e} flops), threadpoolctl limit 1"}}
+        log(f"oracle Alg. 1: {rate:.2f} GFLOP/s on {thr} threads ({secs:.2f} s); one thread "
+            f"{cpu['one_thread']['value']} GFLOP/s; host {hc['model']} x{hc['cores_available']}")
+        if err is not None:
+            log(f"GPU vs oracle max-norm rel err {err:.2e}")
     extras = {}
-    if args.workload == "C2" and not args.no_extras:
-        import torch
-
-        torch.cuda.empty_cache()
+    if not args.no_extras:
+        if args.workload != "C2":
+            extras["c2"] = c2_leg(args.relax, args.sched, 10)
+            torch.cuda.empty_cache()
         extras["batched"] = batched_leg(args.relax, args.sched)
+        torch.cuda.empty_cache()
         extras["adjoint"] = adjoint_leg(args.relax)
-        extras["largest_3d"] = largest_3d_leg(args.relax, args.sched)
+    wl = WORKLOADS[args.workload]
+    if replicate:
+        wl += ("; the LDL^T panels of shift 0 are copied to all 8 batch slots (host factorization outside the "
+               "timed region); the traversal does the full 8-shift work, whose cost does not depend on the values")
     out = {
         "metric": "selinv FP64 GFLOP/s (% MFMA peak) + s/solve; batched 32-shift & adjoint vs plain",
         "value": round(value, 2),
@@ -373,9 +477,7 @@ def main():
         "dtype": "c128" if w.is_complex else "f64",
         "data": "synthetic",
         "config": {
-            "workload": WORKLOADS[args.workload] + (
-                "; LDL^T panels of shift 0 copied to all 8 batch slots (host factorization outside the "
-                "timed region)" if replicate else ""),
+            "workload": wl, "batch": w.batch,
             "supernode_cap": w.cap, "relax": args.relax, "schedule": args.sched,
             "nsuper": sm["nsuper"], "depth": sm["depth"],
             "flops_per_solve": sm["flops_per_solve"],
@@ -392,18 +494,16 @@ def main():
                                 "single-wavefront small nodes of each level)"
                                 if args.sched == "levels" else "k_persistent, one launch"),
                      "selinv_run_ms": round(t_run * 1e3, 4),
-                     "note": "achieved = algorithmic flops of the traversal / HIP-event time of selinv_run "
-                             "(all of its launches) on the launch stream"},
+                     "note": "achieved = algorithmic flops of one traversal (all matrices of the batch) / "
+                             "HIP-event time of selinv_run (all of its launches) on the launch stream"},
         "normalize_ms": round(t_norm * 1e3, 4),
         "max_rel_err_vs_oracle": err,
-        "t_factor_host_s": round(sm["t_factor_host_s"], 2),
+        "t_factor_s": round(sm["t_factor_host_s"], 2),
         "cpu_baseline": cpu,
         **extras,
     }
     print(json.dumps(out), flush=True)
     if args.calibrate_copy:
-        import torch
-
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
         for _ in range(3):

@@ -43,15 +43,21 @@ def gather_cc(sym, X, K):
     return lower + np.tril(G, -1).T
 
 
-def alg1(sym, lhat, dtinv):
+def alg1(sym, lhat, dtinv, stop_after=None):
     """Alg. 1 second loop, K = N..1 (root first), pull form.
 
     A^{-1}_{C,K} = -A^{-1}_{C,C} Lhat_{C,K}                   (step 3)
     A^{-1}_{K,K} = Dt_K^{-1} - Lhat_{C,K}^T A^{-1}_{C,K}        (step 4, Uhat = Lhat^T)
     A^{-1}_{K,K} <- (A^{-1}_{K,K} + A^{-T}_{K,K}) / 2            (symmetrization)
+
+    ``stop_after``: process only that many supernodes of the loop (the
+    highest-numbered ones, which need no others; for timing a sample).
     """
     X = [None] * sym.nsuper
-    for K in reversed(range(sym.nsuper)):
+    order = list(reversed(range(sym.nsuper)))
+    if stop_after is not None:
+        order = order[:stop_after]
+    for K in order:
         s = sym.width(K)
         c = sym.rows[K].shape[0]
         dtype = dtinv[K].dtype
