@@ -221,6 +221,29 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
                                    void *dtilde_dev, void *stream);
 
 /*
+ * selinv_normalize_run_noalloc -- for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): selinv_normalize followed by selinv_run on `stream`, with
+ * the same arguments, kernels and results, but without a work buffer.  The
+ * work area (plan tables, L_KK^{-1} scratch, partial products, dense X_{C,C}
+ * buffers, counters) is a fixed library-owned device array of 64 MiB on each
+ * GPU the library runs on, created with the library's code object and held
+ * until the process ends.  The caller passes the inputs (ldlt_dev, LDL^T
+ * panels) and the outputs (panels_dev, x_dev, dtilde_dev or NULL) only.
+ *   Limit: plans whose forward work area exceeds 64 MiB return SELINV_ENOMEM
+ *   (error_info(0) = bytes needed, error_info(1) = the limit).
+ *   No hipMalloc, hipFree or other allocating routine is called.  The first
+ *   call of a context on a device (and after another context used the array)
+ *   copies the context's tables into the array and waits for that copy.
+ *   Every call on a GPU shares that GPU's array, which keeps the last call's
+ *   contents: calls that overlap on one GPU (different streams or threads)
+ *   race and must be serialized by the caller.
+ * Errors as selinv_normalize_run, plus SELINV_ENOMEM above.
+ */
+selinv_status selinv_normalize_run_noalloc(selinv_ctx *h, const void *ldlt_dev, void *panels_dev, void *x_dev,
+                                           void *dtilde_dev, void *stream);
+
+/*
  * selinv_extract -- X on A's stored lower pattern, original indexing:
  * out_dev[l][e] = (A^{-1})_{rowind[e], col(e)} of matrix l.  Asynchronous.
  */

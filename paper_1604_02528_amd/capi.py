@@ -23,7 +23,7 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "EPATTERN", 3: "ESINGULAR", 4: "ENOMEM", 5: "
 
 EXPORTED = (
     "selinv_default_opts", "selinv_version", "selinv_analyze", "selinv_symbolic", "selinv_sizes",
-    "selinv_factor", "selinv_normalize", "selinv_factor_host", "selinv_run", "selinv_normalize_run", "selinv_extract",
+    "selinv_factor", "selinv_normalize", "selinv_factor_host", "selinv_run", "selinv_normalize_run", "selinv_normalize_run_noalloc", "selinv_extract",
     "selinv_scatter",
     "selinv_backward",
     "selinv_logdet", "selinv_check_plan", "selinv_trace", "selinv_items", "selinv_sync", "selinv_last_error", "selinv_error_info", "selinv_destroy",
@@ -86,6 +86,7 @@ def load():
         "selinv_factor_host": (C.c_int, [vp, vp, vp]),
         "selinv_run": (C.c_int, [vp, vp, vp, vp, vp]),
         "selinv_normalize_run": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+        "selinv_normalize_run_noalloc": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "selinv_extract": (C.c_int, [vp, vp, vp, vp, vp]),
         "selinv_scatter": (C.c_int, [vp, vp, vp, vp, vp]),
         "selinv_backward": (C.c_int, [vp, vp, vp, vp, vp, vp, vp, vp, vp]),
@@ -181,6 +182,10 @@ def selinv_run(h, panels, x, work, stream):
 
 def selinv_normalize_run(h, ldlt, panels, x, work, dtilde, stream):
     check(h, load().selinv_normalize_run(h, ptr(ldlt), ptr(panels), ptr(x), ptr(work), ptr(dtilde), stream))
+
+
+def selinv_normalize_run_noalloc(h, ldlt, panels, x, dtilde, stream):
+    check(h, load().selinv_normalize_run_noalloc(h, ptr(ldlt), ptr(panels), ptr(x), ptr(dtilde), stream))
 
 
 def selinv_extract(h, x, work, out, stream):

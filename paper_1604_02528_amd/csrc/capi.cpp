@@ -6,8 +6,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <atomic>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <queue>
 #include <string>
@@ -31,6 +33,13 @@ hipError_t launch_scatter(const DevPlan &pl, const DevPlan *dpl, bool cplx_, con
 }  // namespace selinv
 
 using namespace selinv;
+
+// Work area of selinv_normalize_run_noalloc, for callers that cannot allocate
+// device memory: one fixed array per GPU, created with the code object and
+// held until the process ends.  Host code never takes the symbol itself for
+// an address; each device's address comes from hipGetSymbolAddress.
+static constexpr int64_t kNoAllocBytes = int64_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
 
@@ -74,7 +83,8 @@ struct HostPlan {
     int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
         nph, node_split, node_kchunk, node_yoff, node_goff, node_ldg, node_parent, order, lvl_items, lvl_recs, chunks, chunks_narrow, rblocks, small_nodes,
         sq_tiles, tiny, toff,
-        apos, adiag, bitems, plan, linv, dinv, part, gbuf, ypart, cnt, adj_z, adj_l, adj_s, adj_t, adj_f, adj_d, ctrl, end;
+        apos, adiag, bitems, plan, linv, dinv, part, gbuf, ypart, cnt, ctrl, fwd_end, adj_z, adj_l, adj_s, adj_t, adj_f,
+        adj_d, end;
   } off{};
   int64_t tables_bytes = 0;  // [0, tables_bytes) is uploaded once
 };
@@ -649,6 +659,8 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.gbuf = take(scalar_bytes * batch * H.g_elems);
   o.ypart = take(scalar_bytes * batch * H.y_elems);
   o.cnt = take(4 * kPhases * batch * ns);
+  o.ctrl = take(4 * CTRL_WORDS);
+  o.fwd_end = p;  // the forward path (normalize, run) touches [0, fwd_end) only
   H.adjoint = scalar_bytes == 8;
   const int64_t pan = H.adjoint ? scalar_bytes * batch * S.panel_elems : 0;
   const int64_t sqb = H.adjoint ? scalar_bytes * batch * H.sq_elems : 0;
@@ -658,7 +670,6 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.adj_t = take(sqb);
   o.adj_f = take(sqb);
   o.adj_d = take(sqb);
-  o.ctrl = take(4 * CTRL_WORDS);
   o.end = p;
 }
 
@@ -681,6 +692,9 @@ struct selinv_ctx {
   uint64_t gen = 0, dtilde_gen = 0, run_gen = 0;
   const void *panels_at = nullptr, *dtilde_at = nullptr, *x_at = nullptr;
   std::vector<Item> bseq;            // adjoint launch sequence for selinv_items (built on demand)
+  const void *ctrl_at = nullptr;     // control words of the last persistent launch (for selinv_sync)
+  uint64_t serial = 0;               // unique per context (owner tag of the no-alloc work area)
+  DevPlan plan_noalloc{};            // staging of the plan copy in the no-alloc work area
   void *uploaded_to = nullptr;       // work buffer holding the tables
   int device = -1;
   double *pinned = nullptr;          // host staging of the factor panels
@@ -879,6 +893,55 @@ selinv_status ensure_uploaded(selinv_ctx *h, void *work, hipStream_t st) {
   return SELINV_OK;
 }
 
+// Launch geometry of the persistent schedule (once per context) and the
+// per-wait budget in device clock ticks: watchdog_ms milliseconds, 0 = 10 s,
+// < 0 = -watchdog_ms ticks.
+selinv_status run_setup(selinv_ctx *h, int64_t *budget) {
+  hipError_t e;
+  if (h->grid == 0) {
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_err(h, e, "hipGetDevice");
+    int ncu = 0, khz = 0;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_err(h, e, "device attribute");
+    e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return hip_err(h, e, "device attribute");
+    // One persistent workgroup per CU by default: with two, items at the
+    // narrow top of the tree can land on the same CU while others idle.
+    int per = persistent_blocks_per_cu(h->is_complex());
+    int want = 1;
+    if (const char *v = std::getenv("SELINV_PERSISTENT_WG_PER_CU")) want = std::atoi(v);
+    if (want < 1) want = 1;
+    if (per < 1) per = 1;
+    h->grid = ncu * std::min(per, want);
+    h->wall_khz = khz > 0 ? khz : 100000;
+  }
+  const int64_t wd = h->opts.watchdog_ms;
+  *budget = wd < 0 ? -wd : (wd > 0 ? wd : 10000) * h->wall_khz;
+  return SELINV_OK;
+}
+
+// Device address of this GPU's no-alloc work area, looked up once per device
+// (with that device current) and kept; and which context's tables it holds.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+uint64_t g_scratch_owner[kMaxDevices] = {};
+std::atomic<uint64_t> g_ctx_serial{0};
+
+selinv_status scratch_for_device(selinv_ctx *h, int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return set_err(h, SELINV_EUNSUPPORTED, "device index beyond the no-alloc table");
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_err(h, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SELINV_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -907,6 +970,7 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *ro
   *out = nullptr;
   selinv_ctx *h = new (std::nothrow) selinv_ctx();
   if (!h) return SELINV_ENOMEM;
+  h->serial = ++g_ctx_serial;
   if (opts)
     h->opts = *opts;
   else
@@ -1084,29 +1148,10 @@ selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, voi
   hipStream_t st = (hipStream_t)stream;
   selinv_status ss = ensure_uploaded(h, work_dev, st);
   if (ss != SELINV_OK) return ss;
+  int64_t budget = 0;
+  ss = run_setup(h, &budget);
+  if (ss != SELINV_OK) return ss;
   hipError_t e;
-  if (h->grid == 0) {
-    int dev = 0;
-    e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_err(h, e, "hipGetDevice");
-    int ncu = 0, khz = 0;
-    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return hip_err(h, e, "device attribute");
-    e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
-    if (e != hipSuccess) return hip_err(h, e, "device attribute");
-    // One persistent workgroup per CU by default: with two, items at the
-    // narrow top of the tree can land on the same CU while others idle.
-    int per = persistent_blocks_per_cu(h->is_complex());
-    int want = 1;
-    if (const char *e = std::getenv("SELINV_PERSISTENT_WG_PER_CU")) want = std::atoi(e);
-    if (want < 1) want = 1;
-    if (per < 1) per = 1;
-    h->grid = ncu * std::min(per, want);
-    h->wall_khz = khz > 0 ? khz : 100000;
-  }
-  // per-wait budget: watchdog_ms milliseconds, 0 = 10 s, < 0 = -watchdog_ms device clock ticks
-  const int64_t wd = h->opts.watchdog_ms;
-  const int64_t budget = wd < 0 ? -wd : (wd > 0 ? wd : 10000) * h->wall_khz;
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
   e = launch_run(pl, dev_plan(h, work_dev), aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, budget, h->grid,
@@ -1114,6 +1159,7 @@ selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, voi
   if (e != hipSuccess) return hip_err(h, e, "selinv launch");
   h->run_gen = h->gen;
   h->x_at = x_dev;
+  h->ctrl_at = static_cast<unsigned char *>(work_dev) + h->H.off.ctrl;
   return SELINV_OK;
 }
 
@@ -1195,6 +1241,57 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
   if (e != hipSuccess) return fail(e, "selinv launch");
   h->run_gen = h->gen;
   h->x_at = x_dev;
+  return SELINV_OK;
+}
+
+selinv_status selinv_normalize_run_noalloc(selinv_ctx *h, const void *ldlt_dev, void *panels_dev, void *x_dev,
+                                           void *dtilde_dev, void *stream) {
+  if (!h) return SELINV_EINVAL;
+  if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
+  if (!ldlt_dev || !panels_dev || !x_dev) return set_err(h, SELINV_EINVAL, "null buffer");
+  const int64_t need = h->H.off.fwd_end;
+  if (need > kNoAllocBytes)
+    return set_err(h, SELINV_ENOMEM,
+                   "selinv_normalize_run_noalloc: this plan needs " + std::to_string(need) +
+                       " bytes of work area, more than the fixed " + std::to_string(kNoAllocBytes) +
+                       " (use selinv_normalize_run with a caller-allocated work buffer)",
+                   need, kNoAllocBytes);
+  hipStream_t st = (hipStream_t)stream;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_err(h, e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  void *work = nullptr;
+  selinv_status ss = scratch_for_device(h, dev, &work);
+  if (ss != SELINV_OK) return ss;
+  // this context's tables and plan into the work area, unless they are still
+  // there from this context's previous call on this device
+  if (g_scratch_owner[dev] != h->serial) {
+    g_scratch_owner[dev] = 0;
+    e = hipMemcpyAsync(work, h->image.data(), h->image.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_err(h, e, "table upload (no-alloc)");
+    h->plan_noalloc = make_devplan(h, work);
+    e = hipMemcpyAsync(static_cast<unsigned char *>(work) + h->H.off.plan, &h->plan_noalloc, sizeof(DevPlan),
+                       hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_err(h, e, "plan upload (no-alloc)");
+    e = hipStreamSynchronize(st);  // the host staging is reused
+    if (e != hipSuccess) return hip_err(h, e, "table upload sync (no-alloc)");
+    g_scratch_owner[dev] = h->serial;
+  }
+  int64_t budget = 0;
+  ss = run_setup(h, &budget);
+  if (ss != SELINV_OK) return ss;
+  DevPlan pl = make_devplan(h, work);
+  const DevPlan *dpl = dev_plan(h, work);
+  LaunchAux aux = make_aux(h, work);
+  e = launch_normalize(pl, dpl, aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st, 0, NORM_ALL);
+  if (e != hipSuccess) return hip_err(h, e, "normalize launch (no-alloc)");
+  note_normalized(h, panels_dev, dtilde_dev);
+  e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, budget, h->grid, st, 0, aux.nlvl);
+  if (e != hipSuccess) return hip_err(h, e, "selinv launch (no-alloc)");
+  h->run_gen = h->gen;
+  h->x_at = x_dev;
+  h->ctrl_at = static_cast<unsigned char *>(work) + h->H.off.ctrl;
   return SELINV_OK;
 }
 
@@ -1348,7 +1445,10 @@ selinv_status selinv_items(const selinv_ctx *hc, int32_t which, const int32_t **
 selinv_status selinv_trace(selinv_ctx *h, void *trace_dev) {
   if (!h) return SELINV_EINVAL;
   h->trace = trace_dev;
-  h->uploaded_to = nullptr;  // the device copy of the plan carries the pointer
+  h->uploaded_to = nullptr;  // the device copies of the plan carry the pointer
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  for (uint64_t &o : g_scratch_owner)
+    if (o == h->serial) o = 0;
   return SELINV_OK;
 }
 
@@ -1357,10 +1457,9 @@ selinv_status selinv_sync(selinv_ctx *h, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_err(h, e, "stream synchronize");
-  if (h->uploaded_to && h->opts.sched == SELINV_SCHED_PERSISTENT) {
+  if (h->ctrl_at && h->opts.sched == SELINV_SCHED_PERSISTENT) {
     int32_t ctrl[4] = {0, 0, 0, 0};
-    const unsigned char *b = static_cast<const unsigned char *>(h->uploaded_to);
-    e = hipMemcpy(ctrl, b + h->H.off.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost);
+    e = hipMemcpy(ctrl, h->ctrl_at, sizeof(ctrl), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_err(h, e, "control readback");
     if (ctrl[CTRL_ERR] == 2)
       return set_err(h, SELINV_EDEVICE, "persistent scheduler: a workgroup drew more tickets than there are items");
