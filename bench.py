@@ -51,6 +51,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TUNE_TABLE = None  # set in main(): the autotuner's table for this GPU and ROCm version, if committed
+
+
+def tune_table_path():
+    """paper_1604_02528_amd/tune/<arch>_rocm<version>.json for this build's key, or None."""
+    from paper_1604_02528_amd import capi
+
+    key = dict(kv.split("=") for kv in capi.selinv_tune_key().split())
+    p = os.path.join(ROOT, "paper_1604_02528_amd", "tune", f"{key['arch']}_rocm{key['rocm']}.json")
+    return p if os.path.exists(p) else None
+
+
 def measured_traffic(workload, sched):
     """HBM bytes per traversal from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE record of this workload (scaled by a 1 GiB copy), or None when
@@ -128,41 +140,40 @@ def timed_steps(S, ldlt, steps, warmup):
     return wall, t_norm, t_run
 
 
-def factor_on_device(w, relax, sched, batch, replicate):
-    """LDL^T panels on the device for `batch` matrices (host factorization,
-    outside every timed region).  replicate: factor matrix 0 only and copy its
-    panels to every batch slot (the traversal does the same work for any
-    values; used where the host factorization of the whole batch takes
-    minutes)."""
+def factor_on_device(w, relax, sched, batch):
+    """LDL^T panels of `batch` matrices on the device, from the library's GPU
+    factorization (selinv_factor_device), outside every timed region.  Returns
+    the panels and the factorization's wall time (after a warm-up call)."""
     import torch
 
     from paper_1604_02528_amd import SelInv
 
     dt = "c128" if w.is_complex else "f64"
-    if replicate and batch > 1:
-        S1 = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=1, cap=w.cap, relax=relax, sched=sched)
-        one = torch.from_numpy(S1.factor_host(w.values[:1])).to("cuda")
-        S1.close()
-        ldlt = one.expand(batch, -1).contiguous()
-        del one
-        return ldlt
     S1 = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=batch, cap=w.cap, relax=relax, sched=sched)
-    out = torch.from_numpy(S1.factor_host(w.values[:batch])).to("cuda")
+    vals = torch.from_numpy(np.ascontiguousarray(w.values[:batch])).to("cuda")
+    out = S1.factor_device(vals)
+    S1.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S1.factor_device(vals, out=out)
+    S1.sync()
+    torch.cuda.synchronize()
+    t_fac = time.perf_counter() - t0
     S1.close()
-    return out
+    del vals
+    return out, t_fac
 
 
-def gpu_leg(w, relax, steps, warmup, sched="levels", replicate=False, batch=None, want_x=False):
+def gpu_leg(w, relax, steps, warmup, sched="levels", batch=None, want_x=False):
     from paper_1604_02528_amd import SelInv
 
     batch = w.batch if batch is None else batch
     dt = "c128" if w.is_complex else "f64"
     t0 = time.perf_counter()
-    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=batch, cap=w.cap, relax=relax, sched=sched)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=batch, cap=w.cap, relax=relax, sched=sched,
+               tune_cache=TUNE_TABLE)
     t_an = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ldlt = factor_on_device(w, relax, sched, batch, replicate)
-    t_fac = time.perf_counter() - t0
+    ldlt, t_fac = factor_on_device(w, relax, sched, batch)
     S._alloc(False)
     wall, t_norm, t_run = timed_steps(S, ldlt, steps, warmup)
     X = S.to_host("x") if want_x else None
@@ -188,7 +199,7 @@ def summary(w, g, steps, name):
         "traversal_tflops": round(flops / t_run / 1e12, 4),
         "traversal_frac_of_peak": round(flops / t_run / 1e12 / PEAK_FP64_TFLOPS, 5),
         "flops_per_solve": sym["flops_exact"], "nsuper": sym["nsuper"], "depth": sym["depth"],
-        "t_factor_host_s": round(g["t_factor"], 2),
+        "t_factor_device_s": round(g["t_factor"], 4),
     }
 
 
@@ -207,8 +218,9 @@ def batched_leg(relax, sched):
     # 32 sequential single-shift solves (normalize + run each), same pattern
     from paper_1604_02528_amd import SelInv
 
-    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128", batch=1, cap=w.cap, relax=relax, sched=sched)
-    ldlt = factor_on_device(w, relax, sched, 1, False)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128", batch=1, cap=w.cap, relax=relax, sched=sched,
+               tune_cache=TUNE_TABLE)
+    ldlt, _ = factor_on_device(w, relax, sched, 1)
     S._alloc(False)
     wall, _, _ = timed_steps(S, ldlt, 3 * w.batch, w.batch)
     S.close()
@@ -392,6 +404,7 @@ def main():
     ap.add_argument("--workload", default="C5", choices=["C2", "C3", "C5"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three 1 GiB device-to-device copies (reference for HBM byte counters)")
+    ap.add_argument("--no-tune", action="store_true", help="ignore the committed autotuner table")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the C2 line, the C3 batched-vs-sequential and the C4 adjoint-vs-forward legs")
     args = ap.parse_args()
@@ -404,10 +417,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     from workloads import config
 
+    global TUNE_TABLE
+    TUNE_TABLE = None if args.no_tune else tune_table_path()
+    log(f"tune table: {TUNE_TABLE}")
+
     w = config(args.workload)
-    replicate = args.workload == "C5"
     log(f"workload {args.workload}: N={w.n} nnz(A)={w.nnz} batch={w.batch} relax={args.relax}")
-    g = gpu_leg(w, args.relax, args.steps, args.warmup, args.sched, replicate,
+    g = gpu_leg(w, args.relax, args.steps, args.warmup, args.sched,
                 want_x=args.workload == "C2" and not args.no_cpu)
     sm = summary(w, g, args.steps, args.workload)
     flops = g["sym"]["flops_exact"] * w.batch
@@ -416,7 +432,7 @@ def main():
     t_run = float(np.mean(g["t_run"]))
     t_norm = float(np.mean(g["t_norm"]))
     achieved = flops / t_run / 1e12
-    log(f"analyze {g['t_analyze']:.2f}s factor {g['t_factor']:.2f}s | step {ms_step:.3f} ms "
+    log(f"analyze {g['t_analyze']:.2f}s device factor {g['t_factor']*1e3:.1f} ms | step {ms_step:.3f} ms "
         f"(normalize {t_norm*1e3:.3f} ms, selinv {t_run*1e3:.3f} ms) | {value:.1f} GFLOP/s")
     X0 = g["X"][0] if g["X"] is not None else None
     g["S"].close()
@@ -434,13 +450,13 @@ def main():
                       "matrix with the same supernode partition, median of 3, factorization excluded")
             one = cpu_leg_sample(w, args.relax, 5e9, one_thread=True)
         else:
-            c = cpu_leg_sample(w, args.relax, 8e11 if args.workload == "C5" else 1e11)
+            c = cpu_leg_sample(w, args.relax, 3e12 if args.workload == "C5" else 3e11)
             rate, secs, thr = c["flops"] / c["t"] / 1e9, c["t"], c["threads"]
             sample = (f"the oracle's Alg. 1 (numpy BLAS) on the first {c['nodes']} of {c['nsuper']} supernodes of "
                       f"its root-first loop for one matrix ({100 * c['frac_of_workload']:.1f}% of one matrix's "
                       f"flops, {c['flops']:.3e}), with seeded random normalized factors of the same shapes (the "
                       f"time depends on the shapes only); GFLOP/s of that sample")
-            one = cpu_leg_sample(w, args.relax, 2e11 if args.workload == "C5" else 2e10, one_thread=True)
+            one = cpu_leg_sample(w, args.relax, 6e11 if args.workload == "C5" else 6e10, one_thread=True)
         cpu = {"value": round(rate, 3), "unit": "GFLOP/s", "cores": thr, "kind": "oracle", "sample": sample,
                "seconds": round(secs, 3), "host_cpu": hc["model"], "host_cores_available": hc["cores_available"],
                "one_thread": {"value": round(one["flops"] / one["t"] / 1e9, 3), "cores": one["threads"],
@@ -460,9 +476,8 @@ def main():
         torch.cuda.empty_cache()
         extras["adjoint"] = adjoint_leg(args.relax)
     wl = WORKLOADS[args.workload]
-    if replicate:
-        wl += ("; the LDL^T panels of shift 0 are copied to all 8 batch slots (host factorization outside the "
-               "timed region); the traversal does the full 8-shift work, whose cost does not depend on the values")
+    if w.batch > 1:
+        wl += f"; {w.batch} distinct shifts, each factored on the GPU (selinv_factor_device) before timing"
     out = {
         "metric": "selinv FP64 GFLOP/s (% MFMA peak) + s/solve; batched 32-shift & adjoint vs plain",
         "value": round(value, 2),
@@ -479,6 +494,7 @@ def main():
         "config": {
             "workload": wl, "batch": w.batch,
             "supernode_cap": w.cap, "relax": args.relax, "schedule": args.sched,
+            "tune_table": os.path.relpath(TUNE_TABLE, ROOT) if TUNE_TABLE else None,
             "nsuper": sm["nsuper"], "depth": sm["depth"],
             "flops_per_solve": sm["flops_per_solve"],
         },
@@ -498,7 +514,7 @@ def main():
                              "HIP-event time of selinv_run (all of its launches) on the launch stream"},
         "normalize_ms": round(t_norm * 1e3, 4),
         "max_rel_err_vs_oracle": err,
-        "t_factor_s": round(sm["t_factor_host_s"], 2),
+        "t_factor_device_s": sm["t_factor_device_s"],
         "cpu_baseline": cpu,
         **extras,
     }

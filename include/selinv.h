@@ -92,6 +92,13 @@ typedef struct {
                           a quarter of it at etree depths whose tiles fill at most a quarter of
                           the GPU */
   int32_t reserved;
+  const char *tune_cache; /* path of a tune table written by the autotuner (JSON, format
+                             "selinv-tune-1"), or NULL.  Entries of this GPU target, ROCm version
+                             and dtype choose, per bucket of supernode width s and |C(K)|, whether
+                             X_{C,C} is gathered into a dense buffer, whether a dense node's GEMM-1
+                             runs in the GEMM-1-only kernel (level schedule), and split_min_k; they
+                             override dense_min_c / split_min_k for the nodes they cover.  Read by
+                             selinv_analyze (EINVAL on a malformed file); the string is copied */
 } selinv_opts;
 
 /* Fill `o` with defaults (cap 256, R64, batch 1, level schedule, relax 0.05).  relax = 0 gives the
@@ -134,6 +141,7 @@ typedef struct {
   double flops_exact;        /* sum_K 2c^2 s + 2 c s^2 over the maximal (relax = 0) partition, x4 for complex */
   double flops;              /* the same over the partition in use */
   int64_t depth;             /* supernodal etree height */
+  int64_t tuned_nodes;       /* supernodes a tune-table entry applied to */
 } selinv_symbolic_view;
 
 selinv_status selinv_symbolic(const selinv_ctx *h, selinv_symbolic_view *v);
@@ -146,6 +154,7 @@ typedef struct {
   int64_t dtilde_bytes;  /* optional pivot blocks Dt_K (needed by selinv_backward) */
   int64_t abar_bytes;    /* adjoint output on A's pattern, batch * nnz(A) scalars */
   int64_t trace_bytes;   /* optional selinv_trace buffer */
+  int64_t tables_bytes;  /* leading part of work_bytes: the plan tables, written on upload and then only read */
 } selinv_sizes_t;
 
 selinv_status selinv_sizes(const selinv_ctx *h, selinv_sizes_t *s);
@@ -188,6 +197,31 @@ selinv_status selinv_normalize(selinv_ctx *h, const void *ldlt_dev, void *panels
  * device work; does not enable selinv_run.  Errors as selinv_factor.
  */
 selinv_status selinv_factor_host(selinv_ctx *h, const void *values, void *panels_host);
+
+/*
+ * selinv_factor_device -- the numeric factorization on the GPU: unpivoted
+ * supernodal LDL^T of every matrix of the batch (the input the paper takes
+ * from an external solver with no dynamic pivoting, Section 4), with the
+ * same output as selinv_factor_host.
+ *   values_dev [batch][nnz(A)] (device): A's stored lower values in rowind
+ *     order (SELINV_C128: interleaved re, im).
+ *   ldlt_dev [batch][panel_elems] (device, caller-owned, panels_bytes):
+ *     receives the LDL^T panels (strict lower L_KK, D_K on the diagonal,
+ *     L_{C,K} below); may be panels_dev, which selinv_normalize can then
+ *     normalize in place.
+ * Leaves to root, one launch per etree depth and step: the diagonal block's
+ * LDL^T, L_KK^{-1}, L_{C,K} on FP64 MFMA, and the Schur update
+ * L_{C,K} D_K L_{C,K}^T scattered into the ancestors' panels through the
+ * ancestor index maps with FP64 atomic adds (the summation order of sibling
+ * updates, and so the last bits, may vary between runs).  Asynchronous on
+ * `stream`.  A zero or non-finite pivot is reported by the next selinv_sync
+ * as SELINV_ESINGULAR (error_info(0) = column of B, error_info(1) = batch
+ * index); the panels are then undefined.  selinv_logdet is valid after that
+ * selinv_sync.  Uses the work buffer's tables (uploaded on the first call);
+ * does not by itself enable selinv_run.
+ */
+selinv_status selinv_factor_device(selinv_ctx *h, const void *values_dev, void *ldlt_dev, void *work_dev,
+                                   void *stream);
 
 /*
  * selinv_run -- selected inversion (Alg. 1 second loop / Alg. 2, LDL^T form).
@@ -314,8 +348,9 @@ selinv_status selinv_trace(selinv_ctx *h, void *trace_dev);
  * selinv_destroy.
  *   which = 0: the forward traversal's items (type: 0 GEMM-1 tile,
  *     1 diagonal-block tile, 2 single-workgroup node, 3 dense X_{C,C} gather
- *     block, 4 split-tile reduction; for type 0, b holds the column tile in
- *     its low 16 bits and the contraction part above them).  Item id i of
+ *     block, 4 split-tile reduction, 5 GEMM-2 share of a tile stored by its
+ *     GEMM-1 item; for type 0, b holds the column tile in its low 16 bits and
+ *     the contraction part above them).  Item id i of
  *     matrix l is l * n + i in traces.
  *   which = 1: the adjoint's items in launch order (R1 leaves to root, then
  *     R3 root to leaves); type 0..11 as the BackItemType of the device plan,
@@ -324,8 +359,10 @@ selinv_status selinv_trace(selinv_ctx *h, void *trace_dev);
  */
 selinv_status selinv_items(const selinv_ctx *h, int32_t which, const int32_t **items, int64_t *n);
 
-/* log det of each matrix of the batch (sum of log pivots; complex log for C128).
-   out_host: batch doubles (R64) or batch (re, im) pairs (C128).  Valid after selinv_factor. */
+/* log det of each matrix of the batch from the pivots (det B = prod D_jj, Section 2.3): the sum of the
+   principal logarithms of the pivots.  out_host: batch doubles (R64: log |det|) or batch (re, im) pairs
+   (C128).  Valid after selinv_factor or selinv_factor_host, and after selinv_factor_device once
+   selinv_sync has returned; SELINV_ESTATE otherwise. */
 selinv_status selinv_logdet(const selinv_ctx *h, double *out_host);
 
 /* Wait for `stream` and report device-side errors (watchdog, HIP errors). */
@@ -337,6 +374,9 @@ void selinv_destroy(selinv_ctx *h);
 
 /* Library version string. */
 const char *selinv_version(void);
+
+/* Key of this build in tune tables: "arch=<gfx target> rocm=<major.minor.patch>". */
+const char *selinv_tune_key(void);
 
 #ifdef __cplusplus
 }

@@ -19,7 +19,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libselinv.so")
 ROOT = os.path.dirname(HERE)
 
-SOURCES = ["symbolic.cpp", "factor_host.cpp", "capi.cpp", "kernels.hip", "adjoint.hip"]
+SOURCES = ["symbolic.cpp", "factor_host.cpp", "tune.cpp", "capi.cpp", "kernels.hip", "adjoint.hip", "factor.hip"]
 
 
 def hipcc():

@@ -22,8 +22,8 @@ STATUS = {0: "OK", 1: "EINVAL", 2: "EPATTERN", 3: "ESINGULAR", 4: "ENOMEM", 5: "
           7: "EUNSUPPORTED"}
 
 EXPORTED = (
-    "selinv_default_opts", "selinv_version", "selinv_analyze", "selinv_symbolic", "selinv_sizes",
-    "selinv_factor", "selinv_normalize", "selinv_factor_host", "selinv_run", "selinv_normalize_run", "selinv_normalize_run_noalloc", "selinv_extract",
+    "selinv_default_opts", "selinv_version", "selinv_tune_key", "selinv_analyze", "selinv_symbolic", "selinv_sizes",
+    "selinv_factor", "selinv_normalize", "selinv_factor_host", "selinv_factor_device", "selinv_run", "selinv_normalize_run", "selinv_normalize_run_noalloc", "selinv_extract",
     "selinv_scatter",
     "selinv_backward",
     "selinv_logdet", "selinv_check_plan", "selinv_trace", "selinv_items", "selinv_sync", "selinv_last_error", "selinv_error_info", "selinv_destroy",
@@ -34,7 +34,7 @@ class Opts(C.Structure):
     _fields_ = [("max_super", C.c_int32), ("dtype", C.c_int32), ("batch", C.c_int32), ("sched", C.c_int32),
                 ("relax", C.c_double), ("nthreads", C.c_int32), ("dense_min_c", C.c_int32),
                 ("watchdog_ms", C.c_int64), ("dense_max_bytes", C.c_int64), ("split_min_k", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("tune_cache", C.c_char_p)]
 
 
 _P64 = C.POINTER(C.c_int64)
@@ -48,12 +48,14 @@ class SymbolicView(C.Structure):
                 ("rowptr", _P64), ("rowind_L", _P64), ("panel_off", _P64),
                 ("seg_ptr", _P64), ("seg_super", _P64), ("seg_start", _P64), ("seg_posoff", _P64),
                 ("posarr", _P32), ("nseg", C.c_int64), ("nposarr", C.c_int64),
-                ("flops_exact", C.c_double), ("flops", C.c_double), ("depth", C.c_int64)]
+                ("flops_exact", C.c_double), ("flops", C.c_double), ("depth", C.c_int64),
+                ("tuned_nodes", C.c_int64)]
 
 
 class Sizes(C.Structure):
     _fields_ = [("panels_bytes", C.c_int64), ("x_bytes", C.c_int64), ("work_bytes", C.c_int64),
-                ("dtilde_bytes", C.c_int64), ("abar_bytes", C.c_int64), ("trace_bytes", C.c_int64)]
+                ("dtilde_bytes", C.c_int64), ("abar_bytes", C.c_int64), ("trace_bytes", C.c_int64),
+                ("tables_bytes", C.c_int64)]
 
 
 class SelinvError(RuntimeError):
@@ -78,12 +80,14 @@ def load():
     sig = {
         "selinv_default_opts": (None, [C.POINTER(Opts)]),
         "selinv_version": (C.c_char_p, []),
+        "selinv_tune_key": (C.c_char_p, []),
         "selinv_analyze": (C.c_int, [C.c_int64, vp, vp, vp, C.POINTER(Opts), C.POINTER(vp)]),
         "selinv_symbolic": (C.c_int, [vp, C.POINTER(SymbolicView)]),
         "selinv_sizes": (C.c_int, [vp, C.POINTER(Sizes)]),
         "selinv_factor": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "selinv_normalize": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "selinv_factor_host": (C.c_int, [vp, vp, vp]),
+        "selinv_factor_device": (C.c_int, [vp, vp, vp, vp, vp]),
         "selinv_run": (C.c_int, [vp, vp, vp, vp, vp]),
         "selinv_normalize_run": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "selinv_normalize_run_noalloc": (C.c_int, [vp, vp, vp, vp, vp, vp]),
@@ -138,6 +142,10 @@ def selinv_version():
     return load().selinv_version().decode()
 
 
+def selinv_tune_key():
+    return load().selinv_tune_key().decode()
+
+
 def selinv_analyze(n, colptr, rowind, perm, opts):
     lib = load()
     h = C.c_void_p()
@@ -174,6 +182,10 @@ def selinv_normalize(h, ldlt, panels, work, dtilde, stream):
 
 def selinv_factor_host(h, values, panels_host):
     check(h, load().selinv_factor_host(h, ptr(values), ptr(panels_host)))
+
+
+def selinv_factor_device(h, values, ldlt, work, stream):
+    check(h, load().selinv_factor_device(h, ptr(values), ptr(ldlt), ptr(work), stream))
 
 
 def selinv_run(h, panels, x, work, stream):

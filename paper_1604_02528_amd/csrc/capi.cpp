@@ -30,6 +30,8 @@ hipError_t launch_backward(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
                            const void *x, const void *dt, void *xbar, const void *wlogdet, void *abar, hipStream_t st);
 hipError_t launch_scatter(const DevPlan &pl, const DevPlan *dpl, bool cplx_, const void *vals, void *panel,
                           hipStream_t st);
+hipError_t launch_factor(const DevPlan &pl, const DevPlan *dpl, const FactorAux &fa, bool cplx_, const void *values,
+                         void *panels, hipStream_t st);
 }  // namespace selinv
 
 using namespace selinv;
@@ -65,7 +67,10 @@ struct HostPlan {
   std::vector<int32_t> tiny_dptr;  // [depth + 1] small-node records of each etree depth
   std::vector<int32_t> tiny_dadj;  // [depth] end of each depth's c <= kTinyC prefix (the adjoint's)
   bool adjoint = false;        // adjoint scratch allocated (FP64 only)
-  std::vector<int32_t> lvl_items, lvl_ptr, lvl_tiny;
+  std::vector<int32_t> lvl_items, lvl_ptr, lvl_tiny, lvl_kind;
+  std::vector<int32_t> node_defer;  // GEMM-2 of the node in ITEM_P items (level schedule, dense buffer, unsplit)
+  std::vector<int32_t> node_ykern;  // GEMM-1 tiles in k_ydense (level schedule, dense buffer)
+  std::vector<int8_t> node_tuned;   // a tune-table entry applied to the node
   int32_t lvl_top = 0;        // level launches of the top depths (see LaunchAux)
   int32_t norm_top[5] = {0, 0, 0, 0, 0};  // their normalization entries: small, narrow, chunks, rblocks, sq
   std::vector<LRec> lvl_recs;  // the items of lvl_items with their nodes, in level order
@@ -76,6 +81,12 @@ struct HostPlan {
   std::vector<int4> sq_tiles;
   std::vector<int64_t> apos;
   std::vector<uint8_t> adiag;
+  // device factorization: per-depth launch lists (deepest first) and pivot positions
+  std::vector<int32_t> fac_nodes;
+  std::vector<int2> fac_cn, fac_cw, fac_rb;
+  std::vector<int4> fac_tiles;
+  std::vector<FacLevel> fac_lev;
+  std::vector<int64_t> dpos;
   int64_t sq_elems = 0;
   int64_t part_elems = 0;
   // byte offsets inside the work buffer
@@ -83,8 +94,8 @@ struct HostPlan {
     int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
         nph, node_split, node_kchunk, node_yoff, node_goff, node_ldg, node_parent, order, lvl_items, lvl_recs, chunks, chunks_narrow, rblocks, small_nodes,
         sq_tiles, tiny, toff,
-        apos, adiag, bitems, plan, linv, dinv, part, gbuf, ypart, cnt, ctrl, fwd_end, adj_z, adj_l, adj_s, adj_t, adj_f,
-        adj_d, end;
+        apos, adiag, bitems, fac_nodes, fac_cn, fac_cw, fac_rb, fac_tiles, dpos, plan, linv, dinv, part, gbuf, ypart,
+        cnt, ctrl, fwd_end, adj_z, adj_l, adj_s, adj_t, adj_f, adj_d, ferr, fldet, end;
   } off{};
   int64_t tables_bytes = 0;  // [0, tables_bytes) is uploaded once
 };
@@ -236,33 +247,41 @@ void ticket_order(const Symbolic &S, HostPlan &H, int64_t batch) {
 // offset 0 of one shared pool and only the largest depth counts against
 // max_bytes.  The persistent schedule overlaps depths: every node gets its own
 // buffer.  The threshold doubles until the footprint fits.
+// pref[K] (from a tune table): -1 = by the threshold, 0 = never, 1 = from
+// c >= 65 on; the forced ones are thinned by their own doubling threshold
+// when the buffers do not fit.
 void choose_dense(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t min_c, int64_t max_bytes,
-                  bool per_level, HostPlan &H) {
+                  bool per_level, const std::vector<int8_t> &pref, HostPlan &H) {
   const int64_t ns = S.nsuper();
   H.node_goff.assign(ns, -1);
   H.node_ldg.assign(ns, 0);
   H.g_elems = 0;
   H.dense_min_c = INT64_MAX;
-  if (min_c < 0) return;
   auto ldg_of = [](int64_t c) { return (c + kPanelAlign - 1) / kPanelAlign * kPanelAlign; };
-  auto footprint = [&](int64_t t) {
+  const int64_t t0 = min_c < 0 ? INT64_MAX / 4 : std::max<int64_t>(min_c, kTileM + 1);
+  auto wants = [&](int64_t K, int64_t t, int64_t tf) {
+    const int64_t c = S.nrows(K);
+    return pref[K] == 0 ? false : pref[K] == 1 ? c >= tf : c >= t;
+  };
+  auto footprint = [&](int64_t t, int64_t tf) {
     std::vector<int64_t> per(per_level ? S.depth : 1, 0);
     for (int64_t K = 0; K < ns; ++K)
-      if (S.nrows(K) >= t) per[per_level ? S.sdepth[K] : 0] += ldg_of(S.nrows(K)) * S.nrows(K);
+      if (wants(K, t, tf)) per[per_level ? S.sdepth[K] : 0] += ldg_of(S.nrows(K)) * S.nrows(K);
     return *std::max_element(per.begin(), per.end());
   };
-  int64_t t = std::max<int64_t>(min_c, kTileM + 1);
+  int64_t t = t0, tf = kTileM + 1;
   while (true) {
-    const int64_t tot = footprint(t);
+    const int64_t tot = footprint(t, tf);
     if (tot == 0) return;
     if (tot * batch * scalar_bytes <= max_bytes) break;
-    t *= 2;
+    t = std::min<int64_t>(t, INT64_MAX / 4) * 2;
+    tf *= 2;
   }
   H.dense_min_c = t;
   std::vector<int64_t> next(per_level ? S.depth : 1, 0);
   for (int64_t K = 0; K < ns; ++K) {
     const int64_t c = S.nrows(K);
-    if (c < t) continue;
+    if (!wants(K, t, tf)) continue;
     int64_t &o = next[per_level ? S.sdepth[K] : 0];
     H.node_goff[K] = o;
     H.node_ldg[K] = (int32_t)ldg_of(c);
@@ -272,8 +291,20 @@ void choose_dense(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_
 }
 
 void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t dense_min_c, int64_t dense_max_bytes,
-                int64_t split_min_k, bool per_level, HostPlan &H) {
+                int64_t split_min_k, bool per_level, const TuneTable *tt, HostPlan &H) {
   const int64_t ns = S.nsuper();
+  // per-node choices from the tune table (bucket of (s, c)), else the defaults
+  std::vector<int8_t> dense_pref(ns, -1), ykern_pref(ns, -1);
+  std::vector<int64_t> node_mink(ns, split_min_k);
+  H.node_tuned.assign(ns, 0);
+  if (tt)
+    for (int64_t K = 0; K < ns; ++K)
+      if (const TuneEntry *e = tt->find(S.width(K), S.nrows(K))) {
+        H.node_tuned[K] = 1;
+        if (e->dense >= 0) dense_pref[K] = (int8_t)(e->dense != 0);
+        if (e->ydense >= 0) ykern_pref[K] = (int8_t)(e->ydense != 0);
+        if (e->split_min_k != 0) node_mink[K] = e->split_min_k;
+      }
   H.node_s.resize(ns);
   H.node_c.resize(ns);
   H.node_off = S.panel_off;
@@ -313,13 +344,13 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     const int64_t nq = (s + kTileN - 1) / kTileN;
     int64_t parts = 1;
     if (tiles < kSplitTarget) parts = std::min<int64_t>(kSplitMax, (kSplitTarget + tiles - 1) / tiles);
-    if (split_min_k < 0) parts = 1;
+    if (node_mink[K] < 0) parts = 1;
     // at a depth that fills at most a quarter of the GPU, the parts may be a
     // quarter as long (as many as one round of items over the GPU allows):
     // there the GEMM-1 tiles wait on memory latency, and the R items that sum
     // the extra parts run on otherwise idle CUs
     const bool sparse = dtiles[S.sdepth[K]] * 4 <= kSplitTarget;
-    const int64_t mink = sparse ? std::max<int64_t>(2 * kSplitAlign, split_min_k / 4) : split_min_k;
+    const int64_t mink = sparse ? std::max<int64_t>(2 * kSplitAlign, node_mink[K] / 4) : node_mink[K];
     if (sparse) parts = std::min<int64_t>(parts, kSplitTarget / dtiles[S.sdepth[K]]);  // one round of items
     parts = std::max<int64_t>(1, std::min<int64_t>(parts, c / std::max<int64_t>(mink, kSplitAlign)));
     int64_t chunk = c;
@@ -363,14 +394,25 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     }
   }
   // work items, phase by phase (see plan.hpp)
-  choose_dense(S, batch, scalar_bytes, dense_min_c, dense_max_bytes, per_level, H);
+  choose_dense(S, batch, scalar_bytes, dense_min_c, dense_max_bytes, per_level, dense_pref, H);
   // GEMM-2 shares of the R items: a depth whose R tiles (over the batch)
   // cannot fill the GPU cuts each tile's share into rq items by 64-row blocks
   // of P (the R phase of the top separator chain is otherwise one long item
   // per tile).
+  // Under the level schedule, the GEMM-1 tiles of nodes with a dense buffer
+  // run in their own kernel without GEMM-2; for unsplit ones the GEMM-2
+  // shares move to ITEM_P items of phase 2.
+  H.node_defer.assign(ns, 0);
+  H.node_ykern.assign(ns, 0);
+  if (per_level)
+    for (int64_t K = 0; K < ns; ++K)
+      if (H.node_goff[K] >= 0 && ykern_pref[K] != 0 && !(S.nrows(K) <= kSmallC && S.width(K) <= kSmallS)) {
+        H.node_ykern[K] = 1;
+        if (H.node_yoff[K] < 0) H.node_defer[K] = 1;
+      }
   std::vector<int64_t> rtiles(S.depth, 0);
   for (int64_t K = 0; K < ns; ++K)
-    if (H.node_yoff[K] >= 0)
+    if (H.node_yoff[K] >= 0 || H.node_defer[K])
       rtiles[S.sdepth[K]] += batch * ((S.nrows(K) + kTileM - 1) / kTileM) * ((S.width(K) + kTileN - 1) / kTileN);
   H.item_ptr.assign(ns + 1, 0);
   H.nph.assign((size_t)kPhases * ns, 0);
@@ -397,13 +439,14 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
         for (int32_t b = 0; b < nb; ++b)
           for (int32_t a = 0; a < nr; ++a) H.items.push_back(Item{(int32_t)K, ITEM_Y, a, b | (p << 16)});
       nph(1, K) = nr * nb * parts;
-      if (H.node_yoff[K] >= 0) {  // partial tiles, summed by R items
+      if (H.node_yoff[K] >= 0 || H.node_defer[K]) {  // partial tiles summed by R items, or GEMM-2 by P items
+        const int32_t type = H.node_defer[K] ? ITEM_P : ITEM_R;
         const int64_t nq = (s + kTileN - 1) / kTileN;
         const int32_t rq = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nq, kSplitTarget / rtiles[S.sdepth[K]]));
         for (int32_t r = 0; r < rq; ++r)
           for (int32_t b = 0; b < nb; ++b)
             for (int32_t a = 0; a < nr; ++a)
-              H.items.push_back(Item{(int32_t)K, ITEM_R, a, rq > 1 ? b | (r << 16) | (rq << 24) : b});
+              H.items.push_back(Item{(int32_t)K, type, a, rq > 1 ? b | (r << 16) | (rq << 24) : b});
         nph(2, K) = nr * nb * rq;
       }
     }
@@ -433,6 +476,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   H.lvl_ptr.assign(1, 0);
   H.lvl_top = 0;
   H.lvl_tiny.clear();
+  H.lvl_kind.clear();
   H.tiny.clear();
   H.toff.clear();
   H.tiny_dptr.assign(S.depth + 1, 0);
@@ -443,22 +487,27 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   auto adj_tiny = [&](int64_t K) { return tiny_ok && H.node_c[K] <= kTinyC && H.node_s[K] <= kTinyS; };
   {
     auto is_tiny = [&](int64_t K) { return tiny_ok && H.node_c[K] <= tiny_cf && H.node_s[K] <= kTinyS; };
-    auto close = [&](int32_t tiny_base) {
+    auto close = [&](int32_t tiny_base, int32_t kind) {
       if ((int32_t)H.lvl_items.size() > H.lvl_ptr.back()) {
         H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
         H.lvl_tiny.push_back(tiny_base);
+        H.lvl_kind.push_back(kind);
       }
     };
     std::vector<std::vector<int64_t>> bydepth(S.depth);
     for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
     for (int64_t d = 0; d < S.depth; ++d) {
       for (int ph = 0; ph < kPhases; ++ph) {
-        for (int64_t K : bydepth[d]) {
-          if (ph == 3 && is_tiny(K)) continue;
-          const int32_t b = phase_begin(H, K, ph), n = phase_count(H, K, ph);
-          for (int32_t q = 0; q < n; ++q) H.lvl_items.push_back(b + q);
+        // phase 1: the GEMM-1 tiles of nodes with a dense buffer form a launch of their own
+        for (int pass = 0; pass < (ph == 1 && per_level ? 2 : 1); ++pass) {
+          for (int64_t K : bydepth[d]) {
+            if (ph == 3 && is_tiny(K)) continue;
+            if (ph == 1 && per_level && (H.node_ykern[K] != 0) != (pass == 1)) continue;
+            const int32_t b = phase_begin(H, K, ph), n = phase_count(H, K, ph);
+            for (int32_t q = 0; q < n; ++q) H.lvl_items.push_back(b + q);
+          }
+          close(-1, pass == 1 ? LVL_YDENSE : LVL_ITEMS);
         }
-        close(-1);
       }
       const int32_t tiny_base = (int32_t)H.tiny.size();
       H.tiny_dptr[d] = tiny_base;
@@ -484,7 +533,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
         }
         if (pass == 0) H.tiny_dadj[d] = (int32_t)H.tiny.size();
       }
-      close(tiny_base);
+      close(tiny_base, LVL_TINY);
       if (d == top_depth && d + 1 < S.depth) H.lvl_top = (int32_t)H.lvl_ptr.size() - 1;
     }
     H.tiny_dptr[S.depth] = (int32_t)H.tiny.size();
@@ -500,6 +549,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     n.ldg = H.node_ldg[K];
     n.split = H.node_split[K];
     n.kchunk = H.node_kchunk[K];
+    n.defer2 = H.node_defer[K];
     n.off = H.node_off[K];
     n.rp = H.node_rowptr[K];
     n.goff = H.node_goff[K];
@@ -610,6 +660,46 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   }
   H.apos = S.apos;
   H.adiag = S.apos_diag;
+  // device factorization lists, deepest depth first
+  H.fac_nodes.clear();
+  H.fac_cn.clear();
+  H.fac_cw.clear();
+  H.fac_rb.clear();
+  H.fac_tiles.clear();
+  H.fac_lev.clear();
+  {
+    std::vector<std::vector<int64_t>> bydepth(S.depth);
+    for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
+    for (int64_t d = S.depth - 1; d >= 0; --d) {
+      FacLevel lv{};
+      lv.nodes_b = (int32_t)H.fac_nodes.size();
+      lv.narrow_b = (int32_t)H.fac_cn.size();
+      lv.wide_b = (int32_t)H.fac_cw.size();
+      lv.rb_b = (int32_t)H.fac_rb.size();
+      lv.tiles_b = (int32_t)H.fac_tiles.size();
+      for (int64_t K : bydepth[d]) {
+        const int32_t s = H.node_s[K], c = H.node_c[K];
+        H.fac_nodes.push_back((int32_t)K);
+        for (int32_t q = 0; q < (s + 15) / 16; ++q) (s <= 64 ? H.fac_cn : H.fac_cw).push_back(int2{(int32_t)K, q});
+        const int32_t nr = (c + kTileM - 1) / kTileM;
+        for (int32_t a = 0; a < nr; ++a) {
+          H.fac_rb.push_back(int2{(int32_t)K, a});
+          for (int32_t b = 0; b <= a; ++b) H.fac_tiles.push_back(int4{(int32_t)K, a, b, 0});
+        }
+      }
+      lv.nodes_n = (int32_t)H.fac_nodes.size() - lv.nodes_b;
+      lv.narrow_n = (int32_t)H.fac_cn.size() - lv.narrow_b;
+      lv.wide_n = (int32_t)H.fac_cw.size() - lv.wide_b;
+      lv.rb_n = (int32_t)H.fac_rb.size() - lv.rb_b;
+      lv.tiles_n = (int32_t)H.fac_tiles.size() - lv.tiles_b;
+      H.fac_lev.push_back(lv);
+    }
+  }
+  H.dpos.assign(S.n, 0);
+  for (int64_t K = 0; K < ns; ++K) {
+    const int64_t s = S.width(K), ld = s + S.nrows(K);
+    for (int64_t j = 0; j < s; ++j) H.dpos[S.xsuper[K] + j] = S.panel_off[K] + j * ld + j;
+  }
 
   // layout
   auto &o = H.off;
@@ -651,6 +741,12 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.apos = take(8 * (int64_t)H.apos.size());
   o.adiag = take((int64_t)H.adiag.size());
   o.bitems = take(16 * (int64_t)H.bitems.size());
+  o.fac_nodes = take(4 * (int64_t)H.fac_nodes.size());
+  o.fac_cn = take(8 * (int64_t)H.fac_cn.size());
+  o.fac_cw = take(8 * (int64_t)H.fac_cw.size());
+  o.fac_rb = take(8 * (int64_t)H.fac_rb.size());
+  o.fac_tiles = take(16 * (int64_t)H.fac_tiles.size());
+  o.dpos = take(8 * (int64_t)H.dpos.size());
   H.tables_bytes = p;
   o.plan = take((int64_t)sizeof(DevPlan));
   o.linv = take(scalar_bytes * batch * H.sq_elems);
@@ -670,6 +766,8 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.adj_t = take(sqb);
   o.adj_f = take(sqb);
   o.adj_d = take(sqb);
+  o.ferr = take(8 * batch);
+  o.fldet = take(16 * batch);
   o.end = p;
 }
 
@@ -693,7 +791,9 @@ struct selinv_ctx {
   const void *panels_at = nullptr, *dtilde_at = nullptr, *x_at = nullptr;
   std::vector<Item> bseq;            // adjoint launch sequence for selinv_items (built on demand)
   const void *ctrl_at = nullptr;     // control words of the last persistent launch (for selinv_sync)
+  void *devfac_work = nullptr;       // work buffer of a device factorization not yet checked by selinv_sync
   uint64_t serial = 0;               // unique per context (owner tag of the no-alloc work area)
+  std::string tune_path;             // copy of opts.tune_cache
   DevPlan plan_noalloc{};            // staging of the plan copy in the no-alloc work area
   void *uploaded_to = nullptr;       // work buffer holding the tables
   int device = -1;
@@ -800,6 +900,9 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.adj_f = H.adjoint ? (void *)(b + o.adj_f) : nullptr;
   d.adj_d = H.adjoint ? (void *)(b + o.adj_d) : nullptr;
   d.bitems = (Item *)(b + o.bitems);
+  d.dpos = (int64_t *)(b + o.dpos);
+  d.ferr = (unsigned long long *)(b + o.ferr);
+  d.fldet = (double *)(b + o.fldet);
   d.ctrl = (int32_t *)(b + o.ctrl);
   d.trace = (int64_t *)h->trace;
   return d;
@@ -807,6 +910,20 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
 
 const DevPlan *dev_plan(const selinv_ctx *h, void *work) {
   return reinterpret_cast<const DevPlan *>(static_cast<unsigned char *>(work) + h->H.off.plan);
+}
+
+FactorAux make_fac_aux(const selinv_ctx *h, void *work) {
+  const auto &H = h->H;
+  unsigned char *b = static_cast<unsigned char *>(work);
+  FactorAux a{};
+  a.nodes = (const int32_t *)(b + H.off.fac_nodes);
+  a.chunks_narrow = (const int2 *)(b + H.off.fac_cn);
+  a.chunks_wide = (const int2 *)(b + H.off.fac_cw);
+  a.rblocks = (const int2 *)(b + H.off.fac_rb);
+  a.tiles = (const int4 *)(b + H.off.fac_tiles);
+  a.lev = H.fac_lev.data();
+  a.nlev = (int32_t)H.fac_lev.size();
+  return a;
 }
 
 LaunchAux make_aux(const selinv_ctx *h, void *work) {
@@ -827,6 +944,7 @@ LaunchAux make_aux(const selinv_ctx *h, void *work) {
   a.lvl_recs = (const LRec *)(b + H.off.lvl_recs);
   a.lvl_ptr = H.lvl_ptr.data();
   a.lvl_tiny = H.lvl_tiny.data();
+  a.lvl_kind = H.lvl_kind.data();
   a.tiny = (const TinyRec *)(b + H.off.tiny);
   a.nlvl = (int32_t)H.lvl_ptr.size() - 1;
   a.blaunch = H.blaunch.data();
@@ -877,6 +995,12 @@ void build_image(selinv_ctx *h) {
   put(img, o.apos, H.apos);
   put(img, o.adiag, H.adiag);
   put(img, o.bitems, H.bitems);
+  put(img, o.fac_nodes, H.fac_nodes);
+  put(img, o.fac_cn, H.fac_cn);
+  put(img, o.fac_cw, H.fac_cw);
+  put(img, o.fac_rb, H.fac_rb);
+  put(img, o.fac_tiles, H.fac_tiles);
+  put(img, o.dpos, H.dpos);
 }
 
 selinv_status ensure_uploaded(selinv_ctx *h, void *work, hipStream_t st) {
@@ -962,7 +1086,12 @@ void selinv_default_opts(selinv_opts *o) {
   o->reserved = 0;
 }
 
-const char *selinv_version(void) { return "selinv-mi355x 0.1"; }
+const char *selinv_version(void) { return "selinv-mi355x 0.2"; }
+
+const char *selinv_tune_key(void) {
+  static const std::string key = std::string("arch=") + tune_arch() + " rocm=" + tune_rocm();
+  return key.c_str();
+}
 
 selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *rowind, const int64_t *perm,
                              const selinv_opts *opts, selinv_ctx **out) {
@@ -975,6 +1104,10 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *ro
     h->opts = *opts;
   else
     selinv_default_opts(&h->opts);
+  if (h->opts.tune_cache) {  // keep a copy: the caller's string is borrowed for the call only
+    h->tune_path = h->opts.tune_cache;
+    h->opts.tune_cache = h->tune_path.c_str();
+  }
   *out = h;
   const selinv_opts &o = h->opts;
   if (o.dtype != SELINV_R64 && o.dtype != SELINV_C128) return set_err(h, SELINV_EUNSUPPORTED, "unknown dtype");
@@ -987,7 +1120,10 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *ro
     const int64_t min_c = o.dense_min_c == 0 ? kDefaultDenseMinC : o.dense_min_c;
     const int64_t max_b = o.dense_max_bytes > 0 ? o.dense_max_bytes : kDefaultDenseMaxBytes;
     const int64_t split_k = o.split_min_k == 0 ? kSplitMinK : o.split_min_k;
-    build_plan(h->S, o.batch, h->sbytes(), min_c, max_b, split_k, o.sched == SELINV_SCHED_LEVELS, h->H);
+    TuneTable tt;
+    if (o.tune_cache && o.tune_cache[0]) tt = load_tune_table(o.tune_cache, h->is_complex() ? "c128" : "f64");
+    build_plan(h->S, o.batch, h->sbytes(), min_c, max_b, split_k, o.sched == SELINV_SCHED_LEVELS,
+               (o.tune_cache && o.tune_cache[0]) ? &tt : nullptr, h->H);
     if ((int64_t)h->H.items.size() * (int64_t)o.batch >= (int64_t)INT32_MAX)
       return set_err(h, SELINV_ENOMEM, "too many work items for int32 item ids");
     build_image(h);
@@ -1032,6 +1168,9 @@ selinv_status selinv_symbolic(const selinv_ctx *h, selinv_symbolic_view *v) {
   v->flops = S.flops * mul;
   v->flops_exact = S.flops_exact * mul;
   v->depth = S.depth;
+  int64_t tuned = 0;
+  for (int8_t t : h->H.node_tuned) tuned += t;
+  v->tuned_nodes = tuned;
   return SELINV_OK;
 }
 
@@ -1045,6 +1184,7 @@ selinv_status selinv_sizes(const selinv_ctx *h, selinv_sizes_t *s) {
   s->dtilde_bytes = align_up(B * h->H.sq_elems * sb);
   s->abar_bytes = align_up(B * h->S.nnzA * sb);
   s->trace_bytes = align_up(64 * B * (int64_t)h->H.items.size());
+  s->tables_bytes = h->H.tables_bytes;
   return SELINV_OK;
 }
 
@@ -1138,6 +1278,23 @@ selinv_status selinv_factor_host(selinv_ctx *h, const void *values, void *panels
     return set_err(h, SELINV_ENOMEM, "host allocation failed in factor");
   }
   h->have_logdet = true;
+  return SELINV_OK;
+}
+
+selinv_status selinv_factor_device(selinv_ctx *h, const void *values_dev, void *ldlt_dev, void *work_dev,
+                                   void *stream) {
+  if (!h) return SELINV_EINVAL;
+  if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
+  if (!values_dev || !ldlt_dev || !work_dev) return set_err(h, SELINV_EINVAL, "null buffer");
+  hipStream_t st = (hipStream_t)stream;
+  selinv_status ss = ensure_uploaded(h, work_dev, st);
+  if (ss != SELINV_OK) return ss;
+  h->have_logdet = false;
+  DevPlan pl = make_devplan(h, work_dev);
+  FactorAux fa = make_fac_aux(h, work_dev);
+  hipError_t e = launch_factor(pl, dev_plan(h, work_dev), fa, h->is_complex(), values_dev, ldlt_dev, st);
+  if (e != hipSuccess) return hip_err(h, e, "factor launch");
+  h->devfac_work = work_dev;
   return SELINV_OK;
 }
 
@@ -1457,6 +1614,20 @@ selinv_status selinv_sync(selinv_ctx *h, void *stream) {
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_err(h, e, "stream synchronize");
+  if (h->devfac_work) {  // pivots and log det of the last device factorization
+    const int64_t B = h->opts.batch;
+    const unsigned char *b = static_cast<const unsigned char *>(h->devfac_work);
+    std::vector<unsigned long long> ferr((size_t)B);
+    std::vector<double> ld((size_t)(2 * B));
+    e = hipMemcpy(ferr.data(), b + h->H.off.ferr, sizeof(unsigned long long) * B, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(ld.data(), b + h->H.off.fldet, sizeof(double) * 2 * B, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_err(h, e, "factor status readback");
+    h->devfac_work = nullptr;
+    for (int64_t l = 0; l < B; ++l)
+      if (ferr[l] != ~0ull) return set_err(h, SELINV_ESINGULAR, "zero or non-finite pivot", (int64_t)ferr[l], l);
+    h->logdet = ld;
+    h->have_logdet = true;
+  }
   if (h->ctrl_at && h->opts.sched == SELINV_SCHED_PERSISTENT) {
     int32_t ctrl[4] = {0, 0, 0, 0};
     e = hipMemcpy(ctrl, h->ctrl_at, sizeof(ctrl), hipMemcpyDeviceToHost);

@@ -49,6 +49,20 @@ struct Symbolic {
   int64_t nrows(int64_t K) const { return rowptr[K + 1] - rowptr[K]; }
 };
 
+// Tune table (tune.cpp): per node-size bucket, how a supernode's GEMM-1 runs.
+struct TuneEntry {
+  std::string arch, rocm, dtype;
+  int64_t s_max = 0, c_max = 0;
+  int dense = -1, ydense = -1, split_min_k = 0;  // -1: not given
+};
+struct TuneTable {
+  std::vector<TuneEntry> entries;  // those of this target, ROCm version and dtype
+  const TuneEntry *find(int64_t s, int64_t c) const;  // smallest bucket holding (s, c), or null
+};
+const char *tune_arch();
+std::string tune_rocm();
+TuneTable load_tune_table(const std::string &path, const std::string &dtype);  // throws Failure
+
 // Throws Failure on malformed input.
 void analyze(Symbolic &S, int64_t n, const int64_t *colptr, const int64_t *rowind, const int64_t *perm,
              int64_t cap, double relax);

@@ -39,6 +39,7 @@ __device__ __forceinline__ NodeInfo uniform(const NodeInfo &a) {
   n.ldg = uniform(a.ldg);
   n.split = uniform(a.split);
   n.kchunk = uniform(a.kchunk);
+  n.defer2 = uniform(a.defer2);
   n.off = uniform64(a.off);
   n.rp = uniform64(a.rp);
   n.goff = uniform64(a.goff);
@@ -57,7 +58,7 @@ __device__ __forceinline__ NodeInfo node_info(const DevPlan &pl, int K) {
   n.ldg = uniform(gp(pl.node_ldg)[K]);
   n.split = uniform(gp(pl.node_split)[K]);
   n.kchunk = uniform(gp(pl.node_kchunk)[K]);
-  n.pad0 = n.pad1 = 0;
+  n.defer2 = n.pad1 = 0;
   n.off = uniform64(gp(pl.node_off)[K]);
   n.rp = uniform64(gp(pl.node_rowptr)[K]);
   n.goff = uniform64(gp(pl.node_goff)[K]);
@@ -292,7 +293,7 @@ __device__ void do_ytile(const Ctx<T> &cx, const NodeInfo &nd, int a, int bp, do
   }
   if (nd.yoff < 0) {
     store_xtile<T, COH>(cx, nd, a, b, acc, smem);
-    gemm2_partial<T, COH>(cx, nd, a, b, acc, smem);
+    if (!uniform(nd.defer2)) gemm2_partial<T, COH>(cx, nd, a, b, acc, smem);
     return;
   }
   // partial tile of a node with an R phase: Ypart[part] (column-major c x s)
@@ -373,6 +374,87 @@ __device__ void do_rtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int br, do
   lds_barrier();
   if (r == 0) store_xtile<T, COH>(cx, nd, a, b, acc, smem);
   gemm2_partial<T, COH>(cx, nd, a, b, acc, smem, qb, qe);
+}
+
+// The GEMM-2 share of a tile whose GEMM-1 item stored Y = X_{C,K} (rows 64a..,
+// columns 64b..) without it: the tile is read back from X into the
+// accumulator layout (acc = -Y) and gemm2_partial computes 64-row blocks
+// [qb, qe) of P_a, with br = b | r << 16 | rq << 24 as for do_rtile.
+template <typename T, bool COH>
+__device__ void do_ptile(const Ctx<T> &cx, const NodeInfo &nd, int a, int br, double *smem) {
+  const int s = uniform(nd.s), c = uniform(nd.c), ld = s + c;
+  const int b = br & 0xffff, r = (br >> 16) & 0xff, rq = max(1, br >> 24);
+  const int nq = (s + 63) / 64, qb = uniform(r * nq / rq), qe = uniform((r + 1) * nq / rq);
+  const int i0 = a * 64, j0 = b * 64;
+  const T *Y = cx.Xp + nd.off + s;
+  constexpr int Q = 64 * 64 / NT;
+  T v[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int i = e & 63, j = e >> 6;
+    v[q] = Mem<COH>::ld(Y + (((int64_t)(j0 + j) * ld + i0 + i) & opaque_mask(i0 + i < c && j0 + j < s)));
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int e = threadIdx.x + NT * q;
+    const int i = e & 63, j = e >> 6;
+    lds_put<T>(smem, i, j, SOps<T>::scale(-1.0, masked(v[q], opaque_mask(i0 + i < c && j0 + j < s))));
+  }
+  lds_barrier();
+  constexpr int P = Planes<T>::P;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w & 1, wj = w >> 1;
+  Acc<T> acc;
+#pragma unroll
+  for (int p = 0; p < P; ++p)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+          const int i = 32 * wi + 16 * bi + 4 * vv + (lane >> 4);
+          const int j = 32 * wj + 16 * bj + (lane & 15);
+          acc.v[p][bi][bj][vv] = smem[p * 64 * PITCH + j * PITCH + i];
+        }
+  lds_barrier();
+  gemm2_partial<T, COH>(cx, nd, a, b, acc, smem, qb, qe);
+}
+
+// GEMM-1 tile of a node with a dense X_{C,C} buffer, without GEMM-2: the
+// level schedule runs these in k_ydense (fewer registers than the general
+// item kernel, two workgroups per CU).  The tile goes to X (nodes whose
+// GEMM-2 runs in ITEM_P items) or to the partial tiles of a split
+// contraction (summed by ITEM_R items).
+template <typename T>
+__device__ __forceinline__ void do_ytile_dense(const Ctx<T> &cx, const NodeInfo &nd, int a, int bp, double *smem) {
+  const int s = uniform(nd.s), c = uniform(nd.c), ld = s + c;
+  const int b = bp & 0xffff, part = bp >> 16;
+  const int kchunk = uniform(nd.kchunk);
+  const int kb = part * kchunk, ke = min(c, kb + kchunk);
+  const int i0 = a * 64, j0 = b * 64;
+  constexpr int TK = DenseTK<T>::TK;
+  const T *G = static_cast<const T *>(cx.Gp) + nd.goff;
+  LoadDenseA<T, TK> la{G, nd.ldg, c, ke, i0};
+  LoadDenseB<T, TK> lb{cx.Lp, nd.off, ld, s, ke, j0, s};
+  Acc<T> acc;
+  gemm_dense<T>(kb, ke, la, lb, smem, acc);
+  acc_to_lds<T>(acc, smem);
+  lds_barrier();
+  if (nd.yoff < 0) {  // Y = -acc into X_{C,K}
+    T *X = cx.Xp + nd.off + s;
+    for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+      const int i = e & 63, j = e >> 6;
+      if (i0 + i < c && j0 + j < s) gstore(X + (int64_t)(j0 + j) * ld + i0 + i, SOps<T>::scale(-1.0, lds_get<T>(smem, i, j)));
+    }
+  } else {  // partial tile Ypart[part] (column-major c x s)
+    T *Y = static_cast<T *>(cx.Yp) + nd.yoff + (int64_t)part * c * s;
+    for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+      const int i = e & 63, j = e >> 6;
+      if (i0 + i < c && j0 + j < s) gstore(Y + (int64_t)(j0 + j) * c + i0 + i, lds_get<T>(smem, i, j));
+    }
+  }
 }
 
 // Blocks (a, b) and (b, a), a >= b, of sym(Src - sum_r P_r) into Dst, where
@@ -846,6 +928,8 @@ __device__ __forceinline__ void do_item(const Ctx<T> &cx, const Item &item, cons
     do_ytile<T, COH>(cx, nd, it.a, it.b, smem, rt);
   } else if (it.type == ITEM_R) {
     do_rtile<T, COH>(cx, nd, it.a, it.b, smem);
+  } else if (it.type == ITEM_P) {
+    do_ptile<T, COH>(cx, nd, it.a, it.b, smem);
   } else if (it.type == ITEM_D) {
     do_dtile<T, COH>(cx, nd, it.a, it.b, smem);
   } else {  // ITEM_S: the whole node (c <= 64, s <= 64) in this workgroup

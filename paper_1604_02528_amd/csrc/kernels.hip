@@ -61,6 +61,36 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1) k_items_list(co
   }
 }
 
+// GEMM-1 tiles of nodes with a dense X_{C,C} buffer (see do_ytile_dense): no
+// GEMM-2 in this kernel, so it fits two workgroups per CU also for complex.
+template <typename T>
+__global__ void __launch_bounds__(NT, 2) k_ydense(const DevPlan *__restrict__ plp, const T *Lp, T *Xp, const LRec *recs,
+                                                  const int32_t *list, int32_t count, int32_t list_pos) {
+  const DevPlan &pl = *plp;
+  constexpr int kStages = 2 * dense_stage_doubles<T, DenseTK<T>::TK>();
+  __shared__ double smem[kStages > tile_doubles<T>() ? kStages : tile_doubles<T>()];
+  const int64_t g = blockIdx.x;
+  const int64_t l = g / count;
+  const int64_t q = g - l * count;
+  const int64_t t_start = pl.trace ? wall_clock64() : 0;
+  Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, nullptr,
+            static_cast<T *>(pl.gbuf) + l * pl.g_elems, static_cast<T *>(pl.ypart) + l * pl.y_elems};
+  const LRec rec = recs[q];
+  const Item it = uniform(rec.it);
+  do_ytile_dense<T>(cx, uniform(rec.nd), it.a, it.b, smem);
+  if (pl.trace) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t *tr = pl.trace + 8 * ((int64_t)list_pos * pl.batch + g);
+      tr[0] = l * pl.nitems + list[q];
+      tr[1] = blockIdx.x;
+      tr[2] = t_start;
+      tr[3] = t_start;
+      tr[4] = wall_clock64();
+    }
+  }
+}
+
 // Small nodes of one level, one wavefront each (see do_tiny).
 template <typename T>
 __global__ void __launch_bounds__(64) k_tiny(const DevPlan *__restrict__ plp, const T *Lp, T *Xp,
@@ -352,6 +382,7 @@ __global__ void __launch_bounds__(64) k_normalize_small(const DevPlan *__restric
   for (int u = 0; u < S * S / 64; ++u) {
     const int e = t + 64 * u, i = e % S, k = e / S;
     lk[i * SP + k] = (i < s && k < s) ? Q[(int64_t)k * ld + i] : zero_of<T>();
+    xs[i * SP + k] = zero_of<T>();  // the rows k >= s are read (times zero) by the Lhat loop below
   }
   __syncthreads();
   if (t < s) {  // column t of L_KK^{-1}, kept in LDS (only this lane touches it)
@@ -393,7 +424,7 @@ __global__ void __launch_bounds__(64) k_normalize_small(const DevPlan *__restric
         T v = zero_of<T>();
 #pragma unroll
         for (int k = 0; k < S; ++k)
-          if (k >= q) v += lr[k] * xs[k * SP + q];
+          if (k >= q && k < s) v += lr[k] * xs[k * SP + q];
         P[(int64_t)q * ld + s + i] = v;
       }
     }
@@ -606,6 +637,28 @@ static hipError_t normalize_impl(const DevPlan &pl, const DevPlan *dpl, const La
   return hipGetLastError();
 }
 
+// L_KK^{-1} and D_K^{-1} of the nodes of a chunk list (the device factorization).
+hipError_t launch_linv(const DevPlan &pl, const DevPlan *dpl, bool cplx_, const void *src, const int2 *chunks,
+                       int32_t n, bool narrow, hipStream_t st) {
+  const dim3 grid((unsigned)(n * pl.batch));
+  if (cplx_) {
+    if (narrow)
+      hipLaunchKernelGGL((k_normalize_inv<cplx, 64>), grid, dim3(NT), 0, st, dpl, reinterpret_cast<const cplx *>(src),
+                         chunks, n);
+    else
+      hipLaunchKernelGGL((k_normalize_inv<cplx, 256>), grid, dim3(NT), 0, st, dpl, reinterpret_cast<const cplx *>(src),
+                         chunks, n);
+  } else {
+    if (narrow)
+      hipLaunchKernelGGL((k_normalize_inv<double, 64>), grid, dim3(NT), 0, st, dpl,
+                         reinterpret_cast<const double *>(src), chunks, n);
+    else
+      hipLaunchKernelGGL((k_normalize_inv<double, 256>), grid, dim3(NT), 0, st, dpl,
+                         reinterpret_cast<const double *>(src), chunks, n);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_normalize(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, const void *src,
                             void *panels, void *dt, hipStream_t st, int part, int steps) {
   return cplx_ ? normalize_impl<cplx>(pl, dpl, aux, src, panels, dt, st, part, steps)
@@ -627,6 +680,9 @@ static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
       if (aux.lvl_tiny[q] >= 0)
         hipLaunchKernelGGL(k_tiny<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(64), 0, st, dpl, Lp, Xp,
                            aux.tiny + aux.lvl_tiny[q], e - b, b);
+      else if (aux.lvl_kind[q] == LVL_YDENSE)
+        hipLaunchKernelGGL(k_ydense<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp,
+                           aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
       else
         hipLaunchKernelGGL(k_items_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,
                            aux.lvl_recs + b, aux.lvl_items + b, e - b, b);

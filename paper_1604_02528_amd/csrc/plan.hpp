@@ -22,7 +22,13 @@
 //           with at least kDSlabRows row tiles split each block pair into
 //           64 / kDSlabW column slabs: b = block | (slab + 1) << 16.
 //   ITEM_S  (K): a node with c <= 64 and s <= 64 done by one workgroup.
-// Phases of a node: 0 = ITEM_G, 1 = ITEM_Y, 2 = ITEM_R, 3 = ITEM_D / ITEM_S
+//   ITEM_P  (K, a, b | r << 16 | rq << 24): the row tile's share of GEMM-2
+//           (step 4) for a node whose GEMM-1 tiles stored X_{C,K} directly and
+//           left GEMM-2 out (level schedule, nodes with a dense X_{C,C}
+//           buffer and an unsplit contraction: their GEMM-1 tiles then run in
+//           a kernel of their own with fewer registers, two workgroups per
+//           CU); the tile is read back from X.  rq as for ITEM_R.
+// Phases of a node: 0 = ITEM_G, 1 = ITEM_Y, 2 = ITEM_R / ITEM_P, 3 = ITEM_D / ITEM_S
 // (never empty).  A node's first non-empty phase becomes ready when its
 // parent's phase 3 is done (C(K) lies in the ancestors, Eq. (newset)); every
 // later phase becomes ready when the previous non-empty phase is done.
@@ -34,10 +40,10 @@
 
 namespace selinv {
 
-enum ItemType : int32_t { ITEM_Y = 0, ITEM_D = 1, ITEM_S = 2, ITEM_G = 3, ITEM_R = 4 };
+enum ItemType : int32_t { ITEM_Y = 0, ITEM_D = 1, ITEM_S = 2, ITEM_G = 3, ITEM_R = 4, ITEM_P = 5 };
 constexpr int kPhases = 4;
 __host__ __device__ constexpr int item_phase(int type) {
-  return type == ITEM_G ? 0 : type == ITEM_Y ? 1 : type == ITEM_R ? 2 : 3;
+  return type == ITEM_G ? 0 : type == ITEM_Y ? 1 : (type == ITEM_R || type == ITEM_P) ? 2 : 3;
 }
 
 // Work items of the adjoint (reverse) sweep, FP64; see adjoint.hip.  R1 runs
@@ -77,7 +83,7 @@ struct alignas(16) Item {
 // each item's record, so an item's first dependent load is its record alone.
 struct alignas(16) NodeInfo {
   int32_t K, s, c, ldg;      // node, width, |C(K)|, leading dimension of its dense X_{C,C} buffer
-  int32_t split, kchunk, pad0, pad1;  // GEMM-1 contraction parts and their length
+  int32_t split, kchunk, defer2, pad1;  // GEMM-1 contraction parts and their length; GEMM-2 in ITEM_P items
   int64_t off, rp, goff;     // panel offset, first row of C(K) in the row tables, dense buffer (-1: none)
   int64_t poff, yoff, pad2;  // GEMM-2 partial products, partial tiles of a split contraction
 };
@@ -146,6 +152,9 @@ struct DevPlan {
   void *adj_z, *adj_l, *adj_s;  // Zbar then M; Lhatbar then Lb; Sbar
   void *adj_t, *adj_f, *adj_d;  // Tbar; F; Dtbar0
   Item *bitems;        // adjoint work items
+  int64_t *dpos;       // [n] panel element of each pivot D_jj (one matrix)
+  unsigned long long *ferr;  // [batch] device factorization: first column with a bad pivot (~0: none)
+  double *fldet;       // [batch][2] device factorization: log det (re, im)
   int32_t *ctrl;       // CTRL_WORDS
   int64_t *trace;      // optional: per ticket {item id, workgroup, t_ticket, t_start, t_end, 0, 0, 0}
 };
@@ -166,6 +175,7 @@ struct LaunchAux {
   const LRec *lvl_recs;     // the same items' records with their nodes, in that order
   const int32_t *lvl_ptr;   // host array [nlvl + 1]
   const int32_t *lvl_tiny;  // host array [nlvl]: -1 (work items), else the first TinyRec of the range
+  const int32_t *lvl_kind;  // host array [nlvl]: LVL_ITEMS, LVL_TINY or LVL_YDENSE
   const TinyRec *tiny;      // single-wavefront node records, in launch order
   int32_t nlvl;
   const int4 *blaunch;        // host array: adjoint launches {kind, first, count, 0} in order; kind 0 =
@@ -177,6 +187,26 @@ struct LaunchAux {
   int32_t lvl_top;
   int32_t nsmall_top, nchunks_narrow_top, nchunks_top, nrblocks_top, nsq_tiles_top;
 };
+
+// Launches of the device factorization, one entry per etree depth (deepest
+// first): ranges of the lists in FactorAux.
+struct FacLevel {
+  int32_t nodes_b, nodes_n;    // nodes of the depth (diagonal-block factorization)
+  int32_t narrow_b, narrow_n;  // 16-column blocks of L_KK^{-1}, s <= 64
+  int32_t wide_b, wide_n;      // the same, s > 64
+  int32_t rb_b, rb_n;          // 64-row blocks of C(K) (L_{C,K})
+  int32_t tiles_b, tiles_n;    // lower 64 x 64 block pairs of C(K) x C(K) (Schur update)
+};
+struct FactorAux {
+  const int32_t *nodes;        // device lists
+  const int2 *chunks_narrow, *chunks_wide, *rblocks;
+  const int4 *tiles;
+  const FacLevel *lev;         // host array
+  int32_t nlev;
+};
+
+// Kernels of the level launches.
+enum LevelKind : int32_t { LVL_ITEMS = 0, LVL_TINY = 1, LVL_YDENSE = 2 };
 
 // Normalization steps, for launching them separately.
 enum NormSteps : int { NORM_INV = 1, NORM_GEMM = 2, NORM_SQ = 4, NORM_ALL = 7 };

@@ -27,7 +27,8 @@ def _bytes(nbytes, device):
 
 class SelInv:
     def __init__(self, n, colptr, rowind, perm=None, *, dtype="f64", batch=1, cap=256, relax=0.05,
-                 sched="levels", nthreads=0, watchdog_ms=0, dense_min_c=0, dense_max_bytes=0, split_min_k=0, device="cuda"):
+                 sched="levels", nthreads=0, watchdog_ms=0, dense_min_c=0, dense_max_bytes=0, split_min_k=0,
+                 tune_cache=None, device="cuda"):
         self.n = int(n)
         self.is_complex = dtype in ("c128", "complex128", torch.complex128)
         self.batch = int(batch)
@@ -43,6 +44,8 @@ class SelInv:
         o.dense_min_c = int(dense_min_c)
         o.dense_max_bytes = int(dense_max_bytes)
         o.split_min_k = int(split_min_k)
+        self._tune_path = None if tune_cache is None else str(tune_cache).encode()
+        o.tune_cache = self._tune_path
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         self._rowind = np.ascontiguousarray(rowind, dtype=np.int64)
         self._perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
@@ -70,6 +73,7 @@ class SelInv:
             "seg_start": arr(v.seg_start, int(v.nseg)), "seg_posoff": arr(v.seg_posoff, int(v.nseg)),
             "posarr": arr(v.posarr, int(v.nposarr)),
             "flops": float(v.flops), "flops_exact": float(v.flops_exact), "depth": int(v.depth),
+            "tuned_nodes": int(v.tuned_nodes),
         }
 
     # -- buffers -----------------------------------------------------------------
@@ -119,13 +123,36 @@ class SelInv:
         v = np.ascontiguousarray(np.asarray(values).reshape(self.batch, self.nnzA), dtype=dt)
         return v
 
-    def factor(self, values, want_dtilde=False):
+    def _values_device(self, values):
+        v = torch.as_tensor(values)
+        return v.to(device=self.device, dtype=self.scalar_dtype).reshape(self.batch, self.nnzA).contiguous()
+
+    def factor(self, values, want_dtilde=False, on_device=False):
+        """LDL^T of every matrix (host C++, or on the GPU with on_device=True),
+        then the normalization kernels into the panels."""
         self._alloc(want_dtilde)
-        v = self._values_host(values)
-        self._vals_keep = v
-        capi.selinv_factor(self.h, v, self._bufs["panels"], self._bufs["work"],
-                           self.dtilde if want_dtilde else None, _stream())
+        dt = self.dtilde if want_dtilde else None
+        if on_device:
+            v = self._values_device(values)
+            self._vals_keep = v
+            P, W = self._bufs["panels"], self._bufs["work"]
+            capi.selinv_factor_device(self.h, v, P, W, _stream())
+            capi.selinv_normalize(self.h, P, P, W, dt, _stream())
+        else:
+            v = self._values_host(values)
+            self._vals_keep = v
+            capi.selinv_factor(self.h, v, self._bufs["panels"], self._bufs["work"], dt, _stream())
         self.generation += 1
+
+    def factor_device(self, values, out=None):
+        """LDL^T panels of every matrix computed on the GPU ([batch, panel_elems]
+        device tensor; strict lower L_KK, D_K on the diagonal, L_{C,K} below)."""
+        self._alloc(False)
+        v = self._values_device(values)
+        if out is None:
+            out = torch.empty((self.batch, self.panel_elems), dtype=self.scalar_dtype, device=self.device)
+        capi.selinv_factor_device(self.h, v, out, self._bufs["work"], _stream())
+        return out
 
     def factor_host(self, values):
         """Host LDL^T panels only (numpy [batch, panel_elems])."""
@@ -177,6 +204,8 @@ class SelInv:
         return abar
 
     def logdet(self):
+        if self._bufs is not None:
+            self.sync()  # a device factorization reports its log det at the next sync
         out = np.zeros(self.batch * (2 if self.is_complex else 1))
         capi.selinv_logdet(self.h, out)
         if self.is_complex:

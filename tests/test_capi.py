@@ -275,7 +275,7 @@ def test_forward_items_cover_every_tile_once(name, scale):
     sym = S.symbolic()
     s_all = np.diff(sym["xsuper"]).astype(int)
     c_all = np.diff(sym["rowptr"]).astype(int)
-    ITEM_Y, ITEM_D, ITEM_S, ITEM_G, ITEM_R = 0, 1, 2, 3, 4
+    ITEM_Y, ITEM_D, ITEM_S, ITEM_G, ITEM_R, ITEM_P = 0, 1, 2, 3, 4, 5
     order = np.argsort(it[:, 0], kind="stable")
     bounds = np.searchsorted(it[order, 0], np.arange(len(s_all) + 1))
     n_rsplit = 0
@@ -292,7 +292,10 @@ def test_forward_items_cover_every_tile_once(name, scale):
         assert parts >= 1 and len(y) == nr * nb * parts
         keys = {(int(a), int(b) & 0xFFFF, int(b) >> 16) for _, _, a, b in y}
         assert keys == {(a, b, p) for a in range(nr) for b in range(nb) for p in range(parts)}
-        r = rows[types == ITEM_R]
+        r = rows[(types == ITEM_R) | (types == ITEM_P)]
+        assert not ((types == ITEM_R).any() and (types == ITEM_P).any())
+        if (types == ITEM_P).any():  # GEMM-2 deferred: dense buffer, unsplit
+            assert (types == ITEM_G).any() and parts == 1
         if len(r):
             rq = max(1, int(r[0, 3]) >> 24)
             nq = nb
@@ -309,3 +312,90 @@ def test_forward_items_cover_every_tile_once(name, scale):
         assert len(d) == nb * (nb + 1) // 2 * nsl
     if name == "C2":
         assert n_rsplit > 0  # the top separator chain cuts its GEMM-2 shares
+
+
+# --------------------------------------------------------------------------
+# tune tables (selinv_opts.tune_cache)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("choice", ["gather", "dense_fused", "dense_ydense"])
+def test_tune_table_choices_shape_the_plan(choice):
+    """A table forcing one choice on every bucket: 'gather' leaves no dense
+    X_{C,C} buffer (no G items); 'dense_fused' gives every node with c > 64 a
+    buffer and keeps GEMM-2 in the GEMM-1 tiles (no P items); 'dense_ydense'
+    moves the GEMM-2 of unsplit dense nodes into P items.  Every supernode is
+    covered by an entry."""
+    from tests._tune import forced_table, remove
+
+    w = workload("C2", 16)
+    path = forced_table(choice, "f64")
+    try:
+        S = _ctx(w, relax=0.05, tune_cache=path)
+        sym = S.symbolic()
+        it = capi_items(S)
+        assert sym["tuned_nodes"] == sym["nsuper"]
+        c_all = np.diff(sym["rowptr"])
+        types = it[:, 1]
+        dense_nodes = set(it[types == 3, 0].tolist())
+        big = {K for K in range(sym["nsuper"]) if c_all[K] > 64}
+        if choice == "gather":
+            assert not dense_nodes and not (types == 5).any()
+        else:
+            assert dense_nodes == big
+            assert (types == 5).any() == (choice == "dense_ydense")
+    finally:
+        remove(path)
+
+
+def capi_items(S):
+    from paper_1604_02528_amd import capi
+
+    return capi.selinv_items(S.h, 0)
+
+
+def test_tune_table_other_keys_are_ignored_and_split_follows_the_table():
+    from tests._tune import forced_table, remove
+
+    w = workload("C2", 16)
+    for kw in ({"arch": "gfx000"}, {"rocm": "0.0.0"}):
+        path = forced_table("gather", "f64", **kw)
+        try:
+            assert _ctx(w, relax=0.05, tune_cache=path).symbolic()["tuned_nodes"] == 0
+        finally:
+            remove(path)
+    path = forced_table("gather", "c128")  # another dtype
+    try:
+        assert _ctx(w, relax=0.05, tune_cache=path).symbolic()["tuned_nodes"] == 0
+    finally:
+        remove(path)
+    path = forced_table("dense_ydense", "f64", split_min_k=-1)  # never split
+    try:
+        it = capi_items(_ctx(w, relax=0.05, tune_cache=path))
+        y = it[it[:, 1] == 0]
+        assert (y[:, 3] >> 16 == 0).all()
+    finally:
+        remove(path)
+
+
+def test_malformed_tune_table_is_einval(tmp_path):
+    from paper_1604_02528_amd.capi import SelinvError
+
+    w = workload("C1")
+    cases = {"not_json.json": "{entries: [", "no_format.json": '{"entries": []}',
+             "bad_format.json": '{"format": "other", "entries": []}'}
+    for name, text in cases.items():
+        p = tmp_path / name
+        p.write_text(text)
+        with pytest.raises(SelinvError) as ei:
+            _ctx(w, tune_cache=str(p))
+        assert ei.value.status == 1, name
+    with pytest.raises(SelinvError) as ei:
+        _ctx(w, tune_cache=str(tmp_path / "missing.json"))
+    assert ei.value.status == 1
+
+
+def test_tune_key_names_this_build():
+    from paper_1604_02528_amd import capi
+
+    k = capi.selinv_tune_key()
+    assert k.startswith("arch=gfx950 rocm=")

@@ -50,7 +50,7 @@ def test_backward_matches_dense_gradient(name, scale, dense, relax, split):
     ref = adjoint.dense_abar(sym, w.values[0], W, w.colptr, w.rowind)
     err = maxrel(got, ref)
     print(f"  max-norm rel err {err:.3e}", flush=True)
-    assert err <= TOL
+    assert err <= TOL, f"{int(np.isnan(got).sum())} NaN of {got.size} entries (first at {np.flatnonzero(np.isnan(got))[:5]})"
 
 
 @pytest.mark.gpu

@@ -125,3 +125,35 @@ def test_normalize_matches_oracle_in_and_out_of_place(name, scale, batch, relax)
         err = maxrel(outplace[l], ref)
         print(f"  matrix {l}: max-norm rel err {err:.3e}", flush=True)
         assert err <= (1e-9 if w.is_complex else 1e-10)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("sched", ["levels", "persistent"])
+@pytest.mark.parametrize("choice", ["gather", "dense_fused", "dense_ydense"])
+@pytest.mark.parametrize("name,scale,batch,relax", [("C2", 20, None, 0.05), ("C3", 14, 2, 0.05), ("C5", 6, 2, 0.05),
+                                                    ("C4s", None, None, 0.0)])
+def test_every_tuned_variant_matches_oracle(name, scale, batch, relax, choice, sched):
+    """Every GEMM-1 variant the autotuner can choose, forced on all
+    supernodes by a tune table, against the oracle."""
+    from paper_1604_02528_amd import SelInv
+    from tests._tune import forced_table, remove
+
+    w = workload(name, scale, batch)
+    print(f"tuned variant {choice} case {name} scale={scale} batch={batch} sched={sched}", flush=True)
+    path = forced_table(choice, "c128" if w.is_complex else "f64")
+    try:
+        S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128" if w.is_complex else "f64", batch=w.batch,
+                   cap=w.cap, relax=relax, sched=sched, tune_cache=path)
+        assert S.symbolic()["tuned_nodes"] == S.symbolic()["nsuper"]
+        S.factor(w.values)
+        S.run()
+        S.sync()
+        X = S.to_host("x")
+        S.close()
+    finally:
+        remove(path)
+    ref = oracle_x(name, scale, batch, relax)
+    for l in range(w.batch):
+        err = maxrel(X[l], ref[l])
+        print(f"  matrix {l}: max-norm rel err {err:.3e}", flush=True)
+        assert err <= (1e-9 if w.is_complex else 1e-10)
