@@ -149,7 +149,8 @@ def factor_on_device(w, relax, sched, batch):
     from paper_1604_02528_amd import SelInv
 
     dt = "c128" if w.is_complex else "f64"
-    S1 = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=batch, cap=w.cap, relax=relax, sched=sched)
+    S1 = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=batch, cap=w.cap, relax=relax, sched=sched,
+                adjoint=False)
     vals = torch.from_numpy(np.ascontiguousarray(w.values[:batch])).to("cuda")
     out = S1.factor_device(vals)
     S1.sync()
@@ -171,7 +172,7 @@ def gpu_leg(w, relax, steps, warmup, sched="levels", batch=None, want_x=False):
     dt = "c128" if w.is_complex else "f64"
     t0 = time.perf_counter()
     S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=batch, cap=w.cap, relax=relax, sched=sched,
-               tune_cache=TUNE_TABLE)
+               tune_cache=TUNE_TABLE, adjoint=False)
     t_an = time.perf_counter() - t0
     ldlt, t_fac = factor_on_device(w, relax, sched, batch)
     S._alloc(False)
@@ -219,7 +220,7 @@ def batched_leg(relax, sched):
     from paper_1604_02528_amd import SelInv
 
     S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128", batch=1, cap=w.cap, relax=relax, sched=sched,
-               tune_cache=TUNE_TABLE)
+               tune_cache=TUNE_TABLE, adjoint=False)
     ldlt, _ = factor_on_device(w, relax, sched, 1)
     S._alloc(False)
     wall, _, _ = timed_steps(S, ldlt, 3 * w.batch, w.batch)
@@ -400,7 +401,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--relax", type=float, default=0.05)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline legs")
-    ap.add_argument("--sched", default="levels", choices=["persistent", "levels"])
+    ap.add_argument("--sched", default="levels", choices=["persistent", "levels", "push"])
     ap.add_argument("--workload", default="C5", choices=["C2", "C3", "C5"])
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with three 1 GiB device-to-device copies (reference for HBM byte counters)")
@@ -506,9 +507,12 @@ def main():
                      "traffic_unit": "HBM bytes per traversal (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, calibrated "
                                      "on a 1 GiB device copy)",
                      "algorithmic_bytes": algorithmic_bytes(w, args.relax),
-                     "kernel": ("k_items_list (one launch per etree level and phase) with k_tiny (the "
-                                "single-wavefront small nodes of each level)"
-                                if args.sched == "levels" else "k_persistent, one launch"),
+                     "kernel": {"levels": "k_ydense (GEMM-1 tiles of nodes with a dense X_{C,C} buffer), "
+                                          "k_items_list (the other items) and k_tiny (single-wavefront small "
+                                          "nodes), one launch per etree depth and phase",
+                                "persistent": "k_persistent, one launch",
+                                "push": "k_push (the O/I/ID tiles of the left-looking form) and k_items_list "
+                                        "(the D step), one launch per etree depth and step"}[args.sched],
                      "selinv_run_ms": round(t_run * 1e3, 4),
                      "note": "achieved = algorithmic flops of one traversal (all matrices of the batch) / "
                              "HIP-event time of selinv_run (all of its launches) on the launch stream"},

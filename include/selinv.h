@@ -67,7 +67,11 @@ typedef enum {
 typedef enum {
   SELINV_SCHED_PERSISTENT = 0, /* one launch; workgroups draw tickets of a topological order and wait on
                                   per-node dependency counters */
-  SELINV_SCHED_LEVELS = 1      /* one launch per etree depth and phase (the default: measured faster) */
+  SELINV_SCHED_LEVELS = 1,     /* one launch per etree depth and phase (the default: measured faster) */
+  SELINV_SCHED_PUSH = 2        /* the paper's left-looking form (Alg. 2): per etree depth, root first,
+                                  the depth's diagonal blocks (D), then every descendant's X_{C,I}
+                                  updated with the depth's blocks (the O, I and ID updates of
+                                  Eqs. (outerprod) and (innerprod)); measured against the pull form */
 } selinv_sched;
 
 typedef struct {
@@ -91,7 +95,9 @@ typedef struct {
                           the GPU splits its contraction over C(K) (0 = 320, < 0 = never split);
                           a quarter of it at etree depths whose tiles fill at most a quarter of
                           the GPU */
-  int32_t reserved;
+  int32_t adjoint;     /* 0 (default): the work area includes the adjoint's scratch (three panel-layout
+                          arrays and three s x s arrays per matrix), so that selinv_backward can run;
+                          < 0: left out (a smaller work area; selinv_backward returns EUNSUPPORTED) */
   const char *tune_cache; /* path of a tune table written by the autotuner (JSON, format
                              "selinv-tune-1"), or NULL.  Entries of this GPU target, ROCm version
                              and dtype choose, per bucket of supernode width s and |C(K)|, whether
@@ -296,12 +302,17 @@ selinv_status selinv_scatter(const selinv_ctx *h, const void *vals_dev, void *wo
 
 /*
  * selinv_backward -- adjoint of selected inversion (not in the paper; reverse
- * mode through Alg. 1 and the block LDL^T of Section 2.3).  FP64 only.
+ * mode through Alg. 1 and the block LDL^T of Section 2.3).  R64 and C128; for
+ * a complex-symmetric A the derivatives are holomorphic (plain transposes, no
+ * conjugation): abar = dloss/da of a loss that is a holomorphic function of
+ * the selected entries (a caller with a real loss of complex data conjugates
+ * its cotangents on the way in and the result on the way out).
  *   xbar_dev [batch][panel_elems] (panel layout): dloss/dx for the stored
  *     selected entries (top blocks: lower triangle incl. diagonal; the strict
  *     upper triangle of every top block is ignored).  Overwritten: used as the
  *     accumulator of the reverse sweep.
- *   wlogdet_dev [batch] (device) or NULL: dloss/d(log det A_l) for a loss that
+ *   wlogdet_dev [batch] scalars of the context's dtype (device) or NULL:
+ *     dloss/d(log det A_l) for a loss that
  *     also depends on the log-determinants (selinv_logdet).  Since
  *     d log det A / dA = A^{-1}, matrix l adds wlogdet[l] times its selected
  *     inverse on A's pattern (x2 off the diagonal) to abar.
@@ -312,8 +323,9 @@ selinv_status selinv_scatter(const selinv_ctx *h, const void *vals_dev, void *wo
  * given a dtilde_dev), and x_dev the buffer of a selinv_run (or
  * selinv_normalize_run) after it; SELINV_ESTATE otherwise.  Same work buffer.
  * Runs the level schedule (R1 leaves to root with FP64 atomic scatter-adds,
- * then R3 root to leaves); asynchronous on `stream`.  Errors: SELINV_ESTATE,
- * SELINV_EUNSUPPORTED (complex), SELINV_EINVAL (null buffer).
+ * one per real plane, then R3 root to leaves); asynchronous on `stream`.
+ * Errors: SELINV_ESTATE, SELINV_EUNSUPPORTED (context built with
+ * opts.adjoint < 0), SELINV_EINVAL (null buffer).
  */
 selinv_status selinv_backward(selinv_ctx *h, const void *panels_dev, const void *x_dev, const void *dtilde_dev,
                               void *xbar_dev, const void *wlogdet_dev, void *work_dev, void *abar_dev,

@@ -1,4 +1,5 @@
-"""torch.autograd binding of the selected inversion and its adjoint (FP64).
+"""torch.autograd binding of the selected inversion and its adjoint (float64 and
+complex128).
 
     S = SelInv(n, colptr, rowind, perm, batch=B)
     x, logdet = SelInvFunction.apply(values, S)   # values [B, nnz(A)], requires_grad
@@ -13,6 +14,12 @@ reverse sweep (selinv_backward), which also adds the log-det term
 d log det A / dA = A^{-1}; no arithmetic happens here.  S holds the buffers of
 the last forward call: a backward whose forward is no longer the latest
 factorization of S raises instead of differentiating the wrong matrix.
+
+For complex-symmetric A the library's adjoint is the holomorphic one (plain
+transposes).  torch passes conjugate cotangents (dL/d conj(y) of a real loss L)
+and expects them back for the input, so the binding conjugates gx and glogdet
+on the way in and the result on the way out: for a holomorphic map with
+Jacobian J that is exactly J^H g.
 """
 
 from __future__ import annotations
@@ -25,12 +32,10 @@ from .selinv import SelInv
 class SelInvFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, values, S: SelInv):
-        if S.is_complex:
-            raise NotImplementedError("the autograd binding is implemented for float64 only")
         S.factor(values.detach(), want_dtilde=True)
         S.run()
         x = S.extract()
-        logdet = torch.as_tensor(S.logdet(), dtype=torch.float64, device=x.device)
+        logdet = torch.as_tensor(S.logdet(), dtype=S.scalar_dtype, device=x.device)
         ctx.S = S
         ctx.generation = S.generation
         ctx.in_device = values.device
@@ -43,8 +48,13 @@ class SelInvFunction(torch.autograd.Function):
             raise RuntimeError("SelInvFunction.backward: S was factored again after this forward call; "
                                "run each forward's backward before the next forward on the same SelInv")
         if gx is None:
-            gx = torch.zeros((S.batch, S.nnzA), dtype=torch.float64, device=S.device)
+            gx = torch.zeros((S.batch, S.nnzA), dtype=S.scalar_dtype, device=S.device)
+        wl = glogdet
+        if S.is_complex:
+            gx = gx.conj().resolve_conj()
+            wl = None if wl is None else wl.conj().resolve_conj()
         xbar = S.scatter(gx.contiguous())
-        wl = None if glogdet is None else glogdet.contiguous()
-        abar = S.backward(xbar, wl)
+        abar = S.backward(xbar, None if wl is None else wl.contiguous())
+        if S.is_complex:
+            abar = abar.conj().resolve_conj()
         return abar.to(ctx.in_device), None

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libselinv.so")
 
 SELINV_R64, SELINV_C128 = 0, 1
-SCHED_PERSISTENT, SCHED_LEVELS = 0, 1
+SCHED_PERSISTENT, SCHED_LEVELS, SCHED_PUSH = 0, 1, 2
 STATUS = {0: "OK", 1: "EINVAL", 2: "EPATTERN", 3: "ESINGULAR", 4: "ENOMEM", 5: "EDEVICE", 6: "ESTATE",
           7: "EUNSUPPORTED"}
 
@@ -34,7 +34,7 @@ class Opts(C.Structure):
     _fields_ = [("max_super", C.c_int32), ("dtype", C.c_int32), ("batch", C.c_int32), ("sched", C.c_int32),
                 ("relax", C.c_double), ("nthreads", C.c_int32), ("dense_min_c", C.c_int32),
                 ("watchdog_ms", C.c_int64), ("dense_max_bytes", C.c_int64), ("split_min_k", C.c_int32),
-                ("reserved", C.c_int32), ("tune_cache", C.c_char_p)]
+                ("adjoint", C.c_int32), ("tune_cache", C.c_char_p)]
 
 
 _P64 = C.POINTER(C.c_int64)

@@ -26,7 +26,7 @@ hipError_t launch_run(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &au
                       const void *panels, void *x, int64_t budget_ticks, int grid, hipStream_t st, int q0, int q1);
 hipError_t launch_extract(const DevPlan &pl, const DevPlan *dpl, bool cplx_, const void *x, void *out, hipStream_t st);
 int persistent_blocks_per_cu(bool cplx_);
-hipError_t launch_backward(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const void *panels,
+hipError_t launch_backward(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx, const void *panels,
                            const void *x, const void *dt, void *xbar, const void *wlogdet, void *abar, hipStream_t st);
 hipError_t launch_scatter(const DevPlan &pl, const DevPlan *dpl, bool cplx_, const void *vals, void *panel,
                           hipStream_t st);
@@ -66,7 +66,7 @@ struct HostPlan {
   std::vector<int4> blaunch;   // adjoint launches in order (see LaunchAux)
   std::vector<int32_t> tiny_dptr;  // [depth + 1] small-node records of each etree depth
   std::vector<int32_t> tiny_dadj;  // [depth] end of each depth's c <= kTinyC prefix (the adjoint's)
-  bool adjoint = false;        // adjoint scratch allocated (FP64 only)
+  bool adjoint = false;        // adjoint scratch allocated (opts.adjoint >= 0)
   std::vector<int32_t> lvl_items, lvl_ptr, lvl_tiny, lvl_kind;
   std::vector<int32_t> node_defer;  // GEMM-2 of the node in ITEM_P items (level schedule, dense buffer, unsplit)
   std::vector<int32_t> node_ykern;  // GEMM-1 tiles in k_ydense (level schedule, dense buffer)
@@ -75,6 +75,7 @@ struct HostPlan {
   int32_t norm_top[5] = {0, 0, 0, 0, 0};  // their normalization entries: small, narrow, chunks, rblocks, sq
   std::vector<LRec> lvl_recs;  // the items of lvl_items with their nodes, in level order
   std::vector<TinyRec> tiny;  // single-wavefront nodes, in launch order
+  std::vector<PushRec> push;  // push-form tiles (SELINV_SCHED_PUSH), in launch order
   std::vector<uint32_t> toff;  // their X_{C,C} tables (byte offsets into the panel array)
   std::vector<int2> chunks, chunks_narrow, rblocks;
   std::vector<int32_t> small_nodes;  // normalized by the single-wavefront kernel
@@ -94,7 +95,7 @@ struct HostPlan {
     int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
         nph, node_split, node_kchunk, node_yoff, node_goff, node_ldg, node_parent, order, lvl_items, lvl_recs, chunks, chunks_narrow, rblocks, small_nodes,
         sq_tiles, tiny, toff,
-        apos, adiag, bitems, fac_nodes, fac_cn, fac_cw, fac_rb, fac_tiles, dpos, plan, linv, dinv, part, gbuf, ypart,
+        apos, adiag, bitems, pushrecs, fac_nodes, fac_cn, fac_cw, fac_rb, fac_tiles, dpos, plan, linv, dinv, part, gbuf, ypart,
         cnt, ctrl, fwd_end, adj_z, adj_l, adj_s, adj_t, adj_f, adj_d, ferr, fldet, end;
   } off{};
   int64_t tables_bytes = 0;  // [0, tables_bytes) is uploaded once
@@ -291,8 +292,18 @@ void choose_dense(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_
 }
 
 void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t dense_min_c, int64_t dense_max_bytes,
-                int64_t split_min_k, bool per_level, const TuneTable *tt, HostPlan &H) {
+                int64_t split_min_k, int sched, const TuneTable *tt, bool adjoint, HostPlan &H) {
   const int64_t ns = S.nsuper();
+  // the push form (Alg. 2) runs one launch per depth and step like the level
+  // schedule; its GEMM-1 work is done by push tiles, so no node gets a dense
+  // buffer, a split contraction, a single-item or a single-wavefront path
+  const bool push = sched == SELINV_SCHED_PUSH;
+  const bool per_level = sched != SELINV_SCHED_PERSISTENT;
+  if (push) {
+    dense_min_c = -1;
+    split_min_k = -1;
+    tt = nullptr;
+  }
   // per-node choices from the tune table (bucket of (s, c)), else the defaults
   std::vector<int8_t> dense_pref(ns, -1), ykern_pref(ns, -1);
   std::vector<int64_t> node_mink(ns, split_min_k);
@@ -363,7 +374,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     // at a depth with few tiles, also takes the R phase (one part): its
     // tiles' GEMM-2 shares are then cut into R items instead of running
     // block after block at the end of each GEMM-1 tile.
-    if (parts <= 1 && !(nq > 1 && dtiles[S.sdepth[K]] * nq <= kSplitTarget)) continue;
+    if (parts <= 1 && (push || !(nq > 1 && dtiles[S.sdepth[K]] * nq <= kSplitTarget))) continue;
     H.node_split[K] = (int32_t)parts;
     H.node_kchunk[K] = (int32_t)chunk;
     H.node_yoff[K] = H.y_elems;
@@ -404,7 +415,9 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   // shares move to ITEM_P items of phase 2.
   H.node_defer.assign(ns, 0);
   H.node_ykern.assign(ns, 0);
-  if (per_level)
+  if (push)
+    for (int64_t K = 0; K < ns; ++K) H.node_defer[K] = S.nrows(K) > 0;
+  if (per_level && !push)
     for (int64_t K = 0; K < ns; ++K)
       if (H.node_goff[K] >= 0 && ykern_pref[K] != 0 && !(S.nrows(K) <= kSmallC && S.width(K) <= kSmallS)) {
         H.node_ykern[K] = 1;
@@ -429,16 +442,18 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
         for (int32_t b = 0; b <= a; ++b) H.items.push_back(Item{(int32_t)K, ITEM_G, a, b});
       nph(0, K) = nr * (nr + 1) / 2;
     }
-    if (c <= kSmallC && s <= kSmallS) {
+    if (c <= kSmallC && s <= kSmallS && !push) {
       H.items.push_back(Item{(int32_t)K, ITEM_S, 0, 0});
       nph(3, K) = 1;
       continue;
     }
     if (c > 0) {
-      for (int32_t p = 0; p < parts; ++p)
-        for (int32_t b = 0; b < nb; ++b)
-          for (int32_t a = 0; a < nr; ++a) H.items.push_back(Item{(int32_t)K, ITEM_Y, a, b | (p << 16)});
-      nph(1, K) = nr * nb * parts;
+      if (!push) {
+        for (int32_t p = 0; p < parts; ++p)
+          for (int32_t b = 0; b < nb; ++b)
+            for (int32_t a = 0; a < nr; ++a) H.items.push_back(Item{(int32_t)K, ITEM_Y, a, b | (p << 16)});
+        nph(1, K) = nr * nb * parts;
+      }
       if (H.node_yoff[K] >= 0 || H.node_defer[K]) {  // partial tiles summed by R items, or GEMM-2 by P items
         const int32_t type = H.node_defer[K] ? ITEM_P : ITEM_R;
         const int64_t nq = (s + kTileN - 1) / kTileN;
@@ -484,8 +499,53 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   // small nodes address X through 32-bit byte offsets
   const bool tiny_ok = S.panel_elems * scalar_bytes < (int64_t(1) << 32);
   const int64_t tiny_cf = scalar_bytes == 8 ? kTinyCF : kTinyC;
-  auto adj_tiny = [&](int64_t K) { return tiny_ok && H.node_c[K] <= kTinyC && H.node_s[K] <= kTinyS; };
-  {
+  auto adj_tiny = [&](int64_t K) { return !push && tiny_ok && H.node_c[K] <= kTinyC && H.node_s[K] <= kTinyS; };
+  H.push.clear();
+  if (push) {
+    // per depth, root first: the D step of the depth's nodes (P items, then
+    // D items), then every tile its nodes push into their descendants
+    std::vector<std::vector<int64_t>> bydepth(S.depth);
+    for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
+    std::vector<std::vector<int64_t>> segs_of(ns);  // segments (of descendants) owned by K
+    for (int64_t I = 0; I < ns; ++I)
+      for (int64_t g = S.seg_ptr[I]; g < S.seg_ptr[I + 1]; ++g) segs_of[S.seg_super[g]].push_back(g);
+    std::vector<int64_t> seg_node(S.seg_super.size());
+    for (int64_t I = 0; I < ns; ++I)
+      for (int64_t g = S.seg_ptr[I]; g < S.seg_ptr[I + 1]; ++g) seg_node[g] = I;
+    auto close_items = [&]() {
+      if ((int32_t)H.lvl_items.size() > H.lvl_ptr.back()) {
+        H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
+        H.lvl_tiny.push_back(-1);
+        H.lvl_kind.push_back(LVL_ITEMS);
+      }
+    };
+    for (int64_t d = 0; d < S.depth; ++d) {
+      for (int ph = 2; ph <= 3; ++ph) {
+        for (int64_t K : bydepth[d]) {
+          const int32_t b = phase_begin(H, K, ph), n = phase_count(H, K, ph);
+          for (int32_t q = 0; q < n; ++q) H.lvl_items.push_back(b + q);
+        }
+        close_items();
+      }
+      const int32_t first = (int32_t)H.push.size();
+      for (int64_t K : bydepth[d])
+        for (int64_t g : segs_of[K]) {
+          const int64_t I = seg_node[g];
+          const int32_t cI = H.node_c[I], sI = H.node_s[I];
+          const int32_t st = (int32_t)S.seg_start[g];
+          const int32_t en = (g + 1 < S.seg_ptr[I + 1]) ? (int32_t)S.seg_start[g + 1] : cI;
+          for (int32_t i0 = st; i0 < cI; i0 += kTileM)
+            for (int32_t x0 = 0; x0 < sI; x0 += kTileN)
+              H.push.push_back(PushRec{(int32_t)I, i0, x0, st, en, i0 >= en ? en : cI, 0, 0});
+        }
+      for (int32_t q = first; q < (int32_t)H.push.size(); ++q) H.lvl_items.push_back(q);
+      if ((int32_t)H.push.size() > first) {
+        H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
+        H.lvl_tiny.push_back(first);
+        H.lvl_kind.push_back(LVL_PUSH);
+      }
+    }
+  } else {
     auto is_tiny = [&](int64_t K) { return tiny_ok && H.node_c[K] <= tiny_cf && H.node_s[K] <= kTinyS; };
     auto close = [&](int32_t tiny_base, int32_t kind) {
       if ((int32_t)H.lvl_items.size() > H.lvl_ptr.back()) {
@@ -540,6 +600,11 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   }
   H.lvl_recs.resize(H.lvl_items.size());
   for (size_t q = 0; q < H.lvl_items.size(); ++q) {
+    if (push && H.lvl_kind[std::upper_bound(H.lvl_ptr.begin(), H.lvl_ptr.end(), (int32_t)q) - H.lvl_ptr.begin() - 1] ==
+                    LVL_PUSH) {
+      H.lvl_recs[q] = LRec{};  // push tiles carry their own records
+      continue;
+    }
     const Item &it = H.items[H.lvl_items[q]];
     const int64_t K = it.K;
     NodeInfo n{};
@@ -741,6 +806,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.apos = take(8 * (int64_t)H.apos.size());
   o.adiag = take((int64_t)H.adiag.size());
   o.bitems = take(16 * (int64_t)H.bitems.size());
+  o.pushrecs = take((int64_t)sizeof(PushRec) * (int64_t)H.push.size());
   o.fac_nodes = take(4 * (int64_t)H.fac_nodes.size());
   o.fac_cn = take(8 * (int64_t)H.fac_cn.size());
   o.fac_cw = take(8 * (int64_t)H.fac_cw.size());
@@ -757,7 +823,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.cnt = take(4 * kPhases * batch * ns);
   o.ctrl = take(4 * CTRL_WORDS);
   o.fwd_end = p;  // the forward path (normalize, run) touches [0, fwd_end) only
-  H.adjoint = scalar_bytes == 8;
+  H.adjoint = adjoint;
   const int64_t pan = H.adjoint ? scalar_bytes * batch * S.panel_elems : 0;
   const int64_t sqb = H.adjoint ? scalar_bytes * batch * H.sq_elems : 0;
   o.adj_z = take(pan);
@@ -945,6 +1011,7 @@ LaunchAux make_aux(const selinv_ctx *h, void *work) {
   a.lvl_ptr = H.lvl_ptr.data();
   a.lvl_tiny = H.lvl_tiny.data();
   a.lvl_kind = H.lvl_kind.data();
+  a.push = (const PushRec *)(b + H.off.pushrecs);
   a.tiny = (const TinyRec *)(b + H.off.tiny);
   a.nlvl = (int32_t)H.lvl_ptr.size() - 1;
   a.blaunch = H.blaunch.data();
@@ -995,6 +1062,7 @@ void build_image(selinv_ctx *h) {
   put(img, o.apos, H.apos);
   put(img, o.adiag, H.adiag);
   put(img, o.bitems, H.bitems);
+  put(img, o.pushrecs, H.push);
   put(img, o.fac_nodes, H.fac_nodes);
   put(img, o.fac_cn, H.fac_cn);
   put(img, o.fac_cw, H.fac_cw);
@@ -1083,7 +1151,7 @@ void selinv_default_opts(selinv_opts *o) {
   o->watchdog_ms = 0;
   o->dense_max_bytes = 0;
   o->split_min_k = 0;
-  o->reserved = 0;
+  o->adjoint = 0;
 }
 
 const char *selinv_version(void) { return "selinv-mi355x 0.2"; }
@@ -1113,7 +1181,7 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *ro
   if (o.dtype != SELINV_R64 && o.dtype != SELINV_C128) return set_err(h, SELINV_EUNSUPPORTED, "unknown dtype");
   if (o.batch < 1) return set_err(h, SELINV_EINVAL, "batch must be >= 1");
   if (o.max_super < 1 || o.max_super > 256) return set_err(h, SELINV_EINVAL, "max_super must be in [1, 256]");
-  if (o.sched != SELINV_SCHED_PERSISTENT && o.sched != SELINV_SCHED_LEVELS)
+  if (o.sched != SELINV_SCHED_PERSISTENT && o.sched != SELINV_SCHED_LEVELS && o.sched != SELINV_SCHED_PUSH)
     return set_err(h, SELINV_EINVAL, "unknown schedule");
   try {
     analyze(h->S, n, colptr, rowind, perm, o.max_super, o.relax);
@@ -1122,8 +1190,8 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *ro
     const int64_t split_k = o.split_min_k == 0 ? kSplitMinK : o.split_min_k;
     TuneTable tt;
     if (o.tune_cache && o.tune_cache[0]) tt = load_tune_table(o.tune_cache, h->is_complex() ? "c128" : "f64");
-    build_plan(h->S, o.batch, h->sbytes(), min_c, max_b, split_k, o.sched == SELINV_SCHED_LEVELS,
-               (o.tune_cache && o.tune_cache[0]) ? &tt : nullptr, h->H);
+    build_plan(h->S, o.batch, h->sbytes(), min_c, max_b, split_k, o.sched,
+               (o.tune_cache && o.tune_cache[0]) ? &tt : nullptr, o.adjoint >= 0, h->H);
     if ((int64_t)h->H.items.size() * (int64_t)o.batch >= (int64_t)INT32_MAX)
       return set_err(h, SELINV_ENOMEM, "too many work items for int32 item ids");
     build_image(h);
@@ -1183,7 +1251,7 @@ selinv_status selinv_sizes(const selinv_ctx *h, selinv_sizes_t *s) {
   s->work_bytes = h->H.off.end;
   s->dtilde_bytes = align_up(B * h->H.sq_elems * sb);
   s->abar_bytes = align_up(B * h->S.nnzA * sb);
-  s->trace_bytes = align_up(64 * B * (int64_t)h->H.items.size());
+  s->trace_bytes = align_up(64 * B * (int64_t)std::max(h->H.items.size(), h->H.lvl_items.size()));
   s->tables_bytes = h->H.tables_bytes;
   return SELINV_OK;
 }
@@ -1485,7 +1553,9 @@ selinv_status selinv_backward(selinv_ctx *h, const void *panels_dev, const void 
                               void *stream) {
   if (!h) return SELINV_EINVAL;
   if (!h->factored) return set_err(h, SELINV_ESTATE, "selinv_backward before a successful selinv_factor");
-  if (h->is_complex()) return set_err(h, SELINV_EUNSUPPORTED, "the adjoint is implemented for R64 only");
+  if (!h->H.adjoint)
+    return set_err(h, SELINV_EUNSUPPORTED, "selinv_backward: the work area was sized without the adjoint's scratch "
+                                           "(opts.adjoint < 0)");
   if (!panels_dev || !x_dev || !dtilde_dev || !xbar_dev || !work_dev || !abar_dev)
     return set_err(h, SELINV_EINVAL, "null buffer");
   if (h->dtilde_gen != h->gen || dtilde_dev != h->dtilde_at)
@@ -1501,8 +1571,8 @@ selinv_status selinv_backward(selinv_ctx *h, const void *panels_dev, const void 
   if (ss != SELINV_OK) return ss;
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
-  hipError_t e = launch_backward(pl, dev_plan(h, work_dev), aux, panels_dev, x_dev, dtilde_dev, xbar_dev, wlogdet_dev,
-                                 abar_dev, st);
+  hipError_t e = launch_backward(pl, dev_plan(h, work_dev), aux, h->is_complex(), panels_dev, x_dev, dtilde_dev,
+                                 xbar_dev, wlogdet_dev, abar_dev, st);
   if (e != hipSuccess) return hip_err(h, e, "backward launch");
   return SELINV_OK;
 }

@@ -91,6 +91,71 @@ __global__ void __launch_bounds__(NT, 2) k_ydense(const DevPlan *__restrict__ pl
   }
 }
 
+// Push-form tiles of one etree depth (see PushRec): a gathered GEMM-1 tile
+// over the ancestor's share of X_{C(I),C(I)}, subtracted from X_{C(I),I}.
+// No two tiles of a launch touch the same entries: the ancestors of I form a
+// chain, so one depth holds at most one of them, and its tiles of I cover
+// distinct rows and columns.
+template <typename T>
+__global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
+    k_push(const DevPlan *__restrict__ plp, const T *Lp, T *Xp, const PushRec *recs, int32_t count, int32_t list_pos) {
+  const DevPlan &pl = *plp;
+  __shared__ double smem[smem_doubles<T>()];
+  __shared__ int64_t rt[128];
+  const int64_t g = blockIdx.x;
+  const int64_t l = g / count;
+  const int64_t q = g - l * count;
+  const int64_t t_start = pl.trace ? wall_clock64() : 0;
+  const PushRec r = recs[q];
+  const int I = uniform(r.I), i0 = uniform(r.i0), x0 = uniform(r.x0), st = uniform(r.st);
+  const int en = uniform(r.en), kend = uniform(r.kend);
+  const NodeInfo nd = node_info(pl, I);
+  const int s = nd.s, c = nd.c, ld = s + c;
+  const T *L = Lp + l * pl.panel_elems;
+  T *X = Xp + l * pl.panel_elems;
+  if (threadIdx.x < 64) {
+    const int ig = i0 + threadIdx.x;
+    rt[threadIdx.x] = gp(pl.kcol)[nd.rp + (ig < c ? ig : 0)];
+    rt[64 + threadIdx.x] = gp(pl.kpos)[nd.rp + (ig < c ? ig : 0)];
+  }
+  lds_barrier();
+  LoadGatherSeg<T, false> la;
+  la.X = X;
+  la.kcol = pl.kcol + nd.rp;
+  la.kpos = pl.kpos + nd.rp;
+  la.posarr = pl.posarr;
+  la.rt_col = rt;
+  la.rt_pos = rt + 64;
+  la.c = c;
+  la.kend = kend;
+  la.i0 = i0;
+  la.en = en;
+  LoadPanelK<T, false> lb{L, nd.off, ld, s, 0, kend, x0, s};
+  Acc<T> acc;
+  gemm_tile<T>(st, kend, la, lb, smem, acc);
+  acc_to_lds<T>(acc, smem);
+  lds_barrier();
+  T *Y = X + nd.off + s;
+  for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+    const int i = e & 63, j = e >> 6;
+    if (i0 + i < c && x0 + j < s) {
+      T *p = Y + (int64_t)(x0 + j) * ld + i0 + i;
+      gstore(p, gload(p) - lds_get<T>(smem, i, j));
+    }
+  }
+  if (pl.trace) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t *tr = pl.trace + 8 * ((int64_t)list_pos * pl.batch + g);
+      tr[0] = -1 - q;  // push tiles are not items: the row names the record
+      tr[1] = blockIdx.x;
+      tr[2] = t_start;
+      tr[3] = t_start;
+      tr[4] = wall_clock64();
+    }
+  }
+}
+
 // Small nodes of one level, one wavefront each (see do_tiny).
 template <typename T>
 __global__ void __launch_bounds__(64) k_tiny(const DevPlan *__restrict__ plp, const T *Lp, T *Xp,
@@ -673,13 +738,22 @@ static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
   const T *Lp = reinterpret_cast<const T *>(panels);
   T *Xp = reinterpret_cast<T *>(x);
   T *Pp = reinterpret_cast<T *>(pl.part);
-  if (sched == 1) {
+  if (sched == 2 && q0 == 0) {  // the push form accumulates into X: start from zero
+    const int64_t total = pl.batch * pl.panel_elems;
+    unsigned gz = (unsigned)((total + 255) / 256);
+    if (gz > 65536u) gz = 65536u;
+    hipLaunchKernelGGL(k_zero<T>, dim3(gz ? gz : 1), dim3(256), 0, st, dpl, Xp);
+  }
+  if (sched == 1 || sched == 2) {
     for (int q = q0; q < q1; ++q) {
       const int32_t b = aux.lvl_ptr[q], e = aux.lvl_ptr[q + 1];
       if (e <= b) continue;
-      if (aux.lvl_tiny[q] >= 0)
+      if (aux.lvl_kind[q] == LVL_TINY)
         hipLaunchKernelGGL(k_tiny<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(64), 0, st, dpl, Lp, Xp,
                            aux.tiny + aux.lvl_tiny[q], e - b, b);
+      else if (aux.lvl_kind[q] == LVL_PUSH)
+        hipLaunchKernelGGL(k_push<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp,
+                           aux.push + aux.lvl_tiny[q], e - b, b);
       else if (aux.lvl_kind[q] == LVL_YDENSE)
         hipLaunchKernelGGL(k_ydense<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp,
                            aux.lvl_recs + b, aux.lvl_items + b, e - b, b);

@@ -46,7 +46,7 @@ __host__ __device__ constexpr int item_phase(int type) {
   return type == ITEM_G ? 0 : type == ITEM_Y ? 1 : (type == ITEM_R || type == ITEM_P) ? 2 : 3;
 }
 
-// Work items of the adjoint (reverse) sweep, FP64; see adjoint.hip.  R1 runs
+// Work items of the adjoint (reverse) sweep; see adjoint.hip.  R1 runs
 // leaves -> root, R3 root -> leaves; each is listed by etree depth and phase.
 enum BackItemType : int32_t {
   BI_T = 0,   // R1 phase 0: Tbar = sym(Xbar_KK) from the stored lower triangle
@@ -148,7 +148,8 @@ struct DevPlan {
   int64_t y_elems;
   int32_t *cnt;        // [kPhases][batch][ns] outstanding items of each phase
   // adjoint scratch, [batch][panel_elems] each (panel layout) and
-  // [batch][sq_elems] each (s x s per node, column-major); null for complex
+  // [batch][sq_elems] each (s x s per node, column-major); null when the work area
+  // was sized without them
   void *adj_z, *adj_l, *adj_s;  // Zbar then M; Lhatbar then Lb; Sbar
   void *adj_t, *adj_f, *adj_d;  // Tbar; F; Dtbar0
   Item *bitems;        // adjoint work items
@@ -157,6 +158,22 @@ struct DevPlan {
   double *fldet;       // [batch][2] device factorization: log det (re, im)
   int32_t *ctrl;       // CTRL_WORDS
   int64_t *trace;      // optional: per ticket {item id, workgroup, t_ticket, t_start, t_end, 0, 0, 0}
+};
+
+// Kernels of the level launches.
+enum LevelKind : int32_t { LVL_ITEMS = 0, LVL_TINY = 1, LVL_YDENSE = 2, LVL_PUSH = 3 };
+
+// A tile of the left-looking (push) form, Alg. 2: supernode K pushes into the
+// X panel of a descendant I (K owns rows C(I)[st, en) of I's row set).  The
+// tile covers rows i0 .. i0 + 63 (C(I)-local, i0 >= st) and columns
+// x0 .. x0 + 63 of X_{C(I), I}, and subtracts
+//   sum over k in [st, kend) with min(i, k) < en of X_{C(I),C(I)}(i, k) Lhat_I(k, x),
+// the O (i >= en), I and ID (i < en) updates of Eqs. (outerprod) and
+// (innerprod); every X_{C(I),C(I)}(i, k) it reads lies in K's X panel.
+// kend = en when the tile lies below R_K, else c(I).
+struct alignas(16) PushRec {
+  int32_t I, i0, x0, st;
+  int32_t en, kend, pad0, pad1;
 };
 
 // Host-side launch lists (device pointers into the work buffer, except lvl_ptr).
@@ -175,7 +192,8 @@ struct LaunchAux {
   const LRec *lvl_recs;     // the same items' records with their nodes, in that order
   const int32_t *lvl_ptr;   // host array [nlvl + 1]
   const int32_t *lvl_tiny;  // host array [nlvl]: -1 (work items), else the first TinyRec of the range
-  const int32_t *lvl_kind;  // host array [nlvl]: LVL_ITEMS, LVL_TINY or LVL_YDENSE
+  const int32_t *lvl_kind;  // host array [nlvl]: LVL_ITEMS, LVL_TINY, LVL_YDENSE or LVL_PUSH
+  const PushRec *push;      // push-form tiles (LVL_PUSH launches start at lvl_tiny[q])
   const TinyRec *tiny;      // single-wavefront node records, in launch order
   int32_t nlvl;
   const int4 *blaunch;        // host array: adjoint launches {kind, first, count, 0} in order; kind 0 =
@@ -204,9 +222,6 @@ struct FactorAux {
   const FacLevel *lev;         // host array
   int32_t nlev;
 };
-
-// Kernels of the level launches.
-enum LevelKind : int32_t { LVL_ITEMS = 0, LVL_TINY = 1, LVL_YDENSE = 2 };
 
 // Normalization steps, for launching them separately.
 enum NormSteps : int { NORM_INV = 1, NORM_GEMM = 2, NORM_SQ = 4, NORM_ALL = 7 };

@@ -434,6 +434,22 @@ template <typename T, bool COH> struct LoadGather {
   }
 };
 
+// LoadGather restricted to the terms one ancestor owns (the push form of
+// Alg. 2): X_{C,C}(i, k) counts only when min(i, k) < en, i.e. when column
+// min(i, k) of X_{C,C} lies in the owner's columns (rows and contraction
+// indices start at the owner's first row st).  Loads stay at the base
+// loader's (valid) addresses; the extra terms are zeroed where the stage is
+// stored to LDS.
+template <typename T, bool COH> struct LoadGatherSeg : LoadGather<T, COH> {
+  int en;
+  __device__ __forceinline__ int64_t mask(int k0, int m) const {
+    int i, kk;
+    this->coords(k0, m, i, kk);
+    const int ig = this->i0 + i, kg = k0 + kk;
+    return opaque_mask(ig < this->c && kg < this->kend && min(ig, kg) < en);
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Dense operands (no index chain): the node's X_{C,C} buffer and the panel.
 // ---------------------------------------------------------------------------

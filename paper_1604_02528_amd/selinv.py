@@ -28,7 +28,7 @@ def _bytes(nbytes, device):
 class SelInv:
     def __init__(self, n, colptr, rowind, perm=None, *, dtype="f64", batch=1, cap=256, relax=0.05,
                  sched="levels", nthreads=0, watchdog_ms=0, dense_min_c=0, dense_max_bytes=0, split_min_k=0,
-                 tune_cache=None, device="cuda"):
+                 tune_cache=None, adjoint=True, device="cuda"):
         self.n = int(n)
         self.is_complex = dtype in ("c128", "complex128", torch.complex128)
         self.batch = int(batch)
@@ -37,7 +37,7 @@ class SelInv:
         o.max_super = int(cap)
         o.dtype = capi.SELINV_C128 if self.is_complex else capi.SELINV_R64
         o.batch = self.batch
-        o.sched = capi.SCHED_LEVELS if sched == "levels" else capi.SCHED_PERSISTENT
+        o.sched = {"levels": capi.SCHED_LEVELS, "persistent": capi.SCHED_PERSISTENT, "push": capi.SCHED_PUSH}[sched]
         o.relax = float(relax)
         o.nthreads = int(nthreads)
         o.watchdog_ms = int(watchdog_ms)
@@ -46,6 +46,7 @@ class SelInv:
         o.split_min_k = int(split_min_k)
         self._tune_path = None if tune_cache is None else str(tune_cache).encode()
         o.tune_cache = self._tune_path
+        o.adjoint = 0 if adjoint else -1
         self._colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         self._rowind = np.ascontiguousarray(rowind, dtype=np.int64)
         self._perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
@@ -192,11 +193,13 @@ class SelInv:
         return out
 
     def backward(self, xbar, wlogdet=None, abar=None):
-        """Adjoint (FP64): xbar [batch, panel_elems] device tensor, dloss/dx for the
+        """Adjoint: xbar [batch, panel_elems] device tensor, dloss/dx for the
         stored selected entries (overwritten); wlogdet: None or a [batch] device
-        tensor, dloss/d(log det A_l); returns dloss/da on A's pattern
-        [batch, nnz(A)].  Needs factor(..., want_dtilde=True) and run() first
-        (the library returns ESTATE otherwise)."""
+        tensor of the scalar dtype, dloss/d(log det A_l); returns dloss/da on A's
+        pattern [batch, nnz(A)].  For complex-symmetric A these are holomorphic
+        derivatives (plain transposes, no conjugation).  Needs
+        factor(..., want_dtilde=True) and run() first (the library returns
+        ESTATE otherwise) and a context built with adjoint=True."""
         if abar is None:
             abar = torch.empty((self.batch, self.nnzA), dtype=self.scalar_dtype, device=self.device)
         capi.selinv_backward(self.h, self._bufs["panels"], self._bufs["x"], self.dtilde, xbar, wlogdet,

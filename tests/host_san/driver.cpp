@@ -28,8 +28,10 @@ hipError_t launch_extract(const DevPlan &, const DevPlan *, bool, const void *, 
   return hipErrorNotSupported;
 }
 int persistent_blocks_per_cu(bool) { return 1; }
-hipError_t launch_backward(const DevPlan &, const DevPlan *, const LaunchAux &, const void *, const void *, const void *,
-                           void *, const void *, void *, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_backward(const DevPlan &, const DevPlan *, const LaunchAux &, bool, const void *, const void *,
+                           const void *, void *, const void *, void *, hipStream_t) {
+  return hipErrorNotSupported;
+}
 hipError_t launch_scatter(const DevPlan &, const DevPlan *, bool, const void *, void *, hipStream_t) {
   return hipErrorNotSupported;
 }

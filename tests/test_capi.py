@@ -253,6 +253,26 @@ def test_absurd_batch_is_enomem_and_unknown_dtype_unsupported():
     assert ei.value.status == 7
 
 
+def test_adjoint_scratch_is_optional():
+    """opts.adjoint < 0 leaves the adjoint's three panel-layout and three
+    s x s arrays per matrix out of the work area; nothing before them moves
+    (the forward path's part of the work area is the same)."""
+    from paper_1604_02528_amd import SelInv
+
+    for name, scale, dt in [("C1", None, "f64"), ("C3", 8, "c128")]:
+        w = workload(name, scale)
+        sb = 16 if dt == "c128" else 8
+        a = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=w.batch, device="cpu")
+        b = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=w.batch, device="cpu", adjoint=False)
+        assert a.sizes.tables_bytes == b.sizes.tables_bytes
+        extra = a.sizes.work_bytes - b.sizes.work_bytes
+        pan = sb * w.batch * a.panel_elems
+        sq = int(a.sizes.dtilde_bytes)  # the Dt blocks: batch * sum of s^2 scalars, padded
+        assert 3 * pan + 2 * sq < extra <= 3 * pan + 3 * sq + 6 * 256
+        a.close()
+        b.close()
+
+
 def test_default_options_are_the_measured_fastest():
     from paper_1604_02528_amd import capi
 

@@ -21,10 +21,10 @@ def random_w(sym, seed):
     return [rng.standard_normal((sym.width(K) + sym.rows[K].shape[0], sym.width(K))) for K in range(sym.nsuper)]
 
 
-def gpu_abar(w, relax, W_panels, sym, dense=0, split=0):
+def gpu_abar(w, relax, W_panels, sym, dense=0, split=0, sched="levels"):
     from paper_1604_02528_amd import SelInv
 
-    S = SelInv(w.n, w.colptr, w.rowind, w.perm, batch=1, cap=w.cap, relax=relax, sched="levels",
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, batch=1, cap=w.cap, relax=relax, sched=sched,
                dense_min_c=dense, split_min_k=split)
     S.factor(w.values, want_dtilde=True)
     S.run()
@@ -192,6 +192,13 @@ def test_backward_state_checks():
     again = S.backward(xbar())
     S.sync()
     assert torch.equal(ok, again) or maxrel(again.cpu().numpy(), ok.cpu().numpy()) < 1e-13
+    # a context built without the adjoint's scratch refuses (EUNSUPPORTED)
+    S2 = SelInv(w.n, w.colptr, w.rowind, w.perm, batch=1, cap=w.cap, relax=0.05, adjoint=False)
+    S2.factor(w.values, want_dtilde=True)
+    S2.run()
+    with pytest.raises(capi.SelinvError) as ei:
+        S2.backward(xbar())
+    assert ei.value.status == 7
 
 
 @pytest.mark.gpu
@@ -208,3 +215,150 @@ def test_autograd_refuses_a_stale_forward():
         x1.sum().backward()
     x2.sum().backward()
     assert torch.isfinite(v2.grad).all()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,scale", [("C4s", None), ("C2", 12)])
+def test_backward_after_push_schedule(name, scale):
+    """The adjoint of a context whose forward runs the push form (its plan has
+    no dense buffers and no single-wavefront nodes)."""
+    w = workload(name, scale, None)
+    sym = oracle_sym(name, scale, None, 0.05)
+    W = random_w(sym, 13)
+    got = gpu_abar(w, 0.05, W, sym, sched="push")
+    ref = adjoint.dense_abar(sym, w.values[0], W, w.colptr, w.rowind)
+    err = maxrel(got, ref)
+    print(f"adjoint after push {name}: max-norm rel err {err:.3e}", flush=True)
+    assert err <= TOL
+
+
+# ---------------------------------------------------------------------------
+# complex128 (complex-symmetric A): holomorphic adjoint
+# ---------------------------------------------------------------------------
+
+def random_w_complex(sym, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for K in range(sym.nsuper):
+        shape = (sym.width(K) + sym.rows[K].shape[0], sym.width(K))
+        out.append(rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+    return out
+
+
+def complex_tol(sym, vals):
+    """1e-9 relative for a well-conditioned shift, growing with cond(A) / 100
+    (G = -X W_s X carries the conditioning of X twice, the reverse sweep's
+    rounding once per solve-like step)."""
+    cond = np.linalg.cond(selinv.permuted_dense(sym, vals))
+    return 1e-9 * max(1.0, cond / 100.0), cond
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,scale,batch,relax,dense,split", [
+    ("C3", 8, 3, 0.0, 0, 0), ("C3", 8, 3, 0.05, 0, 64), ("C3", 12, 2, 0.0, 65, 0), ("C3", 12, 2, 0.05, 0, 0),
+    ("C5", 8, 2, 0.0, 0, 0), ("C5", 10, 2, 0.05, 65, 64)],
+    ids=["C3_8", "C3_8_split", "C3_12_dense", "C3_12", "C5_8", "C5_10_dense_split"])
+def test_complex_backward_matches_dense_gradient(name, scale, batch, relax, dense, split):
+    """A batch of complex-symmetric shifts, each matrix with its own random
+    complex W: selinv_backward against the dense definition G = -X W_s X
+    (plain transposes) for every matrix of the batch."""
+    from paper_1604_02528_amd import SelInv
+
+    w = workload(name, scale, batch)
+    print(f"complex adjoint case {name} scale={scale} batch={batch} relax={relax} dense={dense} split={split}",
+          flush=True)
+    sym = oracle_sym(name, scale, batch, relax)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128", batch=w.batch, cap=w.cap, relax=relax,
+               sched="levels", dense_min_c=dense, split_min_k=split)
+    S.factor(w.values, want_dtilde=True)
+    S.run()
+    idx = torch.from_numpy(S.packed_index())
+    Ws = [random_w_complex(sym, 20 + l) for l in range(w.batch)]
+    xbar = torch.zeros((w.batch, S.panel_elems), dtype=torch.complex128)
+    for l in range(w.batch):
+        xbar[l, idx] = torch.from_numpy(selinv.flatten(sym, Ws[l]))
+    abar = S.backward(xbar.to("cuda"))
+    S.sync()
+    got = abar.cpu().numpy()
+    for l in range(w.batch):
+        ref = adjoint.dense_abar(sym, w.values[l], Ws[l], w.colptr, w.rowind)
+        err = maxrel(got[l], ref)
+        tol, cond = complex_tol(sym, w.values[l])
+        print(f"  matrix {l}: cond {cond:.3g}, max-norm rel err {err:.3e} (tol {tol:.1e})", flush=True)
+        assert err <= tol, f"{int(np.isnan(got[l]).sum())} NaN of {got[l].size} entries"
+
+
+@pytest.mark.gpu
+def test_complex_backward_logdet_weights():
+    """wlogdet of the complex dtype: abar gains wlogdet[l] X_l on A's pattern
+    (x2 off the diagonal), d log det A / dA = A^{-1}."""
+    from paper_1604_02528_amd import SelInv
+
+    w = workload("C3", 10, 2)
+    print("complex adjoint case C3 scale=10 batch=2 with log-det weights", flush=True)
+    sym = oracle_sym("C3", 10, 2, 0.0)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128", batch=2, cap=w.cap, relax=0.0)
+    S.factor(w.values, want_dtilde=True)
+    S.run()
+    idx = torch.from_numpy(S.packed_index())
+    Ws = [random_w_complex(sym, 40 + l) for l in range(2)]
+    xbar = torch.zeros((2, S.panel_elems), dtype=torch.complex128)
+    for l in range(2):
+        xbar[l, idx] = torch.from_numpy(selinv.flatten(sym, Ws[l]))
+    wl = np.array([0.7 - 0.2j, -1.3 + 0.5j])
+    abar = S.backward(xbar.to("cuda"), wlogdet=torch.from_numpy(wl).to("cuda"))
+    S.sync()
+    got = abar.cpu().numpy()
+    for l in range(2):
+        Xd = np.linalg.inv(selinv.permuted_dense(sym, w.values[l]))
+        ref = adjoint.dense_abar(sym, w.values[l], Ws[l], w.colptr, w.rowind) + \
+            wl[l] * adjoint.g_on_pattern_of_A(sym, Xd, w.colptr, w.rowind)
+        err = maxrel(got[l], ref)
+        tol, cond = complex_tol(sym, w.values[l])
+        print(f"  matrix {l}: max-norm rel err {err:.3e} (tol {tol:.1e})", flush=True)
+        assert err <= tol
+
+
+@pytest.mark.gpu
+def test_complex_autograd_vs_torch_dense_autograd():
+    """torch.autograd through SelInvFunction with complex128 values and a real
+    loss mixing real and imaginary parts of selected entries and of log det,
+    against torch's own autograd of a dense complex inverse and slogdet on
+    the CPU (an independent route: torch's conjugate-Wirtinger convention
+    on both sides)."""
+    from paper_1604_02528_amd import SelInv, SelInvFunction
+
+    w = workload("C3", 8, 2)
+    print("complex autograd case C3 scale=8 batch=2", flush=True)
+    rng = np.random.default_rng(9)
+    c = rng.standard_normal(w.n)
+    d = rng.standard_normal(len(w.rowind))
+    diag = np.asarray(w.colptr[:-1], dtype=np.int64)
+
+    def loss_of(x, logdet):
+        return (torch.as_tensor(c, device=x.device) * x[:, diag]).sum().real + \
+            (torch.as_tensor(d, device=x.device) * x).sum().imag + (0.5 * logdet.real - 0.25 * logdet.imag).sum()
+
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128", batch=2, cap=w.cap, sched="levels")
+    vals = torch.from_numpy(np.ascontiguousarray(w.values)).to("cuda").requires_grad_(True)
+    x, logdet = SelInvFunction.apply(vals, S)
+    loss_of(x, logdet).backward()
+    got = vals.grad.cpu().numpy()
+
+    v = torch.from_numpy(np.ascontiguousarray(w.values)).requires_grad_(True)
+    cols = torch.from_numpy(np.repeat(np.arange(w.n), np.diff(w.colptr)))
+    rows = torch.from_numpy(np.asarray(w.rowind, dtype=np.int64))
+    xs, lds = [], []
+    for l in range(2):
+        A = torch.zeros((w.n, w.n), dtype=torch.complex128).index_put((rows, cols), v[l])
+        A = A + A.T - torch.diag(torch.diagonal(A))
+        Xd = torch.linalg.inv(A)
+        xs.append(Xd[rows, cols])
+        sign, labs = torch.linalg.slogdet(A)
+        lds.append(torch.log(sign) + labs)
+    ref_loss = loss_of(torch.stack(xs), torch.stack(lds))
+    ref_loss.backward()
+    ref = v.grad.numpy()
+    err = maxrel(got, ref)
+    print(f"  max-norm rel err {err:.3e}", flush=True)
+    assert err <= 1e-9

@@ -332,3 +332,23 @@ def test_c5_full_size_slot_equals_single_shift_run(c5_full, l):
     assert err <= 1e-13
     S1.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", EDGE)
+def test_edge_cases_push_schedule(name):
+    from paper_1604_02528_amd import SelInv
+
+    w = _edge(name)
+    print(f"edge case {name} n={w.n} sched=push", flush=True)
+    sym = symbolic.analyze(w.n, w.colptr, w.rowind, w.perm, cap=w.cap, relax=0.0)
+    ref = _dense_panels(sym, np.linalg.inv(selinv.permuted_dense(sym, w.values[0])))
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128" if w.is_complex else "f64", batch=1, cap=w.cap,
+               relax=0.0, sched="push")
+    S.factor(w.values)
+    S.run()
+    S.sync()
+    err = maxrel(S.to_host("x")[0], ref)
+    print(f"  max-norm rel err {err:.3e}", flush=True)
+    assert err <= (1e-9 if w.is_complex else 1e-10)
+    S.close()

@@ -157,3 +157,29 @@ def test_every_tuned_variant_matches_oracle(name, scale, batch, relax, choice, s
         err = maxrel(X[l], ref[l])
         print(f"  matrix {l}: max-norm rel err {err:.3e}", flush=True)
         assert err <= (1e-9 if w.is_complex else 1e-10)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,scale,batch,relax", CASES + [("C2", 20, None, 0.0)])
+def test_push_schedule_matches_oracle(name, scale, batch, relax):
+    """The paper's left-looking form (Alg. 2: per depth the D step, then the
+    O / I / ID pushes into the descendants) against the oracle's Alg. 1."""
+    from paper_1604_02528_amd import SelInv
+
+    w = workload(name, scale, batch)
+    print(f"push case {name} scale={scale} batch={batch} relax={relax}", flush=True)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128" if w.is_complex else "f64", batch=w.batch,
+               cap=w.cap, relax=relax, sched="push")
+    S.factor(w.values)
+    S.run()
+    S.sync()
+    X = S.to_host("x")
+    ref = oracle_x(name, scale, batch, relax)
+    for l in range(w.batch):
+        err = maxrel(X[l], ref[l])
+        print(f"  matrix {l}: max-norm rel err {err:.3e}", flush=True)
+        assert err <= (1e-9 if w.is_complex else 1e-10)
+    S.run()  # a second traversal starts again from zero
+    S.sync()
+    assert np.array_equal(S.to_host("x"), X)
+    S.close()

@@ -144,3 +144,76 @@ def test_c4s_gradient_vs_dense_gradient():
     a, b = edges[:, 0], edges[:, 1]
     ref = np.exp(wlog) * (G[a, a] + G[b, b] - 2 * G[a, b])
     assert np.max(np.abs(ref - g_w)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def _complex_setup(scale=5, relax=0.0, shift=0):
+    """A small complex-symmetric shifted matrix H - z S of the C3 family."""
+    w = config("C3", scale=scale, batch=4)
+    vals = np.asarray(w.values[shift])
+    sym = symbolic.analyze(w.n, w.colptr, w.rowind, w.perm, relax=relax, cap=24)
+    return w, sym, vals
+
+
+def _stored_lower_w(sym, rng):
+    """Random complex stored-value gradients (top blocks: lower triangle only)."""
+    W = []
+    for K in range(sym.nsuper):
+        s = sym.width(K)
+        P = rng.standard_normal((s + sym.rows[K].shape[0], s)) + 1j * rng.standard_normal(
+            (s + sym.rows[K].shape[0], s))
+        P[:s, :] = np.tril(P[:s, :])
+        W.append(P)
+    return W
+
+
+def _bilinear_loss(sym, vals, W):
+    """loss(a) = sum over the stored selected entries of W * x (no conjugation:
+    a holomorphic function of A's values), through the oracle's forward path."""
+    P = factor.factor(sym, vals)
+    lh, dt = factor.normalize(sym, P)
+    X = selinv.alg1(sym, lh, dt)
+    tot = 0.0 + 0.0j
+    for K in range(sym.nsuper):
+        s = sym.width(K)
+        tot += np.sum(W[K][:s, :] * np.tril(X[K][:s, :])) + np.sum(W[K][s:, :] * X[K][s:, :])
+    return tot
+
+
+def test_complex_dense_abar_vs_finite_differences_real_and_imaginary():
+    """Complex-symmetric A: the dense definition G = -X W_s X (plain
+    transposes) is the holomorphic derivative of a bilinear loss in the
+    selected entries.  Central differences of the oracle's forward path along
+    a real step h and along an imaginary step i h of single stored values must
+    both equal it (a holomorphic function has one complex derivative in every
+    direction); a conjugated X or W_s fails the imaginary direction."""
+    w, sym, vals = _complex_setup()
+    rng = np.random.default_rng(11)
+    W = _stored_lower_w(sym, rng)
+    g = adjoint.dense_abar(sym, vals, W, w.colptr, w.rowind)
+    h = 1e-6
+    cols = np.repeat(np.arange(w.n), np.diff(w.colptr))
+    picks = list(rng.choice(len(vals), size=6, replace=False))
+    picks += [int(np.flatnonzero(w.rowind == cols)[0])]  # a diagonal value too
+    for e in picks:
+        for step in (h, 1j * h):
+            vp, vm = vals.copy(), vals.copy()
+            vp[e] += step
+            vm[e] -= step
+            fd = (_bilinear_loss(sym, vp, W) - _bilinear_loss(sym, vm, W)) / (2 * step)
+            assert abs(fd - g[e]) <= 1e-6 * max(1.0, abs(g[e])), (e, step, fd, g[e])
+
+
+@pytest.mark.parametrize("relax", [0.0, 0.1])
+def test_complex_reverse_sweep_matches_dense(relax):
+    """The node-by-node reverse sweep in complex arithmetic against the dense
+    definition, with random complex W on every stored entry."""
+    w, sym, vals = _complex_setup(scale=6, relax=relax, shift=2)
+    P = factor.factor(sym, vals)
+    lh, dt = factor.normalize(sym, P)
+    X = selinv.alg1(sym, lh, dt)
+    W = _stored_lower_w(sym, np.random.default_rng(5))
+    g_dense = adjoint.dense_abar(sym, vals, W, w.colptr, w.rowind)
+    S = adjoint.reverse_mode(sym, lh, dt, factor.dtilde(sym, P), X, W)
+    g_rev = adjoint.abar_from_sbar(sym, S, w.colptr, w.rowind)
+    assert np.iscomplexobj(g_rev)
+    assert np.max(np.abs(g_rev - g_dense)) / np.max(np.abs(g_dense)) < 1e-12
