@@ -63,20 +63,49 @@ def tune_table_path():
     return p if os.path.exists(p) else None
 
 
-def measured_traffic(workload, sched):
-    """HBM bytes per traversal from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE record of this workload (scaled by a 1 GiB copy), or None when
-    there is none or the kernel sources have changed since it was taken."""
+KERNEL_SOURCES = [
+    "paper_1604_02528_amd/csrc/kernels.hip",
+    "paper_1604_02528_amd/csrc/items.hpp",
+    "paper_1604_02528_amd/csrc/tile.hpp",
+    "paper_1604_02528_amd/csrc/plan.hpp",
+    "paper_1604_02528_amd/csrc/scalar.hpp",
+]
+
+
+def source_sha256(files):
     import hashlib
 
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def plan_sha256(S):
+    """Fingerprint of a context's forward plan: its work items and its level
+    launches (kind, size, item type, depth), as the library lists them."""
+    import hashlib
+
+    from paper_1604_02528_amd import capi
+
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(capi.selinv_items(S.h, 0)).tobytes())
+    h.update(np.ascontiguousarray(capi.selinv_items(S.h, 2)).tobytes())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, sched, plan_sha):
+    """HBM bytes per traversal from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record of this workload (scaled by a 1 GiB copy), or None when
+    there is none, or when the kernel sources or the plan (work items and
+    launches) differ from those the record was taken on."""
     rec_path = TRAFFIC_RECORDS.get(workload)
     if sched != "levels" or rec_path is None or not os.path.exists(rec_path):
         return None
     rec = json.load(open(rec_path))
-    h = hashlib.sha256()
-    for f in rec["source_files"]:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    return rec["traffic_bytes_per_step"] if h.hexdigest() == rec["source_sha256"] else None
+    if source_sha256(rec["source_files"]) != rec["source_sha256"] or plan_sha != rec.get("plan_sha256"):
+        return None
+    return rec["traffic_bytes_per_step"]
 
 
 def algorithmic_bytes(w, relax):
@@ -182,7 +211,7 @@ def gpu_leg(w, relax, steps, warmup, sched="levels", batch=None, want_x=False):
     del ldlt
     return {
         "S": S, "X": X, "sym": sym, "wall": wall, "t_norm": t_norm, "t_run": t_run,
-        "t_analyze": t_an, "t_factor": t_fac,
+        "t_analyze": t_an, "t_factor": t_fac, "plan_sha256": plan_sha256(S),
     }
 
 
@@ -388,7 +417,7 @@ def c2_leg(relax, sched, steps):
     out["max_rel_err_vs_oracle"] = float(np.max(np.abs(g["X"][0] - c["X"])) / np.max(np.abs(c["X"])))
     out["cpu_oracle_gflops"] = round(c["flops"] / c["t"] / 1e9, 3)
     out["cpu_oracle_threads"] = c["threads"]
-    out["traffic"] = measured_traffic("C2", sched)
+    out["traffic"] = measured_traffic("C2", sched, g["plan_sha256"])
     g["S"].close()
     log(f"C2: {out['gflops']} GFLOP/s, step {out['ms_per_step']} ms, vs oracle {out['max_rel_err_vs_oracle']:.2e}")
     return out
@@ -503,7 +532,7 @@ def main():
         "s_per_solve": ms_step * 1e-3 / w.batch,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 5),
-                     "traffic": measured_traffic(args.workload, args.sched),
+                     "traffic": measured_traffic(args.workload, args.sched, g["plan_sha256"]),
                      "traffic_unit": "HBM bytes per traversal (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, calibrated "
                                      "on a 1 GiB device copy)",
                      "algorithmic_bytes": algorithmic_bytes(w, args.relax),

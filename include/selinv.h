@@ -367,6 +367,11 @@ selinv_status selinv_trace(selinv_ctx *h, void *trace_dev);
  *   which = 1: the adjoint's items in launch order (R1 leaves to root, then
  *     R3 root to leaves); type 0..11 as the BackItemType of the device plan,
  *     12 / 13 = the whole R1 / R3 of a small node in one wavefront.
+ *   which = 2: the forward traversal's launches under the level and push
+ *     schedules, in order: {kind (0 work items, 1 single-wavefront nodes,
+ *     2 GEMM-1-only dense-buffer tiles, 3 push tiles), items per matrix,
+ *     type of the first item (-1 for push tiles), etree depth}.  The list is
+ *     built for every plan; the persistent schedule does not launch by it.
  * Errors: SELINV_EINVAL for another `which`.
  */
 selinv_status selinv_items(const selinv_ctx *h, int32_t which, const int32_t **items, int64_t *n);

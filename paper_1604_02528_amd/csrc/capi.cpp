@@ -856,6 +856,7 @@ struct selinv_ctx {
   uint64_t gen = 0, dtilde_gen = 0, run_gen = 0;
   const void *panels_at = nullptr, *dtilde_at = nullptr, *x_at = nullptr;
   std::vector<Item> bseq;            // adjoint launch sequence for selinv_items (built on demand)
+  std::vector<Item> lseq;            // forward level launches for selinv_items (built on demand)
   const void *ctrl_at = nullptr;     // control words of the last persistent launch (for selinv_sync)
   void *devfac_work = nullptr;       // work buffer of a device factorization not yet checked by selinv_sync
   uint64_t serial = 0;               // unique per context (owner tag of the no-alloc work area)
@@ -1650,7 +1651,30 @@ selinv_status selinv_items(const selinv_ctx *hc, int32_t which, const int32_t **
     *n = (int64_t)h->H.items.size();
     return SELINV_OK;
   }
-  if (which != 1) return set_err(h, SELINV_EINVAL, "selinv_items: which must be 0 (forward) or 1 (adjoint)");
+  if (which == 2) {
+    // the forward traversal's level launches in order (what the level and
+    // push schedules launch): {kind, items per matrix, type of the first
+    // item (-1 for a push launch), etree depth}
+    if (h->lseq.empty()) {
+      const HostPlan &H = h->H;
+      int32_t depth = -1;  // a push launch follows the D step of its depth
+      for (size_t q = 0; q + 1 < H.lvl_ptr.size(); ++q) {
+        const int32_t first = H.lvl_ptr[q], cnt = H.lvl_ptr[q + 1] - first;
+        int32_t type = -1;
+        if (H.lvl_kind[q] != LVL_PUSH) {
+          const Item &it = H.items[H.lvl_items[first]];
+          type = it.type;
+          depth = (int32_t)h->S.sdepth[it.K];
+        }
+        h->lseq.push_back(Item{H.lvl_kind[q], cnt, type, depth});
+      }
+    }
+    *items = reinterpret_cast<const int32_t *>(h->lseq.data());
+    *n = (int64_t)h->lseq.size();
+    return SELINV_OK;
+  }
+  if (which != 1)
+    return set_err(h, SELINV_EINVAL, "selinv_items: which must be 0 (forward), 1 (adjoint) or 2 (level launches)");
   // the adjoint's launches in order, a small-node launch expanded into one
   // row per node
   if (h->bseq.empty()) {

@@ -191,8 +191,31 @@ def test_adjoint_items_which_is_checked():
 
     S = _ctx(workload("C1"))
     with pytest.raises(capi.SelinvError) as ei:
-        capi.selinv_items(S.h, 2)
+        capi.selinv_items(S.h, 3)
     assert ei.value.status == 1
+
+
+@pytest.mark.parametrize("name,scale", [("C2", None), ("C3", 14)])
+def test_level_launch_list(name, scale):
+    """selinv_items(which = 2): the level schedule's launches run the etree
+    depths root first, each depth's phases in order (gathers, GEMM-1 tiles,
+    GEMM-2 and split sums, diagonal blocks, then the single-wavefront nodes),
+    and together hold every work item once."""
+    from paper_1604_02528_amd import SelInv, capi
+
+    w = workload(name, scale)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128" if w.is_complex else "f64", batch=w.batch,
+               cap=w.cap, relax=0.05, device="cpu", adjoint=False)
+    L = capi.selinv_items(S.h, 2)
+    items = capi.selinv_items(S.h, 0)
+    assert L[:, 1].sum() == len(items)
+    assert np.all(np.diff(L[:, 3]) >= 0) and L[0, 3] == 0 and L[-1, 3] == S.symbolic()["depth"] - 1
+    phase = {3: 0, 0: 1, 4: 2, 5: 2, 1: 3, 2: 3}  # item type -> phase
+    for d in np.unique(L[:, 3]):
+        rows = L[L[:, 3] == d]
+        ph = [4 if k == 1 else phase[t] for k, t in zip(rows[:, 0], rows[:, 2])]
+        assert ph == sorted(ph), (d, rows)
+        assert set(rows[:, 0]) <= {0, 1, 2}
 
 
 def _drop_entry(colptr, rowind, vals, j, k):
