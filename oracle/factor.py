@@ -13,6 +13,12 @@ pivots: for every supernode in increasing order, factor the dense diagonal
 block, solve for L_{C,K}, and subtract L_{C,K} D_K L_{C,K}^T from the
 ancestors' panels (the fill property guarantees every target lies in F).
 
+Hermitian A (``herm=True``): the same with conjugate transposes wherever a
+transpose appears (Section 2.3, after Alg. 2): B = L D L^H with real D,
+U = D L^H, Dt_K^{-1} = L_KK^{-H} D_K^{-1} L_KK^{-1}.  A stored lower value of
+A that the permutation moves into B's upper triangle enters B's lower
+triangle conjugated.
+
 Panel layout: supernode K has a dense (s + c) x s array whose rows are K's own
 columns followed by C(K).  After ``factor`` the strict lower part of the top
 s x s block holds L_KK, its diagonal holds D_K and the bottom c x s block
@@ -52,19 +58,32 @@ def assemble(sym, bvals):
     return panels
 
 
-def factor(sym, avals):
-    """Unpivoted supernodal LDL^T of B = P A P^T from A's stored lower values.
+def b_lower_values(sym, avals, herm=False):
+    """B's lower values in B's CSC order from A's stored lower values."""
+    avals = np.asarray(avals)
+    if herm:
+        avals = np.where(sym.aflip, np.conj(avals), avals)
+    bvals = np.empty_like(avals)
+    bvals[sym.amap] = avals
+    return bvals
+
+
+def factor(sym, avals, herm=False):
+    """Unpivoted supernodal LDL^T (LDL^H for ``herm``) of B = P A P^T from A's
+    stored lower values.
 
     ``avals`` is one matrix's values in A's CSC order.  Raises ZeroPivot on an
     exactly zero or non-finite pivot (no perturbation, no pivoting).
     """
-    avals = np.asarray(avals)
-    bvals = np.empty_like(avals)
-    bvals[sym.amap] = avals
-    return factor_panels(sym, assemble(sym, bvals))
+    return factor_panels(sym, assemble(sym, b_lower_values(sym, avals, herm)), herm)
 
 
-def factor_panels(sym, panels):
+def _tr(M, herm):
+    """Transpose, conjugate transpose for a Hermitian matrix."""
+    return M.conj().T if herm else M.T
+
+
+def factor_panels(sym, panels, herm=False):
     """Factor in place panels that already hold B's lower values on the pattern of L.
 
     Entries of the pattern of L that are not in A are allowed to be nonzero:
@@ -81,8 +100,10 @@ def factor_panels(sym, panels):
             if d == 0 or not np.isfinite(d):
                 raise ZeroPivot(f + jj, d)
             col = P[jj + 1:, jj] / d
-            # trailing update of the remaining panel columns (lower part suffices)
-            P[jj + 1:, jj + 1:] -= np.outer(col, P[jj + 1:s, jj])
+            # trailing update of the remaining panel columns (lower part
+            # suffices): entry (i, k) loses L_i d L_k, L_i d conj(L_k) if Hermitian
+            row = P[jj + 1:s, jj]
+            P[jj + 1:, jj + 1:] -= np.outer(col, np.conj(row) if herm else row)
             P[jj + 1:, jj] = col
         C = sym.rows[K]
         c = C.shape[0]
@@ -90,7 +111,7 @@ def factor_panels(sym, panels):
             continue
         Lc = P[s:, :]
         Dk = np.diag(P[:s, :s]).copy()
-        U = (Lc * Dk[None, :]) @ Lc.T  # c x c, symmetric (plain transpose)
+        U = (Lc * Dk[None, :]) @ _tr(Lc, herm)  # c x c: L_C D L_C^T (L_C D L_C^H if Hermitian)
         g0, g1 = sym.seg_ptr[K], sym.seg_ptr[K + 1]
         for g in range(g0, g1):
             J = int(sym.seg_super[g])
@@ -104,10 +125,11 @@ def factor_panels(sym, panels):
     return panels
 
 
-def normalize(sym, panels):
+def normalize(sym, panels, herm=False):
     """Alg. 1 steps 1-2 for LDL^T: returns (Lhat list, Dtinv list).
 
-    Lhat_{C,K} = L_{C,K} L_KK^{-1}; Dt_K^{-1} = L_KK^{-T} D_K^{-1} L_KK^{-1}.
+    Lhat_{C,K} = L_{C,K} L_KK^{-1}; Dt_K^{-1} = L_KK^{-T} D_K^{-1} L_KK^{-1}
+    (L_KK^{-H} for ``herm``).
     """
     lhat, dtinv = [], []
     for K in range(sym.nsuper):
@@ -116,22 +138,22 @@ def normalize(sym, panels):
         Lkk = np.tril(P[:s, :s], -1) + np.eye(s, dtype=P.dtype)
         d = np.diag(P[:s, :s]).copy()
         Linv = sla.solve_triangular(Lkk, np.eye(s, dtype=P.dtype), lower=True, unit_diagonal=True)
-        dtinv.append(Linv.T @ (Linv / d[:, None]))
+        dtinv.append(_tr(Linv, herm) @ (Linv / d[:, None]))
         Lc = P[s:, :]
         # Lhat = Lc Lkk^{-1}  <=>  Lhat^T = Lkk^{-T} Lc^T
         lhat.append(Lc @ Linv)
     return lhat, dtinv
 
 
-def dtilde(sym, panels):
-    """Dt_K = L_KK D_K L_KK^T (the pivot block of the block LDL^T)."""
+def dtilde(sym, panels, herm=False):
+    """Dt_K = L_KK D_K L_KK^T (L_KK^H for ``herm``; the pivot block of the block LDL^T)."""
     out = []
     for K in range(sym.nsuper):
         P = panels[K]
         s = sym.width(K)
         Lkk = np.tril(P[:s, :s], -1) + np.eye(s, dtype=P.dtype)
         d = np.diag(P[:s, :s]).copy()
-        out.append((Lkk * d[None, :]) @ Lkk.T)
+        out.append((Lkk * d[None, :]) @ _tr(Lkk, herm))
     return out
 
 

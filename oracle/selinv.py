@@ -6,7 +6,9 @@ A^{-1}_{K,K} and the bottom c x s block holds A^{-1}_{C,K}.  Together they are
 every selected entry of the lower triangle: (i, j) with L_ij != 0 (Alg. 1 and
 Alg. 2 output lines).  The upper triangle is the transpose (LDL^T
 specialization, Section 2.3).  Transposes are plain transposes, also for
-complex-symmetric matrices.
+complex-symmetric matrices; with ``herm=True`` (Hermitian A, the variant of
+Section 2.3 after Alg. 2) every transpose is a conjugate transpose, so the
+upper triangle is the conjugate transpose of the lower one.
 
 Three independent formulations:
   dense_selected  the definition: (P A P^T)^{-1} restricted to the pattern of L.
@@ -24,8 +26,13 @@ from __future__ import annotations
 import numpy as np
 
 
-def gather_cc(sym, X, K):
-    """Dense A^{-1}_{C,C} for C = C(K) from ancestor panels (lower + transpose)."""
+def _tr(M, herm):
+    return M.conj().T if herm else M.T
+
+
+def gather_cc(sym, X, K, herm=False):
+    """Dense A^{-1}_{C,C} for C = C(K) from ancestor panels (lower part + its
+    transpose, or conjugate transpose for ``herm``)."""
     C = sym.rows[K]
     c = C.shape[0]
     dtype = np.result_type(*[X[int(J)].dtype for J in sym.seg_super[sym.seg_ptr[K]:sym.seg_ptr[K + 1]]]) if c else np.float64
@@ -40,15 +47,16 @@ def gather_cc(sym, X, K):
         # column b of G (b in this segment), rows a >= st: X_J[pos[a - st], C[b] - first(J)]
         G[st:, st:en] = X[J][np.ix_(pos, cols)]
     lower = np.tril(G)
-    return lower + np.tril(G, -1).T
+    return lower + _tr(np.tril(G, -1), herm)
 
 
-def alg1(sym, lhat, dtinv, stop_after=None):
+def alg1(sym, lhat, dtinv, stop_after=None, herm=False):
     """Alg. 1 second loop, K = N..1 (root first), pull form.
 
     A^{-1}_{C,K} = -A^{-1}_{C,C} Lhat_{C,K}                   (step 3)
     A^{-1}_{K,K} = Dt_K^{-1} - Lhat_{C,K}^T A^{-1}_{C,K}        (step 4, Uhat = Lhat^T)
     A^{-1}_{K,K} <- (A^{-1}_{K,K} + A^{-T}_{K,K}) / 2            (symmetrization)
+    (``herm``: ^H in place of ^T.)
 
     ``stop_after``: process only that many supernodes of the loop (the
     highest-numbered ones, which need no others; for timing a sample).
@@ -63,13 +71,13 @@ def alg1(sym, lhat, dtinv, stop_after=None):
         dtype = dtinv[K].dtype
         P = np.zeros((s + c, s), dtype=dtype)
         if c:
-            G = gather_cc(sym, X, K)
+            G = gather_cc(sym, X, K, herm)
             Y = -G @ lhat[K]
-            T = dtinv[K] - lhat[K].T @ Y
+            T = dtinv[K] - _tr(lhat[K], herm) @ Y
             P[s:, :] = Y
         else:
             T = dtinv[K].copy()
-        P[:s, :] = 0.5 * (T + T.T)
+        P[:s, :] = 0.5 * (T + _tr(T, herm))
         X[K] = P
     return X
 
@@ -83,8 +91,9 @@ def descendants(sym):
     return out
 
 
-def alg2(sym, lhat, dtinv):
-    """Alg. 2 (left-looking selected inversion), LDL^T specialization.
+def alg2(sym, lhat, dtinv, herm=False):
+    """Alg. 2 (left-looking selected inversion), LDL^T specialization
+    (``herm``: conjugate transposes in the D and I tasks).
 
     X starts at zero on the pattern of L.  For K = N..1:
       D   : X_KK = Dt_K^{-1} - Lhat_{C,K}^T X_{C,K}, then symmetrize.
@@ -107,8 +116,8 @@ def alg2(sym, lhat, dtinv):
         fK = int(xs[K])
         PK = X[K]
         # D task
-        T = dtinv[K] - lhat[K].T @ PK[s:, :]
-        PK[:s, :] = 0.5 * (T + T.T)
+        T = dtinv[K] - _tr(lhat[K], herm) @ PK[s:, :]
+        PK[:s, :] = 0.5 * (T + _tr(T, herm))
         XKK = PK[:s, :]
         for (I, g) in desc[K]:
             sI = sym.width(I)
@@ -130,7 +139,7 @@ def alg2(sym, lhat, dtinv):
                 XI[sI + ra, :] -= X_a_k @ Lh[rk, :]
             # I task
             if ra.size:
-                XI[sI + rk, :] -= X_a_k.T @ Lh[ra, :]
+                XI[sI + rk, :] -= _tr(X_a_k, herm) @ Lh[ra, :]
             # ID task
             XI[sI + rk, :] -= XKK[np.ix_(colsK, colsK)] @ Lh[rk, :]
     return X
@@ -147,15 +156,19 @@ def dense_selected(sym, bdense):
     return X
 
 
-def permuted_dense(sym, avals):
-    """Dense B = P A P^T from A's stored lower values (small problems)."""
+def permuted_dense(sym, avals, herm=False):
+    """Dense B = P A P^T from A's stored lower values (small problems); the
+    upper triangle mirrors the lower one, conjugated for ``herm``."""
     n = sym.n
+    avals = np.asarray(avals)
+    if herm:
+        avals = np.where(sym.aflip, np.conj(avals), avals)
     bvals = np.empty_like(avals)
     bvals[sym.amap] = avals
-    Bd = np.zeros((n, n), dtype=np.asarray(avals).dtype)
+    Bd = np.zeros((n, n), dtype=avals.dtype)
     cols = np.repeat(np.arange(n), np.diff(sym.Bcolptr))
+    Bd[cols, sym.Browind] = np.conj(bvals) if herm else bvals
     Bd[sym.Browind, cols] = bvals
-    Bd[cols, sym.Browind] = bvals
     return Bd
 
 
@@ -175,10 +188,11 @@ def unflatten(sym, vec):
     return out
 
 
-def on_pattern_of_A(sym, X, colptr, rowind):
+def on_pattern_of_A(sym, X, colptr, rowind, herm=False):
     """Selected entries at A's stored lower positions, original indexing.
 
-    A entry (r, c) reads X at (max(ip[r], ip[c]), min(...)) of B.
+    A entry (r, c) reads X at (max(ip[r], ip[c]), min(...)) of B, conjugated
+    for ``herm`` when ip[r] < ip[c] (the entry lies in B's upper triangle).
     """
     n = sym.n
     ip = np.empty(n, dtype=np.int64)
@@ -198,4 +212,6 @@ def on_pattern_of_A(sym, X, colptr, rowind):
         else:
             pr = (l - f + 1) + int(np.searchsorted(sym.rows[k], r))
         out[e] = X[k][pr, int(lo[e]) - f]
+    if herm:
+        out = np.where(i < j, np.conj(out), out)
     return out

@@ -40,6 +40,7 @@ class Symbolic:
     seg_start: np.ndarray
     seg_posoff: np.ndarray
     posarr: np.ndarray
+    aflip: np.ndarray = None  # A entry e lands in B's strict upper triangle (ip[row] < ip[col])
 
     @property
     def nsuper(self) -> int:
@@ -66,6 +67,9 @@ def permute_lower(n, colptr, rowind, perm):
 
     B[i, j] = A[perm[i], perm[j]]; an A entry (r, c) lands at
     (max(ip[r], ip[c]), min(ip[r], ip[c])) with ip the inverse permutation.
+    The last result flags the entries with ip[r] < ip[c]: their value is that
+    of B's upper triangle, so B's lower entry there is its transpose
+    (conjugated for a Hermitian A).
     """
     colptr = np.asarray(colptr, dtype=np.int64)
     rowind = np.asarray(rowind, dtype=np.int64)
@@ -84,7 +88,7 @@ def permute_lower(n, colptr, rowind, perm):
     Browind = hi[order]
     amap = np.empty_like(order)
     amap[order] = np.arange(order.shape[0], dtype=np.int64)
-    return Bcolptr, Browind, amap
+    return Bcolptr, Browind, amap, i < j
 
 
 def analyze(n, colptr, rowind, perm=None, cap=256, relax=0.0):
@@ -96,7 +100,7 @@ def analyze(n, colptr, rowind, perm=None, cap=256, relax=0.0):
     """
     if perm is None:
         perm = np.arange(n, dtype=np.int64)
-    Bcolptr, Browind, amap = permute_lower(n, colptr, rowind, perm)
+    Bcolptr, Browind, amap, aflip = permute_lower(n, colptr, rowind, perm)
 
     # Column structures by the column-structure theorem: struct(L_j) is the
     # lower pattern of column j of B together with struct(L_c) \ {c} for every
@@ -151,7 +155,7 @@ def analyze(n, colptr, rowind, perm=None, cap=256, relax=0.0):
             sparent[K] = col2super[rows[K][0]]
     maps = ancestor_maps(xsuper, col2super, rows)
     return Symbolic(n, np.asarray(perm, dtype=np.int64), Bcolptr, Browind, amap, parent,
-                    colcount, xsuper, col2super, sparent, rows, *maps)
+                    colcount, xsuper, col2super, sparent, rows, *maps, aflip=aflip)
 
 
 def panel_row(xsuper, rows, J, r):

@@ -3,7 +3,8 @@
 Conventions (shared by every consumer):
 
 * A grid point (x, y[, z]) has original index p = x + nx*(y + ny*z), x fastest.
-* Matrices are symmetric (real) or complex-symmetric (A = A^T, no conjugation).
+* Matrices are symmetric (real), complex-symmetric (A = A^T, no conjugation)
+  or, for the H3 family, Hermitian (A = A^H; ``meta["dtype"] == "h128"``).
   Only the lower triangle is stored: CSC with int64 ``colptr``/``rowind``,
   rows ascending in each column, so the diagonal entry opens every column.
 * ``values`` has shape [B, nnz] (B matrices that share one pattern, the batched
@@ -20,7 +21,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-CONFIG_NAMES = ("C1", "C2", "C3", "C4", "C4s", "C5")
+CONFIG_NAMES = ("C1", "C2", "C3", "C4", "C4s", "C5", "H3")
 
 
 @dataclass
@@ -45,6 +46,15 @@ class Workload:
     @property
     def is_complex(self) -> bool:
         return np.iscomplexobj(self.values)
+
+    @property
+    def is_hermitian(self) -> bool:
+        return self.meta.get("dtype") == "h128"
+
+    @property
+    def dtype(self) -> str:
+        """The library's dtype name: "f64", "c128" (complex-symmetric) or "h128" (Hermitian)."""
+        return "h128" if self.is_hermitian else ("c128" if self.is_complex else "f64")
 
 
 # --------------------------------------------------------------------------
@@ -258,6 +268,42 @@ def weighted_laplacian_3d(shape, sigma, rng=None, wlo=0.5, whi=1.5):
     return _weighted_graph_laplacian(n, a, b, w, ghost, g, diag_extra=sigma)
 
 
+def magnetic_laplacian_3d(shape, rng, wlo=0.5, whi=1.5):
+    """Hermitian 7-point operator sum_e w_e u_e u_e^H + sum_ghost g e_a e_a^T,
+    u_e = e_a - e^{-i theta_e} e_b, on a 3-D grid (a discrete magnetic
+    Laplacian, positive semidefinite).
+
+    Edges as in weighted_laplacian_3d (a < b, b = a + a unit step); the stored
+    lower entry is A[b, a] = -w_e e^{-i theta_e} (so A[a, b] = -w_e e^{i theta_e}).
+    Draw order: edge weights U[wlo, whi], ghost weights, then phases
+    theta_e ~ U[-pi, pi].
+    """
+    shape = tuple(shape)
+    n = int(np.prod(shape))
+    a_list, b_list = [], []
+    for off in _unit_offsets(3):
+        a, b = _axis_edges(shape, off)
+        a_list.append(a)
+        b_list.append(b)
+    a = np.concatenate(a_list)
+    b = np.concatenate(b_list)
+    ghost = _ghost_points(shape)
+    w = rng.uniform(wlo, whi, size=a.shape[0])
+    g = rng.uniform(wlo, whi, size=ghost.shape[0])
+    theta = rng.uniform(-np.pi, np.pi, size=a.shape[0])
+    diag = np.zeros(n)
+    np.add.at(diag, a, w)
+    np.add.at(diag, b, w)
+    np.add.at(diag, ghost, g)
+    hi = np.maximum(a, b)
+    lo = np.minimum(a, b)
+    off = -w * np.exp(-1j * theta)  # at (hi, lo) = (b, a)
+    rows = np.concatenate([np.arange(n, dtype=np.int64), hi])
+    cols = np.concatenate([np.arange(n, dtype=np.int64), lo])
+    vals = np.concatenate([diag.astype(np.complex128), off])[None, :]
+    return _lower_csc(n, rows, cols, vals)
+
+
 def gmrf_2d(nx, ny, kappa, w):
     """GMRF precision kappa^2 I + sum_e exp(w_e)(e_a-e_b)(e_a-e_b)^T (Neumann, no ghosts).
 
@@ -379,6 +425,9 @@ def config(name, scale=None, batch=None):
     C4  GMRF 200x200, kappa 0.5, w_e ~ N(0, 0.3^2), c_i ~ U[0,1], seed 4.
     C4s the same generator on 30x30.
     C5  64^3 27-point complex-symmetric, 8 shifts A - z_l I, cap 256, seed 5.
+    H3  Hermitian: the magnetic 7-point Laplacian H on 30^3 (weights
+        U[0.5,1.5], phases U[-pi,pi]) with 16 real shifts A_l = H + sigma_l I,
+        log10(sigma_l) ~ U[-2, 0], seed 6 (positive definite).
 
     ``scale`` replaces the grid edge length (smaller test instances of the
     same family); ``batch`` replaces the number of shifts.
@@ -425,4 +474,13 @@ def config(name, scale=None, batch=None):
         vals = shifted_batch(colptr, rowind, av[0], None, z)
         return Workload("C5", m ** 3, colptr, rowind, vals, nested_dissection((m, m, m)),
                         cap=256, meta={"grid": (m, m, m), "dtype": "c128", "seed": 5, "z": z})
+    if name == "H3":
+        m = scale or 30
+        B = batch or 16
+        rng = np.random.default_rng(6)
+        colptr, rowind, hv = magnetic_laplacian_3d((m, m, m), rng)
+        sig = 10.0 ** rng.uniform(-2.0, 0.0, size=B)
+        vals = shifted_batch(colptr, rowind, hv[0], None, -sig.astype(np.complex128))
+        return Workload("H3", m ** 3, colptr, rowind, vals, nested_dissection((m, m, m)),
+                        meta={"grid": (m, m, m), "dtype": "h128", "seed": 6, "sigma": sig})
     raise KeyError(name)
