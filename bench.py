@@ -39,6 +39,8 @@ WORKLOADS = {
           "nested dissection, one batched launch",
     "C5": "C5: 3-D 27-point complex-symmetric stencil 64^3 (N=262144), 8 shifts, complex128, seed 5, "
           "nested dissection, supernode cap 256",
+    "H3": "H3: 16 real shifts H + sigma_l I of a Hermitian 3-D 7-point magnetic Laplacian 30^3 (N=27000), "
+          "complex128 Hermitian (conjugate transposes), seed 6, nested dissection, one batched launch",
 }
 
 TRAFFIC_RECORDS = {
@@ -113,7 +115,7 @@ def algorithmic_bytes(w, relax):
     supernode partition in use, times the scalar size."""
     from paper_1604_02528_amd import SelInv
 
-    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128" if w.is_complex else "f64", batch=1, cap=w.cap,
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=w.dtype, batch=1, cap=w.cap,
                relax=relax, device="cpu")
     sym = S.symbolic()
     S.close()
@@ -177,7 +179,7 @@ def factor_on_device(w, relax, sched, batch):
 
     from paper_1604_02528_amd import SelInv
 
-    dt = "c128" if w.is_complex else "f64"
+    dt = w.dtype
     S1 = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=batch, cap=w.cap, relax=relax, sched=sched,
                 adjoint=False)
     vals = torch.from_numpy(np.ascontiguousarray(w.values[:batch])).to("cuda")
@@ -198,7 +200,7 @@ def gpu_leg(w, relax, steps, warmup, sched="levels", batch=None, want_x=False):
     from paper_1604_02528_amd import SelInv
 
     batch = w.batch if batch is None else batch
-    dt = "c128" if w.is_complex else "f64"
+    dt = w.dtype
     t0 = time.perf_counter()
     S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=batch, cap=w.cap, relax=relax, sched=sched,
                tune_cache=TUNE_TABLE, adjoint=False)
@@ -231,6 +233,20 @@ def summary(w, g, steps, name):
         "flops_per_solve": sym["flops_exact"], "nsuper": sym["nsuper"], "depth": sym["depth"],
         "t_factor_device_s": round(g["t_factor"], 4),
     }
+
+
+def hermitian_leg(relax, sched):
+    """H3: the Hermitian variant (Section 2.3) on 16 shifts in one launch,
+    with the same 30^3 grid as C3 (complex-symmetric) for comparison."""
+    from workloads import config
+
+    w = config("H3")
+    g = gpu_leg(w, relax, 3, 1, sched)
+    out = summary(w, g, 3, "H3")
+    g["S"].close()
+    log(f"H3: {out['gflops']} GFLOP/s, step {out['ms_per_step']} ms, traversal "
+        f"{out['traversal_frac_of_peak']:.3f} of the FP64 MFMA peak")
+    return out
 
 
 def batched_leg(relax, sched):
@@ -465,6 +481,7 @@ def main():
     log(f"analyze {g['t_analyze']:.2f}s device factor {g['t_factor']*1e3:.1f} ms | step {ms_step:.3f} ms "
         f"(normalize {t_norm*1e3:.3f} ms, selinv {t_run*1e3:.3f} ms) | {value:.1f} GFLOP/s")
     X0 = g["X"][0] if g["X"] is not None else None
+    plan_sha = g["plan_sha256"]
     g["S"].close()
     del g
     torch.cuda.empty_cache()
@@ -504,6 +521,8 @@ def main():
             torch.cuda.empty_cache()
         extras["batched"] = batched_leg(args.relax, args.sched)
         torch.cuda.empty_cache()
+        extras["hermitian"] = hermitian_leg(args.relax, args.sched)
+        torch.cuda.empty_cache()
         extras["adjoint"] = adjoint_leg(args.relax)
     wl = WORKLOADS[args.workload]
     if w.batch > 1:
@@ -532,7 +551,7 @@ def main():
         "s_per_solve": ms_step * 1e-3 / w.batch,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 5),
-                     "traffic": measured_traffic(args.workload, args.sched, g["plan_sha256"]),
+                     "traffic": measured_traffic(args.workload, args.sched, plan_sha),
                      "traffic_unit": "HBM bytes per traversal (FETCH_SIZE x2.0 + WRITE_SIZE x1.0, calibrated "
                                      "on a 1 GiB device copy)",
                      "algorithmic_bytes": algorithmic_bytes(w, args.relax),

@@ -3,12 +3,13 @@
  *
  * Method: Jacquelin, Lin, Jia, Zhao, Yang, "A Left-Looking Selected Inversion
  * Algorithm and Task Parallelism on Shared Memory Systems" (arXiv:1604.02528).
- * Given a sparse symmetric (real) or complex-symmetric matrix A and a
- * symmetric fill-reducing permutation P, the library computes every entry of
- * B^{-1}, B = P A P^T, on the sparsity pattern of the L factor of B
+ * Given a sparse symmetric (real), complex-symmetric or Hermitian matrix A
+ * and a symmetric fill-reducing permutation P, the library computes every
+ * entry of B^{-1}, B = P A P^T, on the sparsity pattern of the L factor of B
  * (Alg. 1 / Alg. 2 outputs: the selected blocks A^{-1}_{I,J} with L_{I,J}
  * nonempty; the LDL^T specialization of Section 2.3 makes the upper triangle
- * the transpose of the lower one).
+ * the transpose of the lower one, and its Hermitian variant the conjugate
+ * transpose).
  *
  * Conventions shared by every entry point
  *  - Matrices: lower triangle incl. diagonal, CSC, 0-based, int64 indices,
@@ -17,9 +18,13 @@
  *  - perm: new -> old (B[i,j] = A[perm[i], perm[j]]); NULL = identity.
  *    The paper permutes symmetrically without looking at values (Section 4).
  *  - Values: `batch` matrices with one pattern (the shifts H - z_l S of a
- *    pole expansion), laid out [batch][nnz] in rowind order.  SELINV_C128
- *    values are interleaved (re, im) doubles.  Transposes are plain
- *    transposes also for complex values (complex-symmetric, A = A^T).
+ *    pole expansion), laid out [batch][nnz] in rowind order.  Complex values
+ *    (SELINV_C128, SELINV_H128) are interleaved (re, im) doubles.  For
+ *    SELINV_C128 transposes are plain transposes (complex-symmetric,
+ *    A = A^T); for SELINV_H128 (Hermitian, A = A^H, real diagonal) every
+ *    transpose is a conjugate transpose: B = L D L^H, and a stored lower
+ *    value that the permutation moves into B's upper triangle enters B's
+ *    lower triangle conjugated.
  *  - Panels: supernode K (columns first(K)..last(K), width s, row set C(K) of
  *    size c, Eq. (newset)) owns a dense column-major (s + c) x s block whose
  *    rows are K's own columns followed by C(K).  Panels are concatenated in K
@@ -49,7 +54,8 @@ typedef struct selinv_ctx selinv_ctx;
 
 typedef enum {
   SELINV_R64 = 0,  /* real float64 */
-  SELINV_C128 = 1  /* complex128, complex-symmetric */
+  SELINV_C128 = 1, /* complex128, complex-symmetric */
+  SELINV_H128 = 2  /* complex128, Hermitian (Section 2.3: conjugate transposes); no adjoint */
 } selinv_dtype;
 
 typedef enum {

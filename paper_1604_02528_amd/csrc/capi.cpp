@@ -82,6 +82,7 @@ struct HostPlan {
   std::vector<int4> sq_tiles;
   std::vector<int64_t> apos;
   std::vector<uint8_t> adiag;
+  std::vector<uint8_t> aflip;
   // device factorization: per-depth launch lists (deepest first) and pivot positions
   std::vector<int32_t> fac_nodes;
   std::vector<int2> fac_cn, fac_cw, fac_rb;
@@ -95,7 +96,7 @@ struct HostPlan {
     int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
         nph, node_split, node_kchunk, node_yoff, node_goff, node_ldg, node_parent, order, lvl_items, lvl_recs, chunks, chunks_narrow, rblocks, small_nodes,
         sq_tiles, tiny, toff,
-        apos, adiag, bitems, pushrecs, fac_nodes, fac_cn, fac_cw, fac_rb, fac_tiles, dpos, plan, linv, dinv, part, gbuf, ypart,
+        apos, adiag, aflip, bitems, pushrecs, fac_nodes, fac_cn, fac_cw, fac_rb, fac_tiles, dpos, plan, linv, dinv, part, gbuf, ypart,
         cnt, ctrl, fwd_end, adj_z, adj_l, adj_s, adj_t, adj_f, adj_d, ferr, fldet, end;
   } off{};
   int64_t tables_bytes = 0;  // [0, tables_bytes) is uploaded once
@@ -292,7 +293,7 @@ void choose_dense(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_
 }
 
 void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t dense_min_c, int64_t dense_max_bytes,
-                int64_t split_min_k, int sched, const TuneTable *tt, bool adjoint, HostPlan &H) {
+                int64_t split_min_k, int sched, const TuneTable *tt, bool adjoint, bool herm, HostPlan &H) {
   const int64_t ns = S.nsuper();
   // the push form (Alg. 2) runs one launch per depth and step like the level
   // schedule; its GEMM-1 work is done by push tiles, so no node gets a dense
@@ -588,7 +589,8 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
             for (int64_t k = 0; k <= i; ++k) {
               const uint32_t v = (uint32_t)((H.kcol[rp + k] + S.posarr[H.kpos[rp + k] + i]) * scalar_bytes);
               H.toff[t0 + i * c + k] = v;
-              H.toff[t0 + k * c + i] = v;
+              // entry (k, i), k < i, is X(i, k) transposed: conjugated in a Hermitian plan
+              H.toff[t0 + k * c + i] = v | (herm && k < i ? 1u : 0u);
             }
         }
         if (pass == 0) H.tiny_dadj[d] = (int32_t)H.tiny.size();
@@ -725,6 +727,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   }
   H.apos = S.apos;
   H.adiag = S.apos_diag;
+  H.aflip = S.aflip;
   // device factorization lists, deepest depth first
   H.fac_nodes.clear();
   H.fac_cn.clear();
@@ -805,6 +808,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.sq_tiles = take(16 * (int64_t)H.sq_tiles.size());
   o.apos = take(8 * (int64_t)H.apos.size());
   o.adiag = take((int64_t)H.adiag.size());
+  o.aflip = take((int64_t)H.aflip.size());
   o.bitems = take(16 * (int64_t)H.bitems.size());
   o.pushrecs = take((int64_t)sizeof(PushRec) * (int64_t)H.push.size());
   o.fac_nodes = take(4 * (int64_t)H.fac_nodes.size());
@@ -884,7 +888,8 @@ struct selinv_ctx {
     if (side) (void)hipStreamDestroy(side);
     if (side2) (void)hipStreamDestroy(side2);
   }
-  bool is_complex() const { return opts.dtype == SELINV_C128; }
+  bool is_complex() const { return opts.dtype == SELINV_C128 || opts.dtype == SELINV_H128; }
+  bool is_herm() const { return opts.dtype == SELINV_H128; }
   int64_t sbytes() const { return is_complex() ? 16 : 8; }
 };
 
@@ -953,6 +958,8 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.toff = (uint32_t *)(b + o.toff);
   d.apos = (int64_t *)(b + o.apos);
   d.adiag = (uint8_t *)(b + o.adiag);
+  d.aflip = (uint8_t *)(b + o.aflip);
+  d.csign = h->is_herm() ? -1.0 : 1.0;
   d.linv = (void *)(b + o.linv);
   d.dinv = (void *)(b + o.dinv);
   d.part = (void *)(b + o.part);
@@ -1062,6 +1069,7 @@ void build_image(selinv_ctx *h) {
   put(img, o.sq_tiles, H.sq_tiles);
   put(img, o.apos, H.apos);
   put(img, o.adiag, H.adiag);
+  put(img, o.aflip, H.aflip);
   put(img, o.bitems, H.bitems);
   put(img, o.pushrecs, H.push);
   put(img, o.fac_nodes, H.fac_nodes);
@@ -1179,7 +1187,8 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *ro
   }
   *out = h;
   const selinv_opts &o = h->opts;
-  if (o.dtype != SELINV_R64 && o.dtype != SELINV_C128) return set_err(h, SELINV_EUNSUPPORTED, "unknown dtype");
+  if (o.dtype != SELINV_R64 && o.dtype != SELINV_C128 && o.dtype != SELINV_H128)
+    return set_err(h, SELINV_EUNSUPPORTED, "unknown dtype");
   if (o.batch < 1) return set_err(h, SELINV_EINVAL, "batch must be >= 1");
   if (o.max_super < 1 || o.max_super > 256) return set_err(h, SELINV_EINVAL, "max_super must be in [1, 256]");
   if (o.sched != SELINV_SCHED_PERSISTENT && o.sched != SELINV_SCHED_LEVELS && o.sched != SELINV_SCHED_PUSH)
@@ -1192,7 +1201,8 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *ro
     TuneTable tt;
     if (o.tune_cache && o.tune_cache[0]) tt = load_tune_table(o.tune_cache, h->is_complex() ? "c128" : "f64");
     build_plan(h->S, o.batch, h->sbytes(), min_c, max_b, split_k, o.sched,
-               (o.tune_cache && o.tune_cache[0]) ? &tt : nullptr, o.adjoint >= 0, h->H);
+               (o.tune_cache && o.tune_cache[0]) ? &tt : nullptr, o.adjoint >= 0 && o.dtype != SELINV_H128,
+               o.dtype == SELINV_H128, h->H);
     if ((int64_t)h->H.items.size() * (int64_t)o.batch >= (int64_t)INT32_MAX)
       return set_err(h, SELINV_ENOMEM, "too many work items for int32 item ids");
     build_image(h);
@@ -1281,7 +1291,7 @@ selinv_status selinv_factor(selinv_ctx *h, const void *values, void *panels_dev,
   try {
     for (int64_t l = 0; l < B; ++l) {
       double ld[2] = {0.0, 0.0};
-      int64_t bad = factor_host(h->S, h->is_complex(), vals + l * h->S.nnzA * scal, h->pinned + l * pe * scal,
+      int64_t bad = factor_host(h->S, h->opts.dtype, vals + l * h->S.nnzA * scal, h->pinned + l * pe * scal,
                                 h->opts.nthreads, ld);
       if (bad >= 0) return set_err(h, SELINV_ESINGULAR, "zero or non-finite pivot", bad, l);
       h->logdet[2 * l] = ld[0];
@@ -1337,7 +1347,7 @@ selinv_status selinv_factor_host(selinv_ctx *h, const void *values, void *panels
   try {
     for (int64_t l = 0; l < B; ++l) {
       double ld[2] = {0.0, 0.0};
-      int64_t bad = factor_host(h->S, h->is_complex(), vals + l * h->S.nnzA * scal, out + l * pe * scal,
+      int64_t bad = factor_host(h->S, h->opts.dtype, vals + l * h->S.nnzA * scal, out + l * pe * scal,
                                 h->opts.nthreads, ld);
       if (bad >= 0) return set_err(h, SELINV_ESINGULAR, "zero or non-finite pivot", bad, l);
       h->logdet[2 * l] = ld[0];
@@ -1554,6 +1564,7 @@ selinv_status selinv_backward(selinv_ctx *h, const void *panels_dev, const void 
                               void *stream) {
   if (!h) return SELINV_EINVAL;
   if (!h->factored) return set_err(h, SELINV_ESTATE, "selinv_backward before a successful selinv_factor");
+  if (h->is_herm()) return set_err(h, SELINV_EUNSUPPORTED, "selinv_backward: no adjoint for Hermitian matrices");
   if (!h->H.adjoint)
     return set_err(h, SELINV_EUNSUPPORTED, "selinv_backward: the work area was sized without the adjoint's scratch "
                                            "(opts.adjoint < 0)");

@@ -1,4 +1,6 @@
-// Numeric factorization on the GPU: unpivoted supernodal LDL^T of B = P A P^T.
+// Numeric factorization on the GPU: unpivoted supernodal LDL^T of B = P A P^T
+// (LDL^H for a Hermitian A: the transposed factor of every product below is
+// conjugated, Section 2.3).
 //
 // The paper takes its factors from an external solver that permutes
 // symmetrically and does no dynamic pivoting (Section 4); this is the
@@ -94,6 +96,7 @@ __global__ void __launch_bounds__(NT) k_fac_diag(const DevPlan *__restrict__ plp
   T *P = Pall + l * pl.panel_elems + gp(pl.node_off)[K];
   const int64_t first = gp(pl.node_first)[K];
   const int t = threadIdx.x;
+  const double cs = pl.csign;  // LDL^H in a Hermitian plan: the right factor conjugated
   for (int jb = 0; jb < s; jb += BW) {
     const int w = min(BW, s - jb);
     for (int e = t; e < BW * BW; e += NT) {
@@ -108,7 +111,7 @@ __global__ void __launch_bounds__(NT) k_fac_diag(const DevPlan *__restrict__ plp
       __syncthreads();
       for (int e = t; e < BW * BW; e += NT) {
         const int i = e % BW, k = e / BW;
-        if (k > j && k <= i && i < w) ajj[i * BP + k] -= ajj[i * BP + j] * d * ajj[k * BP + j];
+        if (k > j && k <= i && i < w) ajj[i * BP + k] -= ajj[i * BP + j] * d * cj(ajj[k * BP + j], cs);
       }
       __syncthreads();
     }
@@ -130,7 +133,7 @@ __global__ void __launch_bounds__(NT) k_fac_diag(const DevPlan *__restrict__ plp
         if (j < w) {
           T v = a[j];
 #pragma unroll
-          for (int k = 0; k < j; ++k) v -= a[k] * dv[k] * ajj[j * BP + k];
+          for (int k = 0; k < j; ++k) v -= a[k] * dv[k] * cj(ajj[j * BP + k], cs);
           a[j] = SOps<T>::div(v, dv[j]);
         }
       }
@@ -150,14 +153,15 @@ __global__ void __launch_bounds__(NT) k_fac_diag(const DevPlan *__restrict__ plp
       while ((rr + 1) * (rr + 2) / 2 <= e) ++rr;
       const int qq = e - rr * (rr + 1) / 2;
       T acc = zero_of<T>();
-      for (int j = 0; j < w; ++j) acc += lb[rr * BW + j] * dv[j] * lb[qq * BW + j];
+      for (int j = 0; j < w; ++j) acc += lb[rr * BW + j] * dv[j] * cj(lb[qq * BW + j], cs);
       P[(int64_t)(jb + w + qq) * ld + jb + w + rr] -= acc;
     }
     __syncthreads();
   }
 }
 
-// L_{C,K} = S_{C,K} L_KK^{-T} D_K^{-1} for one 64-row block of C(K), in place.
+// L_{C,K} = S_{C,K} L_KK^{-T} D_K^{-1} (L_KK^{-H} if Hermitian) for one 64-row
+// block of C(K), in place.
 // Column tile x of the result needs columns k <= x of S_{C,K} only (L_KK^{-1}
 // is lower triangular), so tiles run right to left and each is stored after
 // its own product has read everything it needs.
@@ -179,7 +183,8 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
   for (int x0 = uniform(((s - 1) / 64) * 64); x0 >= 0; x0 -= 64) {
     const int kend = min(s, x0 + 64);
     LoadDenseA<T, TK> la{P + s, ld, c, kend, i0};     // S_{C,K}(i, k)
-    LoadDenseBT<T, TK> lb{Linv, s, kend, x0, s};       // L_KK^{-1}(x, k)
+    LoadDenseBT<T, TK> lb{Linv, s, kend, x0, s};       // L_KK^{-1}(x, k), conjugated if Hermitian
+    lb.cs = pl.csign;
     Acc<T> acc;
     gemm_dense<T>(0, kend, la, lb, smem, acc);
     acc_to_lds<T>(acc, smem);
@@ -193,7 +198,7 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
   }
 }
 
-// Block (a, b), a >= b, of the update L_{C,K} D_K L_{C,K}^T, subtracted from
+// Block (a, b), a >= b, of the update L_{C,K} D_K L_{C,K}^T (^H if Hermitian), subtracted from
 // the ancestors' entries of S_{C,C} (lower part: C-local rows i >= k).
 template <typename T>
 __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
@@ -211,7 +216,8 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
   const int64_t off = gp(pl.node_off)[K], rp = gp(pl.node_rowptr)[K];
   const T *P = Pl + off;
   LoadDenseA<T, TK> la{P + s, ld, c, s, i0};                           // L_C(i, j)
-  LoadDenseBTScaled<T, TK> lb{P + s, ld, s, k0, c, P, (int64_t)ld + 1};  // D_j L_C(k, j)
+  LoadDenseBTScaled<T, TK> lb{P + s, ld, s, k0, c, P, (int64_t)ld + 1};  // D_j L_C(k, j) (conjugated if Hermitian)
+  lb.cs = pl.csign;
   Acc<T> acc;
   gemm_dense<T>(0, s, la, lb, smem, acc);
   acc_to_lds<T>(acc, smem);

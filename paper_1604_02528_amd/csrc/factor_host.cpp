@@ -1,4 +1,6 @@
-// Host numeric factorization: unpivoted supernodal LDL^T of B = P A P^T.
+// Host numeric factorization: unpivoted supernodal LDL^T of B = P A P^T
+// (LDL^H for a Hermitian A: every transpose below is then a conjugate
+// transpose, Section 2.3).
 //
 // The paper takes its factors from an external package that does no dynamic
 // pivoting (Section 4); this is the library's own producer of that input.
@@ -32,11 +34,12 @@ template <typename T>
 struct Factorizer {
   const Symbolic &S;
   T *P;  // panels of one matrix
+  double cs;  // -1: Hermitian (conjugate transposes), +1 otherwise
   std::vector<std::mutex> locks;
   std::atomic<int64_t> bad_col{-1};
   std::atomic<bool> abort{false};
 
-  Factorizer(const Symbolic &s, T *p) : S(s), P(p), locks(s.nsuper()) {}
+  Factorizer(const Symbolic &s, T *p, double csign) : S(s), P(p), cs(csign), locks(s.nsuper()) {}
 
   void record_bad(int64_t col) {
     int64_t cur = bad_col.load();
@@ -56,9 +59,10 @@ struct Factorizer {
         return false;
       }
       T *colj = A + jj * ld;
-      // trailing update: A[i, k] -= A[i, jj] * A[k, jj] / d for k in (jj, s), i > k-1
+      // trailing update: A[i, k] -= A[i, jj] * tr(A[k, jj] / d) for k in (jj, s),
+      // i > k-1 (tr = conj for a Hermitian matrix, where d is real)
       for (int64_t k = jj + 1; k < s; ++k) {
-        T f = SOps<T>::div(colj[k], d);
+        T f = cj(SOps<T>::div(colj[k], d), cs);
         T *colk = A + k * ld;
         for (int64_t i = k; i < ld; ++i) colk[i] -= colj[i] * f;
       }
@@ -67,7 +71,8 @@ struct Factorizer {
     return true;
   }
 
-  // Subtract L_{C,K} D_K L_{C,K}^T from the ancestors (lower triangle only).
+  // Subtract L_{C,K} D_K L_{C,K}^T (^H if Hermitian) from the ancestors (lower
+  // triangle only).
   void update_ancestors(int64_t K, std::vector<T> &W, std::vector<T> &U) {
     const int64_t s = S.width(K), c = S.nrows(K), ld = s + c;
     if (c == 0) return;
@@ -91,7 +96,7 @@ struct Factorizer {
         for (int64_t k = 0; k < s; ++k) {
           const T *wk = W.data() + k * c;
           const T *lk = A + s + k * ld;
-          T l0 = lk[b], l1 = lk[b + 1], l2 = lk[b + 2], l3 = lk[b + 3];
+          T l0 = cj(lk[b], cs), l1 = cj(lk[b + 1], cs), l2 = cj(lk[b + 2], cs), l3 = cj(lk[b + 3], cs);
           for (int64_t a = b; a < c; ++a) {
             T wv = wk[a];
             u0[a - st] += wv * l0;
@@ -105,7 +110,7 @@ struct Factorizer {
         T *u0 = U.data() + (b - st) * m;
         for (int64_t k = 0; k < s; ++k) {
           const T *wk = W.data() + k * c;
-          T l0 = A[s + b + k * ld];
+          T l0 = cj(A[s + b + k * ld], cs);
           for (int64_t a = b; a < c; ++a) u0[a - st] += wk[a] * l0;
         }
       }
@@ -164,12 +169,15 @@ struct Factorizer {
 };
 
 template <typename T>
-int64_t factor_impl(const Symbolic &S, const double *vals, double *panels_raw, int nthreads, double logdet[2]) {
+int64_t factor_impl(const Symbolic &S, const double *vals, double *panels_raw, int nthreads, double logdet[2],
+                    double cs) {
   T *P = reinterpret_cast<T *>(panels_raw);
   const T *v = reinterpret_cast<const T *>(vals);
   std::memset((void *)P, 0, sizeof(T) * (size_t)S.panel_elems);
-  for (int64_t e = 0; e < S.nnzA; ++e) P[S.apos[e]] = v[e];
-  Factorizer<T> F(S, P);
+  // an entry that the permutation moves into B's upper triangle is B's lower
+  // entry transposed (conjugated if Hermitian)
+  for (int64_t e = 0; e < S.nnzA; ++e) P[S.apos[e]] = S.aflip[e] ? cj(v[e], cs) : v[e];
+  Factorizer<T> F(S, P, cs);
   F.run(nthreads);
   if (F.abort.load()) return F.bad_col.load();
   // log det = sum log D_jj
@@ -196,10 +204,10 @@ int64_t factor_impl(const Symbolic &S, const double *vals, double *panels_raw, i
 
 }  // namespace
 
-int64_t factor_host(const Symbolic &S, bool is_complex, const double *vals, double *panels, int nthreads,
+int64_t factor_host(const Symbolic &S, int kind, const double *vals, double *panels, int nthreads,
                     double logdet[2]) {
-  if (is_complex) return factor_impl<cplx>(S, vals, panels, nthreads, logdet);
-  return factor_impl<double>(S, vals, panels, nthreads, logdet);
+  if (kind == SELINV_R64) return factor_impl<double>(S, vals, panels, nthreads, logdet, 1.0);
+  return factor_impl<cplx>(S, vals, panels, nthreads, logdet, kind == SELINV_H128 ? -1.0 : 1.0);
 }
 
 }  // namespace selinv

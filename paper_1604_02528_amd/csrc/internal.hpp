@@ -39,6 +39,8 @@ struct Symbolic {
   std::vector<int32_t> posarr;
   std::vector<int64_t> apos;                  // A entry -> element offset inside one matrix's panels
   std::vector<uint8_t> apos_diag;             // A entry is a diagonal entry
+  std::vector<uint8_t> aflip;                 // A entry (r, c) has iperm[r] < iperm[c]: B's lower entry is its
+                                              // transpose (conjugated for a Hermitian A)
   std::vector<int64_t> sdepth;                // depth of each supernode (root = 0)
   int64_t depth = 0;
   int64_t nnzL = 0;
@@ -72,7 +74,8 @@ void analyze(Symbolic &S, int64_t n, const int64_t *colptr, const int64_t *rowin
 // `panels` receives panel_elems scalars.  Real or complex (interleaved).
 // Returns the failing column (>= 0) on a zero / non-finite pivot, else -1.
 // logdet receives sum log D_jj (re, im).
-int64_t factor_host(const Symbolic &S, bool is_complex, const double *vals, double *panels, int nthreads,
+// kind: SELINV_R64, SELINV_C128 or SELINV_H128
+int64_t factor_host(const Symbolic &S, int kind, const double *vals, double *panels, int nthreads,
                     double logdet[2]);
 
 }  // namespace selinv

@@ -72,7 +72,7 @@ __device__ __forceinline__ NodeInfo node_info(const DevPlan &pl, int K) {
 // major, leading dimension ldg): element (i, k), i >= k, is the lower-part
 // entry Src[kcol[k] + posarr[kpos[k] + i]] of the ancestor owning column k
 // (Src: the X panels, or any array in the same panel layout); it is written
-// to G(i, k) and G(k, i).  Lanes run along i (one column k per
+// to G(i, k) and G(k, i) (conjugated in a Hermitian plan).  Lanes run along i (one column k per
 // wave and step) for the gather and the G(i, k) stores; the mirror stores go
 // through an LDS transpose so that they are contiguous too.
 template <typename T>
@@ -117,12 +117,13 @@ __device__ void do_gtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, dou
     if (ok) Mem<false>::st(G + (int64_t)k * ldg + i, x);
   }
   lds_barrier();
-  // mirror: G(k, i) = tile[i][k], lanes along k
+  // mirror: G(k, i) = tile[i][k] (its conjugate if Hermitian), lanes along k
+  const double cs = pl.csign;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int e = threadIdx.x + NT * q;
     const int kl = e & 63, il = e >> 6, i = i0 + il, k = k0 + kl;
-    if (i < c && k < c && i > k) Mem<false>::st(G + (int64_t)i * ldg + k, lds_get<T>(smem, il, kl));
+    if (i < c && k < c && i > k) Mem<false>::st(G + (int64_t)i * ldg + k, cj(lds_get<T>(smem, il, kl), cs));
   }
   lds_barrier();
 }
@@ -210,8 +211,9 @@ __device__ void gemm2_block(const Acc<T> &acc, double *Ls) {
 }
 
 // Row tile a's share of GEMM-2 (Alg. 1 step 4): P_a[:, 64b..] = Lhat[rows of
-// tile a, :]^T Y[tile a, 64b..] = -(Lhat_a^T acc), written to the partial
-// buffer (column-major s x s per row tile); rows 64qb .. 64qe - 1 of P_a only.
+// tile a, :]^T Y[tile a, 64b..] = -(Lhat_a^T acc) (^H in a Hermitian plan),
+// written to the partial buffer (column-major s x s per row tile); rows
+// 64qb .. 64qe - 1 of P_a only.
 template <typename T, bool COH>
 __device__ void gemm2_partial(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, const Acc<T> &acc, double *smem,
                               int qb = 0, int qe = 1 << 20) {
@@ -233,13 +235,14 @@ __device__ void gemm2_partial(const Ctx<T> &cx, const NodeInfo &nd, int a, int b
     }
   };
   const int qend = min(s, qe * 64);
+  const double cs = pl.csign;
   load_l(qb * 64);
   for (int q0 = qb * 64; q0 < qend; q0 += 64) {
 #pragma unroll
     for (int q = 0; q < 64 * 64 / NT; ++q) {
       const int e = threadIdx.x + NT * q;
       const int i = e & 63, x = e >> 6;
-      const T v = masked(lv[q], opaque_mask(i0 + i < c && q0 + x < s));
+      const T v = cj(masked(lv[q], opaque_mask(i0 + i < c && q0 + x < s)), cs);
 #pragma unroll
       for (int p = 0; p < P; ++p) Ls[p * 64 * PITCH + i * PITCH + x] = Planes<T>::get(v, p);
     }
@@ -288,6 +291,7 @@ __device__ void do_ytile(const Ctx<T> &cx, const NodeInfo &nd, int a, int bp, do
     }
     lds_barrier();
     LoadGather<T, COH> la{cx.Xp, pl.kcol + rp, pl.kpos + rp, pl.posarr, rt, rt + 64, c, ke, i0};
+    la.cs = pl.csign;
     LoadPanelK<T, false> lb{cx.Lp, off, ld, s, 0, ke, j0, s};
     gemm_tile<T>(kb, ke, la, lb, smem, acc);
   }
@@ -516,13 +520,15 @@ __device__ void dtile_core(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, d
     }
   }
   lds_barrier();
-  // x(i, j) = (T[a0+i, b0+j] + T[b0+j, a0+i]) / 2 ; keep it in Sab
+  // x(i, j) = (T[a0+i, b0+j] + T[b0+j, a0+i]) / 2 (the second term conjugated
+  // in a Hermitian plan); keep it in Sab
+  const double cs = cx.pl->csign;
   T xv[64 * 64 / NT];
 #pragma unroll
   for (int q = 0; q < 64 * 64 / NT; ++q) {
     const int e = threadIdx.x + NT * q;
     const int i = e & 63, j = e >> 6;
-    xv[q] = SOps<T>::scale(0.5, lds_get<T>(Sab, i, j) + lds_get<T>(Sba, j, i));
+    xv[q] = SOps<T>::scale(0.5, lds_get<T>(Sab, i, j) + cj(lds_get<T>(Sba, j, i), cs));
   }
   lds_barrier();
 #pragma unroll
@@ -534,7 +540,8 @@ __device__ void dtile_core(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, d
   for (int e = threadIdx.x; e < 64 * 64; e += NT) {
     const int i = e & 63, j = e >> 6;
     if (a0 + i < s && b0 + j < s) Mem<COH>::st(Xkk + (int64_t)(b0 + j) * dld + a0 + i, lds_get<T>(Sab, i, j));
-    if (a != b && b0 + i < s && a0 + j < s) Mem<COH>::st(Xkk + (int64_t)(a0 + j) * dld + b0 + i, lds_get<T>(Sab, j, i));
+    if (a != b && b0 + i < s && a0 + j < s)
+      Mem<COH>::st(Xkk + (int64_t)(a0 + j) * dld + b0 + i, cj(lds_get<T>(Sab, j, i), cs));
   }
   lds_barrier();
 }
@@ -604,12 +611,14 @@ __device__ void dtile_slab(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, i
     Sba[e] = masked(dba - sba[q], mba);
   }
   lds_barrier();
-  // x(i, j) = (T[a0 + i, b0 + j] + T[b0 + j, a0 + i]) / 2
+  // x(i, j) = (T[a0 + i, b0 + j] + T[b0 + j, a0 + i]) / 2 (the second term
+  // conjugated in a Hermitian plan)
+  const double cs = pl.csign;
 #pragma unroll
   for (int q = 0; q < QE; ++q) {
     const int e = threadIdx.x + NT * q;
     const int ia = e % 64, ja = e / 64;
-    const T x = SOps<T>::scale(0.5, Sab[e] + Sba[ja + W * ia]);
+    const T x = SOps<T>::scale(0.5, Sab[e] + cj(Sba[ja + W * ia], cs));
     Xs[e] = x;
     if (a0 + ia < s && b0 + ja < s) Mem<COH>::st(Xkk + (int64_t)(b0 + ja) * dld + a0 + ia, x);
   }
@@ -619,7 +628,7 @@ __device__ void dtile_slab(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, i
     for (int q = 0; q < QE; ++q) {
       const int e = threadIdx.x + NT * q;
       const int jb = e % W, ib = e / W;
-      if (b0 + jb < s && a0 + ib < s) Mem<COH>::st(Xkk + (int64_t)(a0 + ib) * dld + b0 + jb, Xs[ib + 64 * jb]);
+      if (b0 + jb < s && a0 + ib < s) Mem<COH>::st(Xkk + (int64_t)(a0 + ib) * dld + b0 + jb, cj(Xs[ib + 64 * jb], cs));
     }
   }
   lds_barrier();
@@ -702,12 +711,13 @@ __device__ void do_stile(const Ctx<T> &cx, const NodeInfo &nd, double *smem, int
       const int64_t base = (rt[k] & lm) | (rt[i] & ~lm);
       gv[q] = Mem<COH>::ld(cx.Xp + ((base + (int64_t)pos[q]) & opaque_mask(i < c && k < c)));
     }
-    // GEMM-1 from LDS: four stages of TK contraction indices, A = X_{C,C}, B = Lhat
+    // GEMM-1 from LDS: four stages of TK contraction indices, A = X_{C,C}
+    // (upper part conjugated in a Hermitian plan), B = Lhat
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int e = threadIdx.x + NT * q;
       const int i = e & 63, k = e >> 6;
-      const T g = masked(gv[q], opaque_mask(i < c && k < c));
+      const T g = cj(masked(gv[q], opaque_mask(i < c && k < c)), i < k ? pl.csign : 1.0);
       double *stg = smem + (k / TK) * stage_doubles<T>() + (k % TK) * PITCH + i;
 #pragma unroll
       for (int p = 0; p < P; ++p) stg[p * TK * PITCH] = Planes<T>::get(g, p);  // A plane [kk][i]
@@ -727,13 +737,14 @@ __device__ void do_stile(const Ctx<T> &cx, const NodeInfo &nd, double *smem, int
     lds_barrier();
     // Y = -acc into X_{C,K}
     store_xtile<T, COH>(cx, nd, 0, 0, acc, smem);
-    // Lhat into LDS as Ls[p][i * PITCH + x], then R = Lhat^T acc
+    // Lhat (conjugated if Hermitian) into LDS as Ls[p][i * PITCH + x], then R = Lhat^T acc
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int e = threadIdx.x + NT * q;
       const int i = e & 63, x = e >> 6;
+      const T l = cj(lv[q], pl.csign);
 #pragma unroll
-      for (int p = 0; p < P; ++p) smem[p * 64 * PITCH + i * PITCH + x] = Planes<T>::get(lv[q], p);
+      for (int p = 0; p < P; ++p) smem[p * 64 * PITCH + i * PITCH + x] = Planes<T>::get(l, p);
     }
     lds_barrier();
     gemm2_block<T>(acc, smem);  // R[p][j * PITCH + x] = (Lhat^T acc)(x, j) = -(Lhat^T Y)(x, j)
@@ -760,10 +771,12 @@ __device__ void do_stile(const Ctx<T> &cx, const NodeInfo &nd, double *smem, int
     lds_put<T>(Tt, i, j, d + lds_get<T>(smem, i, j));
   }
   lds_barrier();
+  const double cs = pl.csign;
   for (int e = threadIdx.x; e < 64 * 64; e += NT) {
     const int i = e & 63, j = e >> 6;
     if (i < s && j < s)
-      Mem<COH>::st(cx.Xp + off + (int64_t)j * ld + i, SOps<T>::scale(0.5, lds_get<T>(Tt, i, j) + lds_get<T>(Tt, j, i)));
+      Mem<COH>::st(cx.Xp + off + (int64_t)j * ld + i,
+                   SOps<T>::scale(0.5, lds_get<T>(Tt, i, j) + cj(lds_get<T>(Tt, j, i), cs)));
   }
   lds_barrier();
 }
@@ -775,11 +788,12 @@ __device__ void do_stile(const Ctx<T> &cx, const NodeInfo &nd, double *smem, int
 // Lane (i, grp) holds X_{C,C}(i, k) for k = grp + G u; the partial sums of
 // X_{C,C} Lhat over the G lane groups are combined with a fixed butterfly, so
 // the result does not depend on timing.  LDS blocks are c x s with leading
-// dimension tiny_ldc<T>().
+// dimension tiny_ldc<T>().  HERM: a Hermitian plan (conjugate transposes).
 //   Y = -X_{C,C} Lhat (stored into X_{C,K});  T = Dt^{-1} - Lhat^T Y;
 //   X_{K,K} = (T + T^T) / 2                      (Alg. 1, Eqs. (2.9)-(2.10))
-template <typename T, int CM>
+template <typename T, int CM, bool HERM>
 __device__ __forceinline__ void do_tiny(const TinyRec &r, const uint32_t *toff, const T *L, T *X, T *ls, T *ys) {
+  constexpr double cs = HERM ? -1.0 : 1.0;
   constexpr int G = 64 / CM, U = CM / G, LDC = tiny_ldc<T>();
   const int lane = threadIdx.x, i = lane % CM, grp = lane / CM;
   const int s = r.s, c = r.c;
@@ -800,10 +814,19 @@ __device__ __forceinline__ void do_tiny(const TinyRec &r, const uint32_t *toff, 
   const int x = lane % kTinyS, y = lane / kTinyS;
   const int64_t dm = opaque_mask(x < s && y < s);
   const T dxy = gload(L + r.off + ((y * ld + x) & dm)), dyx = gload(L + r.off + ((x * ld + y) & dm));
-  // round 3: the values
+  // round 3: the values (bit 0 of an offset: the entry is read conjugated,
+  // Hermitian plans only; the bits are kept packed so that the offsets die here)
   T xv[U];
+  uint32_t cbits = 0;
 #pragma unroll
-  for (int u = 0; u < U; ++u) xv[u] = ld_off(X, o[u]);
+  for (int u = 0; u < U; ++u) {
+    if constexpr (HERM) {
+      xv[u] = ld_off(X, o[u] & ~1u);
+      cbits |= (o[u] & 1u) << u;
+    } else {
+      xv[u] = ld_off(X, o[u]);
+    }
+  }
 #pragma unroll
   for (int q = 0; q < QL; ++q) {
     const int e = lane + 64 * q, k = e % CM, j = e / CM;
@@ -816,7 +839,8 @@ __device__ __forceinline__ void do_tiny(const TinyRec &r, const uint32_t *toff, 
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int k = grp + G * u;
-    const T g = masked(xv[u], opaque_mask(i < c && k < c));
+    T g = masked(xv[u], opaque_mask(i < c && k < c));
+    if constexpr (HERM) g = cj(g, ((cbits >> u) & 1u) ? -1.0 : 1.0);
 #pragma unroll
     for (int j = 0; j < kTinyS; ++j)
       if (j < s) acc[j] += g * ls[j * LDC + k];
@@ -835,14 +859,15 @@ __device__ __forceinline__ void do_tiny(const TinyRec &r, const uint32_t *toff, 
       }
   }
   __syncthreads();
-  // T = Dt^{-1} + Lhat^T (X_{C,C} Lhat)
+  // T = Dt^{-1} + Lhat^T (X_{C,C} Lhat); X_KK = (T + T^T) / 2 (^H and
+  // conjugated Lhat in a Hermitian plan)
   if (x < s && y < s) {
     T rxy = zero_of<T>(), ryx = zero_of<T>();
     for (int q = 0; q < c; ++q) {
-      rxy += ls[x * LDC + q] * ys[y * LDC + q];
-      ryx += ls[y * LDC + q] * ys[x * LDC + q];
+      rxy += cj(ls[x * LDC + q], cs) * ys[y * LDC + q];
+      ryx += cj(ls[y * LDC + q], cs) * ys[x * LDC + q];
     }
-    X[r.off + y * ld + x] = SOps<T>::scale(0.5, (dxy + rxy) + (dyx + ryx));
+    X[r.off + y * ld + x] = SOps<T>::scale(0.5, (dxy + rxy) + cj(dyx + ryx, cs));
   }
 }
 

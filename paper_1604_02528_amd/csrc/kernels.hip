@@ -130,6 +130,7 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
   la.kend = kend;
   la.i0 = i0;
   la.en = en;
+  la.cs = pl.csign;
   LoadPanelK<T, false> lb{L, nd.off, ld, s, 0, kend, x0, s};
   Acc<T> acc;
   gemm_tile<T>(st, kend, la, lb, smem, acc);
@@ -157,7 +158,7 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
 }
 
 // Small nodes of one level, one wavefront each (see do_tiny).
-template <typename T>
+template <typename T, bool HERM>
 __global__ void __launch_bounds__(64) k_tiny(const DevPlan *__restrict__ plp, const T *Lp, T *Xp,
                                              const TinyRec *__restrict__ recs, int32_t count, int32_t list_pos) {
   const DevPlan &pl = *plp;
@@ -169,13 +170,13 @@ __global__ void __launch_bounds__(64) k_tiny(const DevPlan *__restrict__ plp, co
   const T *L = Lp + l * pl.panel_elems;
   T *X = Xp + l * pl.panel_elems;
   if (r.c <= 8)
-    do_tiny<T, 8>(r, pl.toff, L, X, ls, ys);
+    do_tiny<T, 8, HERM>(r, pl.toff, L, X, ls, ys);
   else if (r.c <= 16)
-    do_tiny<T, 16>(r, pl.toff, L, X, ls, ys);
+    do_tiny<T, 16, HERM>(r, pl.toff, L, X, ls, ys);
   else if constexpr (sizeof(T) == 16)  // complex plans list c <= kTinyC only
-    do_tiny<T, 32>(r, pl.toff, L, X, ls, ys);
+    do_tiny<T, 32, HERM>(r, pl.toff, L, X, ls, ys);
   else if (r.c <= 32)
-    do_tiny<T, 32>(r, pl.toff, L, X, ls, ys);
+    do_tiny<T, 32, HERM>(r, pl.toff, L, X, ls, ys);
   else
     do_tiny64<T>(r, pl.toff, L, X, ls, ys);
   if (pl.trace) {
@@ -424,7 +425,8 @@ __global__ void __launch_bounds__(NT) k_normalize_inv(const DevPlan *__restrict_
 // All of the normalization (Alg. 1 steps 1-2, LDL^T form of Section 2.3) of
 // a node with s <= kSmallNormS in one wavefront: L_KK^{-1} by forward
 // substitution (lane q owns column q), D^{-1}, Dt^{-1} = L_KK^{-T} D^{-1}
-// L_KK^{-1} into the top block, Dt = L_KK D L_KK^T when dt is given, and
+// L_KK^{-1} into the top block, Dt = L_KK D L_KK^T when dt is given (^H for
+// ^T in a Hermitian plan), and
 // Lhat_{C,K} = L_{C,K} L_KK^{-1} one row per lane.  L_KK is read into LDS
 // before anything is written, and each row of L_{C,K} is read by the lane that
 // overwrites it, so Src may alias Lp.
@@ -465,14 +467,15 @@ __global__ void __launch_bounds__(64) k_normalize_small(const DevPlan *__restric
   for (int u = 0; u < S * S / 64; ++u) {
     const int e = t + 64 * u, a = e % S, b = e / S;
     if (a < s && b < s) {
+      const double cs = pl.csign;
       T acc = zero_of<T>();
-      for (int k = a > b ? a : b; k < s; ++k) acc += (xs[k * SP + a] * dv[k]) * xs[k * SP + b];
+      for (int k = a > b ? a : b; k < s; ++k) acc += (cj(xs[k * SP + a], cs) * dv[k]) * xs[k * SP + b];
       P[(int64_t)b * ld + a] = acc;
       if (dt_all) {
         T dd = zero_of<T>();
         for (int k = 0; k <= (a < b ? a : b); ++k) {
           const T la = (a == k) ? SOps<T>::one() : lk[a * SP + k], lb = (b == k) ? SOps<T>::one() : lk[b * SP + k];
-          dd += (la * lk[k * SP + k]) * lb;
+          dd += (la * lk[k * SP + k]) * cj(lb, cs);
         }
         dt_all[l * pl.sq_elems + gp(pl.node_sq)[K] + (int64_t)b * s + a] = dd;
       }
@@ -534,7 +537,7 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
   }
 }
 
-// 32 x 32 output tiles of the s x s blocks:
+// 32 x 32 output tiles of the s x s blocks (^H for ^T in a Hermitian plan):
 //   mode 0: Dt = L_KK D L_KK^T              -> dt buffer (reads the LDL^T top block)
 //   mode 1: Dt^{-1} = Linv^T D^{-1} Linv    -> panel top block
 template <typename T>
@@ -578,6 +581,11 @@ __global__ void __launch_bounds__(NT) k_normalize_sq(const DevPlan *__restrict__
           if (ia < s) va = gload(Linv + (int64_t)ia * s + k);
           if (jb < s) vb = gload(Linv + (int64_t)jb * s + k);
         }
+        // the transposed factor: L_KK^T (mode 0, right) or Linv^T (mode 1, left)
+        if (mode == 0)
+          vb = cj(vb, pl.csign);
+        else
+          va = cj(va, pl.csign);
       }
 #pragma unroll
       for (int p = 0; p < Planes<T>::P; ++p) {
@@ -632,7 +640,9 @@ __global__ void k_extract(const DevPlan *__restrict__ plp, const T *Xp, T *out) 
   const int64_t total = pl.batch * pl.nnzA;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t l = q / pl.nnzA, e = q - l * pl.nnzA;
-    out[q] = Xp[l * pl.panel_elems + gp(pl.apos)[e]];
+    // an entry the permutation moved into B's upper triangle is the transpose
+    // of the stored one (conjugated in a Hermitian plan)
+    out[q] = cj(Xp[l * pl.panel_elems + gp(pl.apos)[e]], gp(pl.aflip)[e] ? pl.csign : 1.0);
   }
 }
 
@@ -646,14 +656,15 @@ __global__ void k_zero(const DevPlan *__restrict__ plp, T *P) {
     P[q] = zero_of<T>();
 }
 
-// P[l][position of A entry e] = vals[l][e] (the transpose of k_extract).
+// P[l][position of A entry e] = vals[l][e], conjugated where k_extract
+// conjugates (the transpose of k_extract).
 template <typename T>
 __global__ void k_scatter(const DevPlan *__restrict__ plp, const T *vals, T *P) {
   const DevPlan &pl = *plp;
   const int64_t total = pl.batch * pl.nnzA;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
     const int64_t l = q / pl.nnzA, e = q - l * pl.nnzA;
-    P[l * pl.panel_elems + gp(pl.apos)[e]] = vals[q];
+    P[l * pl.panel_elems + gp(pl.apos)[e]] = cj(vals[q], gp(pl.aflip)[e] ? pl.csign : 1.0);
   }
 }
 
@@ -749,7 +760,8 @@ static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
       const int32_t b = aux.lvl_ptr[q], e = aux.lvl_ptr[q + 1];
       if (e <= b) continue;
       if (aux.lvl_kind[q] == LVL_TINY)
-        hipLaunchKernelGGL(k_tiny<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(64), 0, st, dpl, Lp, Xp,
+        hipLaunchKernelGGL((pl.csign < 0 ? k_tiny<T, true> : k_tiny<T, false>), dim3((unsigned)((e - b) * pl.batch)),
+                           dim3(64), 0, st, dpl, Lp, Xp,
                            aux.tiny + aux.lvl_tiny[q], e - b, b);
       else if (aux.lvl_kind[q] == LVL_PUSH)
         hipLaunchKernelGGL(k_push<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp,

@@ -136,9 +136,12 @@ struct DevPlan {
   int32_t *node_parent; // [ns] supernodal etree parent (-1 at a root)
   int32_t *order;      // [batch * nitems] ticket -> l * nitems + item
   int32_t *lvl_items;  // item ids grouped by (level, phase)
-  uint32_t *toff;      // X_{C,C} offset tables of the single-wavefront nodes
+  uint32_t *toff;      // X_{C,C} offset tables of the single-wavefront nodes (bit 0 set on the
+                       // upper-triangle entries of a Hermitian plan: read conjugated)
   int64_t *apos;       // [nnzA] A entry -> panel element
   uint8_t *adiag;      // [nnzA]
+  uint8_t *aflip;      // [nnzA] the entry lands in B's upper triangle (conjugated if Hermitian)
+  double csign;        // -1: Hermitian plan (conjugate transposes), +1 otherwise
   // scratch
   void *linv;          // [batch][sq_elems] scalars
   void *dinv;          // [batch][n] scalars

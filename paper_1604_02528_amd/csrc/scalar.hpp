@@ -1,6 +1,7 @@
 // Scalar types shared by host and device code: real double and a plain
-// complex double (interleaved re, im; complex-symmetric arithmetic, so no
-// conjugation anywhere).  Division uses Smith's algorithm (R. L. Smith,
+// complex double (interleaved re, im).  Complex-symmetric plans use plain
+// transposes; Hermitian plans conjugate wherever a transpose appears, through
+// cj(v, cs) with cs = -1 (cs = +1 leaves v as it is).  Division uses Smith's algorithm (R. L. Smith,
 // "Algorithm 116: Complex division", CACM 5(8), 1962) to avoid overflow.
 #pragma once
 
@@ -24,6 +25,10 @@ SELINV_HD cplx operator*(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.
 SELINV_HD cplx operator*(double s, cplx a) { return {s * a.re, s * a.im}; }
 SELINV_HD cplx &operator+=(cplx &a, cplx b) { a.re += b.re; a.im += b.im; return a; }
 SELINV_HD cplx &operator-=(cplx &a, cplx b) { a.re -= b.re; a.im -= b.im; return a; }
+
+// v for cs = +1, conj(v) for cs = -1 (a Hermitian plan); real values pass through
+SELINV_HD double cj(double v, double) { return v; }
+SELINV_HD cplx cj(cplx v, double cs) { return {v.re, cs * v.im}; }
 
 SELINV_HD cplx cdiv(cplx a, cplx b) {
   // Smith's algorithm

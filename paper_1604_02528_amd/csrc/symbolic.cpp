@@ -64,11 +64,13 @@ void analyze(Symbolic &S, int64_t n, const int64_t *colptr, const int64_t *rowin
 
   // ---- B = P A P^T, lower CSC with rows ascending --------------------------
   std::vector<int64_t> ehi(nnz), elo(nnz);
+  S.aflip.assign(nnz, 0);
   for (int64_t j = 0; j < n; ++j)
     for (int64_t p = colptr[j]; p < colptr[j + 1]; ++p) {
       int64_t a = S.iperm[rowind[p]], b = S.iperm[j];
       ehi[p] = std::max(a, b);
       elo[p] = std::min(a, b);
+      S.aflip[p] = a < b ? 1 : 0;  // the stored lower entry lands in B's upper triangle
     }
   // bucket by row, then stable placement by column -> rows ascending per column
   std::vector<int64_t> rptr(n + 1, 0), byrow(nnz);

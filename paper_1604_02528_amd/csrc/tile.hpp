@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "plan.hpp"
 #include "scalar.hpp"
@@ -210,6 +211,16 @@ template <typename T> struct Vals {
 // from a clamped, valid address) are zeroed here, where the values are
 // consumed.  Masking at the load would make the compiler wait for every load
 // in the iteration that issued it, which serializes the pipeline.
+// A loader whose elements may be stored transposed (the upper triangle of a
+// Hermitian X_{C,C}) declares kConj and gives, per element, the factor of the
+// imaginary plane: -1 where the element is conjugated, else +1.
+template <class L, class = void> struct LoaderConj {
+  static constexpr bool value = false;
+};
+template <class L> struct LoaderConj<L, std::void_t<decltype(L::kConj)>> {
+  static constexpr bool value = L::kConj;
+};
+
 template <typename T, class L, class V, int TK = Planes<T>::TK>
 __device__ __forceinline__ void stage_store(double *stg, int plane_off, int k0, const L &ld, const V &v) {
   constexpr int P = Planes<T>::P;
@@ -219,7 +230,13 @@ __device__ __forceinline__ void stage_store(double *stg, int plane_off, int k0, 
     const int slot = ld.slot(k0, m);
     const T x = masked(v.v[m], ld.mask(k0, m));
 #pragma unroll
-    for (int p = 0; p < P; ++p) stg[(plane_off + p) * TK * PITCH + slot] = Planes<T>::get(x, p);
+    for (int p = 0; p < P; ++p) {
+      double y = Planes<T>::get(x, p);
+      if constexpr (LoaderConj<L>::value && P == 2) {
+        if (p == 1) y *= ld.imsign(k0, m);
+      }
+      stg[(plane_off + p) * TK * PITCH + slot] = y;
+    }
   }
 }
 
@@ -373,11 +390,13 @@ template <typename T, bool COH> struct LoadGather {
     int64_t base[E];
     int32_t pos[E];
   };
+  static constexpr bool kConj = true;
   const T *X;
   const int64_t *kcol, *kpos;  // node-local per-row tables (global)
   const int32_t *posarr;
   const int64_t *rt_col, *rt_pos;  // LDS copies for rows i0 .. i0+63
   int c, kend, i0;  // rows and columns of X_{C,C} < c; contraction indices < kend
+  double cs = 1.0;  // -1 in a Hermitian plan: the upper part is the conjugate of the stored lower part
   __device__ __forceinline__ void coords(int k0, int m, int &i, int &kk) const {
     constexpr int TK = Planes<T>::TK;
     const int e = threadIdx.x + NT * m;
@@ -398,6 +417,11 @@ template <typename T, bool COH> struct LoadGather {
     int i, kk;
     coords(k0, m, i, kk);
     return opaque_mask(i0 + i < c && k0 + kk < kend);
+  }
+  __device__ __forceinline__ double imsign(int k0, int m) const {
+    int i, kk;
+    coords(k0, m, i, kk);
+    return i0 + i < k0 + kk ? cs : 1.0;
   }
   // Each level loads unconditionally (clamped indices, opaque masks) and
   // keeps the raw results; they are combined one level later.
@@ -567,12 +591,15 @@ template <typename T, int TK> struct LoadDenseB {
 // slot, k0 + (t >> 6) + 4 m, is uniform in a wave.
 template <typename T, int TK> struct LoadDenseBT {
   static constexpr int E = 64 * TK / NT;
+  static constexpr bool kConj = true;  // the transposed operand: conjugated in a Hermitian plan
   const T *M;
   int64_t ld;
   int kend, kq;
   uint32_t vcol;
   int64_t cmask;
   bool cols_full;
+  double cs = 1.0;  // -1: conjugate every element
+  __device__ __forceinline__ double imsign(int, int) const { return cs; }
   __device__ __forceinline__ LoadDenseBT(const T *M_, int ld_, int kend_, int x0, int xmax)
       : M(M_), ld(ld_), kend(kend_) {
     const int x = x0 + (threadIdx.x & 63);
@@ -604,12 +631,20 @@ template <typename T, class L, class V, int TK>
 __device__ __forceinline__ void stage_store_dense(double *stg, int plane_off, int k0, const L &ld, const V &v) {
   constexpr int P = Planes<T>::P;
   constexpr int E = sizeof(v.v) / sizeof(v.v[0]);
+  // the imaginary plane's factor of a conjugating loader (see LoaderConj)
+  auto plane = [&](const T &x, int p, int m) {
+    double y = Planes<T>::get(x, p);
+    if constexpr (LoaderConj<L>::value && P == 2) {
+      if (p == 1) y *= ld.imsign(k0, m);
+    }
+    return y;
+  };
   if (uniform(ld.all_valid(k0) ? 1 : 0)) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int slot = ld.slot(k0, m);
 #pragma unroll
-      for (int p = 0; p < P; ++p) stg[(plane_off + p) * TK * PITCH + slot] = Planes<T>::get(v.v[m], p);
+      for (int p = 0; p < P; ++p) stg[(plane_off + p) * TK * PITCH + slot] = plane(v.v[m], p, m);
     }
   } else {
 #pragma unroll
@@ -617,7 +652,7 @@ __device__ __forceinline__ void stage_store_dense(double *stg, int plane_off, in
       const int slot = ld.slot(k0, m);
       const T x = masked(v.v[m], ld.mask(k0, m));
 #pragma unroll
-      for (int p = 0; p < P; ++p) stg[(plane_off + p) * TK * PITCH + slot] = Planes<T>::get(x, p);
+      for (int p = 0; p < P; ++p) stg[(plane_off + p) * TK * PITCH + slot] = plane(x, p, m);
     }
   }
 }

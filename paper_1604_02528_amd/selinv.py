@@ -1,6 +1,6 @@
 """High-level handle over the C ABI: device buffers and streams from torch.
 
-    S = SelInv(n, colptr, rowind, perm, dtype="f64", batch=1)
+    S = SelInv(n, colptr, rowind, perm, dtype="f64", batch=1)   # or "c128" (complex-symmetric), "h128" (Hermitian)
     S.factor(values)          # host LDL^T + upload + normalize kernels
     S.run()                   # selected inversion on the GPU (async)
     X = S.extract()           # [batch, nnz(A)] selected entries on A's pattern
@@ -30,12 +30,16 @@ class SelInv:
                  sched="levels", nthreads=0, watchdog_ms=0, dense_min_c=0, dense_max_bytes=0, split_min_k=0,
                  tune_cache=None, adjoint=True, device="cuda"):
         self.n = int(n)
-        self.is_complex = dtype in ("c128", "complex128", torch.complex128)
+        if dtype not in ("f64", "float64", torch.float64, "c128", "complex128", torch.complex128, "h128", "hermitian"):
+            raise ValueError(f"unknown dtype {dtype!r} (f64, c128 = complex-symmetric, h128 = Hermitian)")
+        self.is_hermitian = dtype in ("h128", "hermitian")
+        self.is_complex = self.is_hermitian or dtype in ("c128", "complex128", torch.complex128)
         self.batch = int(batch)
         self.device = device
         o = capi.selinv_default_opts()
         o.max_super = int(cap)
-        o.dtype = capi.SELINV_C128 if self.is_complex else capi.SELINV_R64
+        o.dtype = (capi.SELINV_H128 if self.is_hermitian else
+                   capi.SELINV_C128 if self.is_complex else capi.SELINV_R64)
         o.batch = self.batch
         o.sched = {"levels": capi.SCHED_LEVELS, "persistent": capi.SCHED_PERSISTENT, "push": capi.SCHED_PUSH}[sched]
         o.relax = float(relax)

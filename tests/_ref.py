@@ -24,11 +24,12 @@ def oracle_x(name, scale=None, batch=None, relax=0.0):
     """Flattened oracle X panels [batch, panel_elems] (Alg. 1)."""
     w = workload(name, scale, batch)
     sym = oracle_sym(name, scale, batch, relax)
+    h = w.is_hermitian
     out = []
     for l in range(w.batch):
-        P = factor.factor(sym, w.values[l])
-        lh, dt = factor.normalize(sym, P)
-        out.append(selinv.flatten(sym, selinv.alg1(sym, lh, dt)))
+        P = factor.factor(sym, w.values[l], herm=h)
+        lh, dt = factor.normalize(sym, P, herm=h)
+        out.append(selinv.flatten(sym, selinv.alg1(sym, lh, dt, herm=h)))
     return np.stack(out)
 
 

@@ -11,7 +11,7 @@ from workloads import random_pattern
 def lib_ctx(w, relax, cap=None):
     from paper_1604_02528_amd import SelInv
 
-    return SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="c128" if w.is_complex else "f64", batch=w.batch,
+    return SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=w.dtype, batch=w.batch,
                   cap=cap or w.cap, relax=relax, device="cpu")
 
 
@@ -83,3 +83,49 @@ def test_scheduler_plan_replay(name, scale, batch, relax):
     w = workload(name, scale, batch)
     S = lib_ctx(w, relax)
     capi.selinv_check_plan(S.h)
+
+
+@pytest.mark.parametrize("relax", [0.0, 0.05])
+@pytest.mark.parametrize("scale,batch", [(6, 2), (10, 3)])
+def test_host_factor_hermitian_matches_oracle(scale, batch, relax):
+    """The library's host LDL^H (dtype h128) against the oracle's Hermitian
+    factorization, and its log det (real for these positive definite shifts)."""
+    from paper_1604_02528_amd import SelInv
+
+    w = workload("H3", scale, batch)
+    sym = oracle_sym("H3", scale, batch, relax)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="h128", batch=w.batch, cap=w.cap, relax=relax, device="cpu")
+    P = S.factor_host(w.values)[:, S.packed_index()]
+    mask = np.concatenate([np.tril(np.ones((sym.width(K) + sym.rows[K].shape[0], sym.width(K)), bool)).reshape(-1, order="F")
+                           for K in range(sym.nsuper)])
+    for l in range(w.batch):
+        Pref = factor.factor(sym, w.values[l], herm=True)
+        ref = selinv.flatten(sym, Pref)
+        err = np.max(np.abs(P[l][mask] - ref[mask])) / np.max(np.abs(ref[mask]))
+        assert err < 1e-13
+        ld = S.logdet()[l]
+        ref_ld = factor.logdet(sym, Pref)
+        assert abs(ld.real - np.real(ref_ld)) <= 1e-10 * max(1.0, abs(ref_ld))
+        assert abs(ld.imag) <= 1e-10
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_host_factor_hermitian_random_permuted(seed):
+    """Random Hermitian patterns under random permutations: the entries that
+    the permutation moves into the upper triangle enter conjugated."""
+    from paper_1604_02528_amd import SelInv
+    from tests.test_oracle_hermitian import hermitian_random
+    from oracle import symbolic
+
+    rng = np.random.default_rng(700 + seed)
+    n = int(rng.integers(20, 120))
+    colptr, rowind, v = hermitian_random(n, 0.08, rng, indefinite=bool(seed % 2))
+    perm = rng.permutation(n).astype(np.int64)
+    cap = int(rng.integers(2, 30))
+    sym = symbolic.analyze(n, colptr, rowind, perm, cap=cap)
+    S = SelInv(n, colptr, rowind, perm, dtype="h128", batch=1, cap=cap, relax=0.0, device="cpu")
+    P = S.factor_host(v[None, :])[:, S.packed_index()]
+    ref = selinv.flatten(sym, factor.factor(sym, v, herm=True))
+    mask = np.concatenate([np.tril(np.ones((sym.width(K) + sym.rows[K].shape[0], sym.width(K)), bool)).reshape(-1, order="F")
+                           for K in range(sym.nsuper)])
+    assert np.max(np.abs(P[0][mask] - ref[mask])) <= 1e-13 * np.max(np.abs(ref[mask]))
