@@ -70,6 +70,8 @@ struct HostPlan {
   std::vector<int32_t> lvl_items, lvl_ptr, lvl_tiny, lvl_kind;
   std::vector<int32_t> node_defer;  // GEMM-2 of the node in ITEM_P items (level schedule, dense buffer, unsplit)
   std::vector<int32_t> node_ykern;  // GEMM-1 tiles in k_ydense (level schedule, dense buffer)
+  std::vector<int8_t> node_y128;    // ... on 128 x 128 tiles in k_ydense128 (FP64, tune table)
+  std::vector<Item> y128;           // the k_ydense128 records, in launch order
   std::vector<int8_t> node_tuned;   // a tune-table entry applied to the node
   int32_t lvl_top = 0;        // level launches of the top depths (see LaunchAux)
   int32_t norm_top[5] = {0, 0, 0, 0, 0};  // their normalization entries: small, narrow, chunks, rblocks, sq
@@ -96,7 +98,7 @@ struct HostPlan {
     int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
         nph, node_split, node_kchunk, node_yoff, node_goff, node_ldg, node_parent, order, lvl_items, lvl_recs, chunks, chunks_narrow, rblocks, small_nodes,
         sq_tiles, tiny, toff,
-        apos, adiag, aflip, bitems, pushrecs, fac_nodes, fac_cn, fac_cw, fac_rb, fac_tiles, dpos, plan, linv, dinv, part, gbuf, ypart,
+        apos, adiag, aflip, bitems, pushrecs, y128recs, fac_nodes, fac_cn, fac_cw, fac_rb, fac_tiles, dpos, plan, linv, dinv, part, gbuf, ypart,
         cnt, ctrl, fwd_end, adj_z, adj_l, adj_s, adj_t, adj_f, adj_d, ferr, fldet, end;
   } off{};
   int64_t tables_bytes = 0;  // [0, tables_bytes) is uploaded once
@@ -306,7 +308,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     tt = nullptr;
   }
   // per-node choices from the tune table (bucket of (s, c)), else the defaults
-  std::vector<int8_t> dense_pref(ns, -1), ykern_pref(ns, -1);
+  std::vector<int8_t> dense_pref(ns, -1), ykern_pref(ns, -1), tile128(ns, 0);
   std::vector<int64_t> node_mink(ns, split_min_k);
   H.node_tuned.assign(ns, 0);
   if (tt)
@@ -316,6 +318,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
         if (e->dense >= 0) dense_pref[K] = (int8_t)(e->dense != 0);
         if (e->ydense >= 0) ykern_pref[K] = (int8_t)(e->ydense != 0);
         if (e->split_min_k != 0) node_mink[K] = e->split_min_k;
+        if (e->tile == 128 && scalar_bytes == 8) tile128[K] = 1;
       }
   H.node_s.resize(ns);
   H.node_c.resize(ns);
@@ -416,12 +419,14 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   // shares move to ITEM_P items of phase 2.
   H.node_defer.assign(ns, 0);
   H.node_ykern.assign(ns, 0);
+  H.node_y128.assign(ns, 0);
   if (push)
     for (int64_t K = 0; K < ns; ++K) H.node_defer[K] = S.nrows(K) > 0;
   if (per_level && !push)
     for (int64_t K = 0; K < ns; ++K)
       if (H.node_goff[K] >= 0 && ykern_pref[K] != 0 && !(S.nrows(K) <= kSmallC && S.width(K) <= kSmallS)) {
         H.node_ykern[K] = 1;
+        H.node_y128[K] = tile128[K];
         if (H.node_yoff[K] < 0) H.node_defer[K] = 1;
       }
   std::vector<int64_t> rtiles(S.depth, 0);
@@ -502,6 +507,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   const int64_t tiny_cf = scalar_bytes == 8 ? kTinyCF : kTinyC;
   auto adj_tiny = [&](int64_t K) { return !push && tiny_ok && H.node_c[K] <= kTinyC && H.node_s[K] <= kTinyS; };
   H.push.clear();
+  H.y128.clear();
   if (push) {
     // per depth, root first: the D step of the depth's nodes (P items, then
     // D items), then every tile its nodes push into their descendants
@@ -564,10 +570,25 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
           for (int64_t K : bydepth[d]) {
             if (ph == 3 && is_tiny(K)) continue;
             if (ph == 1 && per_level && (H.node_ykern[K] != 0) != (pass == 1)) continue;
+            if (ph == 1 && H.node_y128[K]) continue;  // launched on 128 x 128 tiles below
             const int32_t b = phase_begin(H, K, ph), n = phase_count(H, K, ph);
             for (int32_t q = 0; q < n; ++q) H.lvl_items.push_back(b + q);
           }
           close(-1, pass == 1 ? LVL_YDENSE : LVL_ITEMS);
+        }
+        if (ph == 1) {
+          // 128 x 128 GEMM-1 tiles of the depth's FP64 dense-buffer nodes the tune table marks
+          const int32_t first = (int32_t)H.y128.size();
+          for (int64_t K : bydepth[d]) {
+            if (!H.node_y128[K]) continue;
+            const int32_t nr = (H.node_c[K] + 127) / 128, nb = (H.node_s[K] + 127) / 128;
+            for (int32_t part = 0; part < H.node_split[K]; ++part)
+              for (int32_t a = 0; a < nr; ++a)
+                for (int32_t bb = 0; bb < nb; ++bb)
+                  H.y128.push_back(Item{(int32_t)K, ITEM_Y, a, bb | (part << 16)});
+          }
+          for (int32_t q = first; q < (int32_t)H.y128.size(); ++q) H.lvl_items.push_back(q);
+          close(first, LVL_Y128);
         }
       }
       const int32_t tiny_base = (int32_t)H.tiny.size();
@@ -602,9 +623,10 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   }
   H.lvl_recs.resize(H.lvl_items.size());
   for (size_t q = 0; q < H.lvl_items.size(); ++q) {
-    if (push && H.lvl_kind[std::upper_bound(H.lvl_ptr.begin(), H.lvl_ptr.end(), (int32_t)q) - H.lvl_ptr.begin() - 1] ==
-                    LVL_PUSH) {
-      H.lvl_recs[q] = LRec{};  // push tiles carry their own records
+    const int32_t kind =
+        H.lvl_kind[std::upper_bound(H.lvl_ptr.begin(), H.lvl_ptr.end(), (int32_t)q) - H.lvl_ptr.begin() - 1];
+    if (kind == LVL_PUSH || kind == LVL_Y128) {
+      H.lvl_recs[q] = LRec{};  // push tiles and 128-tile records carry their own records
       continue;
     }
     const Item &it = H.items[H.lvl_items[q]];
@@ -811,6 +833,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.aflip = take((int64_t)H.aflip.size());
   o.bitems = take(16 * (int64_t)H.bitems.size());
   o.pushrecs = take((int64_t)sizeof(PushRec) * (int64_t)H.push.size());
+  o.y128recs = take((int64_t)sizeof(Item) * (int64_t)H.y128.size());
   o.fac_nodes = take(4 * (int64_t)H.fac_nodes.size());
   o.fac_cn = take(8 * (int64_t)H.fac_cn.size());
   o.fac_cw = take(8 * (int64_t)H.fac_cw.size());
@@ -1020,6 +1043,7 @@ LaunchAux make_aux(const selinv_ctx *h, void *work) {
   a.lvl_tiny = H.lvl_tiny.data();
   a.lvl_kind = H.lvl_kind.data();
   a.push = (const PushRec *)(b + H.off.pushrecs);
+  a.y128 = (const Item *)(b + H.off.y128recs);
   a.tiny = (const TinyRec *)(b + H.off.tiny);
   a.nlvl = (int32_t)H.lvl_ptr.size() - 1;
   a.blaunch = H.blaunch.data();
@@ -1072,6 +1096,7 @@ void build_image(selinv_ctx *h) {
   put(img, o.aflip, H.aflip);
   put(img, o.bitems, H.bitems);
   put(img, o.pushrecs, H.push);
+  put(img, o.y128recs, H.y128);
   put(img, o.fac_nodes, H.fac_nodes);
   put(img, o.fac_cn, H.fac_cn);
   put(img, o.fac_cw, H.fac_cw);
@@ -1672,7 +1697,11 @@ selinv_status selinv_items(const selinv_ctx *hc, int32_t which, const int32_t **
       for (size_t q = 0; q + 1 < H.lvl_ptr.size(); ++q) {
         const int32_t first = H.lvl_ptr[q], cnt = H.lvl_ptr[q + 1] - first;
         int32_t type = -1;
-        if (H.lvl_kind[q] != LVL_PUSH) {
+        if (H.lvl_kind[q] == LVL_Y128) {
+          const Item &it = H.y128[H.lvl_items[first]];
+          type = it.type;
+          depth = (int32_t)h->S.sdepth[it.K];
+        } else if (H.lvl_kind[q] != LVL_PUSH) {
           const Item &it = H.items[H.lvl_items[first]];
           type = it.type;
           depth = (int32_t)h->S.sdepth[it.K];

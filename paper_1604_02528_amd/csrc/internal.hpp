@@ -56,6 +56,7 @@ struct TuneEntry {
   std::string arch, rocm, dtype;
   int64_t s_max = 0, c_max = 0;
   int dense = -1, ydense = -1, split_min_k = 0;  // -1: not given
+  int tile = 0;                                   // 0: not given; 64 or 128
 };
 struct TuneTable {
   std::vector<TuneEntry> entries;  // those of this target, ROCm version and dtype

@@ -157,6 +157,66 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
   }
 }
 
+// GEMM-1 of FP64 dense-buffer nodes on 128 x 128 tiles (the tune table's
+// tile choice): record {K, type, a, b} names the node, 128-row tile a of C(K)
+// and, in b, the 128-column tile of K (low 16 bits) and the contraction part
+// (high bits).  Like k_ydense: no GEMM-2 here; the tile goes to X (-acc) or
+// to the split contraction's partial tiles.  Each lane stores its
+// accumulator elements directly: per store, the four lanes of a block column
+// write four consecutive rows (32 bytes).
+__global__ void __launch_bounds__(NT, 2) k_ydense128(const DevPlan *__restrict__ plp, const double *Lp, double *Xp,
+                                                     const Item *recs, int32_t count, int32_t list_pos) {
+  const DevPlan &pl = *plp;
+  __shared__ double smem[2 * stage128_doubles()];
+  const int64_t g = blockIdx.x;
+  const int64_t l = g / count;
+  const int64_t q = g - l * count;
+  const int64_t t_start = pl.trace ? wall_clock64() : 0;
+  const Item it = uniform(gload(recs + q));
+  const NodeInfo nd = node_info(pl, it.K);
+  const int s = nd.s, c = nd.c, ld = s + c;
+  const int part = it.b >> 16;
+  const int kb = part * nd.kchunk, ke = min(c, kb + nd.kchunk);
+  const int i0 = it.a * 128, j0 = (it.b & 0xffff) * 128;
+  const double *G = static_cast<const double *>(pl.gbuf) + l * pl.g_elems + nd.goff;
+  LoadDenseA128 la{G, nd.ldg, c, ke, i0};
+  LoadDenseB128 lb{Lp + l * pl.panel_elems, nd.off, ld, s, ke, j0, s};
+  Acc128 acc;
+  gemm_dense128(kb, ke, la, lb, smem, acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w & 1, wj = w >> 1;
+  const bool to_x = nd.yoff < 0;
+  double *dst = to_x ? Xp + l * pl.panel_elems + nd.off + s
+                     : static_cast<double *>(pl.ypart) + l * pl.y_elems + nd.yoff + (int64_t)part * c * s;
+  const int64_t ldd = to_x ? ld : c;
+  const double sg = to_x ? -1.0 : 1.0;
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) {
+      // accumulator element v of a lane: row 4 v + lane / 16, column lane % 16 of the block
+      const int j = j0 + 64 * wj + 16 * bj + (lane & 15);
+      const int ib = i0 + 64 * wi + 16 * bi + (lane >> 4);
+      if (j < s) {
+        double *col = dst + (int64_t)j * ldd;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (ib + 4 * v < c) gstore(col + ib + 4 * v, sg * acc.v[bi][bj][v]);
+      }
+    }
+  if (pl.trace) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t *tr = pl.trace + 8 * ((int64_t)list_pos * pl.batch + g);
+      tr[0] = -1 - q;  // 128-tile records are not items: the row names the record
+      tr[1] = blockIdx.x;
+      tr[2] = t_start;
+      tr[3] = t_start;
+      tr[4] = wall_clock64();
+    }
+  }
+}
+
 // Small nodes of one level, one wavefront each (see do_tiny).
 template <typename T, bool HERM>
 __global__ void __launch_bounds__(64) k_tiny(const DevPlan *__restrict__ plp, const T *Lp, T *Xp,
@@ -766,7 +826,12 @@ static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
       else if (aux.lvl_kind[q] == LVL_PUSH)
         hipLaunchKernelGGL(k_push<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp,
                            aux.push + aux.lvl_tiny[q], e - b, b);
-      else if (aux.lvl_kind[q] == LVL_YDENSE)
+      else if (aux.lvl_kind[q] == LVL_Y128) {
+        if constexpr (sizeof(T) == 8)
+          hipLaunchKernelGGL(k_ydense128, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl,
+                             reinterpret_cast<const double *>(Lp), reinterpret_cast<double *>(Xp),
+                             aux.y128 + aux.lvl_tiny[q], e - b, b);
+      } else if (aux.lvl_kind[q] == LVL_YDENSE)
         hipLaunchKernelGGL(k_ydense<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp,
                            aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
       else

@@ -708,4 +708,169 @@ __device__ __forceinline__ void gemm_dense(int kb, int ke, const LA &la, const L
   lds_barrier();  // the caller reuses the stage buffers
 }
 
+
+// ---------------------------------------------------------------------------
+// 128 x 128 FP64 tile (GEMM-1 of large dense-buffer nodes, a tune-table
+// choice).  Each wave owns a 64 x 64 quadrant (4 x 4 blocks of 16 x 16), so a
+// 16-deep stage carries 64 MFMAs per wave for the same 32 KB of operands as a
+// 32-deep stage of the 64 x 64 tile (which carries 32): twice the flops per
+// byte read through L2, for the FP64 case where the 64 x 64 tile is bound by
+// the operand traffic rather than by the matrix cores.
+// ---------------------------------------------------------------------------
+constexpr int kT128K = 16;      // contraction indices per stage
+constexpr int PITCH128 = 129;   // LDS row pitch (doubles) of a 128-wide operand plane
+
+struct Acc128 {
+  d4 v[4][4];
+};
+
+__device__ __forceinline__ constexpr int stage128_doubles() { return 2 * kT128K * PITCH128; }
+
+// A(i, k) = G[k * ldg + i0 + i], i < 128 (column-major): lanes along i, the
+// contraction index of a slot (k0 + (t >> 7) + 2 m) is uniform in a wave.
+struct LoadDenseA128 {
+  static constexpr int E = 128 * kT128K / NT;
+  const double *G;
+  int64_t ldg;
+  int kend, kq;
+  uint32_t vrow;
+  int64_t rmask;
+  bool rows_full;
+  __device__ __forceinline__ LoadDenseA128(const double *G_, int ldg_, int rows, int kend_, int i0)
+      : G(G_), ldg(ldg_), kend(kend_) {
+    const int i = i0 + (threadIdx.x & 127);
+    kq = uniform((int)(threadIdx.x >> 7));
+    vrow = (uint32_t)(i < rows ? i : 0) * 8u;
+    rmask = opaque_mask(i < rows);
+    rows_full = i0 + 128 <= rows;
+  }
+  __device__ __forceinline__ int slot(int m) const {
+    const int e = threadIdx.x + NT * m;
+    return (e >> 7) * PITCH128 + (e & 127);
+  }
+  __device__ __forceinline__ bool all_valid(int k0) const { return rows_full && k0 + kT128K <= kend; }
+  __device__ __forceinline__ int64_t mask(int k0, int m) const {
+    return rmask & opaque_mask(k0 + kq + (NT / 128) * m < kend);
+  }
+  __device__ __forceinline__ void load(int k0, double (&v)[E]) const {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int k = min(k0 + kq + (NT / 128) * m, kend - 1);
+      v[m] = ld_off(G + (int64_t)k * ldg, vrow);
+    }
+  }
+};
+
+// B(kk, x) = P[off + (x0 + x) * ld + s + k0 + kk], x < 128: a column block of
+// a panel's bottom part, k-major.  Slot m of a thread: kk = t % 16,
+// x = t / 16 + 16 m.
+struct LoadDenseB128 {
+  static constexpr int E = 128 * kT128K / NT;
+  const double *Pn;
+  int kend, kk, xq, x0, xmax;
+  uint32_t voff[E];
+  bool cols_full;
+  __device__ __forceinline__ LoadDenseB128(const double *Pn_, int64_t off, int ld, int s, int kend_, int x0_, int xmax_)
+      : Pn(Pn_ + off), kend(kend_), x0(x0_), xmax(xmax_) {
+    kk = threadIdx.x % kT128K;
+    xq = threadIdx.x / kT128K;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int x = min(x0 + xq + (NT / kT128K) * m, xmax - 1);
+      voff[m] = (uint32_t)((int64_t)x * ld + s + kk) * 8u;
+    }
+    cols_full = x0 + 128 <= xmax;
+  }
+  __device__ __forceinline__ int slot(int m) const {
+    const int e = threadIdx.x + NT * m;
+    return (e % kT128K) * PITCH128 + e / kT128K;
+  }
+  __device__ __forceinline__ bool all_valid(int k0) const { return cols_full && k0 + kT128K <= kend; }
+  __device__ __forceinline__ int64_t mask(int k0, int m) const {
+    return opaque_mask(k0 + kk < kend && x0 + xq + (NT / kT128K) * m < xmax);
+  }
+  __device__ __forceinline__ void load(int k0, double (&v)[E]) const {
+    const int over = k0 + kk - (kend - 1);  // the last stage clamps kk onto kend - 1
+    const uint32_t back = (uint32_t)(over > 0 ? over : 0) * 8u;
+    const double *base = Pn + k0;
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = ld_off(base, voff[m] - back);
+  }
+};
+
+template <class L>
+__device__ __forceinline__ void stage128_store(double *plane, int k0, const L &ld, const double (&v)[L::E]) {
+  if (uniform(ld.all_valid(k0) ? 1 : 0)) {
+#pragma unroll
+    for (int m = 0; m < L::E; ++m) plane[ld.slot(m)] = v[m];
+  } else {
+#pragma unroll
+    for (int m = 0; m < L::E; ++m) plane[ld.slot(m)] = masked(v[m], ld.mask(k0, m));
+  }
+}
+
+// One stage: A plane [k][i] then B plane [k][x], both kT128K x PITCH128.
+__device__ __forceinline__ void stage128_compute(const double *stg, Acc128 &acc) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w & 1, wj = w >> 1;
+#pragma unroll
+  for (int k4 = 0; k4 < kT128K / 4; ++k4) {
+    const int r = (4 * k4 + (lane >> 4)) * PITCH128 + (lane & 15);
+    double a[4], b[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      a[x] = stg[r + 64 * wi + 16 * x];
+      b[x] = stg[kT128K * PITCH128 + r + 64 * wj + 16 * x];
+    }
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) acc.v[bi][bj] = mfma16(a[bi], b[bj], acc.v[bi][bj]);
+  }
+}
+
+// acc = A (128 x [kb, ke)) * B ([kb, ke) x 128), the two-register-set
+// pipeline of gemm_dense.  kb and ke must be wave-uniform.
+__device__ __forceinline__ void gemm_dense128(int kb, int ke, const LoadDenseA128 &la, const LoadDenseB128 &lb,
+                                              double *smem, Acc128 &acc) {
+  constexpr int TK = kT128K, SD = stage128_doubles();
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc.v[bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+  const int nk = (ke - kb + TK - 1) / TK;
+  if (nk <= 0) return;
+  const int klast = kb + (nk - 1) * TK;
+  auto kat = [&](int j) { return min(kb + j * TK, klast); };
+  double a0[LoadDenseA128::E], b0[LoadDenseB128::E], a1[LoadDenseA128::E], b1[LoadDenseB128::E];
+  la.load(kb, a0);
+  lb.load(kb, b0);
+  la.load(kat(1), a1);
+  lb.load(kat(1), b1);
+  stage128_store(smem, kb, la, a0);
+  stage128_store(smem + TK * PITCH128, kb, lb, b0);
+  la.load(kat(2), a0);
+  lb.load(kat(2), b0);
+  lds_barrier();
+  for (int kt = 0;; kt += 2) {
+    stage128_compute(smem, acc);
+    if (kt + 1 >= nk) break;
+    stage128_store(smem + SD, kat(kt + 1), la, a1);
+    stage128_store(smem + SD + TK * PITCH128, kat(kt + 1), lb, b1);
+    lds_barrier();
+    la.load(kat(kt + 3), a1);
+    lb.load(kat(kt + 3), b1);
+    __builtin_amdgcn_sched_barrier(0);
+    stage128_compute(smem + SD, acc);
+    if (kt + 2 >= nk) break;
+    stage128_store(smem, kat(kt + 2), la, a0);
+    stage128_store(smem + TK * PITCH128, kat(kt + 2), lb, b0);
+    lds_barrier();
+    la.load(kat(kt + 4), a0);
+    lb.load(kat(kt + 4), b0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  lds_barrier();
+}
+
 }  // namespace selinv

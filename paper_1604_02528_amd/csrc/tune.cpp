@@ -17,6 +17,8 @@
 //                and GEMM-2 in separate items (level schedule); 0: fused
 //   split_min_k  shortest contraction part of a split GEMM-1 (0: library
 //                default, < 0: never split)
+//   tile         64 or 128: the GEMM-1 tile of a node whose tiles run in the
+//                GEMM-1-only kernel (128 x 128 for FP64 plans only; absent: 64)
 #include <cctype>
 #include <cstdio>
 #include <cstdlib>
@@ -121,7 +123,10 @@ TuneEntry read_entry(Reader &r) {
       else if (k == "dense") e.dense = (int)r.num();
       else if (k == "ydense") e.ydense = (int)r.num();
       else if (k == "split_min_k") e.split_min_k = (int)r.num();
-      else r.skip();
+      else if (k == "tile") {
+        e.tile = (int)r.num();
+        if (e.tile != 64 && e.tile != 128) bad(r.path, "\"tile\" must be 64 or 128");
+      } else r.skip();
     } while (r.peek(',') && (r.expect(','), true));
   }
   r.expect('}');

@@ -9,6 +9,8 @@ Choices per bucket (see csrc/tune.cpp for the file format):
   dense_fused   dense buffer; GEMM-1 tiles with their GEMM-2 share fused, in
                 the general item kernel
   gather        X_{C,C} gathered by the GEMM-1 tiles on the fly (no buffer)
+  dense_ydense128  as dense_ydense on 128 x 128 tiles (FP64 only: the tile
+                shape is the choice)
 and, per workload dtype, the shortest part of a split contraction.
 
 Method: coordinate descent on measured time.  Starting from the library
@@ -43,7 +45,9 @@ CHOICES = {
     "dense_ydense": {"dense": 1, "ydense": 1},
     "dense_fused": {"dense": 1, "ydense": 0},
     "gather": {"dense": 0, "ydense": 0},
+    "dense_ydense128": {"dense": 1, "ydense": 1, "tile": 128},  # FP64 only
 }
+FP64_ONLY = {"dense_ydense128"}
 SPLITS = (128, 320, 640)
 
 
@@ -75,7 +79,7 @@ class Trial:
         from . import SelInv
 
         self.w, self.relax, self.reps = w, relax, reps
-        self.dt = "c128" if w.is_complex else "f64"
+        self.dt = w.dtype
         S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=self.dt, batch=w.batch, cap=w.cap, relax=relax)
         vals = torch.from_numpy(np.ascontiguousarray(w.values)).to("cuda")
         self.ldlt = S.factor_device(vals)
@@ -133,7 +137,7 @@ def tune_workload(name, relax, reps, key_arch, key_rocm):
     from workloads import config
 
     w = config(name)
-    dtype = "c128" if w.is_complex else "f64"
+    dtype = "c128" if w.is_complex else "f64"  # table key: Hermitian plans run the complex kernels
     print(f"tuning on {name} ({dtype}, N={w.n}, batch {w.batch})", flush=True)
     tr = Trial(w, relax, reps)
     counts = tr.buckets()
@@ -146,7 +150,7 @@ def tune_workload(name, relax, reps, key_arch, key_rocm):
         if b[1] <= 64:  # single-item / single-wavefront nodes: no GEMM-1 tile to choose
             continue
         for ch in CHOICES:
-            if ch == choice[b]:
+            if ch == choice[b] or (ch in FP64_ONLY and dtype != "f64"):
                 continue
             trial = dict(choice)
             trial[b] = ch

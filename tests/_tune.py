@@ -10,6 +10,7 @@ FORCED = {
     "dense_ydense": {"dense": 1, "ydense": 1},
     "dense_fused": {"dense": 1, "ydense": 0},
     "gather": {"dense": 0, "ydense": 0},
+    "dense_ydense128": {"dense": 1, "ydense": 1, "tile": 128},
 }
 
 
