@@ -195,3 +195,93 @@ def to_dense_L(sym, panels):
         L[f:l1, f:l1] = np.tril(P[:s, :s], -1) + np.eye(s, dtype=dtype)
         L[np.ix_(sym.rows[K], np.arange(f, l1))] = P[s:, :]
     return L, D
+
+
+# ---------------------------------------------------------------------------
+# Unsymmetric A with a symmetric pattern: B = L D U (Alg. 1 and Alg. 2 in
+# their LU form).  Two panel sets share the layout of L: ``PL`` holds L (strict
+# lower top block, D on the diagonal, L_{C,K} below) and ``PU`` holds U^T the
+# same way (U unit upper, so U^T is unit lower; D again on the diagonal, and
+# U_{K,C}^T below).  A's values come as the stored lower values a_lo[e] =
+# A(r, c) and their mirrors a_up[e] = A(c, r) (r >= c, equal on the diagonal).
+# ---------------------------------------------------------------------------
+
+def b_values_lu(sym, a_lo, a_up):
+    """(B's lower values, B's upper values transposed) in B's lower CSC order:
+    an A entry the permutation moves into B's upper triangle swaps roles."""
+    a_lo, a_up = np.asarray(a_lo), np.asarray(a_up)
+    low = np.where(sym.aflip, a_up, a_lo)
+    up = np.where(sym.aflip, a_lo, a_up)
+    bl, bu = np.empty_like(low), np.empty_like(up)
+    bl[sym.amap] = low
+    bu[sym.amap] = up
+    return bl, bu
+
+
+def factor_lu(sym, a_lo, a_up):
+    """Unpivoted supernodal LDU of B = P A P^T: returns (PL, PU)."""
+    bl, bu = b_values_lu(sym, a_lo, a_up)
+    PL, PU = assemble(sym, bl), assemble(sym, bu)
+    xs = sym.xsuper
+    for K in range(sym.nsuper):
+        L, U = PL[K], PU[K]
+        s = sym.width(K)
+        f = int(xs[K])
+        for jj in range(s):
+            d = L[jj, jj]
+            if d == 0 or not np.isfinite(d):
+                raise ZeroPivot(f + jj, d)
+            lrow = L[jj + 1:s, jj].copy()  # L_k d, k in the block
+            urow = U[jj + 1:s, jj].copy()  # d U_k
+            lcol = L[jj + 1:, jj] / d
+            ucol = U[jj + 1:, jj] / d
+            # B(i, k) -= L_i d U_k: the lower part in PL, the upper part (transposed) in PU
+            L[jj + 1:, jj + 1:] -= np.outer(lcol, urow)
+            U[jj + 1:, jj + 1:] -= np.outer(ucol, lrow)
+            L[jj + 1:, jj] = lcol
+            U[jj + 1:, jj] = ucol
+            U[jj, jj] = d
+        C = sym.rows[K]
+        c = C.shape[0]
+        if c == 0:
+            continue
+        Dk = np.diag(L[:s, :s]).copy()
+        Lc, Uc = L[s:, :], U[s:, :]
+        SL = (Lc * Dk[None, :]) @ Uc.T   # S(a, b) = sum_j L_a D_j U_b, lower part into PL
+        SU = (Uc * Dk[None, :]) @ Lc.T   # S(b, a) for a >= b, transposed into PU
+        g0, g1 = sym.seg_ptr[K], sym.seg_ptr[K + 1]
+        for g in range(g0, g1):
+            J = int(sym.seg_super[g])
+            st = int(sym.seg_start[g])
+            en = int(sym.seg_start[g + 1]) if g + 1 < g1 else c
+            pos = sym.posarr[sym.seg_posoff[g]: sym.seg_posoff[g] + (c - st)]
+            fJ = int(xs[J])
+            aa, bb = np.nonzero(np.arange(st, c)[:, None] >= np.arange(st, en)[None, :])
+            PL[J][pos[aa], C[st + bb] - fJ] -= SL[st + aa, st + bb]
+            PU[J][pos[aa], C[st + bb] - fJ] -= SU[st + aa, st + bb]
+    return PL, PU
+
+
+def normalize_lu(sym, PL, PU):
+    """Alg. 1 steps 1-2 in LU form: (Lhat, Uhat^T, Dt^{-1}) per supernode with
+    Lhat = L_{C,K} L_KK^{-1}, Uhat^T = (U_KK^{-1} U_{K,C})^T and
+    Dt^{-1} = U_KK^{-1} D_K^{-1} L_KK^{-1}."""
+    lhat, uhat_t, dtinv = [], [], []
+    for K in range(sym.nsuper):
+        s = sym.width(K)
+        L, U = PL[K], PU[K]
+        eye = np.eye(s, dtype=L.dtype)
+        Li = sla.solve_triangular(np.tril(L[:s, :s], -1) + eye, eye, lower=True, unit_diagonal=True)
+        Ui_t = sla.solve_triangular(np.tril(U[:s, :s], -1) + eye, eye, lower=True, unit_diagonal=True)  # U_KK^{-T}
+        d = np.diag(L[:s, :s]).copy()
+        lhat.append(L[s:, :] @ Li)
+        uhat_t.append(U[s:, :] @ Ui_t)
+        dtinv.append(Ui_t.T @ (Li / d[:, None]))
+    return lhat, uhat_t, dtinv
+
+
+def to_dense_ldu(sym, PL, PU):
+    """Dense unit lower L, diagonal D and unit upper U (small problems only)."""
+    L, D = to_dense_L(sym, PL)
+    Ut, _ = to_dense_L(sym, PU)
+    return L, D, Ut.T

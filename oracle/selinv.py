@@ -215,3 +215,107 @@ def on_pattern_of_A(sym, X, colptr, rowind, herm=False):
     if herm:
         out = np.where(i < j, np.conj(out), out)
     return out
+
+
+# ---------------------------------------------------------------------------
+# LU form (unsymmetric A, symmetric pattern).  XL holds X on the pattern of L
+# (the lower part and the full diagonal blocks), XU holds X^T the same way
+# (entry (r, q) of XU is X(q, r)), both in the panel layout.
+# ---------------------------------------------------------------------------
+
+def gather_cc_lu(sym, XL, XU, K):
+    """Dense A^{-1}_{C,C}: the lower part from XL, the upper part from XU."""
+    GL = gather_cc(sym, XL, K)
+    GU = gather_cc(sym, XU, K)
+    return np.tril(GL) + np.triu(GU.T, 1)
+
+
+def alg1_lu(sym, lhat, uhat_t, dtinv):
+    """Alg. 1 (LU), K = N..1, pull form:
+    A^{-1}_{C,K} = -A^{-1}_{C,C} Lhat_{C,K};  A^{-1}_{K,C} = -Uhat_{K,C} A^{-1}_{C,C};
+    A^{-1}_{K,K} = U_KK^{-1} L_KK^{-1} - Uhat_{K,C} A^{-1}_{C,K}  (no symmetrization)."""
+    XL, XU = [None] * sym.nsuper, [None] * sym.nsuper
+    for K in reversed(range(sym.nsuper)):
+        s = sym.width(K)
+        c = sym.rows[K].shape[0]
+        PL = np.zeros((s + c, s), dtype=dtinv[K].dtype)
+        PU = np.zeros_like(PL)
+        T = dtinv[K].copy()
+        if c:
+            G = gather_cc_lu(sym, XL, XU, K)
+            YL = -G @ lhat[K]
+            YU = -G.T @ uhat_t[K]       # A^{-1}_{K,C} transposed
+            T = T - uhat_t[K].T @ YL
+            PL[s:, :] = YL
+            PU[s:, :] = YU
+        PL[:s, :] = T
+        PU[:s, :] = T.T
+        XL[K], XU[K] = PL, PU
+    return XL, XU
+
+
+def alg2_lu(sym, lhat, uhat_t, dtinv):
+    """Alg. 2 (LU), left-looking: the D task, then the outer- and
+    inner-product updates of the lower part (Eqs. (outerprod), (innerprod))
+    and of the upper part (the last two steps of Alg. 2), pushed into the
+    descendants."""
+    xs = sym.xsuper
+    XL, XU = [], []
+    for K in range(sym.nsuper):
+        s = sym.width(K)
+        c = sym.rows[K].shape[0]
+        XL.append(np.zeros((s + c, s), dtype=dtinv[K].dtype))
+        XU.append(np.zeros((s + c, s), dtype=dtinv[K].dtype))
+    desc = descendants(sym)
+    for K in reversed(range(sym.nsuper)):
+        s = sym.width(K)
+        fK = int(xs[K])
+        PL, PU = XL[K], XU[K]
+        T = dtinv[K] - uhat_t[K].T @ PL[s:, :]
+        PL[:s, :] = T
+        PU[:s, :] = T.T
+        for (I, g) in desc[K]:
+            sI = sym.width(I)
+            CI = sym.rows[I]
+            cI = CI.shape[0]
+            st = int(sym.seg_start[g])
+            g1 = sym.seg_ptr[I + 1]
+            en = int(sym.seg_start[g + 1]) if g + 1 < g1 else cI
+            pos = sym.posarr[sym.seg_posoff[g]: sym.seg_posoff[g] + (cI - st)]
+            rk = np.arange(st, en)
+            ra = np.arange(en, cI)
+            colsK = CI[rk] - fK
+            posA = pos[en - st:]
+            XLa_k = PL[np.ix_(posA, colsK)]   # X[R_>, R_K]
+            XUa_k = PU[np.ix_(posA, colsK)]   # X[R_K, R_>] transposed
+            Lh, Ut = lhat[I], uhat_t[I]
+            if ra.size:
+                XL[I][sI + ra, :] -= XLa_k @ Lh[rk, :]          # lower, outer product
+                XL[I][sI + rk, :] -= XUa_k.T @ Lh[ra, :]        # lower, inner product (I in C)
+                XU[I][sI + ra, :] -= XUa_k @ Ut[rk, :]          # upper, outer product
+                XU[I][sI + rk, :] -= XLa_k.T @ Ut[ra, :]        # upper, inner product (I in C)
+            XL[I][sI + rk, :] -= PL[:s, :][np.ix_(colsK, colsK)] @ Lh[rk, :]   # lower, I = K
+            XU[I][sI + rk, :] -= PU[:s, :][np.ix_(colsK, colsK)] @ Ut[rk, :]   # upper, I = K
+    return XL, XU
+
+
+def permuted_dense_lu(sym, a_lo, a_up):
+    """Dense B = P A P^T from A's stored lower values and their mirrors."""
+    n = sym.n
+    a_lo, a_up = np.asarray(a_lo), np.asarray(a_up)
+    low = np.where(sym.aflip, a_up, a_lo)
+    up = np.where(sym.aflip, a_lo, a_up)
+    bl, bu = np.empty_like(low), np.empty_like(up)
+    bl[sym.amap] = low
+    bu[sym.amap] = up
+    Bd = np.zeros((n, n), dtype=np.result_type(bl, bu))
+    cols = np.repeat(np.arange(n), np.diff(sym.Bcolptr))
+    Bd[cols, sym.Browind] = bu
+    Bd[sym.Browind, cols] = bl
+    return Bd
+
+
+def dense_selected_lu(sym, bdense):
+    """The definition: (P A P^T)^{-1} on the pattern of L (XL), and its
+    transpose, the inverse of B^T, on the same pattern (XU)."""
+    return dense_selected(sym, bdense), dense_selected(sym, bdense.T)

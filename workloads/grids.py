@@ -4,7 +4,10 @@ Conventions (shared by every consumer):
 
 * A grid point (x, y[, z]) has original index p = x + nx*(y + ny*z), x fastest.
 * Matrices are symmetric (real), complex-symmetric (A = A^T, no conjugation)
-  or, for the H3 family, Hermitian (A = A^H; ``meta["dtype"] == "h128"``).
+  or, for the H3 family, Hermitian (A = A^H; ``meta["dtype"] == "h128"``),
+  or, for the U3 family, unsymmetric with a symmetric pattern
+  (``meta["dtype"] == "lu64"``): ``values`` is then [B, 2 nnz], the stored
+  lower values A(r, c) followed by their mirrors A(c, r).
   Only the lower triangle is stored: CSC with int64 ``colptr``/``rowind``,
   rows ascending in each column, so the diagonal entry opens every column.
 * ``values`` has shape [B, nnz] (B matrices that share one pattern, the batched
@@ -21,7 +24,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-CONFIG_NAMES = ("C1", "C2", "C3", "C4", "C4s", "C5", "H3")
+CONFIG_NAMES = ("C1", "C2", "C3", "C4", "C4s", "C5", "H3", "U3")
 
 
 @dataclass
@@ -52,8 +55,24 @@ class Workload:
         return self.meta.get("dtype") == "h128"
 
     @property
+    def is_lu(self) -> bool:
+        return self.meta.get("dtype") == "lu64"
+
+    @property
+    def lower_values(self):
+        """[B, nnz] stored lower values (for LU workloads the first half)."""
+        return self.values[:, :self.nnz] if self.is_lu else self.values
+
+    @property
+    def upper_values(self):
+        """[B, nnz] their mirrors A(c, r) (LU workloads; the same as lower_values otherwise)."""
+        return self.values[:, self.nnz:] if self.is_lu else self.values
+
+    @property
     def dtype(self) -> str:
         """The library's dtype name: "f64", "c128" (complex-symmetric) or "h128" (Hermitian)."""
+        if self.is_lu:
+            return "lu64"
         return "h128" if self.is_hermitian else ("c128" if self.is_complex else "f64")
 
 
@@ -304,6 +323,40 @@ def magnetic_laplacian_3d(shape, rng, wlo=0.5, whi=1.5):
     return _lower_csc(n, rows, cols, vals)
 
 
+def convection_diffusion_3d(shape, rng, wlo=0.5, whi=1.5, pmax=0.5):
+    """Unsymmetric 7-point operator with a symmetric pattern: for each grid
+    edge (a, b), b = a + a unit step, A(a, b) = -w_e (1 - p_e) and
+    A(b, a) = -w_e (1 + p_e) (a diffusion weight w_e ~ U[wlo, whi] and a
+    convection share p_e ~ U[-pmax, pmax], as a central difference gives);
+    the diagonal is sum_e w_e (1 + |p_e|) over the point's edges plus one
+    ghost weight per missing neighbour, so every row is strictly diagonally
+    dominant.  Returns (colptr, rowind, lower, upper): the stored lower values
+    A(r, c), r >= c, and their mirrors A(c, r).  Draw order: w, p, ghosts."""
+    shape = tuple(shape)
+    n = int(np.prod(shape))
+    a_list, b_list = [], []
+    for off in _unit_offsets(3):
+        a, b = _axis_edges(shape, off)
+        a_list.append(a)
+        b_list.append(b)
+    a = np.concatenate(a_list)
+    b = np.concatenate(b_list)
+    ghost = _ghost_points(shape)
+    w = rng.uniform(wlo, whi, size=a.shape[0])
+    p = rng.uniform(-pmax, pmax, size=a.shape[0])
+    g = rng.uniform(wlo, whi, size=ghost.shape[0])
+    diag = np.zeros(n)
+    np.add.at(diag, a, w * (1 + np.abs(p)))
+    np.add.at(diag, b, w * (1 + np.abs(p)))
+    np.add.at(diag, ghost, g)
+    rows = np.concatenate([np.arange(n, dtype=np.int64), b])  # b > a: (b, a) is the lower entry
+    cols = np.concatenate([np.arange(n, dtype=np.int64), a])
+    low = np.concatenate([diag, -w * (1 + p)])   # A(b, a)
+    up = np.concatenate([diag, -w * (1 - p)])    # A(a, b)
+    colptr, rowind, both = _lower_csc(n, rows, cols, np.stack([low, up]))
+    return colptr, rowind, both[0], both[1]
+
+
 def gmrf_2d(nx, ny, kappa, w):
     """GMRF precision kappa^2 I + sum_e exp(w_e)(e_a-e_b)(e_a-e_b)^T (Neumann, no ghosts).
 
@@ -425,6 +478,9 @@ def config(name, scale=None, batch=None):
     C4  GMRF 200x200, kappa 0.5, w_e ~ N(0, 0.3^2), c_i ~ U[0,1], seed 4.
     C4s the same generator on 30x30.
     C5  64^3 27-point complex-symmetric, 8 shifts A - z_l I, cap 256, seed 5.
+    U3  unsymmetric (LU): the 7-point convection-diffusion operator on 30^3
+        (convection_diffusion_3d) with 4 real shifts A_l = A + sigma_l I,
+        log10(sigma_l) ~ U[-2, 0], seed 7.
     H3  Hermitian: the magnetic 7-point Laplacian H on 30^3 (weights
         U[0.5,1.5], phases U[-pi,pi]) with 16 real shifts A_l = H + sigma_l I,
         log10(sigma_l) ~ U[-2, 0], seed 6 (positive definite).
@@ -483,4 +539,16 @@ def config(name, scale=None, batch=None):
         vals = shifted_batch(colptr, rowind, hv[0], None, -sig.astype(np.complex128))
         return Workload("H3", m ** 3, colptr, rowind, vals, nested_dissection((m, m, m)),
                         meta={"grid": (m, m, m), "dtype": "h128", "seed": 6, "sigma": sig})
+    if name == "U3":
+        m = scale or 30
+        B = batch or 4
+        rng = np.random.default_rng(7)
+        colptr, rowind, lo, up = convection_diffusion_3d((m, m, m), rng)
+        sig = 10.0 ** rng.uniform(-2.0, 0.0, size=B)
+        cols = np.repeat(np.arange(m ** 3), np.diff(colptr))
+        dg = (rowind == cols).astype(np.float64)
+        vals = np.concatenate([lo[None, :] + sig[:, None] * dg[None, :], up[None, :] + sig[:, None] * dg[None, :]],
+                              axis=1)
+        return Workload("U3", m ** 3, colptr, rowind, vals, nested_dissection((m, m, m)),
+                        meta={"grid": (m, m, m), "dtype": "lu64", "seed": 7, "sigma": sig})
     raise KeyError(name)
