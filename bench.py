@@ -41,6 +41,8 @@ WORKLOADS = {
           "nested dissection, supernode cap 256",
     "H3": "H3: 16 real shifts H + sigma_l I of a Hermitian 3-D 7-point magnetic Laplacian 30^3 (N=27000), "
           "complex128 Hermitian (conjugate transposes), seed 6, nested dissection, one batched launch",
+    "U3": "U3: 4 shifts A + sigma_l I of an unsymmetric 3-D 7-point convection-diffusion operator 30^3 "
+          "(N=27000, symmetric pattern), FP64, seed 7, nested dissection, LU form of Alg. 1, one batched launch",
 }
 
 TRAFFIC_RECORDS = {
@@ -245,6 +247,50 @@ def hermitian_leg(relax, sched):
     out = summary(w, g, 3, "H3")
     g["S"].close()
     log(f"H3: {out['gflops']} GFLOP/s, step {out['ms_per_step']} ms, traversal "
+        f"{out['traversal_frac_of_peak']:.3f} of the FP64 MFMA peak")
+    return out
+
+
+def lu_leg(relax):
+    """U3: the LU form of Alg. 1 (unsymmetric values on a symmetric pattern),
+    4 shifts in one launch on the level schedule.  Its traversal does both
+    GEMM-1 products (X_{C,K} and X_{K,C}^T) and GEMM-2 per supernode:
+    4 c^2 s + 2 c s^2 flops.  The L D U panels come from the host
+    factorization (the LU form has no device factorization), uploaded once
+    outside the timed region."""
+    import torch
+
+    from paper_1604_02528_amd import SelInv
+    from workloads import config
+
+    w = config("U3")
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="lu64", batch=w.batch, cap=w.cap, relax=relax,
+               sched="levels", adjoint=False)
+    t0 = time.perf_counter()
+    ldlt = torch.from_numpy(S.factor_host(w.values)).to("cuda")
+    t_fac = time.perf_counter() - t0
+    S._alloc(False)
+    wall, t_norm, t_run = timed_steps(S, ldlt, 3, 1)
+    sym = S.symbolic()
+    S.close()
+    del ldlt
+    s = np.diff(sym["xsuper"]).astype(np.float64)
+    c = np.diff(sym["rowptr"]).astype(np.float64)
+    fl_solve = float(np.sum(4.0 * c * c * s + 2.0 * c * s * s))
+    flops = fl_solve * w.batch
+    ms_step = wall / 3 * 1e3
+    tr = float(np.mean(t_run))
+    out = {
+        "workload": WORKLOADS["U3"], "dtype": "f64", "batch": w.batch,
+        "gflops": round(flops / (ms_step * 1e-3) / 1e9, 2),
+        "ms_per_step": round(ms_step, 4), "selinv_run_ms": round(tr * 1e3, 4),
+        "normalize_ms": round(float(np.mean(t_norm)) * 1e3, 4),
+        "traversal_tflops": round(flops / tr / 1e12, 4),
+        "traversal_frac_of_peak": round(flops / tr / 1e12 / PEAK_FP64_TFLOPS, 5),
+        "flops_per_solve": fl_solve, "nsuper": sym["nsuper"], "depth": sym["depth"],
+        "t_factor_host_s": round(t_fac, 4),
+    }
+    log(f"U3 (LU form): {out['gflops']} GFLOP/s, step {out['ms_per_step']} ms, traversal "
         f"{out['traversal_frac_of_peak']:.3f} of the FP64 MFMA peak")
     return out
 
@@ -522,6 +568,8 @@ def main():
         extras["batched"] = batched_leg(args.relax, args.sched)
         torch.cuda.empty_cache()
         extras["hermitian"] = hermitian_leg(args.relax, args.sched)
+        torch.cuda.empty_cache()
+        extras["lu"] = lu_leg(args.relax)
         torch.cuda.empty_cache()
         extras["adjoint"] = adjoint_leg(args.relax)
     wl = WORKLOADS[args.workload]

@@ -9,7 +9,9 @@
  * (Alg. 1 / Alg. 2 outputs: the selected blocks A^{-1}_{I,J} with L_{I,J}
  * nonempty; the LDL^T specialization of Section 2.3 makes the upper triangle
  * the transpose of the lower one, and its Hermitian variant the conjugate
- * transpose).
+ * transpose).  For a real unsymmetric A with a symmetric pattern
+ * (SELINV_LU64) it computes both triangles from the LU form of Alg. 1
+ * (Section 2.1, with B = L D U unpivoted).
  *
  * Conventions shared by every entry point
  *  - Matrices: lower triangle incl. diagonal, CSC, 0-based, int64 indices,
@@ -24,13 +26,20 @@
  *    A = A^T); for SELINV_H128 (Hermitian, A = A^H, real diagonal) every
  *    transpose is a conjugate transpose: B = L D L^H, and a stored lower
  *    value that the permutation moves into B's upper triangle enters B's
- *    lower triangle conjugated.
+ *    lower triangle conjugated.  SELINV_LU64 values are [batch][2 nnz]
+ *    doubles: per matrix the nnz lower values A(rowind[e], j) in rowind
+ *    order, then their mirrors A(j, rowind[e]) in the same order (the
+ *    diagonal is taken from the first half).
  *  - Panels: supernode K (columns first(K)..last(K), width s, row set C(K) of
  *    size c, Eq. (newset)) owns a dense column-major (s + c) x s block whose
  *    rows are K's own columns followed by C(K).  Panels are concatenated in K
  *    order; one matrix of the batch occupies `panel_elems` scalars and matrix
  *    l starts at l * panel_elems.  The same layout is used for the factor
- *    panels and for the selected inverse X.
+ *    panels and for the selected inverse X.  An SELINV_LU64 matrix holds two
+ *    panel sets of that layout, one after the other (panel_elems counts
+ *    both): the first holds L (unit, with D in the diagonal slots) and X =
+ *    B^{-1} on the pattern of L, the second U^T and X^T on the same
+ *    pattern.
  *  - Device memory is always allocated by the caller (sizes from
  *    selinv_sizes) and never freed by the library.  Device pointers are plain
  *    `void*` from hipMalloc (or a framework allocator on the same device).
@@ -55,7 +64,11 @@ typedef struct selinv_ctx selinv_ctx;
 typedef enum {
   SELINV_R64 = 0,  /* real float64 */
   SELINV_C128 = 1, /* complex128, complex-symmetric */
-  SELINV_H128 = 2  /* complex128, Hermitian (Section 2.3: conjugate transposes); no adjoint */
+  SELINV_H128 = 2, /* complex128, Hermitian (Section 2.3: conjugate transposes); no adjoint */
+  SELINV_LU64 = 3  /* float64, unsymmetric values on a symmetric pattern (Alg. 1 in its LU form,
+                      Section 2.1); level schedule only, gathered X_{C,C} (no dense buffers, split
+                      contractions or tune table), host factorization only; no adjoint, no Dt
+                      output, no selinv_scatter */
 } selinv_dtype;
 
 typedef enum {
@@ -164,7 +177,8 @@ typedef struct {
   int64_t x_bytes;       /* selected inverse, same layout */
   int64_t work_bytes;    /* device tables, normalize scratch, counters, queue */
   int64_t dtilde_bytes;  /* optional pivot blocks Dt_K (needed by selinv_backward) */
-  int64_t abar_bytes;    /* adjoint output on A's pattern, batch * nnz(A) scalars */
+  int64_t abar_bytes;    /* adjoint / selinv_extract output on A's pattern, batch * nnz(A) scalars
+                            (SELINV_LU64: batch * 2 nnz(A)) */
   int64_t trace_bytes;   /* optional selinv_trace buffer */
   int64_t tables_bytes;  /* leading part of work_bytes: the plan tables, written on upload and then only read */
 } selinv_sizes_t;
@@ -183,6 +197,10 @@ selinv_status selinv_sizes(const selinv_ctx *h, selinv_sizes_t *s);
  * normalize kernels of Alg. 1 steps 1-2 (Lhat_{C,K} = L_{C,K} L_KK^{-1},
  * Dt_K^{-1} = (L_KK D_K L_KK^T)^{-1}), which leave Dt_K^{-1} in the top s x s
  * block and Lhat_{C,K} in the bottom c x s block of each panel.
+ * SELINV_LU64: unpivoted supernodal L D U (both panel sets), then
+ * Lhat_{C,K} = L_{C,K} L_KK^{-1}, Uhat_{K,C}^T = U_{K,C}^T U_KK^{-T} (second
+ * set) and Dt_K^{-1} = U_KK^{-1} D_K^{-1} L_KK^{-1} (first set's top block);
+ * dtilde_dev must be NULL (EUNSUPPORTED otherwise).
  * Errors: SELINV_ESINGULAR on an exactly zero or non-finite pivot
  * (error_info(0) = column of B, error_info(1) = batch index).
  * Uploads the device tables into work_dev on the first call.
@@ -242,6 +260,10 @@ selinv_status selinv_factor_device(selinv_ctx *h, const void *values_dev, void *
  *   X_KK <- (X_KK + X_KK^T) / 2.
  * Reads panels_dev (normalized), writes x_dev (same layout: top block = the
  * full symmetric X_KK, bottom block = X_{C,K}).  Asynchronous on `stream`.
+ * SELINV_LU64 (LU form of Alg. 1, Section 2.1): X_{C,K} = -X_{C,C} Lhat_{C,K}
+ * and X_{K,C}^T = -(X_{C,C})^T Uhat_{K,C}^T, X_KK = Dt_K^{-1} - Uhat_{K,C}
+ * X_{C,K} without symmetrization; the first panel set receives X_KK and
+ * X_{C,K}, the second X_KK^T and X_{K,C}^T.
  */
 selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, void *work_dev, void *stream);
 
@@ -291,7 +313,9 @@ selinv_status selinv_normalize_run_noalloc(selinv_ctx *h, const void *ldlt_dev, 
 
 /*
  * selinv_extract -- X on A's stored lower pattern, original indexing:
- * out_dev[l][e] = (A^{-1})_{rowind[e], col(e)} of matrix l.  Asynchronous.
+ * out_dev[l][e] = (A^{-1})_{rowind[e], col(e)} of matrix l.  SELINV_LU64:
+ * out_dev is [batch][2 nnz(A)], the entries as above followed by their
+ * mirrors (A^{-1})_{col(e), rowind[e]}.  Asynchronous.
  */
 selinv_status selinv_extract(const selinv_ctx *h, const void *x_dev, void *work_dev, void *out_dev,
                              void *stream);

@@ -16,7 +16,7 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libselinv.so")
 
-SELINV_R64, SELINV_C128, SELINV_H128 = 0, 1, 2
+SELINV_R64, SELINV_C128, SELINV_H128, SELINV_LU64 = 0, 1, 2, 3
 SCHED_PERSISTENT, SCHED_LEVELS, SCHED_PUSH = 0, 1, 2
 STATUS = {0: "OK", 1: "EINVAL", 2: "EPATTERN", 3: "ESINGULAR", 4: "ENOMEM", 5: "EDEVICE", 6: "ESTATE",
           7: "EUNSUPPORTED"}

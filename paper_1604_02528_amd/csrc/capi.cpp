@@ -67,6 +67,7 @@ struct HostPlan {
   std::vector<int32_t> tiny_dptr;  // [depth + 1] small-node records of each etree depth
   std::vector<int32_t> tiny_dadj;  // [depth] end of each depth's c <= kTinyC prefix (the adjoint's)
   bool adjoint = false;        // adjoint scratch allocated (opts.adjoint >= 0)
+  bool lu = false;             // LU plan: two panel sets (L, U^T), gathered GEMM-1 tiles only
   std::vector<int32_t> lvl_items, lvl_ptr, lvl_tiny, lvl_kind;
   std::vector<int32_t> node_defer;  // GEMM-2 of the node in ITEM_P items (level schedule, dense buffer, unsplit)
   std::vector<int32_t> node_ykern;  // GEMM-1 tiles in k_ydense (level schedule, dense buffer)
@@ -132,7 +133,8 @@ double item_cost_ns(const HostPlan &H, const Item &it) {
   switch (it.type) {
     case ITEM_G:
       return 2500.0 + (double)kTileM * kTileM * 24.0 / 60.0;
-    case ITEM_Y: {
+    case ITEM_Y:
+    case ITEM_YU: {
       const double m = std::min<double>(kTileM, c - (double)kTileM * it.a);
       const double nn = std::min<double>(kTileN, s - (double)kTileN * (it.b & 0xffff));
       const double kk = H.node_kchunk[it.K];
@@ -295,14 +297,19 @@ void choose_dense(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_
 }
 
 void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t dense_min_c, int64_t dense_max_bytes,
-                int64_t split_min_k, int sched, const TuneTable *tt, bool adjoint, bool herm, HostPlan &H) {
+                int64_t split_min_k, int sched, const TuneTable *tt, bool adjoint, bool herm, bool lu, HostPlan &H) {
   const int64_t ns = S.nsuper();
+  H.lu = lu;
   // the push form (Alg. 2) runs one launch per depth and step like the level
   // schedule; its GEMM-1 work is done by push tiles, so no node gets a dense
   // buffer, a split contraction, a single-item or a single-wavefront path
   const bool push = sched == SELINV_SCHED_PUSH;
   const bool per_level = sched != SELINV_SCHED_PERSISTENT;
-  if (push) {
+  // The LU form of Alg. 1 (Section 2.1) runs the level schedule with the gathered
+  // GEMM-1 tiles only: no dense buffer, split contraction, R phase,
+  // single-item or single-wavefront node and no single-wavefront
+  // normalization.
+  if (push || lu) {
     dense_min_c = -1;
     split_min_k = -1;
     tt = nullptr;
@@ -378,7 +385,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     // at a depth with few tiles, also takes the R phase (one part): its
     // tiles' GEMM-2 shares are then cut into R items instead of running
     // block after block at the end of each GEMM-1 tile.
-    if (parts <= 1 && (push || !(nq > 1 && dtiles[S.sdepth[K]] * nq <= kSplitTarget))) continue;
+    if (parts <= 1 && (push || lu || !(nq > 1 && dtiles[S.sdepth[K]] * nq <= kSplitTarget))) continue;
     H.node_split[K] = (int32_t)parts;
     H.node_kchunk[K] = (int32_t)chunk;
     H.node_yoff[K] = H.y_elems;
@@ -448,7 +455,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
         for (int32_t b = 0; b <= a; ++b) H.items.push_back(Item{(int32_t)K, ITEM_G, a, b});
       nph(0, K) = nr * (nr + 1) / 2;
     }
-    if (c <= kSmallC && s <= kSmallS && !push) {
+    if (c <= kSmallC && s <= kSmallS && !push && !lu) {
       H.items.push_back(Item{(int32_t)K, ITEM_S, 0, 0});
       nph(3, K) = 1;
       continue;
@@ -459,6 +466,11 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
           for (int32_t b = 0; b < nb; ++b)
             for (int32_t a = 0; a < nr; ++a) H.items.push_back(Item{(int32_t)K, ITEM_Y, a, b | (p << 16)});
         nph(1, K) = nr * nb * parts;
+        if (lu) {  // the upper part's GEMM-1 tiles, in the same phase
+          for (int32_t b = 0; b < nb; ++b)
+            for (int32_t a = 0; a < nr; ++a) H.items.push_back(Item{(int32_t)K, ITEM_YU, a, b});
+          nph(1, K) += nr * nb;
+        }
       }
       if (H.node_yoff[K] >= 0 || H.node_defer[K]) {  // partial tiles summed by R items, or GEMM-2 by P items
         const int32_t type = H.node_defer[K] ? ITEM_P : ITEM_R;
@@ -471,7 +483,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
         nph(2, K) = nr * nb * rq;
       }
     }
-    const int32_t nsl = nr >= kDSlabRows ? 64 / kDSlabW : 1;
+    const int32_t nsl = nr >= kDSlabRows && !lu ? 64 / kDSlabW : 1;
     for (int32_t a = 0; a < nb; ++a)
       for (int32_t b = 0; b <= a; ++b)
         for (int32_t q = 0; q < nsl; ++q) H.items.push_back(Item{(int32_t)K, ITEM_D, a, nsl > 1 ? b | ((q + 1) << 16) : b});
@@ -503,7 +515,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   H.tiny_dptr.assign(S.depth + 1, 0);
   H.tiny_dadj.assign(S.depth, 0);
   // small nodes address X through 32-bit byte offsets
-  const bool tiny_ok = S.panel_elems * scalar_bytes < (int64_t(1) << 32);
+  const bool tiny_ok = !lu && S.panel_elems * scalar_bytes < (int64_t(1) << 32);
   const int64_t tiny_cf = scalar_bytes == 8 ? kTinyCF : kTinyC;
   auto adj_tiny = [&](int64_t K) { return !push && tiny_ok && H.node_c[K] <= kTinyC && H.node_s[K] <= kTinyS; };
   H.push.clear();
@@ -734,7 +746,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
       }
       for (int64_t K : bydepth[d]) {
         const int32_t s = H.node_s[K], c = H.node_c[K];
-        if (s <= kSmallNormS) {
+        if (s <= kSmallNormS && !lu) {
           H.small_nodes.push_back((int32_t)K);
           continue;
         }
@@ -842,7 +854,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.dpos = take(8 * (int64_t)H.dpos.size());
   H.tables_bytes = p;
   o.plan = take((int64_t)sizeof(DevPlan));
-  o.linv = take(scalar_bytes * batch * H.sq_elems);
+  o.linv = take(scalar_bytes * batch * H.sq_elems * (H.lu ? 2 : 1));  // LU: L_KK^{-1}, then U_KK^{-T}
   o.dinv = take(scalar_bytes * batch * S.n);
   o.part = take(scalar_bytes * batch * H.part_elems);
   o.gbuf = take(scalar_bytes * batch * H.g_elems);
@@ -913,7 +925,12 @@ struct selinv_ctx {
   }
   bool is_complex() const { return opts.dtype == SELINV_C128 || opts.dtype == SELINV_H128; }
   bool is_herm() const { return opts.dtype == SELINV_H128; }
+  bool is_lu() const { return opts.dtype == SELINV_LU64; }
   int64_t sbytes() const { return is_complex() ? 16 : 8; }
+  // elements of one matrix's panels (an LU context holds the L and the U^T
+  // panel sets, one after the other) and doubles of one matrix's values
+  int64_t pelems() const { return is_lu() ? 2 * S.panel_elems : S.panel_elems; }
+  int64_t vdoubles() const { return (is_complex() || is_lu() ? 2 : 1) * S.nnzA; }
 };
 
 namespace {
@@ -951,7 +968,8 @@ DevPlan make_devplan(const selinv_ctx *h, void *work) {
   d.ns = h->S.nsuper();
   d.nitems = (int64_t)H.items.size();
   d.batch = h->opts.batch;
-  d.panel_elems = h->S.panel_elems;
+  d.panel_elems = h->pelems();
+  d.half = h->is_lu() ? h->S.panel_elems : 0;
   d.sq_elems = H.sq_elems;
   d.part_elems = H.part_elems;
   d.nnzA = h->S.nnzA;
@@ -1212,8 +1230,10 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *ro
   }
   *out = h;
   const selinv_opts &o = h->opts;
-  if (o.dtype != SELINV_R64 && o.dtype != SELINV_C128 && o.dtype != SELINV_H128)
+  if (o.dtype != SELINV_R64 && o.dtype != SELINV_C128 && o.dtype != SELINV_H128 && o.dtype != SELINV_LU64)
     return set_err(h, SELINV_EUNSUPPORTED, "unknown dtype");
+  if (o.dtype == SELINV_LU64 && o.sched != SELINV_SCHED_LEVELS)
+    return set_err(h, SELINV_EUNSUPPORTED, "the LU form runs on the level schedule only");
   if (o.batch < 1) return set_err(h, SELINV_EINVAL, "batch must be >= 1");
   if (o.max_super < 1 || o.max_super > 256) return set_err(h, SELINV_EINVAL, "max_super must be in [1, 256]");
   if (o.sched != SELINV_SCHED_PERSISTENT && o.sched != SELINV_SCHED_LEVELS && o.sched != SELINV_SCHED_PUSH)
@@ -1226,8 +1246,9 @@ selinv_status selinv_analyze(int64_t n, const int64_t *colptr, const int64_t *ro
     TuneTable tt;
     if (o.tune_cache && o.tune_cache[0]) tt = load_tune_table(o.tune_cache, h->is_complex() ? "c128" : "f64");
     build_plan(h->S, o.batch, h->sbytes(), min_c, max_b, split_k, o.sched,
-               (o.tune_cache && o.tune_cache[0]) ? &tt : nullptr, o.adjoint >= 0 && o.dtype != SELINV_H128,
-               o.dtype == SELINV_H128, h->H);
+               (o.tune_cache && o.tune_cache[0]) ? &tt : nullptr,
+               o.adjoint >= 0 && o.dtype != SELINV_H128 && o.dtype != SELINV_LU64, o.dtype == SELINV_H128,
+               o.dtype == SELINV_LU64, h->H);
     if ((int64_t)h->H.items.size() * (int64_t)o.batch >= (int64_t)INT32_MAX)
       return set_err(h, SELINV_ENOMEM, "too many work items for int32 item ids");
     build_image(h);
@@ -1250,7 +1271,7 @@ selinv_status selinv_symbolic(const selinv_ctx *h, selinv_symbolic_view *v) {
   v->n = S.n;
   v->nsuper = S.nsuper();
   v->nnzL = S.nnzL;
-  v->panel_elems = S.panel_elems;
+  v->panel_elems = h->pelems();
   v->batch = h->opts.batch;
   v->dtype = h->opts.dtype;
   v->perm = S.perm.data();
@@ -1282,11 +1303,11 @@ selinv_status selinv_sizes(const selinv_ctx *h, selinv_sizes_t *s) {
   if (!h || !s) return SELINV_EINVAL;
   if (h->S.n == 0) return SELINV_ESTATE;
   const int64_t B = h->opts.batch, sb = h->sbytes();
-  s->panels_bytes = align_up(B * h->S.panel_elems * sb);
+  s->panels_bytes = align_up(B * h->pelems() * sb);
   s->x_bytes = s->panels_bytes;
   s->work_bytes = h->H.off.end;
   s->dtilde_bytes = align_up(B * h->H.sq_elems * sb);
-  s->abar_bytes = align_up(B * h->S.nnzA * sb);
+  s->abar_bytes = align_up(B * h->vdoubles() * 8);
   s->trace_bytes = align_up(64 * B * (int64_t)std::max(h->H.items.size(), h->H.lvl_items.size()));
   s->tables_bytes = h->H.tables_bytes;
   return SELINV_OK;
@@ -1300,7 +1321,8 @@ selinv_status selinv_factor(selinv_ctx *h, const void *values, void *panels_dev,
   hipStream_t st = (hipStream_t)stream;
   h->factored = false;
   h->have_logdet = false;
-  const int64_t B = h->opts.batch, sb = h->sbytes(), pe = h->S.panel_elems;
+  if (dtilde_dev && h->is_lu()) return set_err(h, SELINV_EUNSUPPORTED, "no Dt output for the LU form");
+  const int64_t B = h->opts.batch, sb = h->sbytes(), pe = h->pelems();
   const size_t need = (size_t)(B * pe * sb);
   hipError_t e;
   if (h->pinned_bytes < need) {
@@ -1316,7 +1338,7 @@ selinv_status selinv_factor(selinv_ctx *h, const void *values, void *panels_dev,
   try {
     for (int64_t l = 0; l < B; ++l) {
       double ld[2] = {0.0, 0.0};
-      int64_t bad = factor_host(h->S, h->opts.dtype, vals + l * h->S.nnzA * scal, h->pinned + l * pe * scal,
+      int64_t bad = factor_host(h->S, h->opts.dtype, vals + l * h->vdoubles(), h->pinned + l * pe * scal,
                                 h->opts.nthreads, ld);
       if (bad >= 0) return set_err(h, SELINV_ESINGULAR, "zero or non-finite pivot", bad, l);
       h->logdet[2 * l] = ld[0];
@@ -1347,6 +1369,7 @@ selinv_status selinv_normalize(selinv_ctx *h, const void *ldlt_dev, void *panels
   if (!h) return SELINV_EINVAL;
   if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
   if (!ldlt_dev || !panels_dev || !work_dev) return set_err(h, SELINV_EINVAL, "null buffer");
+  if (dtilde_dev && h->is_lu()) return set_err(h, SELINV_EUNSUPPORTED, "no Dt output for the LU form");
   hipStream_t st = (hipStream_t)stream;
   selinv_status ss = ensure_uploaded(h, work_dev, st);
   if (ss != SELINV_OK) return ss;
@@ -1365,14 +1388,14 @@ selinv_status selinv_factor_host(selinv_ctx *h, const void *values, void *panels
   if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
   if (!values || !panels_host) return set_err(h, SELINV_EINVAL, "null buffer");
   h->have_logdet = false;
-  const int64_t B = h->opts.batch, pe = h->S.panel_elems;
+  const int64_t B = h->opts.batch, pe = h->pelems();
   const int64_t scal = h->is_complex() ? 2 : 1;
   const double *vals = static_cast<const double *>(values);
   double *out = static_cast<double *>(panels_host);
   try {
     for (int64_t l = 0; l < B; ++l) {
       double ld[2] = {0.0, 0.0};
-      int64_t bad = factor_host(h->S, h->opts.dtype, vals + l * h->S.nnzA * scal, out + l * pe * scal,
+      int64_t bad = factor_host(h->S, h->opts.dtype, vals + l * h->vdoubles(), out + l * pe * scal,
                                 h->opts.nthreads, ld);
       if (bad >= 0) return set_err(h, SELINV_ESINGULAR, "zero or non-finite pivot", bad, l);
       h->logdet[2 * l] = ld[0];
@@ -1390,6 +1413,7 @@ selinv_status selinv_factor_device(selinv_ctx *h, const void *values_dev, void *
   if (!h) return SELINV_EINVAL;
   if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
   if (!values_dev || !ldlt_dev || !work_dev) return set_err(h, SELINV_EINVAL, "null buffer");
+  if (h->is_lu()) return set_err(h, SELINV_EUNSUPPORTED, "selinv_factor_device: no device LU factorization");
   hipStream_t st = (hipStream_t)stream;
   selinv_status ss = ensure_uploaded(h, work_dev, st);
   if (ss != SELINV_OK) return ss;
@@ -1429,6 +1453,7 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
   if (!h) return SELINV_EINVAL;
   if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
   if (!ldlt_dev || !panels_dev || !x_dev || !work_dev) return set_err(h, SELINV_EINVAL, "null buffer");
+  if (dtilde_dev && h->is_lu()) return set_err(h, SELINV_EUNSUPPORTED, "no Dt output for the LU form");
   hipStream_t st = (hipStream_t)stream;
   selinv_status ss = ensure_uploaded(h, work_dev, st);
   if (ss != SELINV_OK) return ss;
@@ -1510,6 +1535,7 @@ selinv_status selinv_normalize_run_noalloc(selinv_ctx *h, const void *ldlt_dev, 
   if (!h) return SELINV_EINVAL;
   if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
   if (!ldlt_dev || !panels_dev || !x_dev) return set_err(h, SELINV_EINVAL, "null buffer");
+  if (dtilde_dev && h->is_lu()) return set_err(h, SELINV_EUNSUPPORTED, "no Dt output for the LU form");
   const int64_t need = h->H.off.fwd_end;
   if (need > kNoAllocBytes)
     return set_err(h, SELINV_ENOMEM,
@@ -1575,6 +1601,7 @@ selinv_status selinv_scatter(const selinv_ctx *hc, const void *vals_dev, void *w
   if (!h) return SELINV_EINVAL;
   if (h->S.n == 0) return set_err(h, SELINV_ESTATE, "analyze did not succeed");
   if (!vals_dev || !panel_dev || !work_dev) return set_err(h, SELINV_EINVAL, "null buffer");
+  if (h->is_lu()) return set_err(h, SELINV_EUNSUPPORTED, "selinv_scatter: not defined for the LU form");
   hipStream_t st = (hipStream_t)stream;
   selinv_status ss = ensure_uploaded(h, work_dev, st);
   if (ss != SELINV_OK) return ss;
@@ -1590,6 +1617,7 @@ selinv_status selinv_backward(selinv_ctx *h, const void *panels_dev, const void 
   if (!h) return SELINV_EINVAL;
   if (!h->factored) return set_err(h, SELINV_ESTATE, "selinv_backward before a successful selinv_factor");
   if (h->is_herm()) return set_err(h, SELINV_EUNSUPPORTED, "selinv_backward: no adjoint for Hermitian matrices");
+  if (h->is_lu()) return set_err(h, SELINV_EUNSUPPORTED, "selinv_backward: no adjoint for the LU form");
   if (!h->H.adjoint)
     return set_err(h, SELINV_EUNSUPPORTED, "selinv_backward: the work area was sized without the adjoint's scratch "
                                            "(opts.adjoint < 0)");

@@ -1,6 +1,9 @@
 // Host numeric factorization: unpivoted supernodal LDL^T of B = P A P^T
 // (LDL^H for a Hermitian A: every transpose below is then a conjugate
-// transpose, Section 2.3).
+// transpose, Section 2.3), or L D U of an unsymmetric real B with a
+// symmetric pattern (the factors of Alg. 1's LU form, Section 2.1): L and
+// U^T then fill two panel sets of the same layout, and every update of one
+// set takes its other factor from the other set.
 //
 // The paper takes its factors from an external package that does no dynamic
 // pivoting (Section 4); this is the library's own producer of that input.
@@ -35,6 +38,7 @@ struct Factorizer {
   const Symbolic &S;
   T *P;  // panels of one matrix
   double cs;  // -1: Hermitian (conjugate transposes), +1 otherwise
+  T *PU = nullptr;  // L D U: the U^T panel set (P holds L); null for LDL^T
   std::vector<std::mutex> locks;
   std::atomic<int64_t> bad_col{-1};
   std::atomic<bool> abort{false};
@@ -48,8 +52,39 @@ struct Factorizer {
     abort.store(true);
   }
 
+  // Dense right-looking L D U of the (s + c) x s panels of both sets in
+  // place: B(i, k) -= L(i, j) d_j U(j, k) into the L set and, transposed,
+  // B(k, i) into the U^T set, for i >= k.
+  bool factor_panel_lu(int64_t K) {
+    const int64_t s = S.width(K), c = S.nrows(K), ld = s + c;
+    T *A = P + S.panel_off[K], *B = PU + S.panel_off[K];
+    for (int64_t jj = 0; jj < s; ++jj) {
+      const T d = A[jj + jj * ld];
+      if (!finite_nonzero(d)) {
+        record_bad(S.xsuper[K] + jj);
+        return false;
+      }
+      T *lj = A + jj * ld, *uj = B + jj * ld;
+      for (int64_t k = jj + 1; k < s; ++k) {
+        const T fl = SOps<T>::div(uj[k], d), fu = SOps<T>::div(lj[k], d);
+        T *lk = A + k * ld, *uk = B + k * ld;
+        for (int64_t i = k; i < ld; ++i) {
+          lk[i] -= lj[i] * fl;
+          uk[i] -= uj[i] * fu;
+        }
+      }
+      for (int64_t i = jj + 1; i < ld; ++i) {
+        lj[i] = SOps<T>::div(lj[i], d);
+        uj[i] = SOps<T>::div(uj[i], d);
+      }
+      uj[jj] = d;
+    }
+    return true;
+  }
+
   // Dense right-looking LDL^T of the (s + c) x s panel in place.
   bool factor_panel(int64_t K) {
+    if (PU) return factor_panel_lu(K);
     const int64_t s = S.width(K), c = S.nrows(K), ld = s + c;
     T *A = P + S.panel_off[K];
     for (int64_t jj = 0; jj < s; ++jj) {
@@ -72,17 +107,31 @@ struct Factorizer {
   }
 
   // Subtract L_{C,K} D_K L_{C,K}^T (^H if Hermitian) from the ancestors (lower
-  // triangle only).
+  // triangle only); L D U: L_{C,K} D_K U_{K,C} from the L set and its
+  // transpose U_{K,C}^T D_K L_{C,K}^T from the U^T set.
   void update_ancestors(int64_t K, std::vector<T> &W, std::vector<T> &U) {
+    if (!PU) {
+      update_from(K, P, P, P, W, U);
+    } else {
+      update_from(K, P, PU, P, W, U);
+      update_from(K, PU, P, PU, W, U);
+    }
+  }
+
+  // Target(a, b) -= sum_k Left_C(a, k) D_k tr(Right_C(b, k)), a >= b, for the
+  // rows a, b of C(K), scattered into the ancestors' panels of the set
+  // Target; D from the L set's diagonal.
+  void update_from(int64_t K, const T *Lset, const T *Rset, T *Tset, std::vector<T> &W, std::vector<T> &U) {
     const int64_t s = S.width(K), c = S.nrows(K), ld = s + c;
     if (c == 0) return;
-    const T *A = P + S.panel_off[K];
+    const T *A = Rset + S.panel_off[K];
+    const T *Al = Lset + S.panel_off[K], *Ad = P + S.panel_off[K];
     const int64_t *C = S.rowind_L.data() + S.rowptr[K];
-    // W = L_C D (c x s, column-major, ld c)
+    // W = Left_C D (c x s, column-major, ld c)
     W.resize((size_t)(c * s));
     for (int64_t k = 0; k < s; ++k) {
-      T d = A[k + k * ld];
-      for (int64_t a = 0; a < c; ++a) W[a + k * c] = A[s + a + k * ld] * d;
+      T d = Ad[k + k * ld];
+      for (int64_t a = 0; a < c; ++a) W[a + k * c] = Al[s + a + k * ld] * d;
     }
     for (int64_t g = S.seg_ptr[K]; g < S.seg_ptr[K + 1]; ++g) {
       const int64_t J = S.seg_super[g], st = S.seg_start[g];
@@ -117,7 +166,7 @@ struct Factorizer {
       // scatter-subtract into J's panel
       const int64_t fJ = S.xsuper[J], sJ = S.width(J), ldJ = sJ + S.nrows(J);
       const int32_t *pos = S.posarr.data() + S.seg_posoff[g];
-      T *PJ = P + S.panel_off[J];
+      T *PJ = Tset + S.panel_off[J];
       std::lock_guard<std::mutex> lk(locks[J]);
       for (int64_t bb = st; bb < en; ++bb) {
         T *col = PJ + (C[bb] - fJ) * ldJ;
@@ -170,14 +219,26 @@ struct Factorizer {
 
 template <typename T>
 int64_t factor_impl(const Symbolic &S, const double *vals, double *panels_raw, int nthreads, double logdet[2],
-                    double cs) {
+                    double cs, bool lu) {
   T *P = reinterpret_cast<T *>(panels_raw);
   const T *v = reinterpret_cast<const T *>(vals);
-  std::memset((void *)P, 0, sizeof(T) * (size_t)S.panel_elems);
-  // an entry that the permutation moves into B's upper triangle is B's lower
-  // entry transposed (conjugated if Hermitian)
-  for (int64_t e = 0; e < S.nnzA; ++e) P[S.apos[e]] = S.aflip[e] ? cj(v[e], cs) : v[e];
+  T *PU = lu ? P + S.panel_elems : nullptr;
+  std::memset((void *)P, 0, sizeof(T) * (size_t)S.panel_elems * (lu ? 2 : 1));
+  if (lu) {
+    // v[e] = A(row, col), v[nnz + e] = A(col, row); an entry that the
+    // permutation moves into B's upper triangle swaps the two roles
+    for (int64_t e = 0; e < S.nnzA; ++e) {
+      const T lo = v[e], up = v[S.nnzA + e];
+      P[S.apos[e]] = S.aflip[e] ? up : lo;
+      PU[S.apos[e]] = S.aflip[e] ? lo : up;
+    }
+  } else {
+    // an entry that the permutation moves into B's upper triangle is B's lower
+    // entry transposed (conjugated if Hermitian)
+    for (int64_t e = 0; e < S.nnzA; ++e) P[S.apos[e]] = S.aflip[e] ? cj(v[e], cs) : v[e];
+  }
   Factorizer<T> F(S, P, cs);
+  F.PU = PU;
   F.run(nthreads);
   if (F.abort.load()) return F.bad_col.load();
   // log det = sum log D_jj
@@ -206,8 +267,9 @@ int64_t factor_impl(const Symbolic &S, const double *vals, double *panels_raw, i
 
 int64_t factor_host(const Symbolic &S, int kind, const double *vals, double *panels, int nthreads,
                     double logdet[2]) {
-  if (kind == SELINV_R64) return factor_impl<double>(S, vals, panels, nthreads, logdet, 1.0);
-  return factor_impl<cplx>(S, vals, panels, nthreads, logdet, kind == SELINV_H128 ? -1.0 : 1.0);
+  if (kind == SELINV_R64 || kind == SELINV_LU64)
+    return factor_impl<double>(S, vals, panels, nthreads, logdet, 1.0, kind == SELINV_LU64);
+  return factor_impl<cplx>(S, vals, panels, nthreads, logdet, kind == SELINV_H128 ? -1.0 : 1.0, false);
 }
 
 }  // namespace selinv

@@ -75,7 +75,9 @@ void analyze(Symbolic &S, int64_t n, const int64_t *colptr, const int64_t *rowin
 // `panels` receives panel_elems scalars.  Real or complex (interleaved).
 // Returns the failing column (>= 0) on a zero / non-finite pivot, else -1.
 // logdet receives sum log D_jj (re, im).
-// kind: SELINV_R64, SELINV_C128 or SELINV_H128
+// kind: SELINV_R64, SELINV_C128, SELINV_H128 or SELINV_LU64 (2 nnz values:
+// the lower ones, then their mirrors; 2 panel_elems panels: L with D on the
+// diagonal, then U^T with D on the diagonal)
 int64_t factor_host(const Symbolic &S, int kind, const double *vals, double *panels, int nthreads,
                     double logdet[2]);
 

@@ -211,7 +211,8 @@ __device__ void gemm2_block(const Acc<T> &acc, double *Ls) {
 }
 
 // Row tile a's share of GEMM-2 (Alg. 1 step 4): P_a[:, 64b..] = Lhat[rows of
-// tile a, :]^T Y[tile a, 64b..] = -(Lhat_a^T acc) (^H in a Hermitian plan),
+// tile a, :]^T Y[tile a, 64b..] = -(Lhat_a^T acc) (^H in a Hermitian plan;
+// Uhat_{K,C} of the U^T panel set in place of Lhat^T in an LU plan),
 // written to the partial buffer (column-major s x s per row tile); rows
 // 64qb .. 64qe - 1 of P_a only.
 template <typename T, bool COH>
@@ -231,7 +232,7 @@ __device__ void gemm2_partial(const Ctx<T> &cx, const NodeInfo &nd, int a, int b
     for (int q = 0; q < 64 * 64 / NT; ++q) {
       const int e = threadIdx.x + NT * q;
       const int i = e & 63, x = e >> 6;
-      lv[q] = gload(cx.Lp + off + (((int64_t)(q0 + x) * ld + s + i0 + i) & opaque_mask(i0 + i < c && q0 + x < s)));
+      lv[q] = gload(cx.Lp + pl.half + off + (((int64_t)(q0 + x) * ld + s + i0 + i) & opaque_mask(i0 + i < c && q0 + x < s)));
     }
   };
   const int qend = min(s, qe * 64);
@@ -292,6 +293,7 @@ __device__ void do_ytile(const Ctx<T> &cx, const NodeInfo &nd, int a, int bp, do
     lds_barrier();
     LoadGather<T, COH> la{cx.Xp, pl.kcol + rp, pl.kpos + rp, pl.posarr, rt, rt + 64, c, ke, i0};
     la.cs = pl.csign;
+    la.du = pl.half;  // LU plans: X_{C,C}'s upper part from the X^T panel set
     LoadPanelK<T, false> lb{cx.Lp, off, ld, s, 0, ke, j0, s};
     gemm_tile<T>(kb, ke, la, lb, smem, acc);
   }
@@ -520,6 +522,24 @@ __device__ void dtile_core(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, d
     }
   }
   lds_barrier();
+  if (uniform(pl.half > 0 ? 1 : 0)) {
+    // LU plan: no symmetrization.  X_KK's blocks (a, b) and (b, a) into the
+    // L half, their transposes into the U^T half (entry (r, q) = X(q, r)).
+    T *Xu = Xkk + pl.half;
+    for (int e = threadIdx.x; e < 64 * 64; e += NT) {
+      const int i = e & 63, j = e >> 6;
+      if (a0 + i < s && b0 + j < s) {
+        Mem<COH>::st(Xkk + (int64_t)(b0 + j) * dld + a0 + i, lds_get<T>(Sab, i, j));
+        Mem<COH>::st(Xu + (int64_t)(b0 + j) * dld + a0 + i, lds_get<T>(Sba, j, i));
+      }
+      if (a != b && b0 + i < s && a0 + j < s) {
+        Mem<COH>::st(Xkk + (int64_t)(a0 + j) * dld + b0 + i, lds_get<T>(Sba, i, j));
+        Mem<COH>::st(Xu + (int64_t)(a0 + j) * dld + b0 + i, lds_get<T>(Sab, j, i));
+      }
+    }
+    lds_barrier();
+    return;
+  }
   // x(i, j) = (T[a0+i, b0+j] + T[b0+j, a0+i]) / 2 (the second term conjugated
   // in a Hermitian plan); keep it in Sab
   const double cs = cx.pl->csign;
@@ -941,6 +961,33 @@ __device__ __forceinline__ void do_tiny64(const TinyRec &r, const uint32_t *toff
   }
 }
 
+// LU plans (gathered X_{C,C}, unsplit nodes): the GEMM-1 tile of the upper
+// part, rows 64a.. and columns 64b.. of X_{K,C}^T = -(X_{C,C})^T Uhat^T, where
+// Uhat^T is the normalized U^T panel set and (X_{C,C})^T is gathered with the
+// two X panel sets exchanged; stored into the U half of X.  The upper part
+// takes no GEMM-2 share (A^{-1}_{K,K} needs only X_{C,K}).
+template <typename T, bool COH>
+__device__ void do_yutile(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, double *smem, int64_t *rt) {
+  const DevPlan &pl = *cx.pl;
+  const int s = uniform(nd.s), c = uniform(nd.c), ld = s + c;
+  const int64_t off = nd.off, rp = nd.rp;
+  const int i0 = a * 64, j0 = b * 64;
+  if (threadIdx.x < 64) {
+    const int ig = i0 + threadIdx.x;
+    rt[threadIdx.x] = gp(pl.kcol)[rp + (ig < c ? ig : 0)];
+    rt[64 + threadIdx.x] = gp(pl.kpos)[rp + (ig < c ? ig : 0)];
+  }
+  lds_barrier();
+  Ctx<T> cu = cx;
+  cu.Xp = cx.Xp + pl.half;
+  LoadGather<T, COH> la{cu.Xp, pl.kcol + rp, pl.kpos + rp, pl.posarr, rt, rt + 64, c, c, i0};
+  la.du = -pl.half;
+  LoadPanelK<T, false> lb{cx.Lp + pl.half, off, ld, s, 0, c, j0, s};
+  Acc<T> acc;
+  gemm_tile<T>(0, c, la, lb, smem, acc);
+  store_xtile<T, COH>(cu, nd, a, b, acc, smem);
+}
+
 // Inlined into the kernels, so that the node record stays in scalar registers
 // (a call would pass it through the stack).
 template <typename T, bool COH>
@@ -951,6 +998,8 @@ __device__ __forceinline__ void do_item(const Ctx<T> &cx, const Item &item, cons
     do_gtile<T>(cx, nd, it.a, it.b, smem, rt, cx.Xp);
   } else if (it.type == ITEM_Y) {
     do_ytile<T, COH>(cx, nd, it.a, it.b, smem, rt);
+  } else if (it.type == ITEM_YU) {
+    do_yutile<T, COH>(cx, nd, it.a, it.b, smem, rt);
   } else if (it.type == ITEM_R) {
     do_rtile<T, COH>(cx, nd, it.a, it.b, smem);
   } else if (it.type == ITEM_P) {

@@ -404,9 +404,12 @@ __global__ void __launch_bounds__(NT, 1)
 // The L strip of the next row block is loaded while the current one is used.
 // MAXS bounds s for the nodes of the launch (256, or 64 for a launch of narrow
 // nodes with a quarter of the LDS, so that more workgroups share a CU).
+// hs = 1 (LU plans): the second panel set, U^T, whose unit lower diagonal
+// block gives U_KK^{-T} (into the second half of the linv buffer); D_K^{-1}
+// is written by the hs = 0 launch only.
 template <typename T, int MAXS>
 __global__ void __launch_bounds__(NT) k_normalize_inv(const DevPlan *__restrict__ plp, const T *Src_all, const int2 *chunks,
-                                                      int32_t nchunks) {
+                                                      int32_t nchunks, int hs) {
   constexpr int P = Planes<T>::P, XP = 17, LPI = MAXS + 1, U = MAXS / 16;
   const DevPlan &pl = *plp;
   __shared__ double xs[P][MAXS * XP];  // X(j0 + r, j0 + q) at [r * XP + q]
@@ -416,12 +419,12 @@ __global__ void __launch_bounds__(NT) k_normalize_inv(const DevPlan *__restrict_
   const int2 ck = chunks[g - l * nchunks];
   const int K = uniform(ck.x), j0 = uniform(ck.y) * 16;
   const int s = uniform(gp(pl.node_s)[K]), c = gp(pl.node_c)[K], ld = s + c;
-  const T *Q = Src_all + l * pl.panel_elems + gp(pl.node_off)[K];  // LDL^T panel (read only)
-  T *Linv = reinterpret_cast<T *>(pl.linv) + l * pl.sq_elems + gp(pl.node_sq)[K];
+  const T *Q = Src_all + l * pl.panel_elems + hs * pl.half + gp(pl.node_off)[K];  // LDL^T panel (read only)
+  T *Linv = reinterpret_cast<T *>(pl.linv) + (hs * pl.batch + l) * pl.sq_elems + gp(pl.node_sq)[K];
   T *dinv = reinterpret_cast<T *>(pl.dinv) + l * pl.n + gp(pl.node_first)[K];
   const int w = min(16, s - j0);
   const int t = threadIdx.x;
-  if (t < w) gstore(dinv + j0 + t, SOps<T>::div(SOps<T>::one(), Q[(int64_t)(j0 + t) * ld + j0 + t]));
+  if (t < w && hs == 0) gstore(dinv + j0 + t, SOps<T>::div(SOps<T>::one(), Q[(int64_t)(j0 + t) * ld + j0 + t]));
   // strip element u of thread t: i = e & 15, k = e >> 4 with e = t + NT u (k < MAXS)
   auto strip_ok = [&](int I0, int u) {
     const int e = t + NT * u, i = e & 15, k = e >> 4;
@@ -560,13 +563,15 @@ __global__ void __launch_bounds__(64) k_normalize_small(const DevPlan *__restric
 }
 
 // Lhat_{C,K} = L_{C,K} L_KK^{-1} (Alg. 1 steps 1-2) for one 64-row block a of
-// C(K), column tiles left to right on MFMA.  Column x of Lhat needs only
+// C(K), column tiles left to right on MFMA (hs = 1, LU plans: Uhat_{K,C}^T =
+// U_{K,C}^T U_KK^{-T} in the second panel set).  Column x of Lhat needs only
 // columns k >= x of L (L_KK^{-1} is lower triangular), so a workgroup that
 // owns its row block and writes tile b after finishing it never reads a
 // column it has already overwritten: Q may alias P.
 template <typename T>
 __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
-    k_normalize_gemm(const DevPlan *__restrict__ plp, const T *Src_all, T *Lp_all, const int2 *rblocks, int32_t nrb) {
+    k_normalize_gemm(const DevPlan *__restrict__ plp, const T *Src_all, T *Lp_all, const int2 *rblocks, int32_t nrb,
+                     int hs) {
   const DevPlan &pl = *plp;
   // two GEMM stages or one 64 x 64 result tile, whichever is larger (complex:
   // half of smem_doubles, so that two workgroups share a CU)
@@ -578,10 +583,10 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
   const int2 rb = rblocks[g - l * nrb];
   const int K = uniform(rb.x), i0 = uniform(rb.y) * 64;
   const int s = uniform(gp(pl.node_s)[K]), c = uniform(gp(pl.node_c)[K]), ld = s + c;
-  const int64_t off = gp(pl.node_off)[K];
+  const int64_t off = gp(pl.node_off)[K] + hs * pl.half;
   const T *Q = Src_all + l * pl.panel_elems + off;
   T *P = Lp_all + l * pl.panel_elems + off;
-  const T *Linv = reinterpret_cast<const T *>(pl.linv) + l * pl.sq_elems + gp(pl.node_sq)[K];
+  const T *Linv = reinterpret_cast<const T *>(pl.linv) + (hs * pl.batch + l) * pl.sq_elems + gp(pl.node_sq)[K];
   for (int x0 = 0; x0 < s; x0 += 64) {
     LoadDenseA<T, TK> la{Q + s, ld, c, s, i0};      // L_{C,K}(i, k)
     LoadDenseB<T, TK> lb{Linv, 0, s, 0, s, x0, s};  // L_KK^{-1}(k, x)
@@ -600,6 +605,8 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
 // 32 x 32 output tiles of the s x s blocks (^H for ^T in a Hermitian plan):
 //   mode 0: Dt = L_KK D L_KK^T              -> dt buffer (reads the LDL^T top block)
 //   mode 1: Dt^{-1} = Linv^T D^{-1} Linv    -> panel top block
+//           (LU plans: U_KK^{-1} D^{-1} L_KK^{-1}, the left factor from the
+//           second half of the linv buffer; no mode 0)
 template <typename T>
 __global__ void __launch_bounds__(NT) k_normalize_sq(const DevPlan *__restrict__ plp, const T *Src_all, T *Lp_all, T *dt_all,
                                                      const int4 *tiles, int32_t ntiles, int mode) {
@@ -613,6 +620,7 @@ __global__ void __launch_bounds__(NT) k_normalize_sq(const DevPlan *__restrict__
   const T *Q = Src_all + l * pl.panel_elems + gp(pl.node_off)[K];  // LDL^T panel (mode 0 reads it)
   T *P = Lp_all + l * pl.panel_elems + gp(pl.node_off)[K];         // normalized panel (mode 1 writes it)
   const T *Linv = reinterpret_cast<const T *>(pl.linv) + l * pl.sq_elems + gp(pl.node_sq)[K];
+  const T *Uinv = pl.half > 0 ? Linv + pl.batch * pl.sq_elems : Linv;  // U_KK^{-T} in LU plans
   const T *dinv = reinterpret_cast<const T *>(pl.dinv) + l * pl.n + gp(pl.node_first)[K];
   T acc[4];
 #pragma unroll
@@ -638,7 +646,7 @@ __global__ void __launch_bounds__(NT) k_normalize_sq(const DevPlan *__restrict__
           if (ia < s) va = (ia == k) ? SOps<T>::one() : (ia > k ? Q[(int64_t)k * ld + ia] : zero_of<T>());
           if (jb < s) vb = (jb == k) ? SOps<T>::one() : (jb > k ? Q[(int64_t)k * ld + jb] : zero_of<T>());
         } else {  // Linv[k][i] (column-major, ld s), lower triangular
-          if (ia < s) va = gload(Linv + (int64_t)ia * s + k);
+          if (ia < s) va = gload(Uinv + (int64_t)ia * s + k);
           if (jb < s) vb = gload(Linv + (int64_t)jb * s + k);
         }
         // the transposed factor: L_KK^T (mode 0, right) or Linv^T (mode 1, left)
@@ -706,6 +714,24 @@ __global__ void k_extract(const DevPlan *__restrict__ plp, const T *Xp, T *out) 
   }
 }
 
+// LU plans: out[l][e] = A^{-1}(rowind[e], col e) and out[l][nnz + e] =
+// A^{-1}(col e, rowind[e]); entry e sits at the same position in both panel
+// sets, the X set holding B^{-1} there and the X^T set its transpose, which
+// trade places where the permutation moved the entry into B's upper triangle.
+template <typename T>
+__global__ void k_extract_lu(const DevPlan *__restrict__ plp, const T *Xp, T *out) {
+  const DevPlan &pl = *plp;
+  const int64_t total = pl.batch * pl.nnzA;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = q / pl.nnzA, e = q - l * pl.nnzA;
+    const T *X = Xp + l * pl.panel_elems + gp(pl.apos)[e];
+    const T xl = X[0], xu = X[pl.half];
+    const bool f = gp(pl.aflip)[e] != 0;
+    out[2 * l * pl.nnzA + e] = f ? xu : xl;
+    out[2 * l * pl.nnzA + pl.nnzA + e] = f ? xl : xu;
+  }
+}
+
 // Zero a [batch][panel_elems] array (a kernel rather than a memset, so that
 // the call can sit in a captured graph).
 template <typename T>
@@ -746,22 +772,27 @@ static hipError_t normalize_impl(const DevPlan &pl, const DevPlan *dpl, const La
     return part == 0 ? nall : part == 1 ? ntop : nall - ntop;
   };
   int32_t b;
+  // LU plans (no single-wavefront nodes) normalize both panel sets
+  const int nsets = pl.half > 0 ? 2 : 1;
   const int32_t nsm = (steps & NORM_INV) ? range(aux.nsmall, aux.nsmall_top, b) : 0;
   if (nsm > 0)
     hipLaunchKernelGGL(k_normalize_small<T>, dim3((unsigned)(nsm * pl.batch)), dim3(64), 0, st, dpl, Q, Lp,
                        reinterpret_cast<T *>(dt), aux.small_nodes + b, nsm);
   const int32_t nna = (steps & NORM_INV) ? range(aux.nchunks_narrow, aux.nchunks_narrow_top, b) : 0;
   if (nna > 0)
-    hipLaunchKernelGGL((k_normalize_inv<T, 64>), dim3((unsigned)(nna * pl.batch)), dim3(NT), 0, st, dpl, Q,
-                       aux.chunks_narrow + b, nna);
+    for (int hs = 0; hs < nsets; ++hs)
+      hipLaunchKernelGGL((k_normalize_inv<T, 64>), dim3((unsigned)(nna * pl.batch)), dim3(NT), 0, st, dpl, Q,
+                         aux.chunks_narrow + b, nna, hs);
   const int32_t nch = (steps & NORM_INV) ? range(aux.nchunks, aux.nchunks_top, b) : 0;
   if (nch > 0)
-    hipLaunchKernelGGL((k_normalize_inv<T, 256>), dim3((unsigned)(nch * pl.batch)), dim3(NT), 0, st, dpl, Q,
-                       aux.chunks + b, nch);
+    for (int hs = 0; hs < nsets; ++hs)
+      hipLaunchKernelGGL((k_normalize_inv<T, 256>), dim3((unsigned)(nch * pl.batch)), dim3(NT), 0, st, dpl, Q,
+                         aux.chunks + b, nch, hs);
   const int32_t nrb = (steps & NORM_GEMM) ? range(aux.nrblocks, aux.nrblocks_top, b) : 0;
   if (nrb > 0)
-    hipLaunchKernelGGL(k_normalize_gemm<T>, dim3((unsigned)(nrb * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
-                       aux.rblocks + b, nrb);
+    for (int hs = 0; hs < nsets; ++hs)
+      hipLaunchKernelGGL(k_normalize_gemm<T>, dim3((unsigned)(nrb * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
+                         aux.rblocks + b, nrb, hs);
   const int32_t nsq = (steps & NORM_SQ) ? range(aux.nsq_tiles, aux.nsq_tiles_top, b) : 0;
   if (nsq > 0) {
     if (dt)
@@ -780,17 +811,17 @@ hipError_t launch_linv(const DevPlan &pl, const DevPlan *dpl, bool cplx_, const 
   if (cplx_) {
     if (narrow)
       hipLaunchKernelGGL((k_normalize_inv<cplx, 64>), grid, dim3(NT), 0, st, dpl, reinterpret_cast<const cplx *>(src),
-                         chunks, n);
+                         chunks, n, 0);
     else
       hipLaunchKernelGGL((k_normalize_inv<cplx, 256>), grid, dim3(NT), 0, st, dpl, reinterpret_cast<const cplx *>(src),
-                         chunks, n);
+                         chunks, n, 0);
   } else {
     if (narrow)
       hipLaunchKernelGGL((k_normalize_inv<double, 64>), grid, dim3(NT), 0, st, dpl,
-                         reinterpret_cast<const double *>(src), chunks, n);
+                         reinterpret_cast<const double *>(src), chunks, n, 0);
     else
       hipLaunchKernelGGL((k_normalize_inv<double, 256>), grid, dim3(NT), 0, st, dpl,
-                         reinterpret_cast<const double *>(src), chunks, n);
+                         reinterpret_cast<const double *>(src), chunks, n, 0);
   }
   return hipGetLastError();
 }
@@ -865,7 +896,10 @@ hipError_t launch_extract(const DevPlan &pl, const DevPlan *dpl, bool cplx_, con
   unsigned grid = (unsigned)((total + 255) / 256);
   if (grid > 65536u) grid = 65536u;
   if (grid == 0) grid = 1;
-  if (cplx_)
+  if (pl.half > 0)
+    hipLaunchKernelGGL(k_extract_lu<double>, dim3(grid), dim3(256), 0, st, dpl, reinterpret_cast<const double *>(x),
+                       reinterpret_cast<double *>(out));
+  else if (cplx_)
     hipLaunchKernelGGL(k_extract<cplx>, dim3(grid), dim3(256), 0, st, dpl, reinterpret_cast<const cplx *>(x),
                        reinterpret_cast<cplx *>(out));
   else

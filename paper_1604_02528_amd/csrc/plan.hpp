@@ -28,7 +28,9 @@
 //           buffer and an unsplit contraction: their GEMM-1 tiles then run in
 //           a kernel of their own with fewer registers, two workgroups per
 //           CU); the tile is read back from X.  rq as for ITEM_R.
-// Phases of a node: 0 = ITEM_G, 1 = ITEM_Y, 2 = ITEM_R / ITEM_P, 3 = ITEM_D / ITEM_S
+//   ITEM_YU  (LU plans) the GEMM-1 tile of the upper part: rows 64a.. of
+//           X_{K,C}^T = -(X_{C,C})^T Uhat_{K,C}^T into the U half of X.
+// Phases of a node: 0 = ITEM_G, 1 = ITEM_Y / ITEM_YU, 2 = ITEM_R / ITEM_P, 3 = ITEM_D / ITEM_S
 // (never empty).  A node's first non-empty phase becomes ready when its
 // parent's phase 3 is done (C(K) lies in the ancestors, Eq. (newset)); every
 // later phase becomes ready when the previous non-empty phase is done.
@@ -40,10 +42,10 @@
 
 namespace selinv {
 
-enum ItemType : int32_t { ITEM_Y = 0, ITEM_D = 1, ITEM_S = 2, ITEM_G = 3, ITEM_R = 4, ITEM_P = 5 };
+enum ItemType : int32_t { ITEM_Y = 0, ITEM_D = 1, ITEM_S = 2, ITEM_G = 3, ITEM_R = 4, ITEM_P = 5, ITEM_YU = 6 };
 constexpr int kPhases = 4;
 __host__ __device__ constexpr int item_phase(int type) {
-  return type == ITEM_G ? 0 : type == ITEM_Y ? 1 : (type == ITEM_R || type == ITEM_P) ? 2 : 3;
+  return type == ITEM_G ? 0 : (type == ITEM_Y || type == ITEM_YU) ? 1 : (type == ITEM_R || type == ITEM_P) ? 2 : 3;
 }
 
 // Work items of the adjoint (reverse) sweep; see adjoint.hip.  R1 runs
@@ -142,6 +144,8 @@ struct DevPlan {
   uint8_t *adiag;      // [nnzA]
   uint8_t *aflip;      // [nnzA] the entry lands in B's upper triangle (conjugated if Hermitian)
   double csign;        // -1: Hermitian plan (conjugate transposes), +1 otherwise
+  int64_t half;        // LU plans: elements of one panel set; a matrix's panels (and X) are the L
+                       // set, then the U^T set (panel_elems = 2 half); 0 otherwise
   // scratch
   void *linv;          // [batch][sq_elems] scalars
   void *dinv;          // [batch][n] scalars

@@ -397,6 +397,8 @@ template <typename T, bool COH> struct LoadGather {
   const int64_t *rt_col, *rt_pos;  // LDS copies for rows i0 .. i0+63
   int c, kend, i0;  // rows and columns of X_{C,C} < c; contraction indices < kend
   double cs = 1.0;  // -1 in a Hermitian plan: the upper part is the conjugate of the stored lower part
+  int64_t du = 0;   // LU plans: the upper part is read from X + du (the other panel set) at the
+                    // transposed position
   __device__ __forceinline__ void coords(int k0, int m, int &i, int &kk) const {
     constexpr int TK = Planes<T>::TK;
     const int e = threadIdx.x + NT * m;
@@ -444,7 +446,7 @@ template <typename T, bool COH> struct LoadGather {
       const int ig = i0 + i, kg = k0 + kk;
       const int64_t okm = opaque_mask(ig < c && kg < c);
       const int64_t lm = opaque_mask(ig >= kg);
-      const int64_t bu = rt_col[i], pu = rt_pos[i];
+      const int64_t bu = rt_col[i] + du, pu = rt_pos[i];
       q.base[m] = (r.bl[m] & lm) | (bu & ~lm);
       const int64_t pidx = (((r.plo[m] + ig) & lm) | ((pu + kg) & ~lm)) & okm;
       q.pos[m] = gp(posarr)[pidx];

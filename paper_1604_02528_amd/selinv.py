@@ -5,6 +5,11 @@
     S.run()                   # selected inversion on the GPU (async)
     X = S.extract()           # [batch, nnz(A)] selected entries on A's pattern
 
+dtype="lu64" takes an unsymmetric real A with a symmetric pattern: values are
+[batch, 2 nnz(A)] (the stored lower entries, then their mirrors A(j, i)), the
+panels and X hold two panel sets (L and X, then U^T and X^T), and extract()
+returns [batch, 2 nnz(A)] in the values' order.
+
 Everything numeric runs in the library (host C++ factorization, HIP kernels
 for the rest); this module only allocates buffers and passes pointers.
 """
@@ -30,15 +35,18 @@ class SelInv:
                  sched="levels", nthreads=0, watchdog_ms=0, dense_min_c=0, dense_max_bytes=0, split_min_k=0,
                  tune_cache=None, adjoint=True, device="cuda"):
         self.n = int(n)
-        if dtype not in ("f64", "float64", torch.float64, "c128", "complex128", torch.complex128, "h128", "hermitian"):
-            raise ValueError(f"unknown dtype {dtype!r} (f64, c128 = complex-symmetric, h128 = Hermitian)")
+        if dtype not in ("f64", "float64", torch.float64, "c128", "complex128", torch.complex128, "h128", "hermitian",
+                         "lu64", "lu"):
+            raise ValueError(f"unknown dtype {dtype!r} (f64, c128 = complex-symmetric, h128 = Hermitian, "
+                             "lu64 = unsymmetric real with a symmetric pattern)")
         self.is_hermitian = dtype in ("h128", "hermitian")
+        self.is_lu = dtype in ("lu64", "lu")
         self.is_complex = self.is_hermitian or dtype in ("c128", "complex128", torch.complex128)
         self.batch = int(batch)
         self.device = device
         o = capi.selinv_default_opts()
         o.max_super = int(cap)
-        o.dtype = (capi.SELINV_H128 if self.is_hermitian else
+        o.dtype = (capi.SELINV_H128 if self.is_hermitian else capi.SELINV_LU64 if self.is_lu else
                    capi.SELINV_C128 if self.is_complex else capi.SELINV_R64)
         o.batch = self.batch
         o.sched = {"levels": capi.SCHED_LEVELS, "persistent": capi.SCHED_PERSISTENT, "push": capi.SCHED_PUSH}[sched]
@@ -58,6 +66,7 @@ class SelInv:
         self.view = capi.selinv_symbolic(self.h)
         self.sizes = capi.selinv_sizes(self.h)
         self.nnzA = int(self._colptr[-1])
+        self.nvals = 2 * self.nnzA if self.is_lu else self.nnzA  # values (and extracted entries) per matrix
         self.panel_elems = int(self.view.panel_elems)
         self._bufs = None
         self.dtilde = None
@@ -104,7 +113,8 @@ class SelInv:
         return b[:nb].view(self.scalar_dtype).view(self.batch, self.panel_elems)
 
     def packed_index(self):
-        """Element indices of the unpadded concatenation of the panels."""
+        """Element indices of the unpadded concatenation of the panels (LU:
+        of the first panel set, then of the second)."""
         if getattr(self, "_packed", None) is None:
             sym = self.symbolic()
             ws = np.diff(sym["xsuper"])
@@ -112,6 +122,8 @@ class SelInv:
             sizes = (ws + cs) * ws
             starts = sym["panel_off"]
             idx = np.concatenate([np.arange(st, st + sz) for st, sz in zip(starts, sizes)]) if len(sizes) else np.zeros(0, np.int64)
+            if self.is_lu:
+                idx = np.concatenate([idx, idx + self.panel_elems // 2])
             self._packed = idx
         return self._packed
 
@@ -125,12 +137,12 @@ class SelInv:
         if isinstance(values, torch.Tensor):
             values = values.detach().cpu().numpy()
         dt = np.complex128 if self.is_complex else np.float64
-        v = np.ascontiguousarray(np.asarray(values).reshape(self.batch, self.nnzA), dtype=dt)
+        v = np.ascontiguousarray(np.asarray(values).reshape(self.batch, self.nvals), dtype=dt)
         return v
 
     def _values_device(self, values):
         v = torch.as_tensor(values)
-        return v.to(device=self.device, dtype=self.scalar_dtype).reshape(self.batch, self.nnzA).contiguous()
+        return v.to(device=self.device, dtype=self.scalar_dtype).reshape(self.batch, self.nvals).contiguous()
 
     def factor(self, values, want_dtilde=False, on_device=False):
         """LDL^T of every matrix (host C++, or on the GPU with on_device=True),
@@ -185,7 +197,7 @@ class SelInv:
 
     def extract(self, out=None):
         if out is None:
-            out = torch.empty((self.batch, self.nnzA), dtype=self.scalar_dtype, device=self.device)
+            out = torch.empty((self.batch, self.nvals), dtype=self.scalar_dtype, device=self.device)
         capi.selinv_extract(self.h, self._bufs["x"], self._bufs["work"], out, _stream())
         return out
 

@@ -21,11 +21,18 @@ def oracle_sym(name, scale=None, batch=None, relax=0.0):
 
 @functools.lru_cache(maxsize=None)
 def oracle_x(name, scale=None, batch=None, relax=0.0):
-    """Flattened oracle X panels [batch, panel_elems] (Alg. 1)."""
+    """Flattened oracle X panels [batch, panel_elems] (Alg. 1; for an LU
+    workload the X set followed by the X^T set)."""
     w = workload(name, scale, batch)
     sym = oracle_sym(name, scale, batch, relax)
     h = w.is_hermitian
     out = []
+    if w.is_lu:  # both panel sets: X on the pattern of L, then X^T (Alg. 1, LU form)
+        for l in range(w.batch):
+            PL, PU = factor.factor_lu(sym, w.lower_values[l], w.upper_values[l])
+            XL, XU = selinv.alg1_lu(sym, *factor.normalize_lu(sym, PL, PU))
+            out.append(np.concatenate([selinv.flatten(sym, XL), selinv.flatten(sym, XU)]))
+        return np.stack(out)
     for l in range(w.batch):
         P = factor.factor(sym, w.values[l], herm=h)
         lh, dt = factor.normalize(sym, P, herm=h)

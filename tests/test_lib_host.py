@@ -129,3 +129,71 @@ def test_host_factor_hermitian_random_permuted(seed):
     mask = np.concatenate([np.tril(np.ones((sym.width(K) + sym.rows[K].shape[0], sym.width(K)), bool)).reshape(-1, order="F")
                            for K in range(sym.nsuper)])
     assert np.max(np.abs(P[0][mask] - ref[mask])) <= 1e-13 * np.max(np.abs(ref[mask]))
+
+
+def _lower_mask(sym):
+    return np.concatenate([np.tril(np.ones((sym.width(K) + sym.rows[K].shape[0], sym.width(K)), bool)).reshape(-1, order="F")
+                           for K in range(sym.nsuper)])
+
+
+@pytest.mark.parametrize("relax", [0.0, 0.05])
+@pytest.mark.parametrize("scale,batch", [(6, 2), (10, 2)])
+def test_host_factor_lu_matches_oracle(scale, batch, relax):
+    """The library's host L D U (dtype lu64): both panel sets against the
+    oracle's factor_lu, and the log det."""
+    from paper_1604_02528_amd import SelInv
+
+    w = workload("U3", scale, batch)
+    sym = oracle_sym("U3", scale, batch, relax)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="lu64", batch=w.batch, cap=w.cap, relax=relax, device="cpu")
+    P = S.factor_host(w.values)[:, S.packed_index()]
+    mask = _lower_mask(sym)
+    half = mask.size
+    for l in range(w.batch):
+        PL, PU = factor.factor_lu(sym, w.lower_values[l], w.upper_values[l])
+        for got, ref in ((P[l][:half], selinv.flatten(sym, PL)), (P[l][half:], selinv.flatten(sym, PU))):
+            err = np.max(np.abs(got[mask] - ref[mask])) / np.max(np.abs(ref[mask]))
+            assert err < 1e-13
+        ld = S.logdet()[l]
+        ref_ld = factor.logdet(sym, PL)
+        assert abs(ld - np.real(ref_ld)) <= 1e-10 * max(1.0, abs(ref_ld))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_host_factor_lu_random_permuted(seed):
+    """Random unsymmetric values on random symmetric patterns under random
+    permutations: an entry moved into B's upper triangle trades its value with
+    its mirror."""
+    from paper_1604_02528_amd import SelInv
+    from tests.test_oracle_lu import unsymmetric_random
+
+    rng = np.random.default_rng(1700 + seed)
+    n = int(rng.integers(20, 120))
+    colptr, rowind, lo, up = unsymmetric_random(n, 0.08, rng)
+    perm = rng.permutation(n).astype(np.int64)
+    cap = int(rng.integers(2, 30))
+    sym = symbolic.analyze(n, colptr, rowind, perm, cap=cap)
+    S = SelInv(n, colptr, rowind, perm, dtype="lu64", batch=1, cap=cap, relax=0.0, device="cpu")
+    P = S.factor_host(np.concatenate([lo, up])[None, :])[:, S.packed_index()]
+    PL, PU = factor.factor_lu(sym, lo, up)
+    mask = _lower_mask(sym)
+    half = mask.size
+    for got, ref in ((P[0][:half], selinv.flatten(sym, PL)), (P[0][half:], selinv.flatten(sym, PU))):
+        assert np.max(np.abs(got[mask] - ref[mask])) <= 1e-13 * np.max(np.abs(ref[mask]))
+
+
+def test_lu_plan_replay_and_refusals():
+    """An LU plan passes the scheduler replay; the paths the LU form does not
+    have are refused (schedules other than levels at analyze time)."""
+    from paper_1604_02528_amd import SelInv, capi
+
+    w = workload("U3", 8, 2)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="lu64", batch=w.batch, cap=w.cap, relax=0.05, device="cpu")
+    capi.selinv_check_plan(S.h)
+    R = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="f64", batch=w.batch, cap=w.cap, relax=0.05, device="cpu")
+    assert S.panel_elems == 2 * R.panel_elems  # two panel sets of the symmetric layout
+    assert S.packed_index().size == 2 * R.packed_index().size
+    for sched in ("persistent", "push"):
+        with pytest.raises(capi.SelinvError) as ei:
+            SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="lu64", batch=w.batch, cap=w.cap, sched=sched, device="cpu")
+        assert ei.value.status == 7
