@@ -400,7 +400,8 @@ selinv_status selinv_trace(selinv_ctx *h, void *trace_dev);
  *   which = 2: the forward traversal's launches under the level and push
  *     schedules, in order: {kind (0 work items, 1 single-wavefront nodes,
  *     2 GEMM-1-only dense-buffer tiles, 3 push tiles, 4 GEMM-1-only
- *     128 x 128 tiles of FP64 nodes the tune table marks), items or records
+ *     128 x 128 tiles of FP64 nodes the tune table marks, 5 gathers into
+ *     the dense X_{C,C} buffers, 6 GEMM-2 shares), items or records
  *     per matrix, type of the first item (-1 for push tiles), etree depth}.  The list is
  *     built for every plan; the persistent schedule does not launch by it.
  * Errors: SELINV_EINVAL for another `which`.

@@ -586,7 +586,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
             const int32_t b = phase_begin(H, K, ph), n = phase_count(H, K, ph);
             for (int32_t q = 0; q < n; ++q) H.lvl_items.push_back(b + q);
           }
-          close(-1, pass == 1 ? LVL_YDENSE : LVL_ITEMS);
+          close(-1, pass == 1 ? LVL_YDENSE : ph == 0 ? LVL_GATHER : ph == 2 ? LVL_GEMM2 : LVL_ITEMS);
         }
         if (ph == 1) {
           // 128 x 128 GEMM-1 tiles of the depth's FP64 dense-buffer nodes the tune table marks

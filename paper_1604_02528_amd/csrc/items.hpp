@@ -214,8 +214,10 @@ __device__ void gemm2_block(const Acc<T> &acc, double *Ls) {
 // tile a, :]^T Y[tile a, 64b..] = -(Lhat_a^T acc) (^H in a Hermitian plan;
 // Uhat_{K,C} of the U^T panel set in place of Lhat^T in an LU plan),
 // written to the partial buffer (column-major s x s per row tile); rows
-// 64qb .. 64qe - 1 of P_a only.
-template <typename T, bool COH>
+// 64qb .. 64qe - 1 of P_a only.  PF: load the next 64 columns of Lhat while
+// the current block is multiplied (off in kernels that rely on occupancy
+// instead, so that the prefetch registers do not cost a workgroup per CU).
+template <typename T, bool COH, bool PF = true>
 __device__ void gemm2_partial(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, const Acc<T> &acc, double *smem,
                               int qb = 0, int qe = 1 << 20) {
   constexpr int P = Planes<T>::P;
@@ -237,8 +239,9 @@ __device__ void gemm2_partial(const Ctx<T> &cx, const NodeInfo &nd, int a, int b
   };
   const int qend = min(s, qe * 64);
   const double cs = pl.csign;
-  load_l(qb * 64);
+  if (PF) load_l(qb * 64);
   for (int q0 = qb * 64; q0 < qend; q0 += 64) {
+    if (!PF) load_l(q0);
 #pragma unroll
     for (int q = 0; q < 64 * 64 / NT; ++q) {
       const int e = threadIdx.x + NT * q;
@@ -248,7 +251,7 @@ __device__ void gemm2_partial(const Ctx<T> &cx, const NodeInfo &nd, int a, int b
       for (int p = 0; p < P; ++p) Ls[p * 64 * PITCH + i * PITCH + x] = Planes<T>::get(v, p);
     }
     lds_barrier();
-    if (q0 + 64 < qend) load_l(q0 + 64);
+    if (PF && q0 + 64 < qend) load_l(q0 + 64);
     gemm2_block<T>(acc, Ls);
     // P = Lhat^T Y = -(Lhat^T acc)
     const double *R = Ls;
@@ -319,7 +322,7 @@ __device__ void do_ytile(const Ctx<T> &cx, const NodeInfo &nd, int a, int bp, do
 // into rq items by rows of P_a: item r computes 64-row blocks [r nq / rq,
 // (r + 1) nq / rq) of the nq = ceil(s / 64), and item 0 alone stores the tile.
 // Every item sums the parts in the same order, so the result is the same.
-template <typename T, bool COH>
+template <typename T, bool COH, bool PF = true>
 __device__ void do_rtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int br, double *smem) {
   const DevPlan &pl = *cx.pl;
   const int s = uniform(nd.s), c = uniform(nd.c);
@@ -379,14 +382,14 @@ __device__ void do_rtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int br, do
         }
   lds_barrier();
   if (r == 0) store_xtile<T, COH>(cx, nd, a, b, acc, smem);
-  gemm2_partial<T, COH>(cx, nd, a, b, acc, smem, qb, qe);
+  gemm2_partial<T, COH, PF>(cx, nd, a, b, acc, smem, qb, qe);
 }
 
 // The GEMM-2 share of a tile whose GEMM-1 item stored Y = X_{C,K} (rows 64a..,
 // columns 64b..) without it: the tile is read back from X into the
 // accumulator layout (acc = -Y) and gemm2_partial computes 64-row blocks
 // [qb, qe) of P_a, with br = b | r << 16 | rq << 24 as for do_rtile.
-template <typename T, bool COH>
+template <typename T, bool COH, bool PF = true>
 __device__ void do_ptile(const Ctx<T> &cx, const NodeInfo &nd, int a, int br, double *smem) {
   const int s = uniform(nd.s), c = uniform(nd.c), ld = s + c;
   const int b = br & 0xffff, r = (br >> 16) & 0xff, rq = max(1, br >> 24);
@@ -425,7 +428,7 @@ __device__ void do_ptile(const Ctx<T> &cx, const NodeInfo &nd, int a, int br, do
           acc.v[p][bi][bj][vv] = smem[p * 64 * PITCH + j * PITCH + i];
         }
   lds_barrier();
-  gemm2_partial<T, COH>(cx, nd, a, b, acc, smem, qb, qe);
+  gemm2_partial<T, COH, PF>(cx, nd, a, b, acc, smem, qb, qe);
 }
 
 // GEMM-1 tile of a node with a dense X_{C,C} buffer, without GEMM-2: the

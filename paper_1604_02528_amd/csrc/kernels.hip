@@ -61,6 +61,74 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1) k_items_list(co
   }
 }
 
+// Gathers of X_{C,C} into the dense buffers (the G items of a depth, Alg. 1
+// step 3): three dependent rounds of loads per 64 x 64 block and no MFMA,
+// so the kernel takes one tile of LDS and few registers, and twice as many
+// workgroups share a CU as in k_items_list (more loads in flight).
+template <typename T>
+__global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 4 : 2) k_gather_list(const DevPlan *__restrict__ plp, T *Xp,
+                                                                              const LRec *recs, const int32_t *list,
+                                                                              int32_t count, int32_t list_pos) {
+  const DevPlan &pl = *plp;
+  __shared__ double smem[tile_doubles<T>()];
+  __shared__ int64_t rt[128];
+  const int64_t g = blockIdx.x;
+  const int64_t l = g / count;
+  const int64_t q = g - l * count;
+  const int64_t t_start = pl.trace ? wall_clock64() : 0;
+  Ctx<T> cx{&pl, nullptr, Xp + l * pl.panel_elems, nullptr, static_cast<T *>(pl.gbuf) + l * pl.g_elems, nullptr};
+  const LRec rec = recs[q];
+  const Item it = uniform(rec.it);
+  do_gtile<T>(cx, uniform(rec.nd), it.a, it.b, smem, rt, cx.Xp);
+  if (pl.trace) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t *tr = pl.trace + 8 * ((int64_t)list_pos * pl.batch + g);
+      tr[0] = l * pl.nitems + list[q];
+      tr[1] = blockIdx.x;
+      tr[2] = t_start;
+      tr[3] = t_start;
+      tr[4] = wall_clock64();
+    }
+  }
+}
+
+// GEMM-2 shares of a depth (the R and P items, Alg. 1 step 4): one tile of
+// LDS and no GEMM-1 operand stages (and, for complex, no Lhat prefetch), so
+// that two workgroups share a CU also for complex (one in k_items_list).
+template <typename T>
+__global__ void __launch_bounds__(NT, 2) k_gemm2_list(const DevPlan *__restrict__ plp, const T *Lp,
+                                                                             T *Xp, T *Pp, const LRec *recs,
+                                                                             const int32_t *list, int32_t count,
+                                                                             int32_t list_pos) {
+  const DevPlan &pl = *plp;
+  __shared__ double smem[tile_doubles<T>()];
+  const int64_t g = blockIdx.x;
+  const int64_t l = g / count;
+  const int64_t q = g - l * count;
+  const int64_t t_start = pl.trace ? wall_clock64() : 0;
+  Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, Pp + l * pl.part_elems, nullptr,
+            static_cast<T *>(pl.ypart) + l * pl.y_elems};
+  const LRec rec = recs[q];
+  const Item it = uniform(rec.it);
+  constexpr bool PF = Planes<T>::P == 1;  // FP64 keeps the prefetch within two workgroups per CU
+  if (it.type == ITEM_R)
+    do_rtile<T, false, PF>(cx, uniform(rec.nd), it.a, it.b, smem);
+  else
+    do_ptile<T, false, PF>(cx, uniform(rec.nd), it.a, it.b, smem);
+  if (pl.trace) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t *tr = pl.trace + 8 * ((int64_t)list_pos * pl.batch + g);
+      tr[0] = l * pl.nitems + list[q];
+      tr[1] = blockIdx.x;
+      tr[2] = t_start;
+      tr[3] = t_start;
+      tr[4] = wall_clock64();
+    }
+  }
+}
+
 // GEMM-1 tiles of nodes with a dense X_{C,C} buffer (see do_ytile_dense): no
 // GEMM-2 in this kernel, so it fits two workgroups per CU also for complex.
 template <typename T>
@@ -864,6 +932,12 @@ static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
                              aux.y128 + aux.lvl_tiny[q], e - b, b);
       } else if (aux.lvl_kind[q] == LVL_YDENSE)
         hipLaunchKernelGGL(k_ydense<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp,
+                           aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
+      else if (aux.lvl_kind[q] == LVL_GATHER)
+        hipLaunchKernelGGL(k_gather_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Xp,
+                           aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
+      else if (aux.lvl_kind[q] == LVL_GEMM2)
+        hipLaunchKernelGGL(k_gemm2_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,
                            aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
       else
         hipLaunchKernelGGL(k_items_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,

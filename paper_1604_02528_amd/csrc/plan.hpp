@@ -168,7 +168,9 @@ struct DevPlan {
 };
 
 // Kernels of the level launches.
-enum LevelKind : int32_t { LVL_ITEMS = 0, LVL_TINY = 1, LVL_YDENSE = 2, LVL_PUSH = 3, LVL_Y128 = 4 };
+enum LevelKind : int32_t {
+  LVL_ITEMS = 0, LVL_TINY = 1, LVL_YDENSE = 2, LVL_PUSH = 3, LVL_Y128 = 4, LVL_GATHER = 5, LVL_GEMM2 = 6
+};
 
 // A tile of the left-looking (push) form, Alg. 2: supernode K pushes into the
 // X panel of a descendant I (K owns rows C(I)[st, en) of I's row set).  The
@@ -199,7 +201,7 @@ struct LaunchAux {
   const LRec *lvl_recs;     // the same items' records with their nodes, in that order
   const int32_t *lvl_ptr;   // host array [nlvl + 1]
   const int32_t *lvl_tiny;  // host array [nlvl]: -1 (work items), else the first TinyRec of the range
-  const int32_t *lvl_kind;  // host array [nlvl]: LVL_ITEMS, LVL_TINY, LVL_YDENSE or LVL_PUSH
+  const int32_t *lvl_kind;  // host array [nlvl]: a LevelKind
   const PushRec *push;      // push-form tiles (LVL_PUSH launches start at lvl_tiny[q])
   const Item *y128;         // 128 x 128 GEMM-1 tiles of FP64 dense-buffer nodes (LVL_Y128 launches
                             // start at lvl_tiny[q]): {K, ITEM_Y, row tile, column tile | part << 16}

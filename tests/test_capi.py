@@ -215,7 +215,17 @@ def test_level_launch_list(name, scale):
         rows = L[L[:, 3] == d]
         ph = [4 if k == 1 else phase[t] for k, t in zip(rows[:, 0], rows[:, 2])]
         assert ph == sorted(ph), (d, rows)
-        assert set(rows[:, 0]) <= {0, 1, 2}
+        assert set(rows[:, 0]) <= {0, 1, 2, 5, 6}
+        # each launch runs the kernel of its phase: gathers (5), GEMM-2 shares (6)
+        for k, t in zip(rows[:, 0], rows[:, 2]):
+            if k == 5:
+                assert t == 3
+            if k == 6:
+                assert t in (4, 5)
+            if t == 3:
+                assert k == 5
+            if t in (4, 5):
+                assert k == 6
 
 
 def _drop_entry(colptr, rowind, vals, j, k):
