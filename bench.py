@@ -604,14 +604,18 @@ def main():
                                      "on a 1 GiB device copy)",
                      "algorithmic_bytes": algorithmic_bytes(w, args.relax),
                      "kernel": {"levels": "k_ydense (GEMM-1 tiles of nodes with a dense X_{C,C} buffer), "
-                                          "k_items_list (the other items) and k_tiny (single-wavefront small "
-                                          "nodes), one launch per etree depth and phase",
+                                          "k_gather_list (gathers into those buffers), k_gemm2_list (GEMM-2 "
+                                          "shares), k_items_list (the other items) and k_tiny "
+                                          "(single-wavefront small nodes), one launch per etree depth and phase",
                                 "persistent": "k_persistent, one launch",
                                 "push": "k_push (the O/I/ID tiles of the left-looking form) and k_items_list "
                                         "(the D step), one launch per etree depth and step"}[args.sched],
                      "selinv_run_ms": round(t_run * 1e3, 4),
                      "note": "achieved = algorithmic flops of one traversal (all matrices of the batch) / "
-                             "HIP-event time of selinv_run (all of its launches) on the launch stream"},
+                             "HIP-event time of selinv_run (all of its launches) on the launch stream; a complex "
+                             "multiply-add counts 8 real flops (the usual convention), while k_ydense forms "
+                             "complex products from three real MFMA chains (3M), so the MFMA counter reads "
+                             "fewer executed flops than this count"},
         "normalize_ms": round(t_norm * 1e3, 4),
         "max_rel_err_vs_oracle": err,
         "t_factor_device_s": sm["t_factor_device_s"],

@@ -448,7 +448,7 @@ __device__ __forceinline__ void do_ytile_dense(const Ctx<T> &cx, const NodeInfo 
   LoadDenseA<T, TK> la{G, nd.ldg, c, ke, i0};
   LoadDenseB<T, TK> lb{cx.Lp, nd.off, ld, s, ke, j0, s};
   Acc<T> acc;
-  gemm_dense<T>(kb, ke, la, lb, smem, acc);
+  gemm_dense<T, true>(kb, ke, la, lb, smem, acc);  // complex: three real product chains
   acc_to_lds<T>(acc, smem);
   lds_barrier();
   if (nd.yoff < 0) {  // Y = -acc into X_{C,K}

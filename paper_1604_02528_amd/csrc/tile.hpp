@@ -663,19 +663,75 @@ template <typename T, int TK> __device__ __forceinline__ constexpr int dense_sta
   return 2 * Planes<T>::P * TK * PITCH;
 }
 
+// Complex products with three real MFMA chains instead of four (the 3M or
+// Gauss form): P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), then
+// Re = P1 - P2 and Im = P3 - P1 - P2.  The operand sums are formed from the
+// two LDS planes as they are read, so the stages keep their layout.  Its
+// rounding error bound is that of the four-product form with |Ar| + |Ai| and
+// |Br| + |Bi| in place of the moduli (the same order).
+struct Acc3M {
+  d4 v[3][2][2];
+};
+
+template <int TK>
+__device__ __forceinline__ void stage_compute_3m(const double *stg, Acc3M &acc) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wi = w & 1, wj = w >> 1;
+#pragma unroll
+  for (int k4 = 0; k4 < TK / 4; ++k4) {
+    const int r = (4 * k4 + (lane >> 4)) * PITCH + (lane & 15);
+    double a[2][2], b[2][2], as[2], bs[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        a[x][p] = stg[p * TK * PITCH + r + 32 * wi + 16 * x];
+        b[x][p] = stg[(2 + p) * TK * PITCH + r + 32 * wj + 16 * x];
+      }
+      as[x] = a[x][0] + a[x][1];
+      bs[x] = b[x][0] + b[x][1];
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        acc.v[0][bi][bj] = mfma16(a[bi][0], b[bj][0], acc.v[0][bi][bj]);
+        acc.v[1][bi][bj] = mfma16(a[bi][1], b[bj][1], acc.v[1][bi][bj]);
+        acc.v[2][bi][bj] = mfma16(as[bi], bs[bj], acc.v[2][bi][bj]);
+      }
+  }
+}
+
 // acc (+)= A (64 x [kb, ke)) * B ([kb, ke) x 64) from dense operands.  Two
 // register sets alternate, so the loads of a stage are issued two
 // stage-computations before they are stored to LDS; waits are counted waits
 // on the older set only.  kb, ke and accumulate must be wave-uniform.
-template <typename T, class LA, class LB>
+// G3: complex products in the three-chain form (Acc3M) instead of four.
+template <typename T, bool G3 = false, class LA, class LB>
 __device__ __forceinline__ void gemm_dense(int kb, int ke, const LA &la, const LB &lb, double *smem, Acc<T> &acc,
                                            bool accumulate = false) {
   constexpr int TK = DenseTK<T>::TK, P = Planes<T>::P;
+  constexpr bool M3 = G3 && P == 2;
   constexpr int SD = dense_stage_doubles<T, TK>();
   using V = DVals<T, TK>;
   if (!accumulate) acc_zero<T>(acc);
   const int nk = (ke - kb + TK - 1) / TK;
   if (nk <= 0) return;
+  Acc3M a3;
+  if constexpr (M3) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) a3.v[q][bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  auto compute = [&](const double *stg) {
+    if constexpr (M3)
+      stage_compute_3m<TK>(stg, a3);
+    else
+      stage_compute<T, TK>(stg, acc);
+  };
   const int klast = kb + (nk - 1) * TK;
   auto kat = [&](int j) { return min(kb + j * TK, klast); };
   V a0, b0, a1, b1;
@@ -690,7 +746,7 @@ __device__ __forceinline__ void gemm_dense(int kb, int ke, const LA &la, const L
   lds_barrier();
   for (int kt = 0;; kt += 2) {
     // LDS stage 0 holds kt; set 1 holds kt + 1, set 0 holds kt + 2
-    stage_compute<T, TK>(smem, acc);
+    compute(smem);
     if (kt + 1 >= nk) break;
     stage_store_dense<T, LA, V, TK>(smem + SD, 0, kat(kt + 1), la, a1);
     stage_store_dense<T, LB, V, TK>(smem + SD, P, kat(kt + 1), lb, b1);
@@ -698,7 +754,7 @@ __device__ __forceinline__ void gemm_dense(int kb, int ke, const LA &la, const L
     la.load(kat(kt + 3), a1);
     lb.load(kat(kt + 3), b1);
     __builtin_amdgcn_sched_barrier(0);  // issue the loads before the MFMA block
-    stage_compute<T, TK>(smem + SD, acc);
+    compute(smem + SD);
     if (kt + 2 >= nk) break;
     stage_store_dense<T, LA, V, TK>(smem, 0, kat(kt + 2), la, a0);
     stage_store_dense<T, LB, V, TK>(smem, P, kat(kt + 2), lb, b0);
@@ -706,6 +762,17 @@ __device__ __forceinline__ void gemm_dense(int kb, int ke, const LA &la, const L
     la.load(kat(kt + 4), a0);
     lb.load(kat(kt + 4), b0);
     __builtin_amdgcn_sched_barrier(0);
+  }
+  if constexpr (M3) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const d4 re = a3.v[0][bi][bj] - a3.v[1][bi][bj];
+        const d4 im = a3.v[2][bi][bj] - a3.v[0][bi][bj] - a3.v[1][bi][bj];
+        acc.v[0][bi][bj] += re;
+        acc.v[1][bi][bj] += im;
+      }
   }
   lds_barrier();  // the caller reuses the stage buffers
 }
