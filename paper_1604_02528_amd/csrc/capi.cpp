@@ -651,6 +651,9 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     n.split = H.node_split[K];
     n.kchunk = H.node_kchunk[K];
     n.defer2 = H.node_defer[K];
+    // the dense buffer of a node whose GEMM-1 runs in k_ydense holds the
+    // lower triangle only (k_ydense reads the rest mirrored)
+    n.glow = H.node_ykern[K] && !H.node_y128[K];
     n.off = H.node_off[K];
     n.rp = H.node_rowptr[K];
     n.goff = H.node_goff[K];

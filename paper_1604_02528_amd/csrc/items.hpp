@@ -40,6 +40,7 @@ __device__ __forceinline__ NodeInfo uniform(const NodeInfo &a) {
   n.split = uniform(a.split);
   n.kchunk = uniform(a.kchunk);
   n.defer2 = uniform(a.defer2);
+  n.glow = uniform(a.glow);
   n.off = uniform64(a.off);
   n.rp = uniform64(a.rp);
   n.goff = uniform64(a.goff);
@@ -58,7 +59,7 @@ __device__ __forceinline__ NodeInfo node_info(const DevPlan &pl, int K) {
   n.ldg = uniform(gp(pl.node_ldg)[K]);
   n.split = uniform(gp(pl.node_split)[K]);
   n.kchunk = uniform(gp(pl.node_kchunk)[K]);
-  n.defer2 = n.pad1 = 0;
+  n.defer2 = n.glow = 0;
   n.off = uniform64(gp(pl.node_off)[K]);
   n.rp = uniform64(gp(pl.node_rowptr)[K]);
   n.goff = uniform64(gp(pl.node_goff)[K]);
@@ -117,13 +118,16 @@ __device__ void do_gtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, dou
     if (ok) Mem<false>::st(G + (int64_t)k * ldg + i, x);
   }
   lds_barrier();
-  // mirror: G(k, i) = tile[i][k] (its conjugate if Hermitian), lanes along k
+  // mirror: G(k, i) = tile[i][k] (its conjugate if Hermitian), lanes along k;
+  // a lower-only buffer keeps the mirrors of diagonal blocks alone
   const double cs = pl.csign;
+  if (uniform(nd.glow != 0 && a != b ? 0 : 1)) {
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = threadIdx.x + NT * q;
-    const int kl = e & 63, il = e >> 6, i = i0 + il, k = k0 + kl;
-    if (i < c && k < c && i > k) Mem<false>::st(G + (int64_t)i * ldg + k, cj(lds_get<T>(smem, il, kl), cs));
+    for (int q = 0; q < Q; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const int kl = e & 63, il = e >> 6, i = i0 + il, k = k0 + kl;
+      if (i < c && k < c && i > k) Mem<false>::st(G + (int64_t)i * ldg + k, cj(lds_get<T>(smem, il, kl), cs));
+    }
   }
   lds_barrier();
 }
@@ -445,7 +449,8 @@ __device__ __forceinline__ void do_ytile_dense(const Ctx<T> &cx, const NodeInfo 
   const int i0 = a * 64, j0 = b * 64;
   constexpr int TK = DenseTK<T>::TK;
   const T *G = static_cast<const T *>(cx.Gp) + nd.goff;
-  LoadDenseA<T, TK> la{G, nd.ldg, c, ke, i0};
+  LoadDenseASym<T, TK> la{G, nd.ldg, c, ke, i0};  // the buffer holds the lower triangle (see the plan)
+  la.cs = cx.pl->csign;
   LoadDenseB<T, TK> lb{cx.Lp, nd.off, ld, s, ke, j0, s};
   Acc<T> acc;
   gemm_dense<T, true>(kb, ke, la, lb, smem, acc);  // complex: three real product chains

@@ -637,7 +637,7 @@ __global__ void __launch_bounds__(64) k_normalize_small(const DevPlan *__restric
 // owns its row block and writes tile b after finishing it never reads a
 // column it has already overwritten: Q may alias P.
 template <typename T>
-__global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
+__global__ void __launch_bounds__(NT, 2)
     k_normalize_gemm(const DevPlan *__restrict__ plp, const T *Src_all, T *Lp_all, const int2 *rblocks, int32_t nrb,
                      int hs) {
   const DevPlan &pl = *plp;
@@ -659,7 +659,7 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
     LoadDenseA<T, TK> la{Q + s, ld, c, s, i0};      // L_{C,K}(i, k)
     LoadDenseB<T, TK> lb{Linv, 0, s, 0, s, x0, s};  // L_KK^{-1}(k, x)
     Acc<T> acc;
-    gemm_dense<T>(x0, s, la, lb, smem, acc);
+    gemm_dense<T, true>(x0, s, la, lb, smem, acc);  // complex: three real product chains
     acc_to_lds<T>(acc, smem);
     lds_barrier();
     for (int e = threadIdx.x; e < 64 * 64; e += NT) {

@@ -85,7 +85,9 @@ struct alignas(16) Item {
 // each item's record, so an item's first dependent load is its record alone.
 struct alignas(16) NodeInfo {
   int32_t K, s, c, ldg;      // node, width, |C(K)|, leading dimension of its dense X_{C,C} buffer
-  int32_t split, kchunk, defer2, pad1;  // GEMM-1 contraction parts and their length; GEMM-2 in ITEM_P items
+  int32_t split, kchunk, defer2, glow;  // GEMM-1 contraction parts and their length; GEMM-2 in ITEM_P items;
+                                        // glow: the dense buffer holds the lower triangle and the diagonal
+                                        // 64 x 64 blocks only (its GEMM-1 reads the rest mirrored)
   int64_t off, rp, goff;     // panel offset, first row of C(K) in the row tables, dense buffer (-1: none)
   int64_t poff, yoff, pad2;  // GEMM-2 partial products, partial tiles of a split contraction
 };

@@ -545,6 +545,54 @@ template <typename T, int TK> struct LoadDenseA {
   }
 };
 
+// A(i, k) = X_{C,C}(i0 + i, k) from a dense buffer that holds only the lower
+// triangle and the full diagonal 64 x 64 blocks (X_{C,C} is symmetric, or
+// Hermitian): a stage right of the row tile's diagonal block (k0 >= i0 + 64)
+// reads the mirrored entries G[(i0 + i) * ldg + k] (conjugated in a Hermitian
+// plan) with lanes along k, so that the loads stay contiguous; every other
+// stage reads as LoadDenseA.  Slot m of a thread in such a stage is
+// kk = t % TK, i = t / TK + (NT / TK) m.
+template <typename T, int TK> struct LoadDenseASym : LoadDenseA<T, TK> {
+  using Base = LoadDenseA<T, TK>;
+  static constexpr int E = Base::E;
+  static constexpr bool kConj = true;
+  double cs = 1.0;       // -1 in a Hermitian plan
+  int i0, kkt;           // row tile start; this thread's k in a mirrored stage
+  uint32_t uoff[E];      // byte offsets of (row i0 + i, k0 + kkt) relative to G + i0 * ldg + k0 (rows clamped)
+  uint32_t urow_ok = 0;  // bit m: the row of slot m is inside the operand
+  __device__ __forceinline__ LoadDenseASym(const T *G_, int ldg_, int rows, int kend_, int i0_)
+      : Base(G_, ldg_, rows, kend_, i0_), i0(i0_) {
+    kkt = threadIdx.x % TK;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int i = threadIdx.x / TK + (NT / TK) * m;
+      const bool ok = i0 + i < rows;
+      urow_ok |= ok ? (1u << m) : 0u;
+      uoff[m] = (uint32_t)((int64_t)(ok ? i : 0) * ldg_ + kkt) * (uint32_t)sizeof(T);
+    }
+  }
+  __device__ __forceinline__ bool upper(int k0) const { return k0 >= i0 + 64; }
+  __device__ __forceinline__ int slot(int k0, int m) const {
+    const int e = threadIdx.x + NT * m;
+    return upper(k0) ? (e % TK) * PITCH + e / TK : Base::slot(k0, m);
+  }
+  __device__ __forceinline__ int64_t mask(int k0, int m) const {
+    return upper(k0) ? opaque_mask(((urow_ok >> m) & 1u) != 0 && k0 + kkt < this->kend) : Base::mask(k0, m);
+  }
+  __device__ __forceinline__ double imsign(int k0, int) const { return upper(k0) ? cs : 1.0; }
+  __device__ __forceinline__ void load(int k0, DVals<T, TK> &v) const {
+    if (upper(k0)) {
+      const int over = k0 + kkt - (this->kend - 1);  // the last stage clamps k onto kend - 1
+      const uint32_t back = (uint32_t)(over > 0 ? over : 0) * (uint32_t)sizeof(T);
+      const T *base = this->G + (int64_t)i0 * this->ldg + k0;
+#pragma unroll
+      for (int m = 0; m < E; ++m) v.v[m] = ld_off(base, uoff[m] - back);
+    } else {
+      Base::load(k0, v);
+    }
+  }
+};
+
 // B(kk, x) = P[off + (x0 + x) * ld + s + k0 + kk] for k0 + kk < kend,
 // x0 + x < xmax: a column block of a panel's bottom part, k-major.  Slot m of
 // a thread is kk = t % TK, x = t / TK + (NT / TK) m.
