@@ -155,62 +155,79 @@ __device__ void store_xtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, 
 // barrier done); acc is a 64 x 64 GEMM-1 tile in the accumulator layout,
 // which is the MFMA B-operand layout for a contraction over the tile rows
 // (register v of a 16 x 16 block holds rows 4v..4v+3 of lanes l / 16).  R
-// overwrites Ls; ends with a barrier.
+// overwrites Ls; ends with a barrier.  The 64 columns x run in parts of
+// 16 XB (all 64 for FP64, 16 for complex, whose three product chains per
+// block take more registers): R's columns of a part overwrite Ls's, which
+// only that part reads.  Complex products take three real chains (see
+// Acc3M).
 template <typename T>
 __device__ void gemm2_block(const Acc<T> &acc, double *Ls) {
-  constexpr int P = Planes<T>::P;
+  constexpr int P = Planes<T>::P, C = P == 1 ? 1 : 3;  // product chains
+  constexpr int XB = P == 1 ? 4 : 1;                   // 16-column blocks per part
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wi = w & 1, wj = w >> 1;
-  d4 pacc[P][4][2];
+#pragma unroll 1
+  for (int h = 0; h < 4 / XB; ++h) {
+    d4 pacc[C][XB][2];
 #pragma unroll
-  for (int p = 0; p < P; ++p)
+    for (int q = 0; q < C; ++q)
 #pragma unroll
-    for (int xb = 0; xb < 4; ++xb)
+      for (int xb = 0; xb < XB; ++xb)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) pacc[p][xb][bj] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int bj = 0; bj < 2; ++bj) pacc[q][xb][bj] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int k4 = 0; k4 < 4; ++k4) {
-      const int row = 32 * wi + 16 * bi + 4 * k4 + (lane >> 4);
+      for (int k4 = 0; k4 < 4; ++k4) {
+        const int row = 32 * wi + 16 * bi + 4 * k4 + (lane >> 4);
 #pragma unroll
-      for (int xb = 0; xb < 4; ++xb) {
-        double af[P];
-#pragma unroll
-        for (int p = 0; p < P; ++p) af[p] = Ls[p * 64 * PITCH + row * PITCH + 16 * xb + (lane & 15)];
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
+        for (int xb = 0; xb < XB; ++xb) {
+          const int x = 16 * (XB * h + xb) + (lane & 15);
           if constexpr (P == 1) {
-            pacc[0][xb][bj] = mfma16(af[0], acc.v[0][bi][bj][k4], pacc[0][xb][bj]);
+            const double af = Ls[row * PITCH + x];
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) pacc[0][xb][bj] = mfma16(af, acc.v[0][bi][bj][k4], pacc[0][xb][bj]);
           } else {
-            pacc[0][xb][bj] = mfma16(af[0], acc.v[0][bi][bj][k4], pacc[0][xb][bj]);
-            pacc[0][xb][bj] = mfma16(-af[1], acc.v[1][bi][bj][k4], pacc[0][xb][bj]);
-            pacc[1][xb][bj] = mfma16(af[0], acc.v[1][bi][bj][k4], pacc[1][xb][bj]);
-            pacc[1][xb][bj] = mfma16(af[1], acc.v[0][bi][bj][k4], pacc[1][xb][bj]);
+            const double a0 = Ls[row * PITCH + x], a1 = Ls[64 * PITCH + row * PITCH + x];
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+              const double b0 = acc.v[0][bi][bj][k4], b1 = acc.v[1][bi][bj][k4];
+              pacc[0][xb][bj] = mfma16(a0, b0, pacc[0][xb][bj]);
+              pacc[1][xb][bj] = mfma16(a1, b1, pacc[1][xb][bj]);
+              pacc[2][xb][bj] = mfma16(a0 + a1, b0 + b1, pacc[2][xb][bj]);
+            }
           }
         }
       }
-    }
-  lds_barrier();
-  // sum the two row halves (wi = 0, 1) in LDS
-  double *R = Ls;
-  for (int half = 0; half < 2; ++half) {
-    if (wi == half) {
-#pragma unroll
-      for (int p = 0; p < P; ++p)
-#pragma unroll
-        for (int xb = 0; xb < 4; ++xb)
-#pragma unroll
-          for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int x = 16 * xb + 4 * v + (lane >> 4);
-              const int j = 32 * wj + 16 * bj + (lane & 15);
-              double &r = R[p * 64 * PITCH + j * PITCH + x];
-              r = half == 0 ? pacc[p][xb][bj][v] : r + pacc[p][xb][bj][v];
-            }
-    }
     lds_barrier();
+    // sum the two row halves (wi = 0, 1) into R's columns of this part
+    double *R = Ls;
+    for (int part = 0; part < 2; ++part) {
+      if (wi == part) {
+#pragma unroll
+        for (int xb = 0; xb < XB; ++xb)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) {
+            d4 out[P];
+            if constexpr (P == 1) {
+              out[0] = pacc[0][xb][bj];
+            } else {
+              out[0] = pacc[0][xb][bj] - pacc[1][xb][bj];
+              out[1] = pacc[2][xb][bj] - pacc[0][xb][bj] - pacc[1][xb][bj];
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int x = 16 * (XB * h + xb) + 4 * v + (lane >> 4);
+                const int j = 32 * wj + 16 * bj + (lane & 15);
+                double &r = R[p * 64 * PITCH + j * PITCH + x];
+                r = part == 0 ? out[p][v] : r + out[p][v];
+              }
+          }
+      }
+      lds_barrier();
+    }
   }
 }
 
