@@ -404,6 +404,10 @@ selinv_status selinv_trace(selinv_ctx *h, void *trace_dev);
  *     the dense X_{C,C} buffers, 6 GEMM-2 shares), items or records
  *     per matrix, type of the first item (-1 for push tiles), etree depth}.  The list is
  *     built for every plan; the persistent schedule does not launch by it.
+ *   which = 3: the normalization chunks of selinv_normalize_run (level
+ *     schedule), in order: {first level launch, its etree depth,
+ *     normalization work entries of the chunk, 0}.  Chunk 0 is the top
+ *     depths; the traversal of a chunk's depths waits for that chunk only.
  * Errors: SELINV_EINVAL for another `which`.
  */
 selinv_status selinv_items(const selinv_ctx *h, int32_t which, const int32_t **items, int64_t *n);

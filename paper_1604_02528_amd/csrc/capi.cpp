@@ -75,7 +75,9 @@ struct HostPlan {
   std::vector<Item> y128;           // the k_ydense128 records, in launch order
   std::vector<int8_t> node_tuned;   // a tune-table entry applied to the node
   int32_t lvl_top = 0;        // level launches of the top depths (see LaunchAux)
-  int32_t norm_top[5] = {0, 0, 0, 0, 0};  // their normalization entries: small, narrow, chunks, rblocks, sq
+  std::vector<int32_t> lvl_depth_first;  // [depth + 1] first level launch of each etree depth (level schedule)
+  // normalization chunks (see LaunchAux): level launch and list boundaries
+  std::vector<int32_t> lvl_cut, norm_cut;
   std::vector<LRec> lvl_recs;  // the items of lvl_items with their nodes, in level order
   std::vector<TinyRec> tiny;  // single-wavefront nodes, in launch order
   std::vector<PushRec> push;  // push-form tiles (SELINV_SCHED_PUSH), in launch order
@@ -126,6 +128,7 @@ constexpr int64_t kSplitMax = 8;
 constexpr int64_t kSplitMinK = 320;    // default shortest contraction part
 constexpr int64_t kSplitAlign = 32;    // parts start on a contraction-stage boundary
 constexpr int64_t kDefaultDenseMaxBytes = int64_t(32) << 30;
+constexpr double kNormChunkMin = 2e10;  // smallest normalization chunk (c s^2 + s^3 units, x4 complex)
 
 double item_cost_ns(const HostPlan &H, const Item &it) {
   const double s = H.node_s[it.K], c = H.node_c[it.K];
@@ -575,7 +578,9 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     };
     std::vector<std::vector<int64_t>> bydepth(S.depth);
     for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
+    H.lvl_depth_first.assign(S.depth + 1, 0);
     for (int64_t d = 0; d < S.depth; ++d) {
+      H.lvl_depth_first[d] = (int32_t)H.lvl_ptr.size() - 1;
       for (int ph = 0; ph < kPhases; ++ph) {
         // phase 1: the GEMM-1 tiles of nodes with a dense buffer form a launch of their own
         for (int pass = 0; pass < (ph == 1 && per_level ? 2 : 1); ++pass) {
@@ -631,6 +636,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
       close(tiny_base, LVL_TINY);
       if (d == top_depth && d + 1 < S.depth) H.lvl_top = (int32_t)H.lvl_ptr.size() - 1;
     }
+    H.lvl_depth_first[S.depth] = (int32_t)H.lvl_ptr.size() - 1;
     H.tiny_dptr[S.depth] = (int32_t)H.tiny.size();
   }
   H.lvl_recs.resize(H.lvl_items.size());
@@ -733,19 +739,53 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   H.rblocks.clear();
   H.sq_tiles.clear();
   H.small_nodes.clear();
-  for (int32_t &v : H.norm_top) v = 0;
+  H.lvl_cut.clear();
+  H.norm_cut.clear();
   {
+    // Chunks for selinv_normalize_run (level schedule): the top depths, then
+    // depth ranges whose normalization (estimated as sum c s^2 + s^3 per
+    // node) starts at 1/32 of the rest, or kNormChunkMin, and doubles from
+    // chunk to chunk up to a quarter of the rest.  The traversal of a chunk's
+    // depths needs only that chunk's normalization, so the next chunks are
+    // normalized while it runs.
+    std::vector<uint8_t> cut(S.depth + 1, 0);
+    if (H.lvl_top > 0 && !push && sched == SELINV_SCHED_LEVELS) {
+      cut[top_depth + 1] = 1;
+      std::vector<double> wd(S.depth, 0.0);
+      for (int64_t K = 0; K < ns; ++K) {
+        const double s = H.node_s[K], c = H.node_c[K];
+        wd[S.sdepth[K]] += (c * s * s + s * s * s) * (double)batch * (scalar_bytes == 16 ? 4.0 : 1.0);
+      }
+      double rest = 0.0;
+      for (int64_t d = top_depth + 1; d < S.depth; ++d) rest += wd[d];
+      double target = std::max(rest / 32.0, kNormChunkMin), acc = 0.0;
+      if (rest >= 4.0 * kNormChunkMin)
+        for (int64_t d = top_depth + 1; d + 1 < S.depth; ++d) {
+          acc += wd[d];
+          if (acc >= target) {
+            cut[d + 1] = 1;
+            acc = 0.0;
+            target = std::min(2.0 * target, std::max(rest / 4.0, kNormChunkMin));
+          }
+        }
+    }
+    auto mark = [&]() {
+      H.norm_cut.push_back((int32_t)H.small_nodes.size());
+      H.norm_cut.push_back((int32_t)H.chunks_narrow.size());
+      H.norm_cut.push_back((int32_t)H.chunks.size());
+      H.norm_cut.push_back((int32_t)H.rblocks.size());
+      H.norm_cut.push_back((int32_t)H.sq_tiles.size());
+    };
+    mark();
+    H.lvl_cut.push_back(0);
     // root first: the workgroups of the large top nodes, which take longest,
     // are dispatched first (measured: C2 normalization 0.55 -> 0.45 ms)
     std::vector<std::vector<int64_t>> bydepth(S.depth);
     for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
     for (int64_t d = 0; d < S.depth; ++d) {
-      if (d == top_depth + 1 && H.lvl_top > 0) {
-        H.norm_top[0] = (int32_t)H.small_nodes.size();
-        H.norm_top[1] = (int32_t)H.chunks_narrow.size();
-        H.norm_top[2] = (int32_t)H.chunks.size();
-        H.norm_top[3] = (int32_t)H.rblocks.size();
-        H.norm_top[4] = (int32_t)H.sq_tiles.size();
+      if (cut[d]) {
+        mark();
+        H.lvl_cut.push_back(H.lvl_depth_first[d]);
       }
       for (int64_t K : bydepth[d]) {
         const int32_t s = H.node_s[K], c = H.node_c[K];
@@ -761,6 +801,8 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
           for (int32_t b = 0; b < nt; ++b) H.sq_tiles.push_back(int4{(int32_t)K, a, b, 0});
       }
     }
+    mark();
+    H.lvl_cut.push_back((int32_t)H.lvl_ptr.size() - 1);
   }
   H.apos = S.apos;
   H.adiag = S.apos_diag;
@@ -899,6 +941,7 @@ struct selinv_ctx {
   const void *panels_at = nullptr, *dtilde_at = nullptr, *x_at = nullptr;
   std::vector<Item> bseq;            // adjoint launch sequence for selinv_items (built on demand)
   std::vector<Item> lseq;            // forward level launches for selinv_items (built on demand)
+  std::vector<Item> nseq;            // normalization chunks for selinv_items (built on demand)
   const void *ctrl_at = nullptr;     // control words of the last persistent launch (for selinv_sync)
   void *devfac_work = nullptr;       // work buffer of a device factorization not yet checked by selinv_sync
   uint64_t serial = 0;               // unique per context (owner tag of the no-alloc work area)
@@ -916,12 +959,15 @@ struct selinv_ctx {
   std::vector<int64_t> panel_off_view;
 
   hipStream_t side = nullptr, side2 = nullptr;  // side streams of selinv_normalize_run, and its events
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_inv = nullptr, ev_sq = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_inv = nullptr, ev_sq = nullptr;
+  std::vector<hipEvent_t> ev_chunk;  // one per normalization chunk after the top one
   int side_device = -1;
 
   ~selinv_ctx() {
     if (pinned) (void)hipHostFree(pinned);
-    for (hipEvent_t ev : {ev_fork, ev_join, ev_inv, ev_sq})
+    for (hipEvent_t ev : {ev_fork, ev_inv, ev_sq})
+      if (ev) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : ev_chunk)
       if (ev) (void)hipEventDestroy(ev);
     if (side) (void)hipStreamDestroy(side);
     if (side2) (void)hipStreamDestroy(side2);
@@ -1070,11 +1116,9 @@ LaunchAux make_aux(const selinv_ctx *h, void *work) {
   a.blaunch = H.blaunch.data();
   a.nblaunch = (int32_t)H.blaunch.size();
   a.lvl_top = H.lvl_top;
-  a.nsmall_top = H.norm_top[0];
-  a.nchunks_narrow_top = H.norm_top[1];
-  a.nchunks_top = H.norm_top[2];
-  a.nrblocks_top = H.norm_top[3];
-  a.nsq_tiles_top = H.norm_top[4];
+  a.nnorm_chunks = (int32_t)H.lvl_cut.size() - 1;
+  a.lvl_cut = H.lvl_cut.data();
+  a.norm_cut = H.norm_cut.data();
   return a;
 }
 
@@ -1357,7 +1401,7 @@ selinv_status selinv_factor(selinv_ctx *h, const void *values, void *panels_dev,
   if (e != hipSuccess) return hip_err(h, e, "panel upload");
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
-  e = launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), panels_dev, panels_dev, dtilde_dev, st, 0,
+  e = launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), panels_dev, panels_dev, dtilde_dev, st, -1,
                        NORM_ALL);
   if (e != hipSuccess) return hip_err(h, e, "normalize launch");
   // the staging buffer is reused by the next call: wait for the copy
@@ -1379,7 +1423,7 @@ selinv_status selinv_normalize(selinv_ctx *h, const void *ldlt_dev, void *panels
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
   hipError_t e =
-      launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st, 0,
+      launch_normalize(pl, dev_plan(h, work_dev), aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st, -1,
                        NORM_ALL);
   if (e != hipSuccess) return hip_err(h, e, "normalize launch");
   note_normalized(h, panels_dev, dtilde_dev);
@@ -1470,9 +1514,10 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
   e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_err(h, e, "hipGetDevice");
   if (h->side && h->side_device != dev) return set_err(h, SELINV_ESTATE, "context used on another device");
+  const int nq = aux.nnorm_chunks;  // >= 2: the top depths, then the rest in chunks
   if (!h->side) {  // all or nothing: the context keeps them only if every one was created
     hipStream_t s1 = nullptr, s2 = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> ev((size_t)(3 + nq - 1), nullptr);
     e = hipStreamCreateWithFlags(&s1, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
     for (hipEvent_t &v : ev)
@@ -1487,9 +1532,9 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
     h->side = s1;
     h->side2 = s2;
     h->ev_fork = ev[0];
-    h->ev_join = ev[1];
-    h->ev_inv = ev[2];
-    h->ev_sq = ev[3];
+    h->ev_inv = ev[1];
+    h->ev_sq = ev[2];
+    h->ev_chunk.assign(ev.begin() + 3, ev.end());
     h->side_device = dev;
   }
   // on a failure after the fork, the side streams are drained before
@@ -1503,30 +1548,36 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
   const DevPlan *dpl = dev_plan(h, work_dev);
   const bool cx = h->is_complex();
   // fork: the deeper nodes' normalization on the first side stream, after
-  // the caller's earlier work
+  // the caller's earlier work, chunk by chunk root first, an event after each
   e = hipEventRecord(h->ev_fork, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(h->side, h->ev_fork, 0);
-  if (e == hipSuccess) e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, h->side, 2, NORM_ALL);
-  if (e == hipSuccess) e = hipEventRecord(h->ev_join, h->side);
+  for (int q = 1; q < nq && e == hipSuccess; ++q) {
+    e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, h->side, q, NORM_ALL);
+    if (e == hipSuccess) e = hipEventRecord(h->ev_chunk[q - 1], h->side);
+  }
   if (e != hipSuccess) return fail(e, "normalize (side stream)");
   // the top nodes: L_KK^{-1} on the caller's stream, then Lhat there and
   // Dt^{-1} on the second side stream at the same time (both need only
   // L_KK^{-1}; they write different parts of the panels)
-  e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, st, 1, NORM_INV);
+  e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, st, 0, NORM_INV);
   if (e == hipSuccess) e = hipEventRecord(h->ev_inv, st);
   if (e == hipSuccess) e = hipStreamWaitEvent(h->side2, h->ev_inv, 0);
-  if (e == hipSuccess) e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, h->side2, 1, NORM_SQ);
+  if (e == hipSuccess) e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, h->side2, 0, NORM_SQ);
   if (e == hipSuccess) e = hipEventRecord(h->ev_sq, h->side2);
-  if (e == hipSuccess) e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, st, 1, NORM_GEMM);
+  if (e == hipSuccess) e = launch_normalize(pl, dpl, aux, cx, ldlt_dev, panels_dev, dtilde_dev, st, 0, NORM_GEMM);
   if (e == hipSuccess) e = hipStreamWaitEvent(st, h->ev_sq, 0);
   if (e != hipSuccess) return fail(e, "normalize launch");
   note_normalized(h, panels_dev, dtilde_dev);
-  e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, 0, aux.lvl_top);
-  // join before the first depth that needs the deeper nodes
-  if (e == hipSuccess) e = hipStreamWaitEvent(st, h->ev_join, 0);
-  if (e == hipSuccess)
-    e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, aux.lvl_top,
-                   aux.nlvl);
+  // the traversal of a chunk's depths (Alg. 1 steps 3-4 of its nodes need only
+  // their own normalization and the ancestors' X) waits for that chunk alone
+  e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, aux.lvl_cut[0],
+                 aux.lvl_cut[1]);
+  for (int q = 1; q < nq && e == hipSuccess; ++q) {
+    e = hipStreamWaitEvent(st, h->ev_chunk[q - 1], 0);
+    if (e == hipSuccess)
+      e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, aux.lvl_cut[q],
+                     aux.lvl_cut[q + 1]);
+  }
   if (e != hipSuccess) return fail(e, "selinv launch");
   h->run_gen = h->gen;
   h->x_at = x_dev;
@@ -1574,7 +1625,7 @@ selinv_status selinv_normalize_run_noalloc(selinv_ctx *h, const void *ldlt_dev, 
   DevPlan pl = make_devplan(h, work);
   const DevPlan *dpl = dev_plan(h, work);
   LaunchAux aux = make_aux(h, work);
-  e = launch_normalize(pl, dpl, aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st, 0, NORM_ALL);
+  e = launch_normalize(pl, dpl, aux, h->is_complex(), ldlt_dev, panels_dev, dtilde_dev, st, -1, NORM_ALL);
   if (e != hipSuccess) return hip_err(h, e, "normalize launch (no-alloc)");
   note_normalized(h, panels_dev, dtilde_dev);
   e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, budget, h->grid, st, 0, aux.nlvl);
@@ -1706,6 +1757,46 @@ selinv_status selinv_check_plan(const selinv_ctx *hc) {
   }
   for (size_t q = 0; q < left.size(); ++q)
     if (left[q] != 0) return set_err(h, SELINV_EINVAL, "plan check: node never finished", (int64_t)(q / kPhases) % ns, (int64_t)(q / kPhases) / ns);
+  // Normalization chunks of selinv_normalize_run: the level launches and each
+  // normalization list are cut into consecutive ranges, and every level launch
+  // touches only nodes normalized in its own chunk or an earlier one.
+  const int64_t nlvl = (int64_t)H.lvl_ptr.size() - 1, nq = (int64_t)H.lvl_cut.size() - 1;
+  if (nq < 1 || H.lvl_cut.front() != 0 || H.lvl_cut.back() != nlvl || (int64_t)H.norm_cut.size() != 5 * (nq + 1))
+    return set_err(h, SELINV_EINVAL, "plan check: malformed normalization chunks", nq, nlvl);
+  const int64_t sizes[5] = {(int64_t)H.small_nodes.size(), (int64_t)H.chunks_narrow.size(), (int64_t)H.chunks.size(),
+                            (int64_t)H.rblocks.size(), (int64_t)H.sq_tiles.size()};
+  for (int j = 0; j < 5; ++j) {
+    if (H.norm_cut[j] != 0 || H.norm_cut[5 * nq + j] != sizes[j])
+      return set_err(h, SELINV_EINVAL, "plan check: normalization chunks do not cover a list", j, nq);
+    for (int64_t q = 0; q < nq; ++q)
+      if (H.norm_cut[5 * q + j] > H.norm_cut[5 * (q + 1) + j] || H.lvl_cut[q] > H.lvl_cut[q + 1])
+        return set_err(h, SELINV_EINVAL, "plan check: normalization chunks out of order", j, q);
+  }
+  std::vector<int64_t> nchunk(ns, -1);  // chunk of each node's normalization (its last entry)
+  auto note = [&](int j, int64_t idx, int64_t K) {
+    int64_t q = 0;
+    while (idx >= H.norm_cut[5 * (q + 1) + j]) ++q;
+    nchunk[K] = std::max(nchunk[K], q);
+  };
+  for (size_t i = 0; i < H.small_nodes.size(); ++i) note(0, (int64_t)i, H.small_nodes[i]);
+  for (size_t i = 0; i < H.chunks_narrow.size(); ++i) note(1, (int64_t)i, H.chunks_narrow[i].x);
+  for (size_t i = 0; i < H.chunks.size(); ++i) note(2, (int64_t)i, H.chunks[i].x);
+  for (size_t i = 0; i < H.rblocks.size(); ++i) note(3, (int64_t)i, H.rblocks[i].x);
+  for (size_t i = 0; i < H.sq_tiles.size(); ++i) note(4, (int64_t)i, H.sq_tiles[i].x);
+  for (int64_t q = 0; q < nq; ++q)
+    for (int64_t lv = H.lvl_cut[q]; lv < H.lvl_cut[q + 1]; ++lv)
+      for (int32_t r = H.lvl_ptr[lv]; r < H.lvl_ptr[lv + 1]; ++r) {
+        const int32_t kind = H.lvl_kind[lv];
+        int64_t K;
+        if (kind == LVL_PUSH)
+          K = H.push[H.lvl_items[r]].I;
+        else if (kind == LVL_Y128)
+          K = H.y128[H.lvl_items[r]].K;
+        else
+          K = H.items[H.lvl_items[r]].K;
+        if (nchunk[K] > q)
+          return set_err(h, SELINV_EINVAL, "plan check: a level launch runs before its node is normalized", K, q);
+      }
   return SELINV_OK;
 }
 
@@ -1744,8 +1835,28 @@ selinv_status selinv_items(const selinv_ctx *hc, int32_t which, const int32_t **
     *n = (int64_t)h->lseq.size();
     return SELINV_OK;
   }
+  if (which == 3) {
+    // the normalization chunks of selinv_normalize_run: {first level launch,
+    // etree depth of that launch, normalization work-list entries, 0}
+    if (h->nseq.empty()) {
+      const HostPlan &H = h->H;
+      const int64_t nq = (int64_t)H.lvl_cut.size() - 1;
+      for (int64_t q = 0; q < nq; ++q) {
+        int32_t depth = 0;
+        while (depth + 1 < (int32_t)H.lvl_depth_first.size() && H.lvl_depth_first[depth + 1] <= H.lvl_cut[q]) ++depth;
+        int32_t entries = 0;
+        for (int j = 0; j < 5; ++j) entries += H.norm_cut[5 * (q + 1) + j] - H.norm_cut[5 * q + j];
+        h->nseq.push_back(Item{H.lvl_cut[q], depth, entries, 0});
+      }
+    }
+    *items = reinterpret_cast<const int32_t *>(h->nseq.data());
+    *n = (int64_t)h->nseq.size();
+    return SELINV_OK;
+  }
   if (which != 1)
-    return set_err(h, SELINV_EINVAL, "selinv_items: which must be 0 (forward), 1 (adjoint) or 2 (level launches)");
+    return set_err(h, SELINV_EINVAL,
+                   "selinv_items: which must be 0 (forward), 1 (adjoint), 2 (level launches) or 3 (normalization "
+                   "chunks)");
   // the adjoint's launches in order, a small-node launch expanded into one
   // row per node
   if (h->bseq.empty()) {

@@ -825,43 +825,47 @@ __global__ void k_scatter(const DevPlan *__restrict__ plp, const T *vals, T *P) 
 // ---------------------------------------------------------------------------
 // Host-side launchers (called from the C ABI translation unit)
 // ---------------------------------------------------------------------------
-// part 0: every node; 1: the nodes of the top depths (the leading entries of
-// each list); 2: the others.  steps: a mask of NORM_INV (the small nodes'
-// whole normalization and L_KK^{-1}), NORM_GEMM (Lhat) and NORM_SQ (Dt^{-1},
-// and Dt when dt is given); NORM_GEMM and NORM_SQ need NORM_INV done.
+// part < 0: every node; q >= 0: normalization chunk q (see LaunchAux).
+// steps: a mask of NORM_INV (the small nodes' whole normalization and
+// L_KK^{-1}), NORM_GEMM (Lhat) and NORM_SQ (Dt^{-1}, and Dt when dt is
+// given); NORM_GEMM and NORM_SQ need NORM_INV done.
 template <typename T>
 static hipError_t normalize_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const void *src,
                                  void *panels, void *dt, hipStream_t st, int part, int steps) {
   const T *Q = reinterpret_cast<const T *>(src);
   T *Lp = reinterpret_cast<T *>(panels);
-  // [b, b + n) of a list with nall entries, ntop of them in the top part
-  auto range = [&](int32_t nall, int32_t ntop, int32_t &b) {
-    b = part == 2 ? ntop : 0;
-    return part == 0 ? nall : part == 1 ? ntop : nall - ntop;
+  // [b, b + n) of list j, which has nall entries
+  auto range = [&](int j, int32_t nall, int32_t &b) {
+    if (part < 0) {
+      b = 0;
+      return nall;
+    }
+    b = aux.norm_cut[5 * part + j];
+    return aux.norm_cut[5 * (part + 1) + j] - b;
   };
   int32_t b;
   // LU plans (no single-wavefront nodes) normalize both panel sets
   const int nsets = pl.half > 0 ? 2 : 1;
-  const int32_t nsm = (steps & NORM_INV) ? range(aux.nsmall, aux.nsmall_top, b) : 0;
+  const int32_t nsm = (steps & NORM_INV) ? range(0, aux.nsmall, b) : 0;
   if (nsm > 0)
     hipLaunchKernelGGL(k_normalize_small<T>, dim3((unsigned)(nsm * pl.batch)), dim3(64), 0, st, dpl, Q, Lp,
                        reinterpret_cast<T *>(dt), aux.small_nodes + b, nsm);
-  const int32_t nna = (steps & NORM_INV) ? range(aux.nchunks_narrow, aux.nchunks_narrow_top, b) : 0;
+  const int32_t nna = (steps & NORM_INV) ? range(1, aux.nchunks_narrow, b) : 0;
   if (nna > 0)
     for (int hs = 0; hs < nsets; ++hs)
       hipLaunchKernelGGL((k_normalize_inv<T, 64>), dim3((unsigned)(nna * pl.batch)), dim3(NT), 0, st, dpl, Q,
                          aux.chunks_narrow + b, nna, hs);
-  const int32_t nch = (steps & NORM_INV) ? range(aux.nchunks, aux.nchunks_top, b) : 0;
+  const int32_t nch = (steps & NORM_INV) ? range(2, aux.nchunks, b) : 0;
   if (nch > 0)
     for (int hs = 0; hs < nsets; ++hs)
       hipLaunchKernelGGL((k_normalize_inv<T, 256>), dim3((unsigned)(nch * pl.batch)), dim3(NT), 0, st, dpl, Q,
                          aux.chunks + b, nch, hs);
-  const int32_t nrb = (steps & NORM_GEMM) ? range(aux.nrblocks, aux.nrblocks_top, b) : 0;
+  const int32_t nrb = (steps & NORM_GEMM) ? range(3, aux.nrblocks, b) : 0;
   if (nrb > 0)
     for (int hs = 0; hs < nsets; ++hs)
       hipLaunchKernelGGL(k_normalize_gemm<T>, dim3((unsigned)(nrb * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
                          aux.rblocks + b, nrb, hs);
-  const int32_t nsq = (steps & NORM_SQ) ? range(aux.nsq_tiles, aux.nsq_tiles_top, b) : 0;
+  const int32_t nsq = (steps & NORM_SQ) ? range(4, aux.nsq_tiles, b) : 0;
   if (nsq > 0) {
     if (dt)
       hipLaunchKernelGGL(k_normalize_sq<T>, dim3((unsigned)(nsq * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,

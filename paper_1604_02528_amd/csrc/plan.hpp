@@ -213,10 +213,14 @@ struct LaunchAux {
                               // bitems [first, first + count), 1 / 2 = R1 / R3 of small-node records
   int32_t nblaunch;
   // Top of the tree: the level launches of the depths whose tiles fill at
-  // most a quarter of the GPU (0: none), and the leading entries of each
-  // normalization list that belong to those depths (the lists run root first).
+  // most a quarter of the GPU (0: none).
   int32_t lvl_top;
-  int32_t nsmall_top, nchunks_narrow_top, nchunks_top, nrblocks_top, nsq_tiles_top;
+  // Normalization chunks (the lists run root first): chunk q covers the level
+  // launches [lvl_cut[q], lvl_cut[q + 1]) and, of list j (small, narrow,
+  // chunks, rblocks, sq), the entries [norm_cut[5 q + j], norm_cut[5 (q + 1) + j]);
+  // chunk 0 is the top depths.  Host arrays.
+  int32_t nnorm_chunks;
+  const int32_t *lvl_cut, *norm_cut;
 };
 
 // Launches of the device factorization, one entry per etree depth (deepest

@@ -191,7 +191,7 @@ def test_adjoint_items_which_is_checked():
 
     S = _ctx(workload("C1"))
     with pytest.raises(capi.SelinvError) as ei:
-        capi.selinv_items(S.h, 3)
+        capi.selinv_items(S.h, 4)
     assert ei.value.status == 1
 
 
@@ -458,3 +458,28 @@ def test_tune_key_names_this_build():
 
     k = capi.selinv_tune_key()
     assert k.startswith("arch=gfx950 rocm=")
+
+
+@pytest.mark.parametrize("name,scale,chunks", [("C2", None, 2), ("C3", None, 3), ("C5", 16, 2)])
+def test_normalization_chunks(name, scale, chunks):
+    """selinv_items(which = 3): selinv_normalize_run's normalization chunks
+    start at the first level launch, then at increasing level launches and
+    etree depths, and together hold every normalization work entry; the
+    pipelined plan of the full C3 (32 shifts) has more than the two chunks
+    (top depths, rest) of a small plan."""
+    from paper_1604_02528_amd import SelInv, capi
+
+    w = workload(name, scale)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=w.dtype, batch=w.batch, cap=w.cap, relax=0.05,
+               device="cpu", adjoint=False)
+    N = capi.selinv_items(S.h, 3)
+    L = capi.selinv_items(S.h, 2)
+    assert len(N) >= chunks
+    assert N[0, 0] == 0 and N[0, 1] == 0
+    assert np.all(np.diff(N[:, 0]) > 0) and np.all(np.diff(N[:, 1]) > 0)
+    assert np.all(N[:, 0] < len(L))
+    assert np.all(L[N[:, 0], 3] == N[:, 1])  # a chunk starts at the first launch of its depth
+    assert np.all(N[:, 2] >= 0)
+    capi.selinv_check_plan(S.h)
+    with pytest.raises(capi.SelinvError):
+        capi.selinv_items(S.h, 4)

@@ -74,10 +74,14 @@ def test_host_factor_matches_oracle(name, scale, batch, relax):
 
 @pytest.mark.parametrize("name,scale,batch,relax", [("C1", None, None, 0.0), ("C2", 12, None, 0.0),
                                                      ("C2", None, None, 0.05), ("C3", 8, 3, 0.05),
-                                                     ("C5", 6, 2, 0.0)])
+                                                     ("C5", 6, 2, 0.0), ("C3", None, None, 0.05),
+                                                     ("H3", None, None, 0.05)])
 def test_scheduler_plan_replay(name, scale, batch, relax):
     """Host replay of the persistent scheduler's protocol: every item becomes
-    ready exactly once, after all of its dependencies, within queue capacity."""
+    ready exactly once, after all of its dependencies, within queue capacity;
+    and the normalization chunks of selinv_normalize_run cover every list and
+    level launch in order, each launch after its nodes' chunk (the full C3 and
+    H3 plans have several chunks)."""
     from paper_1604_02528_amd import capi
 
     w = workload(name, scale, batch)
