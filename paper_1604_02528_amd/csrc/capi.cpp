@@ -308,12 +308,13 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   // buffer, a split contraction, a single-item or a single-wavefront path
   const bool push = sched == SELINV_SCHED_PUSH;
   const bool per_level = sched != SELINV_SCHED_PERSISTENT;
-  // The LU form of Alg. 1 (Section 2.1) runs the level schedule with the gathered
-  // GEMM-1 tiles only: no dense buffer, split contraction, R phase,
-  // single-item or single-wavefront node and no single-wavefront
-  // normalization.
+  // The LU form of Alg. 1 (Section 2.1) runs the level schedule with
+  // gathered or dense-buffer GEMM-1 tiles (the buffer holds all of
+  // X_{C,C}, its upper part from the X^T panel set): no split contraction,
+  // R phase, tune table, single-item or single-wavefront node and no
+  // single-wavefront normalization.
+  if (push) dense_min_c = -1;
   if (push || lu) {
-    dense_min_c = -1;
     split_min_k = -1;
     tt = nullptr;
   }
@@ -659,7 +660,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     n.defer2 = H.node_defer[K];
     // the dense buffer of a node whose GEMM-1 runs in k_ydense holds the
     // lower triangle only (k_ydense reads the rest mirrored)
-    n.glow = H.node_ykern[K] && !H.node_y128[K];
+    n.glow = H.node_ykern[K] && !H.node_y128[K] && !lu;
     n.off = H.node_off[K];
     n.rp = H.node_rowptr[K];
     n.goff = H.node_goff[K];

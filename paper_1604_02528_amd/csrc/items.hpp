@@ -73,10 +73,13 @@ __device__ __forceinline__ NodeInfo node_info(const DevPlan &pl, int K) {
 // major, leading dimension ldg): element (i, k), i >= k, is the lower-part
 // entry Src[kcol[k] + posarr[kpos[k] + i]] of the ancestor owning column k
 // (Src: the X panels, or any array in the same panel layout); it is written
-// to G(i, k) and G(k, i) (conjugated in a Hermitian plan).  Lanes run along i (one column k per
-// wave and step) for the gather and the G(i, k) stores; the mirror stores go
-// through an LDS transpose so that they are contiguous too.
-template <typename T>
+// to G(i, k) and G(k, i) (conjugated in a Hermitian plan; in an LU plan G(k, i)
+// is the entry at the same position of the second panel set, X^T).  Lanes run
+// along i (one column k per wave and step) for the gather and the G(i, k)
+// stores; the mirror stores go through an LDS transpose so that they are
+// contiguous too.
+// MAYBE_LU = false compiles the LU branch out (a kernel that never runs an LU plan).
+template <typename T, bool MAYBE_LU = true>
 __device__ void do_gtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, double *smem, int64_t *rt, const T *Src) {
   const DevPlan &pl = *cx.pl;
   const int c = uniform(nd.c);
@@ -109,18 +112,36 @@ __device__ void do_gtile(const Ctx<T> &cx, const NodeInfo &nd, int a, int b, dou
     const int kl = w + 4 * q, k = k0 + kl;
     v[q] = Mem<false>::ld(Src + ((rt[kl] + (int64_t)pos[q]) & opaque_mask(i < c && k < c && i >= k)));
   }
+  const bool lu = MAYBE_LU && uniform(pl.half > 0 ? 1 : 0) != 0;
+  if (lu) {  // the mirror values: the same positions of the X^T set
+    T u[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int kl = w + 4 * q, k = k0 + kl;
-    const bool ok = i < c && k < c && i >= k;
-    const T x = masked(v[q], opaque_mask(ok));
-    lds_put<T>(smem, lane, kl, x);  // tile[i][k] at smem[k * PITCH + i]
-    if (ok) Mem<false>::st(G + (int64_t)k * ldg + i, x);
+    for (int q = 0; q < Q; ++q) {
+      const int kl = w + 4 * q, k = k0 + kl;
+      u[q] = Mem<false>::ld(Src + pl.half + ((rt[kl] + (int64_t)pos[q]) & opaque_mask(i < c && k < c && i >= k)));
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int kl = w + 4 * q, k = k0 + kl;
+      const bool ok = i < c && k < c && i >= k;
+      lds_put<T>(smem, lane, kl, masked(u[q], opaque_mask(ok)));
+      if (ok) Mem<false>::st(G + (int64_t)k * ldg + i, masked(v[q], opaque_mask(ok)));
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int kl = w + 4 * q, k = k0 + kl;
+      const bool ok = i < c && k < c && i >= k;
+      const T x = masked(v[q], opaque_mask(ok));
+      lds_put<T>(smem, lane, kl, x);  // tile[i][k] at smem[k * PITCH + i]
+      if (ok) Mem<false>::st(G + (int64_t)k * ldg + i, x);
+    }
   }
   lds_barrier();
-  // mirror: G(k, i) = tile[i][k] (its conjugate if Hermitian), lanes along k;
-  // a lower-only buffer keeps the mirrors of diagonal blocks alone
-  const double cs = pl.csign;
+  // mirror: G(k, i) = tile[i][k] (its conjugate if Hermitian; the X^T entry
+  // in an LU plan), lanes along k; a lower-only buffer keeps the mirrors of
+  // diagonal blocks alone
+  const double cs = lu ? 1.0 : pl.csign;
   if (uniform(nd.glow != 0 && a != b ? 0 : 1)) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -457,24 +478,31 @@ __device__ void do_ptile(const Ctx<T> &cx, const NodeInfo &nd, int a, int br, do
 // item kernel, two workgroups per CU).  The tile goes to X (nodes whose
 // GEMM-2 runs in ITEM_P items) or to the partial tiles of a split
 // contraction (summed by ITEM_R items).
+// LU plans: up (an ITEM_YU tile) takes X_{K,C}^T = -(X_{C,C})^T Uhat^T from
+// the transposed full buffer and the second panel sets.
 template <typename T>
-__device__ __forceinline__ void do_ytile_dense(const Ctx<T> &cx, const NodeInfo &nd, int a, int bp, double *smem) {
+__device__ __forceinline__ void do_ytile_dense(const Ctx<T> &cx, const NodeInfo &nd, int a, int bp, bool up,
+                                               double *smem) {
   const int s = uniform(nd.s), c = uniform(nd.c), ld = s + c;
   const int b = bp & 0xffff, part = bp >> 16;
   const int kchunk = uniform(nd.kchunk);
   const int kb = part * kchunk, ke = min(c, kb + kchunk);
   const int i0 = a * 64, j0 = b * 64;
   constexpr int TK = DenseTK<T>::TK;
+  const int64_t hs = up ? cx.pl->half : 0;
   const T *G = static_cast<const T *>(cx.Gp) + nd.goff;
-  LoadDenseASym<T, TK> la{G, nd.ldg, c, ke, i0};  // the buffer holds the lower triangle (see the plan)
+  // a lower-only buffer (see the plan) mirrors the stages right of the
+  // diagonal block; a full one (LU) reads as is, or transposed for up
+  const int kmir = nd.glow ? i0 + 64 : up ? 0 : 1 << 30;
+  LoadDenseASym<T, TK> la{G, nd.ldg, c, ke, i0, uniform(kmir)};
   la.cs = cx.pl->csign;
-  LoadDenseB<T, TK> lb{cx.Lp, nd.off, ld, s, ke, j0, s};
+  LoadDenseB<T, TK> lb{cx.Lp + hs, nd.off, ld, s, ke, j0, s};
   Acc<T> acc;
   gemm_dense<T, true>(kb, ke, la, lb, smem, acc);  // complex: three real product chains
   acc_to_lds<T>(acc, smem);
   lds_barrier();
-  if (nd.yoff < 0) {  // Y = -acc into X_{C,K}
-    T *X = cx.Xp + nd.off + s;
+  if (nd.yoff < 0) {  // Y = -acc into X_{C,K} (LU up: the second set)
+    T *X = cx.Xp + hs + nd.off + s;
     for (int e = threadIdx.x; e < 64 * 64; e += NT) {
       const int i = e & 63, j = e >> 6;
       if (i0 + i < c && j0 + j < s) gstore(X + (int64_t)(j0 + j) * ld + i0 + i, SOps<T>::scale(-1.0, lds_get<T>(smem, i, j)));

@@ -65,8 +65,8 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1) k_items_list(co
 // step 3): three dependent rounds of loads per 64 x 64 block and no MFMA,
 // so the kernel takes one tile of LDS and few registers, and twice as many
 // workgroups share a CU as in k_items_list (more loads in flight).
-template <typename T>
-__global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 4 : 2) k_gather_list(const DevPlan *__restrict__ plp, T *Xp,
+template <typename T, bool LU>
+__global__ void __launch_bounds__(NT, Planes<T>::P == 1 && !LU ? 4 : 2) k_gather_list(const DevPlan *__restrict__ plp, T *Xp,
                                                                               const LRec *recs, const int32_t *list,
                                                                               int32_t count, int32_t list_pos) {
   const DevPlan &pl = *plp;
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 4 : 2) k_gather_list(c
   Ctx<T> cx{&pl, nullptr, Xp + l * pl.panel_elems, nullptr, static_cast<T *>(pl.gbuf) + l * pl.g_elems, nullptr};
   const LRec rec = recs[q];
   const Item it = uniform(rec.it);
-  do_gtile<T>(cx, uniform(rec.nd), it.a, it.b, smem, rt, cx.Xp);
+  do_gtile<T, LU>(cx, uniform(rec.nd), it.a, it.b, smem, rt, cx.Xp);
   if (pl.trace) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(NT, 2) k_ydense(const DevPlan *__restrict__ pl
             static_cast<T *>(pl.gbuf) + l * pl.g_elems, static_cast<T *>(pl.ypart) + l * pl.y_elems};
   const LRec rec = recs[q];
   const Item it = uniform(rec.it);
-  do_ytile_dense<T>(cx, uniform(rec.nd), it.a, it.b, smem);
+  do_ytile_dense<T>(cx, uniform(rec.nd), it.a, it.b, it.type == ITEM_YU, smem);
   if (pl.trace) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -938,8 +938,9 @@ static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
         hipLaunchKernelGGL(k_ydense<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp,
                            aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
       else if (aux.lvl_kind[q] == LVL_GATHER)
-        hipLaunchKernelGGL(k_gather_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Xp,
-                           aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
+        hipLaunchKernelGGL((pl.half > 0 ? k_gather_list<T, true> : k_gather_list<T, false>),
+                           dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Xp, aux.lvl_recs + b,
+                           aux.lvl_items + b, e - b, b);
       else if (aux.lvl_kind[q] == LVL_GEMM2)
         hipLaunchKernelGGL(k_gemm2_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,
                            aux.lvl_recs + b, aux.lvl_items + b, e - b, b);

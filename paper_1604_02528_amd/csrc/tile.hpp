@@ -545,23 +545,25 @@ template <typename T, int TK> struct LoadDenseA {
   }
 };
 
-// A(i, k) = X_{C,C}(i0 + i, k) from a dense buffer that holds only the lower
-// triangle and the full diagonal 64 x 64 blocks (X_{C,C} is symmetric, or
-// Hermitian): a stage right of the row tile's diagonal block (k0 >= i0 + 64)
-// reads the mirrored entries G[(i0 + i) * ldg + k] (conjugated in a Hermitian
-// plan) with lanes along k, so that the loads stay contiguous; every other
-// stage reads as LoadDenseA.  Slot m of a thread in such a stage is
+// A(i, k) = G(i0 + i, k) of a dense column-major buffer (leading dimension
+// ldg), where the stages k0 >= kmir read the mirrored entries
+// G[(i0 + i) * ldg + k] (conjugated in a Hermitian plan) with lanes along k,
+// so that the loads stay contiguous, and the other stages read as
+// LoadDenseA.  kmir = i0 + 64: X_{C,C} from a buffer that holds only its
+// lower triangle and the full diagonal 64 x 64 blocks (X_{C,C} symmetric or
+// Hermitian); kmir = 0: the transpose of the whole buffer; kmir past the
+// contraction: the buffer itself.  Slot m of a thread in a mirrored stage is
 // kk = t % TK, i = t / TK + (NT / TK) m.
 template <typename T, int TK> struct LoadDenseASym : LoadDenseA<T, TK> {
   using Base = LoadDenseA<T, TK>;
   static constexpr int E = Base::E;
   static constexpr bool kConj = true;
   double cs = 1.0;       // -1 in a Hermitian plan
-  int i0, kkt;           // row tile start; this thread's k in a mirrored stage
+  int i0, kmir, kkt;     // row tile start; first mirrored stage; this thread's k in a mirrored stage
   uint32_t uoff[E];      // byte offsets of (row i0 + i, k0 + kkt) relative to G + i0 * ldg + k0 (rows clamped)
   uint32_t urow_ok = 0;  // bit m: the row of slot m is inside the operand
-  __device__ __forceinline__ LoadDenseASym(const T *G_, int ldg_, int rows, int kend_, int i0_)
-      : Base(G_, ldg_, rows, kend_, i0_), i0(i0_) {
+  __device__ __forceinline__ LoadDenseASym(const T *G_, int ldg_, int rows, int kend_, int i0_, int kmir_)
+      : Base(G_, ldg_, rows, kend_, i0_), i0(i0_), kmir(kmir_) {
     kkt = threadIdx.x % TK;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -571,7 +573,7 @@ template <typename T, int TK> struct LoadDenseASym : LoadDenseA<T, TK> {
       uoff[m] = (uint32_t)((int64_t)(ok ? i : 0) * ldg_ + kkt) * (uint32_t)sizeof(T);
     }
   }
-  __device__ __forceinline__ bool upper(int k0) const { return k0 >= i0 + 64; }
+  __device__ __forceinline__ bool upper(int k0) const { return k0 >= kmir; }
   __device__ __forceinline__ int slot(int k0, int m) const {
     const int e = threadIdx.x + NT * m;
     return upper(k0) ? (e % TK) * PITCH + e / TK : Base::slot(k0, m);

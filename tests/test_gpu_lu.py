@@ -28,14 +28,16 @@ def _ctx(w, relax, **kw):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("dense", [0, 65, -1], ids=["dense_default", "dense_all", "gather_only"])
 @pytest.mark.parametrize("name,scale,batch,relax", CASES)
-def test_lu_matches_oracle(name, scale, batch, relax):
-    """Both panel sets: X_{C,K} from the gathered X_{C,C} (upper part from the
-    X^T set), X_{K,C}^T from (X_{C,C})^T, X_KK = Dt^{-1} - Uhat X_{C,K} with
-    no symmetrization, and its transpose."""
+def test_lu_matches_oracle(name, scale, batch, relax, dense):
+    """Both panel sets: X_{C,K} from X_{C,C} (upper part from the X^T set),
+    gathered on the fly or from the dense buffer, X_{K,C}^T from (X_{C,C})^T
+    (the buffer read transposed), X_KK = Dt^{-1} - Uhat X_{C,K} with no
+    symmetrization, and its transpose."""
     w = workload(name, scale, batch)
-    print(f"lu case {name} scale={scale} batch={batch} relax={relax}", flush=True)
-    S = _ctx(w, relax)
+    print(f"lu case {name} scale={scale} batch={batch} relax={relax} dense={dense}", flush=True)
+    S = _ctx(w, relax, dense_min_c=dense)
     S.factor(w.values)
     S.run()
     S.sync()
@@ -63,7 +65,7 @@ def test_lu_random_patterns_vs_dense_inverse(seed):
     cap = int(rng.integers(4, 80))
     print(f"lu random case seed={seed} n={n} cap={cap}", flush=True)
     sym = symbolic.analyze(n, colptr, rowind, perm, cap=cap)
-    S = SelInv(n, colptr, rowind, perm, dtype="lu64", batch=1, cap=cap, relax=0.0)
+    S = SelInv(n, colptr, rowind, perm, dtype="lu64", batch=1, cap=cap, relax=0.0, dense_min_c=65 if seed % 2 else 0)
     S.factor(np.concatenate([lo, up])[None, :])
     S.run()
     xa = S.extract()
