@@ -472,17 +472,20 @@ __global__ void __launch_bounds__(NT, 1)
 // The L strip of the next row block is loaded while the current one is used.
 // MAXS bounds s for the nodes of the launch (256, or 64 for a launch of narrow
 // nodes with a quarter of the LDS, so that more workgroups share a CU).
-// hs = 1 (LU plans): the second panel set, U^T, whose unit lower diagonal
-// block gives U_KK^{-T} (into the second half of the linv buffer); D_K^{-1}
-// is written by the hs = 0 launch only.
+// LU plans launch nsets = 2 grids' worth of workgroups: the second half
+// works on the second panel set, U^T, whose unit lower diagonal block gives
+// U_KK^{-T} (into the second half of the linv buffer); D_K^{-1} is written by
+// the first half only.
 template <typename T, int MAXS>
 __global__ void __launch_bounds__(NT) k_normalize_inv(const DevPlan *__restrict__ plp, const T *Src_all, const int2 *chunks,
-                                                      int32_t nchunks, int hs) {
+                                                      int32_t nchunks, int nsets) {
   constexpr int P = Planes<T>::P, XP = 17, LPI = MAXS + 1, U = MAXS / 16;
   const DevPlan &pl = *plp;
   __shared__ double xs[P][MAXS * XP];  // X(j0 + r, j0 + q) at [r * XP + q]
   __shared__ double lsd[P][16 * LPI];  // L(I0 + i, j0 + k) at [i * LPI + k]
-  const int64_t g = blockIdx.x;
+  const int64_t per = (int64_t)nchunks * pl.batch;  // workgroups per panel set
+  const int hs = nsets > 1 ? (int)(blockIdx.x / per) : 0;
+  const int64_t g = blockIdx.x - hs * per;
   const int64_t l = g / nchunks;
   const int2 ck = chunks[g - l * nchunks];
   const int K = uniform(ck.x), j0 = uniform(ck.y) * 16;
@@ -639,14 +642,16 @@ __global__ void __launch_bounds__(64) k_normalize_small(const DevPlan *__restric
 template <typename T>
 __global__ void __launch_bounds__(NT, 2)
     k_normalize_gemm(const DevPlan *__restrict__ plp, const T *Src_all, T *Lp_all, const int2 *rblocks, int32_t nrb,
-                     int hs) {
+                     int nsets) {
   const DevPlan &pl = *plp;
   // two GEMM stages or one 64 x 64 result tile, whichever is larger (complex:
   // half of smem_doubles, so that two workgroups share a CU)
   constexpr int kStages = 2 * dense_stage_doubles<T, DenseTK<T>::TK>();
   __shared__ double smem[kStages > tile_doubles<T>() ? kStages : tile_doubles<T>()];
   constexpr int TK = DenseTK<T>::TK;
-  const int64_t g = blockIdx.x;
+  const int64_t per = (int64_t)nrb * pl.batch;  // workgroups per panel set (LU: two sets)
+  const int hs = nsets > 1 ? (int)(blockIdx.x / per) : 0;
+  const int64_t g = blockIdx.x - hs * per;
   const int64_t l = g / nrb;
   const int2 rb = rblocks[g - l * nrb];
   const int K = uniform(rb.x), i0 = uniform(rb.y) * 64;
@@ -852,19 +857,16 @@ static hipError_t normalize_impl(const DevPlan &pl, const DevPlan *dpl, const La
                        reinterpret_cast<T *>(dt), aux.small_nodes + b, nsm);
   const int32_t nna = (steps & NORM_INV) ? range(1, aux.nchunks_narrow, b) : 0;
   if (nna > 0)
-    for (int hs = 0; hs < nsets; ++hs)
-      hipLaunchKernelGGL((k_normalize_inv<T, 64>), dim3((unsigned)(nna * pl.batch)), dim3(NT), 0, st, dpl, Q,
-                         aux.chunks_narrow + b, nna, hs);
+    hipLaunchKernelGGL((k_normalize_inv<T, 64>), dim3((unsigned)(nna * pl.batch * nsets)), dim3(NT), 0, st, dpl, Q,
+                       aux.chunks_narrow + b, nna, nsets);
   const int32_t nch = (steps & NORM_INV) ? range(2, aux.nchunks, b) : 0;
   if (nch > 0)
-    for (int hs = 0; hs < nsets; ++hs)
-      hipLaunchKernelGGL((k_normalize_inv<T, 256>), dim3((unsigned)(nch * pl.batch)), dim3(NT), 0, st, dpl, Q,
-                         aux.chunks + b, nch, hs);
+    hipLaunchKernelGGL((k_normalize_inv<T, 256>), dim3((unsigned)(nch * pl.batch * nsets)), dim3(NT), 0, st, dpl, Q,
+                       aux.chunks + b, nch, nsets);
   const int32_t nrb = (steps & NORM_GEMM) ? range(3, aux.nrblocks, b) : 0;
   if (nrb > 0)
-    for (int hs = 0; hs < nsets; ++hs)
-      hipLaunchKernelGGL(k_normalize_gemm<T>, dim3((unsigned)(nrb * pl.batch)), dim3(NT), 0, st, dpl, Q, Lp,
-                         aux.rblocks + b, nrb, hs);
+    hipLaunchKernelGGL(k_normalize_gemm<T>, dim3((unsigned)(nrb * pl.batch * nsets)), dim3(NT), 0, st, dpl, Q, Lp,
+                       aux.rblocks + b, nrb, nsets);
   const int32_t nsq = (steps & NORM_SQ) ? range(4, aux.nsq_tiles, b) : 0;
   if (nsq > 0) {
     if (dt)
@@ -883,17 +885,17 @@ hipError_t launch_linv(const DevPlan &pl, const DevPlan *dpl, bool cplx_, const 
   if (cplx_) {
     if (narrow)
       hipLaunchKernelGGL((k_normalize_inv<cplx, 64>), grid, dim3(NT), 0, st, dpl, reinterpret_cast<const cplx *>(src),
-                         chunks, n, 0);
+                         chunks, n, 1);
     else
       hipLaunchKernelGGL((k_normalize_inv<cplx, 256>), grid, dim3(NT), 0, st, dpl, reinterpret_cast<const cplx *>(src),
-                         chunks, n, 0);
+                         chunks, n, 1);
   } else {
     if (narrow)
       hipLaunchKernelGGL((k_normalize_inv<double, 64>), grid, dim3(NT), 0, st, dpl,
-                         reinterpret_cast<const double *>(src), chunks, n, 0);
+                         reinterpret_cast<const double *>(src), chunks, n, 1);
     else
       hipLaunchKernelGGL((k_normalize_inv<double, 256>), grid, dim3(NT), 0, st, dpl,
-                         reinterpret_cast<const double *>(src), chunks, n, 0);
+                         reinterpret_cast<const double *>(src), chunks, n, 1);
   }
   return hipGetLastError();
 }
