@@ -66,7 +66,7 @@ typedef enum {
   SELINV_C128 = 1, /* complex128, complex-symmetric */
   SELINV_H128 = 2, /* complex128, Hermitian (Section 2.3: conjugate transposes); no adjoint */
   SELINV_LU64 = 3  /* float64, unsymmetric values on a symmetric pattern (Alg. 1 in its LU form,
-                      Section 2.1); level schedule only, gathered X_{C,C} (no dense buffers, split
+                      Section 2.1); level schedule only (gathered or dense X_{C,C}; no split
                       contractions or tune table), host factorization only; no adjoint, no Dt
                       output, no selinv_scatter */
 } selinv_dtype;
