@@ -1,7 +1,8 @@
-"""selinv_normalize_run (normalization overlapped with the traversal of the
-top etree depths on a second stream) against selinv_normalize followed by
-selinv_run: the same kernels on the same inputs, so the normalized panels, the
-D-tilde output and X must agree bit for bit; and X against the oracle."""
+"""selinv_normalize_run (normalization in depth-range chunks on a second
+stream, each chunk's traversal waiting for that chunk) against
+selinv_normalize followed by selinv_run: the same kernels on the same inputs,
+so the normalized panels, the D-tilde output and X must agree bit for bit; and
+X against the oracle."""
 
 import numpy as np
 import pytest
@@ -10,18 +11,24 @@ import torch
 from tests._ref import maxrel, oracle_x, workload
 
 CASES = [("C2", None, "levels"), ("C2", 12, "levels"), ("C3", 8, "levels"), ("C4", None, "levels"),
-         ("C2", 12, "persistent")]
+         ("C2", 12, "persistent"), ("C3", None, "levels")]
 
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("name,scale,sched", CASES)
 def test_normalize_run_matches_separate_calls(name, scale, sched):
+    """The full C3 (32 shifts) plan has five normalization chunks; the oracle
+    check runs on the smaller cases (the full C3 is checked against the oracle
+    in test_gpu_edge_full.py)."""
     from paper_1604_02528_amd import SelInv, capi
 
     w = workload(name, scale)
     print(f"normalize_run case {name} scale={scale} sched={sched} batch={w.batch}", flush=True)
     dt = "c128" if w.is_complex else "f64"
     S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=dt, batch=w.batch, cap=w.cap, relax=0.05, sched=sched)
+    full = name == "C3" and scale is None
+    if full:
+        assert len(capi.selinv_items(S.h, 3)) >= 3
     ldlt = torch.from_numpy(S.factor_host(w.values)).to("cuda")
     S._alloc(True)
     st = torch.cuda.current_stream().cuda_stream
@@ -45,9 +52,10 @@ def test_normalize_run_matches_separate_calls(name, scale, sched):
                 d = (g64 - r64).abs().max().item()
                 pytest.fail(f"{what} differ in call {rep}: {bad.numel()} of {g64.numel()} doubles, max |diff| {d:.3e}, "
                             f"first at {bad[:8].tolist()}, nan in got {int(torch.isnan(g64).sum())}")
-    err = maxrel(S.to_host("x"), oracle_x(name, scale, None, 0.05))
-    print(f"  max-norm rel err vs oracle {err:.3e}", flush=True)
-    assert err <= (1e-9 if w.is_complex else 1e-10)
+    if not full:
+        err = maxrel(S.to_host("x"), oracle_x(name, scale, None, 0.05))
+        print(f"  max-norm rel err vs oracle {err:.3e}", flush=True)
+        assert err <= (1e-9 if w.is_complex else 1e-10)
     S.close()
 
 
