@@ -467,7 +467,9 @@ __global__ void __launch_bounds__(NT, 1)
 // columns of X = L_KK^{-1} are independent: one workgroup per 16-column block
 // [j0, j0 + 16) of one node solves L_KK X(:, J) = I(:, J) by forward
 // substitution down 16-row strips, with X(:, J) held in LDS.  Strip I:
-//   X(I, J) = I(I, J) - L(I, j0:I0) X(j0:I0, J)   (all threads, one entry each)
+//   X(I, J) = I(I, J) - L(I, j0:I0) X(j0:I0, J)   (one 16 x 16 MFMA product:
+//   the four waves take interleaved 4-deep slices of the contraction and sum
+//   their partials through LDS; complex in the 3M form)
 // then the 16 x 16 unit triangular solve with L(I, I) (one thread per column).
 // The L strip of the next row block is loaded while the current one is used.
 // MAXS bounds s for the nodes of the launch (256, or 64 for a launch of narrow
@@ -483,6 +485,7 @@ __global__ void __launch_bounds__(NT) k_normalize_inv(const DevPlan *__restrict_
   const DevPlan &pl = *plp;
   __shared__ double xs[P][MAXS * XP];  // X(j0 + r, j0 + q) at [r * XP + q]
   __shared__ double lsd[P][16 * LPI];  // L(I0 + i, j0 + k) at [i * LPI + k]
+  __shared__ double red[P][4 * 256];   // the waves' 16 x 16 partial products, [w * 256 + i * 16 + q]
   const int64_t per = (int64_t)nchunks * pl.batch;  // workgroups per panel set
   const int hs = nsets > 1 ? (int)(blockIdx.x / per) : 0;
   const int64_t g = blockIdx.x - hs * per;
@@ -523,11 +526,44 @@ __global__ void __launch_bounds__(NT) k_normalize_inv(const DevPlan *__restrict_
     }
     if (I0 + 16 < s) load_strip(I0 + 16);
     lds_barrier();
-    // X(I0 + ti, j0 + tq) before the diagonal block: identity minus the earlier strips
+    // X(I0 + ti, j0 + tq) before the diagonal block: identity minus the
+    // earlier strips, L(I, j0:I0) X(j0:I0, J) on MFMA (lane l of a wave
+    // holds A(l % 16, l / 16), B(l / 16, l % 16) and the result rows
+    // 4 v + l / 16 of column l % 16)
+    {
+      constexpr int C = P == 1 ? 1 : 3;  // product chains (3M for complex)
+      const int lane = t & 63, wv = t >> 6, m = lane & 15;
+      d4 pc[C];
+#pragma unroll
+      for (int q = 0; q < C; ++q) pc[q] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 4 * wv; k0 < r0; k0 += 16) {
+        const int ka = k0 + (lane >> 4);
+        if constexpr (P == 1) {
+          pc[0] = mfma16(lsd[0][m * LPI + ka], xs[0][ka * XP + m], pc[0]);
+        } else {
+          const double a0 = lsd[0][m * LPI + ka], a1 = lsd[1][m * LPI + ka];
+          const double b0 = xs[0][ka * XP + m], b1 = xs[1][ka * XP + m];
+          pc[0] = mfma16(a0, b0, pc[0]);
+          pc[1] = mfma16(a1, b1, pc[1]);
+          pc[2] = mfma16(a0 + a1, b0 + b1, pc[2]);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int o = wv * 256 + (4 * v + (lane >> 4)) * 16 + m;
+        if constexpr (P == 1) {
+          red[0][o] = pc[0][v];
+        } else {
+          red[0][o] = pc[0][v] - pc[1][v];
+          red[1][o] = pc[2][v] - pc[0][v] - pc[1][v];
+        }
+      }
+    }
+    lds_barrier();
     if (ti < h) {
       T acc = (I0 + ti == j0 + tq) ? SOps<T>::one() : zero_of<T>();
-      for (int k = 0; k < r0; ++k)
-        acc -= Planes<T>::from(&lsd[0][ti * LPI + k], 16 * LPI) * Planes<T>::from(&xs[0][k * XP + tq], MAXS * XP);
+#pragma unroll
+      for (int wq = 0; wq < 4; ++wq) acc -= Planes<T>::from(&red[0][wq * 256 + ti * 16 + tq], 4 * 256);
 #pragma unroll
       for (int p = 0; p < P; ++p) xs[p][(r0 + ti) * XP + tq] = Planes<T>::get(acc, p);
     }
