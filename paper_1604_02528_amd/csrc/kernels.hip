@@ -716,25 +716,31 @@ __global__ void __launch_bounds__(NT, 2)
 //   mode 1: Dt^{-1} = Linv^T D^{-1} Linv    -> panel top block
 //           (LU plans: U_KK^{-1} D^{-1} L_KK^{-1}, the left factor from the
 //           second half of the linv buffer; no mode 0)
+// The contraction runs in 32-deep stages through LDS, the diagonal factor
+// folded into the left operand as it is stored; wave w computes the 16 x 16
+// block (w & 1, w >> 1) of the tile on MFMA (complex in the 3M form), and the
+// tile leaves through LDS so that the stores coalesce.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_normalize_sq(const DevPlan *__restrict__ plp, const T *Src_all, T *Lp_all, T *dt_all,
                                                      const int4 *tiles, int32_t ntiles, int mode) {
+  constexpr int P = Planes<T>::P, C = P == 1 ? 1 : 3;  // product chains (3M for complex)
   const DevPlan &pl = *plp;
-  __shared__ double la[Planes<T>::P][32 * 33], lb[Planes<T>::P][32 * 33], dv[Planes<T>::P][32];
+  __shared__ double la[P][32 * 33], lb[P][32 * 33];
   const int64_t g = blockIdx.x;
   const int64_t l = g / ntiles;
   const int4 tk = tiles[g - l * ntiles];
   const int K = tk.x, i0 = tk.y * 32, j0 = tk.z * 32;
   const int s = gp(pl.node_s)[K], c = gp(pl.node_c)[K], ld = s + c;
   const T *Q = Src_all + l * pl.panel_elems + gp(pl.node_off)[K];  // LDL^T panel (mode 0 reads it)
-  T *P = Lp_all + l * pl.panel_elems + gp(pl.node_off)[K];         // normalized panel (mode 1 writes it)
+  T *P_ = Lp_all + l * pl.panel_elems + gp(pl.node_off)[K];        // normalized panel (mode 1 writes it)
   const T *Linv = reinterpret_cast<const T *>(pl.linv) + l * pl.sq_elems + gp(pl.node_sq)[K];
   const T *Uinv = pl.half > 0 ? Linv + pl.batch * pl.sq_elems : Linv;  // U_KK^{-T} in LU plans
   const T *dinv = reinterpret_cast<const T *>(pl.dinv) + l * pl.n + gp(pl.node_first)[K];
-  T acc[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, m = lane & 15;
+  const int bi = wv & 1, bj = wv >> 1;
+  d4 pc[C];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = zero_of<T>();
-  const int ti = threadIdx.x & 31, tj = threadIdx.x >> 5;  // tj 0..7, 4 columns each
+  for (int q = 0; q < C; ++q) pc[q] = d4{0.0, 0.0, 0.0, 0.0};
   int kb, ke;
   if (mode == 0) {
     kb = 0;
@@ -751,62 +757,68 @@ __global__ void __launch_bounds__(NT) k_normalize_sq(const DevPlan *__restrict__
       T va = zero_of<T>(), vb = zero_of<T>();
       if (k < ke) {
         const int ia = i0 + x, jb = j0 + x;
-        if (mode == 0) {  // L[i][k] with unit diagonal
+        T d;
+        if (mode == 0) {  // L[i][k] with unit diagonal, D_k
           if (ia < s) va = (ia == k) ? SOps<T>::one() : (ia > k ? Q[(int64_t)k * ld + ia] : zero_of<T>());
           if (jb < s) vb = (jb == k) ? SOps<T>::one() : (jb > k ? Q[(int64_t)k * ld + jb] : zero_of<T>());
-        } else {  // Linv[k][i] (column-major, ld s), lower triangular
+          d = Q[(int64_t)k * ld + k];
+        } else {  // Linv[k][i] (column-major, ld s), lower triangular; D_k^{-1}
           if (ia < s) va = gload(Uinv + (int64_t)ia * s + k);
           if (jb < s) vb = gload(Linv + (int64_t)jb * s + k);
+          d = gload(dinv + k);
         }
         // the transposed factor: L_KK^T (mode 0, right) or Linv^T (mode 1, left)
         if (mode == 0)
           vb = cj(vb, pl.csign);
         else
           va = cj(va, pl.csign);
+        va = va * d;
       }
 #pragma unroll
-      for (int p = 0; p < Planes<T>::P; ++p) {
+      for (int p = 0; p < P; ++p) {
         la[p][x * 33 + kk] = Planes<T>::get(va, p);
         lb[p][x * 33 + kk] = Planes<T>::get(vb, p);
       }
     }
-    if (threadIdx.x < 32) {
-      const int k = k0 + threadIdx.x;
-      T d = zero_of<T>();
-      if (k < ke) d = (mode == 0) ? Q[(int64_t)k * ld + k] : gload(dinv + k);
-#pragma unroll
-      for (int p = 0; p < Planes<T>::P; ++p) dv[p][threadIdx.x] = Planes<T>::get(d, p);
-    }
     lds_barrier();
-    for (int kk = 0; kk < 32; ++kk) {
-      T a, d;
-      if constexpr (Planes<T>::P == 1) {
-        a = la[0][ti * 33 + kk];
-        d = dv[0][kk];
-      } else {
-        a = T{la[0][ti * 33 + kk], la[1][ti * 33 + kk]};
-        d = T{dv[0][kk], dv[1][kk]};
-      }
-      const T ad = a * d;
+    // lane l: A(i = 16 bi + l % 16, k = 4 k4 + l / 16), B(k, j = 16 bj + l % 16)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int jj = tj * 4 + q;
-        T b;
-        if constexpr (Planes<T>::P == 1) b = lb[0][jj * 33 + kk];
-        else b = T{lb[0][jj * 33 + kk], lb[1][jj * 33 + kk]};
-        acc[q] += ad * b;
+    for (int k4 = 0; k4 < 8; ++k4) {
+      const int ka = 4 * k4 + (lane >> 4);
+      if constexpr (P == 1) {
+        pc[0] = mfma16(la[0][(16 * bi + m) * 33 + ka], lb[0][(16 * bj + m) * 33 + ka], pc[0]);
+      } else {
+        const double a0 = la[0][(16 * bi + m) * 33 + ka], a1 = la[1][(16 * bi + m) * 33 + ka];
+        const double b0 = lb[0][(16 * bj + m) * 33 + ka], b1 = lb[1][(16 * bj + m) * 33 + ka];
+        pc[0] = mfma16(a0, b0, pc[0]);
+        pc[1] = mfma16(a1, b1, pc[1]);
+        pc[2] = mfma16(a0 + a1, b0 + b1, pc[2]);
       }
     }
   }
-  const int i = i0 + ti;
+  lds_barrier();
+  // the tile into la as [j][i] (result row 4 v + l / 16 of column l % 16 of
+  // the wave's block), then stores with lanes along i
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int j = j0 + tj * 4 + q;
-    if (i < s && j < s) {
+  for (int v = 0; v < 4; ++v) {
+    const int i = 16 * bi + 4 * v + (lane >> 4), j = 16 * bj + m;
+    if constexpr (P == 1) {
+      la[0][j * 33 + i] = pc[0][v];
+    } else {
+      la[0][j * 33 + i] = pc[0][v] - pc[1][v];
+      la[1][j * 33 + i] = pc[2][v] - pc[0][v] - pc[1][v];
+    }
+  }
+  lds_barrier();
+  for (int e = threadIdx.x; e < 32 * 32; e += NT) {
+    const int i = e & 31, jj = e >> 5;
+    const int gi = i0 + i, gj = j0 + jj;
+    if (gi < s && gj < s) {
+      const T v = Planes<T>::from(&la[0][jj * 33 + i], 32 * 33);
       if (mode == 0)
-        dt_all[l * pl.sq_elems + gp(pl.node_sq)[K] + (int64_t)j * s + i] = acc[q];
+        dt_all[l * pl.sq_elems + gp(pl.node_sq)[K] + (int64_t)gj * s + gi] = v;
       else
-        P[(int64_t)j * ld + i] = acc[q];
+        P_[(int64_t)gj * ld + gi] = v;
     }
   }
 }
