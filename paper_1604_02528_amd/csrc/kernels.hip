@@ -1,19 +1,22 @@
 // HIP kernels of the selected-inversion library for gfx950 (CDNA4).
 //
-//  normalize  Alg. 1 steps 1-2 in LDL^T form: Lhat_{C,K} = L_{C,K} L_KK^{-1}
-//             (row-wise back substitution, in place), L_KK^{-1} into scratch,
+//  normalize  Alg. 1 steps 1-2 in LDL^T form (LU form: both panel sets):
+//             L_KK^{-1} into scratch (strip-wise forward substitution),
+//             Lhat_{C,K} = L_{C,K} L_KK^{-1} (MFMA, in place),
 //             Dt_K = L_KK D_K L_KK^T (optional, for the adjoint) and
 //             Dt_K^{-1} = L_KK^{-T} D_K^{-1} L_KK^{-1} into the panel's top block.
 //  selinv     Alg. 1 second loop (root first): per supernode K the gather of
-//             X_{C,C} through the ancestor maps into LDS, GEMM-1
-//             X_{C,K} = -X_{C,C} Lhat_{C,K} and GEMM-2
+//             X_{C,C} through the ancestor maps (on the fly, or once into a
+//             dense buffer), GEMM-1 X_{C,K} = -X_{C,C} Lhat_{C,K} and GEMM-2
 //             X_KK = Dt^{-1} - Lhat^T X_{C,K} on FP64 MFMA
-//             (v_mfma_f64_16x16x4f64; complex128 by four real products), the
-//             diagonal-block symmetrization of Section 2.3, coalesced stores.
-//             Scheduled either level by level or by one persistent launch
-//             whose workgroups pop items from a device ready queue fed by
+//             (v_mfma_f64_16x16x4f64; complex128 by four real products, or
+//             three in the dense GEMM-1, GEMM-2 and normalization kernels),
+//             the diagonal-block symmetrization of Section 2.3, coalesced
+//             stores.  Scheduled level by level (one launch per etree depth
+//             and phase, each phase in a kernel sized for it), by one
+//             persistent launch whose workgroups draw tickets and wait on
 //             per-node dependency counters (the device counterpart of the
-//             task dependencies of Section 3).
+//             task dependencies of Section 3), or in the push form of Alg. 2.
 //  extract    X on A's pattern.
 //
 // MFMA f64 16x16x4 operand layout (measured on gfx950): lane l holds
