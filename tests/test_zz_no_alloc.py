@@ -78,3 +78,42 @@ def test_noalloc_matches_work_buffer_entry_point(sched):
     _noalloc_matches(Sc, lc, rc, "C3 8^3 x2 complex")
     for S in (Sb, Ss, Sc):
         S.close()
+
+
+@pytest.mark.gpu
+def test_noalloc_lu_form():
+    """The LU form through the no-alloc entry point (two panel sets, a doubled
+    L_KK^{-1} scratch in the fixed array): bit for bit the work-buffer call,
+    then a smaller symmetric plan and the LU plan again."""
+    from paper_1604_02528_amd import SelInv, capi
+
+    w = workload("U3", 8, 2)
+    print("no-alloc LU case: U3 8^3 x2, then C1, then U3 again", flush=True)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="lu64", batch=w.batch, cap=w.cap, relax=0.05)
+    ldlt = torch.from_numpy(S.factor_host(w.values)).to("cuda")
+    S._alloc(False)
+    b = S._bufs
+    st = torch.cuda.current_stream().cuda_stream
+    for t in (b["panels"], b["x"]):
+        t.zero_()
+    capi.selinv_normalize_run(S.h, ldlt, b["panels"], b["x"], b["work"], None, st)
+    S.sync()
+    ref = (b["panels"].clone(), b["x"].clone())
+
+    def check(label):
+        for t in (b["panels"], b["x"]):
+            t.zero_()
+        print(f"  no-alloc call: {label}", flush=True)
+        capi.selinv_normalize_run_noalloc(S.h, ldlt, b["panels"], b["x"], None, st)
+        S.sync()
+        torch.cuda.synchronize()
+        assert torch.equal(b["panels"], ref[0]), label
+        assert torch.equal(b["x"], ref[1]), label
+
+    check("U3 8^3 x2")
+    ws, Ss, ls, rs = _setup("C1", None, None, "levels")
+    _noalloc_matches(Ss, ls, rs, "C1 (symmetric, between the LU calls)")
+    check("U3 8^3 x2 again (tables uploaded anew)")
+    assert maxrel(S.to_host("x"), oracle_x("U3", 8, 2, 0.05)) <= 1e-10
+    S.close()
+    Ss.close()
