@@ -189,3 +189,62 @@ def test_u3_full_size_shifts_vs_oracle(u3_full, l):
     err = maxrel(u3_full[0][l], ref)
     print(f"  U3 shift {l}: max-norm rel err {err:.3e}", flush=True)
     assert err <= TOL
+
+
+def _lu_edge(name, rng):
+    """(n, colptr, rowind, lo, up) of a degenerate LU input: A(r, c) for the
+    stored lower entries, then their mirrors A(c, r)."""
+    from workloads.grids import _lower_csc
+
+    if name == "n1":
+        return 1, np.array([0, 1]), np.array([0]), np.array([3.0]), np.array([3.0])
+    if name == "diagonal":
+        n = 50
+        d = rng.uniform(1, 2, n)
+        colptr, rowind, _ = _lower_csc(n, np.arange(n), np.arange(n), d[None, :])
+        return n, colptr, rowind, d, d.copy()
+    if name in ("dense40", "dense300"):  # dense300 is above the supernode cap: two supernodes
+        n = 40 if name == "dense40" else 300
+        A = rng.standard_normal((n, n)) + n * np.eye(n)
+        r, c = np.tril_indices(n)
+        colptr, rowind, both = _lower_csc(n, r, c, np.stack([A[r, c], A[c, r]]))
+        return n, colptr, rowind, both[0], both[1]
+    if name == "arrow":  # every leaf has C(K) = {last column}
+        n = 100
+        r = np.concatenate([np.arange(n), np.full(n - 1, n - 1)])
+        c = np.concatenate([np.arange(n), np.arange(n - 1)])
+        lo = np.concatenate([np.full(n, float(n)), rng.uniform(-1, 1, n - 1)])
+        up = np.concatenate([np.full(n, float(n)), rng.uniform(-1, 1, n - 1)])
+        colptr, rowind, both = _lower_csc(n, r, c, np.stack([lo, up]))
+        return n, colptr, rowind, both[0], both[1]
+    raise KeyError(name)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("dense", [0, 65], ids=["dense_default", "dense_all"])
+@pytest.mark.parametrize("name", ["n1", "diagonal", "dense40", "dense300", "arrow"])
+def test_lu_edge_cases_vs_dense_inverse(name, dense):
+    """Degenerate LU inputs (one unknown, a diagonal matrix, dense unsymmetric
+    matrices below and above the supernode cap, an arrow) against numpy's dense
+    inverse, on both panel sets and through selinv_extract."""
+    from paper_1604_02528_amd import SelInv
+
+    rng = np.random.default_rng(47)
+    n, colptr, rowind, lo, up = _lu_edge(name, rng)
+    perm = np.arange(n, dtype=np.int64)
+    print(f"lu edge case {name} n={n} dense={dense}", flush=True)
+    sym = symbolic.analyze(n, colptr, rowind, perm, cap=256, relax=0.0)
+    S = SelInv(n, colptr, rowind, perm, dtype="lu64", batch=1, cap=256, relax=0.0, dense_min_c=dense)
+    S.factor(np.concatenate([lo, up])[None, :])
+    S.run()
+    xa = S.extract()
+    S.sync()
+    A = dense_original_lu(n, colptr, rowind, lo, up)
+    Ainv = np.linalg.inv(A)
+    RL, RU = selected_from_dense_lu(sym, Ainv)
+    err = maxrel(S.to_host("x")[0], np.concatenate([selinv.flatten(sym, RL), selinv.flatten(sym, RU)]))
+    cols = np.repeat(np.arange(n), np.diff(colptr))
+    err_a = maxrel(xa.cpu().numpy()[0], np.concatenate([Ainv[rowind, cols], Ainv[cols, rowind]]))
+    print(f"  panels {err:.3e}, on A's pattern {err_a:.3e}", flush=True)
+    assert err <= TOL and err_a <= TOL
+    S.close()
