@@ -201,3 +201,17 @@ def test_lu_plan_replay_and_refusals():
         with pytest.raises(capi.SelinvError) as ei:
             SelInv(w.n, w.colptr, w.rowind, w.perm, dtype="lu64", batch=w.batch, cap=w.cap, sched=sched, device="cpu")
         assert ei.value.status == 7
+
+
+@pytest.mark.parametrize("sched", ["persistent", "push"])
+@pytest.mark.parametrize("name,scale", [("C2", 12), ("C3", 8), ("H3", 8)])
+def test_plan_check_other_schedules(name, scale, sched):
+    """The plan check (ticket replay, normalization chunks) on the persistent
+    and push plans too; they have a single normalization chunk."""
+    from paper_1604_02528_amd import SelInv, capi
+
+    w = workload(name, scale)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=w.dtype, batch=w.batch, cap=w.cap, relax=0.05, sched=sched,
+               device="cpu", adjoint=False)
+    capi.selinv_check_plan(S.h)
+    assert len(capi.selinv_items(S.h, 3)) == 1
