@@ -121,7 +121,7 @@ typedef struct {
                              "selinv-tune-1"), or NULL.  Entries of this GPU target, ROCm version
                              and dtype choose, per bucket of supernode width s and |C(K)|, whether
                              X_{C,C} is gathered into a dense buffer, whether a dense node's GEMM-1
-                             runs in the GEMM-1-only kernel (level schedule), and split_min_k; they
+                             runs in the dense-loader kernel (level schedule), and split_min_k; they
                              override dense_min_c / split_min_k for the nodes they cover.  Read by
                              selinv_analyze (EINVAL on a malformed file); the string is copied */
 } selinv_opts;
@@ -399,8 +399,8 @@ selinv_status selinv_trace(selinv_ctx *h, void *trace_dev);
  *     12 / 13 = the whole R1 / R3 of a small node in one wavefront.
  *   which = 2: the forward traversal's launches under the level and push
  *     schedules, in order: {kind (0 work items, 1 single-wavefront nodes,
- *     2 GEMM-1-only dense-buffer tiles, 3 push tiles, 4 GEMM-1-only
- *     128 x 128 tiles of FP64 nodes the tune table marks, 5 gathers into
+ *     2 dense-buffer GEMM-1 tiles with their GEMM-2 shares, 3 push tiles,
+ *     4 GEMM-1-only 128 x 128 tiles of FP64 nodes the tune table marks, 5 gathers into
  *     the dense X_{C,C} buffers, 6 GEMM-2 shares), items or records
  *     per matrix, type of the first item (-1 for push tiles), etree depth}.  The list is
  *     built for every plan; the persistent schedule does not launch by it.

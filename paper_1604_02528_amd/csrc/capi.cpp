@@ -69,7 +69,7 @@ struct HostPlan {
   bool adjoint = false;        // adjoint scratch allocated (opts.adjoint >= 0)
   bool lu = false;             // LU plan: two panel sets (L, U^T), gathered GEMM-1 tiles only
   std::vector<int32_t> lvl_items, lvl_ptr, lvl_tiny, lvl_kind;
-  std::vector<int32_t> node_defer;  // GEMM-2 of the node in ITEM_P items (level schedule, dense buffer, unsplit)
+  std::vector<int32_t> node_defer;  // GEMM-2 of the node in ITEM_P items (push schedule; level schedule: unsplit 128 x 128 tiles)
   std::vector<int32_t> node_ykern;  // GEMM-1 tiles in k_ydense (level schedule, dense buffer)
   std::vector<int8_t> node_y128;    // ... on 128 x 128 tiles in k_ydense128 (FP64, tune table)
   std::vector<Item> y128;           // the k_ydense128 records, in launch order
@@ -426,8 +426,8 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   // of P (the R phase of the top separator chain is otherwise one long item
   // per tile).
   // Under the level schedule, the GEMM-1 tiles of nodes with a dense buffer
-  // run in their own kernel without GEMM-2; for unsplit ones the GEMM-2
-  // shares move to ITEM_P items of phase 2.
+  // run in their own kernel, which also runs the GEMM-2 shares of unsplit 64 x
+  // 64 tiles; those of 128 x 128 tiles move to ITEM_P items of phase 2.
   H.node_defer.assign(ns, 0);
   H.node_ykern.assign(ns, 0);
   H.node_y128.assign(ns, 0);
@@ -438,7 +438,8 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
       if (H.node_goff[K] >= 0 && ykern_pref[K] != 0 && !(S.nrows(K) <= kSmallC && S.width(K) <= kSmallS)) {
         H.node_ykern[K] = 1;
         H.node_y128[K] = tile128[K];
-        if (H.node_yoff[K] < 0) H.node_defer[K] = 1;
+        // GEMM-2 fused into k_ydense's tiles; the 128 x 128 tiles leave it to ITEM_P items
+        if (H.node_yoff[K] < 0 && H.node_y128[K]) H.node_defer[K] = 1;
       }
   std::vector<int64_t> rtiles(S.depth, 0);
   for (int64_t K = 0; K < ns; ++K)

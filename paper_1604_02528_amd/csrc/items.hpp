@@ -473,11 +473,12 @@ __device__ void do_ptile(const Ctx<T> &cx, const NodeInfo &nd, int a, int br, do
   gemm2_partial<T, COH, PF>(cx, nd, a, b, acc, smem, qb, qe);
 }
 
-// GEMM-1 tile of a node with a dense X_{C,C} buffer, without GEMM-2: the
-// level schedule runs these in k_ydense (fewer registers than the general
-// item kernel, two workgroups per CU).  The tile goes to X (nodes whose
-// GEMM-2 runs in ITEM_P items) or to the partial tiles of a split
-// contraction (summed by ITEM_R items).
+// GEMM-1 tile of a node with a dense X_{C,C} buffer: the level schedule runs
+// these in k_ydense (dense loaders only, so fewer registers than the general
+// item kernel: two workgroups per CU).  An unsplit tile goes to X and then
+// adds its GEMM-2 share from the registers; a 128 x 128 tile leaves that
+// share to ITEM_P items, and a split contraction writes partial tiles that
+// ITEM_R items sum.
 // LU plans: up (an ITEM_YU tile) takes X_{K,C}^T = -(X_{C,C})^T Uhat^T from
 // the transposed full buffer and the second panel sets.
 template <typename T>
@@ -506,6 +507,13 @@ __device__ __forceinline__ void do_ytile_dense(const Ctx<T> &cx, const NodeInfo 
     for (int e = threadIdx.x; e < 64 * 64; e += NT) {
       const int i = e & 63, j = e >> 6;
       if (i0 + i < c && j0 + j < s) gstore(X + (int64_t)(j0 + j) * ld + i0 + i, SOps<T>::scale(-1.0, lds_get<T>(smem, i, j)));
+    }
+    // the row tile's GEMM-2 share (Alg. 1 step 4) from the tile still in
+    // registers, unless the plan runs it in ITEM_P items (the LU upper part
+    // has none)
+    if (!up && !uniform(nd.defer2)) {
+      lds_barrier();
+      gemm2_partial<T, false, Planes<T>::P == 1>(cx, nd, a, b, acc, smem);
     }
   } else {  // partial tile Ypart[part] (column-major c x s)
     T *Y = static_cast<T *>(cx.Yp) + nd.yoff + (int64_t)part * c * s;

@@ -132,11 +132,13 @@ __global__ void __launch_bounds__(NT, 2) k_gemm2_list(const DevPlan *__restrict_
   }
 }
 
-// GEMM-1 tiles of nodes with a dense X_{C,C} buffer (see do_ytile_dense): no
-// GEMM-2 in this kernel, so it fits two workgroups per CU also for complex.
+// GEMM-1 tiles of nodes with a dense X_{C,C} buffer (see do_ytile_dense),
+// each followed by its GEMM-2 share when unsplit: dense loaders only, so it
+// fits two workgroups per CU also for complex.
 template <typename T>
-__global__ void __launch_bounds__(NT, 2) k_ydense(const DevPlan *__restrict__ plp, const T *Lp, T *Xp, const LRec *recs,
-                                                  const int32_t *list, int32_t count, int32_t list_pos) {
+__global__ void __launch_bounds__(NT, 2) k_ydense(const DevPlan *__restrict__ plp, const T *Lp, T *Xp, T *Pp,
+                                                  const LRec *recs, const int32_t *list, int32_t count,
+                                                  int32_t list_pos) {
   const DevPlan &pl = *plp;
   constexpr int kStages = 2 * dense_stage_doubles<T, DenseTK<T>::TK>();
   __shared__ double smem[kStages > tile_doubles<T>() ? kStages : tile_doubles<T>()];
@@ -144,7 +146,7 @@ __global__ void __launch_bounds__(NT, 2) k_ydense(const DevPlan *__restrict__ pl
   const int64_t l = g / count;
   const int64_t q = g - l * count;
   const int64_t t_start = pl.trace ? wall_clock64() : 0;
-  Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, nullptr,
+  Ctx<T> cx{&pl, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, Pp + l * pl.part_elems,
             static_cast<T *>(pl.gbuf) + l * pl.g_elems, static_cast<T *>(pl.ypart) + l * pl.y_elems};
   const LRec rec = recs[q];
   const Item it = uniform(rec.it);
@@ -231,7 +233,7 @@ __global__ void __launch_bounds__(NT, Planes<T>::P == 1 ? 2 : 1)
 // GEMM-1 of FP64 dense-buffer nodes on 128 x 128 tiles (the tune table's
 // tile choice): record {K, type, a, b} names the node, 128-row tile a of C(K)
 // and, in b, the 128-column tile of K (low 16 bits) and the contraction part
-// (high bits).  Like k_ydense: no GEMM-2 here; the tile goes to X (-acc) or
+// (high bits).  No GEMM-2 here (ITEM_P items run it); the tile goes to X (-acc) or
 // to the split contraction's partial tiles.  Each lane stores its
 // accumulator elements directly: per store, the four lanes of a block column
 // write four consecutive rows (32 bytes).
@@ -988,7 +990,7 @@ static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
                              reinterpret_cast<const double *>(Lp), reinterpret_cast<double *>(Xp),
                              aux.y128 + aux.lvl_tiny[q], e - b, b);
       } else if (aux.lvl_kind[q] == LVL_YDENSE)
-        hipLaunchKernelGGL(k_ydense<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp,
+        hipLaunchKernelGGL(k_ydense<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,
                            aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
       else if (aux.lvl_kind[q] == LVL_GATHER)
         hipLaunchKernelGGL((pl.half > 0 ? k_gather_list<T, true> : k_gather_list<T, false>),

@@ -13,12 +13,14 @@
 // nodes no entry holds keep the library defaults.  Fields:
 //   dense        1: X_{C,C} gathered once into a dense buffer; 0: gathered by
 //                the GEMM-1 tiles on the fly
-//   ydense       1: a dense node's GEMM-1 tiles run in the GEMM-1-only kernel
-//                and GEMM-2 in separate items (level schedule); 0: fused
+//   ydense       1: a dense node's GEMM-1 tiles run in the dense-loader kernel
+//                (level schedule; GEMM-2 shares fused on 64 x 64 tiles, in
+//                separate items on 128 x 128 ones); 0: in the general kernel,
+//                GEMM-2 fused
 //   split_min_k  shortest contraction part of a split GEMM-1 (0: library
 //                default, < 0: never split)
 //   tile         64 or 128: the GEMM-1 tile of a node whose tiles run in the
-//                GEMM-1-only kernel (128 x 128 for FP64 plans only; absent: 64)
+//                dense-loader kernel (128 x 128 for FP64 plans only; absent: 64)
 #include <cctype>
 #include <cstdio>
 #include <cstdlib>

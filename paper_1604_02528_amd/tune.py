@@ -4,13 +4,13 @@ selinv_opts.tune_cache (SelInv(tune_cache=...)) reads.
 
 Choices per bucket (see csrc/tune.cpp for the file format):
   dense_ydense  X_{C,C} gathered once into a dense buffer; GEMM-1 tiles in the
-                GEMM-1-only kernel (two workgroups per CU), GEMM-2 in separate
-                items
+                dense-loader kernel (two workgroups per CU), each with its
+                GEMM-2 share
   dense_fused   dense buffer; GEMM-1 tiles with their GEMM-2 share fused, in
                 the general item kernel
   gather        X_{C,C} gathered by the GEMM-1 tiles on the fly (no buffer)
   dense_ydense128  as dense_ydense on 128 x 128 tiles (FP64 only: the tile
-                shape is the choice)
+                shape is the choice), GEMM-2 in separate items
 and, per workload dtype, the shortest part of a split contraction.
 
 Method: coordinate descent on measured time.  Starting from the library

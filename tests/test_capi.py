@@ -375,9 +375,11 @@ def test_forward_items_cover_every_tile_once(name, scale):
 def test_tune_table_choices_shape_the_plan(choice):
     """A table forcing one choice on every bucket: 'gather' leaves no dense
     X_{C,C} buffer (no G items); 'dense_fused' gives every node with c > 64 a
-    buffer and keeps GEMM-2 in the GEMM-1 tiles (no P items); 'dense_ydense'
-    moves the GEMM-2 of unsplit dense nodes into P items.  Every supernode is
-    covered by an entry."""
+    buffer and keeps GEMM-2 in the GEMM-1 tiles of the general item kernel;
+    'dense_ydense' runs them in the GEMM-1 kernel of the dense nodes, with the
+    GEMM-2 share still fused (no P items); 'dense_ydense128' moves the GEMM-2
+    of unsplit dense nodes into P items (the 128 x 128 tiles have none).
+    Every supernode is covered by an entry."""
     from paper_1604_02528_amd import capi
     from tests._tune import forced_table, remove
 
@@ -396,8 +398,8 @@ def test_tune_table_choices_shape_the_plan(choice):
             assert not dense_nodes and not (types == 5).any()
         else:
             assert dense_nodes == big
-            assert (types == 5).any() == (choice in ("dense_ydense", "dense_ydense128"))
-        # the 128 x 128 tiles replace the 64 x 64 GEMM-1-only launches (kind 4 for kind 2)
+            assert (types == 5).any() == (choice == "dense_ydense128")
+        # the 128 x 128 tiles replace the 64 x 64 dense-buffer launches (kind 4 for kind 2)
         kinds = set(capi.selinv_items(S.h, 2)[:, 0].tolist())
         assert (4 in kinds) == (choice == "dense_ydense128")
         assert (2 in kinds) == (choice == "dense_ydense")
