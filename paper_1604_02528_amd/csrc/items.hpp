@@ -499,7 +499,7 @@ __device__ __forceinline__ void do_ytile_dense(const Ctx<T> &cx, const NodeInfo 
   la.cs = cx.pl->csign;
   LoadDenseB<T, TK> lb{cx.Lp + hs, nd.off, ld, s, ke, j0, s};
   Acc<T> acc;
-  gemm_dense<T, true>(kb, ke, la, lb, smem, acc);  // complex: three real product chains
+  gemm_dense_il<T, true>(kb, ke, la, lb, smem, acc);  // complex: three real product chains
   acc_to_lds<T>(acc, smem);
   lds_barrier();
   if (nd.yoff < 0) {  // Y = -acc into X_{C,K} (LU up: the second set)

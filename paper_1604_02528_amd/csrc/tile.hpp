@@ -582,6 +582,43 @@ template <typename T, int TK> struct LoadDenseASym : LoadDenseA<T, TK> {
     return upper(k0) ? opaque_mask(((urow_ok >> m) & 1u) != 0 && k0 + kkt < this->kend) : Base::mask(k0, m);
   }
   __device__ __forceinline__ double imsign(int k0, int) const { return upper(k0) ? cs : 1.0; }
+  // Branch-free forms of load and of the stage store (masks always applied;
+  // the mirrored or direct form picked by wave-uniform selects), so that a
+  // stage's loads and stores can share a basic block with the MFMAs of the
+  // previous stage.
+  __device__ __forceinline__ void load_bf(int k0, DVals<T, TK> &v) const {
+    const bool up = upper(k0);
+    const int over = k0 + kkt - (this->kend - 1);
+    const uint32_t back = (uint32_t)(over > 0 ? over : 0) * (uint32_t)sizeof(T);
+    // the element offset of the slot's base blended with an opaque uniform
+    // mask, so that the compiler keeps one straight-line block (a select of
+    // the two offsets becomes a branch)
+    int su32 = uniform(up ? -1 : 0);
+    asm("" : "+s"(su32));
+    const int64_t su = su32;
+    const int64_t eu = (int64_t)i0 * this->ldg + k0;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int k = min(k0 + this->kq + (NT / 64) * m, this->kend - 1);
+      const int64_t eo = (eu & su) | (((int64_t)k * this->ldg) & ~su);
+      v.v[m] = ld_off(this->G + eo, up ? uoff[m] - back : this->vrow);
+    }
+  }
+  __device__ __forceinline__ void store_bf(double *stg, int plane_off, int k0, const DVals<T, TK> &v) const {
+    constexpr int P = Planes<T>::P;
+    const bool up = upper(k0);
+    const double sg = up ? cs : 1.0;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int e = threadIdx.x + NT * m;
+      const int slot = up ? (e % TK) * PITCH + e / TK : (e >> 6) * PITCH + (e & 63);
+      const bool oku = ((urow_ok >> m) & 1u) != 0 && k0 + kkt < this->kend;
+      const bool okl = this->rmask != 0 && k0 + this->kq + (NT / 64) * m < this->kend;
+      const T x = masked(v.v[m], opaque_mask(up ? oku : okl));
+#pragma unroll
+      for (int p = 0; p < P; ++p) stg[(plane_off + p) * TK * PITCH + slot] = p == 1 ? Planes<T>::get(x, p) * sg : Planes<T>::get(x, p);
+    }
+  }
   __device__ __forceinline__ void load(int k0, DVals<T, TK> &v) const {
     if (upper(k0)) {
       const int over = k0 + kkt - (this->kend - 1);  // the last stage clamps k onto kend - 1
@@ -622,6 +659,23 @@ template <typename T, int TK> struct LoadDenseB {
   __device__ __forceinline__ bool all_valid(int k0) const { return cols_full && k0 + TK <= kend; }
   __device__ __forceinline__ int64_t mask(int k0, int m) const {
     return opaque_mask(k0 + kk < kend && x0 + xq + (NT / TK) * m < xmax);
+  }
+  // branch-free forms (see LoadDenseASym::load_bf)
+  __device__ __forceinline__ void load_bf(int k0, DVals<T, TK> &v) const {
+    const int over = k0 + kk - (kend - 1);
+    const uint32_t back = (uint32_t)(over > 0 ? over : 0) * (uint32_t)sizeof(T);
+    const T *base = Pn + k0;
+#pragma unroll
+    for (int m = 0; m < E; ++m) v.v[m] = ld_off(base, voff[m] - back);
+  }
+  __device__ __forceinline__ void store_bf(double *stg, int plane_off, int k0, const DVals<T, TK> &v) const {
+    constexpr int P = Planes<T>::P;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const T x = masked(v.v[m], mask(k0, m));
+#pragma unroll
+      for (int p = 0; p < P; ++p) stg[(plane_off + p) * TK * PITCH + slot(k0, m)] = Planes<T>::get(x, p);
+    }
   }
   __device__ __forceinline__ void load(int k0, DVals<T, TK> &v) const {
     if (k0 + TK <= kend) {
@@ -827,6 +881,90 @@ __device__ __forceinline__ void gemm_dense(int kb, int ke, const LA &la, const L
   lds_barrier();  // the caller reuses the stage buffers
 }
 
+
+// Issue order inside one step of gemm_dense_il: each of its NM MFMAs is
+// followed by one of the NW LDS stores of the next stage, then by one of the
+// NL global loads of the stage after it (the stage's own LDS reads are left
+// to the scheduler).
+template <int NM, int NW, int NL>
+__device__ __forceinline__ void interleave_stage() {
+#pragma unroll
+  for (int i = 0; i < NM; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+    if (i < NW)
+      __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // DS write
+    else if (i < NW + NL)
+      __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM read
+  }
+}
+
+// gemm_dense with the branch-free loaders (load_bf / store_bf): each loop
+// step is one basic block holding a stage's MFMAs, the LDS stores of the next
+// stage (into the other buffer) and the global loads of the stage after
+// that, so the stores and loads can issue in the shadow of the MFMAs instead
+// of between them; one barrier per stage.  Same operands and results as
+// gemm_dense (accumulate = false).
+template <typename T, bool G3, class LA, class LB>
+__device__ __forceinline__ void gemm_dense_il(int kb, int ke, const LA &la, const LB &lb, double *smem, Acc<T> &acc) {
+  constexpr int TK = DenseTK<T>::TK, P = Planes<T>::P;
+  constexpr bool M3 = G3 && P == 2;
+  constexpr int SD = dense_stage_doubles<T, TK>();
+  using V = DVals<T, TK>;
+  acc_zero<T>(acc);
+  const int nk = (ke - kb + TK - 1) / TK;
+  if (nk <= 0) return;
+  Acc3M a3;
+  if constexpr (M3) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) a3.v[q][bi][bj] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+  auto compute = [&](const double *stg) {
+    if constexpr (M3)
+      stage_compute_3m<TK>(stg, a3);
+    else
+      stage_compute<T, TK>(stg, acc);
+  };
+  const int klast = kb + (nk - 1) * TK;
+  auto kat = [&](int j) { return min(kb + j * TK, klast); };
+  // one register set: the loads of stage kt + 2 are issued with the MFMAs of
+  // stage kt and stored with those of stage kt + 1
+  V a, b;
+  la.load_bf(kb, a);
+  lb.load_bf(kb, b);
+  la.store_bf(smem, 0, kb, a);
+  lb.store_bf(smem, P, kb, b);
+  la.load_bf(kat(1), a);
+  lb.load_bf(kat(1), b);
+  lds_barrier();
+  for (int kt = 0; kt + 1 < nk; ++kt) {
+    double *nxt = smem + ((kt + 1) & 1) * SD;
+    compute(smem + (kt & 1) * SD);
+    la.store_bf(nxt, 0, kat(kt + 1), a);
+    lb.store_bf(nxt, P, kat(kt + 1), b);
+    la.load_bf(kat(kt + 2), a);
+    lb.load_bf(kat(kt + 2), b);
+    // MFMAs per stage: (TK / 4) steps of 2 x 2 blocks (x 3 chains in the 3M form)
+    interleave_stage<(TK / 4) * 4 * (M3 ? 3 : 1), 2 * LA::E * P, 2 * LA::E>();
+    lds_barrier();
+  }
+  compute(smem + ((nk - 1) & 1) * SD);
+  if constexpr (M3) {
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const d4 re = a3.v[0][bi][bj] - a3.v[1][bi][bj];
+        const d4 im = a3.v[2][bi][bj] - a3.v[0][bi][bj] - a3.v[1][bi][bj];
+        acc.v[0][bi][bj] += re;
+        acc.v[1][bi][bj] += im;
+      }
+  }
+  lds_barrier();  // the caller reuses the stage buffers
+}
 
 // ---------------------------------------------------------------------------
 // 128 x 128 FP64 tile (GEMM-1 of large dense-buffer nodes, a tune-table
