@@ -264,6 +264,17 @@ selinv_status selinv_factor_device(selinv_ctx *h, const void *values_dev, void *
  * and X_{K,C}^T = -(X_{C,C})^T Uhat_{K,C}^T, X_KK = Dt_K^{-1} - Uhat_{K,C}
  * X_{C,K} without symmetrization; the first panel set receives X_KK and
  * X_{C,K}, the second X_KK^T and X_{K,C}^T.
+ * Under SELINV_SCHED_LEVELS a batch of two or more matrices runs as two
+ * halves, matrices [0, ceil(batch/2)) on `stream` and the rest on a second
+ * stream of the context (default priority; created with a fork and a join
+ * event on the first such call, on the current device, destroyed by
+ * selinv_destroy; a context used this way stays on that device, ESTATE
+ * otherwise): the second stream starts after the work already enqueued on
+ * `stream`, and `stream` waits for it before any later work, so the call's
+ * ordering is that of a single-stream launch.  The halves touch disjoint
+ * per-matrix data; the results are those of a single launch, bit for bit.
+ * A traced run (selinv_trace) keeps one stream.  EDEVICE when the stream or
+ * events cannot be created.
  */
 selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, void *work_dev, void *stream);
 
@@ -275,7 +286,8 @@ selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, voi
  * are normalized on `stream` (their Dt^{-1} blocks on a second stream of the
  * context, at the same time as their Lhat) and their depths traversed there,
  * while the other nodes are normalized on a third stream of the context; the
- * traversal waits for that stream before its first deeper depth.  The two
+ * traversal waits for that stream before its first deeper depth (the two
+ * halves of a batch, as in selinv_run, each wait for it).  The two
  * streams (default priority) and four events are created on the first call,
  * on the current device, and destroyed by selinv_destroy; a context used
  * this way stays on that device (ESTATE otherwise).  Everything is ordered

@@ -101,7 +101,7 @@ struct HostPlan {
     int64_t node_s, node_c, node_off, node_rowptr, node_sq, node_first, node_poff, kcol, kpos, posarr, items, item_ptr,
         nph, node_split, node_kchunk, node_yoff, node_goff, node_ldg, node_parent, order, lvl_items, lvl_recs, chunks, chunks_narrow, rblocks, small_nodes,
         sq_tiles, tiny, toff,
-        apos, adiag, aflip, bitems, pushrecs, y128recs, fac_nodes, fac_cn, fac_cw, fac_rb, fac_tiles, dpos, plan, linv, dinv, part, gbuf, ypart,
+        apos, adiag, aflip, bitems, pushrecs, y128recs, fac_nodes, fac_cn, fac_cw, fac_rb, fac_tiles, dpos, plan, plan2, linv, dinv, part, gbuf, ypart,
         cnt, ctrl, fwd_end, adj_z, adj_l, adj_s, adj_t, adj_f, adj_d, ferr, fldet, end;
   } off{};
   int64_t tables_bytes = 0;  // [0, tables_bytes) is uploaded once
@@ -901,6 +901,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   o.dpos = take(8 * (int64_t)H.dpos.size());
   H.tables_bytes = p;
   o.plan = take((int64_t)sizeof(DevPlan));
+  o.plan2 = take((int64_t)sizeof(DevPlan));  // the plan of the second half of the batch (see batch_half)
   o.linv = take(scalar_bytes * batch * H.sq_elems * (H.lu ? 2 : 1));  // LU: L_KK^{-1}, then U_KK^{-T}
   o.dinv = take(scalar_bytes * batch * S.n);
   o.part = take(scalar_bytes * batch * H.part_elems);
@@ -955,6 +956,7 @@ struct selinv_ctx {
   size_t pinned_bytes = 0;
   int64_t wall_khz = 0;
   DevPlan plan_host{};  // staging of the plan copy in the work buffer
+  DevPlan plan2_host{};  // and of the second half's plan
   void *trace = nullptr;  // optional device trace buffer for the persistent schedule
   int grid = 0;
   // cached strings for views
@@ -964,15 +966,20 @@ struct selinv_ctx {
   hipEvent_t ev_fork = nullptr, ev_inv = nullptr, ev_sq = nullptr;
   std::vector<hipEvent_t> ev_chunk;  // one per normalization chunk after the top one
   int side_device = -1;
+  // the second half of the batch's traversal under the level schedule, and its events
+  hipStream_t tst = nullptr;
+  hipEvent_t ev_tfork = nullptr, ev_tjoin = nullptr;
+  int tst_device = -1;
 
   ~selinv_ctx() {
     if (pinned) (void)hipHostFree(pinned);
-    for (hipEvent_t ev : {ev_fork, ev_inv, ev_sq})
+    for (hipEvent_t ev : {ev_fork, ev_inv, ev_sq, ev_tfork, ev_tjoin})
       if (ev) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : ev_chunk)
       if (ev) (void)hipEventDestroy(ev);
     if (side) (void)hipStreamDestroy(side);
     if (side2) (void)hipStreamDestroy(side2);
+    if (tst) (void)hipStreamDestroy(tst);
   }
   bool is_complex() const { return opts.dtype == SELINV_C128 || opts.dtype == SELINV_H128; }
   bool is_herm() const { return opts.dtype == SELINV_H128; }
@@ -1078,6 +1085,67 @@ const DevPlan *dev_plan(const selinv_ctx *h, void *work) {
   return reinterpret_cast<const DevPlan *>(static_cast<unsigned char *>(work) + h->H.off.plan);
 }
 
+// The plan of matrices [bh, batch) seen as a batch of their own: the
+// per-matrix work arrays the traversal kernels reach through the plan start
+// at matrix bh (the panels, X and the GEMM-2 partials are kernel arguments).
+DevPlan half_plan(const DevPlan &pl, int64_t bh, int64_t sbytes) {
+  DevPlan b = pl;
+  b.batch = pl.batch - bh;
+  b.part = static_cast<unsigned char *>(pl.part) + bh * pl.part_elems * sbytes;
+  b.gbuf = static_cast<unsigned char *>(pl.gbuf) + bh * pl.g_elems * sbytes;
+  b.ypart = static_cast<unsigned char *>(pl.ypart) + bh * pl.y_elems * sbytes;
+  return b;
+}
+
+// Under the level schedule a batch runs as two halves, matrices [0, bh) on
+// the caller's stream and [bh, batch) on a second stream: the halves share
+// no data, and the launches of each fill the other's launch tails.  0: one
+// stream (other schedules, a single matrix, or a traced run, whose trace rows
+// are laid out for one launch over the whole batch).
+int64_t batch_half(const selinv_ctx *h) {
+  const int64_t B = h->opts.batch;
+  return h->opts.sched == SELINV_SCHED_LEVELS && B >= 2 && !h->trace ? (B + 1) / 2 : 0;
+}
+
+// The second traversal stream and its fork and join events (all or nothing).
+selinv_status ensure_tstream(selinv_ctx *h) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_err(h, e, "hipGetDevice");
+  if (h->tst) return h->tst_device == dev ? SELINV_OK : set_err(h, SELINV_ESTATE, "context used on another device");
+  hipStream_t s = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (s) (void)hipStreamDestroy(s);
+    return hip_err(h, e, "traversal stream and events");
+  }
+  h->tst = s;
+  h->ev_tfork = a;
+  h->ev_tjoin = b;
+  h->tst_device = dev;
+  return SELINV_OK;
+}
+
+// Level launches [q0, q1) of both halves of the batch (bh > 0): the first
+// half on st, the second on the traversal stream with the second half's plan.
+hipError_t launch_halves(const selinv_ctx *h, const DevPlan &pl, const LaunchAux &aux, void *work, const void *panels,
+                         void *x, hipStream_t st, int q0, int q1, int64_t bh) {
+  DevPlan a = pl;
+  a.batch = bh;
+  hipError_t e = launch_run(a, dev_plan(h, work), aux, h->is_complex(), h->opts.sched, panels, x, 0, h->grid, st, q0, q1);
+  if (e != hipSuccess) return e;
+  const DevPlan b = half_plan(pl, bh, h->sbytes());
+  const int64_t off = bh * pl.panel_elems * h->sbytes();
+  const DevPlan *db = reinterpret_cast<const DevPlan *>(static_cast<unsigned char *>(work) + h->H.off.plan2);
+  return launch_run(b, db, aux, h->is_complex(), h->opts.sched, static_cast<const unsigned char *>(panels) + off,
+                    static_cast<unsigned char *>(x) + off, 0, h->grid, h->tst, q0, q1);
+}
+
 FactorAux make_fac_aux(const selinv_ctx *h, void *work) {
   const auto &H = h->H;
   unsigned char *b = static_cast<unsigned char *>(work);
@@ -1178,6 +1246,10 @@ selinv_status ensure_uploaded(selinv_ctx *h, void *work, hipStream_t st) {
   if (e != hipSuccess) return hip_err(h, e, "table upload");
   h->plan_host = make_devplan(h, work);
   e = hipMemcpyAsync(static_cast<unsigned char *>(work) + h->H.off.plan, &h->plan_host, sizeof(DevPlan),
+                     hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_err(h, e, "plan upload");
+  h->plan2_host = half_plan(h->plan_host, (h->plan_host.batch + 1) / 2, h->sbytes());
+  e = hipMemcpyAsync(static_cast<unsigned char *>(work) + h->H.off.plan2, &h->plan2_host, sizeof(DevPlan),
                      hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_err(h, e, "plan upload");
   e = hipStreamSynchronize(st);
@@ -1488,9 +1560,24 @@ selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, voi
   hipError_t e;
   DevPlan pl = make_devplan(h, work_dev);
   LaunchAux aux = make_aux(h, work_dev);
-  e = launch_run(pl, dev_plan(h, work_dev), aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, budget, h->grid,
-                 st, 0, aux.nlvl);
-  if (e != hipSuccess) return hip_err(h, e, "selinv launch");
+  const int64_t bh = batch_half(h);
+  if (bh > 0) {
+    ss = ensure_tstream(h);
+    if (ss != SELINV_OK) return ss;
+    e = hipEventRecord(h->ev_tfork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(h->tst, h->ev_tfork, 0);
+    if (e == hipSuccess) e = launch_halves(h, pl, aux, work_dev, panels_dev, x_dev, st, 0, aux.nlvl, bh);
+    if (e == hipSuccess) e = hipEventRecord(h->ev_tjoin, h->tst);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, h->ev_tjoin, 0);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(h->tst);
+      return hip_err(h, e, "selinv launch");
+    }
+  } else {
+    e = launch_run(pl, dev_plan(h, work_dev), aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, budget, h->grid,
+                   st, 0, aux.nlvl);
+    if (e != hipSuccess) return hip_err(h, e, "selinv launch");
+  }
   h->run_gen = h->gen;
   h->x_at = x_dev;
   h->ctrl_at = static_cast<unsigned char *>(work_dev) + h->H.off.ctrl;
@@ -1539,11 +1626,17 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
     h->ev_chunk.assign(ev.begin() + 3, ev.end());
     h->side_device = dev;
   }
+  const int64_t bh = batch_half(h);
+  if (bh > 0) {
+    ss = ensure_tstream(h);
+    if (ss != SELINV_OK) return ss;
+  }
   // on a failure after the fork, the side streams are drained before
   // returning, so that no work of this call still writes the caller's buffers
   auto fail = [&](hipError_t err, const char *what) {
     (void)hipStreamSynchronize(h->side);
     (void)hipStreamSynchronize(h->side2);
+    if (bh > 0) (void)hipStreamSynchronize(h->tst);
     return hip_err(h, err, what);
   };
   DevPlan pl = make_devplan(h, work_dev);
@@ -1571,15 +1664,26 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
   if (e != hipSuccess) return fail(e, "normalize launch");
   note_normalized(h, panels_dev, dtilde_dev);
   // the traversal of a chunk's depths (Alg. 1 steps 3-4 of its nodes need only
-  // their own normalization and the ancestors' X) waits for that chunk alone
-  e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, aux.lvl_cut[0],
-                 aux.lvl_cut[1]);
+  // their own normalization and the ancestors' X) waits for that chunk alone;
+  // the second half of the batch follows the top nodes' normalization on the
+  // traversal stream and waits for the same chunk events
+  auto trav = [&](int q0, int q1) {
+    return bh > 0 ? launch_halves(h, pl, aux, work_dev, panels_dev, x_dev, st, q0, q1, bh)
+                  : launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, q0, q1);
+  };
+  if (bh > 0) {
+    e = hipEventRecord(h->ev_tfork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(h->tst, h->ev_tfork, 0);
+    if (e != hipSuccess) return fail(e, "traversal fork");
+  }
+  e = trav(aux.lvl_cut[0], aux.lvl_cut[1]);
   for (int q = 1; q < nq && e == hipSuccess; ++q) {
     e = hipStreamWaitEvent(st, h->ev_chunk[q - 1], 0);
-    if (e == hipSuccess)
-      e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, aux.lvl_cut[q],
-                     aux.lvl_cut[q + 1]);
+    if (e == hipSuccess && bh > 0) e = hipStreamWaitEvent(h->tst, h->ev_chunk[q - 1], 0);
+    if (e == hipSuccess) e = trav(aux.lvl_cut[q], aux.lvl_cut[q + 1]);
   }
+  if (e == hipSuccess && bh > 0) e = hipEventRecord(h->ev_tjoin, h->tst);
+  if (e == hipSuccess && bh > 0) e = hipStreamWaitEvent(st, h->ev_tjoin, 0);
   if (e != hipSuccess) return fail(e, "selinv launch");
   h->run_gen = h->gen;
   h->x_at = x_dev;
