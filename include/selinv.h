@@ -273,8 +273,11 @@ selinv_status selinv_factor_device(selinv_ctx *h, const void *values_dev, void *
  * `stream`, and `stream` waits for it before any later work, so the call's
  * ordering is that of a single-stream launch.  The halves touch disjoint
  * per-matrix data; the results are those of a single launch, bit for bit.
- * A traced run (selinv_trace) keeps one stream.  EDEVICE when the stream or
- * events cannot be created.
+ * A single-matrix plan runs the two subtree groups below the top chain of
+ * the tree (selinv_items which = 4) the same way, group 1 on `stream` and
+ * group 2 on the second stream, each group's dense X_{C,C} buffers in a
+ * region of their own.  A traced run (selinv_trace) keeps one stream.
+ * EDEVICE when the stream or events cannot be created.
  */
 selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, void *work_dev, void *stream);
 
@@ -420,6 +423,15 @@ selinv_status selinv_trace(selinv_ctx *h, void *trace_dev);
  *     schedule), in order: {first level launch, its etree depth,
  *     normalization work entries of the chunk, 0}.  Chunk 0 is the top
  *     depths; the traversal of a chunk's depths waits for that chunk only.
+ *   which = 4: the subtree groups of a single-matrix level plan, in launch
+ *     order: {group (1 or 2), level launch, first position, end position},
+ *     the positions indexing the launch list of which = 2.  From the roots
+ *     down, the nodes with one child each form the top chain; the subtrees
+ *     under it are dealt to two groups of about equal work, and every launch
+ *     below the chain is one or more ranges of one group each.  selinv_run
+ *     and selinv_normalize_run run the chain on `stream`, then group 1 there
+ *     and group 2 on the context's second stream (as for the halves of a
+ *     batch); empty for other plans.
  * Errors: SELINV_EINVAL for another `which`.
  */
 selinv_status selinv_items(const selinv_ctx *h, int32_t which, const int32_t **items, int64_t *n);

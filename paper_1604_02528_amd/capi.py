@@ -229,7 +229,8 @@ def selinv_items(h, which=0):
     """Host copy of the work items, int32 [n, 4] rows {K, type, a, b}
     (which = 0: the forward traversal, 1: the adjoint in launch order, 2: the
     forward level launches {kind, items per matrix, first item type, depth},
-    3: the normalization chunks {first level launch, depth, entries, 0})."""
+    3: the normalization chunks {first level launch, depth, entries, 0},
+    4: the subtree group ranges {group, level launch, first, end})."""
     import numpy as np
 
     p = _P32()

@@ -24,6 +24,8 @@ hipError_t launch_normalize(const DevPlan &pl, const DevPlan *dpl, const LaunchA
                             void *panels, void *dt, hipStream_t st, int part, int steps);
 hipError_t launch_run(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, int sched,
                       const void *panels, void *x, int64_t budget_ticks, int grid, hipStream_t st, int q0, int q1);
+hipError_t launch_level_range(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, const void *panels,
+                              void *x, hipStream_t st, int q, int32_t b, int32_t e);
 hipError_t launch_extract(const DevPlan &pl, const DevPlan *dpl, bool cplx_, const void *x, void *out, hipStream_t st);
 int persistent_blocks_per_cu(bool cplx_);
 hipError_t launch_backward(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx, const void *panels,
@@ -78,6 +80,12 @@ struct HostPlan {
   std::vector<int32_t> lvl_depth_first;  // [depth + 1] first level launch of each etree depth (level schedule)
   // normalization chunks (see LaunchAux): level launch and list boundaries
   std::vector<int32_t> lvl_cut, norm_cut;
+  // single-matrix level plans: the subtrees under the top chain of the tree
+  // in two groups that run on two streams (see subtree_groups)
+  std::vector<int8_t> node_grp;   // 0: a node of the top chain (or no split); 1, 2: its subtree's group
+  int32_t grp_q = -1;             // first level launch below the chain (-1: no split)
+  std::vector<int32_t> grp_rptr;  // [nlvl + 1]: the group ranges of launch q
+  std::vector<int4> grp_ranges;   // {group, launch, first position, end position}
   std::vector<LRec> lvl_recs;  // the items of lvl_items with their nodes, in level order
   std::vector<TinyRec> tiny;  // single-wavefront nodes, in launch order
   std::vector<PushRec> push;  // push-form tiles (SELINV_SCHED_PUSH), in launch order
@@ -259,8 +267,16 @@ void ticket_order(const Symbolic &S, HostPlan &H, int64_t batch) {
 // pref[K] (from a tune table): -1 = by the threshold, 0 = never, 1 = from
 // c >= 65 on; the forced ones are thinned by their own doubling threshold
 // when the buffers do not fit.
+// Dense X_{C,C} buffers.  Under the level schedule the buffers of one
+// depth share a region with those of every other depth (a depth's gathers
+// start after the previous depth is done); with subtree groups (node_grp),
+// group 2 gets a region of its own, since the groups run on two streams and
+// reach their depths at different times (the top chain runs before both).
 void choose_dense(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t min_c, int64_t max_bytes,
                   bool per_level, const std::vector<int8_t> &pref, HostPlan &H) {
+  const bool two = per_level && !H.node_grp.empty();
+  auto key = [&](int64_t K) { return per_level ? 2 * S.sdepth[K] + (two && H.node_grp[K] == 2 ? 1 : 0) : int64_t(0); };
+  const int64_t nkeys = per_level ? 2 * S.depth : 1;
   const int64_t ns = S.nsuper();
   H.node_goff.assign(ns, -1);
   H.node_ldg.assign(ns, 0);
@@ -272,11 +288,18 @@ void choose_dense(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_
     const int64_t c = S.nrows(K);
     return pref[K] == 0 ? false : pref[K] == 1 ? c >= tf : c >= t;
   };
-  auto footprint = [&](int64_t t, int64_t tf) {
-    std::vector<int64_t> per(per_level ? S.depth : 1, 0);
+  // the largest depth of each region (even keys: the first, odd: group 2's)
+  auto regions = [&](int64_t t, int64_t tf) {
+    std::vector<int64_t> per(nkeys, 0);
     for (int64_t K = 0; K < ns; ++K)
-      if (wants(K, t, tf)) per[per_level ? S.sdepth[K] : 0] += ldg_of(S.nrows(K)) * S.nrows(K);
-    return *std::max_element(per.begin(), per.end());
+      if (wants(K, t, tf)) per[key(K)] += ldg_of(S.nrows(K)) * S.nrows(K);
+    std::pair<int64_t, int64_t> m{0, 0};
+    for (int64_t k = 0; k < nkeys; ++k) (k & 1 ? m.second : m.first) = std::max(k & 1 ? m.second : m.first, per[k]);
+    return m;
+  };
+  auto footprint = [&](int64_t t, int64_t tf) {
+    const auto m = regions(t, tf);
+    return m.first + m.second;
   };
   int64_t t = t0, tf = kTileM + 1;
   while (true) {
@@ -287,16 +310,61 @@ void choose_dense(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_
     tf *= 2;
   }
   H.dense_min_c = t;
-  std::vector<int64_t> next(per_level ? S.depth : 1, 0);
+  const int64_t base2 = regions(t, tf).first;  // group 2's region starts after the first
+  std::vector<int64_t> next(nkeys, 0);
+  for (int64_t k = 1; k < nkeys; k += 2) next[k] = base2;
   for (int64_t K = 0; K < ns; ++K) {
     const int64_t c = S.nrows(K);
     if (!wants(K, t, tf)) continue;
-    int64_t &o = next[per_level ? S.sdepth[K] : 0];
+    int64_t &o = next[key(K)];
     H.node_goff[K] = o;
     H.node_ldg[K] = (int32_t)ldg_of(c);
     o += ldg_of(c) * c;
     H.g_elems = std::max(H.g_elems, o);
   }
+}
+
+// Subtree groups of a single-matrix level plan: from the roots down, the
+// nodes with exactly one child form the top chain (group 0); the subtrees
+// under it are independent (a node's X needs only its ancestors' X), so they
+// are dealt, largest first by the work of GEMM-1 and GEMM-2, to two groups of
+// about equal work, which run on two streams after the chain (the launches of
+// one fill the other's launch tails).  Returns the depth of the subtree roots,
+// or -1 (a chain only, or fewer than two subtrees).
+int64_t subtree_groups(const Symbolic &S, HostPlan &H) {
+  const int64_t ns = S.nsuper();
+  H.node_grp.assign(ns, 0);
+  std::vector<std::vector<int64_t>> kids(ns);
+  std::vector<int64_t> front;
+  for (int64_t K = 0; K < ns; ++K)
+    if (S.sparent[K] < 0)
+      front.push_back(K);
+    else
+      kids[S.sparent[K]].push_back(K);
+  while (front.size() == 1) front = kids[front[0]];
+  if (front.size() < 2) {
+    H.node_grp.clear();
+    return -1;
+  }
+  std::vector<int64_t> byd(ns);  // nodes by depth, root first
+  for (int64_t K = 0; K < ns; ++K) byd[K] = K;
+  std::stable_sort(byd.begin(), byd.end(), [&](int64_t a, int64_t b) { return S.sdepth[a] < S.sdepth[b]; });
+  std::vector<double> work(ns, 0.0);  // subtree work, leaves up
+  for (int64_t i = ns - 1; i >= 0; --i) {
+    const int64_t K = byd[i];
+    const double c = (double)S.nrows(K), s = (double)S.width(K);
+    work[K] += c * c * s + c * s * s;
+    if (S.sparent[K] >= 0) work[S.sparent[K]] += work[K];
+  }
+  std::stable_sort(front.begin(), front.end(), [&](int64_t a, int64_t b) { return work[a] > work[b]; });
+  double w1 = 0, w2 = 0;
+  for (int64_t K : front) {
+    H.node_grp[K] = w1 <= w2 ? 1 : 2;
+    (w1 <= w2 ? w1 : w2) += work[K];
+  }
+  for (int64_t K : byd)  // top down
+    if (H.node_grp[K] == 0 && S.sparent[K] >= 0) H.node_grp[K] = H.node_grp[S.sparent[K]];
+  return S.sdepth[front[0]];
 }
 
 void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t dense_min_c, int64_t dense_max_bytes,
@@ -420,6 +488,9 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     }
   }
   // work items, phase by phase (see plan.hpp)
+  H.node_grp.clear();
+  H.grp_q = -1;
+  const int64_t grp_depth = sched == SELINV_SCHED_LEVELS && batch == 1 ? subtree_groups(S, H) : -1;
   choose_dense(S, batch, scalar_bytes, dense_min_c, dense_max_bytes, per_level, dense_pref, H);
   // GEMM-2 shares of the R items: a depth whose R tiles (over the batch)
   // cannot fill the GPU cuts each tile's share into rq items by 64-row blocks
@@ -580,6 +651,9 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     };
     std::vector<std::vector<int64_t>> bydepth(S.depth);
     for (int64_t K = 0; K < ns; ++K) bydepth[S.sdepth[K]].push_back(K);
+    if (!H.node_grp.empty())  // group 1's nodes before group 2's at every depth: each launch is two ranges
+      for (auto &v : bydepth)
+        std::stable_sort(v.begin(), v.end(), [&](int64_t a, int64_t b) { return H.node_grp[a] < H.node_grp[b]; });
     H.lvl_depth_first.assign(S.depth + 1, 0);
     for (int64_t d = 0; d < S.depth; ++d) {
       H.lvl_depth_first[d] = (int32_t)H.lvl_ptr.size() - 1;
@@ -640,6 +714,32 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
     }
     H.lvl_depth_first[S.depth] = (int32_t)H.lvl_ptr.size() - 1;
     H.tiny_dptr[S.depth] = (int32_t)H.tiny.size();
+    // the group ranges of every launch below the chain (maximal runs of one
+    // group; a single-wavefront launch lists its adjoint nodes first, so it
+    // can hold two runs of each group)
+    const int32_t nl = (int32_t)H.lvl_ptr.size() - 1;
+    H.grp_rptr.assign(nl + 1, 0);
+    H.grp_ranges.clear();
+    if (grp_depth >= 0) {
+      H.grp_q = H.lvl_depth_first[grp_depth];
+      for (int32_t q = 0; q < nl; ++q) {
+        H.grp_rptr[q] = (int32_t)H.grp_ranges.size();
+        if (q < H.grp_q) continue;
+        const int32_t b = H.lvl_ptr[q], e = H.lvl_ptr[q + 1];
+        auto grp_at = [&](int32_t pos) {
+          const int32_t K = H.lvl_kind[q] == LVL_Y128 ? H.y128[H.lvl_items[pos]].K : H.items[H.lvl_items[pos]].K;
+          return (int32_t)H.node_grp[K];
+        };
+        for (int32_t p0 = b; p0 < e;) {
+          const int32_t g = grp_at(p0);
+          int32_t p1 = p0 + 1;
+          while (p1 < e && grp_at(p1) == g) ++p1;
+          H.grp_ranges.push_back(int4{g, q, p0, p1});
+          p0 = p1;
+        }
+      }
+      H.grp_rptr[nl] = (int32_t)H.grp_ranges.size();
+    }
   }
   H.lvl_recs.resize(H.lvl_items.size());
   for (size_t q = 0; q < H.lvl_items.size(); ++q) {
@@ -1131,6 +1231,36 @@ selinv_status ensure_tstream(selinv_ctx *h) {
   return SELINV_OK;
 }
 
+// A single-matrix level plan with subtree groups runs them on two streams:
+// the launches above the groups on st, then (after a fork event) group 1's
+// ranges on st and group 2's on the traversal stream.  No split for a traced
+// run (its trace rows are laid out for one stream).
+bool use_groups(const selinv_ctx *h) { return h->H.grp_q >= 0 && !h->trace; }
+
+// Level launches [q0, q1) of a plan with subtree groups; `forked` records
+// whether the traversal stream has been forked off st (once, at the first
+// launch below the chain).
+hipError_t launch_groups(selinv_ctx *h, const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const void *panels,
+                         void *x, hipStream_t st, int q0, int q1, bool &forked) {
+  const HostPlan &H = h->H;
+  const int qs = std::min(q1, std::max(q0, H.grp_q));
+  hipError_t e = hipSuccess;
+  if (qs > q0) e = launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels, x, 0, h->grid, st, q0, qs);
+  for (int q = qs; q < q1 && e == hipSuccess; ++q) {
+    if (!forked) {
+      e = hipEventRecord(h->ev_tfork, st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(h->tst, h->ev_tfork, 0);
+      if (e != hipSuccess) break;
+      forked = true;
+    }
+    for (int32_t r = H.grp_rptr[q]; r < H.grp_rptr[q + 1] && e == hipSuccess; ++r) {
+      const int4 g = H.grp_ranges[r];
+      e = launch_level_range(pl, dpl, aux, h->is_complex(), panels, x, g.x == 2 ? h->tst : st, q, g.z, g.w);
+    }
+  }
+  return e;
+}
+
 // Level launches [q0, q1) of both halves of the batch (bh > 0): the first
 // half on st, the second on the traversal stream with the second half's plan.
 hipError_t launch_halves(const selinv_ctx *h, const DevPlan &pl, const LaunchAux &aux, void *work, const void *panels,
@@ -1573,6 +1703,17 @@ selinv_status selinv_run(selinv_ctx *h, const void *panels_dev, void *x_dev, voi
       (void)hipStreamSynchronize(h->tst);
       return hip_err(h, e, "selinv launch");
     }
+  } else if (use_groups(h)) {
+    ss = ensure_tstream(h);
+    if (ss != SELINV_OK) return ss;
+    bool forked = false;
+    e = launch_groups(h, pl, dev_plan(h, work_dev), aux, panels_dev, x_dev, st, 0, aux.nlvl, forked);
+    if (e == hipSuccess && forked) e = hipEventRecord(h->ev_tjoin, h->tst);
+    if (e == hipSuccess && forked) e = hipStreamWaitEvent(st, h->ev_tjoin, 0);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(h->tst);
+      return hip_err(h, e, "selinv launch");
+    }
   } else {
     e = launch_run(pl, dev_plan(h, work_dev), aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, budget, h->grid,
                    st, 0, aux.nlvl);
@@ -1627,16 +1768,18 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
     h->side_device = dev;
   }
   const int64_t bh = batch_half(h);
-  if (bh > 0) {
+  const bool groups = bh == 0 && use_groups(h);
+  if (bh > 0 || groups) {
     ss = ensure_tstream(h);
     if (ss != SELINV_OK) return ss;
   }
+  bool forked = false;  // the traversal stream has been forked off `stream`
   // on a failure after the fork, the side streams are drained before
   // returning, so that no work of this call still writes the caller's buffers
   auto fail = [&](hipError_t err, const char *what) {
     (void)hipStreamSynchronize(h->side);
     (void)hipStreamSynchronize(h->side2);
-    if (bh > 0) (void)hipStreamSynchronize(h->tst);
+    if (bh > 0 || groups) (void)hipStreamSynchronize(h->tst);
     return hip_err(h, err, what);
   };
   DevPlan pl = make_devplan(h, work_dev);
@@ -1668,22 +1811,24 @@ selinv_status selinv_normalize_run(selinv_ctx *h, const void *ldlt_dev, void *pa
   // the second half of the batch follows the top nodes' normalization on the
   // traversal stream and waits for the same chunk events
   auto trav = [&](int q0, int q1) {
-    return bh > 0 ? launch_halves(h, pl, aux, work_dev, panels_dev, x_dev, st, q0, q1, bh)
-                  : launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, q0, q1);
+    if (bh > 0) return launch_halves(h, pl, aux, work_dev, panels_dev, x_dev, st, q0, q1, bh);
+    if (groups) return launch_groups(h, pl, dpl, aux, panels_dev, x_dev, st, q0, q1, forked);
+    return launch_run(pl, dpl, aux, h->is_complex(), h->opts.sched, panels_dev, x_dev, 0, h->grid, st, q0, q1);
   };
   if (bh > 0) {
     e = hipEventRecord(h->ev_tfork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(h->tst, h->ev_tfork, 0);
     if (e != hipSuccess) return fail(e, "traversal fork");
+    forked = true;
   }
   e = trav(aux.lvl_cut[0], aux.lvl_cut[1]);
   for (int q = 1; q < nq && e == hipSuccess; ++q) {
     e = hipStreamWaitEvent(st, h->ev_chunk[q - 1], 0);
-    if (e == hipSuccess && bh > 0) e = hipStreamWaitEvent(h->tst, h->ev_chunk[q - 1], 0);
+    if (e == hipSuccess && forked) e = hipStreamWaitEvent(h->tst, h->ev_chunk[q - 1], 0);
     if (e == hipSuccess) e = trav(aux.lvl_cut[q], aux.lvl_cut[q + 1]);
   }
-  if (e == hipSuccess && bh > 0) e = hipEventRecord(h->ev_tjoin, h->tst);
-  if (e == hipSuccess && bh > 0) e = hipStreamWaitEvent(st, h->ev_tjoin, 0);
+  if (e == hipSuccess && forked) e = hipEventRecord(h->ev_tjoin, h->tst);
+  if (e == hipSuccess && forked) e = hipStreamWaitEvent(st, h->ev_tjoin, 0);
   if (e != hipSuccess) return fail(e, "selinv launch");
   h->run_gen = h->gen;
   h->x_at = x_dev;
@@ -1903,6 +2048,40 @@ selinv_status selinv_check_plan(const selinv_ctx *hc) {
         if (nchunk[K] > q)
           return set_err(h, SELINV_EINVAL, "plan check: a level launch runs before its node is normalized", K, q);
       }
+  // Subtree groups: the launches above the groups hold chain nodes only; the
+  // ranges of every later launch cover it in order, each range one group
+  // (1 or 2) that all its items belong to; and no node has an ancestor in
+  // the other group, so the two streams share no X.
+  if (H.grp_q >= 0) {
+    const int32_t nl = (int32_t)H.lvl_ptr.size() - 1;
+    auto node_at = [&](int32_t lv, int32_t r) -> int64_t {
+      return H.lvl_kind[lv] == LVL_Y128 ? H.y128[H.lvl_items[r]].K : H.items[H.lvl_items[r]].K;
+    };
+    for (int32_t lv = 0; lv < nl; ++lv) {
+      if (lv < H.grp_q) {
+        for (int32_t r = H.lvl_ptr[lv]; r < H.lvl_ptr[lv + 1]; ++r)
+          if (H.node_grp[node_at(lv, r)] != 0)
+            return set_err(h, SELINV_EINVAL, "plan check: a launch above the subtree groups runs a group's node", lv, r);
+        continue;
+      }
+      int32_t pos = H.lvl_ptr[lv];
+      for (int32_t i = H.grp_rptr[lv]; i < H.grp_rptr[lv + 1]; ++i) {
+        const int4 g = H.grp_ranges[i];
+        if (g.y != lv || g.z != pos || g.w <= g.z || (g.x != 1 && g.x != 2))
+          return set_err(h, SELINV_EINVAL, "plan check: subtree group ranges do not tile their launch", lv, i);
+        for (int32_t r = g.z; r < g.w; ++r)
+          if (H.node_grp[node_at(lv, r)] != g.x)
+            return set_err(h, SELINV_EINVAL, "plan check: an item outside its range's group", lv, r);
+        pos = g.w;
+      }
+      if (pos != H.lvl_ptr[lv + 1])
+        return set_err(h, SELINV_EINVAL, "plan check: subtree group ranges do not cover their launch", lv, pos);
+    }
+    for (int64_t K = 0; K < ns; ++K)
+      for (int64_t J = S.sparent[K]; J >= 0; J = S.sparent[J])
+        if (H.node_grp[J] != 0 && H.node_grp[J] != H.node_grp[K])
+          return set_err(h, SELINV_EINVAL, "plan check: a node with an ancestor in the other subtree group", K, J);
+  }
   return SELINV_OK;
 }
 
@@ -1959,10 +2138,17 @@ selinv_status selinv_items(const selinv_ctx *hc, int32_t which, const int32_t **
     *n = (int64_t)h->nseq.size();
     return SELINV_OK;
   }
+  if (which == 4) {
+    // the subtree group ranges of a single-matrix level plan: {group, level
+    // launch, first position, end position} (none without groups)
+    *items = reinterpret_cast<const int32_t *>(h->H.grp_ranges.data());
+    *n = (int64_t)h->H.grp_ranges.size();
+    return SELINV_OK;
+  }
   if (which != 1)
     return set_err(h, SELINV_EINVAL,
-                   "selinv_items: which must be 0 (forward), 1 (adjoint), 2 (level launches) or 3 (normalization "
-                   "chunks)");
+                   "selinv_items: which must be 0 (forward), 1 (adjoint), 2 (level launches), 3 (normalization "
+                   "chunks) or 4 (subtree group ranges)");
   // the adjoint's launches in order, a small-node launch expanded into one
   // row per node
   if (h->bseq.empty()) {

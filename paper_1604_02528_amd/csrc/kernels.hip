@@ -959,6 +959,41 @@ hipError_t launch_normalize(const DevPlan &pl, const DevPlan *dpl, const LaunchA
                : normalize_impl<double>(pl, dpl, aux, src, panels, dt, st, part, steps);
 }
 
+// Positions [b, e) of level launch q (a sub-range of [lvl_ptr[q],
+// lvl_ptr[q + 1]): the records of a single-wavefront, push or 128-tile launch
+// are laid out in the launch's order, so a sub-range starts b - lvl_ptr[q]
+// records in).
+template <typename T>
+static void launch_level(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const T *Lp, T *Xp, T *Pp,
+                         hipStream_t st, int q, int32_t b, int32_t e) {
+  if (e <= b) return;
+  if (aux.lvl_kind[q] == LVL_TINY)
+    hipLaunchKernelGGL((pl.csign < 0 ? k_tiny<T, true> : k_tiny<T, false>), dim3((unsigned)((e - b) * pl.batch)),
+                       dim3(64), 0, st, dpl, Lp, Xp,
+                       aux.tiny + aux.lvl_tiny[q] + (b - aux.lvl_ptr[q]), e - b, b);
+  else if (aux.lvl_kind[q] == LVL_PUSH)
+    hipLaunchKernelGGL(k_push<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp,
+                       aux.push + aux.lvl_tiny[q] + (b - aux.lvl_ptr[q]), e - b, b);
+  else if (aux.lvl_kind[q] == LVL_Y128) {
+    if constexpr (sizeof(T) == 8)
+      hipLaunchKernelGGL(k_ydense128, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl,
+                         reinterpret_cast<const double *>(Lp), reinterpret_cast<double *>(Xp),
+                         aux.y128 + aux.lvl_tiny[q] + (b - aux.lvl_ptr[q]), e - b, b);
+  } else if (aux.lvl_kind[q] == LVL_YDENSE)
+    hipLaunchKernelGGL(k_ydense<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,
+                       aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
+  else if (aux.lvl_kind[q] == LVL_GATHER)
+    hipLaunchKernelGGL((pl.half > 0 ? k_gather_list<T, true> : k_gather_list<T, false>),
+                       dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Xp, aux.lvl_recs + b,
+                       aux.lvl_items + b, e - b, b);
+  else if (aux.lvl_kind[q] == LVL_GEMM2)
+    hipLaunchKernelGGL(k_gemm2_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,
+                       aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
+  else
+    hipLaunchKernelGGL(k_items_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,
+                       aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
+}
+
 // Level launches [q0, q1) under the level schedule (the whole traversal
 // is [0, aux.nlvl)); the persistent schedule ignores the range.
 template <typename T>
@@ -974,39 +1009,23 @@ static hipError_t run_impl(const DevPlan &pl, const DevPlan *dpl, const LaunchAu
     hipLaunchKernelGGL(k_zero<T>, dim3(gz ? gz : 1), dim3(256), 0, st, dpl, Xp);
   }
   if (sched == 1 || sched == 2) {
-    for (int q = q0; q < q1; ++q) {
-      const int32_t b = aux.lvl_ptr[q], e = aux.lvl_ptr[q + 1];
-      if (e <= b) continue;
-      if (aux.lvl_kind[q] == LVL_TINY)
-        hipLaunchKernelGGL((pl.csign < 0 ? k_tiny<T, true> : k_tiny<T, false>), dim3((unsigned)((e - b) * pl.batch)),
-                           dim3(64), 0, st, dpl, Lp, Xp,
-                           aux.tiny + aux.lvl_tiny[q], e - b, b);
-      else if (aux.lvl_kind[q] == LVL_PUSH)
-        hipLaunchKernelGGL(k_push<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp,
-                           aux.push + aux.lvl_tiny[q], e - b, b);
-      else if (aux.lvl_kind[q] == LVL_Y128) {
-        if constexpr (sizeof(T) == 8)
-          hipLaunchKernelGGL(k_ydense128, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl,
-                             reinterpret_cast<const double *>(Lp), reinterpret_cast<double *>(Xp),
-                             aux.y128 + aux.lvl_tiny[q], e - b, b);
-      } else if (aux.lvl_kind[q] == LVL_YDENSE)
-        hipLaunchKernelGGL(k_ydense<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,
-                           aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
-      else if (aux.lvl_kind[q] == LVL_GATHER)
-        hipLaunchKernelGGL((pl.half > 0 ? k_gather_list<T, true> : k_gather_list<T, false>),
-                           dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Xp, aux.lvl_recs + b,
-                           aux.lvl_items + b, e - b, b);
-      else if (aux.lvl_kind[q] == LVL_GEMM2)
-        hipLaunchKernelGGL(k_gemm2_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,
-                           aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
-      else
-        hipLaunchKernelGGL(k_items_list<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp, Pp,
-                           aux.lvl_recs + b, aux.lvl_items + b, e - b, b);
-    }
+    for (int q = q0; q < q1; ++q) launch_level<T>(pl, dpl, aux, Lp, Xp, Pp, st, q, aux.lvl_ptr[q], aux.lvl_ptr[q + 1]);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_sched_init, dim3(256), dim3(256), 0, st, dpl);
   hipLaunchKernelGGL(k_persistent<T>, dim3((unsigned)grid), dim3(NT), 0, st, dpl, Lp, Xp, Pp, budget_ticks);
+  return hipGetLastError();
+}
+
+// Positions [b, e) of level launch q alone, on st (level schedule).
+hipError_t launch_level_range(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, bool cplx_, const void *panels,
+                              void *x, hipStream_t st, int q, int32_t b, int32_t e) {
+  if (cplx_)
+    launch_level<cplx>(pl, dpl, aux, reinterpret_cast<const cplx *>(panels), reinterpret_cast<cplx *>(x),
+                       reinterpret_cast<cplx *>(pl.part), st, q, b, e);
+  else
+    launch_level<double>(pl, dpl, aux, reinterpret_cast<const double *>(panels), reinterpret_cast<double *>(x),
+                         reinterpret_cast<double *>(pl.part), st, q, b, e);
   return hipGetLastError();
 }
 

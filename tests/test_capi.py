@@ -191,7 +191,7 @@ def test_adjoint_items_which_is_checked():
 
     S = _ctx(workload("C1"))
     with pytest.raises(capi.SelinvError) as ei:
-        capi.selinv_items(S.h, 4)
+        capi.selinv_items(S.h, 5)
     assert ei.value.status == 1
 
 
@@ -484,4 +484,4 @@ def test_normalization_chunks(name, scale, chunks):
     assert np.all(N[:, 2] >= 0)
     capi.selinv_check_plan(S.h)
     with pytest.raises(capi.SelinvError):
-        capi.selinv_items(S.h, 4)
+        capi.selinv_items(S.h, 5)

@@ -1,8 +1,9 @@
 """The level schedule runs a batch as two halves, matrices [0, ceil(B/2)) on
-the caller's stream and the rest on a second stream of the context.  The
-halves touch disjoint per-matrix data, so X is bit for bit that of the same
-plan launched on one stream (a traced run keeps one stream), for odd and even
-batches, through selinv_run and selinv_normalize_run, and matches the oracle."""
+the caller's stream and the rest on a second stream of the context, and a
+single matrix as its top chain followed by two subtree groups on the two
+streams.  Halves and groups touch disjoint data, so X is bit for bit that of
+the same plan launched on one stream (a traced run keeps one stream), through
+selinv_run and selinv_normalize_run, and matches the oracle."""
 
 import numpy as np
 import pytest
@@ -83,4 +84,30 @@ def test_halves_fp64_batch():
         err = maxrel(xa[l], ref)
         print(f"  matrix {l}: vs oracle {err:.3e}", flush=True)
         assert err <= TOL
+    S.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,scale", [("C2", 12), ("C2", None), ("C1", None), ("C3", 10), ("H3", 8), ("U3", 10)])
+def test_subtree_groups_match_one_stream_and_oracle(name, scale):
+    """Single-matrix plans: the ranges of selinv_items(which = 4) tile every
+    launch below the top chain, and the two-stream X equals the one-stream X
+    bit for bit and the oracle to 1e-10."""
+    from paper_1604_02528_amd import SelInv, capi
+
+    b = None if name in ("C1", "C2") else 1  # the oracle cache key of the other single-matrix tests
+    w = workload(name, scale, b)
+    print(f"subtree groups case {name} scale={scale}", flush=True)
+    S = SelInv(w.n, w.colptr, w.rowind, w.perm, dtype=w.dtype, batch=1, cap=w.cap, relax=0.05, adjoint=False)
+    R = capi.selinv_items(S.h, 4)
+    L = capi.selinv_items(S.h, 2)
+    assert len(R) > 0 and set(R[:, 0]) == {1, 2}
+    assert R[-1, 1] == len(L) - 1  # every launch below the chain has its ranges
+    S._alloc(False)
+    ldlt = torch.from_numpy(S.factor_host(w.values)).cuda()
+    xa, xb, xc = _run_three_ways(S, ldlt)
+    assert np.array_equal(xa, xb) and np.array_equal(xa, xc)
+    err = maxrel(xa, oracle_x(name, scale, b, 0.05))
+    print(f"  {len(R)} group ranges from launch {R[0, 1]}; two streams == one stream; vs oracle {err:.3e}", flush=True)
+    assert err <= TOL
     S.close()
