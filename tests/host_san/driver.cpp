@@ -24,6 +24,10 @@ hipError_t launch_normalize(const DevPlan &, const DevPlan *, const LaunchAux &,
                             hipStream_t, int, int) { return hipErrorNotSupported; }
 hipError_t launch_run(const DevPlan &, const DevPlan *, const LaunchAux &, bool, int, const void *, void *, int64_t, int,
                       hipStream_t, int, int) { return hipErrorNotSupported; }
+hipError_t launch_level_range(const DevPlan &, const DevPlan *, const LaunchAux &, bool, const void *, void *,
+                              hipStream_t, int, int32_t, int32_t) {
+  return hipErrorNotSupported;
+}
 hipError_t launch_extract(const DevPlan &, const DevPlan *, bool, const void *, void *, hipStream_t) {
   return hipErrorNotSupported;
 }
