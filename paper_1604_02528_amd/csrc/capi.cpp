@@ -71,6 +71,7 @@ struct HostPlan {
   bool adjoint = false;        // adjoint scratch allocated (opts.adjoint >= 0)
   bool lu = false;             // LU plan: two panel sets (L, U^T), gathered GEMM-1 tiles only
   std::vector<int32_t> lvl_items, lvl_ptr, lvl_tiny, lvl_kind;
+  std::vector<int32_t> lvl_tsplit;  // [nlvl]: a single-wavefront launch's first forward-only position (else -1)
   std::vector<int32_t> node_defer;  // GEMM-2 of the node in ITEM_P items (push schedule; level schedule: unsplit 128 x 128 tiles)
   std::vector<int32_t> node_ykern;  // GEMM-1 tiles in k_ydense (level schedule, dense buffer)
   std::vector<int8_t> node_y128;    // ... on 128 x 128 tiles in k_ydense128 (FP64, tune table)
@@ -586,13 +587,17 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   H.lvl_top = 0;
   H.lvl_tiny.clear();
   H.lvl_kind.clear();
+  H.lvl_tsplit.clear();
   H.tiny.clear();
   H.toff.clear();
   H.tiny_dptr.assign(S.depth + 1, 0);
   H.tiny_dadj.assign(S.depth, 0);
   // small nodes address X through 32-bit byte offsets
   const bool tiny_ok = !lu && S.panel_elems * scalar_bytes < (int64_t(1) << 32);
-  const int64_t tiny_cf = scalar_bytes == 8 ? kTinyCF : kTinyC;
+  // the forward sweep's single-wavefront nodes: c <= kTinyCF for FP64 and
+  // complex-symmetric plans, c <= kTinyC for Hermitian ones (the wider kernel
+  // reads X_{C,C} as stored, with no conjugated half)
+  const int64_t tiny_cf = herm ? kTinyC : kTinyCF;
   auto adj_tiny = [&](int64_t K) { return !push && tiny_ok && H.node_c[K] <= kTinyC && H.node_s[K] <= kTinyS; };
   H.push.clear();
   H.y128.clear();
@@ -612,6 +617,7 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
         H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
         H.lvl_tiny.push_back(-1);
         H.lvl_kind.push_back(LVL_ITEMS);
+        H.lvl_tsplit.push_back(-1);
       }
     };
     for (int64_t d = 0; d < S.depth; ++d) {
@@ -638,15 +644,18 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
         H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
         H.lvl_tiny.push_back(first);
         H.lvl_kind.push_back(LVL_PUSH);
+        H.lvl_tsplit.push_back(-1);
       }
     }
   } else {
     auto is_tiny = [&](int64_t K) { return tiny_ok && H.node_c[K] <= tiny_cf && H.node_s[K] <= kTinyS; };
+    int32_t tsplit = -1;  // of the single-wavefront launch being built
     auto close = [&](int32_t tiny_base, int32_t kind) {
       if ((int32_t)H.lvl_items.size() > H.lvl_ptr.back()) {
         H.lvl_ptr.push_back((int32_t)H.lvl_items.size());
         H.lvl_tiny.push_back(tiny_base);
         H.lvl_kind.push_back(kind);
+        H.lvl_tsplit.push_back(kind == LVL_TINY ? tsplit : -1);
       }
     };
     std::vector<std::vector<int64_t>> bydepth(S.depth);
@@ -707,7 +716,10 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
               H.toff[t0 + k * c + i] = v | (herm && k < i ? 1u : 0u);
             }
         }
-        if (pass == 0) H.tiny_dadj[d] = (int32_t)H.tiny.size();
+        if (pass == 0) {
+          H.tiny_dadj[d] = (int32_t)H.tiny.size();
+          tsplit = (int32_t)H.lvl_items.size();
+        }
       }
       close(tiny_base, LVL_TINY);
       if (d == top_depth && d + 1 < S.depth) H.lvl_top = (int32_t)H.lvl_ptr.size() - 1;
@@ -1308,6 +1320,7 @@ LaunchAux make_aux(const selinv_ctx *h, void *work) {
   a.lvl_recs = (const LRec *)(b + H.off.lvl_recs);
   a.lvl_ptr = H.lvl_ptr.data();
   a.lvl_tiny = H.lvl_tiny.data();
+  a.lvl_tsplit = H.lvl_tsplit.data();
   a.lvl_kind = H.lvl_kind.data();
   a.push = (const PushRec *)(b + H.off.pushrecs);
   a.y128 = (const Item *)(b + H.off.y128recs);

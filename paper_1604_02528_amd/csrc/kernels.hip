@@ -306,12 +306,38 @@ __global__ void __launch_bounds__(64) k_tiny(const DevPlan *__restrict__ plp, co
     do_tiny<T, 8, HERM>(r, pl.toff, L, X, ls, ys);
   else if (r.c <= 16)
     do_tiny<T, 16, HERM>(r, pl.toff, L, X, ls, ys);
-  else if constexpr (sizeof(T) == 16)  // complex plans list c <= kTinyC only
+  else if constexpr (sizeof(T) == 16)  // complex launches send c > kTinyC to k_tiny64
     do_tiny<T, 32, HERM>(r, pl.toff, L, X, ls, ys);
   else if (r.c <= 32)
     do_tiny<T, 32, HERM>(r, pl.toff, L, X, ls, ys);
   else
     do_tiny64<T>(r, pl.toff, L, X, ls, ys);
+  if (pl.trace) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t *tr = pl.trace + 8 * ((int64_t)list_pos * pl.batch + g);
+      tr[0] = l * pl.nitems + r.it;
+      tr[1] = blockIdx.x;
+      tr[2] = t_start;
+      tr[3] = t_start;
+      tr[4] = wall_clock64();
+    }
+  }
+}
+
+// Complex-symmetric single-wavefront nodes with kTinyC < c <= kTinyCF (the
+// forward-only part of a depth's list): do_tiny64, in a kernel of its own so
+// that the narrower nodes keep k_tiny's registers and LDS.
+template <typename T>
+__global__ void __launch_bounds__(64) k_tiny64(const DevPlan *__restrict__ plp, const T *Lp, T *Xp,
+                                               const TinyRec *__restrict__ recs, int32_t count, int32_t list_pos) {
+  const DevPlan &pl = *plp;
+  __shared__ T ls[kTinyS * kTinyCF], ys[kTinyS * kTinyCF];
+  const int64_t g = blockIdx.x;
+  const int64_t l = g / count;
+  const TinyRec r = recs[g - l * count];
+  const int64_t t_start = pl.trace ? wall_clock64() : 0;
+  do_tiny64<T>(r, pl.toff, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, ls, ys);
   if (pl.trace) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -967,11 +993,17 @@ template <typename T>
 static void launch_level(const DevPlan &pl, const DevPlan *dpl, const LaunchAux &aux, const T *Lp, T *Xp, T *Pp,
                          hipStream_t st, int q, int32_t b, int32_t e) {
   if (e <= b) return;
-  if (aux.lvl_kind[q] == LVL_TINY)
-    hipLaunchKernelGGL((pl.csign < 0 ? k_tiny<T, true> : k_tiny<T, false>), dim3((unsigned)((e - b) * pl.batch)),
-                       dim3(64), 0, st, dpl, Lp, Xp,
-                       aux.tiny + aux.lvl_tiny[q] + (b - aux.lvl_ptr[q]), e - b, b);
-  else if (aux.lvl_kind[q] == LVL_PUSH)
+  if (aux.lvl_kind[q] == LVL_TINY) {
+    // complex plans: the forward-only nodes (from lvl_tsplit[q]) in k_tiny64
+    const int32_t ts = sizeof(T) == 16 && aux.lvl_tsplit[q] >= 0 ? aux.lvl_tsplit[q] : aux.lvl_ptr[q + 1];
+    const int32_t m0 = std::min(e, std::max(b, ts));
+    if (m0 > b)
+      hipLaunchKernelGGL((pl.csign < 0 ? k_tiny<T, true> : k_tiny<T, false>), dim3((unsigned)((m0 - b) * pl.batch)),
+                         dim3(64), 0, st, dpl, Lp, Xp, aux.tiny + aux.lvl_tiny[q] + (b - aux.lvl_ptr[q]), m0 - b, b);
+    if (e > m0)
+      hipLaunchKernelGGL(k_tiny64<T>, dim3((unsigned)((e - m0) * pl.batch)), dim3(64), 0, st, dpl, Lp, Xp,
+                         aux.tiny + aux.lvl_tiny[q] + (m0 - aux.lvl_ptr[q]), e - m0, m0);
+  } else if (aux.lvl_kind[q] == LVL_PUSH)
     hipLaunchKernelGGL(k_push<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp,
                        aux.push + aux.lvl_tiny[q] + (b - aux.lvl_ptr[q]), e - b, b);
   else if (aux.lvl_kind[q] == LVL_Y128) {

@@ -204,6 +204,7 @@ struct LaunchAux {
   const int32_t *lvl_ptr;   // host array [nlvl + 1]
   const int32_t *lvl_tiny;  // host array [nlvl]: -1 (work items), else the first TinyRec of the range
   const int32_t *lvl_kind;  // host array [nlvl]: a LevelKind
+  const int32_t *lvl_tsplit; // host array [nlvl]: a single-wavefront launch's first forward-only position, else -1
   const PushRec *push;      // push-form tiles (LVL_PUSH launches start at lvl_tiny[q])
   const Item *y128;         // 128 x 128 GEMM-1 tiles of FP64 dense-buffer nodes (LVL_Y128 launches
                             // start at lvl_tiny[q]): {K, ITEM_Y, row tile, column tile | part << 16}
