@@ -605,7 +605,7 @@ def main():
                      "algorithmic_bytes": algorithmic_bytes(w, args.relax),
                      "kernel": {"levels": "k_ydense (GEMM-1 tiles of nodes with a dense X_{C,C} buffer), "
                                           "k_gather_list (gathers into those buffers), k_gemm2_list (GEMM-2 "
-                                          "shares), k_items_list (the other items) and k_tiny "
+                                          "shares), k_items_list (the other items) and k_tiny / k_tiny64 "
                                           "(single-wavefront small nodes), one launch per etree depth and phase",
                                 "persistent": "k_persistent, one launch",
                                 "push": "k_push (the O/I/ID tiles of the left-looking form) and k_items_list "
