@@ -594,10 +594,9 @@ void build_plan(const Symbolic &S, int64_t batch, int64_t scalar_bytes, int64_t 
   H.tiny_dadj.assign(S.depth, 0);
   // small nodes address X through 32-bit byte offsets
   const bool tiny_ok = !lu && S.panel_elems * scalar_bytes < (int64_t(1) << 32);
-  // the forward sweep's single-wavefront nodes: c <= kTinyCF for FP64 and
-  // complex-symmetric plans, c <= kTinyC for Hermitian ones (the wider kernel
-  // reads X_{C,C} as stored, with no conjugated half)
-  const int64_t tiny_cf = herm ? kTinyC : kTinyCF;
+  // the forward sweep's single-wavefront nodes: c <= kTinyCF (complex plans
+  // run the ones beyond kTinyC in a kernel of their own)
+  const int64_t tiny_cf = kTinyCF;
   auto adj_tiny = [&](int64_t K) { return !push && tiny_ok && H.node_c[K] <= kTinyC && H.node_s[K] <= kTinyS; };
   H.push.clear();
   H.y128.clear();

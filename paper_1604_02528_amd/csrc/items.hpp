@@ -958,10 +958,12 @@ __device__ __forceinline__ void do_tiny(const TinyRec &r, const uint32_t *toff, 
 // accumulated in LDS (each lane owns its row), one column j at a time.  Four
 // dependent rounds: the record; Lhat, Dt^{-1} and the first half's offsets;
 // the first half's values with the second half's offsets; the second half's
-// values.
-template <typename T>
+// values.  HERM: a Hermitian plan (bit 0 of an offset marks an entry read
+// conjugated; the diagonal block takes Lhat^H and the conjugate transpose).
+template <typename T, bool HERM = false>
 __device__ __forceinline__ void do_tiny64(const TinyRec &r, const uint32_t *toff, const T *L, T *X, T *ls, T *ys) {
   constexpr int H = kTinyCF / 2, LDC = kTinyCF;
+  constexpr double cs = HERM ? -1.0 : 1.0;
   const int i = threadIdx.x;
   const int s = r.s, c = r.c;
   const int64_t ld = s + c;
@@ -983,8 +985,16 @@ __device__ __forceinline__ void do_tiny64(const TinyRec &r, const uint32_t *toff
   for (int u = 0; u < H; ++u) o[u] = ld_off(tb, rowb + 4u * u);
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
+    uint32_t cbits = 0;
 #pragma unroll
-    for (int u = 0; u < H; ++u) xv[u] = ld_off(X, o[u]);
+    for (int u = 0; u < H; ++u) {
+      if constexpr (HERM) {
+        xv[u] = ld_off(X, o[u] & ~1u);
+        cbits |= (o[u] & 1u) << u;
+      } else {
+        xv[u] = ld_off(X, o[u]);
+      }
+    }
     if (h == 0) {
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -997,7 +1007,10 @@ __device__ __forceinline__ void do_tiny64(const TinyRec &r, const uint32_t *toff
       __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < H; ++u) xv[u] = masked(xv[u], opaque_mask(i < c && H * h + u < c));
+    for (int u = 0; u < H; ++u) {
+      xv[u] = masked(xv[u], opaque_mask(i < c && H * h + u < c));
+      if constexpr (HERM) xv[u] = cj(xv[u], ((cbits >> u) & 1u) ? -1.0 : 1.0);
+    }
 #pragma unroll 1
     for (int j = 0; j < s; ++j) {
       T a = h ? ys[j * LDC + i] : zero_of<T>();
@@ -1015,10 +1028,10 @@ __device__ __forceinline__ void do_tiny64(const TinyRec &r, const uint32_t *toff
   if (x < s && y < s) {
     T rxy = zero_of<T>(), ryx = zero_of<T>();
     for (int q = 0; q < c; ++q) {
-      rxy += ls[x * LDC + q] * ys[y * LDC + q];
-      ryx += ls[y * LDC + q] * ys[x * LDC + q];
+      rxy += cj(ls[x * LDC + q], cs) * ys[y * LDC + q];
+      ryx += cj(ls[y * LDC + q], cs) * ys[x * LDC + q];
     }
-    X[r.off + y * ld + x] = SOps<T>::scale(0.5, (dxy + rxy) + (dyx + ryx));
+    X[r.off + y * ld + x] = SOps<T>::scale(0.5, (dxy + rxy) + cj(dyx + ryx, cs));
   }
 }
 

@@ -325,10 +325,10 @@ __global__ void __launch_bounds__(64) k_tiny(const DevPlan *__restrict__ plp, co
   }
 }
 
-// Complex-symmetric single-wavefront nodes with kTinyC < c <= kTinyCF (the
+// Complex single-wavefront nodes with kTinyC < c <= kTinyCF (the
 // forward-only part of a depth's list): do_tiny64, in a kernel of its own so
 // that the narrower nodes keep k_tiny's registers and LDS.
-template <typename T>
+template <typename T, bool HERM>
 __global__ void __launch_bounds__(64) k_tiny64(const DevPlan *__restrict__ plp, const T *Lp, T *Xp,
                                                const TinyRec *__restrict__ recs, int32_t count, int32_t list_pos) {
   const DevPlan &pl = *plp;
@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(64) k_tiny64(const DevPlan *__restrict__ plp, 
   const int64_t l = g / count;
   const TinyRec r = recs[g - l * count];
   const int64_t t_start = pl.trace ? wall_clock64() : 0;
-  do_tiny64<T>(r, pl.toff, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, ls, ys);
+  do_tiny64<T, HERM>(r, pl.toff, Lp + l * pl.panel_elems, Xp + l * pl.panel_elems, ls, ys);
   if (pl.trace) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1001,7 +1001,8 @@ static void launch_level(const DevPlan &pl, const DevPlan *dpl, const LaunchAux 
       hipLaunchKernelGGL((pl.csign < 0 ? k_tiny<T, true> : k_tiny<T, false>), dim3((unsigned)((m0 - b) * pl.batch)),
                          dim3(64), 0, st, dpl, Lp, Xp, aux.tiny + aux.lvl_tiny[q] + (b - aux.lvl_ptr[q]), m0 - b, b);
     if (e > m0)
-      hipLaunchKernelGGL(k_tiny64<T>, dim3((unsigned)((e - m0) * pl.batch)), dim3(64), 0, st, dpl, Lp, Xp,
+      hipLaunchKernelGGL((pl.csign < 0 ? k_tiny64<T, true> : k_tiny64<T, false>), dim3((unsigned)((e - m0) * pl.batch)),
+                         dim3(64), 0, st, dpl, Lp, Xp,
                          aux.tiny + aux.lvl_tiny[q] + (m0 - aux.lvl_ptr[q]), e - m0, m0);
   } else if (aux.lvl_kind[q] == LVL_PUSH)
     hipLaunchKernelGGL(k_push<T>, dim3((unsigned)((e - b) * pl.batch)), dim3(NT), 0, st, dpl, Lp, Xp,
